@@ -1,0 +1,186 @@
+/*
+ * smg.h -- C-ABI of the MI355X stochastic multigrid sampler/solver.
+ *
+ * The library draws Gaussian fields x ~ N(0, kT A^-1), where A = -L is the discrete
+ * Laplacian L = DG on a uniform cell-centred grid (paper: Sec. "Spatially Adaptive
+ * Discretizations", uniform-mesh case), periodic in x and y, with no-slip walls on the
+ * faces z = 0 and z = nz*h (Sec. 2: steady Stokes with u = 0 on the boundary), and it
+ * solves A u = f.  Sampling is the paper's stochastic multigrid method (Sec. "Stochastic
+ * Multigrid Methods", Alg. 3 V-cycle; Sec. "Stochastic Iterative Methods", stochastic
+ * Gauss-Seidel with J = C - R C R^T): the covariance -L^-1 of the driving field xi of
+ * eq. g_gen_xi, scaled by kT.  The solve is the same cycle with the noise switched off
+ * (stationary mean (I - R)^-1 s = A^-1 f).
+ *
+ * Conventions for every entry point:
+ *  - Return value: SMG_OK (0) or a negative SMG_E* code; smg_last_error() then returns a
+ *    message for the calling thread.  No entry point aborts the process.
+ *  - Device memory: every device byte (workspace, chain state, inputs, outputs) belongs
+ *    to the caller.  The library never allocates or frees device memory.  Device pointers
+ *    must be 256-byte aligned.
+ *  - Streams: work is enqueued on the caller's hipStream_t, passed as void*.  Calls are
+ *    asynchronous except smg_solve (which synchronises the stream to test convergence)
+ *    and smg_bind_workspace (which synchronises after uploading its tables).
+ *    A hierarchy holds per-call state in its workspace: calls on one hierarchy must not
+ *    overlap (one stream at a time).  Different hierarchies are independent.
+ *  - Field layout: C-contiguous [ncomp][nz][ny][nx], x fastest, IEEE float64 unless
+ *    stated.  Components are independent scalar fields with the same operator.
+ *  - Noise: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed, with counter
+ *    (site pair, level | slot<<4 | colour<<12 | comp<<16 | kind<<24, cycle lo, cycle hi);
+ *    a result depends only on (seed, cycle indices, parameters), never on launch shape,
+ *    batching or stream.
+ */
+#ifndef SMG_H
+#define SMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SMG_OK = 0,
+  SMG_EINVAL = -1,      /* invalid argument, shape or parameter */
+  SMG_ENOMEM = -2,      /* workspace too small / request over budget */
+  SMG_ENOTCONV = -3,    /* solve did not reach rtol within max_cycles */
+  SMG_ENONFINITE = -4,  /* NaN or Inf in an input or residual */
+  SMG_EHIP = -5,        /* a HIP runtime call failed */
+  SMG_ESTATE = -6       /* hierarchy used before smg_bind_workspace */
+};
+
+enum { SMG_COARSEST_CHOLESKY = 0, SMG_COARSEST_SMOOTH = 1 };
+enum { SMG_FP64 = 0, SMG_FP32_REFINED = 1 };
+enum { SMG_OUT_F64 = 0, SMG_OUT_F32 = 1 };
+
+/* Grid: nx, ny even (red-black periodicity), nz >= 1, ncomp in [1, 255], h > 0, kT >= 0. */
+typedef struct {
+  int32_t nx, ny, nz, ncomp;
+  double h;
+  double kT;
+} smg_grid_desc;
+
+/* Cycle parameters (Alg. 3 V(nu1, nu2); the paper leaves depth and coarsest handling open).
+ *   levels        number of levels (0 = automatic: coarsen while a level has more than
+ *                 coarsest_max unknowns and can be smoothed).
+ *   nu1, nu2      pre/post sweeps per level (each sweep visits every colour once).
+ *   coarsest_max  automatic-depth threshold (1..4096); the dense coarsest factor itself is
+ *                 limited to 4096 unknowns whatever the depth.
+ *   coarsest_mode SMG_COARSEST_CHOLESKY: exact draw A_c^-1 b + sqrt(kT) L_c^-T n;
+ *                 SMG_COARSEST_SMOOTH: nu1 + nu2 sweeps only (the literal Alg. 3 step 2).
+ *   precision     SMG_FP64 (all FP64) or SMG_FP32_REFINED (FP32 sweeps and transfers inside
+ *                 an FP64 correction loop, Alg. 1; FP64 residual and coarsest).
+ *   stride        cycles per emitted sample (>= 1).
+ *   burn_in       cycles run before the first emitted sample of each smg_sample_field call.
+ */
+typedef struct {
+  int32_t levels;
+  int32_t nu1, nu2;
+  int32_t coarsest_max;
+  int32_t coarsest_mode;
+  int32_t precision;
+  int32_t stride;
+  int32_t burn_in;
+} smg_cycle_params;
+
+/* Filled by smg_hierarchy_info. */
+typedef struct {
+  size_t workspace_bytes;   /* device bytes smg_bind_workspace needs */
+  size_t state_bytes;       /* bytes of one chain state: ncomp*nx*ny*nz float64 */
+  int32_t n_levels;
+  int32_t dims[16][3];      /* (nx, ny, nz) per level, finest first */
+  int32_t coarsest_unknowns;
+} smg_info;
+
+typedef struct {
+  int32_t cycles;           /* V-cycles performed */
+  double relres;            /* max over components of ||f - A u||_2 / ||f||_2 */
+} smg_solve_info;
+
+typedef struct smg_hierarchy smg_hierarchy;
+
+/* Plans the level hierarchy and builds, on the host, the Galerkin coarse operators
+ * A^(l) = P^T A^(l-1) P (Sec. "Stochastic Multigrid Methods", variational property) from
+ * 1D recurrences, the 2x2x2 block factors of every Galerkin level and the dense Cholesky
+ * factor of the coarsest level.  *out receives a host object owned by the caller (free it
+ * with smg_destroy_hierarchy).  No device work.  Errors: SMG_EINVAL for unsupported
+ * shapes (nx or ny odd, levels not reachable, coarsest above 4096 unknowns). */
+int smg_create_hierarchy(const smg_grid_desc* desc, const smg_cycle_params* params,
+                         smg_hierarchy** out);
+
+/* Sizes and level dimensions of a created hierarchy. */
+int smg_hierarchy_info(const smg_hierarchy* h, smg_info* info);
+
+/* Binds caller-owned device memory of at least workspace_bytes (256-byte aligned) on the
+ * current device and uploads the operator tables and factors into it on `stream`, then
+ * synchronises the stream.  The memory must stay valid until the hierarchy is destroyed
+ * or re-bound.  Errors: SMG_EINVAL (null/misaligned), SMG_ENOMEM (too small), SMG_EHIP. */
+int smg_bind_workspace(smg_hierarchy* h, void* dev_ptr, size_t bytes, void* stream);
+
+/* Runs the stochastic chain: burn_in + n*stride V-cycles with b = 0 (target N(0, kT A^-1),
+ * eq. J_eq_C_R), cycle indices first_cycle, first_cycle+1, ...  `state` (device, in/out,
+ * state_bytes, float64 [ncomp][nz][ny][nx]) holds the chain's current field: read at the
+ * start, written at the end; zero it for a chain from the zero start.  After the k-th
+ * group of `stride` cycles the field is written to out[k-1] (device, [n][ncomp][nz][ny][nx],
+ * float64 or float32 per out_dtype); out may be NULL when n == 0.  Resuming with the
+ * returned state and first_cycle advanced by the cycles run continues the same chain
+ * bit for bit.  Asynchronous on `stream`.  Errors: SMG_EINVAL, SMG_ESTATE, SMG_EHIP. */
+int smg_sample_field(smg_hierarchy* h, int64_t n, uint64_t seed, uint64_t first_cycle,
+                     void* state, void* out, int32_t out_dtype, void* stream);
+
+/* Solves A u = f (f, u device float64 [ncomp][nz][ny][nx]) by repeated noise-free
+ * V-cycles from u = 0 until ||f - A u||_2 <= rtol ||f||_2 for every component or
+ * max_cycles cycles ran.  Synchronises `stream` after each cycle to read the residual
+ * norms; *info (host) is filled.  Errors: SMG_ENOTCONV (u holds the last iterate),
+ * SMG_ENONFINITE (f or a residual not finite), SMG_EINVAL, SMG_ESTATE, SMG_EHIP. */
+int smg_solve(smg_hierarchy* h, const void* f, void* u, double rtol, int32_t max_cycles,
+              void* stream, smg_solve_info* info);
+
+/* Frees the host object.  Never touches the caller's device memory. */
+void smg_destroy_hierarchy(smg_hierarchy* h);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* smg_last_error(void);
+
+/* ---- Component entry points (used by the parity tests; same kernels as the cycle). ----
+ * All fields natural layout float64 [ncomp][nz_l][ny_l][nx_l] on the device.
+ *
+ * smg_debug_smooth: one stochastic Gauss-Seidel sweep pass of one colour on level l
+ *   (l = 0: red-black point heat bath, colour 0..1; l >= 1: 2x2x2 block heat bath,
+ *   colour 0..7) in place on x with right-hand side b (NULL = 0 on level 0), noise
+ *   counters (seed, cycle, slot); noise off when with_noise == 0.
+ * smg_debug_restrict_residual: b_{l+1} = P^T (b_l - A_l x_l)  (b_l NULL = 0 on level 0).
+ * smg_debug_prolong_add: x_l += P e_{l+1}.
+ * smg_debug_coarsest: x_c = A_c^-1 b_c (+ sqrt(kT) L_c^-T n when with_noise) on the
+ *   coarsest level. */
+int smg_debug_smooth(smg_hierarchy* h, int32_t level, int32_t colour, void* x, const void* b,
+                     uint64_t seed, uint64_t cycle, int32_t slot, int32_t with_noise,
+                     void* stream);
+int smg_debug_restrict_residual(smg_hierarchy* h, int32_t level, const void* x, const void* b,
+                                void* b_coarse, void* stream);
+int smg_debug_prolong_add(smg_hierarchy* h, int32_t level, void* x, const void* e_coarse,
+                          void* stream);
+int smg_debug_coarsest(smg_hierarchy* h, void* x, const void* b, uint64_t seed, uint64_t cycle,
+                       int32_t with_noise, void* stream);
+
+/* smg_debug_host_table: copies a host-built table of level l into out (host memory of
+ *   `count` doubles; no device work, callable without a workspace).
+ *   which = 0: Galerkin row coefficients [nz_l][125], index (dz+2)*25 + (dy+2)*5 + (dx+2);
+ *   which = 1: block factors [nz_l/2][2][64] (A_BB^-1, then L_BB^-T, row-major);
+ *   which = 2: coarsest A_c^-1 [n_c][n_c];  which = 3: coarsest L_c^-1 [n_c][n_c].
+ *   Returns SMG_EINVAL if the table does not exist or count is wrong. */
+int smg_debug_host_table(const smg_hierarchy* h, int32_t level, int32_t which, double* out,
+                         size_t count);
+
+/* ---- Kernel timing (measurement support). ----
+ * When enabled, the library records HIP events on the caller's stream around every launch
+ * of the level-0 colour-pass kernel and accumulates their elapsed times (read after the
+ * stream is idle).  *count receives the number of timed launches, *total_ms their sum;
+ * the counters are reset by smg_kernel_timing(h, 1). */
+int smg_kernel_timing(smg_hierarchy* h, int32_t enable);
+int smg_kernel_timing_read(smg_hierarchy* h, int64_t* count, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMG_H */

@@ -1,0 +1,109 @@
+"""ctypes binding of the C-ABI in include/smg.h (argument marshalling only)."""
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsmg.so")
+
+SMG_OK = 0
+SMG_EINVAL = -1
+SMG_ENOMEM = -2
+SMG_ENOTCONV = -3
+SMG_ENONFINITE = -4
+SMG_EHIP = -5
+SMG_ESTATE = -6
+SMG_COARSEST_CHOLESKY = 0
+SMG_COARSEST_SMOOTH = 1
+SMG_FP64 = 0
+SMG_FP32_REFINED = 1
+SMG_OUT_F64 = 0
+SMG_OUT_F32 = 1
+
+ERROR_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_ENOTCONV",
+               -4: "SMG_ENONFINITE", -5: "SMG_EHIP", -6: "SMG_ESTATE"}
+
+EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
+            "smg_sample_field", "smg_solve", "smg_destroy_hierarchy", "smg_last_error",
+            "smg_debug_smooth", "smg_debug_restrict_residual", "smg_debug_prolong_add",
+            "smg_debug_coarsest", "smg_debug_host_table", "smg_kernel_timing",
+            "smg_kernel_timing_read"]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("ncomp", ctypes.c_int32), ("h", ctypes.c_double), ("kT", ctypes.c_double)]
+
+
+class CycleParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
+                ("coarsest_max", ctypes.c_int32), ("coarsest_mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("burn_in", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_size_t), ("state_bytes", ctypes.c_size_t),
+                ("n_levels", ctypes.c_int32), ("dims", (ctypes.c_int32 * 3) * 16),
+                ("coarsest_unknowns", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("relres", ctypes.c_double)]
+
+
+class SMGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERROR_NAMES.get(code, code), msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libsmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsmg.so not built: run __graft_entry__.build() or "
+                           "python -m paper_1003_2680_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    H = ctypes.c_void_p
+    sig = {
+        "smg_create_hierarchy": ([ctypes.POINTER(GridDesc), ctypes.POINTER(CycleParams),
+                                  ctypes.POINTER(H)], ctypes.c_int),
+        "smg_hierarchy_info": ([H, ctypes.POINTER(Info)], ctypes.c_int),
+        "smg_bind_workspace": ([H, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg_sample_field": ([H, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, P, P,
+                              ctypes.c_int32, P], ctypes.c_int),
+        "smg_solve": ([H, P, P, ctypes.c_double, ctypes.c_int32, P, ctypes.POINTER(SolveInfo)],
+                      ctypes.c_int),
+        "smg_destroy_hierarchy": ([H], None),
+        "smg_last_error": ([], ctypes.c_char_p),
+        "smg_debug_smooth": ([H, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_uint64,
+                              ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, P], ctypes.c_int),
+        "smg_debug_restrict_residual": ([H, ctypes.c_int32, P, P, P, P], ctypes.c_int),
+        "smg_debug_prolong_add": ([H, ctypes.c_int32, P, P, P], ctypes.c_int),
+        "smg_debug_coarsest": ([H, P, P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, P],
+                               ctypes.c_int),
+        "smg_debug_host_table": ([H, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_size_t],
+                                 ctypes.c_int),
+        "smg_kernel_timing": ([H, ctypes.c_int32], ctypes.c_int),
+        "smg_kernel_timing_read": ([H, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(rc):
+    if rc != SMG_OK:
+        msg = load().smg_last_error()
+        raise SMGError(rc, msg.decode() if msg else "")
+    return rc

@@ -1,0 +1,127 @@
+"""Python front end of the C-ABI: torch tensors for device memory, the current torch stream
+for ordering.  Every step of the computation runs in the library's HIP kernels; this module
+only allocates buffers and marshals arguments.
+"""
+import ctypes
+
+import torch
+
+from . import abi
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Hierarchy:
+    """A planned multigrid hierarchy bound to a device workspace.
+
+    Fields are float64 tensors of shape [ncomp, nz, ny, nx] (x fastest).
+    """
+
+    def __init__(self, nx, ny, nz, ncomp=1, h=1.0, kT=1.0, levels=0, nu1=2, nu2=2,
+                 coarsest_max=512, coarsest="cholesky", precision="fp64", stride=1, burn_in=0,
+                 device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no ROCm device: the stochastic multigrid library runs only on the GPU")
+        self.lib = abi.load()
+        dev = torch.device(device if device is not None else "cuda")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.desc = abi.GridDesc(nx, ny, nz, ncomp, h, kT)
+        mode = {"cholesky": abi.SMG_COARSEST_CHOLESKY, "smooth": abi.SMG_COARSEST_SMOOTH}[coarsest]
+        prec = {"fp64": abi.SMG_FP64, "fp32_refined": abi.SMG_FP32_REFINED}[precision]
+        self.params = abi.CycleParams(levels, nu1, nu2, coarsest_max, mode, prec, stride, burn_in)
+        self.shape = (ncomp, nz, ny, nx)
+        handle = ctypes.c_void_p()
+        abi.check(self.lib.smg_create_hierarchy(ctypes.byref(self.desc), ctypes.byref(self.params),
+                                                ctypes.byref(handle)))
+        self._h = handle
+        info = abi.Info()
+        abi.check(self.lib.smg_hierarchy_info(self._h, ctypes.byref(info)))
+        self.info = info
+        self.n_levels = info.n_levels
+        self.level_dims = [tuple(info.dims[l]) for l in range(info.n_levels)]
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(max(int(info.workspace_bytes), 256), dtype=torch.uint8,
+                                         device=self.device)
+            abi.check(self.lib.smg_bind_workspace(self._h, _ptr(self.workspace),
+                                                  self.workspace.numel(), _stream(self.device)))
+
+    def close(self):
+        if self._h:
+            self.lib.smg_destroy_hierarchy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ main entry points
+    def new_state(self):
+        return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+
+    def sample(self, n, seed, first_cycle=0, state=None, out_dtype=torch.float64, out=None):
+        """Run the chain; returns (samples [n, ncomp, nz, ny, nx], state)."""
+        if state is None:
+            state = self.new_state()
+        self._check_field(state)
+        if out is None and n > 0:
+            out = torch.empty((n,) + self.shape, dtype=out_dtype, device=self.device)
+        code = abi.SMG_OUT_F32 if out_dtype == torch.float32 else abi.SMG_OUT_F64
+        abi.check(self.lib.smg_sample_field(self._h, int(n), int(seed), int(first_cycle),
+                                            _ptr(state), _ptr(out) if n > 0 else None, code,
+                                            _stream(self.device)))
+        return out, state
+
+    def solve(self, f, rtol=1e-12, max_cycles=100, u=None, raise_on_notconv=True):
+        """Solve A u = f from u = 0; returns (u, cycles, relres)."""
+        self._check_field(f)
+        if u is None:
+            u = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        info = abi.SolveInfo()
+        rc = self.lib.smg_solve(self._h, _ptr(f), _ptr(u), float(rtol), int(max_cycles),
+                                _stream(self.device), ctypes.byref(info))
+        if rc != abi.SMG_ENOTCONV or raise_on_notconv:
+            abi.check(rc)
+        return u, info.cycles, info.relres
+
+    # ------------------------------------------------------------------ component entry points
+    def debug_smooth(self, level, colour, x, b=None, seed=0, cycle=0, slot=0, noise=True):
+        abi.check(self.lib.smg_debug_smooth(self._h, level, colour, _ptr(x), _ptr(b), int(seed),
+                                            int(cycle), int(slot), int(bool(noise)),
+                                            _stream(self.device)))
+
+    def debug_restrict_residual(self, level, x, b, b_coarse):
+        abi.check(self.lib.smg_debug_restrict_residual(self._h, level, _ptr(x), _ptr(b),
+                                                       _ptr(b_coarse), _stream(self.device)))
+
+    def debug_prolong_add(self, level, x, e_coarse):
+        abi.check(self.lib.smg_debug_prolong_add(self._h, level, _ptr(x), _ptr(e_coarse),
+                                                 _stream(self.device)))
+
+    def debug_coarsest(self, x, b, seed=0, cycle=0, noise=True):
+        abi.check(self.lib.smg_debug_coarsest(self._h, _ptr(x), _ptr(b), int(seed), int(cycle),
+                                              int(bool(noise)), _stream(self.device)))
+
+    def kernel_timing(self, enable):
+        abi.check(self.lib.smg_kernel_timing(self._h, int(bool(enable))))
+
+    def kernel_timing_read(self):
+        cnt = ctypes.c_int64()
+        ms = ctypes.c_double()
+        abi.check(self.lib.smg_kernel_timing_read(self._h, ctypes.byref(cnt), ctypes.byref(ms)))
+        return cnt.value, ms.value
+
+    def _check_field(self, t):
+        if t.dtype != torch.float64 or tuple(t.shape) != self.shape or not t.is_contiguous() \
+                or t.device != self.device:
+            raise ValueError("field must be a contiguous float64 %s tensor on %s" %
+                             (self.shape, self.device))

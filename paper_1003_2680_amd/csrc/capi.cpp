@@ -1,0 +1,581 @@
+// C-ABI entry points and the host-side cycle driver.
+//
+// The V-cycle follows Alg. 3 of the paper: nu1 pre-sweeps; b^(l+1) = P^T (b^(l) - A^(l) v^(l));
+// v^(l+1) = 0; recurse; v^(l) += P v^(l+1); nu2 post-sweeps.  The coarsest level is either an
+// exact draw (dense Cholesky) or nu1 + nu2 sweeps.  Sampling runs the cycle with b = 0 and the
+// noise on (target N(0, kT A^-1)); the solve runs it with the noise off from u = 0 (its fixed
+// point is A^-1 f).  Noise counters: level | slot<<4 | colour<<12 | comp<<16 | kind<<24, where
+// slot is the sweep number within the level's visit (pre-sweeps first) and kind is 0 for
+// smoother noise, 1 for the coarsest draw.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "smg_internal.hpp"
+
+struct smg_hierarchy {
+  smg::Hierarchy h;
+};
+
+namespace smg {
+namespace {
+
+thread_local std::string g_err;
+
+#define SMG_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));                \
+      return SMG_EHIP;                                                             \
+    }                                                                              \
+  } while (0)
+
+#define SMG_TRY(expr)        \
+  do {                       \
+    int rc_ = (expr);        \
+    if (rc_ != SMG_OK) return rc_; \
+  } while (0)
+
+constexpr uint32_t KIND_SMOOTH_NOISE = 0;
+constexpr uint32_t KIND_COARSEST_NOISE = 1;
+
+struct Run {
+  Hierarchy* h;
+  hipStream_t s;
+  bool noise;
+  bool has_b0;      // level-0 right-hand side present (solve)
+  uint64_t seed;
+  uint64_t cycle;
+};
+
+NoiseArgs make_noise(const Run& r, int level, int slot, int colour, uint32_t kind) {
+  NoiseArgs na;
+  na.k0 = (uint32_t)r.seed;
+  na.k1 = (uint32_t)(r.seed >> 32);
+  na.sid = (uint32_t)level | ((uint32_t)slot << 4) | ((uint32_t)colour << 12) | (kind << 24);
+  na.c2 = (uint32_t)r.cycle;
+  na.c3 = (uint32_t)(r.cycle >> 32);
+  na.sqkT = std::sqrt(r.h->desc.kT);
+  return na;
+}
+
+size_t half_field(const Hierarchy& h) { return (size_t)h.desc.ncomp * (h.lv[0].n / 2); }
+
+double* red(Level& v) { return v.x; }
+double* blk(const Hierarchy& h, Level& v) { return v.x + half_field(h); }
+double* bred(Level& v) { return v.b; }
+double* bblk(const Hierarchy& h, Level& v) { return v.b + half_field(h); }
+
+int timed_rb_pass(Run& r, double* xc, const double* xo, const double* bc, int colour,
+                  const NoiseArgs& na) {
+  Hierarchy& h = *r.h;
+  const Level& v = h.lv[0];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h.timing) {
+    if (h.ev_used + 2 > h.ev_pool.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        SMG_HIP(hipEventCreate(&e));
+        h.ev_pool.push_back(e);
+      }
+    }
+    e0 = h.ev_pool[h.ev_used++];
+    e1 = h.ev_pool[h.ev_used++];
+    SMG_HIP(hipEventRecord(e0, r.s));
+  }
+  SMG_HIP(launch_rb_pass(xc, xo, bc, v.nx, v.ny, v.nz, h.desc.ncomp, colour, h.desc.h,
+                         h.desc.kT, r.noise, na, r.s));
+  if (h.timing) SMG_HIP(hipEventRecord(e1, r.s));
+  return SMG_OK;
+}
+
+int sweep(Run& r, int l, int slot, bool post) {
+  Hierarchy& h = *r.h;
+  Level& v = h.lv[l];
+  const int nc = h.desc.ncomp;
+  if (v.kind == KIND_POINT) {
+    for (int t = 0; t < 2; ++t) {
+      const int colour = post ? 1 - t : t;
+      NoiseArgs na = make_noise(r, l, slot, colour, KIND_SMOOTH_NOISE);
+      double* xc = colour ? blk(h, v) : red(v);
+      double* xo = colour ? red(v) : blk(h, v);
+      const double* bc = r.has_b0 ? (colour ? bblk(h, v) : bred(v)) : nullptr;
+      SMG_TRY(timed_rb_pass(r, xc, xo, bc, colour, na));
+    }
+  } else {
+    for (int t = 0; t < 8; ++t) {
+      const int colour = post ? 7 - t : t;
+      NoiseArgs na = make_noise(r, l, slot, colour, KIND_SMOOTH_NOISE);
+      SMG_HIP(launch_block_pass(v.x, v.b, v.coef_d, v.bfac_d, v.nx, v.ny, v.nz, nc, colour,
+                                r.noise, na, r.s));
+    }
+  }
+  return SMG_OK;
+}
+
+// b^(l+1) = P^T (b^(l) - A^(l) x^(l))
+int restrict_residual(Run& r, int l) {
+  Hierarchy& h = *r.h;
+  Level& v = h.lv[l];
+  const int nc = h.desc.ncomp;
+  if (v.kind == KIND_POINT) {
+    SMG_HIP(launch_residual0(v.r, red(v), blk(h, v), r.has_b0 ? bred(v) : nullptr,
+                             r.has_b0 ? bblk(h, v) : nullptr, v.nx, v.ny, v.nz, nc, h.desc.h,
+                             r.s));
+  } else {
+    SMG_HIP(launch_residual_gal(v.r, v.x, v.b, v.coef_d, v.nx, v.ny, v.nz, nc, r.s));
+  }
+  SMG_HIP(launch_restrict(h.lv[l + 1].b, v.r, v.nx, v.ny, v.nz, nc, r.s));
+  return SMG_OK;
+}
+
+int prolong_add(Run& r, int l) {
+  Hierarchy& h = *r.h;
+  Level& v = h.lv[l];
+  const int nc = h.desc.ncomp;
+  if (v.kind == KIND_POINT)
+    SMG_HIP(launch_prolong0(red(v), blk(h, v), h.lv[l + 1].x, v.nx, v.ny, v.nz, nc, r.s));
+  else
+    SMG_HIP(launch_prolong(v.x, h.lv[l + 1].x, v.nx, v.ny, v.nz, nc, r.s));
+  return SMG_OK;
+}
+
+int coarsest_step(Run& r, int l) {
+  Hierarchy& h = *r.h;
+  Level& v = h.lv[l];
+  NoiseArgs na = make_noise(r, l, 0, 0, KIND_COARSEST_NOISE);
+  SMG_HIP(launch_coarsest(v.x, v.b, h.ainv_d, h.w_d, h.nc, h.desc.ncomp, r.noise, na, r.s));
+  return SMG_OK;
+}
+
+int vcycle(Run& r, int l) {
+  Hierarchy& h = *r.h;
+  Level& v = h.lv[l];
+  const int nu1 = h.prm.nu1, nu2 = h.prm.nu2;
+  if (v.kind == KIND_CHOL) return coarsest_step(r, l);
+  for (int s = 0; s < nu1; ++s) SMG_TRY(sweep(r, l, s, false));
+  if (!v.coarsest) {
+    SMG_TRY(restrict_residual(r, l));
+    Level& c = h.lv[l + 1];
+    SMG_HIP(launch_zero(c.x, (int64_t)h.desc.ncomp * c.n, r.s));
+    SMG_TRY(vcycle(r, l + 1));
+    SMG_TRY(prolong_add(r, l));
+  }
+  for (int s = 0; s < nu2; ++s) SMG_TRY(sweep(r, l, nu1 + s, true));
+  return SMG_OK;
+}
+
+// natural [ncomp][N] field -> level-0 storage (x or b)
+int import_level0(Hierarchy& h, double* dst, const double* nat, hipStream_t s) {
+  Level& v = h.lv[0];
+  if (v.kind == KIND_POINT)
+    SMG_HIP(launch_to_split(dst, dst + half_field(h), nat, v.nx, v.ny, v.nz, h.desc.ncomp, s));
+  else
+    SMG_HIP(launch_copy(dst, nat, (int64_t)h.desc.ncomp * v.n, s));
+  return SMG_OK;
+}
+
+int export_level0(Hierarchy& h, void* nat, int out_f32, const double* src, hipStream_t s) {
+  Level& v = h.lv[0];
+  if (v.kind == KIND_POINT)
+    SMG_HIP(launch_from_split(nat, out_f32, src, src + half_field(h), v.nx, v.ny, v.nz,
+                              h.desc.ncomp, s));
+  else
+    SMG_HIP(launch_cast(nat, out_f32, src, (int64_t)h.desc.ncomp * v.n, s));
+  return SMG_OK;
+}
+
+bool aligned(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+int check_bound(const smg_hierarchy* hh) {
+  if (!hh) {
+    set_error("null hierarchy");
+    return SMG_EINVAL;
+  }
+  if (!hh->h.ws) {
+    set_error("hierarchy has no workspace bound (call smg_bind_workspace)");
+    return SMG_ESTATE;
+  }
+  return SMG_OK;
+}
+
+int check_ptr(const void* p, const char* what) {
+  if (!p || !aligned(p)) {
+    set_error(std::string(what) + " must be a non-null 256-byte aligned device pointer");
+    return SMG_EINVAL;
+  }
+  return SMG_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace smg
+
+using namespace smg;
+
+extern "C" {
+
+int smg_create_hierarchy(const smg_grid_desc* desc, const smg_cycle_params* params,
+                         smg_hierarchy** out) {
+  if (!desc || !params || !out) {
+    set_error("null argument");
+    return SMG_EINVAL;
+  }
+  *out = nullptr;
+  smg_hierarchy* hh = new (std::nothrow) smg_hierarchy();
+  if (!hh) {
+    set_error("host allocation failed");
+    return SMG_ENOMEM;
+  }
+  std::string err;
+  int rc = build_plan(*desc, *params, hh->h, err);
+  if (rc != SMG_OK) {
+    set_error(err);
+    delete hh;
+    return rc;
+  }
+  *out = hh;
+  return SMG_OK;
+}
+
+int smg_hierarchy_info(const smg_hierarchy* hh, smg_info* info) {
+  if (!hh || !info) {
+    set_error("null argument");
+    return SMG_EINVAL;
+  }
+  const Hierarchy& h = hh->h;
+  std::memset(info, 0, sizeof(*info));
+  info->workspace_bytes = h.ws_bytes;
+  info->state_bytes = (size_t)h.desc.ncomp * h.lv[0].n * sizeof(double);
+  info->n_levels = (int32_t)h.lv.size();
+  for (size_t l = 0; l < h.lv.size() && l < 16; ++l) {
+    info->dims[l][0] = h.lv[l].nx;
+    info->dims[l][1] = h.lv[l].ny;
+    info->dims[l][2] = h.lv[l].nz;
+  }
+  info->coarsest_unknowns = (int32_t)h.lv.back().n;
+  return SMG_OK;
+}
+
+int smg_bind_workspace(smg_hierarchy* hh, void* dev_ptr, size_t bytes, void* stream) {
+  if (!hh) {
+    set_error("null hierarchy");
+    return SMG_EINVAL;
+  }
+  SMG_TRY(check_ptr(dev_ptr, "workspace"));
+  Hierarchy& h = hh->h;
+  if (bytes < h.ws_bytes) {
+    set_error("workspace too small: need " + std::to_string(h.ws_bytes) + " bytes");
+    return SMG_ENOMEM;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)dev_ptr;
+  SMG_HIP(hipGetDevice(&h.device));
+  for (Level& v : h.lv) {
+    v.x = (double*)(ws + v.off_x);
+    v.b = (double*)(ws + v.off_b);
+    v.r = v.kind == KIND_CHOL ? nullptr : (double*)(ws + v.off_r);
+    if (v.kind == KIND_BLOCK) {
+      v.coef_d = (double*)(ws + v.off_coef);
+      v.bfac_d = (double*)(ws + v.off_bfac);
+      SMG_HIP(hipMemcpyAsync(v.coef_d, v.coef.data(), v.coef.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      SMG_HIP(hipMemcpyAsync(v.bfac_d, v.bfac.data(), v.bfac.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+    }
+  }
+  if (h.nc > 0) {
+    h.ainv_d = (double*)(ws + h.off_ainv);
+    h.w_d = (double*)(ws + h.off_w);
+    SMG_HIP(hipMemcpyAsync(h.ainv_d, h.ainv.data(), h.ainv.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+    SMG_HIP(hipMemcpyAsync(h.w_d, h.w.data(), h.w.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+  }
+  h.part_d = (double*)(ws + h.off_part);
+  h.norm_d = (double*)(ws + h.off_norm);
+  SMG_HIP(hipStreamSynchronize(s));
+  h.ws = ws;
+  return SMG_OK;
+}
+
+int smg_sample_field(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
+                     void* state, void* out, int32_t out_dtype, void* stream) {
+  SMG_TRY(check_bound(hh));
+  SMG_TRY(check_ptr(state, "state"));
+  if (n < 0 || (n > 0 && !out) || (out_dtype != SMG_OUT_F64 && out_dtype != SMG_OUT_F32)) {
+    set_error("invalid n / out / out_dtype");
+    return SMG_EINVAL;
+  }
+  if (n > 0) SMG_TRY(check_ptr(out, "out"));
+  Hierarchy& h = hh->h;
+  hipStream_t s = (hipStream_t)stream;
+  Level& v0 = h.lv[0];
+  const int64_t field = (int64_t)h.desc.ncomp * v0.n;
+  SMG_TRY(import_level0(h, v0.x, (const double*)state, s));
+  if (v0.kind == KIND_CHOL) SMG_HIP(launch_zero(v0.b, field, s));
+  Run r{&h, s, h.desc.kT > 0.0, false, seed, first_cycle};
+  const int64_t total = (int64_t)h.prm.burn_in + n * (int64_t)h.prm.stride;
+  const size_t out_elem = out_dtype == SMG_OUT_F32 ? sizeof(float) : sizeof(double);
+  for (int64_t k = 0; k < total; ++k) {
+    r.cycle = first_cycle + (uint64_t)k;
+    SMG_TRY(vcycle(r, 0));
+    const int64_t after = k + 1 - h.prm.burn_in;
+    if (after > 0 && after % h.prm.stride == 0) {
+      const int64_t idx = after / h.prm.stride - 1;
+      SMG_TRY(export_level0(h, (char*)out + (size_t)idx * field * out_elem,
+                            out_dtype == SMG_OUT_F32, v0.x, s));
+    }
+  }
+  SMG_TRY(export_level0(h, state, 0, v0.x, s));
+  return SMG_OK;
+}
+
+int smg_solve(smg_hierarchy* hh, const void* f, void* u, double rtol, int32_t max_cycles,
+              void* stream, smg_solve_info* info) {
+  SMG_TRY(check_bound(hh));
+  SMG_TRY(check_ptr(f, "f"));
+  SMG_TRY(check_ptr(u, "u"));
+  if (!(rtol >= 0.0) || max_cycles < 0) {
+    set_error("rtol must be >= 0 and max_cycles >= 0");
+    return SMG_EINVAL;
+  }
+  Hierarchy& h = hh->h;
+  hipStream_t s = (hipStream_t)stream;
+  Level& v0 = h.lv[0];
+  const int nc = h.desc.ncomp;
+  const int64_t field = (int64_t)nc * v0.n;
+  std::vector<double> fn(nc), rn(nc);
+  SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)f, v0.n, nc, s));
+  SMG_HIP(hipMemcpyAsync(fn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+  SMG_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < nc; ++c)
+    if (!std::isfinite(fn[c])) {
+      set_error("f is not finite");
+      return SMG_ENONFINITE;
+    }
+  SMG_TRY(import_level0(h, v0.b, (const double*)f, s));
+  SMG_HIP(launch_zero(v0.x, field, s));
+  Run r{&h, s, false, true, 0, 0};
+  double relres = 0.0;
+  bool all_zero = true;
+  for (int c = 0; c < nc; ++c) all_zero = all_zero && fn[c] == 0.0;
+  int cycles = 0;
+  if (!all_zero) {
+    relres = 1.0;
+    while (cycles < max_cycles) {
+      SMG_TRY(vcycle(r, 0));
+      ++cycles;
+      if (v0.kind == KIND_POINT)
+        SMG_HIP(launch_residual0(v0.r, red(v0), blk(h, v0), bred(v0), bblk(h, v0), v0.nx, v0.ny,
+                                 v0.nz, nc, h.desc.h, s));
+      else
+        SMG_HIP(launch_residual7_nat(v0.r ? v0.r : (double*)u, v0.x, v0.b, v0.nx, v0.ny, v0.nz,
+                                     nc, h.desc.h, s));
+      const double* rv = v0.r ? v0.r : (const double*)u;
+      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, rv, v0.n, nc, s));
+      SMG_HIP(hipMemcpyAsync(rn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+      SMG_HIP(hipStreamSynchronize(s));
+      relres = 0.0;
+      for (int c = 0; c < nc; ++c) {
+        if (!std::isfinite(rn[c])) {
+          set_error("residual is not finite");
+          return SMG_ENONFINITE;
+        }
+        double rr = fn[c] > 0.0 ? std::sqrt(rn[c] / fn[c]) : (rn[c] > 0.0 ? INFINITY : 0.0);
+        relres = rr > relres ? rr : relres;
+      }
+      if (relres <= rtol) break;
+    }
+  }
+  SMG_TRY(export_level0(h, u, 0, v0.x, s));
+  SMG_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->cycles = cycles;
+    info->relres = relres;
+  }
+  if (!all_zero && relres > rtol) {
+    set_error("solve did not converge: relres " + std::to_string(relres));
+    return SMG_ENOTCONV;
+  }
+  return SMG_OK;
+}
+
+void smg_destroy_hierarchy(smg_hierarchy* hh) {
+  if (!hh) return;
+  for (hipEvent_t e : hh->h.ev_pool) (void)hipEventDestroy(e);
+  delete hh;
+}
+
+const char* smg_last_error(void) { return g_err.c_str(); }
+
+int smg_debug_smooth(smg_hierarchy* hh, int32_t level, int32_t colour, void* x, const void* b,
+                     uint64_t seed, uint64_t cycle, int32_t slot, int32_t with_noise,
+                     void* stream) {
+  SMG_TRY(check_bound(hh));
+  SMG_TRY(check_ptr(x, "x"));
+  Hierarchy& h = hh->h;
+  if (level < 0 || level >= (int)h.lv.size() || h.lv[level].kind == KIND_CHOL || slot < 0 ||
+      slot > 255) {
+    set_error("level has no smoother / invalid slot");
+    return SMG_EINVAL;
+  }
+  Level& v = h.lv[level];
+  if (colour < 0 || colour >= (v.kind == KIND_POINT ? 2 : 8) || (level > 0 && !b)) {
+    set_error("invalid colour or missing b");
+    return SMG_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Run r{&h, s, with_noise != 0, b != nullptr, seed, cycle};
+  NoiseArgs na = make_noise(r, level, slot, colour, KIND_SMOOTH_NOISE);
+  if (v.kind == KIND_POINT) {
+    SMG_TRY(import_level0(h, v.x, (const double*)x, s));
+    if (b) SMG_TRY(import_level0(h, v.b, (const double*)b, s));
+    double* xc = colour ? blk(h, v) : red(v);
+    double* xo = colour ? red(v) : blk(h, v);
+    const double* bc = b ? (colour ? bblk(h, v) : bred(v)) : nullptr;
+    SMG_TRY(timed_rb_pass(r, xc, xo, bc, colour, na));
+    SMG_TRY(export_level0(h, x, 0, v.x, s));
+  } else {
+    SMG_HIP(launch_block_pass((double*)x, (const double*)b, v.coef_d, v.bfac_d, v.nx, v.ny, v.nz,
+                              h.desc.ncomp, colour, r.noise, na, s));
+  }
+  return SMG_OK;
+}
+
+int smg_debug_restrict_residual(smg_hierarchy* hh, int32_t level, const void* x, const void* b,
+                                void* b_coarse, void* stream) {
+  SMG_TRY(check_bound(hh));
+  SMG_TRY(check_ptr(x, "x"));
+  SMG_TRY(check_ptr(b_coarse, "b_coarse"));
+  Hierarchy& h = hh->h;
+  if (level < 0 || level + 1 >= (int)h.lv.size()) {
+    set_error("level has no coarser level");
+    return SMG_EINVAL;
+  }
+  Level& v = h.lv[level];
+  if (level > 0 && !b) {
+    set_error("missing b");
+    return SMG_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int nc = h.desc.ncomp;
+  if (v.kind == KIND_POINT) {
+    SMG_TRY(import_level0(h, v.x, (const double*)x, s));
+    if (b) SMG_TRY(import_level0(h, v.b, (const double*)b, s));
+    SMG_HIP(launch_residual0(v.r, red(v), blk(h, v), b ? bred(v) : nullptr,
+                             b ? bblk(h, v) : nullptr, v.nx, v.ny, v.nz, nc, h.desc.h, s));
+  } else {
+    SMG_HIP(launch_residual_gal(v.r, (const double*)x, (const double*)b, v.coef_d, v.nx, v.ny,
+                                v.nz, nc, s));
+  }
+  SMG_HIP(launch_restrict((double*)b_coarse, v.r, v.nx, v.ny, v.nz, nc, s));
+  return SMG_OK;
+}
+
+int smg_debug_prolong_add(smg_hierarchy* hh, int32_t level, void* x, const void* e_coarse,
+                          void* stream) {
+  SMG_TRY(check_bound(hh));
+  SMG_TRY(check_ptr(x, "x"));
+  SMG_TRY(check_ptr(e_coarse, "e_coarse"));
+  Hierarchy& h = hh->h;
+  if (level < 0 || level + 1 >= (int)h.lv.size()) {
+    set_error("level has no coarser level");
+    return SMG_EINVAL;
+  }
+  Level& v = h.lv[level];
+  hipStream_t s = (hipStream_t)stream;
+  const int nc = h.desc.ncomp;
+  if (v.kind == KIND_POINT) {
+    SMG_TRY(import_level0(h, v.x, (const double*)x, s));
+    SMG_HIP(launch_prolong0(red(v), blk(h, v), (const double*)e_coarse, v.nx, v.ny, v.nz, nc, s));
+    SMG_TRY(export_level0(h, x, 0, v.x, s));
+  } else {
+    SMG_HIP(launch_prolong((double*)x, (const double*)e_coarse, v.nx, v.ny, v.nz, nc, s));
+  }
+  return SMG_OK;
+}
+
+int smg_debug_coarsest(smg_hierarchy* hh, void* x, const void* b, uint64_t seed, uint64_t cycle,
+                       int32_t with_noise, void* stream) {
+  SMG_TRY(check_bound(hh));
+  SMG_TRY(check_ptr(x, "x"));
+  SMG_TRY(check_ptr(b, "b"));
+  Hierarchy& h = hh->h;
+  if (h.lv.back().kind != KIND_CHOL) {
+    set_error("coarsest level is not drawn exactly (SMG_COARSEST_SMOOTH)");
+    return SMG_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Run r{&h, s, with_noise != 0, false, seed, cycle};
+  const int l = (int)h.lv.size() - 1;
+  NoiseArgs na = make_noise(r, l, 0, 0, KIND_COARSEST_NOISE);
+  SMG_HIP(launch_coarsest((double*)x, (const double*)b, h.ainv_d, h.w_d, h.nc, h.desc.ncomp,
+                          r.noise, na, s));
+  return SMG_OK;
+}
+
+int smg_debug_host_table(const smg_hierarchy* hh, int32_t level, int32_t which, double* out,
+                         size_t count) {
+  if (!hh || !out) {
+    set_error("null argument");
+    return SMG_EINVAL;
+  }
+  const Hierarchy& h = hh->h;
+  if (level < 0 || level >= (int)h.lv.size()) {
+    set_error("invalid level");
+    return SMG_EINVAL;
+  }
+  const Level& v = h.lv[level];
+  const std::vector<double>* src = nullptr;
+  if (which == 0) src = &v.coef;
+  else if (which == 1) src = &v.bfac;
+  else if (which == 2 && v.kind == KIND_CHOL) src = &h.ainv;
+  else if (which == 3 && v.kind == KIND_CHOL) src = &h.w;
+  if (!src || src->empty() || src->size() != count) {
+    set_error("table not present on this level or wrong count");
+    return SMG_EINVAL;
+  }
+  std::memcpy(out, src->data(), count * sizeof(double));
+  return SMG_OK;
+}
+
+int smg_kernel_timing(smg_hierarchy* hh, int32_t enable) {
+  if (!hh) {
+    set_error("null hierarchy");
+    return SMG_EINVAL;
+  }
+  Hierarchy& h = hh->h;
+  h.timing = enable != 0;
+  h.ev_used = 0;
+  h.tcount = 0;
+  h.tms = 0.0;
+  return SMG_OK;
+}
+
+int smg_kernel_timing_read(smg_hierarchy* hh, int64_t* count, double* total_ms) {
+  if (!hh || !count || !total_ms) {
+    set_error("null argument");
+    return SMG_EINVAL;
+  }
+  Hierarchy& h = hh->h;
+  for (size_t i = 0; i + 1 < h.ev_used; i += 2) {
+    float ms = 0.0f;
+    SMG_HIP(hipEventElapsedTime(&ms, h.ev_pool[i], h.ev_pool[i + 1]));
+    h.tms += ms;
+    h.tcount += 1;
+  }
+  h.ev_used = 0;
+  *count = h.tcount;
+  *total_ms = h.tms;
+  return SMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// Device-side counter-based Gaussian noise.
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+// SC'11): ten rounds, each multiplying words 0 and 2 by the two Philox constants, splitting
+// the 64-bit products into halves and forming (hi1^w1^k0, lo1, hi0^w3^k1, lo0); the key
+// advances by the two Weyl constants between rounds.  One 32x32->64 multiply per product
+// maps to a single v_mad_u64_u32 on CDNA.
+//
+// Box-Muller turns words (w0,w1) and (w2,w3) into two 53-bit uniforms in (0,1] and then
+// into two standard normals: sqrt(-2 ln u1) cos(2 pi u2) and sqrt(-2 ln u1) sin(2 pi u2).
+// The angle uses sincospi(2 u2), which needs no reduction by pi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smg {
+
+struct NoiseArgs {
+  uint32_t k0, k1;   // seed low / high
+  uint32_t sid;      // level | slot<<4 | colour<<12 | kind<<24 (component added per thread)
+  uint32_t c2, c3;   // cycle low / high
+  double sqkT;       // sqrt(kT)
+};
+
+__device__ __forceinline__ void philox4x32_10(uint32_t& w0, uint32_t& w1, uint32_t& w2,
+                                              uint32_t& w3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * w0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * w2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ w1 ^ k0;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ w3 ^ k1;
+    w1 = (uint32_t)p1;
+    w3 = (uint32_t)p0;
+    w0 = n0;
+    w2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
+  uint64_t v = (((uint64_t)a << 32) | b) >> 11;
+  return ((double)v + 0.5) * 0x1p-53;
+}
+
+// Two normals of call `call` in stream (sid | comp<<16) at the given cycle.
+__device__ __forceinline__ void normal_pair(const NoiseArgs& na, uint32_t comp, uint32_t call,
+                                            double& z0, double& z1) {
+  uint32_t w0 = call, w1 = na.sid | (comp << 16), w2 = na.c2, w3 = na.c3;
+  philox4x32_10(w0, w1, w2, w3, na.k0, na.k1);
+  double u1 = uniform53(w0, w1);
+  double u2 = uniform53(w2, w3);
+  double r = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+}  // namespace smg

@@ -1,0 +1,69 @@
+// Internal host-side structures of the stochastic multigrid library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/smg.h"
+
+namespace smg {
+
+// How a level is smoothed (Sec. "Stochastic Multigrid Methods": the smoother is stochastic
+// Gauss-Seidel; on Galerkin levels a 2x2x2 block heat bath keeps every colour class
+// uncoupled) or, for the coarsest level, drawn exactly.
+enum LevelKind { KIND_POINT = 0, KIND_BLOCK = 1, KIND_CHOL = 2 };
+
+constexpr int STENCIL = 125;  // 5x5x5 offsets of a Galerkin operator row
+
+struct Level {
+  int nx = 0, ny = 0, nz = 0;
+  int64_t n = 0;
+  int kind = KIND_POINT;
+  bool coarsest = false;
+  // 1D factors of A^(l) = a_z (x) m_y (x) m_x + m_z (x) a_y (x) m_x + m_z (x) m_y (x) a_x
+  double ax[5] = {0}, mx[5] = {0}, ay[5] = {0}, my[5] = {0};  // periodic stencils, offsets -2..2
+  std::vector<double> az, mz;                                 // dense nz x nz (walls)
+  std::vector<double> coef;  // KIND_BLOCK: [nz][125] row coefficients, index (dz+2)*25+(dy+2)*5+(dx+2)
+  std::vector<double> bfac;  // KIND_BLOCK: [nz/2][2][64]: A_BB^-1 then L_BB^-T (row-major)
+  // workspace offsets (bytes); level 0 of KIND_POINT stores x and b split by colour
+  size_t off_x = 0, off_b = 0, off_r = 0, off_coef = 0, off_bfac = 0;
+  double* x = nullptr;
+  double* b = nullptr;
+  double* r = nullptr;
+  double* coef_d = nullptr;
+  double* bfac_d = nullptr;
+};
+
+struct Hierarchy {
+  smg_grid_desc desc{};
+  smg_cycle_params prm{};
+  std::vector<Level> lv;
+  int nc = 0;                    // unknowns of the coarsest level when it is drawn exactly
+  std::vector<double> ainv, w;   // coarsest A_c^-1 and W = L_c^-1 (row-major, n_c x n_c)
+  size_t off_ainv = 0, off_w = 0, off_part = 0, off_norm = 0;
+  size_t part_len = 0;
+  size_t ws_bytes = 0;
+  double* ainv_d = nullptr;
+  double* w_d = nullptr;
+  double* part_d = nullptr;      // partial sums of squares [ncomp][part_len]
+  double* norm_d = nullptr;      // [2][ncomp]
+  char* ws = nullptr;
+  int device = -1;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  int64_t tcount = 0;
+  double tms = 0.0;
+};
+
+// plan.cpp
+int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, std::string& err);
+
+// error helpers (capi.cpp)
+void set_error(const std::string& msg);
+
+}  // namespace smg

@@ -1,0 +1,164 @@
+"""C-ABI host-side checks (no GPU needed).
+
+* the library loads and exports every entry point that include/smg.h declares;
+* the planner's level dimensions equal the oracle's;
+* the host-built Galerkin tables (1D recurrences, folded by modular indexing) equal the
+  oracle's explicit sparse triple products P^T A P, and the block / coarsest factors invert
+  the oracle's operators -- two independent constructions of the same operators;
+* invalid shapes and parameters are rejected with SMG_EINVAL.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle.hierarchy import build_hierarchy, plan_levels, block_sets
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+abi = pytest.importorskip("paper_1003_2680_amd.abi")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(abi.LIB_PATH):
+        pytest.fail("libsmg.so is not built (run __graft_entry__.build())")
+    return abi.load()
+
+
+def _create(lib, nx, ny, nz, ncomp=1, levels=0, coarsest_max=512, mode=0, h=1.0, kT=1.0):
+    desc = abi.GridDesc(nx, ny, nz, ncomp, h, kT)
+    prm = abi.CycleParams(levels, 2, 2, coarsest_max, mode, 0, 1, 0)
+    hd = ctypes.c_void_p()
+    rc = lib.smg_create_hierarchy(ctypes.byref(desc), ctypes.byref(prm), ctypes.byref(hd))
+    return rc, hd
+
+
+def _info(lib, hd):
+    info = abi.Info()
+    abi.check(lib.smg_hierarchy_info(hd, ctypes.byref(info)))
+    return info
+
+
+def _table(lib, hd, level, which, count):
+    out = np.empty(count)
+    abi.check(lib.smg_debug_host_table(hd, level, which, out.ctypes.data_as(ctypes.c_void_p),
+                                       count))
+    return out
+
+
+def test_exports_match_header(lib):
+    hdr = open(os.path.join(ROOT, "include", "smg.h")).read()
+    declared = set(re.findall(r"^(?:int|void|const char\*)\s+(smg_\w+)\(", hdr, re.M))
+    assert declared, "no declarations parsed"
+    assert declared == set(abi.EXPORTED)
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+@pytest.mark.parametrize("dims,levels,cmax", [((16, 16, 16), 3, 512), ((128, 128, 128), 6, 512),
+                                              ((256, 256, 16), 0, 512), ((48, 48, 48), 0, 4096),
+                                              ((12, 8, 6), 0, 64), ((8, 8, 8), 3, 512)])
+def test_plan_matches_oracle(lib, dims, levels, cmax):
+    rc, hd = _create(lib, *dims, levels=levels, coarsest_max=cmax)
+    abi.check(rc)
+    try:
+        info = _info(lib, hd)
+        got = [tuple(info.dims[l]) for l in range(info.n_levels)]
+        assert got == plan_levels(*dims, levels=levels, coarsest_max=cmax)
+        assert info.state_bytes == 8 * dims[0] * dims[1] * dims[2]
+        assert info.workspace_bytes > 0
+    finally:
+        lib.smg_destroy_hierarchy(hd)
+
+
+def _matrix_from_table(coef, nx, ny, nz):
+    """Sparse operator assembled from [nz][125] row coefficients (wrapping in x and y)."""
+    rows, cols, vals = [], [], []
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x = x.ravel(); y = y.ravel(); z = z.ravel()
+    i = x + nx * (y + ny * z)
+    for oz in range(-2, 3):
+        for oy in range(-2, 3):
+            for ox in range(-2, 3):
+                c = coef.reshape(nz, 125)[z, (oz + 2) * 25 + (oy + 2) * 5 + (ox + 2)]
+                zz = z + oz
+                ok = (zz >= 0) & (zz < nz) & (c != 0)
+                j = (x[ok] + ox) % nx + nx * (((y[ok] + oy) % ny) + ny * zz[ok])
+                rows.append(i[ok]); cols.append(j); vals.append(c[ok])
+    n = nx * ny * nz
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n, n)).tocsr()
+
+
+@pytest.mark.parametrize("dims,levels", [((16, 16, 16), 4), ((16, 16, 8), 3), ((32, 16, 12), 3),
+                                         ((8, 8, 8), 3)])
+def test_galerkin_tables_match_oracle(lib, dims, levels):
+    H = build_hierarchy(*dims, h=0.7, levels=levels)
+    rc, hd = _create(lib, *dims, levels=levels, h=0.7, coarsest_max=4096)
+    abi.check(rc)
+    try:
+        for L in H[1:]:
+            nx, ny, nz = L.dims
+            if L.coarsest:
+                n = L.n
+                ainv = _table(lib, hd, L.index, 2, n * n).reshape(n, n)
+                W = _table(lib, hd, L.index, 3, n * n).reshape(n, n)
+                Ad = L.A.toarray()
+                assert np.max(np.abs(ainv @ Ad - np.eye(n))) < 1e-10
+                assert np.max(np.abs(W.T @ W @ Ad - np.eye(n))) < 1e-10
+                assert np.max(np.abs(np.triu(W, 1))) == 0.0
+                continue
+            coef = _table(lib, hd, L.index, 0, nz * 125)
+            A_tab = _matrix_from_table(coef, nx, ny, nz)
+            scale = abs(L.A).max()
+            assert abs(A_tab - L.A).max() <= 1e-14 * scale
+            bf = _table(lib, hd, L.index, 1, (nz // 2) * 128).reshape(nz // 2, 2, 8, 8)
+            for c, (bid, cells) in enumerate(block_sets(nx, ny, nz)):
+                for k in range(0, len(bid), max(1, len(bid) // 5)):
+                    ABB = L.A[cells[k]][:, cells[k]].toarray()
+                    bz = cells[k][0] // (nx * ny) // 2
+                    Ainv, U = bf[bz, 0], bf[bz, 1]
+                    assert np.max(np.abs(Ainv @ ABB - np.eye(8))) < 1e-12
+                    assert np.max(np.abs(U @ U.T @ ABB - np.eye(8))) < 1e-12
+                    assert np.max(np.abs(np.tril(U, -1))) == 0.0
+    finally:
+        lib.smg_destroy_hierarchy(hd)
+
+
+@pytest.mark.parametrize("dims,levels", [((7, 8, 8), 0), ((8, 5, 8), 0), ((12, 12, 12), 4),
+                                         ((0, 8, 8), 0)])
+def test_invalid_shapes_rejected(lib, dims, levels):
+    rc, hd = _create(lib, *dims, levels=levels)
+    assert rc == abi.SMG_EINVAL and not hd.value
+    assert len(lib.smg_last_error()) > 0
+
+
+def test_invalid_params_rejected(lib):
+    desc = abi.GridDesc(8, 8, 8, 1, 1.0, 1.0)
+    hd = ctypes.c_void_p()
+    for prm in (abi.CycleParams(0, 2, 2, 0, 0, 0, 1, 0), abi.CycleParams(0, 2, 2, 512, 5, 0, 1, 0),
+                abi.CycleParams(0, 2, 2, 512, 0, 0, 0, 0), abi.CycleParams(0, -1, 2, 512, 0, 0, 1, 0),
+                abi.CycleParams(0, 2, 2, 8192, 0, 0, 1, 0)):
+        assert lib.smg_create_hierarchy(ctypes.byref(desc), ctypes.byref(prm),
+                                        ctypes.byref(hd)) == abi.SMG_EINVAL
+    # too large a dense coarsest level
+    rc, hd = _create(lib, 32, 32, 32, levels=1, coarsest_max=4096)
+    assert rc == abi.SMG_EINVAL
+
+
+def test_unbound_hierarchy_refuses_work(lib):
+    rc, hd = _create(lib, 8, 8, 8, levels=3)
+    abi.check(rc)
+    try:
+        info = abi.SolveInfo()
+        rc = lib.smg_solve(hd, ctypes.c_void_p(256), ctypes.c_void_p(512), 1e-8, 5, None,
+                           ctypes.byref(info))
+        assert rc == abi.SMG_ESTATE
+        rc = lib.smg_sample_field(hd, 1, 0, 0, ctypes.c_void_p(256), ctypes.c_void_p(512), 0, None)
+        assert rc == abi.SMG_ESTATE
+    finally:
+        lib.smg_destroy_hierarchy(hd)
