@@ -95,6 +95,8 @@ typedef struct {
 typedef struct {
   int32_t cycles;           /* V-cycles performed */
   double relres;            /* max over components of ||f - A u||_2 / ||f||_2 */
+  double last_ratio;        /* max over components of ||r_k|| / ||r_{k-1}|| for the last cycle
+                               (0 when fewer than two cycles ran): the cycle's contraction */
 } smg_solve_info;
 
 typedef struct smg_hierarchy smg_hierarchy;
@@ -166,11 +168,17 @@ int smg_debug_coarsest(smg_hierarchy* h, void* x, const void* b, uint64_t seed, 
 /* smg_debug_host_table: copies a host-built table of level l into out (host memory of
  *   `count` doubles; no device work, callable without a workspace).
  *   which = 0: Galerkin row coefficients [nz_l][125], index (dz+2)*25 + (dy+2)*5 + (dx+2);
- *   which = 1: block factors [nz_l/2][2][64] (A_BB^-1, then L_BB^-T, row-major);
+ *   which = 1: block factors [nz_l/2][3][64] (A_BB^-1, L_BB^-T, A_BB, row-major);
  *   which = 2: coarsest A_c^-1 [n_c][n_c];  which = 3: coarsest L_c^-1 [n_c][n_c].
  *   Returns SMG_EINVAL if the table does not exist or count is wrong. */
 int smg_debug_host_table(const smg_hierarchy* h, int32_t level, int32_t which, double* out,
                          size_t count);
+
+/* smg_set_option: execution switches that never change results.
+ *   SMG_OPT_BOTTOM_KERNEL (default 1): run the levels with at most 4096 cells (and the
+ *   coarsest draw) in one LDS-resident launch per cycle; 0 = one launch per colour pass. */
+enum { SMG_OPT_BOTTOM_KERNEL = 1 };
+int smg_set_option(smg_hierarchy* h, int32_t option, int64_t value);
 
 /* ---- Kernel timing (measurement support). ----
  * When enabled, the library records HIP events on the caller's stream around every launch

@@ -18,6 +18,7 @@ SMG_FP64 = 0
 SMG_FP32_REFINED = 1
 SMG_OUT_F64 = 0
 SMG_OUT_F32 = 1
+SMG_OPT_BOTTOM_KERNEL = 1
 
 ERROR_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_ENOTCONV",
                -4: "SMG_ENONFINITE", -5: "SMG_EHIP", -6: "SMG_ESTATE"}
@@ -25,8 +26,8 @@ ERROR_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_ENOTCON
 EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
             "smg_sample_field", "smg_solve", "smg_destroy_hierarchy", "smg_last_error",
             "smg_debug_smooth", "smg_debug_restrict_residual", "smg_debug_prolong_add",
-            "smg_debug_coarsest", "smg_debug_host_table", "smg_kernel_timing",
-            "smg_kernel_timing_read"]
+            "smg_debug_coarsest", "smg_debug_host_table", "smg_set_option",
+            "smg_kernel_timing", "smg_kernel_timing_read"]
 
 
 class GridDesc(ctypes.Structure):
@@ -48,7 +49,8 @@ class Info(ctypes.Structure):
 
 
 class SolveInfo(ctypes.Structure):
-    _fields_ = [("cycles", ctypes.c_int32), ("relres", ctypes.c_double)]
+    _fields_ = [("cycles", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("last_ratio", ctypes.c_double)]
 
 
 class SMGError(RuntimeError):
@@ -90,6 +92,7 @@ def load():
                                ctypes.c_int),
         "smg_debug_host_table": ([H, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_size_t],
                                  ctypes.c_int),
+        "smg_set_option": ([H, ctypes.c_int32, ctypes.c_int64], ctypes.c_int),
         "smg_kernel_timing": ([H, ctypes.c_int32], ctypes.c_int),
         "smg_kernel_timing_read": ([H, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double)], ctypes.c_int),

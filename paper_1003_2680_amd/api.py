@@ -82,7 +82,8 @@ class Hierarchy:
         return out, state
 
     def solve(self, f, rtol=1e-12, max_cycles=100, u=None, raise_on_notconv=True):
-        """Solve A u = f from u = 0; returns (u, cycles, relres)."""
+        """Solve A u = f from u = 0; returns (u, cycles, relres).  The contraction of the
+        last cycle is kept in ``self.last_ratio``."""
         self._check_field(f)
         if u is None:
             u = torch.empty(self.shape, dtype=torch.float64, device=self.device)
@@ -91,6 +92,7 @@ class Hierarchy:
                                 _stream(self.device), ctypes.byref(info))
         if rc != abi.SMG_ENOTCONV or raise_on_notconv:
             abi.check(rc)
+        self.last_ratio = info.last_ratio
         return u, info.cycles, info.relres
 
     # ------------------------------------------------------------------ component entry points
@@ -110,6 +112,10 @@ class Hierarchy:
     def debug_coarsest(self, x, b, seed=0, cycle=0, noise=True):
         abi.check(self.lib.smg_debug_coarsest(self._h, _ptr(x), _ptr(b), int(seed), int(cycle),
                                               int(bool(noise)), _stream(self.device)))
+
+    def set_bottom_kernel(self, enable):
+        """Run the small levels in one LDS-resident launch per cycle (default) or per pass."""
+        abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_BOTTOM_KERNEL, int(bool(enable))))
 
     def kernel_timing(self, enable):
         abi.check(self.lib.smg_kernel_timing(self._h, int(bool(enable))))

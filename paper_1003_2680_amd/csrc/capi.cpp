@@ -111,8 +111,9 @@ int sweep(Run& r, int l, int slot, bool post) {
     for (int t = 0; t < 8; ++t) {
       const int colour = post ? 7 - t : t;
       NoiseArgs na = make_noise(r, l, slot, colour, KIND_SMOOTH_NOISE);
-      SMG_HIP(launch_block_pass(v.x, v.b, v.coef_d, v.bfac_d, v.nx, v.ny, v.nz, nc, colour,
-                                r.noise, na, r.s));
+      const double* zn = r.noise ? v.noise_d + (size_t)slot * nc * v.n : nullptr;
+      SMG_HIP(launch_block_pass(v.x, v.b, v.g2d_d, v.zt_d, v.bfac_d, v.nx, v.ny, v.nz, nc,
+                                colour, zn, na.sqkT, r.s));
     }
   }
   return SMG_OK;
@@ -128,9 +129,12 @@ int restrict_residual(Run& r, int l) {
                              r.has_b0 ? bblk(h, v) : nullptr, v.nx, v.ny, v.nz, nc, h.desc.h,
                              r.s));
   } else {
-    SMG_HIP(launch_residual_gal(v.r, v.x, v.b, v.coef_d, v.nx, v.ny, v.nz, nc, r.s));
+    SMG_HIP(launch_residual_gal(v.r, v.x, v.b, v.g2d_d, v.zt_d, v.nx, v.ny, v.nz, nc, r.s));
   }
-  SMG_HIP(launch_restrict(h.lv[l + 1].b, v.r, v.nx, v.ny, v.nz, nc, r.s));
+  // the bottom kernel starts its level from zero itself
+  Level& c = h.lv[l + 1];
+  SMG_HIP(launch_restrict(c.b, (l + 1 == h.bottom) ? nullptr : c.x, v.r, v.nx, v.ny, v.nz, nc,
+                          r.s));
   return SMG_OK;
 }
 
@@ -153,16 +157,88 @@ int coarsest_step(Run& r, int l) {
   return SMG_OK;
 }
 
+// Noise of every sweep of every block level (levels l >= 1 with 2x2x2 blocks) for the cycle
+// r.cycle, in one launch (or of one level and slot when level >= 0).
+int gen_level_noise(Run& r, int only_level = -1, int only_slot = 0) {
+  Hierarchy& h = *r.h;
+  NoiseGenArgs a{};
+  a.ncomp = h.desc.ncomp;
+  uint32_t calls = 0;
+  for (int l = 0; l < (int)h.lv.size(); ++l) {
+    const Level& v = h.lv[l];
+    if (v.kind != KIND_BLOCK || (only_level >= 0 && l != only_level)) continue;
+    if (a.nlev == kMaxNoiseLevels) {
+      set_error("too many block levels");
+      return SMG_EINVAL;
+    }
+    NoiseLevel& e = a.lv[a.nlev++];
+    e.level = l;
+    e.nx = v.nx; e.ny = v.ny; e.nz = v.nz;
+    e.nslot = only_level >= 0 ? 1 : h.prm.nu1 + h.prm.nu2;
+    e.slot0 = only_level >= 0 ? only_slot : 0;
+    e.out = v.noise_d;
+    e.calls_before = calls;
+    calls += (uint32_t)(e.nslot * a.ncomp * (v.n / 2));
+  }
+  a.total = calls;
+  NoiseArgs na = make_noise(r, 0, 0, 0, KIND_SMOOTH_NOISE);
+  SMG_HIP(launch_level_noise(a, na, r.s));
+  return SMG_OK;
+}
+
+// Level descriptors of the bottom kernel (device pointers are known once bound).
+BotArgs make_botargs(const Hierarchy& h) {
+  BotArgs a{};
+  a.nlev = (int)h.lv.size() - h.bottom;
+  a.level0 = h.bottom;
+  a.nu1 = h.prm.nu1;
+  a.nu2 = h.prm.nu2;
+  a.ncomp = h.desc.ncomp;
+  int off = 0;
+  for (int i = 0; i < a.nlev; ++i) {
+    const Level& v = h.lv[h.bottom + i];
+    int sy, sz;
+    bot_strides(v.kind, v.nx, v.ny, sy, sz);
+    a.lv[i] = BotLevel{v.nx, v.ny, v.nz, v.kind, sy, sz, v.noise_d, v.g2d_d, v.zt_d, v.bfac_d};
+    a.lds_off[i] = off;
+    off += 3 * (int)bot_field_doubles(v.kind, v.nx, v.ny, v.nz);
+  }
+  for (int i = 0; i < a.nlev; ++i) {
+    const Level& v = h.lv[h.bottom + i];
+    a.tab_off[i] = off;
+    if (v.kind == KIND_BLOCK) off += 50 + v.nz * 10 + (v.nz / 2) * 192;
+  }
+  a.b_in = h.lv[h.bottom].b;
+  a.x_out = h.lv[h.bottom].x;
+  a.ainv = h.ainv_d;
+  a.w = h.w_d;
+  return a;
+}
+
+// Every level from h.bottom down, in one launch (LDS-resident, one work-group per component).
+int bottom_cycle(Run& r) {
+  Hierarchy& h = *r.h;
+  NoiseArgs na = make_noise(r, 0, 0, 0, KIND_SMOOTH_NOISE);
+  SMG_HIP(launch_bottom(h.botargs_d, h.desc.ncomp, h.bottom_lds, r.noise, na, r.s));
+  return SMG_OK;
+}
+
 int vcycle(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   const int nu1 = h.prm.nu1, nu2 = h.prm.nu2;
+  if (l == h.bottom && h.use_bottom) return bottom_cycle(r);
+  if (v.kind == KIND_BLOCK && !v.bfac_d) {
+    set_error("internal: block level without tables");
+    return SMG_EINVAL;
+  }
   if (v.kind == KIND_CHOL) return coarsest_step(r, l);
   for (int s = 0; s < nu1; ++s) SMG_TRY(sweep(r, l, s, false));
   if (!v.coarsest) {
     SMG_TRY(restrict_residual(r, l));
     Level& c = h.lv[l + 1];
-    SMG_HIP(launch_zero(c.x, (int64_t)h.desc.ncomp * c.n, r.s));
+    if (l + 1 == h.bottom && !h.use_bottom)
+      SMG_HIP(launch_zero(c.x, (int64_t)h.desc.ncomp * c.n, r.s));
     SMG_TRY(vcycle(r, l + 1));
     SMG_TRY(prolong_add(r, l));
   }
@@ -283,9 +359,13 @@ int smg_bind_workspace(smg_hierarchy* hh, void* dev_ptr, size_t bytes, void* str
     v.b = (double*)(ws + v.off_b);
     v.r = v.kind == KIND_CHOL ? nullptr : (double*)(ws + v.off_r);
     if (v.kind == KIND_BLOCK) {
-      v.coef_d = (double*)(ws + v.off_coef);
+      v.g2d_d = (double*)(ws + v.off_g2d);
+      v.zt_d = (double*)(ws + v.off_zt);
       v.bfac_d = (double*)(ws + v.off_bfac);
-      SMG_HIP(hipMemcpyAsync(v.coef_d, v.coef.data(), v.coef.size() * sizeof(double),
+      v.noise_d = (double*)(ws + v.off_noise);
+      SMG_HIP(hipMemcpyAsync(v.g2d_d, v.g2d.data(), v.g2d.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      SMG_HIP(hipMemcpyAsync(v.zt_d, v.zt.data(), v.zt.size() * sizeof(double),
                              hipMemcpyHostToDevice, s));
       SMG_HIP(hipMemcpyAsync(v.bfac_d, v.bfac.data(), v.bfac.size() * sizeof(double),
                              hipMemcpyHostToDevice, s));
@@ -301,6 +381,12 @@ int smg_bind_workspace(smg_hierarchy* hh, void* dev_ptr, size_t bytes, void* str
   }
   h.part_d = (double*)(ws + h.off_part);
   h.norm_d = (double*)(ws + h.off_norm);
+  BotArgs ba{};
+  if (h.bottom >= 0) {
+    h.botargs_d = (BotArgs*)(ws + h.off_botargs);
+    ba = make_botargs(h);
+    SMG_HIP(hipMemcpyAsync(h.botargs_d, &ba, sizeof(BotArgs), hipMemcpyHostToDevice, s));
+  }
   SMG_HIP(hipStreamSynchronize(s));
   h.ws = ws;
   return SMG_OK;
@@ -326,6 +412,7 @@ int smg_sample_field(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first
   const size_t out_elem = out_dtype == SMG_OUT_F32 ? sizeof(float) : sizeof(double);
   for (int64_t k = 0; k < total; ++k) {
     r.cycle = first_cycle + (uint64_t)k;
+    if (r.noise) SMG_TRY(gen_level_noise(r));
     SMG_TRY(vcycle(r, 0));
     const int64_t after = k + 1 - h.prm.burn_in;
     if (after > 0 && after % h.prm.stride == 0) {
@@ -352,7 +439,8 @@ int smg_solve(smg_hierarchy* hh, const void* f, void* u, double rtol, int32_t ma
   Level& v0 = h.lv[0];
   const int nc = h.desc.ncomp;
   const int64_t field = (int64_t)nc * v0.n;
-  std::vector<double> fn(nc), rn(nc);
+  std::vector<double> fn(nc), rn(nc), rprev(nc, 0.0);
+  double last_ratio = 0.0;
   SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)f, v0.n, nc, s));
   SMG_HIP(hipMemcpyAsync(fn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
   SMG_HIP(hipStreamSynchronize(s));
@@ -384,6 +472,7 @@ int smg_solve(smg_hierarchy* hh, const void* f, void* u, double rtol, int32_t ma
       SMG_HIP(hipMemcpyAsync(rn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
       SMG_HIP(hipStreamSynchronize(s));
       relres = 0.0;
+      last_ratio = 0.0;
       for (int c = 0; c < nc; ++c) {
         if (!std::isfinite(rn[c])) {
           set_error("residual is not finite");
@@ -391,6 +480,11 @@ int smg_solve(smg_hierarchy* hh, const void* f, void* u, double rtol, int32_t ma
         }
         double rr = fn[c] > 0.0 ? std::sqrt(rn[c] / fn[c]) : (rn[c] > 0.0 ? INFINITY : 0.0);
         relres = rr > relres ? rr : relres;
+        if (cycles >= 2 && rprev[c] > 0.0) {
+          double q = std::sqrt(rn[c] / rprev[c]);
+          last_ratio = q > last_ratio ? q : last_ratio;
+        }
+        rprev[c] = rn[c];
       }
       if (relres <= rtol) break;
     }
@@ -400,6 +494,7 @@ int smg_solve(smg_hierarchy* hh, const void* f, void* u, double rtol, int32_t ma
   if (info) {
     info->cycles = cycles;
     info->relres = relres;
+    info->last_ratio = last_ratio;
   }
   if (!all_zero && relres > rtol) {
     set_error("solve did not converge: relres " + std::to_string(relres));
@@ -444,8 +539,10 @@ int smg_debug_smooth(smg_hierarchy* hh, int32_t level, int32_t colour, void* x, 
     SMG_TRY(timed_rb_pass(r, xc, xo, bc, colour, na));
     SMG_TRY(export_level0(h, x, 0, v.x, s));
   } else {
-    SMG_HIP(launch_block_pass((double*)x, (const double*)b, v.coef_d, v.bfac_d, v.nx, v.ny, v.nz,
-                              h.desc.ncomp, colour, r.noise, na, s));
+    if (r.noise) SMG_TRY(gen_level_noise(r, level, slot));
+    SMG_HIP(launch_block_pass((double*)x, (const double*)b, v.g2d_d, v.zt_d, v.bfac_d, v.nx, v.ny,
+                              v.nz, h.desc.ncomp, colour, r.noise ? v.noise_d : nullptr, na.sqkT,
+                              s));
   }
   return SMG_OK;
 }
@@ -473,10 +570,10 @@ int smg_debug_restrict_residual(smg_hierarchy* hh, int32_t level, const void* x,
     SMG_HIP(launch_residual0(v.r, red(v), blk(h, v), b ? bred(v) : nullptr,
                              b ? bblk(h, v) : nullptr, v.nx, v.ny, v.nz, nc, h.desc.h, s));
   } else {
-    SMG_HIP(launch_residual_gal(v.r, (const double*)x, (const double*)b, v.coef_d, v.nx, v.ny,
-                                v.nz, nc, s));
+    SMG_HIP(launch_residual_gal(v.r, (const double*)x, (const double*)b, v.g2d_d, v.zt_d, v.nx,
+                                v.ny, v.nz, nc, s));
   }
-  SMG_HIP(launch_restrict((double*)b_coarse, v.r, v.nx, v.ny, v.nz, nc, s));
+  SMG_HIP(launch_restrict((double*)b_coarse, nullptr, v.r, v.nx, v.ny, v.nz, nc, s));
   return SMG_OK;
 }
 
@@ -545,6 +642,19 @@ int smg_debug_host_table(const smg_hierarchy* hh, int32_t level, int32_t which, 
   }
   std::memcpy(out, src->data(), count * sizeof(double));
   return SMG_OK;
+}
+
+int smg_set_option(smg_hierarchy* hh, int32_t option, int64_t value) {
+  if (!hh) {
+    set_error("null hierarchy");
+    return SMG_EINVAL;
+  }
+  if (option == SMG_OPT_BOTTOM_KERNEL && (value == 0 || value == 1)) {
+    hh->h.use_bottom = value != 0;
+    return SMG_OK;
+  }
+  set_error("unknown option or value");
+  return SMG_EINVAL;
 }
 
 int smg_kernel_timing(smg_hierarchy* hh, int32_t enable) {

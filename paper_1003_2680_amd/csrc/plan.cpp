@@ -132,6 +132,10 @@ std::vector<double> ring_matrix(const double s[5], int n) {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+constexpr int64_t kBottomCells = 4096;
+constexpr size_t kBottomLdsMax = 160 * 1024;
+constexpr int kBottomLevelsMax = 6;
+
 }  // namespace
 
 int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, std::string& err) {
@@ -231,9 +235,24 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
               v.coef[(size_t)k * STENCIL + (oz + 2) * 25 + (oy + 2) * 5 + (ox + 2)] = c;
             }
         }
+      v.g2d.assign(50, 0.0);
+      for (int oy = -2; oy <= 2; ++oy)
+        for (int ox = -2; ox <= 2; ++ox) {
+          v.g2d[(oy + 2) * 5 + (ox + 2)] = v.my[oy + 2] * v.mx[ox + 2];
+          v.g2d[25 + (oy + 2) * 5 + (ox + 2)] =
+              v.ay[oy + 2] * v.mx[ox + 2] + v.my[oy + 2] * v.ax[ox + 2];
+        }
+      v.zt.assign((size_t)v.nz * 10, 0.0);
+      for (int k = 0; k < v.nz; ++k)
+        for (int oz = -2; oz <= 2; ++oz) {
+          int kk = k + oz;
+          if (kk < 0 || kk >= v.nz) continue;
+          v.zt[(size_t)k * 10 + oz + 2] = v.az[(size_t)k * v.nz + kk];
+          v.zt[(size_t)k * 10 + 5 + oz + 2] = v.mz[(size_t)k * v.nz + kk];
+        }
       // exact 8-variable conditionals of the 2x2x2 blocks, one factor per block row
       int nbz = v.nz / 2;
-      v.bfac.assign((size_t)nbz * 128, 0.0);
+      v.bfac.assign((size_t)nbz * 192, 0.0);
       for (int bz = 0; bz < nbz; ++bz) {
         std::vector<double> ABB(64);
         for (int i = 0; i < 8; ++i)
@@ -243,13 +262,14 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
             int zi = 2 * bz + (i >> 2);
             ABB[i * 8 + j] = v.coef[(size_t)zi * STENCIL + (oz + 2) * 25 + (oy + 2) * 5 + (ox + 2)];
           }
+        double* dst = &v.bfac[(size_t)bz * 192];
+        for (int i = 0; i < 64; ++i) dst[128 + i] = ABB[i];
         if (!cholesky(ABB, 8)) {
           err = "block operator not positive definite";
           return SMG_EINVAL;
         }
         std::vector<double> W = lower_inverse(ABB, 8);
         std::vector<double> Ai = inverse_from_w(W, 8);
-        double* dst = &v.bfac[(size_t)bz * 128];
         for (int i = 0; i < 8; ++i)
           for (int j = 0; j < 8; ++j) {
             dst[i * 8 + j] = Ai[i * 8 + j];
@@ -307,14 +327,34 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
     v.off_b = take(field);
     if (v.kind != KIND_CHOL) v.off_r = take(field);
     if (v.kind == KIND_BLOCK) {
-      v.off_coef = take(v.coef.size() * sizeof(double));
+      v.off_g2d = take(v.g2d.size() * sizeof(double));
+      v.off_zt = take(v.zt.size() * sizeof(double));
       v.off_bfac = take(v.bfac.size() * sizeof(double));
+      v.off_noise = take((size_t)(p.nu1 + p.nu2) * nc * v.n * sizeof(double));
     }
+  }
+  // Bottom of the V-cycle: the first Galerkin level with at most kBottomCells cells and every
+  // level below it live in one work-group's LDS per component (x, b and one scratch field per
+  // level; the coarsest draw stages b and the noise).
+  for (int l = 1; l < L; ++l) {
+    if (h.lv[l].n > kBottomCells) continue;
+    size_t lds = 0;
+    for (int m = l; m < L; ++m) {
+      const Level& v = h.lv[m];
+      lds += 3 * bot_field_doubles(v.kind, v.nx, v.ny, v.nz) * sizeof(double);
+      if (v.kind == KIND_BLOCK) lds += (50 + (size_t)v.nz * 10 + (size_t)(v.nz / 2) * 192) * sizeof(double);
+    }
+    if (lds <= kBottomLdsMax && L - l <= kBottomLevelsMax) {
+      h.bottom = l;
+      h.bottom_lds = lds;
+    }
+    break;
   }
   if (h.nc > 0) {
     h.off_ainv = take((size_t)h.nc * h.nc * sizeof(double));
     h.off_w = take((size_t)h.nc * h.nc * sizeof(double));
   }
+  if (h.bottom >= 0) h.off_botargs = take(sizeof(BotArgs));
   // partial sums for the residual norms: one per 256-cell block of level 0
   h.part_len = (size_t)((h.lv[0].n + 255) / 256);
   h.off_part = take((size_t)nc * h.part_len * sizeof(double));

@@ -8,13 +8,9 @@
 #include <vector>
 
 #include "../../include/smg.h"
+#include "kernels.hpp"
 
 namespace smg {
-
-// How a level is smoothed (Sec. "Stochastic Multigrid Methods": the smoother is stochastic
-// Gauss-Seidel; on Galerkin levels a 2x2x2 block heat bath keeps every colour class
-// uncoupled) or, for the coarsest level, drawn exactly.
-enum LevelKind { KIND_POINT = 0, KIND_BLOCK = 1, KIND_CHOL = 2 };
 
 constexpr int STENCIL = 125;  // 5x5x5 offsets of a Galerkin operator row
 
@@ -27,13 +23,20 @@ struct Level {
   double ax[5] = {0}, mx[5] = {0}, ay[5] = {0}, my[5] = {0};  // periodic stencils, offsets -2..2
   std::vector<double> az, mz;                                 // dense nz x nz (walls)
   std::vector<double> coef;  // KIND_BLOCK: [nz][125] row coefficients, index (dz+2)*25+(dy+2)*5+(dx+2)
-  std::vector<double> bfac;  // KIND_BLOCK: [nz/2][2][64]: A_BB^-1 then L_BB^-T (row-major)
+  // The device kernels use the factored form of the same rows:
+  //   coef[k][dz][dy][dx] = zt[k][dz] * g2d[dy][dx] + zt[k][5+dz] * g2d[25 + dy*5 + dx]
+  // with g2d = (m_y m_x, a_y m_x + m_y a_x) (uniform) and zt[k] = (a_z[k][k+dz], m_z[k][k+dz]).
+  std::vector<double> g2d;   // KIND_BLOCK: [2][25]
+  std::vector<double> zt;    // KIND_BLOCK: [nz][10]
+  std::vector<double> bfac;  // KIND_BLOCK: [nz/2][3][64]: A_BB^-1, L_BB^-T, A_BB (row-major)
   // workspace offsets (bytes); level 0 of KIND_POINT stores x and b split by colour
-  size_t off_x = 0, off_b = 0, off_r = 0, off_coef = 0, off_bfac = 0;
+  size_t off_x = 0, off_b = 0, off_r = 0, off_g2d = 0, off_zt = 0, off_bfac = 0, off_noise = 0;
+  double* noise_d = nullptr;  // KIND_BLOCK: pregenerated noise [nu1+nu2][ncomp][n] of one cycle
   double* x = nullptr;
   double* b = nullptr;
   double* r = nullptr;
-  double* coef_d = nullptr;
+  double* g2d_d = nullptr;
+  double* zt_d = nullptr;
   double* bfac_d = nullptr;
 };
 
@@ -41,6 +44,11 @@ struct Hierarchy {
   smg_grid_desc desc{};
   smg_cycle_params prm{};
   std::vector<Level> lv;
+  int bottom = -1;               // first level handled by the LDS-resident bottom kernel
+  size_t bottom_lds = 0;         // its LDS bytes
+  bool use_bottom = true;        // false: run those levels with one launch per pass instead
+  size_t off_botargs = 0;
+  BotArgs* botargs_d = nullptr;  // device copy of the bottom kernel's level descriptors
   int nc = 0;                    // unknowns of the coarsest level when it is drawn exactly
   std::vector<double> ainv, w;   // coarsest A_c^-1 and W = L_c^-1 (row-major, n_c x n_c)
   size_t off_ainv = 0, off_w = 0, off_part = 0, off_norm = 0;

@@ -116,12 +116,13 @@ def test_galerkin_tables_match_oracle(lib, dims, levels):
             A_tab = _matrix_from_table(coef, nx, ny, nz)
             scale = abs(L.A).max()
             assert abs(A_tab - L.A).max() <= 1e-14 * scale
-            bf = _table(lib, hd, L.index, 1, (nz // 2) * 128).reshape(nz // 2, 2, 8, 8)
+            bf = _table(lib, hd, L.index, 1, (nz // 2) * 192).reshape(nz // 2, 3, 8, 8)
             for c, (bid, cells) in enumerate(block_sets(nx, ny, nz)):
                 for k in range(0, len(bid), max(1, len(bid) // 5)):
                     ABB = L.A[cells[k]][:, cells[k]].toarray()
                     bz = cells[k][0] // (nx * ny) // 2
                     Ainv, U = bf[bz, 0], bf[bz, 1]
+                    assert np.max(np.abs(bf[bz, 2] - ABB)) <= 1e-14 * np.max(np.abs(ABB))
                     assert np.max(np.abs(Ainv @ ABB - np.eye(8))) < 1e-12
                     assert np.max(np.abs(U @ U.T @ ABB - np.eye(8))) < 1e-12
                     assert np.max(np.abs(np.tril(U, -1))) == 0.0

@@ -246,3 +246,29 @@ def test_solve_errors():
     assert e.value.code == SMG_ENONFINITE
     u, cycles, relres = H.solve(torch.zeros(H.shape, dtype=torch.float64, device="cuda"))
     assert cycles == 0 and relres == 0.0 and float(u.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("dims,levels,ncomp", [((32, 32, 16), 4, 2), ((16, 16, 16), 3, 1),
+                                               ((64, 32, 32), 0, 1)])
+def test_bottom_kernel_matches_per_pass_launches(dims, levels, ncomp):
+    """The LDS-resident bottom of the V-cycle and the one-launch-per-pass path agree, and both
+    follow the oracle's chain."""
+    _announce("bottom on/off %s L=%d" % (dims, levels))
+    outs = []
+    for use in (True, False):
+        H = _hier(*dims, ncomp=ncomp, levels=levels, coarsest_max=64)
+        H.set_bottom_kernel(use)
+        out, _ = H.sample(3, 21)
+        outs.append(_host(out))
+    assert _relerr(outs[0], outs[1]) <= 1e-13
+    mg = StochasticMG(*dims, levels=levels, coarsest_max=64)
+    ref, _ = mg.sample_chain(3, 21, ncomp=ncomp)
+    assert _relerr(outs[0].reshape(ref.shape), ref) <= RTOL
+    f = gaussian_field((ncomp,) + tuple(reversed(dims)), 3)
+    sols = []
+    for use in (True, False):
+        H = _hier(*dims, ncomp=ncomp, levels=levels, coarsest_max=64)
+        H.set_bottom_kernel(use)
+        u, cycles, relres = H.solve(_dev(f), rtol=1e-11)
+        sols.append(_host(u))
+    assert _relerr(sols[0], sols[1]) <= 1e-12
