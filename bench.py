@@ -39,7 +39,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rb_pass_128cubed_3comp_traffic.js
 
 
 def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_1003_2680_amd", "csrc", "kernels.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_1003_2680_amd", "csrc", "kernels_fine.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -90,8 +90,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the sampler's workload (one 128^3 3-component "
-              "chain) is a single-device job here; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the sampler chains (128^3, 3 components) "
+              "are single-device jobs here; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

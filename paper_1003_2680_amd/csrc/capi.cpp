@@ -7,6 +7,12 @@
 // point is A^-1 f).  Noise counters: level | slot<<4 | colour<<12 | comp<<16 | kind<<24, where
 // slot is the sweep number within the level's visit (pre-sweeps first) and kind is 0 for
 // smoother noise, 1 for the coarsest draw.
+//
+// SMG_FP32_REFINED runs the same cycle in correction form (Alg. 1, with the residual
+// r = b - A x): per cycle r = b - A x in FP64, e = V-cycle(e = 0, rhs r) with FP32 sweeps and
+// transfers (FP64 coarsest arithmetic), x += e in FP64.  In exact arithmetic this is the same
+// chain: every step of the cycle is affine in (x, b), so running it on (x, b) equals x plus
+// running it on (0, b - A x).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -35,9 +41,9 @@ thread_local std::string g_err;
     }                                                                              \
   } while (0)
 
-#define SMG_TRY(expr)        \
-  do {                       \
-    int rc_ = (expr);        \
+#define SMG_TRY(expr)              \
+  do {                             \
+    int rc_ = (expr);              \
     if (rc_ != SMG_OK) return rc_; \
   } while (0)
 
@@ -48,7 +54,7 @@ struct Run {
   Hierarchy* h;
   hipStream_t s;
   bool noise;
-  bool has_b0;      // level-0 right-hand side present (solve)
+  bool has_b0;  // level-0 right-hand side present (solve, and the refined inner cycle)
   uint64_t seed;
   uint64_t cycle;
 };
@@ -64,15 +70,28 @@ NoiseArgs make_noise(const Run& r, int level, int slot, int colour, uint32_t kin
   return na;
 }
 
+bool refined(const Hierarchy& h) { return h.prm.precision == SMG_FP32_REFINED; }
+
 size_t half_field(const Hierarchy& h) { return (size_t)h.desc.ncomp * (h.lv[0].n / 2); }
 
-double* red(Level& v) { return v.x; }
-double* blk(const Hierarchy& h, Level& v) { return v.x + half_field(h); }
-double* bred(Level& v) { return v.b; }
-double* bblk(const Hierarchy& h, Level& v) { return v.b + half_field(h); }
+// The fields a sweep of precision T works on: FP64 mode x, b, r; refined mode xf, bf, rf.
+template <typename T>
+struct Fld;
+template <>
+struct Fld<double> {
+  static double* x(Level& v) { return v.x; }
+  static double* b(Level& v) { return v.b; }
+  static double* r(Level& v) { return v.r; }
+};
+template <>
+struct Fld<float> {
+  static float* x(Level& v) { return v.xf; }
+  static float* b(Level& v) { return v.bf; }
+  static float* r(Level& v) { return v.rf; }
+};
 
-int timed_rb_pass(Run& r, double* xc, const double* xo, const double* bc, int colour,
-                  const NoiseArgs& na) {
+template <typename T>
+int timed_rb_pass(Run& r, T* xc, const T* xo, const T* bc, int colour, const NoiseArgs& na) {
   Hierarchy& h = *r.h;
   const Level& v = h.lv[0];
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -88,77 +107,93 @@ int timed_rb_pass(Run& r, double* xc, const double* xo, const double* bc, int co
     e1 = h.ev_pool[h.ev_used++];
     SMG_HIP(hipEventRecord(e0, r.s));
   }
-  SMG_HIP(launch_rb_pass(xc, xo, bc, v.nx, v.ny, v.nz, h.desc.ncomp, colour, h.desc.h,
-                         h.desc.kT, r.noise, na, r.s));
+  SMG_HIP(launch_rb_pass<T>(xc, xo, bc, v.nx, v.ny, v.nz, h.desc.ncomp, colour, h.desc.h,
+                            h.desc.kT, r.noise, na, r.s));
   if (h.timing) SMG_HIP(hipEventRecord(e1, r.s));
   return SMG_OK;
 }
 
+template <typename T>
 int sweep(Run& r, int l, int slot, bool post) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   const int nc = h.desc.ncomp;
   if (v.kind == KIND_POINT) {
+    T* xr = Fld<T>::x(v);
+    T* xb = xr + half_field(h);
+    const T* br = Fld<T>::b(v);
+    const T* bb = br + half_field(h);
     for (int t = 0; t < 2; ++t) {
       const int colour = post ? 1 - t : t;
       NoiseArgs na = make_noise(r, l, slot, colour, KIND_SMOOTH_NOISE);
-      double* xc = colour ? blk(h, v) : red(v);
-      double* xo = colour ? red(v) : blk(h, v);
-      const double* bc = r.has_b0 ? (colour ? bblk(h, v) : bred(v)) : nullptr;
-      SMG_TRY(timed_rb_pass(r, xc, xo, bc, colour, na));
+      const T* bc = r.has_b0 ? (colour ? bb : br) : nullptr;
+      SMG_TRY(timed_rb_pass<T>(r, colour ? xb : xr, colour ? xr : xb, bc, colour, na));
     }
   } else {
+    const T* noise = (const T*)v.noise_d;
     for (int t = 0; t < 8; ++t) {
       const int colour = post ? 7 - t : t;
-      NoiseArgs na = make_noise(r, l, slot, colour, KIND_SMOOTH_NOISE);
-      const double* zn = r.noise ? v.noise_d + (size_t)slot * nc * v.n : nullptr;
-      SMG_HIP(launch_block_pass(v.x, v.b, v.g2d_d, v.zt_d, v.bfac_d, v.nx, v.ny, v.nz, nc,
-                                colour, zn, na.sqkT, r.s));
+      const T* zn = r.noise ? noise + (size_t)slot * nc * v.n : nullptr;
+      SMG_HIP(launch_block_pass<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.g2d_d,
+                                   (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz, nc,
+                                   colour, zn, std::sqrt(h.desc.kT), r.s));
     }
   }
   return SMG_OK;
 }
 
-// b^(l+1) = P^T (b^(l) - A^(l) x^(l))
+// b^(l+1) = P^T (b^(l) - A^(l) x^(l)); the coarse iterate starts from zero
+template <typename T>
 int restrict_residual(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   const int nc = h.desc.ncomp;
+  T* rr = Fld<T>::r(v);
   if (v.kind == KIND_POINT) {
-    SMG_HIP(launch_residual0(v.r, red(v), blk(h, v), r.has_b0 ? bred(v) : nullptr,
-                             r.has_b0 ? bblk(h, v) : nullptr, v.nx, v.ny, v.nz, nc, h.desc.h,
-                             r.s));
+    T* xr = Fld<T>::x(v);
+    T* br = Fld<T>::b(v);
+    SMG_HIP(launch_residual0<T>(rr, xr, xr + half_field(h), r.has_b0 ? br : nullptr,
+                                r.has_b0 ? br + half_field(h) : nullptr, v.nx, v.ny, v.nz, nc,
+                                h.desc.h, r.s));
   } else {
-    SMG_HIP(launch_residual_gal(v.r, v.x, v.b, v.g2d_d, v.zt_d, v.nx, v.ny, v.nz, nc, r.s));
+    SMG_HIP(launch_residual_gal<T>(rr, Fld<T>::x(v), Fld<T>::b(v), (const T*)v.g2d_d,
+                                   (const T*)v.zt_d, v.nx, v.ny, v.nz, nc, r.s));
   }
-  // the bottom kernel starts its level from zero itself
   Level& c = h.lv[l + 1];
-  SMG_HIP(launch_restrict(c.b, (l + 1 == h.bottom) ? nullptr : c.x, v.r, v.nx, v.ny, v.nz, nc,
-                          r.s));
+  const bool bottom_next = (l + 1 == h.bottom) && h.use_bottom;
+  SMG_HIP(launch_restrict<T>(Fld<T>::b(c), bottom_next ? nullptr : Fld<T>::x(c), rr, v.nx, v.ny,
+                             v.nz, nc, r.s));
   return SMG_OK;
 }
 
+template <typename T>
 int prolong_add(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   const int nc = h.desc.ncomp;
-  if (v.kind == KIND_POINT)
-    SMG_HIP(launch_prolong0(red(v), blk(h, v), h.lv[l + 1].x, v.nx, v.ny, v.nz, nc, r.s));
-  else
-    SMG_HIP(launch_prolong(v.x, h.lv[l + 1].x, v.nx, v.ny, v.nz, nc, r.s));
+  const T* e = Fld<T>::x(h.lv[l + 1]);
+  if (v.kind == KIND_POINT) {
+    T* xr = Fld<T>::x(v);
+    SMG_HIP(launch_prolong0<T>(xr, xr + half_field(h), e, v.nx, v.ny, v.nz, nc, r.s));
+  } else {
+    SMG_HIP(launch_prolong<T>(Fld<T>::x(v), e, v.nx, v.ny, v.nz, nc, r.s));
+  }
   return SMG_OK;
 }
 
+template <typename T>
 int coarsest_step(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   NoiseArgs na = make_noise(r, l, 0, 0, KIND_COARSEST_NOISE);
-  SMG_HIP(launch_coarsest(v.x, v.b, h.ainv_d, h.w_d, h.nc, h.desc.ncomp, r.noise, na, r.s));
+  SMG_HIP(launch_coarsest<T>(Fld<T>::x(v), Fld<T>::b(v), h.ainv_d, h.w_d, h.nc, h.desc.ncomp,
+                             r.noise, na, r.s));
   return SMG_OK;
 }
 
-// Noise of every sweep of every block level (levels l >= 1 with 2x2x2 blocks) for the cycle
-// r.cycle, in one launch (or of one level and slot when level >= 0).
+// Noise of every sweep of every block level for the cycle r.cycle, in one launch (or of one
+// level and slot when only_level >= 0).
+template <typename T>
 int gen_level_noise(Run& r, int only_level = -1, int only_slot = 0) {
   Hierarchy& h = *r.h;
   NoiseGenArgs a{};
@@ -173,22 +208,26 @@ int gen_level_noise(Run& r, int only_level = -1, int only_slot = 0) {
     }
     NoiseLevel& e = a.lv[a.nlev++];
     e.level = l;
-    e.nx = v.nx; e.ny = v.ny; e.nz = v.nz;
+    e.nx = v.nx;
+    e.ny = v.ny;
+    e.nz = v.nz;
     e.nslot = only_level >= 0 ? 1 : h.prm.nu1 + h.prm.nu2;
     e.slot0 = only_level >= 0 ? only_slot : 0;
     e.out = v.noise_d;
     e.calls_before = calls;
     calls += (uint32_t)(e.nslot * a.ncomp * (v.n / 2));
   }
+  if (a.nlev == 0) return SMG_OK;
   a.total = calls;
   NoiseArgs na = make_noise(r, 0, 0, 0, KIND_SMOOTH_NOISE);
-  SMG_HIP(launch_level_noise(a, na, r.s));
+  SMG_HIP(launch_level_noise<T>(a, na, r.s));
   return SMG_OK;
 }
 
 // Level descriptors of the bottom kernel (device pointers are known once bound).
-BotArgs make_botargs(const Hierarchy& h) {
+BotArgs make_botargs(Hierarchy& h) {
   BotArgs a{};
+  const bool f32 = refined(h);
   a.nlev = (int)h.lv.size() - h.bottom;
   a.level0 = h.bottom;
   a.nu1 = h.prm.nu1;
@@ -201,48 +240,68 @@ BotArgs make_botargs(const Hierarchy& h) {
     bot_strides(v.kind, v.nx, v.ny, sy, sz);
     a.lv[i] = BotLevel{v.nx, v.ny, v.nz, v.kind, sy, sz, v.noise_d, v.g2d_d, v.zt_d, v.bfac_d};
     a.lds_off[i] = off;
-    off += 3 * (int)bot_field_doubles(v.kind, v.nx, v.ny, v.nz);
+    off += 3 * (int)bot_field_elems(v.kind, v.nx, v.ny, v.nz);
   }
   for (int i = 0; i < a.nlev; ++i) {
     const Level& v = h.lv[h.bottom + i];
     a.tab_off[i] = off;
     if (v.kind == KIND_BLOCK) off += 50 + v.nz * 10 + (v.nz / 2) * 192;
   }
-  a.b_in = h.lv[h.bottom].b;
-  a.x_out = h.lv[h.bottom].x;
+  Level& b0 = h.lv[h.bottom];
+  a.b_in = f32 ? (const void*)b0.bf : (const void*)b0.b;
+  a.x_out = f32 ? (void*)b0.xf : (void*)b0.x;
   a.ainv = h.ainv_d;
   a.w = h.w_d;
   return a;
 }
 
 // Every level from h.bottom down, in one launch (LDS-resident, one work-group per component).
+template <typename T>
 int bottom_cycle(Run& r) {
   Hierarchy& h = *r.h;
   NoiseArgs na = make_noise(r, 0, 0, 0, KIND_SMOOTH_NOISE);
-  SMG_HIP(launch_bottom(h.botargs_d, h.desc.ncomp, h.bottom_lds, r.noise, na, r.s));
+  SMG_HIP(launch_bottom<T>(h.botargs_d, h.desc.ncomp, h.bottom_lds, r.noise, na, r.s));
   return SMG_OK;
 }
 
+template <typename T>
 int vcycle(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   const int nu1 = h.prm.nu1, nu2 = h.prm.nu2;
-  if (l == h.bottom && h.use_bottom) return bottom_cycle(r);
-  if (v.kind == KIND_BLOCK && !v.bfac_d) {
-    set_error("internal: block level without tables");
-    return SMG_EINVAL;
-  }
-  if (v.kind == KIND_CHOL) return coarsest_step(r, l);
-  for (int s = 0; s < nu1; ++s) SMG_TRY(sweep(r, l, s, false));
+  if (l == h.bottom && h.use_bottom) return bottom_cycle<T>(r);
+  if (v.kind == KIND_CHOL) return coarsest_step<T>(r, l);
+  for (int s = 0; s < nu1; ++s) SMG_TRY(sweep<T>(r, l, s, false));
   if (!v.coarsest) {
-    SMG_TRY(restrict_residual(r, l));
+    SMG_TRY(restrict_residual<T>(r, l));
     Level& c = h.lv[l + 1];
     if (l + 1 == h.bottom && !h.use_bottom)
-      SMG_HIP(launch_zero(c.x, (int64_t)h.desc.ncomp * c.n, r.s));
-    SMG_TRY(vcycle(r, l + 1));
-    SMG_TRY(prolong_add(r, l));
+      SMG_HIP(launch_zero<T>(Fld<T>::x(c), (int64_t)h.desc.ncomp * c.n, r.s));
+    SMG_TRY(vcycle<T>(r, l + 1));
+    SMG_TRY(prolong_add<T>(r, l));
   }
-  for (int s = 0; s < nu2; ++s) SMG_TRY(sweep(r, l, nu1 + s, true));
+  for (int s = 0; s < nu2; ++s) SMG_TRY(sweep<T>(r, l, nu1 + s, true));
+  return SMG_OK;
+}
+
+// One cycle on the FP64 level-0 state x.  Refined mode: residual_ready says that lv[0].bf
+// already holds the FP32 residual of the current x (the solve computes it with the norms).
+int full_cycle(Run& r, bool residual_ready = false) {
+  Hierarchy& h = *r.h;
+  Level& v0 = h.lv[0];
+  if (!refined(h)) {
+    if (r.noise) SMG_TRY(gen_level_noise<double>(r));
+    return vcycle<double>(r, 0);
+  }
+  if (r.noise) SMG_TRY(gen_level_noise<float>(r));
+  if (!residual_ready)
+    SMG_HIP(launch_refine_residual(v0.bf, v0.x, r.has_b0 ? v0.b : nullptr, v0.nx, v0.ny, v0.nz,
+                                   h.desc.ncomp, h.desc.h, nullptr, nullptr, r.s));
+  SMG_HIP(launch_zero<float>(v0.xf, (int64_t)2 * half_field(h), r.s));
+  Run ri = r;
+  ri.has_b0 = true;
+  SMG_TRY(vcycle<float>(ri, 0));
+  SMG_HIP(launch_refine_update(v0.x, v0.xf, (int64_t)2 * half_field(h), r.s));
   return SMG_OK;
 }
 
@@ -285,6 +344,33 @@ int check_ptr(const void* p, const char* what) {
     set_error(std::string(what) + " must be a non-null 256-byte aligned device pointer");
     return SMG_EINVAL;
   }
+  return SMG_OK;
+}
+
+// The per-component entry points drive the FP64 kernels on FP64 level storage.
+int check_fp64(const Hierarchy& h) {
+  if (refined(h)) {
+    set_error("component entry points need a hierarchy created with SMG_FP64");
+    return SMG_EINVAL;
+  }
+  return SMG_OK;
+}
+
+// Block-level tables in the sweep precision T (rounded from the FP64 tables in refined mode).
+template <typename T>
+int upload_tables(Level& v, char* ws, hipStream_t s) {
+  std::vector<T> g(v.g2d.begin(), v.g2d.end());
+  std::vector<T> z(v.zt.begin(), v.zt.end());
+  std::vector<T> b(v.bfac.begin(), v.bfac.end());
+  v.g2d_d = ws + v.off_g2d;
+  v.zt_d = ws + v.off_zt;
+  v.bfac_d = ws + v.off_bfac;
+  v.noise_d = ws + v.off_noise;
+  SMG_HIP(hipMemcpyAsync(v.g2d_d, g.data(), g.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  SMG_HIP(hipMemcpyAsync(v.zt_d, z.data(), z.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  SMG_HIP(hipMemcpyAsync(v.bfac_d, b.data(), b.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  // the staging vectors die on return
+  SMG_HIP(hipStreamSynchronize(s));
   return SMG_OK;
 }
 
@@ -353,22 +439,24 @@ int smg_bind_workspace(smg_hierarchy* hh, void* dev_ptr, size_t bytes, void* str
   }
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)dev_ptr;
+  const bool f32 = refined(h);
   SMG_HIP(hipGetDevice(&h.device));
-  for (Level& v : h.lv) {
-    v.x = (double*)(ws + v.off_x);
-    v.b = (double*)(ws + v.off_b);
-    v.r = v.kind == KIND_CHOL ? nullptr : (double*)(ws + v.off_r);
+  for (size_t l = 0; l < h.lv.size(); ++l) {
+    Level& v = h.lv[l];
+    if (!f32 || l == 0) {
+      v.x = (double*)(ws + v.off_x);
+      v.b = (double*)(ws + v.off_b);
+    }
+    if (!f32) {
+      v.r = v.kind == KIND_CHOL ? nullptr : (double*)(ws + v.off_r);
+    } else {
+      v.xf = (float*)(ws + v.off_xf);
+      v.bf = (float*)(ws + v.off_bf);
+      v.rf = v.kind == KIND_CHOL ? nullptr : (float*)(ws + v.off_rf);
+    }
     if (v.kind == KIND_BLOCK) {
-      v.g2d_d = (double*)(ws + v.off_g2d);
-      v.zt_d = (double*)(ws + v.off_zt);
-      v.bfac_d = (double*)(ws + v.off_bfac);
-      v.noise_d = (double*)(ws + v.off_noise);
-      SMG_HIP(hipMemcpyAsync(v.g2d_d, v.g2d.data(), v.g2d.size() * sizeof(double),
-                             hipMemcpyHostToDevice, s));
-      SMG_HIP(hipMemcpyAsync(v.zt_d, v.zt.data(), v.zt.size() * sizeof(double),
-                             hipMemcpyHostToDevice, s));
-      SMG_HIP(hipMemcpyAsync(v.bfac_d, v.bfac.data(), v.bfac.size() * sizeof(double),
-                             hipMemcpyHostToDevice, s));
+      if (f32) SMG_TRY(upload_tables<float>(v, ws, s));
+      else SMG_TRY(upload_tables<double>(v, ws, s));
     }
   }
   if (h.nc > 0) {
@@ -406,14 +494,13 @@ int smg_sample_field(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first
   Level& v0 = h.lv[0];
   const int64_t field = (int64_t)h.desc.ncomp * v0.n;
   SMG_TRY(import_level0(h, v0.x, (const double*)state, s));
-  if (v0.kind == KIND_CHOL) SMG_HIP(launch_zero(v0.b, field, s));
+  if (v0.kind == KIND_CHOL) SMG_HIP(launch_zero<double>(v0.b, field, s));
   Run r{&h, s, h.desc.kT > 0.0, false, seed, first_cycle};
   const int64_t total = (int64_t)h.prm.burn_in + n * (int64_t)h.prm.stride;
   const size_t out_elem = out_dtype == SMG_OUT_F32 ? sizeof(float) : sizeof(double);
   for (int64_t k = 0; k < total; ++k) {
     r.cycle = first_cycle + (uint64_t)k;
-    if (r.noise) SMG_TRY(gen_level_noise(r));
-    SMG_TRY(vcycle(r, 0));
+    SMG_TRY(full_cycle(r));
     const int64_t after = k + 1 - h.prm.burn_in;
     if (after > 0 && after % h.prm.stride == 0) {
       const int64_t idx = after / h.prm.stride - 1;
@@ -439,6 +526,7 @@ int smg_solve(smg_hierarchy* hh, const void* f, void* u, double rtol, int32_t ma
   Level& v0 = h.lv[0];
   const int nc = h.desc.ncomp;
   const int64_t field = (int64_t)nc * v0.n;
+  const bool f32 = refined(h);
   std::vector<double> fn(nc), rn(nc), rprev(nc, 0.0);
   double last_ratio = 0.0;
   SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)f, v0.n, nc, s));
@@ -450,42 +538,58 @@ int smg_solve(smg_hierarchy* hh, const void* f, void* u, double rtol, int32_t ma
       return SMG_ENONFINITE;
     }
   SMG_TRY(import_level0(h, v0.b, (const double*)f, s));
-  SMG_HIP(launch_zero(v0.x, field, s));
+  SMG_HIP(launch_zero<double>(v0.x, field, s));
   Run r{&h, s, false, true, 0, 0};
   double relres = 0.0;
   bool all_zero = true;
   for (int c = 0; c < nc; ++c) all_zero = all_zero && fn[c] == 0.0;
   int cycles = 0;
+  // squared residual norms of the current iterate -> relres (max over components) and the
+  // contraction of the last cycle; refined mode leaves the FP32 residual in lv[0].bf
+  auto residual_norms = [&]() -> int {
+    if (f32) {
+      SMG_HIP(launch_refine_residual(v0.bf, v0.x, v0.b, v0.nx, v0.ny, v0.nz, nc, h.desc.h,
+                                     h.part_d, h.norm_d, s));
+    } else if (v0.kind == KIND_POINT) {
+      SMG_HIP(launch_residual0<double>(v0.r, v0.x, v0.x + half_field(h), v0.b,
+                                       v0.b + half_field(h), v0.nx, v0.ny, v0.nz, nc, h.desc.h,
+                                       s));
+      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, v0.r, v0.n, nc, s));
+    } else {
+      // a level 0 that is drawn exactly has no residual buffer: u serves as scratch
+      SMG_HIP(launch_residual7_nat((double*)u, v0.x, v0.b, v0.nx, v0.ny, v0.nz, nc, h.desc.h, s));
+      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)u, v0.n, nc, s));
+    }
+    SMG_HIP(hipMemcpyAsync(rn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    SMG_HIP(hipStreamSynchronize(s));
+    relres = 0.0;
+    last_ratio = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      if (!std::isfinite(rn[c])) {
+        set_error("residual is not finite");
+        return SMG_ENONFINITE;
+      }
+      double rr = fn[c] > 0.0 ? std::sqrt(rn[c] / fn[c]) : (rn[c] > 0.0 ? INFINITY : 0.0);
+      relres = rr > relres ? rr : relres;
+      if (cycles >= 2 && rprev[c] > 0.0) {
+        double q = std::sqrt(rn[c] / rprev[c]);
+        last_ratio = q > last_ratio ? q : last_ratio;
+      }
+      rprev[c] = rn[c];
+    }
+    return SMG_OK;
+  };
   if (!all_zero) {
     relres = 1.0;
+    bool ready = false;
+    if (f32 && max_cycles > 0) {
+      SMG_TRY(residual_norms());  // residual of u = 0, i.e. f, rounded to FP32
+      ready = true;
+    }
     while (cycles < max_cycles) {
-      SMG_TRY(vcycle(r, 0));
+      SMG_TRY(full_cycle(r, ready));
       ++cycles;
-      if (v0.kind == KIND_POINT)
-        SMG_HIP(launch_residual0(v0.r, red(v0), blk(h, v0), bred(v0), bblk(h, v0), v0.nx, v0.ny,
-                                 v0.nz, nc, h.desc.h, s));
-      else
-        SMG_HIP(launch_residual7_nat(v0.r ? v0.r : (double*)u, v0.x, v0.b, v0.nx, v0.ny, v0.nz,
-                                     nc, h.desc.h, s));
-      const double* rv = v0.r ? v0.r : (const double*)u;
-      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, rv, v0.n, nc, s));
-      SMG_HIP(hipMemcpyAsync(rn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
-      SMG_HIP(hipStreamSynchronize(s));
-      relres = 0.0;
-      last_ratio = 0.0;
-      for (int c = 0; c < nc; ++c) {
-        if (!std::isfinite(rn[c])) {
-          set_error("residual is not finite");
-          return SMG_ENONFINITE;
-        }
-        double rr = fn[c] > 0.0 ? std::sqrt(rn[c] / fn[c]) : (rn[c] > 0.0 ? INFINITY : 0.0);
-        relres = rr > relres ? rr : relres;
-        if (cycles >= 2 && rprev[c] > 0.0) {
-          double q = std::sqrt(rn[c] / rprev[c]);
-          last_ratio = q > last_ratio ? q : last_ratio;
-        }
-        rprev[c] = rn[c];
-      }
+      SMG_TRY(residual_norms());
       if (relres <= rtol) break;
     }
   }
@@ -517,6 +621,7 @@ int smg_debug_smooth(smg_hierarchy* hh, int32_t level, int32_t colour, void* x, 
   SMG_TRY(check_bound(hh));
   SMG_TRY(check_ptr(x, "x"));
   Hierarchy& h = hh->h;
+  SMG_TRY(check_fp64(h));
   if (level < 0 || level >= (int)h.lv.size() || h.lv[level].kind == KIND_CHOL || slot < 0 ||
       slot > 255) {
     set_error("level has no smoother / invalid slot");
@@ -529,20 +634,22 @@ int smg_debug_smooth(smg_hierarchy* hh, int32_t level, int32_t colour, void* x, 
   }
   hipStream_t s = (hipStream_t)stream;
   Run r{&h, s, with_noise != 0, b != nullptr, seed, cycle};
-  NoiseArgs na = make_noise(r, level, slot, colour, KIND_SMOOTH_NOISE);
   if (v.kind == KIND_POINT) {
+    NoiseArgs na = make_noise(r, level, slot, colour, KIND_SMOOTH_NOISE);
     SMG_TRY(import_level0(h, v.x, (const double*)x, s));
     if (b) SMG_TRY(import_level0(h, v.b, (const double*)b, s));
-    double* xc = colour ? blk(h, v) : red(v);
-    double* xo = colour ? red(v) : blk(h, v);
-    const double* bc = b ? (colour ? bblk(h, v) : bred(v)) : nullptr;
-    SMG_TRY(timed_rb_pass(r, xc, xo, bc, colour, na));
+    double* xr = v.x;
+    double* xb = v.x + half_field(h);
+    const double* bc = b ? (colour ? v.b + half_field(h) : v.b) : nullptr;
+    SMG_TRY(timed_rb_pass<double>(r, colour ? xb : xr, colour ? xr : xb, bc, colour, na));
     SMG_TRY(export_level0(h, x, 0, v.x, s));
   } else {
-    if (r.noise) SMG_TRY(gen_level_noise(r, level, slot));
-    SMG_HIP(launch_block_pass((double*)x, (const double*)b, v.g2d_d, v.zt_d, v.bfac_d, v.nx, v.ny,
-                              v.nz, h.desc.ncomp, colour, r.noise ? v.noise_d : nullptr, na.sqkT,
-                              s));
+    if (r.noise) SMG_TRY(gen_level_noise<double>(r, level, slot));
+    SMG_HIP(launch_block_pass<double>((double*)x, (const double*)b, (const double*)v.g2d_d,
+                                      (const double*)v.zt_d, (const double*)v.bfac_d, v.nx, v.ny,
+                                      v.nz, h.desc.ncomp, colour,
+                                      r.noise ? (const double*)v.noise_d : nullptr,
+                                      std::sqrt(h.desc.kT), s));
   }
   return SMG_OK;
 }
@@ -553,6 +660,7 @@ int smg_debug_restrict_residual(smg_hierarchy* hh, int32_t level, const void* x,
   SMG_TRY(check_ptr(x, "x"));
   SMG_TRY(check_ptr(b_coarse, "b_coarse"));
   Hierarchy& h = hh->h;
+  SMG_TRY(check_fp64(h));
   if (level < 0 || level + 1 >= (int)h.lv.size()) {
     set_error("level has no coarser level");
     return SMG_EINVAL;
@@ -567,13 +675,15 @@ int smg_debug_restrict_residual(smg_hierarchy* hh, int32_t level, const void* x,
   if (v.kind == KIND_POINT) {
     SMG_TRY(import_level0(h, v.x, (const double*)x, s));
     if (b) SMG_TRY(import_level0(h, v.b, (const double*)b, s));
-    SMG_HIP(launch_residual0(v.r, red(v), blk(h, v), b ? bred(v) : nullptr,
-                             b ? bblk(h, v) : nullptr, v.nx, v.ny, v.nz, nc, h.desc.h, s));
+    SMG_HIP(launch_residual0<double>(v.r, v.x, v.x + half_field(h), b ? v.b : nullptr,
+                                     b ? v.b + half_field(h) : nullptr, v.nx, v.ny, v.nz, nc,
+                                     h.desc.h, s));
   } else {
-    SMG_HIP(launch_residual_gal(v.r, (const double*)x, (const double*)b, v.g2d_d, v.zt_d, v.nx,
-                                v.ny, v.nz, nc, s));
+    SMG_HIP(launch_residual_gal<double>(v.r, (const double*)x, (const double*)b,
+                                        (const double*)v.g2d_d, (const double*)v.zt_d, v.nx,
+                                        v.ny, v.nz, nc, s));
   }
-  SMG_HIP(launch_restrict((double*)b_coarse, nullptr, v.r, v.nx, v.ny, v.nz, nc, s));
+  SMG_HIP(launch_restrict<double>((double*)b_coarse, nullptr, v.r, v.nx, v.ny, v.nz, nc, s));
   return SMG_OK;
 }
 
@@ -583,6 +693,7 @@ int smg_debug_prolong_add(smg_hierarchy* hh, int32_t level, void* x, const void*
   SMG_TRY(check_ptr(x, "x"));
   SMG_TRY(check_ptr(e_coarse, "e_coarse"));
   Hierarchy& h = hh->h;
+  SMG_TRY(check_fp64(h));
   if (level < 0 || level + 1 >= (int)h.lv.size()) {
     set_error("level has no coarser level");
     return SMG_EINVAL;
@@ -592,10 +703,11 @@ int smg_debug_prolong_add(smg_hierarchy* hh, int32_t level, void* x, const void*
   const int nc = h.desc.ncomp;
   if (v.kind == KIND_POINT) {
     SMG_TRY(import_level0(h, v.x, (const double*)x, s));
-    SMG_HIP(launch_prolong0(red(v), blk(h, v), (const double*)e_coarse, v.nx, v.ny, v.nz, nc, s));
+    SMG_HIP(launch_prolong0<double>(v.x, v.x + half_field(h), (const double*)e_coarse, v.nx, v.ny,
+                                    v.nz, nc, s));
     SMG_TRY(export_level0(h, x, 0, v.x, s));
   } else {
-    SMG_HIP(launch_prolong((double*)x, (const double*)e_coarse, v.nx, v.ny, v.nz, nc, s));
+    SMG_HIP(launch_prolong<double>((double*)x, (const double*)e_coarse, v.nx, v.ny, v.nz, nc, s));
   }
   return SMG_OK;
 }
@@ -606,6 +718,7 @@ int smg_debug_coarsest(smg_hierarchy* hh, void* x, const void* b, uint64_t seed,
   SMG_TRY(check_ptr(x, "x"));
   SMG_TRY(check_ptr(b, "b"));
   Hierarchy& h = hh->h;
+  SMG_TRY(check_fp64(h));
   if (h.lv.back().kind != KIND_CHOL) {
     set_error("coarsest level is not drawn exactly (SMG_COARSEST_SMOOTH)");
     return SMG_EINVAL;
@@ -614,8 +727,8 @@ int smg_debug_coarsest(smg_hierarchy* hh, void* x, const void* b, uint64_t seed,
   Run r{&h, s, with_noise != 0, false, seed, cycle};
   const int l = (int)h.lv.size() - 1;
   NoiseArgs na = make_noise(r, l, 0, 0, KIND_COARSEST_NOISE);
-  SMG_HIP(launch_coarsest((double*)x, (const double*)b, h.ainv_d, h.w_d, h.nc, h.desc.ncomp,
-                          r.noise, na, s));
+  SMG_HIP(launch_coarsest<double>((double*)x, (const double*)b, h.ainv_d, h.w_d, h.nc,
+                                  h.desc.ncomp, r.noise, na, s));
   return SMG_OK;
 }
 

@@ -23,7 +23,8 @@ __device__ __forceinline__ uint32_t udiv(uint32_t a, uint32_t d, int lg2) {
 }
 
 // 1D prolongation weights for the fine cells 2J-1, 2J, 2J+1, 2J+2 around coarse cell J.
-__device__ __forceinline__ double pw(int i) { return (i == 1 || i == 2) ? 0.75 : 0.25; }
+template <typename T = double>
+__device__ __forceinline__ T pw(int i) { return (i == 1 || i == 2) ? T(0.75) : T(0.25); }
 
 // (A x) at cell (cx, cy, cz) of a Galerkin level, from the factored row coefficients
 //   coef[dz][dy][dx] = zt[cz][dz] g2d[dy][dx] + zt[cz][5+dz] g2d[25 + dy*5 + dx].
@@ -32,11 +33,11 @@ __device__ __forceinline__ double pw(int i) { return (i == 1 || i == 2) ? 0.75 :
 // Fields are addressed as X[z*sz + y*sy + x]; global fields use sy = nx, sz = nx*ny, LDS copies
 // use padded strides (sy = 2 mod 4, sz = 1 mod 4 doubles) so that the 64 lanes of a wave --
 // 8 blocks x 8 cells -- spread evenly over the LDS banks.
-__device__ __forceinline__ double gal_apply(const double* __restrict__ X, int sy, int sz,
-                                            const double* __restrict__ g2d,
-                                            const double* __restrict__ zt, int nx, int ny, int nz,
-                                            int cx, int cy, int cz) {
-  const double* zr = zt + cz * 10;
+template <typename T>
+__device__ __forceinline__ T gal_apply(const T* __restrict__ X, int sy, int sz,
+                                       const T* __restrict__ g2d, const T* __restrict__ zt,
+                                       int nx, int ny, int nz, int cx, int cy, int cz) {
+  const T* zr = zt + cz * 10;
   int xs[5], ys[5];
 #pragma unroll
   for (int d = 0; d < 5; ++d) {
@@ -45,27 +46,27 @@ __device__ __forceinline__ double gal_apply(const double* __restrict__ X, int sy
   }
   // independent partial sums per row keep the dependent FMA chains short (a lone wave cannot
   // hide FMA latency behind other waves on the small levels)
-  double acc0 = 0.0, acc1 = 0.0;
+  T acc0 = 0, acc1 = 0;
 #pragma unroll 1
   for (int dz = 0; dz < 5; ++dz) {
     int zz = cz + dz - 2;
     zz = zz < 0 ? 0 : (zz >= nz ? nz - 1 : zz);
-    double p1[5], p2[5];
+    T p1[5], p2[5];
 #pragma unroll
     for (int dy = 0; dy < 5; ++dy) {
-      const double* row = X + (size_t)zz * sz + (size_t)ys[dy] * sy;
-      double a1 = 0.0, a2 = 0.0;
+      const T* row = X + (size_t)zz * sz + (size_t)ys[dy] * sy;
+      T a1 = 0, a2 = 0;
 #pragma unroll
       for (int dx = 0; dx < 5; ++dx) {
-        const double v = row[xs[dx]];
+        const T v = row[xs[dx]];
         a1 = fma(g2d[dy * 5 + dx], v, a1);
         a2 = fma(g2d[25 + dy * 5 + dx], v, a2);
       }
       p1[dy] = a1;
       p2[dy] = a2;
     }
-    const double s1 = (p1[0] + p1[1]) + (p1[2] + p1[3]) + p1[4];
-    const double s2 = (p2[0] + p2[1]) + (p2[2] + p2[3]) + p2[4];
+    const T s1 = (p1[0] + p1[1]) + (p1[2] + p1[3]) + p1[4];
+    const T s2 = (p2[0] + p2[1]) + (p2[2] + p2[3]) + p2[4];
     acc0 = fma(zr[dz], s1, acc0);
     acc1 = fma(zr[5 + dz], s2, acc1);
   }
@@ -79,33 +80,31 @@ __device__ __forceinline__ double gal_apply(const double* __restrict__ X, int sy
 // lanes of the wave must call this together; inactive lanes pass active = false.
 // The lane's standard normal comes from a pregenerated noise field Z (natural layout of the
 // level: one normal per cell and sweep, drawn from the stream of the cell's block colour).
-template <bool NOISE>
-__device__ __forceinline__ double block_lane(const double* __restrict__ X, int sy, int sz,
-                                             const double* __restrict__ Bv,
-                                             const double* __restrict__ g2d,
-                                             const double* __restrict__ zt,
-                                             const double* __restrict__ bfac, int nx, int ny,
-                                             int nz, int bx, int by, int bz, int k, bool active,
-                                             const double* __restrict__ Z, double sqkT,
-                                             uint32_t& cell_out) {
+template <typename T, bool NOISE>
+__device__ __forceinline__ T block_lane(const T* __restrict__ X, int sy, int sz,
+                                        const T* __restrict__ Bv, const T* __restrict__ g2d,
+                                        const T* __restrict__ zt, const T* __restrict__ bfac,
+                                        int nx, int ny, int nz, int bx, int by, int bz, int k,
+                                        bool active, const T* __restrict__ Z, T sqkT,
+                                        uint32_t& cell_out) {
   const int cx = 2 * bx + (k & 1);
   const int cy = 2 * by + ((k >> 1) & 1);
   const int cz = 2 * bz + (k >> 2);
   const uint32_t cell = (uint32_t)cz * sz + (uint32_t)cy * sy + cx;
   cell_out = cell;
-  double ax = 0.0, xk = 0.0, bk = 0.0, nrm = 0.0;
+  T ax = 0, xk = 0, bk = 0, nrm = 0;
   if (active) {
     if (NOISE) nrm = Z[((uint32_t)cz * ny + cy) * nx + cx];
-    ax = gal_apply(X, sy, sz, g2d, zt, nx, ny, nz, cx, cy, cz);
+    ax = gal_apply<T>(X, sy, sz, g2d, zt, nx, ny, nz, cx, cy, cz);
     xk = X[cell];
     bk = Bv[cell];
   }
-  const double* F = bfac + (size_t)(active ? bz : 0) * 192;
-  double inb = 0.0;
+  const T* F = bfac + (size_t)(active ? bz : 0) * 192;
+  T inb = 0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) inb = fma(F[128 + k * 8 + j], __shfl(xk, j, 8), inb);
-  const double rhs = bk - ax + inb;
-  double v0 = 0.0, v1 = 0.0, w0 = 0.0, w1 = 0.0;
+  const T rhs = bk - ax + inb;
+  T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
 #pragma unroll
   for (int j = 0; j < 8; j += 2) {
     v0 = fma(F[k * 8 + j], __shfl(rhs, j, 8), v0);
@@ -115,31 +114,32 @@ __device__ __forceinline__ double block_lane(const double* __restrict__ X, int s
       w1 = fma(F[64 + k * 8 + j + 1], __shfl(nrm, j + 1, 8), w1);
     }
   }
-  double v = v0 + v1;
+  T v = v0 + v1;
   if (NOISE) v = fma(sqkT, w0 + w1, v);
   return v;
 }
 
 // b_c = P^T r at coarse cell (X,Y,Z): 4x4x4 fine window 2J-1..2J+2 per axis, weights
 // (1/4, 3/4, 3/4, 1/4); on the wall axis the fine cell next to a wall carries 1/2.
-__device__ __forceinline__ double restrict_at(const double* __restrict__ R, int sy, int sz,
-                                              int nxf, int nyf, int nzf, int X, int Y, int Z) {
+template <typename T>
+__device__ __forceinline__ T restrict_at(const T* __restrict__ R, int sy, int sz, int nxf, int nyf,
+                                         int nzf, int X, int Y, int Z) {
   const int nzc = nzf >> 1;
-  double acc = 0.0;
+  T acc = 0;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int zf = 2 * Z - 1 + c;
     if (zf < 0 || zf >= nzf) continue;
-    double wz = pw(c);
-    if ((Z == 0 && zf == 0) || (Z == nzc - 1 && zf == nzf - 1)) wz = 0.5;
+    T wz = pw<T>(c);
+    if ((Z == 0 && zf == 0) || (Z == nzc - 1 && zf == nzf - 1)) wz = T(0.5);
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int yf = wrapm(2 * Y - 1 + b, nyf);
-      const double* Rr = R + (size_t)zf * sz + (size_t)yf * sy;
-      double s = 0.0;
+      const T* Rr = R + (size_t)zf * sz + (size_t)yf * sy;
+      T s = 0;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) s = fma(pw(a), Rr[wrapm(2 * X - 1 + a, nxf)], s);
-      acc = fma(wz * pw(b), s, acc);
+      for (int a = 0; a < 4; ++a) s = fma(pw<T>(a), Rr[wrapm(2 * X - 1 + a, nxf)], s);
+      acc = fma(wz * pw<T>(b), s, acc);
     }
   }
   return acc;
@@ -147,24 +147,26 @@ __device__ __forceinline__ double restrict_at(const double* __restrict__ R, int 
 
 // (P e) at fine cell (xf, yf, zf): trilinear, 3/4 to the own parent and 1/4 to the next one;
 // beyond a wall the ghost parent carries -e, so the wall-layer cell gets 1/2 e.
-__device__ __forceinline__ double prolong_at(const double* __restrict__ E, int sy, int sz, int xf,
-                                             int yf, int zf, int nxc, int nyc, int nzc) {
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T* __restrict__ E, int sy, int sz, int xf, int yf,
+                                        int zf, int nxc, int nyc, int nzc) {
   const int X0 = xf >> 1, Y0 = yf >> 1, Z0 = zf >> 1;
   const int X1 = wrapm((xf & 1) ? X0 + 1 : X0 - 1, nxc);
   const int Y1 = wrapm((yf & 1) ? Y0 + 1 : Y0 - 1, nyc);
   int Z1 = (zf & 1) ? Z0 + 1 : Z0 - 1;
-  double wz0 = 0.75, wz1 = 0.25;
+  T wz0 = T(0.75), wz1 = T(0.25);
   if (Z1 < 0 || Z1 >= nzc) {
-    wz0 = 0.5;
-    wz1 = 0.0;
+    wz0 = T(0.5);
+    wz1 = T(0);
     Z1 = Z0;
   }
-  const double* r00 = E + (size_t)Z0 * sz + (size_t)Y0 * sy;
-  const double* r01 = E + (size_t)Z0 * sz + (size_t)Y1 * sy;
-  const double* r10 = E + (size_t)Z1 * sz + (size_t)Y0 * sy;
-  const double* r11 = E + (size_t)Z1 * sz + (size_t)Y1 * sy;
-  const double p0 = 0.75 * (0.75 * r00[X0] + 0.25 * r00[X1]) + 0.25 * (0.75 * r01[X0] + 0.25 * r01[X1]);
-  const double p1 = 0.75 * (0.75 * r10[X0] + 0.25 * r10[X1]) + 0.25 * (0.75 * r11[X0] + 0.25 * r11[X1]);
+  const T* r00 = E + (size_t)Z0 * sz + (size_t)Y0 * sy;
+  const T* r01 = E + (size_t)Z0 * sz + (size_t)Y1 * sy;
+  const T* r10 = E + (size_t)Z1 * sz + (size_t)Y0 * sy;
+  const T* r11 = E + (size_t)Z1 * sz + (size_t)Y1 * sy;
+  const T q = T(0.75), o = T(0.25);
+  const T p0 = q * (q * r00[X0] + o * r00[X1]) + o * (q * r01[X0] + o * r01[X1]);
+  const T p1 = q * (q * r10[X0] + o * r10[X1]) + o * (q * r11[X0] + o * r11[X1]);
   return wz0 * p0 + wz1 * p1;
 }
 

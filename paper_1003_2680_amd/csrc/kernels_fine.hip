@@ -14,20 +14,32 @@
 namespace smg {
 namespace {
 
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+
+template <typename T>
 struct Diag3 {
-  double inv_d[3];  // h^2 / (6 + walls)
-  double sig[3];    // sqrt(kT h^2 / (6 + walls))
+  T inv_d[3];  // h^2 / (6 + walls)
+  T sig[3];    // sqrt(kT h^2 / (6 + walls))
 };
 
 // Colour pass, nh = nx/2 even: thread (row, jp) owns the two sites j = 2jp, 2jp+1 of a row,
-// i.e. Philox call q = row*nh/2 + jp, and moves them with 16-byte loads and stores.
-template <bool HAS_B, bool NOISE>
-__global__ __launch_bounds__(TPB) void k_rb_pass_v2(double* __restrict__ xc,
-                                                     const double* __restrict__ xo,
-                                                     const double* __restrict__ bc, int nh,
-                                                     int ny, int nz, uint32_t nrowpairs,
-                                                     int lg_nhp, int lg_ny, int colour,
-                                                     double inv_h2, Diag3 dg, NoiseArgs na) {
+// i.e. Philox call q = row*nh/2 + jp, and moves them with one vector load/store each.
+template <typename T, bool HAS_B, bool NOISE>
+__global__ __launch_bounds__(TPB) void k_rb_pass_v2(T* __restrict__ xc, const T* __restrict__ xo,
+                                                     const T* __restrict__ bc, int nh, int ny,
+                                                     int nz, uint32_t nrowpairs, int lg_nhp,
+                                                     int lg_ny, int colour, T inv_h2,
+                                                     Diag3<T> dg, NoiseArgs na) {
+  using V2 = typename Vec2<T>::type;
   const uint32_t comp = blockIdx.y;
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= nrowpairs) return;
@@ -38,59 +50,62 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_v2(double* __restrict__ xc,
   const int y = (int)(row - z * ny);
   const uint32_t nsite = (uint32_t)nh * ny * nz;
   const size_t base = (size_t)comp * nsite;
-  const double* __restrict__ o = xo + base;
+  const T* __restrict__ o = xo + base;
   const uint32_t plane = (uint32_t)nh * ny;
   const uint32_t rb = row * nh;
   const int j0 = 2 * jp;
   const int xs = (y + (int)z + colour) & 1;
   // own row: entries j0, j0+1 and the one beyond on the side the x-neighbours lie
-  const double2 c2 = *reinterpret_cast<const double2*>(o + rb + j0);
+  const V2 c2 = *reinterpret_cast<const V2*>(o + rb + j0);
   const int jx = xs ? (j0 + 2 == nh ? 0 : j0 + 2) : (j0 == 0 ? nh - 1 : j0 - 1);
-  const double ex = o[rb + jx];
+  const T ex = o[rb + jx];
   const int yn = (y + 1 == ny) ? 0 : y + 1;
   const int ys = (y == 0) ? ny - 1 : y - 1;
-  const double2 n2 = *reinterpret_cast<const double2*>(o + (z * ny + yn) * nh + j0);
-  const double2 s2 = *reinterpret_cast<const double2*>(o + (z * ny + ys) * nh + j0);
-  double2 u2 = make_double2(0.0, 0.0), d2 = make_double2(0.0, 0.0);
+  const V2 n2 = *reinterpret_cast<const V2*>(o + (z * ny + yn) * nh + j0);
+  const V2 s2 = *reinterpret_cast<const V2*>(o + (z * ny + ys) * nh + j0);
+  V2 u2, d2;
+  u2.x = u2.y = d2.x = d2.y = T(0);
   int nw = 0;
-  if (z + 1 < (uint32_t)nz) u2 = *reinterpret_cast<const double2*>(o + rb + plane + j0); else ++nw;
-  if (z > 0) d2 = *reinterpret_cast<const double2*>(o + rb - plane + j0); else ++nw;
+  if (z + 1 < (uint32_t)nz) u2 = *reinterpret_cast<const V2*>(o + rb + plane + j0); else ++nw;
+  if (z > 0) d2 = *reinterpret_cast<const V2*>(o + rb - plane + j0); else ++nw;
   // x-neighbour pairs: xs == 0 -> (j-1, j), xs == 1 -> (j, j+1)
-  const double xa0 = xs ? c2.x : ex, xb0 = xs ? c2.y : c2.x;
-  const double xa1 = xs ? c2.y : c2.x, xb1 = xs ? ex : c2.y;
-  double v0 = ((xa0 + xb0) + (n2.x + s2.x) + (u2.x + d2.x)) * inv_h2;
-  double v1 = ((xa1 + xb1) + (n2.y + s2.y) + (u2.y + d2.y)) * inv_h2;
+  const T xa0 = xs ? c2.x : ex, xb0 = xs ? c2.y : c2.x;
+  const T xa1 = xs ? c2.y : c2.x, xb1 = xs ? ex : c2.y;
+  T v0 = ((xa0 + xb0) + (n2.x + s2.x) + (u2.x + d2.x)) * inv_h2;
+  T v1 = ((xa1 + xb1) + (n2.y + s2.y) + (u2.y + d2.y)) * inv_h2;
   if (HAS_B) {
-    const double2 b2 = *reinterpret_cast<const double2*>(bc + base + rb + j0);
+    const V2 b2 = *reinterpret_cast<const V2*>(bc + base + rb + j0);
     v0 += b2.x;
     v1 += b2.y;
   }
   v0 *= dg.inv_d[nw];
   v1 *= dg.inv_d[nw];
   if (NOISE) {
-    double z0, z1;
-    normal_pair(na, comp, row * nhp + jp, z0, z1);
+    T z0, z1;
+    normal_pair_t<T>(na, comp, row * nhp + jp, z0, z1);
     v0 = fma(dg.sig[nw], z0, v0);
     v1 = fma(dg.sig[nw], z1, v1);
   }
-  *reinterpret_cast<double2*>(xc + base + rb + j0) = make_double2(v0, v1);
+  V2 out;
+  out.x = v0;
+  out.y = v1;
+  *reinterpret_cast<V2*>(xc + base + rb + j0) = out;
 }
 
 // Generic colour pass (any even nx): thread q owns colour sites 2q and 2q+1 (one Philox call).
-template <bool HAS_B, bool NOISE>
-__global__ __launch_bounds__(TPB) void k_rb_pass(double* __restrict__ xc,
-                                                  const double* __restrict__ xo,
-                                                  const double* __restrict__ bc, int nh, int ny,
-                                                  int nz, uint32_t nsite, int colour,
-                                                  double inv_h2, Diag3 dg, NoiseArgs na) {
+template <typename T, bool HAS_B, bool NOISE>
+__global__ __launch_bounds__(TPB) void k_rb_pass(T* __restrict__ xc, const T* __restrict__ xo,
+                                                  const T* __restrict__ bc, int nh, int ny, int nz,
+                                                  uint32_t nsite, int colour, T inv_h2,
+                                                  Diag3<T> dg, NoiseArgs na) {
   const uint32_t comp = blockIdx.y;
   const uint32_t q = blockIdx.x * TPB + threadIdx.x;
   const uint32_t p0 = 2u * q;
   if (p0 >= nsite) return;
   const size_t base = (size_t)comp * nsite;
-  const double* __restrict__ o = xo + base;
-  double z0 = 0.0, z1 = 0.0;
-  if (NOISE) normal_pair(na, comp, q, z0, z1);
+  const T* __restrict__ o = xo + base;
+  T z0 = 0, z1 = 0;
+  if (NOISE) normal_pair_t<T>(na, comp, q, z0, z1);
   const uint32_t plane = (uint32_t)nh * ny;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -104,14 +119,14 @@ __global__ __launch_bounds__(TPB) void k_rb_pass(double* __restrict__ xc,
     const uint32_t rb = row * nh;
     const int jl = xs ? j : (j == 0 ? nh - 1 : j - 1);
     const int jr = xs ? (j == nh - 1 ? 0 : j + 1) : j;
-    double s = o[rb + jl] + o[rb + jr];
+    T s = o[rb + jl] + o[rb + jr];
     const int yn = (y + 1 == ny) ? 0 : y + 1;
     const int ys = (y == 0) ? ny - 1 : y - 1;
     s += o[((uint32_t)z * ny + yn) * nh + j] + o[((uint32_t)z * ny + ys) * nh + j];
     int nw = 0;
     if (z + 1 < nz) s += o[rb + j + plane]; else ++nw;
     if (z > 0) s += o[rb + j - plane]; else ++nw;
-    double v = s * inv_h2;
+    T v = s * inv_h2;
     if (HAS_B) v += bc[base + p];
     v *= dg.inv_d[nw];
     if (NOISE) v += dg.sig[nw] * (t == 0 ? z0 : z1);
@@ -119,21 +134,20 @@ __global__ __launch_bounds__(TPB) void k_rb_pass(double* __restrict__ xc,
   }
 }
 
-__device__ __forceinline__ double split_at(const double* __restrict__ xr,
-                                           const double* __restrict__ xb, size_t cbase, int x,
-                                           int y, int z, int nh, int ny) {
-  const double* a = ((x + y + z) & 1) ? xb : xr;
+template <typename T>
+__device__ __forceinline__ T split_at(const T* __restrict__ xr, const T* __restrict__ xb,
+                                      size_t cbase, int x, int y, int z, int nh, int ny) {
+  const T* a = ((x + y + z) & 1) ? xb : xr;
   return a[cbase + ((size_t)z * ny + y) * nh + (x >> 1)];
 }
 
 // r = b - A x on level 0 (split input, natural output).
-template <bool HAS_B>
-__global__ __launch_bounds__(TPB) void k_residual0(double* __restrict__ r,
-                                                    const double* __restrict__ xr,
-                                                    const double* __restrict__ xb,
-                                                    const double* __restrict__ br,
-                                                    const double* __restrict__ bb, int nx, int ny,
-                                                    int nz, uint32_t N, double inv_h2) {
+template <typename T, bool HAS_B>
+__global__ __launch_bounds__(TPB) void k_residual0(T* __restrict__ r, const T* __restrict__ xr,
+                                                    const T* __restrict__ xb,
+                                                    const T* __restrict__ br,
+                                                    const T* __restrict__ bb, int nx, int ny,
+                                                    int nz, uint32_t N, T inv_h2) {
   const uint32_t comp = blockIdx.y;
   const uint32_t i = blockIdx.x * TPB + threadIdx.x;
   if (i >= N) return;
@@ -143,25 +157,78 @@ __global__ __launch_bounds__(TPB) void k_residual0(double* __restrict__ r,
   const int z = row / ny;
   const int nh = nx >> 1;
   const size_t cb = (size_t)comp * (N >> 1);
-  double c = split_at(xr, xb, cb, x, y, z, nh, ny);
-  double s = split_at(xr, xb, cb, wrapm(x - 1, nx), y, z, nh, ny) +
-             split_at(xr, xb, cb, wrapm(x + 1, nx), y, z, nh, ny) +
-             split_at(xr, xb, cb, x, wrapm(y - 1, ny), z, nh, ny) +
-             split_at(xr, xb, cb, x, wrapm(y + 1, ny), z, nh, ny);
+  T c = split_at(xr, xb, cb, x, y, z, nh, ny);
+  T s = split_at(xr, xb, cb, wrapm(x - 1, nx), y, z, nh, ny) +
+        split_at(xr, xb, cb, wrapm(x + 1, nx), y, z, nh, ny) +
+        split_at(xr, xb, cb, x, wrapm(y - 1, ny), z, nh, ny) +
+        split_at(xr, xb, cb, x, wrapm(y + 1, ny), z, nh, ny);
   int nw = 0;
   if (z + 1 < nz) s += split_at(xr, xb, cb, x, y, z + 1, nh, ny); else ++nw;
   if (z > 0) s += split_at(xr, xb, cb, x, y, z - 1, nh, ny); else ++nw;
-  double ax = ((6 + nw) * c - s) * inv_h2;
-  double bv = HAS_B ? split_at(br, bb, cb, x, y, z, nh, ny) : 0.0;
+  T ax = (T(6 + nw) * c - s) * inv_h2;
+  T bv = HAS_B ? split_at(br, bb, cb, x, y, z, nh, ny) : T(0);
   r[(size_t)comp * N + i] = bv - ax;
 }
 
+// FP32-refined bridge: r32 = (float)(b - A x) from FP64 split storage, written split; the
+// optional fixed-order partial sums of (b - A x)^2 go to part[comp][colour*nblk + block].
+template <bool HAS_B, bool NORM>
+__global__ __launch_bounds__(TPB) void k_refine_residual(float* __restrict__ r32,
+                                                          const double* __restrict__ x64,
+                                                          const double* __restrict__ b64, int nx,
+                                                          int ny, int nz, uint32_t nsite,
+                                                          double inv_h2, double* __restrict__ part,
+                                                          uint32_t nblk) {
+  __shared__ double sh[TPB];
+  const uint32_t comp = blockIdx.y;
+  const int colour = blockIdx.z;
+  const uint32_t p = blockIdx.x * TPB + threadIdx.x;
+  const int nh = nx >> 1;
+  const size_t half = (size_t)gridDim.y * nsite;
+  const double* xr = x64;
+  const double* xb = x64 + half;
+  double rr = 0.0;
+  if (p < nsite) {
+    const uint32_t row = p / nh;
+    const int j = p - row * nh;
+    const int y = row % ny;
+    const int z = row / ny;
+    const int x = 2 * j + ((y + z + colour) & 1);
+    const size_t cb = (size_t)comp * nsite;
+    const double c = split_at(xr, xb, cb, x, y, z, nh, ny);
+    double s = split_at(xr, xb, cb, wrapm(x - 1, nx), y, z, nh, ny) +
+               split_at(xr, xb, cb, wrapm(x + 1, nx), y, z, nh, ny) +
+               split_at(xr, xb, cb, x, wrapm(y - 1, ny), z, nh, ny) +
+               split_at(xr, xb, cb, x, wrapm(y + 1, ny), z, nh, ny);
+    int nw = 0;
+    if (z + 1 < nz) s += split_at(xr, xb, cb, x, y, z + 1, nh, ny); else ++nw;
+    if (z > 0) s += split_at(xr, xb, cb, x, y, z - 1, nh, ny); else ++nw;
+    const double bv = HAS_B ? b64[colour * half + cb + p] : 0.0;
+    rr = bv - ((6 + nw) * c - s) * inv_h2;
+    r32[colour * half + cb + p] = (float)rr;
+  }
+  if (NORM) {
+    sh[threadIdx.x] = rr * rr;
+    __syncthreads();
+    for (int st = TPB / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)comp * 2 * nblk + colour * nblk + blockIdx.x] = sh[0];
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_refine_update(double* __restrict__ x64,
+                                                        const float* __restrict__ e32, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * TPB) x64[i] += (double)e32[i];
+}
+
 // x += P e into the split level-0 storage (grid.z = colour).
-__global__ __launch_bounds__(TPB) void k_prolong0(double* __restrict__ xr,
-                                                   double* __restrict__ xb,
-                                                   const double* __restrict__ e, int nxf,
-                                                   int nyf, int nzf, uint32_t nsite,
-                                                   uint32_t Nc) {
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_prolong0(T* __restrict__ xr, T* __restrict__ xb,
+                                                   const T* __restrict__ e, int nxf, int nyf,
+                                                   int nzf, uint32_t nsite, uint32_t Nc) {
   const uint32_t comp = blockIdx.y;
   const int colour = blockIdx.z;
   const uint32_t p = blockIdx.x * TPB + threadIdx.x;
@@ -172,9 +239,9 @@ __global__ __launch_bounds__(TPB) void k_prolong0(double* __restrict__ xr,
   const int yf = row % nyf;
   const int zf = row / nyf;
   const int xf = 2 * j + ((yf + zf + colour) & 1);
-  double* X = (colour ? xb : xr) + (size_t)comp * nsite;
+  T* X = (colour ? xb : xr) + (size_t)comp * nsite;
   const int nxc = nxf >> 1, nyc = nyf >> 1;
-  X[p] += prolong_at(e + (size_t)comp * Nc, nxc, nxc * nyc, xf, yf, zf, nxc, nyc, nzf >> 1);
+  X[p] += prolong_at<T>(e + (size_t)comp * Nc, nxc, nxc * nyc, xf, yf, zf, nxc, nyc, nzf >> 1);
 }
 
 __global__ __launch_bounds__(TPB) void k_to_split(double* __restrict__ xr,
@@ -219,31 +286,32 @@ int ilog2_exact(uint32_t v) {
 
 }  // namespace
 
-hipError_t launch_rb_pass(double* xc, const double* xo, const double* bc, int nx, int ny, int nz,
-                          int ncomp, int colour, double h, double kT, bool noise,
-                          const NoiseArgs& na, hipStream_t s) {
+template <typename T>
+hipError_t launch_rb_pass(T* xc, const T* xo, const T* bc, int nx, int ny, int nz, int ncomp,
+                          int colour, double h, double kT, bool noise, const NoiseArgs& na,
+                          hipStream_t s) {
   const int nh = nx / 2;
   const uint32_t nsite = (uint32_t)nh * ny * nz;
-  Diag3 dg;
+  Diag3<T> dg;
   for (int w = 0; w < 3; ++w) {
-    dg.inv_d[w] = h * h / (6.0 + w);
-    dg.sig[w] = sqrt(kT * h * h / (6.0 + w));
+    dg.inv_d[w] = (T)(h * h / (6.0 + w));
+    dg.sig[w] = (T)sqrt(kT * h * h / (6.0 + w));
   }
-  const double ih2 = 1.0 / (h * h);
+  const T ih2 = (T)(1.0 / (h * h));
   if (nh % 2 == 0) {
     const uint32_t npairs = nsite / 2;
     const int lg_nhp = ilog2_exact((uint32_t)nh / 2), lg_ny = ilog2_exact((uint32_t)ny);
     dim3 grid(blocks_for(npairs), ncomp);
-#define SMG_RB2(HB, NZ)                                                                     \
-  k_rb_pass_v2<HB, NZ><<<grid, TPB, 0, s>>>(xc, xo, bc, nh, ny, nz, npairs, lg_nhp, lg_ny, \
-                                            colour, ih2, dg, na)
+#define SMG_RB2(HB, NZ)                                                                        \
+  k_rb_pass_v2<T, HB, NZ><<<grid, TPB, 0, s>>>(xc, xo, bc, nh, ny, nz, npairs, lg_nhp, lg_ny, \
+                                               colour, ih2, dg, na)
     if (bc) { if (noise) SMG_RB2(true, true); else SMG_RB2(true, false); }
     else { if (noise) SMG_RB2(false, true); else SMG_RB2(false, false); }
 #undef SMG_RB2
   } else {
     dim3 grid(blocks_for((nsite + 1) / 2), ncomp);
 #define SMG_RB(HB, NZ) \
-  k_rb_pass<HB, NZ><<<grid, TPB, 0, s>>>(xc, xo, bc, nh, ny, nz, nsite, colour, ih2, dg, na)
+  k_rb_pass<T, HB, NZ><<<grid, TPB, 0, s>>>(xc, xo, bc, nh, ny, nz, nsite, colour, ih2, dg, na)
     if (bc) { if (noise) SMG_RB(true, true); else SMG_RB(true, false); }
     else { if (noise) SMG_RB(false, true); else SMG_RB(false, false); }
 #undef SMG_RB
@@ -251,22 +319,65 @@ hipError_t launch_rb_pass(double* xc, const double* xo, const double* bc, int nx
   return hipGetLastError();
 }
 
-hipError_t launch_residual0(double* r, const double* xr, const double* xb, const double* br,
-                            const double* bb, int nx, int ny, int nz, int ncomp, double h,
-                            hipStream_t s) {
+template <typename T>
+hipError_t launch_residual0(T* r, const T* xr, const T* xb, const T* br, const T* bb, int nx,
+                            int ny, int nz, int ncomp, double h, hipStream_t s) {
   const uint32_t N = (uint32_t)nx * ny * nz;
   dim3 grid(blocks_for(N), ncomp);
-  if (br) k_residual0<true><<<grid, TPB, 0, s>>>(r, xr, xb, br, bb, nx, ny, nz, N, 1.0 / (h * h));
-  else k_residual0<false><<<grid, TPB, 0, s>>>(r, xr, xb, br, bb, nx, ny, nz, N, 1.0 / (h * h));
+  const T ih2 = (T)(1.0 / (h * h));
+  if (br) k_residual0<T, true><<<grid, TPB, 0, s>>>(r, xr, xb, br, bb, nx, ny, nz, N, ih2);
+  else k_residual0<T, false><<<grid, TPB, 0, s>>>(r, xr, xb, br, bb, nx, ny, nz, N, ih2);
   return hipGetLastError();
 }
 
-hipError_t launch_prolong0(double* xr, double* xb, const double* e, int nxf, int nyf, int nzf,
-                           int ncomp, hipStream_t s) {
+template <typename T>
+hipError_t launch_prolong0(T* xr, T* xb, const T* e, int nxf, int nyf, int nzf, int ncomp,
+                           hipStream_t s) {
   const uint32_t nsite = (uint32_t)(nxf / 2) * nyf * nzf;
   const uint32_t Nc = (uint32_t)(nxf / 2) * (nyf / 2) * (nzf / 2);
   dim3 grid(blocks_for(nsite), ncomp, 2);
-  k_prolong0<<<grid, TPB, 0, s>>>(xr, xb, e, nxf, nyf, nzf, nsite, Nc);
+  k_prolong0<T><<<grid, TPB, 0, s>>>(xr, xb, e, nxf, nyf, nzf, nsite, Nc);
+  return hipGetLastError();
+}
+
+template hipError_t launch_rb_pass<double>(double*, const double*, const double*, int, int, int,
+                                           int, int, double, double, bool, const NoiseArgs&,
+                                           hipStream_t);
+template hipError_t launch_rb_pass<float>(float*, const float*, const float*, int, int, int, int,
+                                          int, double, double, bool, const NoiseArgs&,
+                                          hipStream_t);
+template hipError_t launch_residual0<double>(double*, const double*, const double*, const double*,
+                                             const double*, int, int, int, int, double,
+                                             hipStream_t);
+template hipError_t launch_residual0<float>(float*, const float*, const float*, const float*,
+                                            const float*, int, int, int, int, double, hipStream_t);
+template hipError_t launch_prolong0<double>(double*, double*, const double*, int, int, int, int,
+                                            hipStream_t);
+template hipError_t launch_prolong0<float>(float*, float*, const float*, int, int, int, int,
+                                           hipStream_t);
+
+hipError_t launch_refine_residual(float* r32, const double* x64, const double* b64, int nx,
+                                  int ny, int nz, int ncomp, double h, double* part,
+                                  double* norm, hipStream_t s) {
+  const uint32_t nsite = (uint32_t)(nx / 2) * ny * nz;
+  const uint32_t nblk = blocks_for(nsite);
+  dim3 grid(nblk, ncomp, 2);
+  const double ih2 = 1.0 / (h * h);
+#define SMG_RR(HB, NM) \
+  k_refine_residual<HB, NM><<<grid, TPB, 0, s>>>(r32, x64, b64, nx, ny, nz, nsite, ih2, part, nblk)
+  if (b64) { if (norm) SMG_RR(true, true); else SMG_RR(true, false); }
+  else { if (norm) SMG_RR(false, true); else SMG_RR(false, false); }
+#undef SMG_RR
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !norm) return e;
+  // second stage of the fixed-order sum over the 2*nblk partials of each component
+  return launch_sumsq_final_parts(norm, part, 2 * nblk, ncomp, s);
+}
+
+hipError_t launch_refine_update(double* x64, const float* e32, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t b = (n + TPB - 1) / TPB;
+  k_refine_update<<<(unsigned)(b < 65536 ? b : 65536), TPB, 0, s>>>(x64, e32, n);
   return hipGetLastError();
 }
 

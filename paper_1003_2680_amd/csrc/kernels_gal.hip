@@ -18,6 +18,7 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); 
 
 // Block-level noise for whole sweeps: thread = one Philox call = the two cells (in-block k = 2m,
 // 2m+1) of one block.
+template <typename T>
 __global__ __launch_bounds__(TPB) void k_level_noise(NoiseGenArgs a, NoiseArgs na) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= a.total) return;
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(TPB) void k_level_noise(NoiseGenArgs a, NoiseArgs n
   const uint32_t N = (uint32_t)L.nx * L.ny * L.nz;
   const uint32_t half = N >> 1;
   uint32_t u = t - L.calls_before;
-  const uint32_t q = u % half;          // call within (slot, comp)
+  const uint32_t q = u % half;  // call within (slot, comp)
   u /= half;
   const uint32_t comp = u % (uint32_t)a.ncomp;
   const uint32_t s = u / (uint32_t)a.ncomp;
@@ -40,11 +41,11 @@ __global__ __launch_bounds__(TPB) void k_level_noise(NoiseGenArgs a, NoiseArgs n
   const int colour = (bx & 1) + 2 * (by & 1) + 4 * (bz & 1);
   NoiseArgs nl = na;
   nl.sid = (uint32_t)L.level | ((uint32_t)(L.slot0 + s) << 4) | ((uint32_t)colour << 12);
-  double z0, z1;
-  normal_pair(nl, comp, q, z0, z1);
-  const int dy = m & 1, dz = m >> 1;   // in-block index k = 2m + dx
+  T z0, z1;
+  normal_pair_t<T>(nl, comp, q, z0, z1);
+  const int dy = m & 1, dz = m >> 1;  // in-block index k = 2m + dx
   const uint32_t c0 = ((uint32_t)(2 * bz + dz) * L.ny + (2 * by + dy)) * L.nx + 2 * bx;
-  double* out = L.out + ((size_t)s * a.ncomp + comp) * N;
+  T* out = (T*)L.out + ((size_t)s * a.ncomp + comp) * N;
   out[c0] = z0;
   out[c0 + 1] = z1;
 }
@@ -59,18 +60,17 @@ constexpr int TILE_I = 4, TILE_J = 4;
 constexpr int TILE_W = 4 * TILE_I + 2, TILE_H = 4 * TILE_J + 2, TILE_D = 6;
 constexpr int TILE_TPB = TILE_I * TILE_J * 8;
 
-template <bool NOISE>
-__global__ __launch_bounds__(TILE_TPB) void k_block_tile(double* __restrict__ xg,
-                                                          const double* __restrict__ bg,
-                                                          const double* __restrict__ g2d,
-                                                          const double* __restrict__ zt,
-                                                          const double* __restrict__ bfac, int nx,
+template <typename T, bool NOISE>
+__global__ __launch_bounds__(TILE_TPB) void k_block_tile(T* __restrict__ xg,
+                                                          const T* __restrict__ bg,
+                                                          const T* __restrict__ g2d,
+                                                          const T* __restrict__ zt,
+                                                          const T* __restrict__ bfac, int nx,
                                                           int ny, int nz, uint32_t N, int colour,
                                                           int nbx2, int nby2, int ntx,
-                                                          const double* __restrict__ zn,
-                                                          double sqkT) {
-  constexpr int TP = TILE_H * TILE_W + 1;  // plane stride: 1 mod 4 doubles (row stride 18)
-  __shared__ double T[TILE_D * TP];
+                                                          const T* __restrict__ zn, T sqkT) {
+  constexpr int TP = TILE_H * TILE_W + 1;  // plane stride: 1 mod 4 elements (row stride 18)
+  __shared__ T Tl[TILE_D * TP];
   const uint32_t comp = blockIdx.z;
   const int l = blockIdx.y;
   const int ti = blockIdx.x % ntx, tj = blockIdx.x / ntx;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_block_tile(double* __restrict__ xg
   const int bz = 2 * l + (colour >> 2);
   const int i0 = ti * TILE_I, j0 = tj * TILE_J;
   const int x0 = 4 * i0 + 2 * cx - 2, y0 = 4 * j0 + 2 * cy - 2, z0 = 2 * bz - 2;
-  double* X = xg + (size_t)comp * N;
+  T* X = xg + (size_t)comp * N;
   const int tid = threadIdx.x;
   for (int q = tid; q < TILE_D * TILE_H * TILE_W; q += TILE_TPB) {
     const int tx = q % TILE_W;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_block_tile(double* __restrict__ xg
     int gx = (x0 + tx) % nx; gx += gx < 0 ? nx : 0;
     int gy = (y0 + ty) % ny; gy += gy < 0 ? ny : 0;
     int gz = z0 + tz; gz = gz < 0 ? 0 : (gz >= nz ? nz - 1 : gz);
-    T[tz * TP + ty * TILE_W + tx] = X[((size_t)gz * ny + gy) * nx + gx];
+    Tl[tz * TP + ty * TILE_W + tx] = X[((size_t)gz * ny + gy) * nx + gx];
   }
   __syncthreads();
   const int k = tid & 7;
@@ -100,21 +100,21 @@ __global__ __launch_bounds__(TILE_TPB) void k_block_tile(double* __restrict__ xg
   const int tx = 4 * il + 2 + kx, ty = 4 * jl + 2 + ky, tz = 2 + kz;
   const int gcx = 2 * bx + kx, gcy = 2 * by + ky, gcz = 2 * bz + kz;
   const uint32_t cell = ((uint32_t)gcz * ny + gcy) * nx + gcx;
-  double ax = 0.0, xk = 0.0, bk = 0.0, nrm = 0.0;
+  T ax = 0, xk = 0, bk = 0, nrm = 0;
   if (active) {
     if (NOISE) nrm = zn[(size_t)comp * N + cell];
-    const double* zr = zt + gcz * 10;
-    double ax0 = 0.0, ax1 = 0.0;
+    const T* zr = zt + gcz * 10;
+    T ax0 = 0, ax1 = 0;
 #pragma unroll
     for (int dz = 0; dz < 5; ++dz) {
-      double p1[5], p2[5];
+      T p1[5], p2[5];
 #pragma unroll
       for (int dy = 0; dy < 5; ++dy) {
-        const double* row = T + (tz + dz - 2) * TP + (ty + dy - 2) * TILE_W + tx - 2;
-        double a1 = 0.0, a2 = 0.0;
+        const T* row = Tl + (tz + dz - 2) * TP + (ty + dy - 2) * TILE_W + tx - 2;
+        T a1 = 0, a2 = 0;
 #pragma unroll
         for (int dx = 0; dx < 5; ++dx) {
-          const double v = row[dx];
+          const T v = row[dx];
           a1 = fma(g2d[dy * 5 + dx], v, a1);
           a2 = fma(g2d[25 + dy * 5 + dx], v, a2);
         }
@@ -125,15 +125,15 @@ __global__ __launch_bounds__(TILE_TPB) void k_block_tile(double* __restrict__ xg
       ax1 = fma(zr[5 + dz], (p2[0] + p2[1]) + (p2[2] + p2[3]) + p2[4], ax1);
     }
     ax = ax0 + ax1;
-    xk = T[tz * TP + ty * TILE_W + tx];
+    xk = Tl[tz * TP + ty * TILE_W + tx];
     bk = bg[(size_t)comp * N + cell];
   }
-  const double* F = bfac + (size_t)bz * 192;
-  double inb = 0.0;
+  const T* F = bfac + (size_t)bz * 192;
+  T inb = 0;
 #pragma unroll
   for (int jj = 0; jj < 8; ++jj) inb = fma(F[128 + k * 8 + jj], __shfl(xk, jj, 8), inb);
-  const double rhs = bk - ax + inb;
-  double v0 = 0.0, v1 = 0.0, w0 = 0.0, w1 = 0.0;
+  const T rhs = bk - ax + inb;
+  T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
 #pragma unroll
   for (int jj = 0; jj < 8; jj += 2) {
     v0 = fma(F[k * 8 + jj], __shfl(rhs, jj, 8), v0);
@@ -143,18 +143,18 @@ __global__ __launch_bounds__(TILE_TPB) void k_block_tile(double* __restrict__ xg
       w1 = fma(F[64 + k * 8 + jj + 1], __shfl(nrm, jj + 1, 8), w1);
     }
   }
-  double v = v0 + v1;
+  T v = v0 + v1;
   if (NOISE) v = fma(sqkT, w0 + w1, v);
   if (active) X[cell] = v;
 }
 
 // r = b - A x on a Galerkin level
-__global__ __launch_bounds__(TPB) void k_residual_gal(double* __restrict__ r,
-                                                       const double* __restrict__ xg,
-                                                       const double* __restrict__ bg,
-                                                       const double* __restrict__ g2d,
-                                                       const double* __restrict__ zt, int nx,
-                                                       int ny, int nz, uint32_t N) {
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_residual_gal(T* __restrict__ r, const T* __restrict__ xg,
+                                                       const T* __restrict__ bg,
+                                                       const T* __restrict__ g2d,
+                                                       const T* __restrict__ zt, int nx, int ny,
+                                                       int nz, uint32_t N) {
   const uint32_t comp = blockIdx.y;
   const uint32_t i = blockIdx.x * TPB + threadIdx.x;
   if (i >= N) return;
@@ -162,14 +162,15 @@ __global__ __launch_bounds__(TPB) void k_residual_gal(double* __restrict__ r,
   const uint32_t row = i / nx;
   const int y = row % ny;
   const int z = row / ny;
-  const double ax = gal_apply(xg + (size_t)comp * N, nx, nx * ny, g2d, zt, nx, ny, nz, x, y, z);
+  const T ax = gal_apply<T>(xg + (size_t)comp * N, nx, nx * ny, g2d, zt, nx, ny, nz, x, y, z);
   r[(size_t)comp * N + i] = bg[(size_t)comp * N + i] - ax;
 }
 
 // b_c = P^T r, and x_c = 0 (the coarse iterate of Alg. 3 starts from zero)
-__global__ __launch_bounds__(TPB) void k_restrict(double* __restrict__ bc, double* __restrict__ xc,
-                                                   const double* __restrict__ r, int nxf,
-                                                   int nyf, int nzf, uint32_t Nf, uint32_t Nc) {
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_restrict(T* __restrict__ bc, T* __restrict__ xc,
+                                                   const T* __restrict__ r, int nxf, int nyf,
+                                                   int nzf, uint32_t Nf, uint32_t Nc) {
   const uint32_t comp = blockIdx.y;
   const uint32_t I = blockIdx.x * TPB + threadIdx.x;
   if (I >= Nc) return;
@@ -178,13 +179,15 @@ __global__ __launch_bounds__(TPB) void k_restrict(double* __restrict__ bc, doubl
   const uint32_t row = I / nxc;
   const int Y = row % nyc;
   const int Z = row / nyc;
-  bc[(size_t)comp * Nc + I] = restrict_at(r + (size_t)comp * Nf, nxf, nxf * nyf, nxf, nyf, nzf, X, Y, Z);
-  if (xc) xc[(size_t)comp * Nc + I] = 0.0;
+  bc[(size_t)comp * Nc + I] =
+      restrict_at<T>(r + (size_t)comp * Nf, nxf, nxf * nyf, nxf, nyf, nzf, X, Y, Z);
+  if (xc) xc[(size_t)comp * Nc + I] = T(0);
 }
 
-__global__ __launch_bounds__(TPB) void k_prolong(double* __restrict__ x,
-                                                  const double* __restrict__ e, int nxf, int nyf,
-                                                  int nzf, uint32_t Nf, uint32_t Nc) {
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_prolong(T* __restrict__ x, const T* __restrict__ e,
+                                                  int nxf, int nyf, int nzf, uint32_t Nf,
+                                                  uint32_t Nc) {
   const uint32_t comp = blockIdx.y;
   const uint32_t i = blockIdx.x * TPB + threadIdx.x;
   if (i >= Nf) return;
@@ -194,21 +197,20 @@ __global__ __launch_bounds__(TPB) void k_prolong(double* __restrict__ x,
   const int zf = row / nyf;
   const int nxc = nxf >> 1, nyc = nyf >> 1;
   x[(size_t)comp * Nf + i] +=
-      prolong_at(e + (size_t)comp * Nc, nxc, nxc * nyc, xf, yf, zf, nxc, nyc, nzf >> 1);
+      prolong_at<T>(e + (size_t)comp * Nc, nxc, nxc * nyc, xf, yf, zf, nxc, nyc, nzf >> 1);
 }
 
-// x = A_c^-1 b (+ sqrt(kT) L_c^-T n): rows split over work-groups; each work-group stages b and
-// the whole noise vector in LDS.
-template <bool NOISE>
-__global__ __launch_bounds__(TPB) void k_coarsest(double* __restrict__ xg,
-                                                   const double* __restrict__ bg,
+// x = A_c^-1 b (+ sqrt(kT) L_c^-T n) in FP64: rows split over work-groups; each work-group
+// stages b and the whole noise vector in LDS.
+template <typename T, bool NOISE>
+__global__ __launch_bounds__(TPB) void k_coarsest(T* __restrict__ xg, const T* __restrict__ bg,
                                                    const double* __restrict__ ainv,
                                                    const double* __restrict__ w, int n,
                                                    NoiseArgs na) {
   extern __shared__ double sh[];
   const uint32_t comp = blockIdx.y;
-  const double* B = bg + (size_t)comp * n;
-  for (int i = threadIdx.x; i < n; i += TPB) sh[i] = B[i];
+  const T* B = bg + (size_t)comp * n;
+  for (int i = threadIdx.x; i < n; i += TPB) sh[i] = (double)B[i];
   if (NOISE) {
     for (int q = threadIdx.x; 2 * q < n; q += TPB) {
       double z0, z1;
@@ -227,23 +229,22 @@ __global__ __launch_bounds__(TPB) void k_coarsest(double* __restrict__ xg,
     for (int jj = row; jj < n; ++jj) an = fma(w[(size_t)jj * n + row], sh[n + jj], an);
     acc = fma(na.sqkT, an, acc);
   }
-  xg[(size_t)comp * n + row] = acc;
+  xg[(size_t)comp * n + row] = (T)acc;
 }
 
 // ----------------------------------------------------------------------------- bottom of the V
 // One work-group per component runs every level from the bottom level down to the coarsest
 // and back up, with x, b and a scratch field of each level in LDS; only b of the bottom level
 // comes from global memory and only its x goes back.  Colour passes are separated by
-// work-group barriers instead of kernel launches.
+// work-group barriers instead of kernel launches.  The coarsest draw is FP64 in every mode.
 constexpr int BOT_TPB = 512;
 
-template <bool NOISE>
-__device__ __forceinline__ void bot_block_pass(double* X, const double* Bv, const BotLevel& L,
-                                               const double* tab, int colour, const double* Z,
-                                               double sqkT) {
-  const double* g2d = tab;
-  const double* zt = tab + 50;
-  const double* bfac = tab + 50 + L.nz * 10;
+template <typename T, bool NOISE>
+__device__ __forceinline__ void bot_block_pass(T* X, const T* Bv, const BotLevel& L, const T* tab,
+                                               int colour, const T* Z, T sqkT) {
+  const T* g2d = tab;
+  const T* zt = tab + 50;
+  const T* bfac = tab + 50 + L.nz * 10;
   const int nbx2 = L.nx / 4, nby2 = L.ny / 4;
   const int nbzc = (L.nz / 2 + 1 - (colour >> 2)) / 2;
   const int total = nbx2 * nby2 * nbzc * 8;
@@ -257,23 +258,22 @@ __device__ __forceinline__ void bot_block_pass(double* X, const double* Bv, cons
     const int j = rest % nby2;
     const int l = rest / nby2;
     uint32_t cell;
-    const double v = block_lane<NOISE>(X, L.sy, L.sz, Bv, g2d, zt, bfac, L.nx, L.ny, L.nz,
-                                       2 * i + (colour & 1), 2 * j + ((colour >> 1) & 1),
-                                       2 * l + (colour >> 2), k, active, Z, sqkT, cell);
+    const T v = block_lane<T, NOISE>(X, L.sy, L.sz, Bv, g2d, zt, bfac, L.nx, L.ny, L.nz,
+                                     2 * i + (colour & 1), 2 * j + ((colour >> 1) & 1),
+                                     2 * l + (colour >> 2), k, active, Z, sqkT, cell);
     if (active) X[cell] = v;
   }
   __syncthreads();
 }
 
-template <bool NOISE>
-__device__ __forceinline__ void bot_sweep(double* X, const double* Bv, const BotLevel& L,
-                                          const double* tab, int slot, bool post, int ncomp,
-                                          uint32_t comp, double sqkT) {
+template <typename T, bool NOISE>
+__device__ __forceinline__ void bot_sweep(T* X, const T* Bv, const BotLevel& L, const T* tab,
+                                          int slot, bool post, int ncomp, uint32_t comp, T sqkT) {
   const int n = L.nx * L.ny * L.nz;
-  const double* Z = NOISE ? L.noise + ((size_t)slot * ncomp + comp) * n : nullptr;
+  const T* Z = NOISE ? (const T*)L.noise + ((size_t)slot * ncomp + comp) * n : nullptr;
   for (int t = 0; t < 8; ++t) {
     const int colour = post ? 7 - t : t;
-    bot_block_pass<NOISE>(X, Bv, L, tab, colour, Z, sqkT);
+    bot_block_pass<T, NOISE>(X, Bv, L, tab, colour, Z, sqkT);
   }
 }
 
@@ -283,27 +283,32 @@ __device__ __forceinline__ int bot_pos(const BotLevel& L, int q) {
   return z * L.sz + y * L.sy + x;
 }
 
-template <bool NOISE>
+template <typename T, bool NOISE>
 __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ ap, NoiseArgs na) {
-  extern __shared__ double sm[];
+  extern __shared__ char smraw[];
+  T* sm = reinterpret_cast<T*>(smraw);
   const BotArgs& a = *ap;
   const uint32_t comp = blockIdx.x;
   const int tid = threadIdx.x;
+  const T sqkT = (T)na.sqkT;
   const BotLevel& L0 = a.lv[0];
   const int n0 = L0.nx * L0.ny * L0.nz;
   const int f0 = L0.nz * L0.sz;
-  for (int q = tid; q < f0; q += BOT_TPB) sm[a.lds_off[0] + q] = 0.0;
+  for (int q = tid; q < f0; q += BOT_TPB) sm[a.lds_off[0] + q] = T(0);
   __syncthreads();
   for (int q = tid; q < n0; q += BOT_TPB)
-    sm[a.lds_off[0] + f0 + bot_pos(L0, q)] = a.b_in[(size_t)comp * n0 + q];
+    sm[a.lds_off[0] + f0 + bot_pos(L0, q)] = ((const T*)a.b_in)[(size_t)comp * n0 + q];
   // operator tables of the block levels: [g2d 50][zt nz*10][bfac nz/2*192] at tab_off[i]
   for (int i = 0; i < a.nlev; ++i) {
     if (a.lv[i].kind != KIND_BLOCK) continue;
     const int nz = a.lv[i].nz;
-    double* t = sm + a.tab_off[i];
-    for (int q = tid; q < 50; q += BOT_TPB) t[q] = a.lv[i].g2d[q];
-    for (int q = tid; q < nz * 10; q += BOT_TPB) t[50 + q] = a.lv[i].zt[q];
-    for (int q = tid; q < (nz / 2) * 192; q += BOT_TPB) t[50 + nz * 10 + q] = a.lv[i].bfac[q];
+    T* t = sm + a.tab_off[i];
+    const T* g = (const T*)a.lv[i].g2d;
+    const T* zt = (const T*)a.lv[i].zt;
+    const T* bf = (const T*)a.lv[i].bfac;
+    for (int q = tid; q < 50; q += BOT_TPB) t[q] = g[q];
+    for (int q = tid; q < nz * 10; q += BOT_TPB) t[50 + q] = zt[q];
+    for (int q = tid; q < (nz / 2) * 192; q += BOT_TPB) t[50 + nz * 10 + q] = bf[q];
   }
   __syncthreads();
   int last = a.nlev - 1;
@@ -312,9 +317,9 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
     const int level = a.level0 + i;
     const int n = L.nx * L.ny * L.nz;
     const int f = L.nz * L.sz;
-    double* xi = sm + a.lds_off[i];
-    double* bi = xi + f;
-    double* ri = bi + f;
+    T* xi = sm + a.lds_off[i];
+    T* bi = xi + f;
+    T* ri = bi + f;
     if (L.kind == KIND_CHOL) {
       // exact draw x = A_c^-1 b + sqrt(kT) L_c^-T n (natural layout on this level)
       if (NOISE) {
@@ -323,32 +328,33 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
         for (int q = tid; 2 * q < n; q += BOT_TPB) {
           double z0, z1;
           normal_pair(nc, comp, (uint32_t)q, z0, z1);
-          ri[2 * q] = z0;
-          if (2 * q + 1 < n) ri[2 * q + 1] = z1;
+          ri[2 * q] = (T)z0;
+          if (2 * q + 1 < n) ri[2 * q + 1] = (T)z1;
         }
         __syncthreads();
       }
       for (int row = tid; row < n; row += BOT_TPB) {
         double acc = 0.0;
-        for (int jj = 0; jj < n; ++jj) acc = fma(a.ainv[(size_t)jj * n + row], bi[jj], acc);
+        for (int jj = 0; jj < n; ++jj)
+          acc = fma(a.ainv[(size_t)jj * n + row], (double)bi[jj], acc);
         if (NOISE) {
           double an = 0.0;
-          for (int jj = row; jj < n; ++jj) an = fma(a.w[(size_t)jj * n + row], ri[jj], an);
+          for (int jj = row; jj < n; ++jj) an = fma(a.w[(size_t)jj * n + row], (double)ri[jj], an);
           acc = fma(na.sqkT, an, acc);
         }
-        xi[row] = acc;
+        xi[row] = (T)acc;
       }
       __syncthreads();
       last = i;
       break;
     }
-    const double* tab = sm + a.tab_off[i];
+    const T* tab = sm + a.tab_off[i];
     for (int s = 0; s < a.nu1; ++s)
-      bot_sweep<NOISE>(xi, bi, L, tab, s, false, a.ncomp, comp, na.sqkT);
+      bot_sweep<T, NOISE>(xi, bi, L, tab, s, false, a.ncomp, comp, sqkT);
     if (i == a.nlev - 1) {
       // smoothing-only coarsest level: the post-sweeps follow at once
       for (int s = 0; s < a.nu2; ++s)
-        bot_sweep<NOISE>(xi, bi, L, tab, a.nu1 + s, true, a.ncomp, comp, na.sqkT);
+        bot_sweep<T, NOISE>(xi, bi, L, tab, a.nu1 + s, true, a.ncomp, comp, sqkT);
       last = i;
       break;
     }
@@ -356,17 +362,17 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
     for (int q = tid; q < n; q += BOT_TPB) {
       const int x = q % L.nx, y = (q / L.nx) % L.ny, z = q / (L.nx * L.ny);
       const int p = z * L.sz + y * L.sy + x;
-      ri[p] = bi[p] - gal_apply(xi, L.sy, L.sz, tab, tab + 50, L.nx, L.ny, L.nz, x, y, z);
+      ri[p] = bi[p] - gal_apply<T>(xi, L.sy, L.sz, tab, tab + 50, L.nx, L.ny, L.nz, x, y, z);
     }
     __syncthreads();
     const BotLevel& C = a.lv[i + 1];
     const int nc = C.nx * C.ny * C.nz;
     const int fc = C.nz * C.sz;
-    double* xc = sm + a.lds_off[i + 1];
-    for (int q = tid; q < fc; q += BOT_TPB) xc[q] = 0.0;
+    T* xc = sm + a.lds_off[i + 1];
+    for (int q = tid; q < fc; q += BOT_TPB) xc[q] = T(0);
     for (int q = tid; q < nc; q += BOT_TPB) {
       const int X = q % C.nx, Y = (q / C.nx) % C.ny, Z = q / (C.nx * C.ny);
-      xc[fc + Z * C.sz + Y * C.sy + X] = restrict_at(ri, L.sy, L.sz, L.nx, L.ny, L.nz, X, Y, Z);
+      xc[fc + Z * C.sz + Y * C.sy + X] = restrict_at<T>(ri, L.sy, L.sz, L.nx, L.ny, L.nz, X, Y, Z);
     }
     __syncthreads();
   }
@@ -374,95 +380,115 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
     const BotLevel& L = a.lv[i];
     const BotLevel& C = a.lv[i + 1];
     const int n = L.nx * L.ny * L.nz;
-    double* xi = sm + a.lds_off[i];
-    const double* xc = sm + a.lds_off[i + 1];
+    T* xi = sm + a.lds_off[i];
+    const T* xc = sm + a.lds_off[i + 1];
     for (int q = tid; q < n; q += BOT_TPB) {
       const int x = q % L.nx, y = (q / L.nx) % L.ny, z = q / (L.nx * L.ny);
-      xi[z * L.sz + y * L.sy + x] += prolong_at(xc, C.sy, C.sz, x, y, z, C.nx, C.ny, C.nz);
+      xi[z * L.sz + y * L.sy + x] += prolong_at<T>(xc, C.sy, C.sz, x, y, z, C.nx, C.ny, C.nz);
     }
     __syncthreads();
     for (int s = 0; s < a.nu2; ++s)
-      bot_sweep<NOISE>(xi, xi + L.nz * L.sz, L, sm + a.tab_off[i], a.nu1 + s, true, a.ncomp,
-                       comp, na.sqkT);
+      bot_sweep<T, NOISE>(xi, xi + L.nz * L.sz, L, sm + a.tab_off[i], a.nu1 + s, true, a.ncomp,
+                          comp, sqkT);
   }
   for (int q = tid; q < n0; q += BOT_TPB)
-    a.x_out[(size_t)comp * n0 + q] = sm[a.lds_off[0] + bot_pos(L0, q)];
+    ((T*)a.x_out)[(size_t)comp * n0 + q] = sm[a.lds_off[0] + bot_pos(L0, q)];
 }
 
 }  // namespace
 
-hipError_t launch_block_pass(double* x, const double* b, const double* g2d, const double* zt,
-                             const double* bfac, int nx, int ny, int nz, int ncomp, int colour,
-                             const double* zn, double sqkT, hipStream_t s) {
+template <typename T>
+hipError_t launch_block_pass(T* x, const T* b, const T* g2d, const T* zt, const T* bfac, int nx,
+                             int ny, int nz, int ncomp, int colour, const T* zn, double sqkT,
+                             hipStream_t s) {
   const int nbx2 = nx / 4, nby2 = ny / 4;
   const int nbz = nz / 2;
   const int nbzc = (nbz + 1 - (colour >> 2)) / 2;
-  const uint32_t total = (uint32_t)nbx2 * nby2 * nbzc * 8;
-  if (total == 0) return hipSuccess;
+  if (nbx2 * nby2 * nbzc == 0) return hipSuccess;
   const uint32_t N = (uint32_t)nx * ny * nz;
   const int ntx = (nbx2 + TILE_I - 1) / TILE_I, nty = (nby2 + TILE_J - 1) / TILE_J;
   dim3 grid(ntx * nty, nbzc, ncomp);
-  if (zn) k_block_tile<true><<<grid, TILE_TPB, 0, s>>>(x, b, g2d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, sqkT);
-  else k_block_tile<false><<<grid, TILE_TPB, 0, s>>>(x, b, g2d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, sqkT);
+  if (zn) k_block_tile<T, true><<<grid, TILE_TPB, 0, s>>>(x, b, g2d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, (T)sqkT);
+  else k_block_tile<T, false><<<grid, TILE_TPB, 0, s>>>(x, b, g2d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, (T)sqkT);
   return hipGetLastError();
 }
 
-hipError_t launch_residual_gal(double* r, const double* x, const double* b, const double* g2d,
-                               const double* zt, int nx, int ny, int nz, int ncomp,
-                               hipStream_t s) {
+template <typename T>
+hipError_t launch_residual_gal(T* r, const T* x, const T* b, const T* g2d, const T* zt, int nx,
+                               int ny, int nz, int ncomp, hipStream_t s) {
   const uint32_t N = (uint32_t)nx * ny * nz;
   dim3 grid(blocks_for(N), ncomp);
-  k_residual_gal<<<grid, TPB, 0, s>>>(r, x, b, g2d, zt, nx, ny, nz, N);
+  k_residual_gal<T><<<grid, TPB, 0, s>>>(r, x, b, g2d, zt, nx, ny, nz, N);
   return hipGetLastError();
 }
 
-hipError_t launch_restrict(double* bc, double* xc, const double* r, int nxf, int nyf, int nzf,
-                           int ncomp, hipStream_t s) {
+template <typename T>
+hipError_t launch_restrict(T* bc, T* xc, const T* r, int nxf, int nyf, int nzf, int ncomp,
+                           hipStream_t s) {
   const uint32_t Nf = (uint32_t)nxf * nyf * nzf;
   const uint32_t Nc = Nf / 8;
   dim3 grid(blocks_for(Nc), ncomp);
-  k_restrict<<<grid, TPB, 0, s>>>(bc, xc, r, nxf, nyf, nzf, Nf, Nc);
+  k_restrict<T><<<grid, TPB, 0, s>>>(bc, xc, r, nxf, nyf, nzf, Nf, Nc);
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(double* x, const double* e, int nxf, int nyf, int nzf, int ncomp,
-                          hipStream_t s) {
+template <typename T>
+hipError_t launch_prolong(T* x, const T* e, int nxf, int nyf, int nzf, int ncomp, hipStream_t s) {
   const uint32_t Nf = (uint32_t)nxf * nyf * nzf;
   dim3 grid(blocks_for(Nf), ncomp);
-  k_prolong<<<grid, TPB, 0, s>>>(x, e, nxf, nyf, nzf, Nf, Nf / 8);
+  k_prolong<T><<<grid, TPB, 0, s>>>(x, e, nxf, nyf, nzf, Nf, Nf / 8);
   return hipGetLastError();
 }
 
-hipError_t launch_coarsest(double* x, const double* b, const double* ainv, const double* w, int n,
+template <typename T>
+hipError_t launch_coarsest(T* x, const T* b, const double* ainv, const double* w, int n,
                            int ncomp, bool noise, const NoiseArgs& na, hipStream_t s) {
   dim3 grid(blocks_for(n), ncomp);
   size_t lds = (size_t)(noise ? 2 : 1) * n * sizeof(double);
-  if (noise) k_coarsest<true><<<grid, TPB, lds, s>>>(x, b, ainv, w, n, na);
-  else k_coarsest<false><<<grid, TPB, lds, s>>>(x, b, ainv, w, n, na);
+  if (noise) k_coarsest<T, true><<<grid, TPB, lds, s>>>(x, b, ainv, w, n, na);
+  else k_coarsest<T, false><<<grid, TPB, lds, s>>>(x, b, ainv, w, n, na);
   return hipGetLastError();
 }
 
+template <typename T>
 hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStream_t s) {
   if (a.total == 0) return hipSuccess;
-  k_level_noise<<<blocks_for(a.total), TPB, 0, s>>>(a, na);
+  k_level_noise<T><<<blocks_for(a.total), TPB, 0, s>>>(a, na);
   return hipGetLastError();
 }
 
+template <typename T>
 hipError_t launch_bottom(const BotArgs* a, int ncomp, size_t lds, bool noise, const NoiseArgs& na,
                          hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_bottom<true>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_bottom<T, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_bottom<false>,
+      e = hipFuncSetAttribute((const void*)k_bottom<T, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  if (noise) k_bottom<true><<<ncomp, BOT_TPB, lds, s>>>(a, na);
-  else k_bottom<false><<<ncomp, BOT_TPB, lds, s>>>(a, na);
+  if (noise) k_bottom<T, true><<<ncomp, BOT_TPB, lds, s>>>(a, na);
+  else k_bottom<T, false><<<ncomp, BOT_TPB, lds, s>>>(a, na);
   return hipGetLastError();
 }
+
+#define SMG_INST(T)                                                                            \
+  template hipError_t launch_block_pass<T>(T*, const T*, const T*, const T*, const T*, int, int, \
+                                           int, int, int, const T*, double, hipStream_t);       \
+  template hipError_t launch_residual_gal<T>(T*, const T*, const T*, const T*, const T*, int,    \
+                                             int, int, int, hipStream_t);                        \
+  template hipError_t launch_restrict<T>(T*, T*, const T*, int, int, int, int, hipStream_t);    \
+  template hipError_t launch_prolong<T>(T*, const T*, int, int, int, int, hipStream_t);         \
+  template hipError_t launch_coarsest<T>(T*, const T*, const double*, const double*, int, int,  \
+                                         bool, const NoiseArgs&, hipStream_t);                  \
+  template hipError_t launch_level_noise<T>(const NoiseGenArgs&, const NoiseArgs&, hipStream_t); \
+  template hipError_t launch_bottom<T>(const BotArgs*, int, size_t, bool, const NoiseArgs&,     \
+                                       hipStream_t);
+SMG_INST(double)
+SMG_INST(float)
+#undef SMG_INST
 
 }  // namespace smg

@@ -34,9 +34,10 @@ __global__ __launch_bounds__(TPB) void k_residual7_nat(double* __restrict__ r,
 }
 
 // ----------------------------------------------------------------------------- utilities
-__global__ __launch_bounds__(TPB) void k_zero(double* __restrict__ p, int64_t n) {
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_zero(T* __restrict__ p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  for (; i < n; i += (int64_t)gridDim.x * TPB) p[i] = 0.0;
+  for (; i < n; i += (int64_t)gridDim.x * TPB) p[i] = T(0);
 }
 
 __global__ __launch_bounds__(TPB) void k_copy(double* __restrict__ d, const double* __restrict__ s,
@@ -106,9 +107,18 @@ hipError_t launch_residual7_nat(double* r, const double* x, const double* b, int
   return hipGetLastError();
 }
 
-hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
+template <typename T>
+hipError_t launch_zero(T* p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_zero<<<grid_stride_blocks(n), TPB, 0, s>>>(p, n);
+  k_zero<T><<<grid_stride_blocks(n), TPB, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+template hipError_t launch_zero<double>(double*, int64_t, hipStream_t);
+template hipError_t launch_zero<float>(float*, int64_t, hipStream_t);
+
+hipError_t launch_sumsq_final_parts(double* out, const double* part, uint32_t nparts, int ncomp,
+                                    hipStream_t s) {
+  k_sumsq_final<<<ncomp, TPB, 0, s>>>(out, part, nparts);
   return hipGetLastError();
 }
 

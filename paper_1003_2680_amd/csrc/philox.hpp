@@ -59,4 +59,35 @@ __device__ __forceinline__ void normal_pair(const NoiseArgs& na, uint32_t comp, 
   z1 = r * s;
 }
 
+// FP32 variant for the FP32 sweeps of the refined mode: the same Philox words and the same
+// 53-bit uniforms, rounded to FP32 (full relative precision down to the smallest uniform, so
+// the tail is not clipped), then the hardware log2 / sin / cos (v_sin_f32 and v_cos_f32 take
+// revolutions, so the angle 2 pi u2 needs no multiplication by pi).  The normals differ from
+// the FP64 ones only by FP32 rounding.
+__device__ __forceinline__ void normal_pair_f32(const NoiseArgs& na, uint32_t comp, uint32_t call,
+                                                float& z0, float& z1) {
+  uint32_t w0 = call, w1 = na.sid | (comp << 16), w2 = na.c2, w3 = na.c3;
+  philox4x32_10(w0, w1, w2, w3, na.k0, na.k1);
+  const float u1 = (float)uniform53(w0, w1);
+  const float u2 = (float)uniform53(w2, w3);
+  const float r = __builtin_sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u1));
+  z0 = r * __builtin_amdgcn_cosf(u2);
+  z1 = r * __builtin_amdgcn_sinf(u2);
+}
+
+// normals in the storage precision T of the sweep
+template <typename T>
+__device__ __forceinline__ void normal_pair_t(const NoiseArgs& na, uint32_t comp, uint32_t call,
+                                              T& z0, T& z1);
+template <>
+__device__ __forceinline__ void normal_pair_t<double>(const NoiseArgs& na, uint32_t comp,
+                                                      uint32_t call, double& z0, double& z1) {
+  normal_pair(na, comp, call, z0, z1);
+}
+template <>
+__device__ __forceinline__ void normal_pair_t<float>(const NoiseArgs& na, uint32_t comp,
+                                                     uint32_t call, float& z0, float& z1) {
+  normal_pair_f32(na, comp, call, z0, z1);
+}
+
 }  // namespace smg

@@ -154,10 +154,7 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
     err = "invalid cycle parameters";
     return SMG_EINVAL;
   }
-  if (p.precision != SMG_FP64) {
-    err = "SMG_FP32_REFINED is not available in this build";
-    return SMG_EINVAL;
-  }
+
   // ---- level plan
   std::vector<int> dx{d.nx}, dy{d.ny}, dz{d.nz};
   for (;;) {
@@ -313,6 +310,12 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
     }
   }
   // ---- workspace layout
+  const bool f32 = p.precision == SMG_FP32_REFINED;
+  if (f32 && h.lv[0].kind != KIND_POINT) {
+    err = "SMG_FP32_REFINED needs a smoothed finest level (use SMG_FP64 for one-level Cholesky)";
+    return SMG_EINVAL;
+  }
+  const size_t ts = f32 ? sizeof(float) : sizeof(double);  // sweep element size
   const int nc = d.ncomp;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -322,15 +325,25 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
   };
   for (int l = 0; l < L; ++l) {
     Level& v = h.lv[l];
-    size_t field = (size_t)nc * v.n * sizeof(double);
-    v.off_x = take(field);
-    v.off_b = take(field);
-    if (v.kind != KIND_CHOL) v.off_r = take(field);
+    const size_t n = (size_t)nc * v.n;
+    if (!f32) {
+      v.off_x = take(n * sizeof(double));
+      v.off_b = take(n * sizeof(double));
+      if (v.kind != KIND_CHOL) v.off_r = take(n * sizeof(double));
+    } else {
+      if (l == 0) {
+        v.off_x = take(n * sizeof(double));
+        v.off_b = take(n * sizeof(double));
+      }
+      v.off_xf = take(n * sizeof(float));
+      v.off_bf = take(n * sizeof(float));
+      if (v.kind != KIND_CHOL) v.off_rf = take(n * sizeof(float));
+    }
     if (v.kind == KIND_BLOCK) {
-      v.off_g2d = take(v.g2d.size() * sizeof(double));
-      v.off_zt = take(v.zt.size() * sizeof(double));
-      v.off_bfac = take(v.bfac.size() * sizeof(double));
-      v.off_noise = take((size_t)(p.nu1 + p.nu2) * nc * v.n * sizeof(double));
+      v.off_g2d = take(v.g2d.size() * ts);
+      v.off_zt = take(v.zt.size() * ts);
+      v.off_bfac = take(v.bfac.size() * ts);
+      v.off_noise = take((size_t)(p.nu1 + p.nu2) * n * ts);
     }
   }
   // Bottom of the V-cycle: the first Galerkin level with at most kBottomCells cells and every
@@ -341,8 +354,8 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
     size_t lds = 0;
     for (int m = l; m < L; ++m) {
       const Level& v = h.lv[m];
-      lds += 3 * bot_field_doubles(v.kind, v.nx, v.ny, v.nz) * sizeof(double);
-      if (v.kind == KIND_BLOCK) lds += (50 + (size_t)v.nz * 10 + (size_t)(v.nz / 2) * 192) * sizeof(double);
+      lds += 3 * bot_field_elems(v.kind, v.nx, v.ny, v.nz) * ts;
+      if (v.kind == KIND_BLOCK) lds += (50 + (size_t)v.nz * 10 + (size_t)(v.nz / 2) * 192) * ts;
     }
     if (lds <= kBottomLdsMax && L - l <= kBottomLevelsMax) {
       h.bottom = l;
@@ -356,7 +369,7 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
   }
   if (h.bottom >= 0) h.off_botargs = take(sizeof(BotArgs));
   // partial sums for the residual norms: one per 256-cell block of level 0
-  h.part_len = (size_t)((h.lv[0].n + 255) / 256);
+  h.part_len = (size_t)((h.lv[0].n + 255) / 256) + 2;
   h.off_part = take((size_t)nc * h.part_len * sizeof(double));
   h.off_norm = take((size_t)2 * nc * sizeof(double));
   h.ws_bytes = off;

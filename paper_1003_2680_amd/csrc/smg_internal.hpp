@@ -30,14 +30,22 @@ struct Level {
   std::vector<double> zt;    // KIND_BLOCK: [nz][10]
   std::vector<double> bfac;  // KIND_BLOCK: [nz/2][3][64]: A_BB^-1, L_BB^-T, A_BB (row-major)
   // workspace offsets (bytes); level 0 of KIND_POINT stores x and b split by colour
-  size_t off_x = 0, off_b = 0, off_r = 0, off_g2d = 0, off_zt = 0, off_bfac = 0, off_noise = 0;
-  double* noise_d = nullptr;  // KIND_BLOCK: pregenerated noise [nu1+nu2][ncomp][n] of one cycle
+  // Workspace offsets (bytes).  FP64 mode: x, b, r and the tables and noise in double.
+  // FP32-refined mode: level 0 keeps x (the FP64 state) and b (the FP64 right-hand side), and
+  // every level has FP32 fields xf, bf, rf (level 0: xf = correction e, bf = FP32 residual,
+  // both split by colour), FP32 tables and FP32 noise.
+  size_t off_x = 0, off_b = 0, off_r = 0, off_xf = 0, off_bf = 0, off_rf = 0;
+  size_t off_g2d = 0, off_zt = 0, off_bfac = 0, off_noise = 0;
   double* x = nullptr;
   double* b = nullptr;
   double* r = nullptr;
-  double* g2d_d = nullptr;
-  double* zt_d = nullptr;
-  double* bfac_d = nullptr;
+  float* xf = nullptr;
+  float* bf = nullptr;
+  float* rf = nullptr;
+  void* g2d_d = nullptr;    // T tables of the sweep precision
+  void* zt_d = nullptr;
+  void* bfac_d = nullptr;
+  void* noise_d = nullptr;  // KIND_BLOCK: pregenerated noise [nu1+nu2][ncomp][n] of one cycle
 };
 
 struct Hierarchy {

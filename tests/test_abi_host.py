@@ -163,3 +163,27 @@ def test_unbound_hierarchy_refuses_work(lib):
         assert rc == abi.SMG_ESTATE
     finally:
         lib.smg_destroy_hierarchy(hd)
+
+
+def test_refined_precision_plan(lib):
+    """SMG_FP32_REFINED needs a smoothed finest level; its plan has the FP64 plan's levels."""
+    desc = abi.GridDesc(4, 4, 4, 1, 1.0, 1.0)  # one level, drawn exactly
+    prm = abi.CycleParams(1, 2, 2, 512, 0, abi.SMG_FP32_REFINED, 1, 0)
+    hd = ctypes.c_void_p()
+    assert lib.smg_create_hierarchy(ctypes.byref(desc), ctypes.byref(prm),
+                                    ctypes.byref(hd)) == abi.SMG_EINVAL
+    assert "FP32" in lib.smg_last_error().decode()
+    for dims in ((16, 16, 16), (128, 128, 128)):
+        desc = abi.GridDesc(*dims, 3, 1.0, 1.0)
+        infos = []
+        for prec in (abi.SMG_FP64, abi.SMG_FP32_REFINED):
+            prm = abi.CycleParams(0, 2, 2, 512, 0, prec, 1, 0)
+            abi.check(lib.smg_create_hierarchy(ctypes.byref(desc), ctypes.byref(prm),
+                                               ctypes.byref(hd)))
+            infos.append(_info(lib, hd))
+            lib.smg_destroy_hierarchy(hd)
+        a, b = infos
+        assert a.n_levels == b.n_levels and a.state_bytes == b.state_bytes
+        assert [tuple(a.dims[l]) for l in range(a.n_levels)] == \
+            [tuple(b.dims[l]) for l in range(b.n_levels)]
+        assert b.workspace_bytes > 0

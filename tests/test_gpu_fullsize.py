@@ -55,3 +55,39 @@ def test_fullsize_solve(hier):
         assert np.linalg.norm(r) / np.linalg.norm(f[c]) <= 1.01e-12
         exact = spectral.solve(f[c], *N3)
         assert np.max(np.abs(ug[c].ravel() - exact)) <= 1e-8 * np.max(np.abs(exact))
+
+
+@pytest.fixture(scope="module")
+def hier32():
+    from paper_1003_2680_amd.api import Hierarchy
+    return Hierarchy(*N3, ncomp=3, kT=1.0, levels=6, precision="fp32_refined")
+
+
+def test_fullsize_refined_chain_parity(hier32):
+    """FP32-refined mode on the same streams: relative RMS error per sample <= 1e-4."""
+    print("[gpu-case] 128^3 x3 refined chain, 2 cycles", flush=True)
+    out, state = hier32.sample(2, seed=0)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(2, 3, -1)
+    mg = StochasticMG(*N3, kT=1.0, levels=6)
+    from oracle.philox import PhiloxNoise
+    noise = PhiloxNoise(0)
+    zero = np.zeros(mg.levels[0].n)
+    x = zero.copy()
+    for cyc in range(2):
+        x = mg.vcycle(x, zero, noise, cyc, 1)
+        err = np.linalg.norm(got[cyc, 1] - x) / np.linalg.norm(x)
+        print("  cycle %d rel RMS %.3e" % (cyc, err), flush=True)
+        assert err <= 1e-4, (cyc, err)
+
+
+def test_fullsize_refined_solve(hier32):
+    print("[gpu-case] 128^3 x3 refined solve", flush=True)
+    f = gaussian_field(hier32.shape, 101)
+    u, cycles, relres = hier32.solve(torch.from_numpy(f).cuda(), rtol=1e-10)
+    torch.cuda.synchronize()
+    assert relres <= 1e-10 and cycles <= 16
+    ug = u.cpu().numpy()
+    for c in (0, 2):
+        r = f[c].ravel() - apply_A(ug[c], *N3)
+        assert np.linalg.norm(r) / np.linalg.norm(f[c]) <= 1.01e-10
