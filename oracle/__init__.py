@@ -18,6 +18,8 @@ written so that each step can be checked against the paper by eye:
                    (FFT in x,y and DST-II in z), used as an independent reference.
 * ``analysis``  -- affine-map extraction, the stationary-covariance (Lyapunov) check of
                    eq. J_eq_C_R, autocorrelation estimates.
+* ``observables`` -- projections onto eigenvectors of A, the energy 1/2 x^T A x and
+                   per-cell moments of the samples (the decorrelation observables).
 
 The oracle shares no code with the HIP path; the two meet only on seeded inputs.
 """
