@@ -176,14 +176,18 @@ int smg_debug_host_table(const smg_hierarchy* h, int32_t level, int32_t which, d
 
 /* smg_set_option: execution switches that never change results.
  *   SMG_OPT_BOTTOM_KERNEL (default 1): run the levels with at most 4096 cells (and the
- *   coarsest draw) in one LDS-resident launch per cycle; 0 = one launch per colour pass. */
-enum { SMG_OPT_BOTTOM_KERNEL = 1 };
+ *   coarsest draw) in one LDS-resident launch per cycle; 0 = one launch per colour pass.
+ *   SMG_OPT_TIMED_KERNEL (default SMG_TIMED_FINE_PASS): the kernel class that
+ *   smg_kernel_timing brackets with events: the level-0 colour pass, the level-1 block
+ *   colour pass, or the LDS-resident bottom launch. */
+enum { SMG_OPT_BOTTOM_KERNEL = 1, SMG_OPT_TIMED_KERNEL = 2 };
+enum { SMG_TIMED_FINE_PASS = 0, SMG_TIMED_LEVEL1_BLOCK_PASS = 1, SMG_TIMED_BOTTOM = 2 };
 int smg_set_option(smg_hierarchy* h, int32_t option, int64_t value);
 
 /* ---- Kernel timing (measurement support). ----
  * When enabled, the library records HIP events on the caller's stream around every launch
- * of the level-0 colour-pass kernel and accumulates their elapsed times (read after the
- * stream is idle).  *count receives the number of timed launches, *total_ms their sum;
+ * of the kernel class chosen by SMG_OPT_TIMED_KERNEL and accumulates their elapsed times
+ * (read after the stream is idle).  *count receives the number of timed launches, *total_ms their sum;
  * the counters are reset by smg_kernel_timing(h, 1). */
 int smg_kernel_timing(smg_hierarchy* h, int32_t enable);
 int smg_kernel_timing_read(smg_hierarchy* h, int64_t* count, double* total_ms);

@@ -19,6 +19,10 @@ SMG_FP32_REFINED = 1
 SMG_OUT_F64 = 0
 SMG_OUT_F32 = 1
 SMG_OPT_BOTTOM_KERNEL = 1
+SMG_OPT_TIMED_KERNEL = 2
+SMG_TIMED_FINE_PASS = 0
+SMG_TIMED_LEVEL1_BLOCK_PASS = 1
+SMG_TIMED_BOTTOM = 2
 
 ERROR_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_ENOTCONV",
                -4: "SMG_ENONFINITE", -5: "SMG_EHIP", -6: "SMG_ESTATE"}

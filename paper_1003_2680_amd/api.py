@@ -117,7 +117,13 @@ class Hierarchy:
         """Run the small levels in one LDS-resident launch per cycle (default) or per pass."""
         abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_BOTTOM_KERNEL, int(bool(enable))))
 
-    def kernel_timing(self, enable):
+    def kernel_timing(self, enable, kernel="fine_pass"):
+        """Bracket every launch of one kernel class with HIP events: "fine_pass" (level-0
+        colour pass), "level1_block_pass" or "bottom"."""
+        which = {"fine_pass": abi.SMG_TIMED_FINE_PASS,
+                 "level1_block_pass": abi.SMG_TIMED_LEVEL1_BLOCK_PASS,
+                 "bottom": abi.SMG_TIMED_BOTTOM}[kernel]
+        abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_TIMED_KERNEL, which))
         abi.check(self.lib.smg_kernel_timing(self._h, int(bool(enable))))
 
     def kernel_timing_read(self):

@@ -90,27 +90,50 @@ struct Fld<float> {
   static float* r(Level& v) { return v.rf; }
 };
 
+// Events around one launch of the timed kernel class (measurement support).
+struct TimedScope {
+  Hierarchy& h;
+  hipStream_t s;
+  hipEvent_t e1 = nullptr;
+  int rc = SMG_OK;
+  TimedScope(Hierarchy& hh, hipStream_t ss, int kind) : h(hh), s(ss) {
+    if (!h.timing || h.timed_kernel != kind) return;
+    if (h.ev_used + 2 > h.ev_pool.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+          set_error("hipEventCreate failed");
+          rc = SMG_EHIP;
+          return;
+        }
+        h.ev_pool.push_back(e);
+      }
+    }
+    hipEvent_t e0 = h.ev_pool[h.ev_used++];
+    e1 = h.ev_pool[h.ev_used++];
+    if (hipEventRecord(e0, s) != hipSuccess) {
+      set_error("hipEventRecord failed");
+      rc = SMG_EHIP;
+    }
+  }
+  int close() {
+    if (rc == SMG_OK && e1 && hipEventRecord(e1, s) != hipSuccess) {
+      set_error("hipEventRecord failed");
+      rc = SMG_EHIP;
+    }
+    return rc;
+  }
+};
+
 template <typename T>
 int timed_rb_pass(Run& r, T* xc, const T* xo, const T* bc, int colour, const NoiseArgs& na) {
   Hierarchy& h = *r.h;
   const Level& v = h.lv[0];
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h.timing) {
-    if (h.ev_used + 2 > h.ev_pool.size()) {
-      for (int i = 0; i < 64; ++i) {
-        hipEvent_t e;
-        SMG_HIP(hipEventCreate(&e));
-        h.ev_pool.push_back(e);
-      }
-    }
-    e0 = h.ev_pool[h.ev_used++];
-    e1 = h.ev_pool[h.ev_used++];
-    SMG_HIP(hipEventRecord(e0, r.s));
-  }
+  TimedScope ts(h, r.s, SMG_TIMED_FINE_PASS);
+  SMG_TRY(ts.rc);
   SMG_HIP(launch_rb_pass<T>(xc, xo, bc, v.nx, v.ny, v.nz, h.desc.ncomp, colour, h.desc.h,
                             h.desc.kT, r.noise, na, r.s));
-  if (h.timing) SMG_HIP(hipEventRecord(e1, r.s));
-  return SMG_OK;
+  return ts.close();
 }
 
 template <typename T>
@@ -134,9 +157,12 @@ int sweep(Run& r, int l, int slot, bool post) {
     for (int t = 0; t < 8; ++t) {
       const int colour = post ? 7 - t : t;
       const T* zn = r.noise ? noise + (size_t)slot * nc * v.n : nullptr;
+      TimedScope ts(h, r.s, l == 1 ? SMG_TIMED_LEVEL1_BLOCK_PASS : -1);
+      SMG_TRY(ts.rc);
       SMG_HIP(launch_block_pass<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.g2d_d,
                                    (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz, nc,
                                    colour, zn, std::sqrt(h.desc.kT), r.s));
+      SMG_TRY(ts.close());
     }
   }
   return SMG_OK;
@@ -260,8 +286,10 @@ template <typename T>
 int bottom_cycle(Run& r) {
   Hierarchy& h = *r.h;
   NoiseArgs na = make_noise(r, 0, 0, 0, KIND_SMOOTH_NOISE);
+  TimedScope ts(h, r.s, SMG_TIMED_BOTTOM);
+  SMG_TRY(ts.rc);
   SMG_HIP(launch_bottom<T>(h.botargs_d, h.desc.ncomp, h.bottom_lds, r.noise, na, r.s));
-  return SMG_OK;
+  return ts.close();
 }
 
 template <typename T>
@@ -764,6 +792,10 @@ int smg_set_option(smg_hierarchy* hh, int32_t option, int64_t value) {
   }
   if (option == SMG_OPT_BOTTOM_KERNEL && (value == 0 || value == 1)) {
     hh->h.use_bottom = value != 0;
+    return SMG_OK;
+  }
+  if (option == SMG_OPT_TIMED_KERNEL && value >= SMG_TIMED_FINE_PASS && value <= SMG_TIMED_BOTTOM) {
+    hh->h.timed_kernel = (int)value;
     return SMG_OK;
   }
   set_error("unknown option or value");

@@ -68,8 +68,9 @@ struct Hierarchy {
   double* norm_d = nullptr;      // [2][ncomp]
   char* ws = nullptr;
   int device = -1;
-  // kernel timing
+  // kernel timing: events around every launch of one kernel class (SMG_TIMED_*)
   bool timing = false;
+  int timed_kernel = 0;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   int64_t tcount = 0;
