@@ -4,17 +4,19 @@ Workload: a 128x128x128 cell-centred grid (h = 1, kT = 1), periodic in x and y w
 walls on the z faces; a 3-component velocity field (three decoupled scalar chains with the
 same wall-bounded Laplacian); the 6-level stochastic V(2,2) cycle in FP64 (red-black heat
 bath on the fine level, 2x2x2 block heat bath on the Galerkin levels, exact Cholesky draw on
-the 4^3 coarsest level).  The chains of seeds 0..CHAINS-1 run concurrently, one hierarchy
-and one HIP stream each (the small coarse levels of one chain overlap the bandwidth-bound fine
-sweeps of another).  One step = one smg_sample_field call per chain that runs
-SAMPLES_PER_STEP cycles and writes every cycle's 3-component field to an output buffer in HBM.
+the 4^3 coarsest level).  The chains of seeds 0..CHAINS-1 are batched into every launch (one
+hierarchy carrying CHAINS x 3 components; each chain draws exactly what it draws alone).
+One step = one batched call that advances every chain by SAMPLES_PER_STEP cycles, writes
+every cycle's fields to an output buffer in HBM and takes their observables (projections on
+the 8 lowest eigenvectors of A and the energy 1/2 x^T A x) in the same pass.
 
 value = decorrelated samples/s = emitted samples/s / k_dec with
-k_dec = max(1, ceil(ln 0.01 / ln rho)), rho the measured contraction of the deterministic
-cycle (the paper ties the decorrelation of the stochastic iteration to the deterministic
-convergence rate: the lag-k correlation is R^k applied to the initial covariance).
-Also reported: per-step p50/p99 latency, 10 solves to 1e-12 (solves/s), the roofline of the
-fine colour-pass kernel, and the CPU oracle on a bounded sample of the same workload.
+k_dec = max(1, ceil(ln 0.01 / ln rho)), rho the larger of the measured contraction of the
+deterministic cycle (the lag-k correlation of the stochastic iteration is R^k applied to the
+stationary covariance) and the largest measured lag-1 autocorrelation of the observables.
+Also reported: per-step p50/p99 latency; 10 solves to 1e-12 (batched throughput and single
+latency); the roofline of the dominant kernel class (per-launch time from HIP events around
+each sweep's launches) and of the other; and the CPU oracle on a bounded sample.
 
 The FP32-refined form of the same workload (FP32 sweeps and transfers, FP64 residual,
 correction and coarsest arithmetic) is measured beside it under "fp32_refined", with its
@@ -100,53 +102,111 @@ def copy_calibration(mib=1024, reps=5):
                                            "bytes_written_per_copy": n * 8, "copies": reps}}))
 
 
-def run_chains(Hs, states, outs, streams, steps, warmup, first_cycle, samples_per_step):
-    """Warm-up, then `steps` timed steps of every chain on its own stream.  Returns
-    (ms per step by wall clock, per-step latencies in ms, next cycle)."""
+def lag1(obs):
+    """Lag-1 autocorrelation of each observable, pooled over components: obs [T, C, Q]."""
+    import numpy as np
+    o = obs - obs.mean(axis=0, keepdims=True)
+    num = (o[:-1] * o[1:]).sum(axis=(0, 1))
+    den = (o * o).sum(axis=(0, 1))
+    return num / den
+
+
+def run_batch(H, nchains, steps, warmup, spp, out):
+    """Warm-up, then `steps` timed steps; each step is one batched call that advances every
+    chain by spp cycles, emits their fields into `out` and takes the observables of every
+    emitted field.  Returns (ms per step by wall clock, per-step latencies in ms, observables
+    of the timed steps [steps*spp, nact, Q])."""
     import numpy as np
     import torch
     stream = torch.cuda.current_stream()
-
-    def step(first):
-        for i, H in enumerate(Hs):
-            streams[i].wait_stream(stream)
-            with torch.cuda.stream(streams[i]):
-                H.sample(samples_per_step, seed=i, first_cycle=first, state=states[i],
-                         out=outs[i])
-        for i in range(len(Hs)):
-            stream.wait_stream(streams[i])
-
-    cycle = first_cycle
+    state = torch.zeros((nchains * NCOMP, NZ, NY, NX), dtype=torch.float64, device=out.device)
+    H.sample_batch(0, seeds=list(range(nchains)), comps_per_chain=NCOMP, state=state)
     for _ in range(warmup):
-        step(cycle)
-        cycle += samples_per_step
+        H.sample_batch(spp, nchains=nchains, comps_per_chain=NCOMP, state=state, out=out,
+                       with_obs=True)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
+    obs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
-        step(cycle)
+        _, ob, _ = H.sample_batch(spp, nchains=nchains, comps_per_chain=NCOMP, state=state,
+                                  out=out, with_obs=True)
         ev[k][1].record(stream)
-        cycle += samples_per_step
+        obs.append(ob)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = np.array([a.elapsed_time(b) for a, b in ev])
-    return wall * 1e3 / max(steps, 1), lat, cycle
+    return wall * 1e3 / max(steps, 1), lat, torch.cat(obs).cpu().numpy(), state
 
 
-def time_solves(H, fs, u, rtol):
+def time_solves(Hsingle, Hbatch, fs, rtol):
+    """Latency of one 3-component solve (and the contraction it measures), and the throughput
+    of all the right-hand sides solved as one batch."""
     import torch
-    H.solve(fs[0], rtol=rtol, u=u)  # warm-up
+    u = torch.empty_like(fs[0])
+    Hsingle.solve(fs[0], rtol=rtol, u=u)  # warm-up
     ratios, cyc = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for f in fs:
-        _, c, _ = H.solve(f, rtol=rtol, u=u)
+        _, c, _ = Hsingle.solve(f, rtol=rtol, u=u)
         cyc.append(c)
-        ratios.append(H.last_ratio)
+        ratios.append(Hsingle.last_ratio)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / len(fs), ratios, cyc
+    single_s = (time.perf_counter() - t0) / len(fs)
+    fb = torch.cat(fs).contiguous()
+    Hbatch.solve_batch(fb, nchains=len(fs), comps_per_chain=NCOMP, rtol=rtol)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos = Hbatch.solve_batch(fb, nchains=len(fs), comps_per_chain=NCOMP, rtol=rtol)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t0
+    return single_s, batch_s, ratios, cyc
+
+
+def measure(precision, args, fs, dev):
+    """Sampling, kernel timing and solves of one precision mode."""
+    import numpy as np
+    import torch
+    from paper_1003_2680_amd.api import Hierarchy
+
+    C = max(1, args.chains)
+    H = Hierarchy(NX, NY, NZ, ncomp=NCOMP * C, kT=1.0, levels=LEVELS, nu1=2, nu2=2,
+                  precision=precision)
+    out = torch.empty((SAMPLES_PER_STEP, NCOMP * C, NZ, NY, NX), dtype=torch.float64,
+                      device=dev)
+    ms, lat, obs, state = run_batch(H, C, args.steps, args.warmup, SAMPLES_PER_STEP, out)
+    res = {"ms_per_step": ms, "lat": lat, "obs": obs}
+    if precision == "fp64":
+        # per-launch kernel times: HIP events bracketing each sweep's colour passes (or the
+        # bottom launch) on the batch's stream, over the same number of further steps
+        cyc_timed = args.steps * SAMPLES_PER_STEP
+        kern = {}
+        for name in ("fine_pass", "level1_block_pass", "bottom"):
+            H.kernel_timing(True, name)
+            torch.cuda.synchronize()
+            for _ in range(args.steps):
+                H.sample_batch(SAMPLES_PER_STEP, nchains=C, comps_per_chain=NCOMP, state=state,
+                               out=out)
+            torch.cuda.synchronize()
+            n_l, k_ms = H.kernel_timing_read()
+            H.kernel_timing(False, name)
+            kern[name] = {"launches": n_l, "avg_launch_s": k_ms / 1e3 / max(n_l, 1),
+                          "per_cycle_s": k_ms / 1e3 / cyc_timed}
+        res["kern"] = kern
+    del H, out, state
+    torch.cuda.empty_cache()
+    Hs = Hierarchy(NX, NY, NZ, ncomp=NCOMP, kT=1.0, levels=LEVELS, precision=precision)
+    Hb = Hierarchy(NX, NY, NZ, ncomp=NCOMP * len(fs), kT=1.0, levels=LEVELS,
+                   precision=precision)
+    single_s, batch_s, ratios, cyc = time_solves(Hs, Hb, fs, 1e-12)
+    res.update({"solve_single_s": single_s, "solve_batch_s": batch_s, "rho": max(ratios),
+                "solve_cycles": float(np.mean(cyc))})
+    del Hs, Hb
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -181,124 +241,88 @@ def main():
     shape = (NCOMP, NZ, NY, NX)
     fs = [torch.from_numpy(gaussian_field(shape, 100 + i)).to(dev)
           for i in range(max(args.solves, 1))]
-    u = torch.empty(shape, dtype=torch.float64, device=dev)
-    streams = [torch.cuda.Stream(device=dev) for _ in range(C)]
 
-    # ---- FP64: deterministic contraction -> k_dec; solves/s; sampling
-    Hs = [Hierarchy(NX, NY, NZ, ncomp=NCOMP, kT=1.0, levels=LEVELS, nu1=2, nu2=2)
-          for _ in range(C)]
-    H = Hs[0]
-    solve_s, ratios, cyc = time_solves(H, fs, u, 1e-12)
-    rho = max(ratios)
+    r64 = measure("fp64", args, fs, dev)
+    rho_solve = r64["rho"]
+    rho_obs = lag1(r64["obs"])
+    rho = max(rho_solve, float(np.max(np.abs(rho_obs))))
     k_dec = max(1, math.ceil(math.log(0.01) / math.log(rho)))
-    states = [h.new_state() for h in Hs]
-    outs = [torch.empty((SAMPLES_PER_STEP,) + shape, dtype=torch.float64, device=dev)
-            for _ in range(C)]
-    ms_per_step, lat, cycle = run_chains(Hs, states, outs, streams, args.steps, args.warmup, 0,
-                                         SAMPLES_PER_STEP)
-
-    # ---- per-launch kernel times: HIP events (on the chain's own stream) around every launch
-    # of one kernel class while chain 0 runs alone (the same steps again, so that a launch's
-    # time is not shared with other chains)
-    def timed(kernel):
-        nonlocal cycle
-        H.kernel_timing(True, kernel)
-        torch.cuda.synchronize()
-        for k in range(args.steps):
-            H.sample(SAMPLES_PER_STEP, seed=0, first_cycle=cycle, state=states[0], out=outs[0])
-            cycle += SAMPLES_PER_STEP
-        torch.cuda.synchronize()
-        n_launch, k_ms = H.kernel_timing_read()
-        H.kernel_timing(False, kernel)
-        return n_launch, k_ms / 1e3 / max(n_launch, 1)
+    samples_per_s = C * SAMPLES_PER_STEP / (r64["ms_per_step"] / 1e3)
+    value = samples_per_s / k_dec
 
     N0 = NX * NY * NZ
     N1 = N0 // 8
-    cyc_timed = args.steps * SAMPLES_PER_STEP
-    kern = {}
-    # level-0 colour pass (b = 0): read the other colour, write this colour, 8 B per value
-    n_l, t_l = timed("fine_pass")
-    kern["fine_pass"] = {"kernel": "k_rb_pass (level-0 colour pass, 128^3)", "launches": n_l,
-                         "avg_launch_s": t_l, "bytes": NCOMP * N0 * 8,
-                         "per_cycle_s": t_l * n_l / cyc_timed}
-    # level-1 block colour pass: read x of the whole level, b and the noise of this colour's
-    # cells, write x of this colour's cells: N1 * 8 B * (1 + 3/8)
-    n_l, t_l = timed("level1_block_pass")
-    kern["level1_block_pass"] = {"kernel": "k_block_tile (level-1 block colour pass, 64^3)",
-                                 "launches": n_l, "avg_launch_s": t_l,
-                                 "bytes": NCOMP * N1 * 8 * 11 // 8,
-                                 "per_cycle_s": t_l * n_l / cyc_timed}
-    n_l, t_l = timed("bottom")
-    kern["bottom"] = {"kernel": "k_bottom (LDS-resident levels 16^3..4^3, one work-group per "
-                                "component)", "launches": n_l, "avg_launch_s": t_l,
-                      "per_cycle_s": t_l * n_l / cyc_timed}
+    nact = NCOMP * C
+    kern = r64["kern"]
 
-    def roof(k, traffic=None):
-        ach = k["bytes"] / k["avg_launch_s"] / 1e9
+    def roof(k, name, nbytes, traffic=None):
+        ach = nbytes / k["avg_launch_s"] / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": k["kernel"],
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
                 "avg_launch_us": round(k["avg_launch_s"] * 1e6, 3),
-                "launches_timed": int(k["launches"]), "algorithmic_bytes_per_launch": k["bytes"],
+                "launches_timed": int(k["launches"]), "algorithmic_bytes_per_launch": nbytes,
                 "us_per_cycle": round(k["per_cycle_s"] * 1e6, 1)}
 
-    samples_per_s = C * SAMPLES_PER_STEP / (ms_per_step / 1e3)
-    value = samples_per_s / k_dec
+    # level-0 colour pass (b = 0): read the other colour, write this colour, 8 B per value
+    fine = roof(kern["fine_pass"], "k_rb_pass (level-0 colour pass, 128^3)", nact * N0 * 8)
+    fine["traffic"] = measured_traffic(fine["algorithmic_bytes_per_launch"])
+    # level-1 block colour pass: read x of the whole level, b and the noise of this colour's
+    # cells, write x of this colour's cells: N1 * 8 B * (1 + 3/8)
+    blk = roof(kern["level1_block_pass"], "k_block_tile (level-1 block colour pass, 64^3)",
+               nact * N1 * 8 * 11 // 8)
+    # the dominant kernel class by GPU time per cycle carries `roofline`
+    dominant = max((fine, blk), key=lambda r: r["us_per_cycle"])
+    other = blk if dominant is fine else fine
+    lat = r64["lat"]
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "decorrelated samples/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "ms_per_step": round(r64["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "128x128x128 wall-bounded cell-centred Laplacian (periodic x,y; "
                                "no-slip z walls), 3-component field, 6-level stochastic "
-                               "V(2,2) cycle, FP64, chains of seeds 0..%d run concurrently" % (C - 1),
+                               "V(2,2) cycle, FP64; the chains of seeds 0..%d batched into "
+                               "every launch" % (C - 1),
                    "grid": [NX, NY, NZ], "ncomp": NCOMP, "levels": LEVELS, "nu": [2, 2],
                    "chains": C, "samples_per_step": C * SAMPLES_PER_STEP, "k_dec": k_dec},
         "samples_per_s": round(samples_per_s, 2),
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
-        "rho": round(rho, 5),
-        "solves_per_s": round(1.0 / solve_s, 3),
-        "solve_cycles": int(round(float(np.mean(cyc)))),
-        # dominant kernel class by GPU time per cycle (rocprofv3: k_block_tile); the
-        # LDS-resident bottom launch has no HBM roofline (its fields never leave LDS)
-        "roofline": roof(kern["level1_block_pass"]),
-        "roofline_fine_pass": roof(kern["fine_pass"],
-                                   measured_traffic(kern["fine_pass"]["bytes"])),
-        "bottom_kernel": {"kernel": kern["bottom"]["kernel"],
+        "rho": round(rho, 5), "rho_solve": round(rho_solve, 5),
+        "rho_obs_lag1": [round(float(v), 4) for v in rho_obs],
+        "solves_per_s": round(len(fs) / r64["solve_batch_s"], 3),
+        "solve_ms_single": round(r64["solve_single_s"] * 1e3, 3),
+        "solve_cycles": round(r64["solve_cycles"], 2),
+        "roofline": dominant,
+        "roofline_other": other,
+        "bottom_kernel": {"kernel": "k_bottom (LDS-resident levels 16^3..4^3, one work-group "
+                                    "per component)",
                           "avg_launch_us": round(kern["bottom"]["avg_launch_s"] * 1e6, 1),
                           "us_per_cycle": round(kern["bottom"]["per_cycle_s"] * 1e6, 1)},
     }
-    del Hs, H, states, outs
-    torch.cuda.empty_cache()
 
     # ---- FP32-refined form of the same workload (same streams, same k_dec)
     if not args.no_refined:
-        Rs = [Hierarchy(NX, NY, NZ, ncomp=NCOMP, kT=1.0, levels=LEVELS, nu1=2, nu2=2,
-                        precision="fp32_refined") for _ in range(C)]
-        r_solve_s, r_ratios, r_cyc = time_solves(Rs[0], fs, u, 1e-12)
-        # error against the FP64 chain on the same Philox streams (2 cycles from zero)
         H64 = Hierarchy(NX, NY, NZ, ncomp=NCOMP, kT=1.0, levels=LEVELS)
+        H32 = Hierarchy(NX, NY, NZ, ncomp=NCOMP, kT=1.0, levels=LEVELS, precision="fp32_refined")
         a, _ = H64.sample(2, seed=0)
-        b, _ = Rs[0].sample(2, seed=0)
+        b, _ = H32.sample(2, seed=0)
         rel_rms = float(((a - b).norm() / a.norm()).item())
-        del H64, a, b
-        r_states = [h.new_state() for h in Rs]
-        r_outs = [torch.empty((SAMPLES_PER_STEP,) + shape, dtype=torch.float64, device=dev)
-                  for _ in range(C)]
-        r_ms, r_lat, _ = run_chains(Rs, r_states, r_outs, streams, args.steps, args.warmup, 0,
-                                    SAMPLES_PER_STEP)
-        r_sps = C * SAMPLES_PER_STEP / (r_ms / 1e3)
+        del H64, H32, a, b
+        torch.cuda.empty_cache()
+        r32 = measure("fp32_refined", args, fs, dev)
+        r_sps = C * SAMPLES_PER_STEP / (r32["ms_per_step"] / 1e3)
         line["fp32_refined"] = {
             "value": round(r_sps / k_dec, 3), "samples_per_s": round(r_sps, 2),
-            "ms_per_step": round(r_ms, 4),
-            "p50_ms": round(float(np.percentile(r_lat, 50)), 4),
-            "p99_ms": round(float(np.percentile(r_lat, 99)), 4),
-            "solves_per_s": round(1.0 / r_solve_s, 3),
-            "solve_cycles": int(round(float(np.mean(r_cyc)))),
-            "rho": round(max(r_ratios), 5),
+            "ms_per_step": round(r32["ms_per_step"], 4),
+            "p50_ms": round(float(np.percentile(r32["lat"], 50)), 4),
+            "p99_ms": round(float(np.percentile(r32["lat"], 99)), 4),
+            "solves_per_s": round(len(fs) / r32["solve_batch_s"], 3),
+            "solve_ms_single": round(r32["solve_single_s"] * 1e3, 3),
+            "solve_cycles": round(r32["solve_cycles"], 2),
+            "rho_solve": round(r32["rho"], 5),
+            "rho_obs_lag1_max": round(float(np.max(np.abs(lag1(r32["obs"])))), 4),
             "rel_rms_vs_fp64_2_cycles": float("%.3e" % rel_rms)}
-        del Rs, r_states, r_outs
-        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(k_dec)

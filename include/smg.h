@@ -138,6 +138,65 @@ int smg_sample_field(smg_hierarchy* h, int64_t n, uint64_t seed, uint64_t first_
 int smg_solve(smg_hierarchy* h, const void* f, void* u, double rtol, int32_t max_cycles,
               void* stream, smg_solve_info* info);
 
+/* ---- Observables of the chain (Sec. "Stochastic Iterative Methods": the lag-k correlation of
+ * the emitted samples decides how many cycles separate effectively independent draws). ----
+ * A mode is a triple (a, b, m) naming the real eigenvector phi = e_a(x) e_b(y) w_m(z) of A:
+ * e_a is the a-th real periodic vector on n points (a = 0: 1/sqrt(n); a = 2j-1 and a = 2j,
+ * 1 <= j < n/2: sqrt(2/n) cos(2 pi j i/n) and sqrt(2/n) sin(2 pi j i/n); a = n-1:
+ * (-1)^i/sqrt(n)); w_m (m = 1..nz) is sin(pi m (z + 1/2)/nz) normalised.  Its eigenvalue is
+ * (4/h^2)(sin^2(pi j_a/nx) + sin^2(pi j_b/ny) + sin^2(pi m/(2 nz))). */
+#define SMG_MAX_MODES 32
+
+/* smg_lowest_modes: the k (<= SMG_MAX_MODES, <= nx*ny*nz) modes with the smallest
+ * eigenvalues on an nx x ny x nz grid (nx, ny even), ascending; ties broken by m, then b,
+ * then a, eigenvalues compared after rounding to multiples of 2^-30/h^2.  modes: host
+ * int32 [k][3] (a, b, m).  Host only.  Errors: SMG_EINVAL. */
+int smg_lowest_modes(int32_t nx, int32_t ny, int32_t nz, int32_t k, int32_t* modes);
+
+/* smg_sample_stats: smg_sample_field with FP64 statistics of every emitted sample, taken in
+ * the same pass that writes it.  For emitted sample i and component c:
+ *   obs[i][c][q] = <phi_q, x_c>  (q < n_modes),  obs[i][c][n_modes] = 1/2 x_c^T A x_c
+ *   (obs: device float64 [n][ncomp][n_modes + 1], 8-byte aligned; NULL = none);
+ *   moments[0][c][cell] += x_c[cell], moments[1][c][cell] += x_c[cell]^2
+ *   (moments: device float64 [2][ncomp][nz][ny][nx], accumulated over calls -- the caller
+ *   zeroes it; NULL = none).
+ * out may be NULL (statistics only).  modes: host int32 [n_modes][3], 0 <= n_modes <=
+ * SMG_MAX_MODES (read during the call).  Sums run in a fixed order, so results do not
+ * depend on timing.  Asynchronous, except that a new mode list is uploaded synchronously.
+ * Errors: as smg_sample_field, SMG_EINVAL for a mode outside the grid. */
+int smg_sample_stats(smg_hierarchy* h, int64_t n, uint64_t seed, uint64_t first_cycle,
+                     void* state, void* out, int32_t out_dtype, const int32_t* modes,
+                     int32_t n_modes, void* obs, void* moments, void* stream);
+
+/* ---- Batched chains: many independent instances of one grid in every launch. ----
+ * A hierarchy of ncomp components can carry nchains independent chains of comps_per_chain
+ * components each (nchains * comps_per_chain <= ncomp; only those first components are
+ * processed).  Chain c is keyed by its own seed and first cycle and draws exactly the noise
+ * that smg_sample_field on a hierarchy of comps_per_chain components draws for that seed and
+ * cycle (its components are numbered from 0 in the noise counters), so every result is bit
+ * for bit that of the chain run alone; each launch covers all chains at once. */
+
+/* smg_sample_batch: like smg_sample_stats for nchains chains.  seeds and first_cycles: host
+ * uint64 [nchains] (first_cycles NULL = all 0), copied into the hierarchy's chain table in
+ * stream order; seeds == NULL reuses the table as the previous batched call left it.  Every
+ * call advances the table by the cycles it ran, so a repeated call -- or a replay of a
+ * captured graph of the call -- continues every chain.  state, out, obs, moments cover the
+ * nchains*comps_per_chain processed components ([..][nchains*comps_per_chain][..] layouts).
+ * Errors: as smg_sample_stats; SMG_ESTATE when seeds == NULL and no table of this shape
+ * was written; at most 255 chains. */
+int smg_sample_batch(smg_hierarchy* h, int32_t nchains, int32_t comps_per_chain,
+                     const uint64_t* seeds, const uint64_t* first_cycles, int64_t n, void* state,
+                     void* out, int32_t out_dtype, const int32_t* modes, int32_t n_modes,
+                     void* obs, void* moments, void* stream);
+
+/* smg_solve_batch: solves A u = f for every chain (f, u: [nchains*comps_per_chain][N]).
+ * All chains cycle together; a chain's u is written at the cycle its components all reach
+ * rtol, so it equals the solve of that chain alone.  infos: host [nchains].  Returns
+ * SMG_ENOTCONV if any chain missed rtol within max_cycles (its u is the last iterate). */
+int smg_solve_batch(smg_hierarchy* h, int32_t nchains, int32_t comps_per_chain, const void* f,
+                    void* u, double rtol, int32_t max_cycles, void* stream,
+                    smg_solve_info* infos);
+
 /* Frees the host object.  Never touches the caller's device memory. */
 void smg_destroy_hierarchy(smg_hierarchy* h);
 
@@ -177,18 +236,23 @@ int smg_debug_host_table(const smg_hierarchy* h, int32_t level, int32_t which, d
 /* smg_set_option: execution switches that never change results.
  *   SMG_OPT_BOTTOM_KERNEL (default 1): run the levels with at most 4096 cells (and the
  *   coarsest draw) in one LDS-resident launch per cycle; 0 = one launch per colour pass.
+ *   SMG_OPT_BLOCK_TILE (default SMG_TILE_AUTO): see below.
  *   SMG_OPT_TIMED_KERNEL (default SMG_TIMED_FINE_PASS): the kernel class that
  *   smg_kernel_timing brackets with events: the level-0 colour pass, the level-1 block
  *   colour pass, or the LDS-resident bottom launch. */
-enum { SMG_OPT_BOTTOM_KERNEL = 1, SMG_OPT_TIMED_KERNEL = 2 };
+enum { SMG_OPT_BOTTOM_KERNEL = 1, SMG_OPT_TIMED_KERNEL = 2, SMG_OPT_BLOCK_TILE = 3 };
+/* SMG_OPT_BLOCK_TILE: blocks per work-group (x by y) of the Galerkin-level block passes;
+ * SMG_TILE_AUTO (default) takes 4x4 unless that gives fewer than 512 work-groups. */
+enum { SMG_TILE_AUTO = 0, SMG_TILE_4X4 = 1, SMG_TILE_4X2 = 2, SMG_TILE_8X4 = 3 };
 enum { SMG_TIMED_FINE_PASS = 0, SMG_TIMED_LEVEL1_BLOCK_PASS = 1, SMG_TIMED_BOTTOM = 2 };
 int smg_set_option(smg_hierarchy* h, int32_t option, int64_t value);
 
 /* ---- Kernel timing (measurement support). ----
- * When enabled, the library records HIP events on the caller's stream around every launch
- * of the kernel class chosen by SMG_OPT_TIMED_KERNEL and accumulates their elapsed times
- * (read after the stream is idle).  *count receives the number of timed launches, *total_ms their sum;
- * the counters are reset by smg_kernel_timing(h, 1). */
+ * When enabled, the library records HIP events on the caller's stream around every run of
+ * back-to-back launches of the kernel class chosen by SMG_OPT_TIMED_KERNEL (the colour
+ * passes of one sweep, or one bottom launch) and accumulates their elapsed times (read after
+ * the stream is idle).  *count receives the number of launches inside the bracketed runs,
+ * *total_ms the sum of the runs' elapsed times; both are reset by smg_kernel_timing(h, 1). */
 int smg_kernel_timing(smg_hierarchy* h, int32_t enable);
 int smg_kernel_timing_read(smg_hierarchy* h, int64_t* count, double* total_ms);
 

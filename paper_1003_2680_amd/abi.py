@@ -23,6 +23,12 @@ SMG_OPT_TIMED_KERNEL = 2
 SMG_TIMED_FINE_PASS = 0
 SMG_TIMED_LEVEL1_BLOCK_PASS = 1
 SMG_TIMED_BOTTOM = 2
+SMG_MAX_MODES = 32
+SMG_OPT_BLOCK_TILE = 3
+SMG_TILE_AUTO = 0
+SMG_TILE_4X4 = 1
+SMG_TILE_4X2 = 2
+SMG_TILE_8X4 = 3
 
 ERROR_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_ENOTCONV",
                -4: "SMG_ENONFINITE", -5: "SMG_EHIP", -6: "SMG_ESTATE"}
@@ -31,7 +37,8 @@ EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
             "smg_sample_field", "smg_solve", "smg_destroy_hierarchy", "smg_last_error",
             "smg_debug_smooth", "smg_debug_restrict_residual", "smg_debug_prolong_add",
             "smg_debug_coarsest", "smg_debug_host_table", "smg_set_option",
-            "smg_kernel_timing", "smg_kernel_timing_read"]
+            "smg_kernel_timing", "smg_kernel_timing_read", "smg_lowest_modes",
+            "smg_sample_stats", "smg_sample_batch", "smg_solve_batch"]
 
 
 class GridDesc(ctypes.Structure):
@@ -100,6 +107,14 @@ def load():
         "smg_kernel_timing": ([H, ctypes.c_int32], ctypes.c_int),
         "smg_kernel_timing_read": ([H, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "smg_lowest_modes": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P],
+                             ctypes.c_int),
+        "smg_sample_stats": ([H, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, P, P,
+                              ctypes.c_int32, P, ctypes.c_int32, P, P, P], ctypes.c_int),
+        "smg_sample_batch": ([H, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int64, P, P,
+                              ctypes.c_int32, P, ctypes.c_int32, P, P, P], ctypes.c_int),
+        "smg_solve_batch": ([H, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_double,
+                             ctypes.c_int32, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -17,6 +17,15 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def lowest_modes(nx, ny, nz, k):
+    """The k eigenvectors of A with the smallest eigenvalues, as (a, b, m) triples (C-ABI
+    smg_lowest_modes)."""
+    lib = abi.load()
+    arr = (ctypes.c_int32 * (3 * max(k, 1)))()
+    abi.check(lib.smg_lowest_modes(int(nx), int(ny), int(nz), int(k), arr))
+    return [(arr[3 * q], arr[3 * q + 1], arr[3 * q + 2]) for q in range(k)]
+
+
 class Hierarchy:
     """A planned multigrid hierarchy bound to a device workspace.
 
@@ -81,6 +90,98 @@ class Hierarchy:
                                             _stream(self.device)))
         return out, state
 
+    def sample_stats(self, n, seed, modes=None, first_cycle=0, state=None, out=None,
+                     out_dtype=torch.float64, moments=None, with_obs=True):
+        """Run the chain and take FP64 statistics of every emitted sample.
+
+        modes: (a, b, m) triples (default: the 8 lowest modes of A).  Returns
+        (obs [n, ncomp, len(modes) + 1] float64 -- projections then the energy 1/2 x^T A x --
+        or None, state).  `moments` ([2, ncomp, nz, ny, nx] float64, caller-zeroed) receives
+        running sums of x and x^2; `out` (optional) the samples themselves."""
+        if state is None:
+            state = self.new_state()
+        self._check_field(state)
+        if modes is None:
+            modes = lowest_modes(self.desc.nx, self.desc.ny, self.desc.nz, 8)
+        marr = (ctypes.c_int32 * (3 * max(len(modes), 1)))(*[int(v) for md in modes for v in md])
+        obs = None
+        if with_obs:
+            obs = torch.empty((n, self.shape[0], len(modes) + 1), dtype=torch.float64,
+                              device=self.device)
+        if moments is not None:
+            if moments.dtype != torch.float64 or tuple(moments.shape) != (2,) + self.shape \
+                    or not moments.is_contiguous():
+                raise ValueError("moments must be a contiguous float64 (2,) + shape tensor")
+        code = abi.SMG_OUT_F32 if out_dtype == torch.float32 else abi.SMG_OUT_F64
+        abi.check(self.lib.smg_sample_stats(
+            self._h, int(n), int(seed), int(first_cycle), _ptr(state),
+            _ptr(out) if out is not None else None, code, marr, len(modes),
+            _ptr(obs) if obs is not None and n > 0 else None,
+            _ptr(moments) if moments is not None else None, _stream(self.device)))
+        return obs, state
+
+    # ------------------------------------------------------------------ batched chains
+    def _batch_shape(self, nchains, comps_per_chain):
+        if comps_per_chain is None:
+            comps_per_chain = self.shape[0] // nchains
+        nact = nchains * comps_per_chain
+        if nchains < 1 or comps_per_chain < 1 or nact > self.shape[0]:
+            raise ValueError("nchains * comps_per_chain must be within ncomp")
+        return comps_per_chain, (nact,) + self.shape[1:]
+
+    def sample_batch(self, n, seeds=None, first_cycles=None, nchains=None, comps_per_chain=None,
+                     state=None, out=None, out_dtype=torch.float64, modes=None, with_obs=False,
+                     moments=None, emit=True):
+        """Run nchains independent chains (seeds[c], first_cycles[c]) in the same launches.
+
+        seeds=None continues the chains of the previous batched call (nchains required).
+        emit=False runs the cycles without writing samples (unless `out` is given).
+        Returns (out [n, nact, nz, ny, nx] or None, obs or None, state [nact, nz, ny, nx])
+        with nact = nchains * comps_per_chain."""
+        if seeds is not None:
+            nchains = len(seeds)
+        cpc, fshape = self._batch_shape(nchains, comps_per_chain)
+        if state is None:
+            state = torch.zeros(fshape, dtype=torch.float64, device=self.device)
+        if state.dtype != torch.float64 or tuple(state.shape) != fshape or not state.is_contiguous():
+            raise ValueError("state must be a contiguous float64 %s tensor" % (fshape,))
+        if out is None and n > 0 and emit and not with_obs and moments is None:
+            out = torch.empty((n,) + fshape, dtype=out_dtype, device=self.device)
+        sd = fc = None
+        if seeds is not None:
+            sd = (ctypes.c_uint64 * nchains)(*[int(v) for v in seeds])
+            if first_cycles is not None:
+                fc = (ctypes.c_uint64 * nchains)(*[int(v) for v in first_cycles])
+        marr, nm, obs = None, 0, None
+        if with_obs:
+            if modes is None:
+                modes = lowest_modes(self.desc.nx, self.desc.ny, self.desc.nz, 8)
+            nm = len(modes)
+            marr = (ctypes.c_int32 * (3 * max(nm, 1)))(*[int(v) for md in modes for v in md])
+            obs = torch.empty((n, fshape[0], nm + 1), dtype=torch.float64, device=self.device)
+        code = abi.SMG_OUT_F32 if out_dtype == torch.float32 else abi.SMG_OUT_F64
+        abi.check(self.lib.smg_sample_batch(
+            self._h, int(nchains), int(cpc), sd, fc, int(n), _ptr(state),
+            _ptr(out) if out is not None else None, code, marr, nm,
+            _ptr(obs) if obs is not None and n > 0 else None,
+            _ptr(moments) if moments is not None else None, _stream(self.device)))
+        return out, obs, state
+
+    def solve_batch(self, f, nchains, comps_per_chain=None, rtol=1e-12, max_cycles=100, u=None,
+                    raise_on_notconv=True):
+        """Solve every chain's A u = f together; returns (u, [(cycles, relres, last_ratio)])."""
+        cpc, fshape = self._batch_shape(nchains, comps_per_chain)
+        if f.dtype != torch.float64 or tuple(f.shape) != fshape or not f.is_contiguous():
+            raise ValueError("f must be a contiguous float64 %s tensor" % (fshape,))
+        if u is None:
+            u = torch.empty(fshape, dtype=torch.float64, device=self.device)
+        infos = (abi.SolveInfo * nchains)()
+        rc = self.lib.smg_solve_batch(self._h, int(nchains), int(cpc), _ptr(f), _ptr(u),
+                                      float(rtol), int(max_cycles), _stream(self.device), infos)
+        if rc != abi.SMG_ENOTCONV or raise_on_notconv:
+            abi.check(rc)
+        return u, [(i.cycles, i.relres, i.last_ratio) for i in infos]
+
     def solve(self, f, rtol=1e-12, max_cycles=100, u=None, raise_on_notconv=True):
         """Solve A u = f from u = 0; returns (u, cycles, relres).  The contraction of the
         last cycle is kept in ``self.last_ratio``."""
@@ -116,6 +217,12 @@ class Hierarchy:
     def set_bottom_kernel(self, enable):
         """Run the small levels in one LDS-resident launch per cycle (default) or per pass."""
         abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_BOTTOM_KERNEL, int(bool(enable))))
+
+    def set_block_tile(self, tile):
+        """Tile shape of the Galerkin block passes: "auto", "4x4", "4x2" or "8x4"."""
+        code = {"auto": abi.SMG_TILE_AUTO, "4x4": abi.SMG_TILE_4X4, "4x2": abi.SMG_TILE_4X2,
+                "8x4": abi.SMG_TILE_8X4}[tile]
+        abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_BLOCK_TILE, code))
 
     def kernel_timing(self, enable, kernel="fine_pass"):
         """Bracket every launch of one kernel class with HIP events: "fine_pass" (level-0

@@ -11,7 +11,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libsmg.so")
-SOURCES = ["plan.cpp", "capi.cpp", "kernels_fine.hip", "kernels_gal.hip", "kernels_util.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "kernels_fine.hip", "kernels_gal.hip", "kernels_util.hip",
+           "kernels_stats.hip"]
 ARCH = os.environ.get("SMG_OFFLOAD_ARCH", "gfx950")
 
 

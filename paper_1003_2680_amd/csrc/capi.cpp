@@ -15,6 +15,7 @@
 // running it on (0, b - A x).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -56,8 +57,16 @@ struct Run {
   bool noise;
   bool has_b0;  // level-0 right-hand side present (solve, and the refined inner cycle)
   uint64_t seed;
-  uint64_t cycle;
+  uint64_t cycle;  // with `chains`: cycles since each chain's first cycle
+  int nc;          // components processed: the first nc of the hierarchy's ncomp
+  const ChainKey* chains;  // batched chains (device table) or null
+  uint32_t cpc;            // components per chain
 };
+
+Run make_run(Hierarchy& h, hipStream_t s, bool noise, bool has_b0, uint64_t seed,
+             uint64_t cycle) {
+  return Run{&h, s, noise, has_b0, seed, cycle, h.desc.ncomp, nullptr, 1};
+}
 
 NoiseArgs make_noise(const Run& r, int level, int slot, int colour, uint32_t kind) {
   NoiseArgs na;
@@ -67,6 +76,8 @@ NoiseArgs make_noise(const Run& r, int level, int slot, int colour, uint32_t kin
   na.c2 = (uint32_t)r.cycle;
   na.c3 = (uint32_t)(r.cycle >> 32);
   na.sqkT = std::sqrt(r.h->desc.kT);
+  na.chains = r.chains;
+  na.comps_per_chain = r.cpc;
   return na;
 }
 
@@ -90,13 +101,17 @@ struct Fld<float> {
   static float* r(Level& v) { return v.rf; }
 };
 
-// Events around one launch of the timed kernel class (measurement support).
+// Events around a run of back-to-back launches of the timed kernel class (measurement
+// support): the colour passes of one sweep, or one bottom launch.  Bracketing the run rather
+// than each launch keeps the event overhead out of the per-launch average.
 struct TimedScope {
   Hierarchy& h;
   hipStream_t s;
   hipEvent_t e1 = nullptr;
+  int launches;
   int rc = SMG_OK;
-  TimedScope(Hierarchy& hh, hipStream_t ss, int kind) : h(hh), s(ss) {
+  TimedScope(Hierarchy& hh, hipStream_t ss, int kind, int nlaunch)
+      : h(hh), s(ss), launches(nlaunch) {
     if (!h.timing || h.timed_kernel != kind) return;
     if (h.ev_used + 2 > h.ev_pool.size()) {
       for (int i = 0; i < 64; ++i) {
@@ -117,23 +132,24 @@ struct TimedScope {
     }
   }
   int close() {
-    if (rc == SMG_OK && e1 && hipEventRecord(e1, s) != hipSuccess) {
-      set_error("hipEventRecord failed");
-      rc = SMG_EHIP;
+    if (rc == SMG_OK && e1) {
+      if (hipEventRecord(e1, s) != hipSuccess) {
+        set_error("hipEventRecord failed");
+        rc = SMG_EHIP;
+      }
+      h.ev_launches.push_back(launches);
     }
     return rc;
   }
 };
 
 template <typename T>
-int timed_rb_pass(Run& r, T* xc, const T* xo, const T* bc, int colour, const NoiseArgs& na) {
+int rb_pass(Run& r, T* xc, const T* xo, const T* bc, int colour, const NoiseArgs& na) {
   Hierarchy& h = *r.h;
   const Level& v = h.lv[0];
-  TimedScope ts(h, r.s, SMG_TIMED_FINE_PASS);
-  SMG_TRY(ts.rc);
-  SMG_HIP(launch_rb_pass<T>(xc, xo, bc, v.nx, v.ny, v.nz, h.desc.ncomp, colour, h.desc.h,
+  SMG_HIP(launch_rb_pass<T>(xc, xo, bc, v.nx, v.ny, v.nz, r.nc, colour, h.desc.h,
                             h.desc.kT, r.noise, na, r.s));
-  return ts.close();
+  return SMG_OK;
 }
 
 template <typename T>
@@ -146,24 +162,27 @@ int sweep(Run& r, int l, int slot, bool post) {
     T* xb = xr + half_field(h);
     const T* br = Fld<T>::b(v);
     const T* bb = br + half_field(h);
+    TimedScope ts(h, r.s, SMG_TIMED_FINE_PASS, 2);
+    SMG_TRY(ts.rc);
     for (int t = 0; t < 2; ++t) {
       const int colour = post ? 1 - t : t;
       NoiseArgs na = make_noise(r, l, slot, colour, KIND_SMOOTH_NOISE);
       const T* bc = r.has_b0 ? (colour ? bb : br) : nullptr;
-      SMG_TRY(timed_rb_pass<T>(r, colour ? xb : xr, colour ? xr : xb, bc, colour, na));
+      SMG_TRY(rb_pass<T>(r, colour ? xb : xr, colour ? xr : xb, bc, colour, na));
     }
+    SMG_TRY(ts.close());
   } else {
     const T* noise = (const T*)v.noise_d;
+    TimedScope ts(h, r.s, l == 1 ? SMG_TIMED_LEVEL1_BLOCK_PASS : -1, 8);
+    SMG_TRY(ts.rc);
     for (int t = 0; t < 8; ++t) {
       const int colour = post ? 7 - t : t;
       const T* zn = r.noise ? noise + (size_t)slot * nc * v.n : nullptr;
-      TimedScope ts(h, r.s, l == 1 ? SMG_TIMED_LEVEL1_BLOCK_PASS : -1);
-      SMG_TRY(ts.rc);
-      SMG_HIP(launch_block_pass<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.g2d_d,
-                                   (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz, nc,
-                                   colour, zn, std::sqrt(h.desc.kT), r.s));
-      SMG_TRY(ts.close());
+      SMG_HIP(launch_block_pass<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
+                                   (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz, r.nc,
+                                   colour, zn, std::sqrt(h.desc.kT), h.block_tile, r.s));
     }
+    SMG_TRY(ts.close());
   }
   return SMG_OK;
 }
@@ -173,7 +192,7 @@ template <typename T>
 int restrict_residual(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
-  const int nc = h.desc.ncomp;
+  const int nc = r.nc;
   T* rr = Fld<T>::r(v);
   if (v.kind == KIND_POINT) {
     T* xr = Fld<T>::x(v);
@@ -182,7 +201,7 @@ int restrict_residual(Run& r, int l) {
                                 r.has_b0 ? br + half_field(h) : nullptr, v.nx, v.ny, v.nz, nc,
                                 h.desc.h, r.s));
   } else {
-    SMG_HIP(launch_residual_gal<T>(rr, Fld<T>::x(v), Fld<T>::b(v), (const T*)v.g2d_d,
+    SMG_HIP(launch_residual_gal<T>(rr, Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
                                    (const T*)v.zt_d, v.nx, v.ny, v.nz, nc, r.s));
   }
   Level& c = h.lv[l + 1];
@@ -196,7 +215,7 @@ template <typename T>
 int prolong_add(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
-  const int nc = h.desc.ncomp;
+  const int nc = r.nc;
   const T* e = Fld<T>::x(h.lv[l + 1]);
   if (v.kind == KIND_POINT) {
     T* xr = Fld<T>::x(v);
@@ -212,7 +231,7 @@ int coarsest_step(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   NoiseArgs na = make_noise(r, l, 0, 0, KIND_COARSEST_NOISE);
-  SMG_HIP(launch_coarsest<T>(Fld<T>::x(v), Fld<T>::b(v), h.ainv_d, h.w_d, h.nc, h.desc.ncomp,
+  SMG_HIP(launch_coarsest<T>(Fld<T>::x(v), Fld<T>::b(v), h.ainv_d, h.w_d, h.nc, r.nc,
                              r.noise, na, r.s));
   return SMG_OK;
 }
@@ -224,6 +243,7 @@ int gen_level_noise(Run& r, int only_level = -1, int only_slot = 0) {
   Hierarchy& h = *r.h;
   NoiseGenArgs a{};
   a.ncomp = h.desc.ncomp;
+  a.nact = r.nc;
   uint32_t calls = 0;
   for (int l = 0; l < (int)h.lv.size(); ++l) {
     const Level& v = h.lv[l];
@@ -241,7 +261,7 @@ int gen_level_noise(Run& r, int only_level = -1, int only_slot = 0) {
     e.slot0 = only_level >= 0 ? only_slot : 0;
     e.out = v.noise_d;
     e.calls_before = calls;
-    calls += (uint32_t)(e.nslot * a.ncomp * (v.n / 2));
+    calls += (uint32_t)(e.nslot * a.nact * (v.n / 2));
   }
   if (a.nlev == 0) return SMG_OK;
   a.total = calls;
@@ -264,14 +284,24 @@ BotArgs make_botargs(Hierarchy& h) {
     const Level& v = h.lv[h.bottom + i];
     int sy, sz;
     bot_strides(v.kind, v.nx, v.ny, sy, sz);
-    a.lv[i] = BotLevel{v.nx, v.ny, v.nz, v.kind, sy, sz, v.noise_d, v.g2d_d, v.zt_d, v.bfac_d};
+    BotLevel& bl = a.lv[i];
+    bl.nx = v.nx;
+    bl.ny = v.ny;
+    bl.nz = v.nz;
+    bl.kind = v.kind;
+    bl.sy = sy;
+    bl.sz = sz;
+    bl.noise = v.noise_d;
+    for (int q = 0; q < 20; ++q) bl.s1d[q] = v.s1d.empty() ? 0.0 : v.s1d[q];
+    bl.zt = v.zt_d;
+    bl.bfac = v.bfac_d;
     a.lds_off[i] = off;
     off += 3 * (int)bot_field_elems(v.kind, v.nx, v.ny, v.nz);
   }
   for (int i = 0; i < a.nlev; ++i) {
     const Level& v = h.lv[h.bottom + i];
     a.tab_off[i] = off;
-    if (v.kind == KIND_BLOCK) off += 50 + v.nz * 10 + (v.nz / 2) * 192;
+    if (v.kind == KIND_BLOCK) off += v.nz * 10 + (v.nz / 2) * 192;
   }
   Level& b0 = h.lv[h.bottom];
   a.b_in = f32 ? (const void*)b0.bf : (const void*)b0.b;
@@ -286,9 +316,9 @@ template <typename T>
 int bottom_cycle(Run& r) {
   Hierarchy& h = *r.h;
   NoiseArgs na = make_noise(r, 0, 0, 0, KIND_SMOOTH_NOISE);
-  TimedScope ts(h, r.s, SMG_TIMED_BOTTOM);
+  TimedScope ts(h, r.s, SMG_TIMED_BOTTOM, 1);
   SMG_TRY(ts.rc);
-  SMG_HIP(launch_bottom<T>(h.botargs_d, h.desc.ncomp, h.bottom_lds, r.noise, na, r.s));
+  SMG_HIP(launch_bottom<T>(h.botargs_d, r.nc, h.bottom_lds, r.noise, na, r.s));
   return ts.close();
 }
 
@@ -304,7 +334,7 @@ int vcycle(Run& r, int l) {
     SMG_TRY(restrict_residual<T>(r, l));
     Level& c = h.lv[l + 1];
     if (l + 1 == h.bottom && !h.use_bottom)
-      SMG_HIP(launch_zero<T>(Fld<T>::x(c), (int64_t)h.desc.ncomp * c.n, r.s));
+      SMG_HIP(launch_zero<T>(Fld<T>::x(c), (int64_t)r.nc * c.n, r.s));
     SMG_TRY(vcycle<T>(r, l + 1));
     SMG_TRY(prolong_add<T>(r, l));
   }
@@ -324,32 +354,46 @@ int full_cycle(Run& r, bool residual_ready = false) {
   if (r.noise) SMG_TRY(gen_level_noise<float>(r));
   if (!residual_ready)
     SMG_HIP(launch_refine_residual(v0.bf, v0.x, r.has_b0 ? v0.b : nullptr, v0.nx, v0.ny, v0.nz,
-                                   h.desc.ncomp, h.desc.h, nullptr, nullptr, r.s));
-  SMG_HIP(launch_zero<float>(v0.xf, (int64_t)2 * half_field(h), r.s));
+                                   r.nc, h.desc.ncomp, h.desc.h, nullptr, nullptr, r.s));
+  // the processed components of both colour arrays
+  const int64_t act = (int64_t)r.nc * (v0.n / 2);
+  const size_t half = half_field(h);
+  SMG_HIP(launch_zero<float>(v0.xf, act, r.s));
+  SMG_HIP(launch_zero<float>(v0.xf + half, act, r.s));
   Run ri = r;
   ri.has_b0 = true;
   SMG_TRY(vcycle<float>(ri, 0));
-  SMG_HIP(launch_refine_update(v0.x, v0.xf, (int64_t)2 * half_field(h), r.s));
+  SMG_HIP(launch_refine_update(v0.x, v0.xf, act, r.s));
+  SMG_HIP(launch_refine_update(v0.x + half, v0.xf + half, act, r.s));
   return SMG_OK;
 }
 
-// natural [ncomp][N] field -> level-0 storage (x or b)
-int import_level0(Hierarchy& h, double* dst, const double* nat, hipStream_t s) {
+// natural [nc][N] field -> components c0 .. c0+nc-1 of the level-0 storage (x or b)
+int import_level0(Hierarchy& h, double* dst, const double* nat, hipStream_t s, int nc = -1,
+                  int c0 = 0) {
   Level& v = h.lv[0];
-  if (v.kind == KIND_POINT)
-    SMG_HIP(launch_to_split(dst, dst + half_field(h), nat, v.nx, v.ny, v.nz, h.desc.ncomp, s));
-  else
-    SMG_HIP(launch_copy(dst, nat, (int64_t)h.desc.ncomp * v.n, s));
+  if (nc < 0) nc = h.desc.ncomp;
+  if (v.kind == KIND_POINT) {
+    const size_t off = (size_t)c0 * (v.n / 2);
+    SMG_HIP(launch_to_split(dst + off, dst + half_field(h) + off, nat, v.nx, v.ny, v.nz, nc, s));
+  } else {
+    SMG_HIP(launch_copy(dst + (size_t)c0 * v.n, nat, (int64_t)nc * v.n, s));
+  }
   return SMG_OK;
 }
 
-int export_level0(Hierarchy& h, void* nat, int out_f32, const double* src, hipStream_t s) {
+// components c0 .. c0+nc-1 of the level-0 storage -> natural [nc][N] (float64 or float32)
+int export_level0(Hierarchy& h, void* nat, int out_f32, const double* src, hipStream_t s,
+                  int nc = -1, int c0 = 0) {
   Level& v = h.lv[0];
-  if (v.kind == KIND_POINT)
-    SMG_HIP(launch_from_split(nat, out_f32, src, src + half_field(h), v.nx, v.ny, v.nz,
-                              h.desc.ncomp, s));
-  else
-    SMG_HIP(launch_cast(nat, out_f32, src, (int64_t)h.desc.ncomp * v.n, s));
+  if (nc < 0) nc = h.desc.ncomp;
+  if (v.kind == KIND_POINT) {
+    const size_t off = (size_t)c0 * (v.n / 2);
+    SMG_HIP(launch_from_split(nat, out_f32, src + off, src + half_field(h) + off, v.nx, v.ny,
+                              v.nz, nc, s));
+  } else {
+    SMG_HIP(launch_cast(nat, out_f32, src + (size_t)c0 * v.n, (int64_t)nc * v.n, s));
+  }
   return SMG_OK;
 }
 
@@ -387,18 +431,346 @@ int check_fp64(const Hierarchy& h) {
 // Block-level tables in the sweep precision T (rounded from the FP64 tables in refined mode).
 template <typename T>
 int upload_tables(Level& v, char* ws, hipStream_t s) {
-  std::vector<T> g(v.g2d.begin(), v.g2d.end());
+  std::vector<T> g(v.s1d.begin(), v.s1d.end());
   std::vector<T> z(v.zt.begin(), v.zt.end());
   std::vector<T> b(v.bfac.begin(), v.bfac.end());
-  v.g2d_d = ws + v.off_g2d;
+  v.s1d_d = ws + v.off_s1d;
   v.zt_d = ws + v.off_zt;
   v.bfac_d = ws + v.off_bfac;
   v.noise_d = ws + v.off_noise;
-  SMG_HIP(hipMemcpyAsync(v.g2d_d, g.data(), g.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  SMG_HIP(hipMemcpyAsync(v.s1d_d, g.data(), g.size() * sizeof(T), hipMemcpyHostToDevice, s));
   SMG_HIP(hipMemcpyAsync(v.zt_d, z.data(), z.size() * sizeof(T), hipMemcpyHostToDevice, s));
   SMG_HIP(hipMemcpyAsync(v.bfac_d, b.data(), b.size() * sizeof(T), hipMemcpyHostToDevice, s));
   // the staging vectors die on return
   SMG_HIP(hipStreamSynchronize(s));
+  return SMG_OK;
+}
+
+// Real 1D eigenvectors (see smg.h, observables): periodic axis on n points, index a.
+double periodic_factor(int n, int a, int i) {
+  if (a == 0) return 1.0 / std::sqrt((double)n);
+  if (a == n - 1) return ((i & 1) ? -1.0 : 1.0) / std::sqrt((double)n);
+  const int j = (a + 1) / 2;
+  const double t = 2.0 * M_PI * j * i / n;
+  return std::sqrt(2.0 / n) * ((a & 1) ? std::cos(t) : std::sin(t));
+}
+
+// wall axis, m = 1..nz: sin(pi m (z + 1/2) / nz), normalised
+void wall_vector(int nz, int m, double* out) {
+  double ss = 0.0;
+  for (int z = 0; z < nz; ++z) {
+    out[z] = std::sin(M_PI * m * (z + 0.5) / nz);
+    ss += out[z] * out[z];
+  }
+  const double inv = 1.0 / std::sqrt(ss);
+  for (int z = 0; z < nz; ++z) out[z] *= inv;
+}
+
+int periodic_wavenumber(int n, int a) {
+  if (a == 0) return 0;
+  if (a == n - 1) return n / 2;
+  return (a + 1) / 2;
+}
+
+int check_modes(const Hierarchy& h, const int32_t* modes, int k) {
+  const Level& v = h.lv[0];
+  if (k < 0 || k > kMaxModes || (k > 0 && !modes)) {
+    set_error("n_modes must be in [0, " + std::to_string(kMaxModes) + "] with a mode list");
+    return SMG_EINVAL;
+  }
+  for (int q = 0; q < k; ++q) {
+    const int a = modes[3 * q], b = modes[3 * q + 1], m = modes[3 * q + 2];
+    if (a < 0 || a >= v.nx || b < 0 || b >= v.ny || m < 1 || m > v.nz) {
+      set_error("mode " + std::to_string(q) + " out of range for the grid");
+      return SMG_EINVAL;
+    }
+  }
+  return SMG_OK;
+}
+
+// Device tables of the modes' 1D factors (uploaded when the mode list changes).
+int load_modes(Hierarchy& h, const int32_t* modes, int k, hipStream_t s) {
+  std::vector<int32_t> want(modes, modes + 3 * k);
+  if (h.modes_valid && want == h.modes_loaded) return SMG_OK;
+  const Level& v = h.lv[0];
+  std::vector<double> tab((size_t)kMaxModes * (v.nx + v.ny + v.nz), 0.0);
+  double* tx = tab.data();
+  double* ty = tx + (size_t)kMaxModes * v.nx;
+  double* tz = ty + (size_t)kMaxModes * v.ny;
+  for (int q = 0; q < k; ++q) {
+    for (int i = 0; i < v.nx; ++i) tx[q * v.nx + i] = periodic_factor(v.nx, modes[3 * q], i);
+    for (int i = 0; i < v.ny; ++i) ty[q * v.ny + i] = periodic_factor(v.ny, modes[3 * q + 1], i);
+    wall_vector(v.nz, modes[3 * q + 2], tz + q * v.nz);
+  }
+  SMG_HIP(hipMemcpyAsync(h.ws + h.off_mtab, tab.data(), tab.size() * sizeof(double),
+                         hipMemcpyHostToDevice, s));
+  SMG_HIP(hipStreamSynchronize(s));  // the staging vector dies on return
+  h.modes_loaded = want;
+  h.modes_valid = true;
+  return SMG_OK;
+}
+
+// Emission of components c0 .. c0+nc-1 of the level-0 state with optional statistics (one
+// fused pass; obs, m1, m2 and out are laid out over those nc components).
+int emit(Hierarchy& h, void* out, int out_f32, double* obs, double* m1, double* m2, int k,
+         int nc, hipStream_t s) {
+  Level& v0 = h.lv[0];
+  if (!obs && !m1) {
+    if (out) SMG_TRY(export_level0(h, out, out_f32, v0.x, s, nc));
+    return SMG_OK;
+  }
+  StatsArgs a{};
+  const bool split = v0.kind == KIND_POINT;
+  a.xr = v0.x;
+  a.xb = split ? v0.x + half_field(h) : nullptr;
+  a.nx = v0.nx;
+  a.ny = v0.ny;
+  a.nz = v0.nz;
+  a.nmodes = obs ? k : 0;
+  a.nblk = h.stats_nblk;
+  a.tx = (const double*)(h.ws + h.off_mtab);
+  a.ty = a.tx + (size_t)kMaxModes * v0.nx;
+  a.tz = a.ty + (size_t)kMaxModes * v0.ny;
+  a.out = out;
+  a.out_f32 = out_f32;
+  a.m1 = m1;
+  a.m2 = m2;
+  a.part = (double*)(h.ws + h.off_spart);
+  SMG_HIP(launch_stats(a, nc, obs, 0.5 / (h.desc.h * h.desc.h), s));
+  return SMG_OK;
+}
+
+// Batch description of a call: nchains chains of cpc components each (the first
+// nchains*cpc components of the hierarchy); nchains == 0 means one chain over all components.
+struct Batch {
+  int nchains = 0;
+  int cpc = 0;
+  int nc(const Hierarchy& h) const { return nchains > 0 ? nchains * cpc : h.desc.ncomp; }
+};
+
+int check_batch(const Hierarchy& h, const Batch& bt) {
+  if (bt.nchains == 0) return SMG_OK;
+  if (bt.nchains < 0 || bt.cpc < 1 || (int64_t)bt.nchains * bt.cpc > h.desc.ncomp ||
+      bt.nchains > kMaxChains) {
+    set_error("chains * comps_per_chain must be within the hierarchy's ncomp (and chains <= " +
+              std::to_string(kMaxChains) + ")");
+    return SMG_EINVAL;
+  }
+  return SMG_OK;
+}
+
+// Writes the chain table (seeds and first cycles) into the workspace, stream-ordered.
+int set_chains(Hierarchy& h, const Batch& bt, const uint64_t* seeds, const uint64_t* first,
+               hipStream_t s) {
+  for (int c0 = 0; c0 < bt.nchains; c0 += kChainsPerLaunch) {
+    ChainKeyBatch kb{};
+    kb.first = c0;
+    kb.count = std::min(kChainsPerLaunch, bt.nchains - c0);
+    for (int i = 0; i < kb.count; ++i) {
+      const uint64_t sd = seeds[c0 + i], fc = first ? first[c0 + i] : 0;
+      kb.k[i] = ChainKey{(uint32_t)sd, (uint32_t)(sd >> 32), (uint32_t)fc, (uint32_t)(fc >> 32)};
+    }
+    SMG_HIP(launch_set_chains(h.chains_d, kb, s));
+  }
+  h.chains_set = bt.nchains;
+  h.chains_cpc = bt.cpc;
+  return SMG_OK;
+}
+
+int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
+                const uint64_t* first_cycles, int64_t n, uint64_t seed, uint64_t first_cycle,
+                void* state, void* out, int32_t out_dtype, const int32_t* modes,
+                int32_t n_modes, void* obs, void* moments, void* stream) {
+  SMG_TRY(check_bound(hh));
+  SMG_TRY(check_ptr(state, "state"));
+  if (n < 0 || (out_dtype != SMG_OUT_F64 && out_dtype != SMG_OUT_F32)) {
+    set_error("invalid n / out_dtype");
+    return SMG_EINVAL;
+  }
+  if (n > 0 && out) SMG_TRY(check_ptr(out, "out"));
+  if (moments) SMG_TRY(check_ptr(moments, "moments"));
+  if (obs && ((uintptr_t)obs & 7u)) {
+    set_error("obs must be 8-byte aligned");
+    return SMG_EINVAL;
+  }
+  Hierarchy& h = hh->h;
+  SMG_TRY(check_batch(h, bt));
+  hipStream_t s = (hipStream_t)stream;
+  if (bt.nchains > 0) {
+    if (seeds) {
+      SMG_TRY(set_chains(h, bt, seeds, first_cycles, s));
+    } else if (h.chains_set != bt.nchains || h.chains_cpc != bt.cpc) {
+      set_error("no chain table of this shape was set (pass seeds)");
+      return SMG_ESTATE;
+    }
+  }
+  if (obs) {
+    SMG_TRY(check_modes(h, modes, n_modes));
+    SMG_TRY(load_modes(h, modes, n_modes, s));
+  }
+  Level& v0 = h.lv[0];
+  const int nc = bt.nc(h);
+  const int64_t field = (int64_t)nc * v0.n;
+  SMG_TRY(import_level0(h, v0.x, (const double*)state, s, nc));
+  if (v0.kind == KIND_CHOL) SMG_HIP(launch_zero<double>(v0.b, field, s));
+  Run r = make_run(h, s, h.desc.kT > 0.0, false, seed, first_cycle);
+  r.nc = nc;
+  if (bt.nchains > 0) {
+    r.chains = h.chains_d;
+    r.cpc = (uint32_t)bt.cpc;
+  }
+  const int64_t total = (int64_t)h.prm.burn_in + n * (int64_t)h.prm.stride;
+  const size_t out_elem = out_dtype == SMG_OUT_F32 ? sizeof(float) : sizeof(double);
+  const size_t obs_stride = (size_t)nc * (n_modes + 1);
+  double* m1 = (double*)moments;
+  double* m2 = m1 ? m1 + field : nullptr;
+  for (int64_t k = 0; k < total; ++k) {
+    r.cycle = bt.nchains > 0 ? (uint64_t)k : first_cycle + (uint64_t)k;
+    SMG_TRY(full_cycle(r));
+    const int64_t after = k + 1 - h.prm.burn_in;
+    if (after > 0 && after % h.prm.stride == 0) {
+      const int64_t idx = after / h.prm.stride - 1;
+      SMG_TRY(emit(h, out ? (char*)out + (size_t)idx * field * out_elem : nullptr,
+                   out_dtype == SMG_OUT_F32, obs ? (double*)obs + (size_t)idx * obs_stride : nullptr,
+                   m1, m2, n_modes, nc, s));
+    }
+  }
+  SMG_TRY(export_level0(h, state, 0, v0.x, s, nc));
+  // the chains continue from here: a repeated (or replayed) call draws the next cycles
+  if (bt.nchains > 0) SMG_HIP(launch_advance_chains(h.chains_d, bt.nchains, (uint64_t)total, s));
+  return SMG_OK;
+}
+
+// Solves for every chain (one chain = cpc components, or all components when nchains == 0).
+// A chain stops counting once all its components reach rtol: its u is written at that cycle,
+// so each result equals that of a solve of the chain alone.
+int solve_impl(smg_hierarchy* hh, const Batch& bt, const void* f, void* u, double rtol,
+               int32_t max_cycles, void* stream, smg_solve_info* infos) {
+  SMG_TRY(check_bound(hh));
+  SMG_TRY(check_ptr(f, "f"));
+  SMG_TRY(check_ptr(u, "u"));
+  if (!(rtol >= 0.0) || max_cycles < 0) {
+    set_error("rtol must be >= 0 and max_cycles >= 0");
+    return SMG_EINVAL;
+  }
+  Hierarchy& h = hh->h;
+  SMG_TRY(check_batch(h, bt));
+  hipStream_t s = (hipStream_t)stream;
+  Level& v0 = h.lv[0];
+  const int nc = bt.nc(h);
+  const int nch = bt.nchains > 0 ? bt.nchains : 1;
+  const int cpc = bt.nchains > 0 ? bt.cpc : nc;
+  const int64_t field = (int64_t)nc * v0.n;
+  const bool f32 = refined(h);
+  std::vector<double> fn(nc), rn(nc), rprev(nc, 0.0);
+  SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)f, v0.n, nc, s));
+  SMG_HIP(hipMemcpyAsync(fn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+  SMG_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < nc; ++c)
+    if (!std::isfinite(fn[c])) {
+      set_error("f is not finite");
+      return SMG_ENONFINITE;
+    }
+  SMG_TRY(import_level0(h, v0.b, (const double*)f, s, nc));
+  SMG_HIP(launch_zero<double>(v0.x, field, s));
+  Run r = make_run(h, s, false, true, 0, 0);
+  r.nc = nc;
+  struct ChainState {
+    bool done = false, all_zero = true;
+    int cycles = 0;
+    double relres = 0.0, last_ratio = 0.0;
+  };
+  std::vector<ChainState> cs(nch);
+  int pending = 0;
+  for (int ch = 0; ch < nch; ++ch) {
+    for (int c = ch * cpc; c < (ch + 1) * cpc; ++c) cs[ch].all_zero = cs[ch].all_zero && fn[c] == 0.0;
+    if (cs[ch].all_zero) {
+      cs[ch].done = true;  // u = 0 after zero cycles
+      SMG_TRY(export_level0(h, (double*)u + (size_t)ch * cpc * v0.n, 0, v0.x, s, cpc, ch * cpc));
+    } else {
+      cs[ch].relres = 1.0;
+      ++pending;
+    }
+  }
+  int cycles = 0;
+  // residual norms of the current iterate (refined mode leaves the FP32 residual in lv[0].bf)
+  auto residual_norms = [&]() -> int {
+    if (f32) {
+      SMG_HIP(launch_refine_residual(v0.bf, v0.x, v0.b, v0.nx, v0.ny, v0.nz, nc, h.desc.ncomp,
+                                     h.desc.h, h.part_d, h.norm_d, s));
+    } else if (v0.kind == KIND_POINT) {
+      SMG_HIP(launch_residual0<double>(v0.r, v0.x, v0.x + half_field(h), v0.b,
+                                       v0.b + half_field(h), v0.nx, v0.ny, v0.nz, nc, h.desc.h,
+                                       s));
+      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, v0.r, v0.n, nc, s));
+    } else {
+      // a level 0 that is drawn exactly has no residual buffer: u serves as scratch
+      SMG_HIP(launch_residual7_nat((double*)u, v0.x, v0.b, v0.nx, v0.ny, v0.nz, nc, h.desc.h, s));
+      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)u, v0.n, nc, s));
+    }
+    SMG_HIP(hipMemcpyAsync(rn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    SMG_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < nc; ++c)
+      if (!std::isfinite(rn[c])) {
+        set_error("residual is not finite");
+        return SMG_ENONFINITE;
+      }
+    return SMG_OK;
+  };
+  // per-chain relres and contraction of the last cycle from rn (rprev: previous cycle)
+  auto chain_norms = [&](int ch, double& relres, double& ratio) {
+    relres = 0.0;
+    ratio = 0.0;
+    for (int c = ch * cpc; c < (ch + 1) * cpc; ++c) {
+      const double rr = fn[c] > 0.0 ? std::sqrt(rn[c] / fn[c]) : (rn[c] > 0.0 ? INFINITY : 0.0);
+      relres = rr > relres ? rr : relres;
+      if (cycles >= 2 && rprev[c] > 0.0) {
+        const double q = std::sqrt(rn[c] / rprev[c]);
+        ratio = q > ratio ? q : ratio;
+      }
+    }
+  };
+  if (pending > 0) {
+    bool ready = false;
+    if (f32 && max_cycles > 0) {
+      SMG_TRY(residual_norms());  // residual of u = 0, i.e. f, rounded to FP32
+      rprev = rn;
+      ready = true;
+    }
+    while (pending > 0 && cycles < max_cycles) {
+      SMG_TRY(full_cycle(r, ready));
+      ++cycles;
+      SMG_TRY(residual_norms());
+      for (int ch = 0; ch < nch; ++ch) {
+        if (cs[ch].done) continue;
+        chain_norms(ch, cs[ch].relres, cs[ch].last_ratio);
+        cs[ch].cycles = cycles;
+        if (cs[ch].relres <= rtol) {
+          cs[ch].done = true;
+          --pending;
+          SMG_TRY(export_level0(h, (double*)u + (size_t)ch * cpc * v0.n, 0, v0.x, s, cpc,
+                                ch * cpc));
+        }
+      }
+      rprev = rn;
+    }
+  }
+  for (int ch = 0; ch < nch; ++ch)
+    if (!cs[ch].done)
+      SMG_TRY(export_level0(h, (double*)u + (size_t)ch * cpc * v0.n, 0, v0.x, s, cpc, ch * cpc));
+  SMG_HIP(hipStreamSynchronize(s));
+  if (infos)
+    for (int ch = 0; ch < nch; ++ch) {
+      infos[ch].cycles = cs[ch].cycles;
+      infos[ch].relres = cs[ch].relres;
+      infos[ch].last_ratio = cs[ch].last_ratio;
+    }
+  if (pending > 0) {
+    double worst = 0.0;
+    for (const auto& c : cs) worst = c.relres > worst ? c.relres : worst;
+    set_error("solve did not converge: relres " + std::to_string(worst));
+    return SMG_ENOTCONV;
+  }
   return SMG_OK;
 }
 
@@ -497,6 +869,9 @@ int smg_bind_workspace(smg_hierarchy* hh, void* dev_ptr, size_t bytes, void* str
   }
   h.part_d = (double*)(ws + h.off_part);
   h.norm_d = (double*)(ws + h.off_norm);
+  h.chains_d = (ChainKey*)(ws + h.off_chains);
+  h.chains_set = 0;
+  h.modes_valid = false;
   BotArgs ba{};
   if (h.bottom >= 0) {
     h.botargs_d = (BotArgs*)(ws + h.off_botargs);
@@ -510,129 +885,87 @@ int smg_bind_workspace(smg_hierarchy* hh, void* dev_ptr, size_t bytes, void* str
 
 int smg_sample_field(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
                      void* state, void* out, int32_t out_dtype, void* stream) {
-  SMG_TRY(check_bound(hh));
-  SMG_TRY(check_ptr(state, "state"));
-  if (n < 0 || (n > 0 && !out) || (out_dtype != SMG_OUT_F64 && out_dtype != SMG_OUT_F32)) {
-    set_error("invalid n / out / out_dtype");
+  if (n > 0 && !out) {
+    set_error("out is null");
     return SMG_EINVAL;
   }
-  if (n > 0) SMG_TRY(check_ptr(out, "out"));
-  Hierarchy& h = hh->h;
-  hipStream_t s = (hipStream_t)stream;
-  Level& v0 = h.lv[0];
-  const int64_t field = (int64_t)h.desc.ncomp * v0.n;
-  SMG_TRY(import_level0(h, v0.x, (const double*)state, s));
-  if (v0.kind == KIND_CHOL) SMG_HIP(launch_zero<double>(v0.b, field, s));
-  Run r{&h, s, h.desc.kT > 0.0, false, seed, first_cycle};
-  const int64_t total = (int64_t)h.prm.burn_in + n * (int64_t)h.prm.stride;
-  const size_t out_elem = out_dtype == SMG_OUT_F32 ? sizeof(float) : sizeof(double);
-  for (int64_t k = 0; k < total; ++k) {
-    r.cycle = first_cycle + (uint64_t)k;
-    SMG_TRY(full_cycle(r));
-    const int64_t after = k + 1 - h.prm.burn_in;
-    if (after > 0 && after % h.prm.stride == 0) {
-      const int64_t idx = after / h.prm.stride - 1;
-      SMG_TRY(export_level0(h, (char*)out + (size_t)idx * field * out_elem,
-                            out_dtype == SMG_OUT_F32, v0.x, s));
-    }
+  return sample_impl(hh, Batch{}, nullptr, nullptr, n, seed, first_cycle, state, out, out_dtype,
+                     nullptr, 0, nullptr, nullptr, stream);
+}
+
+int smg_sample_stats(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
+                     void* state, void* out, int32_t out_dtype, const int32_t* modes,
+                     int32_t n_modes, void* obs, void* moments, void* stream) {
+  return sample_impl(hh, Batch{}, nullptr, nullptr, n, seed, first_cycle, state, out, out_dtype,
+                     modes, n_modes, obs, moments, stream);
+}
+
+int smg_sample_batch(smg_hierarchy* hh, int32_t nchains, int32_t comps_per_chain,
+                     const uint64_t* seeds, const uint64_t* first_cycles, int64_t n, void* state,
+                     void* out, int32_t out_dtype, const int32_t* modes, int32_t n_modes,
+                     void* obs, void* moments, void* stream) {
+  if (nchains < 1) {
+    set_error("nchains must be >= 1");
+    return SMG_EINVAL;
   }
-  SMG_TRY(export_level0(h, state, 0, v0.x, s));
+  Batch bt;
+  bt.nchains = nchains;
+  bt.cpc = comps_per_chain;
+  return sample_impl(hh, bt, seeds, first_cycles, n, 0, 0, state, out, out_dtype, modes, n_modes,
+                     obs, moments, stream);
+}
+
+int smg_solve_batch(smg_hierarchy* hh, int32_t nchains, int32_t comps_per_chain, const void* f,
+                    void* u, double rtol, int32_t max_cycles, void* stream,
+                    smg_solve_info* infos) {
+  if (nchains < 1) {
+    set_error("nchains must be >= 1");
+    return SMG_EINVAL;
+  }
+  Batch bt;
+  bt.nchains = nchains;
+  bt.cpc = comps_per_chain;
+  return solve_impl(hh, bt, f, u, rtol, max_cycles, stream, infos);
+}
+
+int smg_lowest_modes(int32_t nx, int32_t ny, int32_t nz, int32_t k, int32_t* modes) {
+  if (nx < 2 || ny < 2 || nz < 1 || (nx & 1) || (ny & 1) || k < 0 || k > kMaxModes ||
+      (int64_t)k > (int64_t)nx * ny * nz || (k > 0 && !modes)) {
+    set_error("invalid grid or k");
+    return SMG_EINVAL;
+  }
+  struct Cand {
+    int64_t key;
+    int m, b, a;
+  };
+  std::vector<Cand> c;
+  const int am = std::min(nx, 2 * k + 2), bm = std::min(ny, 2 * k + 2), mm = std::min(nz, k + 1);
+  for (int m = 1; m <= mm; ++m)
+    for (int b = 0; b < bm; ++b)
+      for (int a = 0; a < am; ++a) {
+        const double jx = periodic_wavenumber(nx, a), jy = periodic_wavenumber(ny, b);
+        const double sx = std::sin(M_PI * jx / nx), sy = std::sin(M_PI * jy / ny);
+        const double sz = std::sin(M_PI * m / (2.0 * nz));
+        const double lam = 4.0 * sx * sx + 4.0 * sy * sy + 4.0 * sz * sz;
+        c.push_back({(int64_t)std::llround(lam * 1073741824.0), m, b, a});
+      }
+  std::sort(c.begin(), c.end(), [](const Cand& p, const Cand& q) {
+    if (p.key != q.key) return p.key < q.key;
+    if (p.m != q.m) return p.m < q.m;
+    if (p.b != q.b) return p.b < q.b;
+    return p.a < q.a;
+  });
+  for (int q = 0; q < k; ++q) {
+    modes[3 * q] = c[q].a;
+    modes[3 * q + 1] = c[q].b;
+    modes[3 * q + 2] = c[q].m;
+  }
   return SMG_OK;
 }
 
 int smg_solve(smg_hierarchy* hh, const void* f, void* u, double rtol, int32_t max_cycles,
               void* stream, smg_solve_info* info) {
-  SMG_TRY(check_bound(hh));
-  SMG_TRY(check_ptr(f, "f"));
-  SMG_TRY(check_ptr(u, "u"));
-  if (!(rtol >= 0.0) || max_cycles < 0) {
-    set_error("rtol must be >= 0 and max_cycles >= 0");
-    return SMG_EINVAL;
-  }
-  Hierarchy& h = hh->h;
-  hipStream_t s = (hipStream_t)stream;
-  Level& v0 = h.lv[0];
-  const int nc = h.desc.ncomp;
-  const int64_t field = (int64_t)nc * v0.n;
-  const bool f32 = refined(h);
-  std::vector<double> fn(nc), rn(nc), rprev(nc, 0.0);
-  double last_ratio = 0.0;
-  SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)f, v0.n, nc, s));
-  SMG_HIP(hipMemcpyAsync(fn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
-  SMG_HIP(hipStreamSynchronize(s));
-  for (int c = 0; c < nc; ++c)
-    if (!std::isfinite(fn[c])) {
-      set_error("f is not finite");
-      return SMG_ENONFINITE;
-    }
-  SMG_TRY(import_level0(h, v0.b, (const double*)f, s));
-  SMG_HIP(launch_zero<double>(v0.x, field, s));
-  Run r{&h, s, false, true, 0, 0};
-  double relres = 0.0;
-  bool all_zero = true;
-  for (int c = 0; c < nc; ++c) all_zero = all_zero && fn[c] == 0.0;
-  int cycles = 0;
-  // squared residual norms of the current iterate -> relres (max over components) and the
-  // contraction of the last cycle; refined mode leaves the FP32 residual in lv[0].bf
-  auto residual_norms = [&]() -> int {
-    if (f32) {
-      SMG_HIP(launch_refine_residual(v0.bf, v0.x, v0.b, v0.nx, v0.ny, v0.nz, nc, h.desc.h,
-                                     h.part_d, h.norm_d, s));
-    } else if (v0.kind == KIND_POINT) {
-      SMG_HIP(launch_residual0<double>(v0.r, v0.x, v0.x + half_field(h), v0.b,
-                                       v0.b + half_field(h), v0.nx, v0.ny, v0.nz, nc, h.desc.h,
-                                       s));
-      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, v0.r, v0.n, nc, s));
-    } else {
-      // a level 0 that is drawn exactly has no residual buffer: u serves as scratch
-      SMG_HIP(launch_residual7_nat((double*)u, v0.x, v0.b, v0.nx, v0.ny, v0.nz, nc, h.desc.h, s));
-      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)u, v0.n, nc, s));
-    }
-    SMG_HIP(hipMemcpyAsync(rn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
-    SMG_HIP(hipStreamSynchronize(s));
-    relres = 0.0;
-    last_ratio = 0.0;
-    for (int c = 0; c < nc; ++c) {
-      if (!std::isfinite(rn[c])) {
-        set_error("residual is not finite");
-        return SMG_ENONFINITE;
-      }
-      double rr = fn[c] > 0.0 ? std::sqrt(rn[c] / fn[c]) : (rn[c] > 0.0 ? INFINITY : 0.0);
-      relres = rr > relres ? rr : relres;
-      if (cycles >= 2 && rprev[c] > 0.0) {
-        double q = std::sqrt(rn[c] / rprev[c]);
-        last_ratio = q > last_ratio ? q : last_ratio;
-      }
-      rprev[c] = rn[c];
-    }
-    return SMG_OK;
-  };
-  if (!all_zero) {
-    relres = 1.0;
-    bool ready = false;
-    if (f32 && max_cycles > 0) {
-      SMG_TRY(residual_norms());  // residual of u = 0, i.e. f, rounded to FP32
-      ready = true;
-    }
-    while (cycles < max_cycles) {
-      SMG_TRY(full_cycle(r, ready));
-      ++cycles;
-      SMG_TRY(residual_norms());
-      if (relres <= rtol) break;
-    }
-  }
-  SMG_TRY(export_level0(h, u, 0, v0.x, s));
-  SMG_HIP(hipStreamSynchronize(s));
-  if (info) {
-    info->cycles = cycles;
-    info->relres = relres;
-    info->last_ratio = last_ratio;
-  }
-  if (!all_zero && relres > rtol) {
-    set_error("solve did not converge: relres " + std::to_string(relres));
-    return SMG_ENOTCONV;
-  }
-  return SMG_OK;
+  return solve_impl(hh, Batch{}, f, u, rtol, max_cycles, stream, info);
 }
 
 void smg_destroy_hierarchy(smg_hierarchy* hh) {
@@ -661,7 +994,7 @@ int smg_debug_smooth(smg_hierarchy* hh, int32_t level, int32_t colour, void* x, 
     return SMG_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
-  Run r{&h, s, with_noise != 0, b != nullptr, seed, cycle};
+  Run r = make_run(h, s, with_noise != 0, b != nullptr, seed, cycle);
   if (v.kind == KIND_POINT) {
     NoiseArgs na = make_noise(r, level, slot, colour, KIND_SMOOTH_NOISE);
     SMG_TRY(import_level0(h, v.x, (const double*)x, s));
@@ -669,15 +1002,15 @@ int smg_debug_smooth(smg_hierarchy* hh, int32_t level, int32_t colour, void* x, 
     double* xr = v.x;
     double* xb = v.x + half_field(h);
     const double* bc = b ? (colour ? v.b + half_field(h) : v.b) : nullptr;
-    SMG_TRY(timed_rb_pass<double>(r, colour ? xb : xr, colour ? xr : xb, bc, colour, na));
+    SMG_TRY(rb_pass<double>(r, colour ? xb : xr, colour ? xr : xb, bc, colour, na));
     SMG_TRY(export_level0(h, x, 0, v.x, s));
   } else {
     if (r.noise) SMG_TRY(gen_level_noise<double>(r, level, slot));
-    SMG_HIP(launch_block_pass<double>((double*)x, (const double*)b, (const double*)v.g2d_d,
+    SMG_HIP(launch_block_pass<double>((double*)x, (const double*)b, (const double*)v.s1d_d,
                                       (const double*)v.zt_d, (const double*)v.bfac_d, v.nx, v.ny,
                                       v.nz, h.desc.ncomp, colour,
                                       r.noise ? (const double*)v.noise_d : nullptr,
-                                      std::sqrt(h.desc.kT), s));
+                                      std::sqrt(h.desc.kT), h.block_tile, s));
   }
   return SMG_OK;
 }
@@ -708,7 +1041,7 @@ int smg_debug_restrict_residual(smg_hierarchy* hh, int32_t level, const void* x,
                                      h.desc.h, s));
   } else {
     SMG_HIP(launch_residual_gal<double>(v.r, (const double*)x, (const double*)b,
-                                        (const double*)v.g2d_d, (const double*)v.zt_d, v.nx,
+                                        (const double*)v.s1d_d, (const double*)v.zt_d, v.nx,
                                         v.ny, v.nz, nc, s));
   }
   SMG_HIP(launch_restrict<double>((double*)b_coarse, nullptr, v.r, v.nx, v.ny, v.nz, nc, s));
@@ -752,7 +1085,7 @@ int smg_debug_coarsest(smg_hierarchy* hh, void* x, const void* b, uint64_t seed,
     return SMG_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
-  Run r{&h, s, with_noise != 0, false, seed, cycle};
+  Run r = make_run(h, s, with_noise != 0, false, seed, cycle);
   const int l = (int)h.lv.size() - 1;
   NoiseArgs na = make_noise(r, l, 0, 0, KIND_COARSEST_NOISE);
   SMG_HIP(launch_coarsest<double>((double*)x, (const double*)b, h.ainv_d, h.w_d, h.nc,
@@ -794,6 +1127,10 @@ int smg_set_option(smg_hierarchy* hh, int32_t option, int64_t value) {
     hh->h.use_bottom = value != 0;
     return SMG_OK;
   }
+  if (option == SMG_OPT_BLOCK_TILE && value >= SMG_TILE_AUTO && value <= SMG_TILE_8X4) {
+    hh->h.block_tile = (int)value;
+    return SMG_OK;
+  }
   if (option == SMG_OPT_TIMED_KERNEL && value >= SMG_TIMED_FINE_PASS && value <= SMG_TIMED_BOTTOM) {
     hh->h.timed_kernel = (int)value;
     return SMG_OK;
@@ -810,6 +1147,7 @@ int smg_kernel_timing(smg_hierarchy* hh, int32_t enable) {
   Hierarchy& h = hh->h;
   h.timing = enable != 0;
   h.ev_used = 0;
+  h.ev_launches.clear();
   h.tcount = 0;
   h.tms = 0.0;
   return SMG_OK;
@@ -825,9 +1163,10 @@ int smg_kernel_timing_read(smg_hierarchy* hh, int64_t* count, double* total_ms) 
     float ms = 0.0f;
     SMG_HIP(hipEventElapsedTime(&ms, h.ev_pool[i], h.ev_pool[i + 1]));
     h.tms += ms;
-    h.tcount += 1;
+    h.tcount += i / 2 < h.ev_launches.size() ? h.ev_launches[i / 2] : 1;
   }
   h.ev_used = 0;
+  h.ev_launches.clear();
   *count = h.tcount;
   *total_ms = h.tms;
   return SMG_OK;

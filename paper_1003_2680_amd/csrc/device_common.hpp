@@ -26,17 +26,48 @@ __device__ __forceinline__ uint32_t udiv(uint32_t a, uint32_t d, int lg2) {
 template <typename T = double>
 __device__ __forceinline__ T pw(int i) { return (i == 1 || i == 2) ? T(0.75) : T(0.25); }
 
-// (A x) at cell (cx, cy, cz) of a Galerkin level, from the factored row coefficients
-//   coef[dz][dy][dx] = zt[cz][dz] g2d[dy][dx] + zt[cz][5+dz] g2d[25 + dy*5 + dx].
+// (A x) at cell (cx, cy, cz) of a Galerkin level.  The Galerkin operator of the wall-bounded
+// Laplacian is a Kronecker sum, A = a_z (x) m_y (x) m_x + m_z (x) (a_y (x) m_x + m_y (x) a_x),
+// with 5-point periodic 1D stencils s1d = (m_x, a_x, m_y, a_y) (offsets -2..2, uniform over
+// the level) and the wall-axis rows zt[cz] = (a_z[cz][cz+dz], m_z[cz][cz+dz]).  Each row of a
+// plane is reduced with m_x and a_x, then the plane with m_y and a_y: 65 FMAs per plane.
 // Rows beyond a wall have zero z-factors; their loads are clamped into the grid so the
 // accumulation is branch-free.
 // Fields are addressed as X[z*sz + y*sy + x]; global fields use sy = nx, sz = nx*ny, LDS copies
 // use padded strides (sy = 2 mod 4, sz = 1 mod 4 doubles) so that the 64 lanes of a wave --
 // 8 blocks x 8 cells -- spread evenly over the LDS banks.
 template <typename T>
-__device__ __forceinline__ T gal_apply(const T* __restrict__ X, int sy, int sz,
-                                       const T* __restrict__ g2d, const T* __restrict__ zt,
-                                       int nx, int ny, int nz, int cx, int cy, int cz) {
+__device__ __forceinline__ T gal_plane(const T* __restrict__ P, int sy, const int* xs,
+                                       const int* ys, const T* s1d, T& p1) {
+  T q0[5], q1[5];
+#pragma unroll
+  for (int dy = 0; dy < 5; ++dy) {
+    const T* row = P + (size_t)ys[dy] * sy;
+    T sm = 0, sa = 0;
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx) {
+      const T v = row[xs[dx]];
+      sm = fma(s1d[dx], v, sm);
+      sa = fma(s1d[5 + dx], v, sa);
+    }
+    q0[dy] = sm;
+    q1[dy] = sa;
+  }
+  T p0 = 0, pa = 0, pb = 0;
+#pragma unroll
+  for (int dy = 0; dy < 5; ++dy) {
+    p0 = fma(s1d[10 + dy], q0[dy], p0);
+    pa = fma(s1d[15 + dy], q0[dy], pa);
+    pb = fma(s1d[10 + dy], q1[dy], pb);
+  }
+  p1 = pa + pb;
+  return p0;
+}
+
+template <typename T>
+__device__ __forceinline__ T gal_apply(const T* __restrict__ X, int sy, int sz, const T* s1d,
+                                       const T* __restrict__ zt, int nx, int ny, int nz, int cx,
+                                       int cy, int cz) {
   const T* zr = zt + cz * 10;
   int xs[5], ys[5];
 #pragma unroll
@@ -44,31 +75,15 @@ __device__ __forceinline__ T gal_apply(const T* __restrict__ X, int sy, int sz,
     xs[d] = wrapm(cx + d - 2, nx);
     ys[d] = wrapm(cy + d - 2, ny);
   }
-  // independent partial sums per row keep the dependent FMA chains short (a lone wave cannot
-  // hide FMA latency behind other waves on the small levels)
   T acc0 = 0, acc1 = 0;
 #pragma unroll 1
   for (int dz = 0; dz < 5; ++dz) {
     int zz = cz + dz - 2;
     zz = zz < 0 ? 0 : (zz >= nz ? nz - 1 : zz);
-    T p1[5], p2[5];
-#pragma unroll
-    for (int dy = 0; dy < 5; ++dy) {
-      const T* row = X + (size_t)zz * sz + (size_t)ys[dy] * sy;
-      T a1 = 0, a2 = 0;
-#pragma unroll
-      for (int dx = 0; dx < 5; ++dx) {
-        const T v = row[xs[dx]];
-        a1 = fma(g2d[dy * 5 + dx], v, a1);
-        a2 = fma(g2d[25 + dy * 5 + dx], v, a2);
-      }
-      p1[dy] = a1;
-      p2[dy] = a2;
-    }
-    const T s1 = (p1[0] + p1[1]) + (p1[2] + p1[3]) + p1[4];
-    const T s2 = (p2[0] + p2[1]) + (p2[2] + p2[3]) + p2[4];
-    acc0 = fma(zr[dz], s1, acc0);
-    acc1 = fma(zr[5 + dz], s2, acc1);
+    T p1;
+    const T p0 = gal_plane<T>(X + (size_t)zz * sz, sy, xs, ys, s1d, p1);
+    acc0 = fma(zr[dz], p0, acc0);
+    acc1 = fma(zr[5 + dz], p1, acc1);
   }
   return acc0 + acc1;
 }
@@ -82,7 +97,7 @@ __device__ __forceinline__ T gal_apply(const T* __restrict__ X, int sy, int sz,
 // level: one normal per cell and sweep, drawn from the stream of the cell's block colour).
 template <typename T, bool NOISE>
 __device__ __forceinline__ T block_lane(const T* __restrict__ X, int sy, int sz,
-                                        const T* __restrict__ Bv, const T* __restrict__ g2d,
+                                        const T* __restrict__ Bv, const T* s1d,
                                         const T* __restrict__ zt, const T* __restrict__ bfac,
                                         int nx, int ny, int nz, int bx, int by, int bz, int k,
                                         bool active, const T* __restrict__ Z, T sqkT,
@@ -95,7 +110,7 @@ __device__ __forceinline__ T block_lane(const T* __restrict__ X, int sy, int sz,
   T ax = 0, xk = 0, bk = 0, nrm = 0;
   if (active) {
     if (NOISE) nrm = Z[((uint32_t)cz * ny + cy) * nx + cx];
-    ax = gal_apply<T>(X, sy, sz, g2d, zt, nx, ny, nz, cx, cy, cz);
+    ax = gal_apply<T>(X, sy, sz, s1d, zt, nx, ny, nz, cx, cy, cz);
     xk = X[cell];
     bk = Bv[cell];
   }

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/smg.h"
 #include "philox.hpp"
 
 namespace smg {
@@ -24,10 +25,12 @@ constexpr int kMaxNoiseLevels = 16;
 struct NoiseLevel {
   int level, nx, ny, nz, nslot, slot0;
   void* out;              // T[nslot][ncomp][N]
-  uint32_t calls_before;  // prefix sum of nslot*ncomp*N/2 over the previous entries
+  uint32_t calls_before;  // prefix sum of nslot*nact*N/2 over the previous entries
 };
 struct NoiseGenArgs {
-  int nlev, ncomp;
+  int nlev;
+  int ncomp;   // component stride of the noise buffers
+  int nact;    // components drawn (the first nact)
   uint32_t total;
   NoiseLevel lv[kMaxNoiseLevels];
 };
@@ -38,7 +41,7 @@ struct BotLevel {
   int nx, ny, nz, kind;
   int sy, sz;          // LDS strides: padded for block levels, natural for the coarsest
   const void* noise;   // T: pregenerated noise of this level [slot][ncomp][N] (block levels)
-  const void* g2d;     // T: [2][25]
+  double s1d[20];      // 1D stencils (m_x, a_x, m_y, a_y), offsets -2..2
   const void* zt;      // T: [nz][10]
   const void* bfac;    // T: [nz/2][3][64]
 };
@@ -81,7 +84,7 @@ template <typename T>
 hipError_t launch_prolong0(T* xr, T* xb, const T* e, int nxf, int nyf, int nzf, int ncomp,
                            hipStream_t s);
 template <typename T>
-hipError_t launch_residual_gal(T* r, const T* x, const T* b, const T* g2d, const T* zt, int nx,
+hipError_t launch_residual_gal(T* r, const T* x, const T* b, const T* s1d, const T* zt, int nx,
                                int ny, int nz, int ncomp, hipStream_t s);
 // b_c = P^T r; also x_c = 0 when xc is not null
 template <typename T>
@@ -89,11 +92,12 @@ hipError_t launch_restrict(T* bc, T* xc, const T* r, int nxf, int nyf, int nzf, 
                            hipStream_t s);
 template <typename T>
 hipError_t launch_prolong(T* x, const T* e, int nxf, int nyf, int nzf, int ncomp, hipStream_t s);
-// z: pregenerated noise of this pass's sweep, [ncomp][N] (null without noise)
+// z: pregenerated noise of this pass's sweep, [ncomp][N] (null without noise); tile: one of
+// the SMG_TILE_* shapes of smg.h (SMG_TILE_AUTO picks by work-group count)
 template <typename T>
-hipError_t launch_block_pass(T* x, const T* b, const T* g2d, const T* zt, const T* bfac, int nx,
+hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
                              int ny, int nz, int ncomp, int colour, const T* z, double sqkT,
-                             hipStream_t s);
+                             int tile, hipStream_t s);
 template <typename T>
 hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStream_t s);
 // `a` points to a BotArgs in device memory
@@ -123,13 +127,45 @@ hipError_t launch_sumsq(double* out, double* part, const double* v, int64_t n, i
 hipError_t launch_sumsq_final_parts(double* out, const double* part, uint32_t nparts, int ncomp,
                                     hipStream_t s);
 
-// FP32-refined bridge on level 0 (split storage):
+// FP32-refined bridge on level 0 (split storage, colour 1 starting ncomp_stride*N/2 after
+// colour 0), over the first ncomp components:
 //   r32 = (float)(b64 - A x64)   (b64 null = 0); with `norm` non-null also
 //   norm[comp] = ||b64 - A x64||_2^2 (fixed order, via `part`: ncomp * 2*ceil(N/512) doubles)
 hipError_t launch_refine_residual(float* r32, const double* x64, const double* b64, int nx,
-                                  int ny, int nz, int ncomp, double h, double* part,
-                                  double* norm, hipStream_t s);
+                                  int ny, int nz, int ncomp, int ncomp_stride, double h,
+                                  double* part, double* norm, hipStream_t s);
 //   x64 += (double)e32 over n elements (both colour arrays)
 hipError_t launch_refine_update(double* x64, const float* e32, int64_t n, hipStream_t s);
+
+// Chain table of batched runs: dst[first .. first+count) = keys; advance adds `cycles` to the
+// first cycle of chains 0..n-1 (so that a replayed launch sequence continues the chains).
+constexpr int kChainsPerLaunch = 32;
+struct ChainKeyBatch {
+  int first, count;
+  ChainKey k[kChainsPerLaunch];
+};
+hipError_t launch_set_chains(ChainKey* dst, const ChainKeyBatch& b, hipStream_t s);
+hipError_t launch_advance_chains(ChainKey* dst, int n, uint64_t cycles, hipStream_t s);
+
+// Statistics of one emitted sample of level 0 (FP64 state), fused with its emission.
+constexpr int kMaxModes = 32;
+struct StatsArgs {
+  const double* xr;   // split layout: colour-0 half [ncomp][N/2]; natural layout: [ncomp][N]
+  const double* xb;   // split layout: colour-1 half; null for the natural layout
+  int nx, ny, nz;
+  int nmodes;         // 0..kMaxModes projections (with obs)
+  int nblk;           // work-groups per component (rows are dealt to their waves)
+  const double* tx;   // [nmodes][nx], [nmodes][ny], [nmodes][nz]: the 1D factors of each mode
+  const double* ty;
+  const double* tz;
+  void* out;          // [ncomp][N] natural emission (float or double) or null
+  int out_f32;
+  double* m1;         // [ncomp][N] running sum of x and of x^2, or null
+  double* m2;
+  double* part;       // [ncomp][nblk][nmodes + 1] partial sums
+};
+// obs (null: moments / emission only): [ncomp][nmodes + 1], the last entry escale * sum of
+// squared face differences (wall faces against the antisymmetric ghost).
+hipError_t launch_stats(const StatsArgs& a, int ncomp, double* obs, double escale, hipStream_t s);
 
 }  // namespace smg

@@ -178,13 +178,12 @@ __global__ __launch_bounds__(TPB) void k_refine_residual(float* __restrict__ r32
                                                           const double* __restrict__ b64, int nx,
                                                           int ny, int nz, uint32_t nsite,
                                                           double inv_h2, double* __restrict__ part,
-                                                          uint32_t nblk) {
+                                                          uint32_t nblk, size_t half) {
   __shared__ double sh[TPB];
   const uint32_t comp = blockIdx.y;
   const int colour = blockIdx.z;
   const uint32_t p = blockIdx.x * TPB + threadIdx.x;
   const int nh = nx >> 1;
-  const size_t half = (size_t)gridDim.y * nsite;
   const double* xr = x64;
   const double* xb = x64 + half;
   double rr = 0.0;
@@ -357,14 +356,15 @@ template hipError_t launch_prolong0<float>(float*, float*, const float*, int, in
                                            hipStream_t);
 
 hipError_t launch_refine_residual(float* r32, const double* x64, const double* b64, int nx,
-                                  int ny, int nz, int ncomp, double h, double* part,
-                                  double* norm, hipStream_t s) {
+                                  int ny, int nz, int ncomp, int ncomp_stride, double h,
+                                  double* part, double* norm, hipStream_t s) {
   const uint32_t nsite = (uint32_t)(nx / 2) * ny * nz;
   const uint32_t nblk = blocks_for(nsite);
   dim3 grid(nblk, ncomp, 2);
   const double ih2 = 1.0 / (h * h);
 #define SMG_RR(HB, NM) \
-  k_refine_residual<HB, NM><<<grid, TPB, 0, s>>>(r32, x64, b64, nx, ny, nz, nsite, ih2, part, nblk)
+  k_refine_residual<HB, NM><<<grid, TPB, 0, s>>>(r32, x64, b64, nx, ny, nz, nsite, ih2, part, nblk, \
+                                                 (size_t)ncomp_stride * nsite)
   if (b64) { if (norm) SMG_RR(true, true); else SMG_RR(true, false); }
   else { if (norm) SMG_RR(false, true); else SMG_RR(false, false); }
 #undef SMG_RR

@@ -30,8 +30,8 @@ __global__ __launch_bounds__(TPB) void k_level_noise(NoiseGenArgs a, NoiseArgs n
   uint32_t u = t - L.calls_before;
   const uint32_t q = u % half;  // call within (slot, comp)
   u /= half;
-  const uint32_t comp = u % (uint32_t)a.ncomp;
-  const uint32_t s = u / (uint32_t)a.ncomp;
+  const uint32_t comp = u % (uint32_t)a.nact;
+  const uint32_t s = u / (uint32_t)a.nact;
   const uint32_t bid = q >> 2;
   const int m = q & 3;
   const int nbx = L.nx >> 1, nby = L.ny >> 1;
@@ -56,20 +56,22 @@ __global__ __launch_bounds__(TPB) void k_level_noise(NoiseGenArgs a, NoiseArgs n
 // with coalesced row loads; the 125-point rows are then gathered from LDS.  The box never
 // contains another work-group's blocks of this colour (blocks of one colour are >= 3 cells
 // apart), so staging and the writes of other work-groups do not overlap.
-constexpr int TILE_I = 4, TILE_J = 4;
-constexpr int TILE_W = 4 * TILE_I + 2, TILE_H = 4 * TILE_J + 2, TILE_D = 6;
-constexpr int TILE_TPB = TILE_I * TILE_J * 8;
+// Tile shapes (blocks per work-group along x, y): 4x4 (128 threads), 4x2 (one wavefront) and
+// 8x4 (256 threads); the shape changes only the work distribution, never a result.
+constexpr int TILE_D = 6;
 
-template <typename T, bool NOISE>
-__global__ __launch_bounds__(TILE_TPB) void k_block_tile(T* __restrict__ xg,
+template <typename T, bool NOISE, int TILE_I, int TILE_J>
+__global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restrict__ xg,
                                                           const T* __restrict__ bg,
-                                                          const T* __restrict__ g2d,
+                                                          const T* __restrict__ s1d,
                                                           const T* __restrict__ zt,
                                                           const T* __restrict__ bfac, int nx,
                                                           int ny, int nz, uint32_t N, int colour,
                                                           int nbx2, int nby2, int ntx,
                                                           const T* __restrict__ zn, T sqkT) {
-  constexpr int TP = TILE_H * TILE_W + 1;  // plane stride: 1 mod 4 elements (row stride 18)
+  constexpr int TILE_W = 4 * TILE_I + 2, TILE_H = 4 * TILE_J + 2;
+  constexpr int TILE_TPB = TILE_I * TILE_J * 8;
+  constexpr int TP = TILE_H * TILE_W + 1;  // plane stride: 1 mod 4 elements
   __shared__ T Tl[TILE_D * TP];
   const uint32_t comp = blockIdx.z;
   const int l = blockIdx.y;
@@ -104,25 +106,15 @@ __global__ __launch_bounds__(TILE_TPB) void k_block_tile(T* __restrict__ xg,
   if (active) {
     if (NOISE) nrm = zn[(size_t)comp * N + cell];
     const T* zr = zt + gcz * 10;
+    const int xs[5] = {tx - 2, tx - 1, tx, tx + 1, tx + 2};
+    const int ys[5] = {ty - 2, ty - 1, ty, ty + 1, ty + 2};
     T ax0 = 0, ax1 = 0;
 #pragma unroll
     for (int dz = 0; dz < 5; ++dz) {
-      T p1[5], p2[5];
-#pragma unroll
-      for (int dy = 0; dy < 5; ++dy) {
-        const T* row = Tl + (tz + dz - 2) * TP + (ty + dy - 2) * TILE_W + tx - 2;
-        T a1 = 0, a2 = 0;
-#pragma unroll
-        for (int dx = 0; dx < 5; ++dx) {
-          const T v = row[dx];
-          a1 = fma(g2d[dy * 5 + dx], v, a1);
-          a2 = fma(g2d[25 + dy * 5 + dx], v, a2);
-        }
-        p1[dy] = a1;
-        p2[dy] = a2;
-      }
-      ax0 = fma(zr[dz], (p1[0] + p1[1]) + (p1[2] + p1[3]) + p1[4], ax0);
-      ax1 = fma(zr[5 + dz], (p2[0] + p2[1]) + (p2[2] + p2[3]) + p2[4], ax1);
+      T p1;
+      const T p0 = gal_plane<T>(Tl + (tz + dz - 2) * TP, TILE_W, xs, ys, s1d, p1);
+      ax0 = fma(zr[dz], p0, ax0);
+      ax1 = fma(zr[5 + dz], p1, ax1);
     }
     ax = ax0 + ax1;
     xk = Tl[tz * TP + ty * TILE_W + tx];
@@ -152,7 +144,7 @@ __global__ __launch_bounds__(TILE_TPB) void k_block_tile(T* __restrict__ xg,
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_residual_gal(T* __restrict__ r, const T* __restrict__ xg,
                                                        const T* __restrict__ bg,
-                                                       const T* __restrict__ g2d,
+                                                       const T* __restrict__ s1d,
                                                        const T* __restrict__ zt, int nx, int ny,
                                                        int nz, uint32_t N) {
   const uint32_t comp = blockIdx.y;
@@ -162,7 +154,7 @@ __global__ __launch_bounds__(TPB) void k_residual_gal(T* __restrict__ r, const T
   const uint32_t row = i / nx;
   const int y = row % ny;
   const int z = row / ny;
-  const T ax = gal_apply<T>(xg + (size_t)comp * N, nx, nx * ny, g2d, zt, nx, ny, nz, x, y, z);
+  const T ax = gal_apply<T>(xg + (size_t)comp * N, nx, nx * ny, s1d, zt, nx, ny, nz, x, y, z);
   r[(size_t)comp * N + i] = bg[(size_t)comp * N + i] - ax;
 }
 
@@ -242,12 +234,16 @@ constexpr int BOT_TPB = 512;
 template <typename T, bool NOISE>
 __device__ __forceinline__ void bot_block_pass(T* X, const T* Bv, const BotLevel& L, const T* tab,
                                                int colour, const T* Z, T sqkT) {
-  const T* g2d = tab;
-  const T* zt = tab + 50;
-  const T* bfac = tab + 50 + L.nz * 10;
+  // the 1D stencils are the same for every lane: scalar loads from the level descriptor
+  T s1d[20];
+#pragma unroll
+  for (int q = 0; q < 20; ++q) s1d[q] = (T)L.s1d[q];
+  const T* zt = tab;
+  const T* bfac = tab + L.nz * 10;
   const int nbx2 = L.nx / 4, nby2 = L.ny / 4;
   const int nbzc = (L.nz / 2 + 1 - (colour >> 2)) / 2;
   const int total = nbx2 * nby2 * nbzc * 8;
+#pragma unroll 1
   for (int base = 0; base < total; base += BOT_TPB) {
     const int t = base + (int)threadIdx.x;
     const bool active = t < total;
@@ -258,7 +254,7 @@ __device__ __forceinline__ void bot_block_pass(T* X, const T* Bv, const BotLevel
     const int j = rest % nby2;
     const int l = rest / nby2;
     uint32_t cell;
-    const T v = block_lane<T, NOISE>(X, L.sy, L.sz, Bv, g2d, zt, bfac, L.nx, L.ny, L.nz,
+    const T v = block_lane<T, NOISE>(X, L.sy, L.sz, Bv, s1d, zt, bfac, L.nx, L.ny, L.nz,
                                      2 * i + (colour & 1), 2 * j + ((colour >> 1) & 1),
                                      2 * l + (colour >> 2), k, active, Z, sqkT, cell);
     if (active) X[cell] = v;
@@ -271,6 +267,7 @@ __device__ __forceinline__ void bot_sweep(T* X, const T* Bv, const BotLevel& L, 
                                           int slot, bool post, int ncomp, uint32_t comp, T sqkT) {
   const int n = L.nx * L.ny * L.nz;
   const T* Z = NOISE ? (const T*)L.noise + ((size_t)slot * ncomp + comp) * n : nullptr;
+#pragma unroll 1
   for (int t = 0; t < 8; ++t) {
     const int colour = post ? 7 - t : t;
     bot_block_pass<T, NOISE>(X, Bv, L, tab, colour, Z, sqkT);
@@ -298,17 +295,15 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
   __syncthreads();
   for (int q = tid; q < n0; q += BOT_TPB)
     sm[a.lds_off[0] + f0 + bot_pos(L0, q)] = ((const T*)a.b_in)[(size_t)comp * n0 + q];
-  // operator tables of the block levels: [g2d 50][zt nz*10][bfac nz/2*192] at tab_off[i]
+  // operator tables of the block levels: [zt nz*10][bfac nz/2*192] at tab_off[i]
   for (int i = 0; i < a.nlev; ++i) {
     if (a.lv[i].kind != KIND_BLOCK) continue;
     const int nz = a.lv[i].nz;
     T* t = sm + a.tab_off[i];
-    const T* g = (const T*)a.lv[i].g2d;
     const T* zt = (const T*)a.lv[i].zt;
     const T* bf = (const T*)a.lv[i].bfac;
-    for (int q = tid; q < 50; q += BOT_TPB) t[q] = g[q];
-    for (int q = tid; q < nz * 10; q += BOT_TPB) t[50 + q] = zt[q];
-    for (int q = tid; q < (nz / 2) * 192; q += BOT_TPB) t[50 + nz * 10 + q] = bf[q];
+    for (int q = tid; q < nz * 10; q += BOT_TPB) t[q] = zt[q];
+    for (int q = tid; q < (nz / 2) * 192; q += BOT_TPB) t[nz * 10 + q] = bf[q];
   }
   __syncthreads();
   int last = a.nlev - 1;
@@ -359,10 +354,15 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
       break;
     }
     // b_{i+1} = P^T (b_i - A_i x_i), x_{i+1} = 0
-    for (int q = tid; q < n; q += BOT_TPB) {
-      const int x = q % L.nx, y = (q / L.nx) % L.ny, z = q / (L.nx * L.ny);
-      const int p = z * L.sz + y * L.sy + x;
-      ri[p] = bi[p] - gal_apply<T>(xi, L.sy, L.sz, tab, tab + 50, L.nx, L.ny, L.nz, x, y, z);
+    {
+      T s1d[20];
+#pragma unroll
+      for (int q = 0; q < 20; ++q) s1d[q] = (T)L.s1d[q];
+      for (int q = tid; q < n; q += BOT_TPB) {
+        const int x = q % L.nx, y = (q / L.nx) % L.ny, z = q / (L.nx * L.ny);
+        const int p = z * L.sz + y * L.sy + x;
+        ri[p] = bi[p] - gal_apply<T>(xi, L.sy, L.sz, s1d, tab, L.nx, L.ny, L.nz, x, y, z);
+      }
     }
     __syncthreads();
     const BotLevel& C = a.lv[i + 1];
@@ -397,28 +397,49 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
 
 }  // namespace
 
+template <typename T, int TI, int TJ>
+void launch_block_tile(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx, int ny,
+                       int nz, int ncomp, int colour, const T* zn, double sqkT, int nbx2,
+                       int nby2, int nbzc, hipStream_t s) {
+  const uint32_t N = (uint32_t)nx * ny * nz;
+  const int ntx = (nbx2 + TI - 1) / TI, nty = (nby2 + TJ - 1) / TJ;
+  dim3 grid(ntx * nty, nbzc, ncomp);
+  if (zn)
+    k_block_tile<T, true, TI, TJ><<<grid, TI * TJ * 8, 0, s>>>(
+        x, b, s1d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, (T)sqkT);
+  else
+    k_block_tile<T, false, TI, TJ><<<grid, TI * TJ * 8, 0, s>>>(
+        x, b, s1d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, (T)sqkT);
+}
+
 template <typename T>
-hipError_t launch_block_pass(T* x, const T* b, const T* g2d, const T* zt, const T* bfac, int nx,
+hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
                              int ny, int nz, int ncomp, int colour, const T* zn, double sqkT,
-                             hipStream_t s) {
+                             int tile, hipStream_t s) {
   const int nbx2 = nx / 4, nby2 = ny / 4;
   const int nbz = nz / 2;
   const int nbzc = (nbz + 1 - (colour >> 2)) / 2;
   if (nbx2 * nby2 * nbzc == 0) return hipSuccess;
-  const uint32_t N = (uint32_t)nx * ny * nz;
-  const int ntx = (nbx2 + TILE_I - 1) / TILE_I, nty = (nby2 + TILE_J - 1) / TILE_J;
-  dim3 grid(ntx * nty, nbzc, ncomp);
-  if (zn) k_block_tile<T, true><<<grid, TILE_TPB, 0, s>>>(x, b, g2d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, (T)sqkT);
-  else k_block_tile<T, false><<<grid, TILE_TPB, 0, s>>>(x, b, g2d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, (T)sqkT);
+  if (tile == SMG_TILE_AUTO) {
+    // 4x4 tiles unless that leaves fewer than two work-groups per compute unit
+    const int64_t wg = (int64_t)((nbx2 + 3) / 4) * ((nby2 + 3) / 4) * nbzc * ncomp;
+    tile = wg >= 512 ? SMG_TILE_4X4 : SMG_TILE_4X2;
+  }
+  if (tile == SMG_TILE_4X2)
+    launch_block_tile<T, 4, 2>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, sqkT, nbx2, nby2, nbzc, s);
+  else if (tile == SMG_TILE_8X4)
+    launch_block_tile<T, 8, 4>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, sqkT, nbx2, nby2, nbzc, s);
+  else
+    launch_block_tile<T, 4, 4>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, sqkT, nbx2, nby2, nbzc, s);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_residual_gal(T* r, const T* x, const T* b, const T* g2d, const T* zt, int nx,
+hipError_t launch_residual_gal(T* r, const T* x, const T* b, const T* s1d, const T* zt, int nx,
                                int ny, int nz, int ncomp, hipStream_t s) {
   const uint32_t N = (uint32_t)nx * ny * nz;
   dim3 grid(blocks_for(N), ncomp);
-  k_residual_gal<T><<<grid, TPB, 0, s>>>(r, x, b, g2d, zt, nx, ny, nz, N);
+  k_residual_gal<T><<<grid, TPB, 0, s>>>(r, x, b, s1d, zt, nx, ny, nz, N);
   return hipGetLastError();
 }
 
@@ -477,7 +498,7 @@ hipError_t launch_bottom(const BotArgs* a, int ncomp, size_t lds, bool noise, co
 
 #define SMG_INST(T)                                                                            \
   template hipError_t launch_block_pass<T>(T*, const T*, const T*, const T*, const T*, int, int, \
-                                           int, int, int, const T*, double, hipStream_t);       \
+                                           int, int, int, const T*, double, int, hipStream_t);  \
   template hipError_t launch_residual_gal<T>(T*, const T*, const T*, const T*, const T*, int,    \
                                              int, int, int, hipStream_t);                        \
   template hipError_t launch_restrict<T>(T*, T*, const T*, int, int, int, int, hipStream_t);    \

@@ -97,6 +97,22 @@ inline unsigned grid_stride_blocks(int64_t n) {
   return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
 }
 
+__global__ void k_set_chains(ChainKey* __restrict__ dst, ChainKeyBatch b) {
+  const int t = threadIdx.x;
+  if (t < b.count) dst[b.first + t] = b.k[t];
+}
+
+__global__ __launch_bounds__(TPB) void k_advance_chains(ChainKey* __restrict__ dst, int n,
+                                                         uint64_t cycles) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= n) return;
+  ChainKey k = dst[t];
+  const uint64_t c = ((((uint64_t)k.c1) << 32) | k.c0) + cycles;
+  k.c0 = (uint32_t)c;
+  k.c1 = (uint32_t)(c >> 32);
+  dst[t] = k;
+}
+
 }  // namespace
 
 hipError_t launch_residual7_nat(double* r, const double* x, const double* b, int nx, int ny,
@@ -142,6 +158,18 @@ hipError_t launch_sumsq(double* out, double* part, const double* v, int64_t n, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_sumsq_final<<<ncomp, TPB, 0, s>>>(out, part, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_chains(ChainKey* dst, const ChainKeyBatch& b, hipStream_t s) {
+  if (b.count <= 0) return hipSuccess;
+  k_set_chains<<<1, kChainsPerLaunch, 0, s>>>(dst, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_chains(ChainKey* dst, int n, uint64_t cycles, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_advance_chains<<<(n + TPB - 1) / TPB, TPB, 0, s>>>(dst, n, cycles);
   return hipGetLastError();
 }
 

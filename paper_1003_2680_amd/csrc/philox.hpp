@@ -16,12 +16,43 @@
 
 namespace smg {
 
-struct NoiseArgs {
+// Batched chains: component c belongs to chain c / comps_per_chain, which has its own seed and
+// first cycle; its noise is that of component c % comps_per_chain of a one-chain run.
+struct ChainKey {
   uint32_t k0, k1;   // seed low / high
-  uint32_t sid;      // level | slot<<4 | colour<<12 | kind<<24 (component added per thread)
-  uint32_t c2, c3;   // cycle low / high
-  double sqkT;       // sqrt(kT)
+  uint32_t c0, c1;   // first cycle low / high
 };
+
+struct NoiseArgs {
+  uint32_t k0, k1;   // seed low / high (one chain)
+  uint32_t sid;      // level | slot<<4 | colour<<12 | kind<<24 (component added per thread)
+  uint32_t c2, c3;   // cycle low / high; with `chains`: cycles since each chain's first cycle
+  double sqkT;       // sqrt(kT)
+  const ChainKey* chains;    // null: one chain keyed by (k0, k1)
+  uint32_t comps_per_chain;
+};
+
+// Philox key, counter words 1..3 for component `comp`.
+__device__ __forceinline__ void noise_key(const NoiseArgs& na, uint32_t comp, uint32_t& k0,
+                                          uint32_t& k1, uint32_t& w1, uint32_t& w2,
+                                          uint32_t& w3) {
+  if (na.chains) {
+    const uint32_t ch = comp / na.comps_per_chain;
+    const ChainKey key = na.chains[ch];
+    const uint64_t cyc = (((uint64_t)key.c1 << 32) | key.c0) + (((uint64_t)na.c3 << 32) | na.c2);
+    k0 = key.k0;
+    k1 = key.k1;
+    w1 = na.sid | ((comp - ch * na.comps_per_chain) << 16);
+    w2 = (uint32_t)cyc;
+    w3 = (uint32_t)(cyc >> 32);
+  } else {
+    k0 = na.k0;
+    k1 = na.k1;
+    w1 = na.sid | (comp << 16);
+    w2 = na.c2;
+    w3 = na.c3;
+  }
+}
 
 __device__ __forceinline__ void philox4x32_10(uint32_t& w0, uint32_t& w1, uint32_t& w2,
                                               uint32_t& w3, uint32_t k0, uint32_t k1) {
@@ -48,8 +79,9 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
 // Two normals of call `call` in stream (sid | comp<<16) at the given cycle.
 __device__ __forceinline__ void normal_pair(const NoiseArgs& na, uint32_t comp, uint32_t call,
                                             double& z0, double& z1) {
-  uint32_t w0 = call, w1 = na.sid | (comp << 16), w2 = na.c2, w3 = na.c3;
-  philox4x32_10(w0, w1, w2, w3, na.k0, na.k1);
+  uint32_t w0 = call, w1, w2, w3, k0, k1;
+  noise_key(na, comp, k0, k1, w1, w2, w3);
+  philox4x32_10(w0, w1, w2, w3, k0, k1);
   double u1 = uniform53(w0, w1);
   double u2 = uniform53(w2, w3);
   double r = sqrt(-2.0 * log(u1));
@@ -66,8 +98,9 @@ __device__ __forceinline__ void normal_pair(const NoiseArgs& na, uint32_t comp, 
 // the FP64 ones only by FP32 rounding.
 __device__ __forceinline__ void normal_pair_f32(const NoiseArgs& na, uint32_t comp, uint32_t call,
                                                 float& z0, float& z1) {
-  uint32_t w0 = call, w1 = na.sid | (comp << 16), w2 = na.c2, w3 = na.c3;
-  philox4x32_10(w0, w1, w2, w3, na.k0, na.k1);
+  uint32_t w0 = call, w1, w2, w3, k0, k1;
+  noise_key(na, comp, k0, k1, w1, w2, w3);
+  philox4x32_10(w0, w1, w2, w3, k0, k1);
   const float u1 = (float)uniform53(w0, w1);
   const float u2 = (float)uniform53(w2, w3);
   const float r = __builtin_sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u1));

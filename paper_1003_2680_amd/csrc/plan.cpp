@@ -232,13 +232,13 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
               v.coef[(size_t)k * STENCIL + (oz + 2) * 25 + (oy + 2) * 5 + (ox + 2)] = c;
             }
         }
-      v.g2d.assign(50, 0.0);
-      for (int oy = -2; oy <= 2; ++oy)
-        for (int ox = -2; ox <= 2; ++ox) {
-          v.g2d[(oy + 2) * 5 + (ox + 2)] = v.my[oy + 2] * v.mx[ox + 2];
-          v.g2d[25 + (oy + 2) * 5 + (ox + 2)] =
-              v.ay[oy + 2] * v.mx[ox + 2] + v.my[oy + 2] * v.ax[ox + 2];
-        }
+      v.s1d.assign(20, 0.0);
+      for (int o = 0; o < 5; ++o) {
+        v.s1d[o] = v.mx[o];
+        v.s1d[5 + o] = v.ax[o];
+        v.s1d[10 + o] = v.my[o];
+        v.s1d[15 + o] = v.ay[o];
+      }
       v.zt.assign((size_t)v.nz * 10, 0.0);
       for (int k = 0; k < v.nz; ++k)
         for (int oz = -2; oz <= 2; ++oz) {
@@ -340,7 +340,7 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
       if (v.kind != KIND_CHOL) v.off_rf = take(n * sizeof(float));
     }
     if (v.kind == KIND_BLOCK) {
-      v.off_g2d = take(v.g2d.size() * ts);
+      v.off_s1d = take(v.s1d.size() * ts);
       v.off_zt = take(v.zt.size() * ts);
       v.off_bfac = take(v.bfac.size() * ts);
       v.off_noise = take((size_t)(p.nu1 + p.nu2) * n * ts);
@@ -355,7 +355,7 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
     for (int m = l; m < L; ++m) {
       const Level& v = h.lv[m];
       lds += 3 * bot_field_elems(v.kind, v.nx, v.ny, v.nz) * ts;
-      if (v.kind == KIND_BLOCK) lds += (50 + (size_t)v.nz * 10 + (size_t)(v.nz / 2) * 192) * ts;
+      if (v.kind == KIND_BLOCK) lds += ((size_t)v.nz * 10 + (size_t)(v.nz / 2) * 192) * ts;
     }
     if (lds <= kBottomLdsMax && L - l <= kBottomLevelsMax) {
       h.bottom = l;
@@ -372,6 +372,15 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
   h.part_len = (size_t)((h.lv[0].n + 255) / 256) + 2;
   h.off_part = take((size_t)nc * h.part_len * sizeof(double));
   h.off_norm = take((size_t)2 * nc * sizeof(double));
+  {
+    const Level& v0 = h.lv[0];
+    const int rows = v0.ny * v0.nz;
+    int nb = (rows + 31) / 32;
+    h.stats_nblk = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
+    h.off_mtab = take((size_t)kMaxModes * (v0.nx + v0.ny + v0.nz) * sizeof(double));
+    h.off_spart = take((size_t)nc * h.stats_nblk * (kMaxModes + 1) * sizeof(double));
+  }
+  h.off_chains = take((size_t)kMaxChains * sizeof(ChainKey));
   h.ws_bytes = off;
   return SMG_OK;
 }

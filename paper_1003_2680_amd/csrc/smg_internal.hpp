@@ -13,6 +13,7 @@
 namespace smg {
 
 constexpr int STENCIL = 125;  // 5x5x5 offsets of a Galerkin operator row
+constexpr int kMaxChains = 255;  // batched chains per hierarchy (at most one per component)
 
 struct Level {
   int nx = 0, ny = 0, nz = 0;
@@ -24,9 +25,9 @@ struct Level {
   std::vector<double> az, mz;                                 // dense nz x nz (walls)
   std::vector<double> coef;  // KIND_BLOCK: [nz][125] row coefficients, index (dz+2)*25+(dy+2)*5+(dx+2)
   // The device kernels use the factored form of the same rows:
-  //   coef[k][dz][dy][dx] = zt[k][dz] * g2d[dy][dx] + zt[k][5+dz] * g2d[25 + dy*5 + dx]
-  // with g2d = (m_y m_x, a_y m_x + m_y a_x) (uniform) and zt[k] = (a_z[k][k+dz], m_z[k][k+dz]).
-  std::vector<double> g2d;   // KIND_BLOCK: [2][25]
+  //   coef[k][dz][dy][dx] = zt[k][dz] my[dy] mx[dx] + zt[k][5+dz] (ay[dy] mx[dx] + my[dy] ax[dx])
+  // with zt[k] = (a_z[k][k+dz], m_z[k][k+dz]) and the uniform 1D stencils s1d = (mx, ax, my, ay).
+  std::vector<double> s1d;   // KIND_BLOCK: [4][5]
   std::vector<double> zt;    // KIND_BLOCK: [nz][10]
   std::vector<double> bfac;  // KIND_BLOCK: [nz/2][3][64]: A_BB^-1, L_BB^-T, A_BB (row-major)
   // workspace offsets (bytes); level 0 of KIND_POINT stores x and b split by colour
@@ -35,14 +36,14 @@ struct Level {
   // every level has FP32 fields xf, bf, rf (level 0: xf = correction e, bf = FP32 residual,
   // both split by colour), FP32 tables and FP32 noise.
   size_t off_x = 0, off_b = 0, off_r = 0, off_xf = 0, off_bf = 0, off_rf = 0;
-  size_t off_g2d = 0, off_zt = 0, off_bfac = 0, off_noise = 0;
+  size_t off_s1d = 0, off_zt = 0, off_bfac = 0, off_noise = 0;
   double* x = nullptr;
   double* b = nullptr;
   double* r = nullptr;
   float* xf = nullptr;
   float* bf = nullptr;
   float* rf = nullptr;
-  void* g2d_d = nullptr;    // T tables of the sweep precision
+  void* s1d_d = nullptr;    // T tables of the sweep precision
   void* zt_d = nullptr;
   void* bfac_d = nullptr;
   void* noise_d = nullptr;  // KIND_BLOCK: pregenerated noise [nu1+nu2][ncomp][n] of one cycle
@@ -55,11 +56,22 @@ struct Hierarchy {
   int bottom = -1;               // first level handled by the LDS-resident bottom kernel
   size_t bottom_lds = 0;         // its LDS bytes
   bool use_bottom = true;        // false: run those levels with one launch per pass instead
+  int block_tile = SMG_TILE_AUTO;  // tile shape of the block-pass launches
   size_t off_botargs = 0;
   BotArgs* botargs_d = nullptr;  // device copy of the bottom kernel's level descriptors
   int nc = 0;                    // unknowns of the coarsest level when it is drawn exactly
   std::vector<double> ainv, w;   // coarsest A_c^-1 and W = L_c^-1 (row-major, n_c x n_c)
   size_t off_ainv = 0, off_w = 0, off_part = 0, off_norm = 0;
+  // statistics of emitted samples: mode factor tables [kMaxModes][nx + ny + nz] and partial
+  // sums [ncomp][stats_nblk][kMaxModes + 1]
+  size_t off_mtab = 0, off_spart = 0;
+  int stats_nblk = 1;
+  std::vector<int32_t> modes_loaded;  // modes whose tables are on the device
+  bool modes_valid = false;
+  // batched chains: device table of (seed, first cycle) per chain
+  size_t off_chains = 0;
+  ChainKey* chains_d = nullptr;
+  int chains_set = 0, chains_cpc = 0;  // shape of the table last written
   size_t part_len = 0;
   size_t ws_bytes = 0;
   double* ainv_d = nullptr;
@@ -72,6 +84,7 @@ struct Hierarchy {
   bool timing = false;
   int timed_kernel = 0;
   std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_launches;  // launches bracketed by each event pair
   size_t ev_used = 0;
   int64_t tcount = 0;
   double tms = 0.0;

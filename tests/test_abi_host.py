@@ -187,3 +187,19 @@ def test_refined_precision_plan(lib):
         assert [tuple(a.dims[l]) for l in range(a.n_levels)] == \
             [tuple(b.dims[l]) for l in range(b.n_levels)]
         assert b.workspace_bytes > 0
+
+
+@pytest.mark.parametrize("dims,k", [((128, 128, 128), 8), ((16, 16, 8), 32), ((6, 4, 3), 20),
+                                    ((256, 256, 64), 12), ((2, 2, 1), 4)])
+def test_lowest_modes_match_oracle(lib, dims, k):
+    from oracle.observables import lowest_modes
+    arr = (ctypes.c_int32 * (3 * k))()
+    abi.check(lib.smg_lowest_modes(*dims, k, arr))
+    got = [(arr[3 * q], arr[3 * q + 1], arr[3 * q + 2]) for q in range(k)]
+    assert got == lowest_modes(*dims, k)
+
+
+def test_lowest_modes_invalid(lib):
+    arr = (ctypes.c_int32 * 3)()
+    for args in ((7, 8, 8, 1), (8, 8, 8, 33), (8, 8, 8, -1), (2, 2, 1, 5)):
+        assert lib.smg_lowest_modes(*args, arr) == abi.SMG_EINVAL

@@ -91,3 +91,25 @@ def test_fullsize_refined_solve(hier32):
     for c in (0, 2):
         r = f[c].ravel() - apply_A(ug[c], *N3)
         assert np.linalg.norm(r) / np.linalg.norm(f[c]) <= 1.01e-10
+
+
+def test_fullsize_stats(hier):
+    """Observables (8 lowest modes + energy) and moments of 2 emitted 128^3 x 3 samples, in the
+    launch configuration the bench uses, against the oracle's observables of those samples."""
+    print("[gpu-case] 128^3 x3 stats", flush=True)
+    from oracle import observables as ob
+    modes = ob.lowest_modes(*N3, 8)
+    out = torch.empty((2,) + hier.shape, dtype=torch.float64, device="cuda")
+    mom = torch.zeros((2,) + hier.shape, dtype=torch.float64, device="cuda")
+    obs, _ = hier.sample_stats(2, 7, modes=modes, out=out, moments=mom)
+    torch.cuda.synchronize()
+    o = obs.cpu().numpy()
+    s = out.cpu().numpy().reshape(2, 3, -1)
+    for i in range(2):
+        for c in (0, 2):
+            want = ob.observables(s[i, c], *N3, modes)
+            assert np.max(np.abs(o[i, c, :8] - want[:8])) <= 1e-12 * np.linalg.norm(s[i, c])
+            assert abs(o[i, c, 8] - want[8]) <= 1e-12 * want[8]
+    m = mom.cpu().numpy().reshape(2, 3, -1)
+    assert np.max(np.abs(m[0] - s.sum(0))) <= 1e-12 * np.max(np.abs(s.sum(0)))
+    assert np.max(np.abs(m[1] - (s * s).sum(0))) <= 1e-12 * np.max((s * s).sum(0))
