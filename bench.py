@@ -209,6 +209,107 @@ def measure(precision, args, fs, dev):
     return res
 
 
+def measure_batched(dev, n_instances=64, n_samples=100):
+    """64 uneven instances ({32,48,64,96}^3 drawn by seed), FP32-refined, tuned per grid:
+    100 samples (float32, in HBM) and one solve to 1e-10 per instance, grouped launches; beside
+    it the plain FP64 V(2,2) form run instance by instance (timed on 10 cycles each, scaled),
+    and the refined form's error against FP64 on the same streams."""
+    import numpy as np
+    import torch
+    from paper_1003_2680_amd.api import Hierarchy
+    from paper_1003_2680_amd.batch import BatchRunner, Instance
+    from paper_1003_2680_amd.inputs import batched_sizes, gaussian_field_device
+
+    sizes = batched_sizes(n_instances)
+    insts = [Instance((e, e, e), seed=1000 + i) for i, e in enumerate(sizes)]
+    t0 = time.perf_counter()
+    R = BatchRunner(insts, precision="fp32_refined", tune=True, device=dev)
+    tune_s = time.perf_counter() - t0
+    R.start()
+    R.sample(2, emit=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = R.sample(n_samples, out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    sample_s = time.perf_counter() - t0
+    del outs
+    R.capture(n_samples)
+    R.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R.replay()
+    torch.cuda.synchronize()
+    graph_s = time.perf_counter() - t0
+    fs = {i: gaussian_field_device(inst.dims[::-1], 2000 + i, dev) for i, inst in enumerate(insts)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    us, infos = R.solve(fs, rtol=1e-10)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    cfgs = {"%dx%dx%d" % d: {k: (round(v, 6) if isinstance(v, float) else v)
+                             for k, v in c.items() if k != "table"}
+            for d, c in R.configs.items()}
+    cells = R.cells()
+    del R, us, fs
+    torch.cuda.empty_cache()
+    # plain FP64 form, one instance at a time (10 cycles each, scaled to n_samples cycles)
+    plain_s = 0.0
+    err = {}
+    for e in sorted(set(sizes)):
+        H = Hierarchy(e, e, e, ncomp=1, levels=0)
+        st = H.new_state()
+        o = torch.empty((10,) + H.shape, dtype=torch.float64, device=dev)
+        H.sample(2, 1, state=st, out=o[:2])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.sample(10, 1, first_cycle=2, state=st, out=o)
+        torch.cuda.synchronize()
+        per_cycle = (time.perf_counter() - t0) / 10
+        plain_s += per_cycle * n_samples * sizes.count(e)
+        # refined vs FP64 error on the same Philox stream (2 cycles from zero), same config
+        H32 = Hierarchy(e, e, e, ncomp=1, levels=0, precision="fp32_refined")
+        a, _ = Hierarchy(e, e, e, ncomp=1, levels=0).sample(2, 5)
+        b, _ = H32.sample(2, 5)
+        err["%d^3" % e] = float("%.3e" % float(((a - b).norm() / a.norm()).item()))
+        del H, H32, a, b, o, st
+    torch.cuda.empty_cache()
+    return {"workload": "%d instances, grids {32,48,64,96}^3 drawn by seed 2026, scalar, "
+                        "FP32-refined, tuned per grid" % n_instances,
+            "cells": cells, "groups": len(cfgs), "configs": cfgs,
+            "tune_s": round(tune_s, 2),
+            "instance_samples_per_s": round(n_instances * n_samples / sample_s, 1),
+            "sample_s": round(sample_s, 4), "graph_replay_cycles_s": round(graph_s, 4),
+            "solve_all_s": round(solve_s, 4),
+            "plain_fp64_sequential_s_est": round(plain_s, 3),
+            "speedup_vs_plain_fp64_sequential": round(plain_s / sample_s, 2),
+            "refined_rel_rms_vs_fp64_2_cycles": err}
+
+
+def measure_serving(dev, stride, rate=200.0, n=300):
+    """Poisson arrivals (seed 7) of sample (k ~ U{1..16}, stride = burn-in = k_dec) and solve
+    (1e-10) requests on grids nx = ny in {32..256}, nz in {16..128}, FP32-refined, 32 GB HBM
+    budget, 16 chain slots per pool."""
+    import numpy as np
+    import torch
+    from paper_1003_2680_amd.inputs import gaussian_field_device
+    from paper_1003_2680_amd.serve import Server, make_requests, simulate
+
+    srv = Server(budget_bytes=32 << 30, slots=16, stride=stride, precision="fp32_refined",
+                 device=dev)
+    reqs = make_requests(n, rate, seed=7)
+    ok, wall, lat = simulate(srv, reqs, lambda r: gaussian_field_device(r.dims[::-1], r.seed, dev),
+                             timeout=150.0)
+    errors = sum(1 for r in srv.done if r.error)
+    pools = len(srv.pools) + srv.evictions
+    srv.shutdown()
+    torch.cuda.empty_cache()
+    return {"rate_req_s": rate, "requests": n, "completed": len(lat), "errors": errors,
+            "all_completed": bool(ok), "throughput_req_s": round(len(lat) / wall, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "pools_created": pools, "evictions": srv.evictions}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +320,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refined", action="store_true",
                     help="skip the FP32-refined measurement")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-instance batched measurement")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving-loop measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -324,6 +429,10 @@ def main():
             "rho_obs_lag1_max": round(float(np.max(np.abs(lag1(r32["obs"])))), 4),
             "rel_rms_vs_fp64_2_cycles": float("%.3e" % rel_rms)}
 
+    if not args.no_batched:
+        line["batched"] = measure_batched(dev)
+    if not args.no_serving:
+        line["serving"] = measure_serving(dev, stride=k_dec)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(k_dec)
     print(json.dumps(line), flush=True)

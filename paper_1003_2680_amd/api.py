@@ -26,6 +26,22 @@ def lowest_modes(nx, ny, nz, k):
     return [(arr[3 * q], arr[3 * q + 1], arr[3 * q + 2]) for q in range(k)]
 
 
+def plan_bytes(dims, ncomp, precision="fp64", levels=0, coarsest_max=512):
+    """Workspace bytes of a hierarchy (host planning only, no device work)."""
+    lib = abi.load()
+    desc = abi.GridDesc(dims[0], dims[1], dims[2], ncomp, 1.0, 1.0)
+    prec = {"fp64": abi.SMG_FP64, "fp32_refined": abi.SMG_FP32_REFINED}[precision]
+    prm = abi.CycleParams(levels, 2, 2, coarsest_max, abi.SMG_COARSEST_CHOLESKY, prec, 1, 0)
+    h = ctypes.c_void_p()
+    abi.check(lib.smg_create_hierarchy(ctypes.byref(desc), ctypes.byref(prm), ctypes.byref(h)))
+    try:
+        info = abi.Info()
+        abi.check(lib.smg_hierarchy_info(h, ctypes.byref(info)))
+        return int(info.workspace_bytes)
+    finally:
+        lib.smg_destroy_hierarchy(h)
+
+
 class Hierarchy:
     """A planned multigrid hierarchy bound to a device workspace.
 

@@ -50,7 +50,10 @@ class BatchRunner:
 
     def __init__(self, instances, precision="fp32_refined", configs=None, tune=False,
                  device=None):
-        self.device = torch.device(device if device is not None else "cuda")
+        dev = torch.device(device if device is not None else "cuda")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
         self.instances = list(instances)
         self.precision = precision
         by_dims = OrderedDict()

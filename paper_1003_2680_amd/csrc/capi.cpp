@@ -672,7 +672,15 @@ int solve_impl(smg_hierarchy* hh, const Batch& bt, const void* f, void* u, doubl
       return SMG_ENONFINITE;
     }
   SMG_TRY(import_level0(h, v0.b, (const double*)f, s, nc));
-  SMG_HIP(launch_zero<double>(v0.x, field, s));
+  if (v0.kind == KIND_POINT) {
+    // split storage: the processed components of both colour arrays (colour 1 starts after
+    // all components of colour 0, not after the processed ones)
+    const int64_t act = (int64_t)nc * (v0.n / 2);
+    SMG_HIP(launch_zero<double>(v0.x, act, s));
+    SMG_HIP(launch_zero<double>(v0.x + half_field(h), act, s));
+  } else {
+    SMG_HIP(launch_zero<double>(v0.x, field, s));
+  }
   Run r = make_run(h, s, false, true, 0, 0);
   r.nc = nc;
   struct ChainState {

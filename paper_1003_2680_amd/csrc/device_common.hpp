@@ -26,6 +26,14 @@ __device__ __forceinline__ uint32_t udiv(uint32_t a, uint32_t d, int lg2) {
 template <typename T = double>
 __device__ __forceinline__ T pw(int i) { return (i == 1 || i == 2) ? T(0.75) : T(0.25); }
 
+// v mod n for v >= -n (one or two corrections cover every tile narrower than the level)
+__device__ __forceinline__ int wrap_near(int v, int n) {
+  if (v < 0) v += n;
+  if (v >= n) v -= n;
+  if (v >= n) v %= n;
+  return v;
+}
+
 // (A x) at cell (cx, cy, cz) of a Galerkin level.  The Galerkin operator of the wall-bounded
 // Laplacian is a Kronecker sum, A = a_z (x) m_y (x) m_x + m_z (x) (a_y (x) m_x + m_y (x) a_x),
 // with 5-point periodic 1D stencils s1d = (m_x, a_x, m_y, a_y) (offsets -2..2, uniform over
@@ -64,7 +72,9 @@ __device__ __forceinline__ T gal_plane(const T* __restrict__ P, int sy, const in
   return p0;
 }
 
-template <typename T>
+// UNROLL_Z: all five planes in flight at once (global-memory operands, where load latency
+// dominates); otherwise one plane at a time (LDS operands, fewer registers).
+template <typename T, bool UNROLL_Z = false>
 __device__ __forceinline__ T gal_apply(const T* __restrict__ X, int sy, int sz, const T* s1d,
                                        const T* __restrict__ zt, int nx, int ny, int nz, int cx,
                                        int cy, int cz) {
@@ -76,14 +86,20 @@ __device__ __forceinline__ T gal_apply(const T* __restrict__ X, int sy, int sz, 
     ys[d] = wrapm(cy + d - 2, ny);
   }
   T acc0 = 0, acc1 = 0;
-#pragma unroll 1
-  for (int dz = 0; dz < 5; ++dz) {
+  auto plane = [&](int dz) {
     int zz = cz + dz - 2;
     zz = zz < 0 ? 0 : (zz >= nz ? nz - 1 : zz);
     T p1;
     const T p0 = gal_plane<T>(X + (size_t)zz * sz, sy, xs, ys, s1d, p1);
     acc0 = fma(zr[dz], p0, acc0);
     acc1 = fma(zr[5 + dz], p1, acc1);
+  };
+  if constexpr (UNROLL_Z) {
+#pragma unroll
+    for (int dz = 0; dz < 5; ++dz) plane(dz);
+  } else {
+#pragma unroll 1
+    for (int dz = 0; dz < 5; ++dz) plane(dz);
   }
   return acc0 + acc1;
 }

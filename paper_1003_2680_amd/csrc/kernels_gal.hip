@@ -82,17 +82,7 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
   const int x0 = 4 * i0 + 2 * cx - 2, y0 = 4 * j0 + 2 * cy - 2, z0 = 2 * bz - 2;
   T* X = xg + (size_t)comp * N;
   const int tid = threadIdx.x;
-  for (int q = tid; q < TILE_D * TILE_H * TILE_W; q += TILE_TPB) {
-    const int tx = q % TILE_W;
-    const int r = q / TILE_W;
-    const int ty = r % TILE_H;
-    const int tz = r / TILE_H;
-    int gx = (x0 + tx) % nx; gx += gx < 0 ? nx : 0;
-    int gy = (y0 + ty) % ny; gy += gy < 0 ? ny : 0;
-    int gz = z0 + tz; gz = gz < 0 ? 0 : (gz >= nz ? nz - 1 : gz);
-    Tl[tz * TP + ty * TILE_W + tx] = X[((size_t)gz * ny + gy) * nx + gx];
-  }
-  __syncthreads();
+  // this lane's cell: its b and noise loads go out before the tile is staged
   const int k = tid & 7;
   const int il = (tid >> 3) % TILE_I, jl = (tid >> 3) / TILE_I;
   const int i = i0 + il, j = j0 + jl;
@@ -104,7 +94,41 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
   const uint32_t cell = ((uint32_t)gcz * ny + gcy) * nx + gcx;
   T ax = 0, xk = 0, bk = 0, nrm = 0;
   if (active) {
+    bk = bg[(size_t)comp * N + cell];
     if (NOISE) nrm = zn[(size_t)comp * N + cell];
+  }
+  // stage the box: every load is issued before the first LDS store, so the work-group waits
+  // for global memory once rather than once per element
+  constexpr int NTOT = TILE_D * TILE_H * TILE_W;
+  constexpr int NIT = (NTOT + TILE_TPB - 1) / TILE_TPB;
+  T stage[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int q = tid + it * TILE_TPB;
+    stage[it] = T(0);
+    if (q < NTOT) {
+      const int sx = q % TILE_W;
+      const int r = q / TILE_W;
+      const int sy = r % TILE_H;
+      const int sz = r / TILE_H;
+      const int gx = wrap_near(x0 + sx, nx);
+      const int gy = wrap_near(y0 + sy, ny);
+      int gz = z0 + sz;
+      gz = gz < 0 ? 0 : (gz >= nz ? nz - 1 : gz);
+      stage[it] = X[((size_t)gz * ny + gy) * nx + gx];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int q = tid + it * TILE_TPB;
+    if (q < NTOT) {
+      const int sx = q % TILE_W;
+      const int r = q / TILE_W;
+      Tl[(r / TILE_H) * TP + (r % TILE_H) * TILE_W + sx] = stage[it];
+    }
+  }
+  __syncthreads();
+  if (active) {
     const T* zr = zt + gcz * 10;
     const int xs[5] = {tx - 2, tx - 1, tx, tx + 1, tx + 2};
     const int ys[5] = {ty - 2, ty - 1, ty, ty + 1, ty + 2};
@@ -118,7 +142,6 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
     }
     ax = ax0 + ax1;
     xk = Tl[tz * TP + ty * TILE_W + tx];
-    bk = bg[(size_t)comp * N + cell];
   }
   const T* F = bfac + (size_t)bz * 192;
   T inb = 0;
@@ -154,7 +177,8 @@ __global__ __launch_bounds__(TPB) void k_residual_gal(T* __restrict__ r, const T
   const uint32_t row = i / nx;
   const int y = row % ny;
   const int z = row / ny;
-  const T ax = gal_apply<T>(xg + (size_t)comp * N, nx, nx * ny, s1d, zt, nx, ny, nz, x, y, z);
+  const T ax =
+      gal_apply<T, true>(xg + (size_t)comp * N, nx, nx * ny, s1d, zt, nx, ny, nz, x, y, z);
   r[(size_t)comp * N + i] = bg[(size_t)comp * N + i] - ax;
 }
 

@@ -11,6 +11,15 @@ def gaussian_field(shape, seed):
     return np.random.default_rng(seed).standard_normal(shape)
 
 
+def gaussian_field_device(shape, seed, device):
+    """Independent N(0, 1) float64 entries drawn on the device (torch's seeded generator):
+    right-hand sides too large to stage from the host at request rate."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return torch.randn(shape, generator=g, dtype=torch.float64, device=device)
+
+
 def uniform_field(shape, seed, lo=-1.0, hi=1.0):
     return np.random.default_rng(seed).uniform(lo, hi, shape)
 

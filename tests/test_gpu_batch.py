@@ -67,7 +67,9 @@ def test_batch_solve_equals_alone(precision):
     f[2:4] *= 1e-3   # a chain with a smaller right-hand side
     f[4:6] = 0.0     # a chain with f = 0
     fd = torch.from_numpy(f).cuda()
-    HB = _hier(*dims, ncomp=3 * cpc, levels=4, precision=precision)
+    # two idle components, and a sampling call first so the workspace holds old values
+    HB = _hier(*dims, ncomp=3 * cpc + 2, levels=4, precision=precision)
+    HB.sample(2, 9)
     u, infos = HB.solve_batch(fd, nchains=3, comps_per_chain=cpc, rtol=1e-11)
     for c in range(3):
         H = _hier(*dims, ncomp=cpc, levels=4, precision=precision)
