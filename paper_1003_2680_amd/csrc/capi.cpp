@@ -78,10 +78,19 @@ NoiseArgs make_noise(const Run& r, int level, int slot, int colour, uint32_t kin
   na.sqkT = std::sqrt(r.h->desc.kT);
   na.chains = r.chains;
   na.comps_per_chain = r.cpc;
+  na.bm = box_muller_coef();
   return na;
 }
 
 bool refined(const Hierarchy& h) { return h.prm.precision == SMG_FP32_REFINED; }
+
+// log2(v) if v is a power of two, else -1
+int log2_exact(int v) {
+  if (v <= 0 || (v & (v - 1))) return -1;
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
 
 size_t half_field(const Hierarchy& h) { return (size_t)h.desc.ncomp * (h.lv[0].n / 2); }
 
@@ -194,18 +203,20 @@ int restrict_residual(Run& r, int l) {
   Level& v = h.lv[l];
   const int nc = r.nc;
   T* rr = Fld<T>::r(v);
-  if (v.kind == KIND_POINT) {
-    T* xr = Fld<T>::x(v);
-    T* br = Fld<T>::b(v);
-    SMG_HIP(launch_residual0<T>(rr, xr, xr + half_field(h), r.has_b0 ? br : nullptr,
-                                r.has_b0 ? br + half_field(h) : nullptr, v.nx, v.ny, v.nz, nc,
-                                h.desc.h, r.s));
-  } else {
-    SMG_HIP(launch_residual_gal<T>(rr, Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
-                                   (const T*)v.zt_d, v.nx, v.ny, v.nz, nc, r.s));
-  }
   Level& c = h.lv[l + 1];
   const bool bottom_next = (l + 1 == h.bottom) && h.use_bottom;
+  if (v.kind == KIND_POINT) {
+    // level 0: fused, the fine residual never goes to memory
+    T* xr = Fld<T>::x(v);
+    T* br = Fld<T>::b(v);
+    SMG_HIP(launch_restrict_residual0<T>(Fld<T>::b(c), bottom_next ? nullptr : Fld<T>::x(c), xr,
+                                         xr + half_field(h), r.has_b0 ? br : nullptr,
+                                         r.has_b0 ? br + half_field(h) : nullptr, v.nx, v.ny,
+                                         v.nz, nc, h.desc.h, r.s));
+    return SMG_OK;
+  }
+  SMG_HIP(launch_residual_gal<T>(rr, Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
+                                 (const T*)v.zt_d, v.nx, v.ny, v.nz, nc, r.s));
   SMG_HIP(launch_restrict<T>(Fld<T>::b(c), bottom_next ? nullptr : Fld<T>::x(c), rr, v.nx, v.ny,
                              v.nz, nc, r.s));
   return SMG_OK;
@@ -260,6 +271,8 @@ int gen_level_noise(Run& r, int only_level = -1, int only_slot = 0) {
     e.nslot = only_level >= 0 ? 1 : h.prm.nu1 + h.prm.nu2;
     e.slot0 = only_level >= 0 ? only_slot : 0;
     e.out = v.noise_d;
+    e.lg_bx = log2_exact(v.nx / 2);
+    e.lg_bxy = log2_exact((v.nx / 2) * (v.ny / 2));
     e.calls_before = calls;
     calls += (uint32_t)(e.nslot * a.nact * (v.n / 2));
   }
@@ -488,19 +501,23 @@ int check_modes(const Hierarchy& h, const int32_t* modes, int k) {
   return SMG_OK;
 }
 
-// Device tables of the modes' 1D factors (uploaded when the mode list changes).
+// Device tables of the modes (uploaded when the mode list changes): the x factor e_a(x) and
+// the row factor e_b(y) w_m(z) of each mode.
 int load_modes(Hierarchy& h, const int32_t* modes, int k, hipStream_t s) {
   std::vector<int32_t> want(modes, modes + 3 * k);
   if (h.modes_valid && want == h.modes_loaded) return SMG_OK;
   const Level& v = h.lv[0];
-  std::vector<double> tab((size_t)kMaxModes * (v.nx + v.ny + v.nz), 0.0);
+  const size_t rows = (size_t)v.ny * v.nz;
+  std::vector<double> tab((size_t)kMaxModes * (v.nx + rows), 0.0);
   double* tx = tab.data();
-  double* ty = tx + (size_t)kMaxModes * v.nx;
-  double* tz = ty + (size_t)kMaxModes * v.ny;
+  double* tr = tx + (size_t)kMaxModes * v.nx;
+  std::vector<double> wz(v.nz);
   for (int q = 0; q < k; ++q) {
     for (int i = 0; i < v.nx; ++i) tx[q * v.nx + i] = periodic_factor(v.nx, modes[3 * q], i);
-    for (int i = 0; i < v.ny; ++i) ty[q * v.ny + i] = periodic_factor(v.ny, modes[3 * q + 1], i);
-    wall_vector(v.nz, modes[3 * q + 2], tz + q * v.nz);
+    wall_vector(v.nz, modes[3 * q + 2], wz.data());
+    for (int z = 0; z < v.nz; ++z)
+      for (int y = 0; y < v.ny; ++y)
+        tr[q * rows + (size_t)z * v.ny + y] = periodic_factor(v.ny, modes[3 * q + 1], y) * wz[z];
   }
   SMG_HIP(hipMemcpyAsync(h.ws + h.off_mtab, tab.data(), tab.size() * sizeof(double),
                          hipMemcpyHostToDevice, s));
@@ -526,11 +543,12 @@ int emit(Hierarchy& h, void* out, int out_f32, double* obs, double* m1, double* 
   a.nx = v0.nx;
   a.ny = v0.ny;
   a.nz = v0.nz;
+  a.lgx = log2_exact(v0.nx);
+  a.lgy = log2_exact(v0.ny);
   a.nmodes = obs ? k : 0;
   a.nblk = h.stats_nblk;
   a.tx = (const double*)(h.ws + h.off_mtab);
-  a.ty = a.tx + (size_t)kMaxModes * v0.nx;
-  a.tz = a.ty + (size_t)kMaxModes * v0.ny;
+  a.trow = a.tx + (size_t)kMaxModes * v0.nx;
   a.out = out;
   a.out_f32 = out_f32;
   a.m1 = m1;

@@ -26,6 +26,28 @@ __device__ __forceinline__ uint32_t udiv(uint32_t a, uint32_t d, int lg2) {
 template <typename T = double>
 __device__ __forceinline__ T pw(int i) { return (i == 1 || i == 2) ? T(0.75) : T(0.25); }
 
+// XCD-aware work-group numbering.  The dispatcher deals work-groups to the 8 XCDs round-robin
+// by linear id, and each XCD has its own L2.  Renumbering so that XCD k runs the k-th
+// contiguous eighth of the grid keeps neighbouring tiles (which share halo rows and planes)
+// on one L2.  A bijection on [0, total); the ragged tail beyond a multiple of 8 keeps its ids.
+constexpr uint32_t kXcds = 8;
+struct Blk3 {
+  uint32_t x, y, z;
+};
+__device__ __forceinline__ Blk3 xcd_block() {
+  const uint32_t gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const uint32_t total = gx * gy * gz;
+  uint32_t lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const uint32_t per = total / kXcds;
+  if (lin < per * kXcds) lin = (lin % kXcds) * per + lin / kXcds;
+  Blk3 b;
+  b.x = lin % gx;
+  const uint32_t r = lin / gx;
+  b.y = r % gy;
+  b.z = r / gy;
+  return b;
+}
+
 // v mod n for v >= -n (one or two corrections cover every tile narrower than the level)
 __device__ __forceinline__ int wrap_near(int v, int n) {
   if (v < 0) v += n;

@@ -24,6 +24,7 @@ enum LevelKind { KIND_POINT = 0, KIND_BLOCK = 1, KIND_CHOL = 2 };
 constexpr int kMaxNoiseLevels = 16;
 struct NoiseLevel {
   int level, nx, ny, nz, nslot, slot0;
+  int lg_bx, lg_bxy;      // log2 of nx/2 and of (nx/2)(ny/2) when powers of two, else -1
   void* out;              // T[nslot][ncomp][N]
   uint32_t calls_before;  // prefix sum of nslot*nact*N/2 over the previous entries
 };
@@ -80,6 +81,12 @@ hipError_t launch_rb_pass(T* xc, const T* xo, const T* bc, int nx, int ny, int n
 template <typename T>
 hipError_t launch_residual0(T* r, const T* xr, const T* xb, const T* br, const T* bb, int nx,
                             int ny, int nz, int ncomp, double h, hipStream_t s);
+// b_c = P^T (b - A x) from split level-0 storage straight to the natural coarse level (r is
+// never written); also x_c = 0 when xc is not null.  br/bb null = 0.
+template <typename T>
+hipError_t launch_restrict_residual0(T* bc, T* xc, const T* xr, const T* xb, const T* br,
+                                     const T* bb, int nx, int ny, int nz, int ncomp, double h,
+                                     hipStream_t s);
 template <typename T>
 hipError_t launch_prolong0(T* xr, T* xb, const T* e, int nxf, int nyf, int nzf, int ncomp,
                            hipStream_t s);
@@ -149,15 +156,17 @@ hipError_t launch_advance_chains(ChainKey* dst, int n, uint64_t cycles, hipStrea
 
 // Statistics of one emitted sample of level 0 (FP64 state), fused with its emission.
 constexpr int kMaxModes = 32;
+constexpr int STATS_CPT = 4;                 // cells per thread
+constexpr int STATS_CELLS = STATS_CPT * 256;  // cells per work-group
 struct StatsArgs {
   const double* xr;   // split layout: colour-0 half [ncomp][N/2]; natural layout: [ncomp][N]
   const double* xb;   // split layout: colour-1 half; null for the natural layout
   int nx, ny, nz;
+  int lgx, lgy;       // log2 of nx and ny when powers of two, else -1
   int nmodes;         // 0..kMaxModes projections (with obs)
-  int nblk;           // work-groups per component (rows are dealt to their waves)
-  const double* tx;   // [nmodes][nx], [nmodes][ny], [nmodes][nz]: the 1D factors of each mode
-  const double* ty;
-  const double* tz;
+  int nblk;           // work-groups per component: ceil(N / STATS_CELLS)
+  const double* tx;   // [kMaxModes][nx]: x factor e_a(x) of each mode
+  const double* trow; // [kMaxModes][ny*nz]: row factor e_b(y) w_m(z) of each mode
   void* out;          // [ncomp][N] natural emission (float or double) or null
   int out_f32;
   double* m1;         // [ncomp][N] running sum of x and of x^2, or null

@@ -170,6 +170,108 @@ __global__ __launch_bounds__(TPB) void k_residual0(T* __restrict__ r, const T* _
   r[(size_t)comp * N + i] = bv - ax;
 }
 
+// Fused residual and restriction from level 0: b_c = P^T (b - A x) without writing r.
+// A work-group owns RX x RY x RZ coarse cells.  Their restriction windows cover the fine box
+// [2X0-1, 2X0+2RX+1) (x, y) and [2Z0-1, 2Z0+2RZ+1) (z); the residual there needs x one cell
+// further out.  x is staged from the split storage into LDS (all loads in flight first), the
+// residual of the window box goes to LDS, and each coarse cell sums its 4x4x4 window with the
+// weights (1/4, 3/4, 3/4, 1/4) per axis (1/2 for a fine cell next to a wall).  Also zeroes the
+// coarse iterate when xc is not null.
+constexpr int RR_X = 8, RR_Y = 8, RR_Z = 2;
+constexpr int RR_FX = 2 * RR_X + 2, RR_FY = 2 * RR_Y + 2, RR_FZ = 2 * RR_Z + 2;  // residual box
+constexpr int RR_SX = RR_FX + 2, RR_SY = RR_FY + 2, RR_SZ = RR_FZ + 2;           // x box
+
+template <typename T, bool HAS_B>
+__global__ __launch_bounds__(TPB) void k_restrict_residual0(
+    T* __restrict__ bc, T* __restrict__ xc, const T* __restrict__ xr, const T* __restrict__ xb,
+    const T* __restrict__ br, const T* __restrict__ bb, int nx, int ny, int nz, int ntx,
+    T inv_h2) {
+  __shared__ T Xs[RR_SZ * RR_SY * RR_SX];
+  __shared__ T Rs[RR_FZ * RR_FY * RR_FX];
+  const Blk3 wg = xcd_block();
+  const uint32_t comp = wg.z;
+  const int nxc = nx >> 1, nyc = ny >> 1, nzc = nz >> 1;
+  const int X0 = (wg.x % ntx) * RR_X, Y0 = (wg.x / ntx) * RR_Y;
+  const int Z0 = wg.y * RR_Z;
+  const int nh = nx >> 1;
+  const size_t cb = (size_t)comp * ((size_t)(nx >> 1) * ny * nz);
+  const int tid = threadIdx.x;
+  // ---- stage x: box origin (2X0-2, 2Y0-2, 2Z0-2); planes outside the grid are never read
+  {
+    constexpr int PLANE = RR_SX * RR_SY;
+    constexpr int PPT = (PLANE + TPB - 1) / TPB;
+    int gxs[PPT], gys[PPT], loff[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      const int pos = tid + p * TPB;
+      const int sx = pos % RR_SX, sy = pos / RR_SX;
+      loff[p] = pos < PLANE ? sy * RR_SX + sx : -1;
+      gxs[p] = wrap_near(2 * X0 - 2 + sx, nx);
+      gys[p] = pos < PLANE ? wrap_near(2 * Y0 - 2 + sy, ny) : 0;
+    }
+    T st[RR_SZ][PPT];
+#pragma unroll
+    for (int sz = 0; sz < RR_SZ; ++sz) {
+      int gz = 2 * Z0 - 2 + sz;
+      gz = gz < 0 ? 0 : (gz >= nz ? nz - 1 : gz);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) st[sz][p] = split_at(xr, xb, cb, gxs[p], gys[p], gz, nh, ny);
+    }
+#pragma unroll
+    for (int sz = 0; sz < RR_SZ; ++sz)
+#pragma unroll
+      for (int p = 0; p < PPT; ++p)
+        if (loff[p] >= 0) Xs[sz * (RR_SX * RR_SY) + loff[p]] = st[sz][p];
+  }
+  __syncthreads();
+  // ---- residual of the window box: fine cell (2X0-1+rx, 2Y0-1+ry, 2Z0-1+rz)
+  for (int q = tid; q < RR_FX * RR_FY * RR_FZ; q += TPB) {
+    const int rx = q % RR_FX, t2 = q / RR_FX, ry = t2 % RR_FY, rz = t2 / RR_FY;
+    const int fz = 2 * Z0 - 1 + rz;
+    T rv = T(0);
+    if (fz >= 0 && fz < nz) {
+      const T* c = Xs + (rz + 1) * (RR_SX * RR_SY) + (ry + 1) * RR_SX + (rx + 1);
+      T sn = (c[-1] + c[1]) + (c[-RR_SX] + c[RR_SX]);
+      int nw = 0;
+      if (fz + 1 < nz) sn += c[RR_SX * RR_SY]; else ++nw;
+      if (fz > 0) sn += c[-RR_SX * RR_SY]; else ++nw;
+      rv = -(T(6 + nw) * c[0] - sn) * inv_h2;
+      if (HAS_B) {
+        const int fx = wrap_near(2 * X0 - 1 + rx, nx), fy = wrap_near(2 * Y0 - 1 + ry, ny);
+        rv += split_at(br, bb, cb, fx, fy, fz, nh, ny);
+      }
+    }
+    Rs[q] = rv;
+  }
+  __syncthreads();
+  // ---- restriction of the window of each owned coarse cell
+  if (tid < RR_X * RR_Y * RR_Z) {
+    const int lx = tid % RR_X, ly = (tid / RR_X) % RR_Y, lz = tid / (RR_X * RR_Y);
+    const int X = X0 + lx, Y = Y0 + ly, Z = Z0 + lz;
+    if (X < nxc && Y < nyc && Z < nzc) {
+      T acc = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int zf = 2 * Z - 1 + c;
+        if (zf < 0 || zf >= nz) continue;
+        T wz = pw<T>(c);
+        if ((Z == 0 && zf == 0) || (Z == nzc - 1 && zf == nz - 1)) wz = T(0.5);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const T* Rr = Rs + ((2 * lz + c) * RR_FY + (2 * ly + b)) * RR_FX + 2 * lx;
+          T sacc = 0;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) sacc = fma(pw<T>(a), Rr[a], sacc);
+          acc = fma(wz * pw<T>(b), sacc, acc);
+        }
+      }
+      const size_t I = (size_t)comp * nxc * nyc * nzc + ((size_t)Z * nyc + Y) * nxc + X;
+      bc[I] = acc;
+      if (xc) xc[I] = T(0);
+    }
+  }
+}
+
 // FP32-refined bridge: r32 = (float)(b - A x) from FP64 split storage, written split; the
 // optional fixed-order partial sums of (b - A x)^2 go to part[comp][colour*nblk + block].
 template <bool HAS_B, bool NORM>
@@ -330,6 +432,20 @@ hipError_t launch_residual0(T* r, const T* xr, const T* xb, const T* br, const T
 }
 
 template <typename T>
+hipError_t launch_restrict_residual0(T* bc, T* xc, const T* xr, const T* xb, const T* br,
+                                     const T* bb, int nx, int ny, int nz, int ncomp, double h,
+                                     hipStream_t s) {
+  const int nxc = nx >> 1, nyc = ny >> 1, nzc = nz >> 1;
+  if (nxc * nyc * nzc == 0) return hipSuccess;
+  const int ntx = (nxc + RR_X - 1) / RR_X, nty = (nyc + RR_Y - 1) / RR_Y;
+  dim3 grid(ntx * nty, (nzc + RR_Z - 1) / RR_Z, ncomp);
+  const T ih2 = (T)(1.0 / (h * h));
+  if (br) k_restrict_residual0<T, true><<<grid, TPB, 0, s>>>(bc, xc, xr, xb, br, bb, nx, ny, nz, ntx, ih2);
+  else k_restrict_residual0<T, false><<<grid, TPB, 0, s>>>(bc, xc, xr, xb, br, bb, nx, ny, nz, ntx, ih2);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_prolong0(T* xr, T* xb, const T* e, int nxf, int nyf, int nzf, int ncomp,
                            hipStream_t s) {
   const uint32_t nsite = (uint32_t)(nxf / 2) * nyf * nzf;
@@ -352,6 +468,13 @@ template hipError_t launch_residual0<float>(float*, const float*, const float*, 
                                             const float*, int, int, int, int, double, hipStream_t);
 template hipError_t launch_prolong0<double>(double*, double*, const double*, int, int, int, int,
                                             hipStream_t);
+template hipError_t launch_restrict_residual0<double>(double*, double*, const double*,
+                                                      const double*, const double*,
+                                                      const double*, int, int, int, int, double,
+                                                      hipStream_t);
+template hipError_t launch_restrict_residual0<float>(float*, float*, const float*, const float*,
+                                                     const float*, const float*, int, int, int,
+                                                     int, double, hipStream_t);
 template hipError_t launch_prolong0<float>(float*, float*, const float*, int, int, int, int,
                                            hipStream_t);
 

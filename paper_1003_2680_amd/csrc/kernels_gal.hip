@@ -17,34 +17,32 @@ namespace {
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
 
 // Block-level noise for whole sweeps: thread = one Philox call = the two cells (in-block k = 2m,
-// 2m+1) of one block.
+// 2m+1) of one block.  Grid: x over the calls of one (sweep slot, component) of the largest
+// level, y = level entry, z = slot * nact + component, so every index below is uniform per
+// work-group except the call number.
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_level_noise(NoiseGenArgs a, NoiseArgs na) {
-  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
-  if (t >= a.total) return;
-  int e = 0;
-  while (e + 1 < a.nlev && t >= a.lv[e + 1].calls_before) ++e;
-  const NoiseLevel& L = a.lv[e];
+  const NoiseLevel& L = a.lv[blockIdx.y];
   const uint32_t N = (uint32_t)L.nx * L.ny * L.nz;
   const uint32_t half = N >> 1;
-  uint32_t u = t - L.calls_before;
-  const uint32_t q = u % half;  // call within (slot, comp)
-  u /= half;
-  const uint32_t comp = u % (uint32_t)a.nact;
-  const uint32_t s = u / (uint32_t)a.nact;
+  const uint32_t q = blockIdx.x * TPB + threadIdx.x;  // call within (slot, comp)
+  const uint32_t s = blockIdx.z / (uint32_t)a.nact;
+  const uint32_t comp = blockIdx.z - s * (uint32_t)a.nact;
+  if (q >= half || (int)s >= L.nslot) return;
   const uint32_t bid = q >> 2;
   const int m = q & 3;
-  const int nbx = L.nx >> 1, nby = L.ny >> 1;
-  const int bx = bid % nbx;
-  const int by = (bid / nbx) % nby;
-  const int bz = bid / (nbx * nby);
+  const uint32_t nbx = (uint32_t)L.nx >> 1, nby = (uint32_t)L.ny >> 1;
+  const uint32_t bxy = udiv(bid, nbx * nby, L.lg_bxy);
+  const uint32_t rem = bid - bxy * nbx * nby;
+  const uint32_t by = udiv(rem, nbx, L.lg_bx);
+  const uint32_t bx = rem - by * nbx;
+  const uint32_t bz = bxy;
   const int colour = (bx & 1) + 2 * (by & 1) + 4 * (bz & 1);
-  NoiseArgs nl = na;
-  nl.sid = (uint32_t)L.level | ((uint32_t)(L.slot0 + s) << 4) | ((uint32_t)colour << 12);
+  const uint32_t sid = (uint32_t)L.level | ((uint32_t)(L.slot0 + s) << 4) | ((uint32_t)colour << 12);
   T z0, z1;
-  normal_pair_t<T>(nl, comp, q, z0, z1);
+  normal_pair_t<T>(na, sid, comp, q, z0, z1);
   const int dy = m & 1, dz = m >> 1;  // in-block index k = 2m + dx
-  const uint32_t c0 = ((uint32_t)(2 * bz + dz) * L.ny + (2 * by + dy)) * L.nx + 2 * bx;
+  const uint32_t c0 = ((2 * bz + dz) * L.ny + (2 * by + dy)) * L.nx + 2 * bx;
   T* out = (T*)L.out + ((size_t)s * a.ncomp + comp) * N;
   out[c0] = z0;
   out[c0 + 1] = z1;
@@ -73,9 +71,10 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
   constexpr int TILE_TPB = TILE_I * TILE_J * 8;
   constexpr int TP = TILE_H * TILE_W + 1;  // plane stride: 1 mod 4 elements
   __shared__ T Tl[TILE_D * TP];
-  const uint32_t comp = blockIdx.z;
-  const int l = blockIdx.y;
-  const int ti = blockIdx.x % ntx, tj = blockIdx.x / ntx;
+  const Blk3 wg = xcd_block();
+  const uint32_t comp = wg.z;
+  const int l = wg.y;
+  const int ti = wg.x % ntx, tj = wg.x / ntx;
   const int cx = colour & 1, cy = (colour >> 1) & 1;
   const int bz = 2 * l + (colour >> 2);
   const int i0 = ti * TILE_I, j0 = tj * TILE_J;
@@ -97,36 +96,33 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
     bk = bg[(size_t)comp * N + cell];
     if (NOISE) nrm = zn[(size_t)comp * N + cell];
   }
-  // stage the box: every load is issued before the first LDS store, so the work-group waits
-  // for global memory once rather than once per element
-  constexpr int NTOT = TILE_D * TILE_H * TILE_W;
-  constexpr int NIT = (NTOT + TILE_TPB - 1) / TILE_TPB;
-  T stage[NIT];
+  // stage the box: each thread owns up to PPT (x, y) positions of a plane and loads them in all
+  // TILE_D planes; every load is issued before the first LDS store, so the work-group waits for
+  // global memory once, and the index arithmetic is done once per position, not per element
+  constexpr int PLANE = TILE_W * TILE_H;
+  constexpr int PPT = (PLANE + TILE_TPB - 1) / TILE_TPB;
+  int goff[PPT], loff[PPT];
 #pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int q = tid + it * TILE_TPB;
-    stage[it] = T(0);
-    if (q < NTOT) {
-      const int sx = q % TILE_W;
-      const int r = q / TILE_W;
-      const int sy = r % TILE_H;
-      const int sz = r / TILE_H;
-      const int gx = wrap_near(x0 + sx, nx);
-      const int gy = wrap_near(y0 + sy, ny);
-      int gz = z0 + sz;
-      gz = gz < 0 ? 0 : (gz >= nz ? nz - 1 : gz);
-      stage[it] = X[((size_t)gz * ny + gy) * nx + gx];
-    }
+  for (int p = 0; p < PPT; ++p) {
+    const int pos = tid + p * TILE_TPB;
+    const int sx = pos % TILE_W, sy = pos / TILE_W;
+    loff[p] = pos < PLANE ? sy * TILE_W + sx : -1;
+    goff[p] = pos < PLANE ? wrap_near(y0 + sy, ny) * nx + wrap_near(x0 + sx, nx) : 0;
+  }
+  T stage[TILE_D][PPT];
+#pragma unroll
+  for (int sz = 0; sz < TILE_D; ++sz) {
+    int gz = z0 + sz;
+    gz = gz < 0 ? 0 : (gz >= nz ? nz - 1 : gz);
+    const T* P = X + (size_t)gz * nx * ny;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) stage[sz][p] = P[goff[p]];  // goff = 0 (in range) if unused
   }
 #pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int q = tid + it * TILE_TPB;
-    if (q < NTOT) {
-      const int sx = q % TILE_W;
-      const int r = q / TILE_W;
-      Tl[(r / TILE_H) * TP + (r % TILE_H) * TILE_W + sx] = stage[it];
-    }
-  }
+  for (int sz = 0; sz < TILE_D; ++sz)
+#pragma unroll
+    for (int p = 0; p < PPT; ++p)
+      if (loff[p] >= 0) Tl[sz * TP + loff[p]] = stage[sz][p];
   __syncthreads();
   if (active) {
     const T* zr = zt + gcz * 10;
@@ -230,7 +226,7 @@ __global__ __launch_bounds__(TPB) void k_coarsest(T* __restrict__ xg, const T* _
   if (NOISE) {
     for (int q = threadIdx.x; 2 * q < n; q += TPB) {
       double z0, z1;
-      normal_pair(na, comp, (uint32_t)q, z0, z1);
+      normal_pair(na, na.sid, comp, (uint32_t)q, z0, z1);
       sh[n + 2 * q] = z0;
       if (2 * q + 1 < n) sh[n + 2 * q + 1] = z1;
     }
@@ -342,11 +338,10 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
     if (L.kind == KIND_CHOL) {
       // exact draw x = A_c^-1 b + sqrt(kT) L_c^-T n (natural layout on this level)
       if (NOISE) {
-        NoiseArgs nc = na;
-        nc.sid = (uint32_t)level | (1u << 24);
+        const uint32_t sid = (uint32_t)level | (1u << 24);
         for (int q = tid; 2 * q < n; q += BOT_TPB) {
           double z0, z1;
-          normal_pair(nc, comp, (uint32_t)q, z0, z1);
+          normal_pair(na, sid, comp, (uint32_t)q, z0, z1);
           ri[2 * q] = (T)z0;
           if (2 * q + 1 < n) ri[2 * q + 1] = (T)z1;
         }
@@ -497,8 +492,16 @@ hipError_t launch_coarsest(T* x, const T* b, const double* ainv, const double* w
 
 template <typename T>
 hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStream_t s) {
-  if (a.total == 0) return hipSuccess;
-  k_level_noise<T><<<blocks_for(a.total), TPB, 0, s>>>(a, na);
+  if (a.total == 0 || a.nlev == 0) return hipSuccess;
+  uint32_t maxhalf = 0;
+  int maxslot = 0;
+  for (int e = 0; e < a.nlev; ++e) {
+    const uint32_t h = (uint32_t)a.lv[e].nx * a.lv[e].ny * a.lv[e].nz / 2;
+    maxhalf = h > maxhalf ? h : maxhalf;
+    maxslot = a.lv[e].nslot > maxslot ? a.lv[e].nslot : maxslot;
+  }
+  dim3 grid(blocks_for(maxhalf), a.nlev, maxslot * a.nact);
+  k_level_noise<T><<<grid, TPB, 0, s>>>(a, na);
   return hipGetLastError();
 }
 

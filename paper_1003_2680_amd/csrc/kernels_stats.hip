@@ -2,11 +2,13 @@
 // onto eigenvectors of A and the energy 1/2 x^T A x (the observables whose lag-k correlation
 // measures how fast the chain decorrelates, Sec. "Stochastic Iterative Methods").
 //
-// One wavefront walks whole grid rows (y, z uniform across the wave), its lanes along x.  An
-// eigenvector is a product e_a(x) e_b(y) w_m(z), so the (y, z) factor of every mode is read
-// once per row (uniform loads) and the x factor once per cell.  Sums run in a fixed order:
-// lane partials over a wave's rows, a butterfly over the lanes, the four waves of a work-group,
-// then a second kernel over the work-groups, so results do not depend on timing.
+// A work-group takes STATS_CELLS consecutive cells of one component, STATS_CPT per thread
+// (256 apart, all loads issued before any arithmetic), so every wave keeps its whole working
+// set in flight at once.  An eigenvector is a product e_a(x) e_b(y) w_m(z): when rows are a
+// multiple of 64 cells a wavefront lies in one row and the (y, z) factor of each mode (a
+// per-row table) is a uniform (scalar) load.  Sums run in a fixed order -- thread, butterfly over the lanes, the
+// four waves of a work-group, then a tree over the work-groups -- so results do not depend on
+// timing.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
@@ -21,62 +23,88 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int KB, bool SPLIT, bool MOM, typename TO>
+template <int KB, bool SPLIT, bool MOM, typename TO, bool UROW>
 __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   const uint32_t comp = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const size_t N = (size_t)nx * ny * nz;
-  const size_t hN = N >> 1;
+  const uint32_t N = (uint32_t)nx * ny * nz;
+  const uint32_t hN = N >> 1;
   const int nh = nx >> 1;
-  const double* Xr = a.xr + comp * (SPLIT ? hN : N);
-  const double* Xb = SPLIT ? a.xb + comp * hN : nullptr;
+  const double* Xr = a.xr + (size_t)comp * (SPLIT ? hN : N);
+  const double* Xb = SPLIT ? a.xb + (size_t)comp * hN : nullptr;
   auto load = [&](int x, int y, int z) -> double {
     if (SPLIT) {
-      const size_t i = ((size_t)z * ny + y) * nh + (x >> 1);
+      const uint32_t i = ((uint32_t)z * ny + y) * nh + (x >> 1);
       return ((x + y + z) & 1) ? Xb[i] : Xr[i];
     }
-    return Xr[((size_t)z * ny + y) * nx + x];
+    return Xr[((uint32_t)z * ny + y) * nx + x];
   };
   TO* out = (TO*)a.out;
   const int K = a.nmodes;
+  // the mode tables are read-only for the kernel's lifetime: through the constant address
+  // space the row factor of a mode (a uniform address when a wave lies in one row) becomes a
+  // scalar load used directly as an FMA operand
+  typedef const __attribute__((address_space(4))) double* cptr;
+  const double* __restrict__ tx = a.tx;
+  const cptr trow = (cptr)a.trow;
+  const uint32_t rows = (uint32_t)ny * nz;
+  const uint32_t base = blockIdx.x * STATS_CELLS;
+  // all loads of this thread's cells first
+  double v[STATS_CPT], nb[STATS_CPT][3];
+  int cx[STATS_CPT], cy[STATS_CPT], cz[STATS_CPT];
+#pragma unroll
+  for (int c = 0; c < STATS_CPT; ++c) {
+    const uint32_t cell = base + c * TPB + threadIdx.x;
+    const bool in = cell < N;
+    const uint32_t cc = in ? cell : 0;
+    const uint32_t row = udiv(cc, nx, a.lgx);
+    const int x = cc - row * nx;
+    const uint32_t zz = udiv(row, ny, a.lgy);
+    const int y = row - zz * ny, z = zz;
+    cx[c] = x;
+    cy[c] = y;
+    cz[c] = in ? z : -1;
+    v[c] = in ? load(x, y, z) : 0.0;
+    if (KB > 0) {
+      nb[c][0] = in ? load(x + 1 == nx ? 0 : x + 1, y, z) : 0.0;
+      nb[c][1] = in ? load(x, y + 1 == ny ? 0 : y + 1, z) : 0.0;
+      nb[c][2] = (in && z + 1 < nz) ? load(x, y, z + 1) : 0.0;
+    }
+  }
   double acc[KB > 0 ? KB : 1];
 #pragma unroll
   for (int q = 0; q < (KB > 0 ? KB : 1); ++q) acc[q] = 0.0;
   double accE = 0.0;
-  const int rows = ny * nz;
-  for (int r = blockIdx.x * 4 + w; r < rows; r += a.nblk * 4) {
-    const int y = r % ny, z = r / ny;
-    double u[KB > 0 ? KB : 1];
-    if (KB > 0) {
 #pragma unroll
-      for (int q = 0; q < KB; ++q) u[q] = q < K ? a.ty[q * ny + y] * a.tz[q * nz + z] : 0.0;
+  for (int c = 0; c < STATS_CPT; ++c) {
+    if (cz[c] < 0) continue;
+    const size_t gi = (size_t)comp * N + base + c * TPB + threadIdx.x;
+    const double x0 = v[c];
+    if (out) out[gi] = (TO)x0;
+    if (MOM) {
+      a.m1[gi] += x0;
+      a.m2[gi] = fma(x0, x0, a.m2[gi]);
     }
-    for (int x = lane; x < nx; x += 64) {
-      const double v = load(x, y, z);
-      const size_t cell = comp * N + (size_t)r * nx + x;
-      if (out) out[cell] = (TO)v;
-      if (MOM) {
-        a.m1[cell] += v;
-        a.m2[cell] = fma(v, v, a.m2[cell]);
-      }
-      if (KB > 0) {
+    if (KB > 0) {
+      const int z = cz[c];
+      uint32_t row = (uint32_t)z * ny + cy[c];
+      if (UROW) row = __builtin_amdgcn_readfirstlane(row);  // the wavefront lies in one row
 #pragma unroll
-        for (int q = 0; q < KB; ++q)
-          if (q < K) acc[q] = fma(a.tx[q * nx + x], v * u[q], acc[q]);
-        // faces +x, +y (periodic) and +z (interior), plus the wall faces (ghost = -v)
-        const double d1 = v - load(x + 1 == nx ? 0 : x + 1, y, z);
-        const double d2 = v - load(x, y + 1 == ny ? 0 : y + 1, z);
-        double e = fma(d1, d1, d2 * d2);
-        if (z + 1 < nz) {
-          const double d3 = v - load(x, y, z + 1);
-          e = fma(d3, d3, e);
-        }
-        if (z == 0) e = fma(2.0 * v, v, e);
-        if (z == nz - 1) e = fma(2.0 * v, v, e);
-        accE += e;
+      for (int q = 0; q < KB; ++q)
+        if (q < K) acc[q] = fma(tx[q * nx + cx[c]] * trow[q * rows + row], x0, acc[q]);
+      // faces +x, +y (periodic) and +z (interior), plus the wall faces (ghost = -v)
+      const double d1 = x0 - nb[c][0];
+      const double d2 = x0 - nb[c][1];
+      double e = fma(d1, d1, d2 * d2);
+      if (z + 1 < nz) {
+        const double d3 = x0 - nb[c][2];
+        e = fma(d3, d3, e);
       }
+      if (z == 0) e = fma(2.0 * x0, x0, e);
+      if (z == nz - 1) e = fma(2.0 * x0, x0, e);
+      accE += e;
     }
   }
   if (KB == 0) return;
@@ -95,24 +123,36 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   }
 }
 
-// obs[comp][q] = sum over work-groups of part[comp][blk][q]; the energy (q = K) is scaled by
-// 1/(2 h^2).
+// obs[comp][q] = sum over work-groups of part[comp][blk][q]: one work-group per (comp, q),
+// thread t adds partials t, t + 256, ... in order, then a fixed tree in LDS.  The energy
+// (q = K) is scaled by 1/(2 h^2).
 __global__ __launch_bounds__(TPB) void k_stats_final(double* __restrict__ obs,
                                                       const double* __restrict__ part, int nblk,
-                                                      int K1, int ncomp, double escale) {
-  const int t = blockIdx.x * TPB + threadIdx.x;
-  if (t >= ncomp * K1) return;
-  const int comp = t / K1, q = t % K1;
+                                                      int K1, double escale) {
+  __shared__ double sh[TPB];
+  const int comp = blockIdx.y, q = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[((size_t)comp * nblk + b) * K1 + q];
-  obs[t] = q == K1 - 1 ? s * escale : s;
+  for (int b = threadIdx.x; b < nblk; b += TPB) s += part[((size_t)comp * nblk + b) * K1 + q];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = TPB / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) obs[comp * K1 + q] = q == K1 - 1 ? sh[0] * escale : sh[0];
+}
+
+template <int KB, bool SPLIT, bool MOM, bool UROW>
+void launch_stats_u(const StatsArgs& a, int ncomp, hipStream_t s) {
+  dim3 grid(a.nblk, ncomp);
+  if (a.out && a.out_f32) k_stats<KB, SPLIT, MOM, float, UROW><<<grid, TPB, 0, s>>>(a);
+  else k_stats<KB, SPLIT, MOM, double, UROW><<<grid, TPB, 0, s>>>(a);
 }
 
 template <int KB, bool SPLIT, bool MOM>
 void launch_stats_k(const StatsArgs& a, int ncomp, hipStream_t s) {
-  dim3 grid(a.nblk, ncomp);
-  if (a.out && a.out_f32) k_stats<KB, SPLIT, MOM, float><<<grid, TPB, 0, s>>>(a);
-  else k_stats<KB, SPLIT, MOM, double><<<grid, TPB, 0, s>>>(a);
+  if (a.nx % 64 == 0) launch_stats_u<KB, SPLIT, MOM, true>(a, ncomp, s);
+  else launch_stats_u<KB, SPLIT, MOM, false>(a, ncomp, s);
 }
 
 template <int KB>
@@ -137,8 +177,7 @@ hipError_t launch_stats(const StatsArgs& a, int ncomp, double* obs, double escal
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !obs) return e;
   const int K1 = a.nmodes + 1;
-  const int total = ncomp * K1;
-  k_stats_final<<<(total + TPB - 1) / TPB, TPB, 0, s>>>(obs, a.part, a.nblk, K1, ncomp, escale);
+  k_stats_final<<<dim3(K1, ncomp), TPB, 0, s>>>(obs, a.part, a.nblk, K1, escale);
   return hipGetLastError();
 }
 

@@ -8,7 +8,9 @@
 //
 // Box-Muller turns words (w0,w1) and (w2,w3) into two 53-bit uniforms in (0,1] and then
 // into two standard normals: sqrt(-2 ln u1) cos(2 pi u2) and sqrt(-2 ln u1) sin(2 pi u2).
-// The angle uses sincospi(2 u2), which needs no reduction by pi.
+// The FP64 logarithm and the sine/cosine of pi t are evaluated here (below) from their
+// series, with a bounded argument range: the general-purpose library routines spend about
+// twice the instructions on full-range reduction and extra-precise arithmetic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,6 +25,15 @@ struct ChainKey {
   uint32_t c0, c1;   // first cycle low / high
 };
 
+// Polynomial coefficients of the FP64 Box-Muller (see log_unit and sincospi_turns).  They
+// travel in the kernel arguments so that a wave reads them with scalar loads and the FMAs take
+// them as scalar operands, instead of materialising every 64-bit literal in vector registers.
+struct BoxMullerCoef {
+  double lg[9];  // 1/19, 1/17, ..., 1/3
+  double sn[9];  // (-1)^k pi^(2k+1)/(2k+1)!, k = 8 .. 0
+  double cs[8];  // (-1)^k pi^(2k)/(2k)!, k = 8 .. 1
+};
+
 struct NoiseArgs {
   uint32_t k0, k1;   // seed low / high (one chain)
   uint32_t sid;      // level | slot<<4 | colour<<12 | kind<<24 (component added per thread)
@@ -30,11 +41,25 @@ struct NoiseArgs {
   double sqkT;       // sqrt(kT)
   const ChainKey* chains;    // null: one chain keyed by (k0, k1)
   uint32_t comps_per_chain;
+  BoxMullerCoef bm;
 };
 
-// Philox key, counter words 1..3 for component `comp`.
-__device__ __forceinline__ void noise_key(const NoiseArgs& na, uint32_t comp, uint32_t& k0,
-                                          uint32_t& k1, uint32_t& w1, uint32_t& w2,
+// The coefficient values (host and device).
+inline __host__ __device__ BoxMullerCoef box_muller_coef() {
+  return BoxMullerCoef{
+      {1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0, 1.0 / 9.0, 1.0 / 7.0,
+       1.0 / 5.0, 1.0 / 3.0},
+      {0x1.aaec32af93359p-21, -0x1.6fadb9f155744p-16, 0x1.e8f434d018d63p-12,
+       -0x1.e3074fde8871fp-8, 0x1.50783487ee782p-4, -0x1.32d2cce62bd86p-1, 0x1.466bc6775aae2p+1,
+       -0x1.4abbce625be53p+2, 0x1.921fb54442d18p+1},
+      {0x1.20c62c2f2d7f5p-18, -0x1.b6e24f44b128fp-14, 0x1.f9d38a3763cc3p-10,
+       -0x1.a6d1f2a204a8cp-6, 0x1.e1f506891babbp-3, -0x1.55d3c7e3cbffap+0, 0x1.03c1f081b5ac4p+2,
+       -0x1.3bd3cc9be45dep+2}};
+}
+
+// Philox key, counter words 1..3 for component `comp` of stream `sid`.
+__device__ __forceinline__ void noise_key(const NoiseArgs& na, uint32_t sid, uint32_t comp,
+                                          uint32_t& k0, uint32_t& k1, uint32_t& w1, uint32_t& w2,
                                           uint32_t& w3) {
   if (na.chains) {
     const uint32_t ch = comp / na.comps_per_chain;
@@ -42,13 +67,13 @@ __device__ __forceinline__ void noise_key(const NoiseArgs& na, uint32_t comp, ui
     const uint64_t cyc = (((uint64_t)key.c1 << 32) | key.c0) + (((uint64_t)na.c3 << 32) | na.c2);
     k0 = key.k0;
     k1 = key.k1;
-    w1 = na.sid | ((comp - ch * na.comps_per_chain) << 16);
+    w1 = sid | ((comp - ch * na.comps_per_chain) << 16);
     w2 = (uint32_t)cyc;
     w3 = (uint32_t)(cyc >> 32);
   } else {
     k0 = na.k0;
     k1 = na.k1;
-    w1 = na.sid | (comp << 16);
+    w1 = sid | (comp << 16);
     w2 = na.c2;
     w3 = na.c3;
   }
@@ -76,17 +101,72 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
   return ((double)v + 0.5) * 0x1p-53;
 }
 
+// ln(u) for u in (0, 1], FP64, within a few ulp.  u = m 2^e with m in [sqrt(1/2), sqrt(2));
+// ln m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, summed as the odd Taylor series
+// 2 s (1 + s^2/3 + s^4/5 + ... + s^18/19) (the first omitted term is below 2^-55 of the sum);
+// the quotient comes from the hardware reciprocal refined by two Newton steps and a residual
+// correction; e ln 2 is added with ln 2 split so that e * ln2_hi is exact.
+__device__ __forceinline__ double log_unit(double u, const BoxMullerCoef& c) {
+  int e;
+  double m = frexp(u, &e);  // m in [1/2, 1)
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double f = m - 1.0;  // exact
+  const double d = m + 1.0;
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  double s = f * r;
+  s = fma(fma(-d, s, f), r, s);
+  const double z = s * s;
+  double p = c.lg[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) p = fma(p, z, c.lg[i]);
+  const double s2 = 2.0 * s;
+  const double lm = fma(s2 * z, p, s2);
+  constexpr double LN2_HI = 0x1.62e42fef00000p-1;  // ln 2 with the low 20 bits cleared
+  constexpr double LN2_LO = 0x1.473de6af278edp-34; // ln 2 - LN2_HI
+  return fma((double)e, LN2_HI, fma((double)e, LN2_LO, lm));
+}
+
+// sin(pi t) and cos(pi t) for t in [0, 2], FP64, within a few ulp: t = n/2 + r with n the
+// nearest integer to 2t and |r| <= 1/4 (exact); sin(pi r) and cos(pi r) from their Taylor
+// series to degree 17 and 16 (|pi r| <= pi/4: the first omitted terms are below 2^-56); then
+// the quarter-turn rotation by n.  Coefficients: (-1)^k pi^(2k+1)/(2k+1)! and
+// (-1)^k pi^(2k)/(2k)!, rounded to double.
+__device__ __forceinline__ void sincospi_turns(double t, const BoxMullerCoef& c, double& sn,
+                                               double& cs) {
+  const double n = rint(2.0 * t);
+  const double r = fma(-0.5, n, t);
+  const double z = r * r;
+  double ps = c.sn[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) ps = fma(ps, z, c.sn[i]);
+  const double S = r * ps;
+  double pc = c.cs[0];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) pc = fma(pc, z, c.cs[i]);
+  const double C = fma(pc, z, 1.0);
+  const int q = (int)n & 3;
+  const double a = (q & 1) ? C : S;  // sin(pi (r + n/2))
+  const double b = (q & 1) ? S : C;  // cos(pi (r + n/2))
+  sn = (q & 2) ? -a : a;
+  cs = ((q + 1) & 2) ? -b : b;
+}
+
 // Two normals of call `call` in stream (sid | comp<<16) at the given cycle.
-__device__ __forceinline__ void normal_pair(const NoiseArgs& na, uint32_t comp, uint32_t call,
-                                            double& z0, double& z1) {
+__device__ __forceinline__ void normal_pair(const NoiseArgs& na, uint32_t sid, uint32_t comp,
+                                            uint32_t call, double& z0, double& z1) {
   uint32_t w0 = call, w1, w2, w3, k0, k1;
-  noise_key(na, comp, k0, k1, w1, w2, w3);
+  noise_key(na, sid, comp, k0, k1, w1, w2, w3);
   philox4x32_10(w0, w1, w2, w3, k0, k1);
   double u1 = uniform53(w0, w1);
   double u2 = uniform53(w2, w3);
-  double r = sqrt(-2.0 * log(u1));
+  double r = sqrt(-2.0 * log_unit(u1, na.bm));
   double s, c;
-  sincospi(2.0 * u2, &s, &c);
+  sincospi_turns(2.0 * u2, na.bm, s, c);
   z0 = r * c;
   z1 = r * s;
 }
@@ -96,10 +176,10 @@ __device__ __forceinline__ void normal_pair(const NoiseArgs& na, uint32_t comp, 
 // the tail is not clipped), then the hardware log2 / sin / cos (v_sin_f32 and v_cos_f32 take
 // revolutions, so the angle 2 pi u2 needs no multiplication by pi).  The normals differ from
 // the FP64 ones only by FP32 rounding.
-__device__ __forceinline__ void normal_pair_f32(const NoiseArgs& na, uint32_t comp, uint32_t call,
-                                                float& z0, float& z1) {
+__device__ __forceinline__ void normal_pair_f32(const NoiseArgs& na, uint32_t sid, uint32_t comp,
+                                                uint32_t call, float& z0, float& z1) {
   uint32_t w0 = call, w1, w2, w3, k0, k1;
-  noise_key(na, comp, k0, k1, w1, w2, w3);
+  noise_key(na, sid, comp, k0, k1, w1, w2, w3);
   philox4x32_10(w0, w1, w2, w3, k0, k1);
   const float u1 = (float)uniform53(w0, w1);
   const float u2 = (float)uniform53(w2, w3);
@@ -108,19 +188,26 @@ __device__ __forceinline__ void normal_pair_f32(const NoiseArgs& na, uint32_t co
   z1 = r * __builtin_amdgcn_sinf(u2);
 }
 
-// normals in the storage precision T of the sweep
+// normals in the storage precision T of the sweep, stream sid (default: na.sid)
 template <typename T>
-__device__ __forceinline__ void normal_pair_t(const NoiseArgs& na, uint32_t comp, uint32_t call,
-                                              T& z0, T& z1);
+__device__ __forceinline__ void normal_pair_t(const NoiseArgs& na, uint32_t sid, uint32_t comp,
+                                              uint32_t call, T& z0, T& z1);
 template <>
-__device__ __forceinline__ void normal_pair_t<double>(const NoiseArgs& na, uint32_t comp,
-                                                      uint32_t call, double& z0, double& z1) {
-  normal_pair(na, comp, call, z0, z1);
+__device__ __forceinline__ void normal_pair_t<double>(const NoiseArgs& na, uint32_t sid,
+                                                      uint32_t comp, uint32_t call, double& z0,
+                                                      double& z1) {
+  normal_pair(na, sid, comp, call, z0, z1);
 }
 template <>
-__device__ __forceinline__ void normal_pair_t<float>(const NoiseArgs& na, uint32_t comp,
-                                                     uint32_t call, float& z0, float& z1) {
-  normal_pair_f32(na, comp, call, z0, z1);
+__device__ __forceinline__ void normal_pair_t<float>(const NoiseArgs& na, uint32_t sid,
+                                                     uint32_t comp, uint32_t call, float& z0,
+                                                     float& z1) {
+  normal_pair_f32(na, sid, comp, call, z0, z1);
+}
+template <typename T>
+__device__ __forceinline__ void normal_pair_t(const NoiseArgs& na, uint32_t comp, uint32_t call,
+                                              T& z0, T& z1) {
+  normal_pair_t<T>(na, na.sid, comp, call, z0, z1);
 }
 
 }  // namespace smg

@@ -374,10 +374,8 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
   h.off_norm = take((size_t)2 * nc * sizeof(double));
   {
     const Level& v0 = h.lv[0];
-    const int rows = v0.ny * v0.nz;
-    int nb = (rows + 31) / 32;
-    h.stats_nblk = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
-    h.off_mtab = take((size_t)kMaxModes * (v0.nx + v0.ny + v0.nz) * sizeof(double));
+    h.stats_nblk = (int)((v0.n + STATS_CELLS - 1) / STATS_CELLS);
+    h.off_mtab = take((size_t)kMaxModes * (v0.nx + (size_t)v0.ny * v0.nz) * sizeof(double));
     h.off_spart = take((size_t)nc * h.stats_nblk * (kMaxModes + 1) * sizeof(double));
   }
   h.off_chains = take((size_t)kMaxChains * sizeof(ChainKey));

@@ -62,8 +62,8 @@ struct Hierarchy {
   int nc = 0;                    // unknowns of the coarsest level when it is drawn exactly
   std::vector<double> ainv, w;   // coarsest A_c^-1 and W = L_c^-1 (row-major, n_c x n_c)
   size_t off_ainv = 0, off_w = 0, off_part = 0, off_norm = 0;
-  // statistics of emitted samples: mode factor tables [kMaxModes][nx + ny + nz] and partial
-  // sums [ncomp][stats_nblk][kMaxModes + 1]
+  // statistics of emitted samples: mode tables [kMaxModes][nx + ny*nz] and partial
+  // sums [ncomp][stats_nblk][kMaxModes + 1], stats_nblk = ceil(N / STATS_CELLS)
   size_t off_mtab = 0, off_spart = 0;
   int stats_nblk = 1;
   std::vector<int32_t> modes_loaded;  // modes whose tables are on the device
