@@ -148,9 +148,46 @@ __device__ __forceinline__ T block_lane(const T* __restrict__ X, int sy, int sz,
   T ax = 0, xk = 0, bk = 0, nrm = 0;
   if (active) {
     if (NOISE) nrm = Z[((uint32_t)cz * ny + cy) * nx + cx];
-    ax = gal_apply<T>(X, sy, sz, s1d, zt, nx, ny, nz, cx, cy, cz);
     xk = X[cell];
     bk = Bv[cell];
+  }
+  {
+    // The block's two z-layers reach the same six planes 2bz-2 .. 2bz+3 (clamped at the
+    // walls, where their factors vanish): lane kz reduces planes 3kz .. 3kz+2 and trades them
+    // with its partner lane ^ 4.  Every lane takes part (the shuffles need the partner).
+    const int kz = k >> 2;
+    int xs[5], ys[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      xs[d] = wrapm(cx + d - 2, nx);
+      ys[d] = wrapm(cy + d - 2, ny);
+    }
+    T q0[3], q1[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      int pz = 2 * bz - 2 + 3 * kz + j;
+      pz = pz < 0 ? 0 : (pz >= nz ? nz - 1 : pz);
+      q0[j] = gal_plane<T>(X + (size_t)pz * sz, sy, xs, ys, s1d, q1[j]);
+    }
+    T P0[6], P1[6];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T o0 = __shfl_xor(q0[j], 4, 8), o1 = __shfl_xor(q1[j], 4, 8);
+      P0[j] = kz ? o0 : q0[j];
+      P1[j] = kz ? o1 : q1[j];
+      P0[3 + j] = kz ? q0[j] : o0;
+      P1[3 + j] = kz ? q1[j] : o1;
+    }
+    if (active) {
+      const T* zr = zt + cz * 10;
+      T acc0 = 0, acc1 = 0;
+#pragma unroll
+      for (int dz = 0; dz < 5; ++dz) {
+        acc0 = fma(zr[dz], kz ? P0[dz + 1] : P0[dz], acc0);
+        acc1 = fma(zr[5 + dz], kz ? P1[dz + 1] : P1[dz], acc1);
+      }
+      ax = acc0 + acc1;
+    }
   }
   const T* F = bfac + (size_t)(active ? bz : 0) * 192;
   T inb = 0;

@@ -124,20 +124,38 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
     for (int p = 0; p < PPT; ++p)
       if (loff[p] >= 0) Tl[sz * TP + loff[p]] = stage[sz][p];
   __syncthreads();
-  if (active) {
-    const T* zr = zt + gcz * 10;
+  {
+    // The two z-layers of a block reach the same six staged planes (tile planes 0..5).  Lane
+    // kz computes the in-plane sums of planes 3kz .. 3kz+2 and trades them with its partner
+    // (lane ^ 4, same x and y), so each plane is reduced once per (x, y) pair, not twice.
     const int xs[5] = {tx - 2, tx - 1, tx, tx + 1, tx + 2};
     const int ys[5] = {ty - 2, ty - 1, ty, ty + 1, ty + 2};
-    T ax0 = 0, ax1 = 0;
+    T q0[3], q1[3];
 #pragma unroll
-    for (int dz = 0; dz < 5; ++dz) {
-      T p1;
-      const T p0 = gal_plane<T>(Tl + (tz + dz - 2) * TP, TILE_W, xs, ys, s1d, p1);
-      ax0 = fma(zr[dz], p0, ax0);
-      ax1 = fma(zr[5 + dz], p1, ax1);
+    for (int j = 0; j < 3; ++j) q0[j] = gal_plane<T>(Tl + (3 * kz + j) * TP, TILE_W, xs, ys, s1d, q1[j]);
+    T P0[6], P1[6];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T o0 = __shfl_xor(q0[j], 4, 8), o1 = __shfl_xor(q1[j], 4, 8);
+      P0[j] = kz ? o0 : q0[j];
+      P1[j] = kz ? o1 : q1[j];
+      P0[3 + j] = kz ? q0[j] : o0;
+      P1[3 + j] = kz ? q1[j] : o1;
     }
-    ax = ax0 + ax1;
-    xk = Tl[tz * TP + ty * TILE_W + tx];
+    if (active) {
+      // cell tz = 2 + kz sees planes kz .. kz + 4 as dz = 0 .. 4
+      const T* zr = zt + gcz * 10;
+      T ax0 = 0, ax1 = 0;
+#pragma unroll
+      for (int dz = 0; dz < 5; ++dz) {
+        const T p0 = kz ? P0[dz + 1] : P0[dz];
+        const T p1 = kz ? P1[dz + 1] : P1[dz];
+        ax0 = fma(zr[dz], p0, ax0);
+        ax1 = fma(zr[5 + dz], p1, ax1);
+      }
+      ax = ax0 + ax1;
+      xk = Tl[tz * TP + ty * TILE_W + tx];
+    }
   }
   const T* F = bfac + (size_t)bz * 192;
   T inb = 0;
@@ -159,23 +177,81 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
   if (active) X[cell] = v;
 }
 
-// r = b - A x on a Galerkin level
+// r = b - A x on a Galerkin level, LDS-tiled: a work-group owns GR_X x GR_Y x GR_Z cells and
+// stages the box within 2 of them; a thread takes a z-column of GR_Z cells and forms each of
+// the GR_Z + 4 staged planes' two partial sums once, adding them into every cell of the
+// column they reach (the per-cell order of the additions is that of gal_apply).
+constexpr int GR_X = 16, GR_Y = 16, GR_Z = 4;
+constexpr int GR_SX = GR_X + 4, GR_SY = GR_Y + 4, GR_SZ = GR_Z + 4;
+
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_residual_gal(T* __restrict__ r, const T* __restrict__ xg,
-                                                       const T* __restrict__ bg,
-                                                       const T* __restrict__ s1d,
-                                                       const T* __restrict__ zt, int nx, int ny,
-                                                       int nz, uint32_t N) {
-  const uint32_t comp = blockIdx.y;
-  const uint32_t i = blockIdx.x * TPB + threadIdx.x;
-  if (i >= N) return;
-  const int x = i % nx;
-  const uint32_t row = i / nx;
-  const int y = row % ny;
-  const int z = row / ny;
-  const T ax =
-      gal_apply<T, true>(xg + (size_t)comp * N, nx, nx * ny, s1d, zt, nx, ny, nz, x, y, z);
-  r[(size_t)comp * N + i] = bg[(size_t)comp * N + i] - ax;
+__global__ __launch_bounds__(TPB) void k_residual_gal_tile(T* __restrict__ r,
+                                                            const T* __restrict__ xg,
+                                                            const T* __restrict__ bg,
+                                                            const T* __restrict__ s1d,
+                                                            const T* __restrict__ zt, int nx,
+                                                            int ny, int nz, int ntx) {
+  __shared__ T Xs[GR_SZ * GR_SY * GR_SX];
+  const Blk3 wg = xcd_block();
+  const uint32_t comp = wg.z;
+  const int X0 = (wg.x % ntx) * GR_X, Y0 = (wg.x / ntx) * GR_Y, Z0 = wg.y * GR_Z;
+  const size_t N = (size_t)nx * ny * nz;
+  const T* X = xg + comp * N;
+  const int tid = threadIdx.x;
+  {
+    constexpr int PLANE = GR_SX * GR_SY;
+    constexpr int PPT = (PLANE + TPB - 1) / TPB;
+    int goff[PPT], loff[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      const int pos = tid + p * TPB;
+      const int sx = pos % GR_SX, sy = pos / GR_SX;
+      loff[p] = pos < PLANE ? sy * GR_SX + sx : -1;
+      goff[p] = pos < PLANE ? wrap_near(Y0 - 2 + sy, ny) * nx + wrap_near(X0 - 2 + sx, nx) : 0;
+    }
+    T st[GR_SZ][PPT];
+#pragma unroll
+    for (int sz = 0; sz < GR_SZ; ++sz) {
+      int gz = Z0 - 2 + sz;
+      gz = gz < 0 ? 0 : (gz >= nz ? nz - 1 : gz);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) st[sz][p] = X[(size_t)gz * nx * ny + goff[p]];
+    }
+#pragma unroll
+    for (int sz = 0; sz < GR_SZ; ++sz)
+#pragma unroll
+      for (int p = 0; p < PPT; ++p)
+        if (loff[p] >= 0) Xs[sz * PLANE + loff[p]] = st[sz][p];
+  }
+  __syncthreads();
+  const int lx = tid % GR_X, ly = tid / GR_X;
+  const int cx = X0 + lx, cy = Y0 + ly;
+  const int xs[5] = {lx, lx + 1, lx + 2, lx + 3, lx + 4};
+  const int ys[5] = {ly, ly + 1, ly + 2, ly + 3, ly + 4};
+  const int kmax = nz - Z0 < GR_Z ? nz - Z0 : GR_Z;
+  T acc0[GR_Z], acc1[GR_Z];
+#pragma unroll
+  for (int k = 0; k < GR_Z; ++k) acc0[k] = acc1[k] = T(0);
+#pragma unroll
+  for (int p = 0; p < GR_SZ; ++p) {
+    T p1;
+    const T p0 = gal_plane<T>(Xs + p * (GR_SX * GR_SY), GR_SX, xs, ys, s1d, p1);
+#pragma unroll
+    for (int k = 0; k < GR_Z; ++k) {
+      const int dz = p - k;  // plane offset + 2 seen from cell Z0 + k
+      if (dz < 0 || dz > 4 || k >= kmax) continue;
+      const T* zr = zt + (Z0 + k) * 10;
+      acc0[k] = fma(zr[dz], p0, acc0[k]);
+      acc1[k] = fma(zr[5 + dz], p1, acc1[k]);
+    }
+  }
+  if (cx >= nx || cy >= ny) return;
+#pragma unroll
+  for (int k = 0; k < GR_Z; ++k) {
+    if (k >= kmax) break;
+    const size_t i = comp * N + ((size_t)(Z0 + k) * ny + cy) * nx + cx;
+    r[i] = bg[i] - (acc0[k] + acc1[k]);
+  }
 }
 
 // b_c = P^T r, and x_c = 0 (the coarse iterate of Alg. 3 starts from zero)
@@ -456,9 +532,9 @@ hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const 
 template <typename T>
 hipError_t launch_residual_gal(T* r, const T* x, const T* b, const T* s1d, const T* zt, int nx,
                                int ny, int nz, int ncomp, hipStream_t s) {
-  const uint32_t N = (uint32_t)nx * ny * nz;
-  dim3 grid(blocks_for(N), ncomp);
-  k_residual_gal<T><<<grid, TPB, 0, s>>>(r, x, b, s1d, zt, nx, ny, nz, N);
+  const int ntx = (nx + GR_X - 1) / GR_X, nty = (ny + GR_Y - 1) / GR_Y;
+  dim3 grid(ntx * nty, (nz + GR_Z - 1) / GR_Z, ncomp);
+  k_residual_gal_tile<T><<<grid, TPB, 0, s>>>(r, x, b, s1d, zt, nx, ny, nz, ntx);
   return hipGetLastError();
 }
 
