@@ -423,16 +423,23 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
         }
         __syncthreads();
       }
-      for (int row = tid; row < n; row += BOT_TPB) {
-        double acc = 0.0;
-        for (int jj = 0; jj < n; ++jj)
+      // G lanes per row (a power of two, G <= 32) split the columns, so that every lane has
+      // only n/G loads of the dense factors in its chain; their sums meet by shuffles
+      int G = 1;
+      while (G < 32 && 2 * G * n <= BOT_TPB) G *= 2;
+      const int part = tid % G;
+      for (int row = tid / G; row < n; row += BOT_TPB / G) {
+        double acc = 0.0, an = 0.0;
+        for (int jj = part; jj < n; jj += G) {
           acc = fma(a.ainv[(size_t)jj * n + row], (double)bi[jj], acc);
-        if (NOISE) {
-          double an = 0.0;
-          for (int jj = row; jj < n; ++jj) an = fma(a.w[(size_t)jj * n + row], (double)ri[jj], an);
-          acc = fma(na.sqkT, an, acc);
+          if (NOISE && jj >= row) an = fma(a.w[(size_t)jj * n + row], (double)ri[jj], an);
         }
-        xi[row] = (T)acc;
+        for (int off = G / 2; off >= 1; off >>= 1) {
+          acc += __shfl_xor(acc, off, G);
+          if (NOISE) an += __shfl_xor(an, off, G);
+        }
+        if (NOISE) acc = fma(na.sqkT, an, acc);
+        if (part == 0) xi[row] = (T)acc;
       }
       __syncthreads();
       last = i;
