@@ -230,7 +230,11 @@ int prolong_add(Run& r, int l) {
   const T* e = Fld<T>::x(h.lv[l + 1]);
   if (v.kind == KIND_POINT) {
     T* xr = Fld<T>::x(v);
-    SMG_HIP(launch_prolong0<T>(xr, xr + half_field(h), e, v.nx, v.ny, v.nz, nc, r.s));
+    // The first post-sweep pass draws every colour-1 site afresh from its colour-0 neighbours
+    // (a heat-bath update never reads the value it replaces), so with post-sweeps only the
+    // colour-0 sites need the correction.
+    const int colours = h.prm.nu2 > 0 ? 1 : 3;
+    SMG_HIP(launch_prolong0<T>(xr, xr + half_field(h), e, v.nx, v.ny, v.nz, nc, colours, r.s));
   } else {
     SMG_HIP(launch_prolong<T>(Fld<T>::x(v), e, v.nx, v.ny, v.nz, nc, r.s));
   }
@@ -1091,7 +1095,7 @@ int smg_debug_prolong_add(smg_hierarchy* hh, int32_t level, void* x, const void*
   if (v.kind == KIND_POINT) {
     SMG_TRY(import_level0(h, v.x, (const double*)x, s));
     SMG_HIP(launch_prolong0<double>(v.x, v.x + half_field(h), (const double*)e_coarse, v.nx, v.ny,
-                                    v.nz, nc, s));
+                                    v.nz, nc, 3, s));
     SMG_TRY(export_level0(h, x, 0, v.x, s));
   } else {
     SMG_HIP(launch_prolong<double>((double*)x, (const double*)e_coarse, v.nx, v.ny, v.nz, nc, s));

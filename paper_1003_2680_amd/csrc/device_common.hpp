@@ -126,6 +126,21 @@ __device__ __forceinline__ T gal_apply(const T* __restrict__ X, int sy, int sz, 
   return acc0 + acc1;
 }
 
+// The two z-layers of a 2x2x2 block see six Galerkin planes between them; lane kz of a block
+// reduces planes 3kz .. 3kz+2 (q) and receives its partner's three (o).  The cell's own
+// window of five planes (dz = 0 .. 4, i.e. planes kz .. kz+4) is then one select per entry
+// between two registers, never an indexed access into a private array (which would be
+// placed in scratch memory).
+template <typename T>
+__device__ __forceinline__ void plane_window(int kz, const T (&q)[3], const T (&o)[3],
+                                             T (&w)[5]) {
+  w[0] = kz ? o[1] : q[0];
+  w[1] = kz ? o[2] : q[1];
+  w[2] = kz ? q[0] : q[2];
+  w[3] = kz ? q[1] : o[0];
+  w[4] = kz ? q[2] : o[1];
+}
+
 // Block heat-bath lane: lane k (0..7) of 2x2x2 block (bx,by,bz) returns its new value
 //   x_B[k] = sum_j A_BB^-1[k][j] rhs_j + sqrt(kT) sum_j L_BB^-T[k][j] n_j,
 //   rhs_j  = b_j - (A x)_j + sum_i A_BB[j][i] x_B[i]   (= b_j - A_{j,rest} x_rest).
@@ -169,22 +184,21 @@ __device__ __forceinline__ T block_lane(const T* __restrict__ X, int sy, int sz,
       pz = pz < 0 ? 0 : (pz >= nz ? nz - 1 : pz);
       q0[j] = gal_plane<T>(X + (size_t)pz * sz, sy, xs, ys, s1d, q1[j]);
     }
-    T P0[6], P1[6];
+    T o0[3], o1[3], w0[5], w1[5];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const T o0 = __shfl_xor(q0[j], 4, 8), o1 = __shfl_xor(q1[j], 4, 8);
-      P0[j] = kz ? o0 : q0[j];
-      P1[j] = kz ? o1 : q1[j];
-      P0[3 + j] = kz ? q0[j] : o0;
-      P1[3 + j] = kz ? q1[j] : o1;
+      o0[j] = __shfl_xor(q0[j], 4, 8);
+      o1[j] = __shfl_xor(q1[j], 4, 8);
     }
+    plane_window(kz, q0, o0, w0);
+    plane_window(kz, q1, o1, w1);
     if (active) {
       const T* zr = zt + cz * 10;
       T acc0 = 0, acc1 = 0;
 #pragma unroll
       for (int dz = 0; dz < 5; ++dz) {
-        acc0 = fma(zr[dz], kz ? P0[dz + 1] : P0[dz], acc0);
-        acc1 = fma(zr[5 + dz], kz ? P1[dz + 1] : P1[dz], acc1);
+        acc0 = fma(zr[dz], w0[dz], acc0);
+        acc1 = fma(zr[5 + dz], w1[dz], acc1);
       }
       ax = acc0 + acc1;
     }

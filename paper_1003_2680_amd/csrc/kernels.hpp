@@ -87,9 +87,10 @@ template <typename T>
 hipError_t launch_restrict_residual0(T* bc, T* xc, const T* xr, const T* xb, const T* br,
                                      const T* bb, int nx, int ny, int nz, int ncomp, double h,
                                      hipStream_t s);
+// colours: bit c set = add P e to the sites of colour c
 template <typename T>
 hipError_t launch_prolong0(T* xr, T* xb, const T* e, int nxf, int nyf, int nzf, int ncomp,
-                           hipStream_t s);
+                           int colours, hipStream_t s);
 template <typename T>
 hipError_t launch_residual_gal(T* r, const T* x, const T* b, const T* s1d, const T* zt, int nx,
                                int ny, int nz, int ncomp, hipStream_t s);

@@ -171,104 +171,166 @@ __global__ __launch_bounds__(TPB) void k_residual0(T* __restrict__ r, const T* _
 }
 
 // Fused residual and restriction from level 0: b_c = P^T (b - A x) without writing r.
-// A work-group owns RX x RY x RZ coarse cells.  Their restriction windows cover the fine box
-// [2X0-1, 2X0+2RX+1) (x, y) and [2Z0-1, 2Z0+2RZ+1) (z); the residual there needs x one cell
-// further out.  x is staged from the split storage into LDS (all loads in flight first), the
-// residual of the window box goes to LDS, and each coarse cell sums its 4x4x4 window with the
-// weights (1/4, 3/4, 3/4, 1/4) per axis (1/2 for a fine cell next to a wall).  Also zeroes the
+// A work-group owns an RR_X x RR_Y column of coarse cells over up to RR_Z coarse layers and
+// marches up through the fine planes of their restriction windows, [2Z0-1, 2Z0+2RZ].  For
+// each fine plane f it stages x plane f+1 into a ring of four LDS planes (the global loads
+// of the planes two steps ahead are in flight meanwhile), forms the residual of plane f over
+// the 18 x 18 window of the column, and every coarse cell of the column takes that plane's
+// 4x4 window sum (weights 1/4, 3/4, 3/4, 1/4 per axis; 1/2 for a fine cell next to a wall)
+// into the running sums of the two coarse layers the plane belongs to: four lanes per coarse
+// cell, one window row each, joined by shuffles.  Each x plane is loaded once per column and
+// each residual plane formed once, instead of once per coarse layer pair.  Also zeroes the
 // coarse iterate when xc is not null.
-constexpr int RR_X = 8, RR_Y = 8, RR_Z = 2;
-constexpr int RR_FX = 2 * RR_X + 2, RR_FY = 2 * RR_Y + 2, RR_FZ = 2 * RR_Z + 2;  // residual box
-constexpr int RR_SX = RR_FX + 2, RR_SY = RR_FY + 2, RR_SZ = RR_FZ + 2;           // x box
+constexpr int RR_X = 8, RR_Y = 8, RR_Z = 8;
+constexpr int RR_FX = 2 * RR_X + 2, RR_FY = 2 * RR_Y + 2;  // residual window of a plane
+constexpr int RR_SX = RR_FX + 2, RR_SY = RR_FY + 2;        // x box of a plane
+constexpr int RR_XP = RR_SX * RR_SY;                       // x plane in LDS
+constexpr int RR_RP = RR_FX * RR_FY;                       // residual plane in LDS
+constexpr int RR_PPT = (RR_XP + TPB - 1) / TPB;            // x positions per thread
+constexpr int RR_RPT = (RR_RP + TPB - 1) / TPB;            // residual positions per thread
+static_assert(RR_X * RR_Y * 4 == TPB, "four lanes per coarse cell of the column");
 
 template <typename T, bool HAS_B>
 __global__ __launch_bounds__(TPB) void k_restrict_residual0(
     T* __restrict__ bc, T* __restrict__ xc, const T* __restrict__ xr, const T* __restrict__ xb,
     const T* __restrict__ br, const T* __restrict__ bb, int nx, int ny, int nz, int ntx,
     T inv_h2) {
-  __shared__ T Xs[RR_SZ * RR_SY * RR_SX];
-  __shared__ T Rs[RR_FZ * RR_FY * RR_FX];
+  __shared__ T Xs[4 * RR_XP];
+  __shared__ T Rs[2 * RR_RP];
   const Blk3 wg = xcd_block();
   const uint32_t comp = wg.z;
   const int nxc = nx >> 1, nyc = ny >> 1, nzc = nz >> 1;
   const int X0 = (wg.x % ntx) * RR_X, Y0 = (wg.x / ntx) * RR_Y;
   const int Z0 = wg.y * RR_Z;
+  const int zc = min(RR_Z, nzc - Z0);
   const int nh = nx >> 1;
   const size_t cb = (size_t)comp * ((size_t)(nx >> 1) * ny * nz);
   const int tid = threadIdx.x;
-  // ---- stage x: box origin (2X0-2, 2Y0-2, 2Z0-2); planes outside the grid are never read
-  {
-    constexpr int PLANE = RR_SX * RR_SY;
-    constexpr int PPT = (PLANE + TPB - 1) / TPB;
-    int gxs[PPT], gys[PPT], loff[PPT];
+  // x positions this thread stages (box origin 2X0-2, 2Y0-2) and residual positions it forms
+  // (window origin 2X0-1, 2Y0-1)
+  int gxs[RR_PPT], gys[RR_PPT], xoff[RR_PPT];
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      const int pos = tid + p * TPB;
-      const int sx = pos % RR_SX, sy = pos / RR_SX;
-      loff[p] = pos < PLANE ? sy * RR_SX + sx : -1;
-      gxs[p] = wrap_near(2 * X0 - 2 + sx, nx);
-      gys[p] = pos < PLANE ? wrap_near(2 * Y0 - 2 + sy, ny) : 0;
-    }
-    T st[RR_SZ][PPT];
-#pragma unroll
-    for (int sz = 0; sz < RR_SZ; ++sz) {
-      int gz = 2 * Z0 - 2 + sz;
-      gz = gz < 0 ? 0 : (gz >= nz ? nz - 1 : gz);
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) st[sz][p] = split_at(xr, xb, cb, gxs[p], gys[p], gz, nh, ny);
-    }
-#pragma unroll
-    for (int sz = 0; sz < RR_SZ; ++sz)
-#pragma unroll
-      for (int p = 0; p < PPT; ++p)
-        if (loff[p] >= 0) Xs[sz * (RR_SX * RR_SY) + loff[p]] = st[sz][p];
+  for (int p = 0; p < RR_PPT; ++p) {
+    const int pos = tid + p * TPB;
+    const int sx = pos % RR_SX, sy = pos / RR_SX;
+    xoff[p] = pos < RR_XP ? pos : -1;
+    gxs[p] = wrap_near(2 * X0 - 2 + sx, nx);
+    gys[p] = pos < RR_XP ? wrap_near(2 * Y0 - 2 + sy, ny) : 0;
   }
-  __syncthreads();
-  // ---- residual of the window box: fine cell (2X0-1+rx, 2Y0-1+ry, 2Z0-1+rz)
-  for (int q = tid; q < RR_FX * RR_FY * RR_FZ; q += TPB) {
-    const int rx = q % RR_FX, t2 = q / RR_FX, ry = t2 % RR_FY, rz = t2 / RR_FY;
-    const int fz = 2 * Z0 - 1 + rz;
-    T rv = T(0);
-    if (fz >= 0 && fz < nz) {
-      const T* c = Xs + (rz + 1) * (RR_SX * RR_SY) + (ry + 1) * RR_SX + (rx + 1);
-      T sn = (c[-1] + c[1]) + (c[-RR_SX] + c[RR_SX]);
-      int nw = 0;
-      if (fz + 1 < nz) sn += c[RR_SX * RR_SY]; else ++nw;
-      if (fz > 0) sn += c[-RR_SX * RR_SY]; else ++nw;
-      rv = -(T(6 + nw) * c[0] - sn) * inv_h2;
-      if (HAS_B) {
-        const int fx = wrap_near(2 * X0 - 1 + rx, nx), fy = wrap_near(2 * Y0 - 1 + ry, ny);
-        rv += split_at(br, bb, cb, fx, fy, fz, nh, ny);
+  int roff[RR_RPT], rxo[RR_RPT];
+#pragma unroll
+  for (int p = 0; p < RR_RPT; ++p) {
+    const int q = tid + p * TPB;
+    const int rx = q % RR_FX, ry = q / RR_FX;
+    roff[p] = q < RR_RP ? q : -1;
+    rxo[p] = (ry + 1) * RR_SX + rx + 1;  // centre of the 7-point star in an x plane
+  }
+  const int f0 = 2 * Z0 - 1, f1 = 2 * (Z0 + zc);  // residual planes of the column
+  auto load_plane = [&](T (&reg)[RR_PPT], int g) {
+    g = g < 0 ? 0 : (g >= nz ? nz - 1 : g);  // planes beyond the walls are never read
+#pragma unroll
+    for (int p = 0; p < RR_PPT; ++p) reg[p] = split_at(xr, xb, cb, gxs[p], gys[p], g, nh, ny);
+  };
+  auto store_plane = [&](const T (&reg)[RR_PPT], int g) {
+    T* P = Xs + (g & 3) * RR_XP;
+#pragma unroll
+    for (int p = 0; p < RR_PPT; ++p)
+      if (xoff[p] >= 0) P[xoff[p]] = reg[p];
+  };
+  auto load_b = [&](T (&reg)[RR_RPT], int f) {
+    const int g = f < 0 ? 0 : (f >= nz ? nz - 1 : f);
+#pragma unroll
+    for (int p = 0; p < RR_RPT; ++p) {
+      const int q = roff[p] < 0 ? 0 : roff[p];
+      const int fx = wrap_near(2 * X0 - 1 + q % RR_FX, nx);
+      const int fy = wrap_near(2 * Y0 - 1 + q / RR_FX, ny);
+      reg[p] = HAS_B ? split_at(br, bb, cb, fx, fy, g, nh, ny) : T(0);
+    }
+  };
+  // this lane's coarse cell and window row
+  const int wb = tid & 3, cell = tid >> 2;
+  const int lx = cell % RR_X, ly = cell / RR_X;
+  const int X = X0 + lx, Y = Y0 + ly;
+  const bool owner = wb == 0 && X < nxc && Y < nyc;
+  T acc0 = 0, acc1 = 0;  // running sums of the even and the odd coarse layer
+  // one fine plane f: stage x plane f+1 (held in `cur`), start loading plane f+3 into `cur`
+  // once stored, form the residual of plane f, and take its window sums
+  auto step = [&](int f, T (&cur)[RR_PPT], T (&bcur)[RR_RPT]) {
+    store_plane(cur, f + 1);
+    if (f + 3 <= f1 + 1) load_plane(cur, f + 3);
+    __syncthreads();
+    T* R = Rs + (f & 1) * RR_RP;
+    if (f >= 0 && f < nz) {
+      const T* Pm = Xs + ((f - 1) & 3) * RR_XP;
+      const T* P0 = Xs + (f & 3) * RR_XP;
+      const T* Pp = Xs + ((f + 1) & 3) * RR_XP;
+#pragma unroll
+      for (int p = 0; p < RR_RPT; ++p) {
+        if (roff[p] < 0) continue;
+        const T* c = P0 + rxo[p];
+        T sn = (c[-1] + c[1]) + (c[-RR_SX] + c[RR_SX]);
+        int nw = 0;
+        if (f + 1 < nz) sn += Pp[rxo[p]]; else ++nw;
+        if (f > 0) sn += Pm[rxo[p]]; else ++nw;
+        T rv = -(T(6 + nw) * c[0] - sn) * inv_h2;
+        if (HAS_B) rv += bcur[p];
+        R[roff[p]] = rv;
       }
     }
-    Rs[q] = rv;
-  }
-  __syncthreads();
-  // ---- restriction of the window of each owned coarse cell
-  if (tid < RR_X * RR_Y * RR_Z) {
-    const int lx = tid % RR_X, ly = (tid / RR_X) % RR_Y, lz = tid / (RR_X * RR_Y);
-    const int X = X0 + lx, Y = Y0 + ly, Z = Z0 + lz;
-    if (X < nxc && Y < nyc && Z < nzc) {
-      T acc = 0;
+    if (HAS_B && f + 2 <= f1) load_b(bcur, f + 2);
+    __syncthreads();
+    if (f < 0 || f >= nz) return;
+    const T* Rr = R + (2 * ly + wb) * RR_FX + 2 * lx;
+    T s = 0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int zf = 2 * Z - 1 + c;
-        if (zf < 0 || zf >= nz) continue;
-        T wz = pw<T>(c);
-        if ((Z == 0 && zf == 0) || (Z == nzc - 1 && zf == nz - 1)) wz = T(0.5);
+    for (int a = 0; a < 4; ++a) s = fma(pw<T>(a), Rr[a], s);
+    s *= pw<T>(wb);
+    s += __shfl_xor(s, 1, 4);
+    s += __shfl_xor(s, 2, 4);
+    // plane f is window plane c1 of coarse layer Z1 and plane c1 + 2 of layer Z1 - 1
+    const int Z1 = (f + 1) >> 1, c1 = f - (2 * Z1 - 1);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const T* Rr = Rs + ((2 * lz + c) * RR_FY + (2 * ly + b)) * RR_FX + 2 * lx;
-          T sacc = 0;
-#pragma unroll
-          for (int a = 0; a < 4; ++a) sacc = fma(pw<T>(a), Rr[a], sacc);
-          acc = fma(wz * pw<T>(b), sacc, acc);
-        }
-      }
+    for (int k = 0; k < 2; ++k) {
+      const int Z = Z1 - k, c = c1 + 2 * k;
+      if (Z < Z0 || Z >= Z0 + zc) continue;
+      T wz = pw<T>(c);
+      if ((Z == 0 && f == 0) || (Z == nzc - 1 && f == nz - 1)) wz = T(0.5);
+      if (Z & 1) acc1 = fma(wz, s, acc1);
+      else acc0 = fma(wz, s, acc0);
+    }
+  };
+  // the layer Z1 - 1 is complete after its window plane 3, i.e. after an even plane f
+  auto finish = [&](int f) {
+    if (f & 1) return;
+    const int Z = (f >> 1) - 1;
+    if (Z < Z0 || Z >= Z0 + zc) return;
+    if (owner) {
       const size_t I = (size_t)comp * nxc * nyc * nzc + ((size_t)Z * nyc + Y) * nxc + X;
-      bc[I] = acc;
+      bc[I] = (Z & 1) ? acc1 : acc0;
       if (xc) xc[I] = T(0);
     }
+    if (Z & 1) acc1 = T(0);
+    else acc0 = T(0);
+  };
+  // prologue: planes f0-1 and f0 in the ring, f0+1 and f0+2 in registers
+  T ra[RR_PPT], rb[RR_PPT], ba[RR_RPT], bbn[RR_RPT];
+  load_plane(ra, f0 - 1);
+  load_plane(rb, f0);
+  if (HAS_B) {
+    load_b(ba, f0);
+    load_b(bbn, f0 + 1);
+  }
+  store_plane(ra, f0 - 1);
+  store_plane(rb, f0);
+  load_plane(ra, f0 + 1);
+  load_plane(rb, f0 + 2);
+  // the column has 2 zc + 2 planes: an even count, taken two at a time so the two register
+  // sets keep their roles
+  for (int f = f0; f <= f1; f += 2) {
+    step(f, ra, ba);
+    finish(f);
+    step(f + 1, rb, bbn);
+    finish(f + 1);
   }
 }
 
@@ -329,9 +391,10 @@ __global__ __launch_bounds__(TPB) void k_refine_update(double* __restrict__ x64,
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_prolong0(T* __restrict__ xr, T* __restrict__ xb,
                                                    const T* __restrict__ e, int nxf, int nyf,
-                                                   int nzf, uint32_t nsite, uint32_t Nc) {
+                                                   int nzf, uint32_t nsite, uint32_t Nc,
+                                                   int cfirst) {
   const uint32_t comp = blockIdx.y;
-  const int colour = blockIdx.z;
+  const int colour = cfirst + blockIdx.z;
   const uint32_t p = blockIdx.x * TPB + threadIdx.x;
   if (p >= nsite) return;
   const int nh = nxf >> 1;
@@ -447,11 +510,13 @@ hipError_t launch_restrict_residual0(T* bc, T* xc, const T* xr, const T* xb, con
 
 template <typename T>
 hipError_t launch_prolong0(T* xr, T* xb, const T* e, int nxf, int nyf, int nzf, int ncomp,
-                           hipStream_t s) {
+                           int colours, hipStream_t s) {
   const uint32_t nsite = (uint32_t)(nxf / 2) * nyf * nzf;
   const uint32_t Nc = (uint32_t)(nxf / 2) * (nyf / 2) * (nzf / 2);
-  dim3 grid(blocks_for(nsite), ncomp, 2);
-  k_prolong0<T><<<grid, TPB, 0, s>>>(xr, xb, e, nxf, nyf, nzf, nsite, Nc);
+  colours &= 3;
+  if (colours == 0) return hipSuccess;
+  dim3 grid(blocks_for(nsite), ncomp, colours == 3 ? 2 : 1);
+  k_prolong0<T><<<grid, TPB, 0, s>>>(xr, xb, e, nxf, nyf, nzf, nsite, Nc, colours == 2 ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -467,7 +532,7 @@ template hipError_t launch_residual0<double>(double*, const double*, const doubl
 template hipError_t launch_residual0<float>(float*, const float*, const float*, const float*,
                                             const float*, int, int, int, int, double, hipStream_t);
 template hipError_t launch_prolong0<double>(double*, double*, const double*, int, int, int, int,
-                                            hipStream_t);
+                                            int, hipStream_t);
 template hipError_t launch_restrict_residual0<double>(double*, double*, const double*,
                                                       const double*, const double*,
                                                       const double*, int, int, int, int, double,
@@ -476,7 +541,7 @@ template hipError_t launch_restrict_residual0<float>(float*, float*, const float
                                                      const float*, const float*, int, int, int,
                                                      int, double, hipStream_t);
 template hipError_t launch_prolong0<float>(float*, float*, const float*, int, int, int, int,
-                                           hipStream_t);
+                                            int, hipStream_t);
 
 hipError_t launch_refine_residual(float* r32, const double* x64, const double* b64, int nx,
                                   int ny, int nz, int ncomp, int ncomp_stride, double h,

@@ -133,25 +133,22 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
     T q0[3], q1[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) q0[j] = gal_plane<T>(Tl + (3 * kz + j) * TP, TILE_W, xs, ys, s1d, q1[j]);
-    T P0[6], P1[6];
+    T o0[3], o1[3], w0[5], w1[5];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const T o0 = __shfl_xor(q0[j], 4, 8), o1 = __shfl_xor(q1[j], 4, 8);
-      P0[j] = kz ? o0 : q0[j];
-      P1[j] = kz ? o1 : q1[j];
-      P0[3 + j] = kz ? q0[j] : o0;
-      P1[3 + j] = kz ? q1[j] : o1;
+      o0[j] = __shfl_xor(q0[j], 4, 8);
+      o1[j] = __shfl_xor(q1[j], 4, 8);
     }
+    plane_window(kz, q0, o0, w0);
+    plane_window(kz, q1, o1, w1);
     if (active) {
       // cell tz = 2 + kz sees planes kz .. kz + 4 as dz = 0 .. 4
       const T* zr = zt + gcz * 10;
       T ax0 = 0, ax1 = 0;
 #pragma unroll
       for (int dz = 0; dz < 5; ++dz) {
-        const T p0 = kz ? P0[dz + 1] : P0[dz];
-        const T p1 = kz ? P1[dz + 1] : P1[dz];
-        ax0 = fma(zr[dz], p0, ax0);
-        ax1 = fma(zr[5 + dz], p1, ax1);
+        ax0 = fma(zr[dz], w0[dz], ax0);
+        ax1 = fma(zr[5 + dz], w1[dz], ax1);
       }
       ax = ax0 + ax1;
       xk = Tl[tz * TP + ty * TILE_W + tx];

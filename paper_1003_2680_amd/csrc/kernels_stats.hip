@@ -23,7 +23,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int KB, bool SPLIT, bool MOM, typename TO, bool UROW>
+template <int KB, bool SPLIT, bool MOM, typename TO, bool UROW, bool XSAME>
 __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   const uint32_t comp = blockIdx.y;
   const int lane = threadIdx.x & 63;
@@ -51,9 +51,12 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   const cptr trow = (cptr)a.trow;
   const uint32_t rows = (uint32_t)ny * nz;
   const uint32_t base = blockIdx.x * STATS_CELLS;
-  // all loads of this thread's cells first
+  // all loads of this thread's cells first.  When a wavefront lies in one row (UROW) the +x
+  // neighbour of a cell is the next lane's value and only the wave's last lane loads it; when
+  // the thread's cells are whole rows apart (XSAME) they share their x, hence the x factors.
   double v[STATS_CPT], nb[STATS_CPT][3];
   int cx[STATS_CPT], cy[STATS_CPT], cz[STATS_CPT];
+  double txs[KB > 0 ? KB : 1];
 #pragma unroll
   for (int c = 0; c < STATS_CPT; ++c) {
     const uint32_t cell = base + c * TPB + threadIdx.x;
@@ -68,9 +71,21 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
     cz[c] = in ? z : -1;
     v[c] = in ? load(x, y, z) : 0.0;
     if (KB > 0) {
-      nb[c][0] = in ? load(x + 1 == nx ? 0 : x + 1, y, z) : 0.0;
+      const int xp = x + 1 == nx ? 0 : x + 1;
+      nb[c][0] = (in && (!UROW || lane == 63)) ? load(xp, y, z) : 0.0;
       nb[c][1] = in ? load(x, y + 1 == ny ? 0 : y + 1, z) : 0.0;
       nb[c][2] = (in && z + 1 < nz) ? load(x, y, z + 1) : 0.0;
+    }
+  }
+  if (KB > 0 && XSAME) {
+#pragma unroll
+    for (int q = 0; q < KB; ++q) txs[q] = q < K ? tx[q * nx + cx[0]] : 0.0;
+  }
+  if (KB > 0 && UROW) {
+#pragma unroll
+    for (int c = 0; c < STATS_CPT; ++c) {
+      const double nxt = __shfl_down(v[c], 1, 64);
+      if (lane != 63) nb[c][0] = nxt;
     }
   }
   double acc[KB > 0 ? KB : 1];
@@ -93,7 +108,8 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
       if (UROW) row = __builtin_amdgcn_readfirstlane(row);  // the wavefront lies in one row
 #pragma unroll
       for (int q = 0; q < KB; ++q)
-        if (q < K) acc[q] = fma(tx[q * nx + cx[c]] * trow[q * rows + row], x0, acc[q]);
+        if (q < K)
+          acc[q] = fma((XSAME ? txs[q] : tx[q * nx + cx[c]]) * trow[q * rows + row], x0, acc[q]);
       // faces +x, +y (periodic) and +z (interior), plus the wall faces (ghost = -v)
       const double d1 = x0 - nb[c][0];
       const double d2 = x0 - nb[c][1];
@@ -142,17 +158,20 @@ __global__ __launch_bounds__(TPB) void k_stats_final(double* __restrict__ obs,
   if (threadIdx.x == 0) obs[comp * K1 + q] = q == K1 - 1 ? sh[0] * escale : sh[0];
 }
 
-template <int KB, bool SPLIT, bool MOM, bool UROW>
+template <int KB, bool SPLIT, bool MOM, bool UROW, bool XSAME>
 void launch_stats_u(const StatsArgs& a, int ncomp, hipStream_t s) {
   dim3 grid(a.nblk, ncomp);
-  if (a.out && a.out_f32) k_stats<KB, SPLIT, MOM, float, UROW><<<grid, TPB, 0, s>>>(a);
-  else k_stats<KB, SPLIT, MOM, double, UROW><<<grid, TPB, 0, s>>>(a);
+  if (a.out && a.out_f32) k_stats<KB, SPLIT, MOM, float, UROW, XSAME><<<grid, TPB, 0, s>>>(a);
+  else k_stats<KB, SPLIT, MOM, double, UROW, XSAME><<<grid, TPB, 0, s>>>(a);
 }
 
 template <int KB, bool SPLIT, bool MOM>
 void launch_stats_k(const StatsArgs& a, int ncomp, hipStream_t s) {
-  if (a.nx % 64 == 0) launch_stats_u<KB, SPLIT, MOM, true>(a, ncomp, s);
-  else launch_stats_u<KB, SPLIT, MOM, false>(a, ncomp, s);
+  // rows of 64, 128 or 256 cells: a wave lies in one row and a thread's cells are whole rows
+  // apart
+  if (a.nx % 64 == 0 && TPB % a.nx == 0) launch_stats_u<KB, SPLIT, MOM, true, true>(a, ncomp, s);
+  else if (a.nx % 64 == 0) launch_stats_u<KB, SPLIT, MOM, true, false>(a, ncomp, s);
+  else launch_stats_u<KB, SPLIT, MOM, false, false>(a, ncomp, s);
 }
 
 template <int KB>

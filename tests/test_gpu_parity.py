@@ -124,6 +124,29 @@ def test_transfers(dims, levels):
             assert _relerr(got[c], x[c] + L.P @ e[c]) <= RTOL
 
 
+# level-0 residual + restriction on grids whose coarse columns and coarse layers are ragged
+# (partial tiles in x and y, several z-runs per column with a short last one)
+@pytest.mark.parametrize("dims,levels", [((48, 24, 40), 3), ((20, 12, 36), 2)])
+def test_restrict_residual0_ragged(dims, levels):
+    _announce("restrict_residual0 %s L=%d" % (dims, levels))
+    ncomp = 2
+    H = _hier(*dims, ncomp=ncomp, levels=levels, coarsest_max=2048)
+    mg = StochasticMG(*dims, levels=levels, coarsest_max=2048)
+    L, C = mg.levels[0], mg.levels[1]
+    shape = (ncomp,) + tuple(reversed(L.dims))
+    cshape = (ncomp,) + tuple(reversed(C.dims))
+    x = uniform_field((ncomp, L.n), 41)
+    b = gaussian_field((ncomp, L.n), 42)
+    for use_b in (False, True):
+        bc = torch.zeros(cshape, dtype=torch.float64, device="cuda")
+        H.debug_restrict_residual(0, _dev(x.reshape(shape)),
+                                  _dev(b.reshape(shape)) if use_b else None, bc)
+        got = _host(bc).reshape(ncomp, C.n)
+        for c in range(ncomp):
+            ref = L.P.T @ ((b[c] if use_b else 0.0) - L.A @ x[c])
+            assert _relerr(got[c], ref) <= RTOL
+
+
 @pytest.mark.parametrize("dims,levels", [((16, 16, 16), 3), ((8, 8, 8), 1), ((16, 16, 8), 3),
                                          ((32, 32, 16), 3)])
 def test_coarsest(dims, levels):

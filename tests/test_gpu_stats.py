@@ -32,18 +32,21 @@ def _announce(msg):
     print("[gpu-case] " + msg, flush=True)
 
 
-@pytest.mark.parametrize("dims,ncomp,levels,K,precision", [
-    ((16, 16, 8), 2, 3, 8, "fp64"), ((12, 8, 6), 1, 2, 20, "fp64"),
-    ((4, 4, 4), 2, 1, 5, "fp64"), ((64, 32, 16), 1, 4, 32, "fp64"),
-    ((16, 16, 8), 2, 3, 3, "fp32_refined"), ((128, 8, 4), 1, 2, 0, "fp64")])
-def test_stats_parity(dims, ncomp, levels, K, precision):
+# rows of 64/128 cells (a wave per row, shared x factors), of 192 cells (a wave per row, x
+# factors per cell) and of fewer than 64 cells
+@pytest.mark.parametrize("dims,ncomp,levels,K,precision,cmax", [
+    ((16, 16, 8), 2, 3, 8, "fp64", 64), ((12, 8, 6), 1, 2, 20, "fp64", 64),
+    ((4, 4, 4), 2, 1, 5, "fp64", 64), ((64, 32, 16), 1, 4, 32, "fp64", 64),
+    ((16, 16, 8), 2, 3, 3, "fp32_refined", 64), ((128, 8, 4), 1, 2, 0, "fp64", 64),
+    ((128, 8, 4), 2, 2, 8, "fp64", 512), ((192, 8, 8), 1, 3, 8, "fp64", 512)])
+def test_stats_parity(dims, ncomp, levels, K, precision, cmax):
     _announce("stats %s ncomp=%d L=%d K=%d %s" % (dims, ncomp, levels, K, precision))
     from paper_1003_2680_amd.api import lowest_modes
     nx, ny, nz = dims
     modes = lowest_modes(nx, ny, nz, K)
     assert modes == ob.lowest_modes(nx, ny, nz, K)
     n = 5
-    kw = dict(ncomp=ncomp, kT=1.4, levels=levels, coarsest_max=64)
+    kw = dict(ncomp=ncomp, kT=1.4, levels=levels, coarsest_max=cmax)
     H = _hier(*dims, precision=precision, **kw)
     out = torch.empty((n,) + H.shape, dtype=torch.float64, device="cuda")
     mom = torch.zeros((2,) + H.shape, dtype=torch.float64, device="cuda")
@@ -54,7 +57,7 @@ def test_stats_parity(dims, ncomp, levels, K, precision):
     assert np.array_equal(_host(ref_out), got_out)
     # observables of the emitted samples (the GPU samples themselves match the oracle chain to
     # 1e-12 in FP64 -- see the chain parity tests; here the statistics are checked)
-    mg = StochasticMG(*dims, kT=1.4, levels=levels, coarsest_max=64)
+    mg = StochasticMG(*dims, kT=1.4, levels=levels, coarsest_max=cmax)
     if precision == "fp64":
         ref, _ = mg.sample_chain(n, 17, ncomp=ncomp)
         assert np.max(np.abs(got_out.reshape(ref.shape) - ref)) <= 1e-12 * np.max(np.abs(ref))
