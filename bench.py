@@ -4,8 +4,9 @@ Workload: a 128x128x128 cell-centred grid (h = 1, kT = 1), periodic in x and y w
 walls on the z faces; a 3-component velocity field (three decoupled scalar chains with the
 same wall-bounded Laplacian); the 6-level stochastic V(2,2) cycle in FP64 (red-black heat
 bath on the fine level, 2x2x2 block heat bath on the Galerkin levels, exact Cholesky draw on
-the 4^3 coarsest level).  The chains of seeds 0..CHAINS-1 are batched into every launch (one
-hierarchy carrying CHAINS x 3 components; each chain draws exactly what it draws alone).
+the 4^3 coarsest level).  The chains of seeds 0..CHAINS-1 (--chains, default 8) are batched
+into every launch (one hierarchy carrying CHAINS x 3 components; each chain draws exactly what
+it draws alone).
 One step = one batched call that advances every chain by SAMPLES_PER_STEP cycles, writes
 every cycle's fields to an output buffer in HBM and takes their observables (projections on
 the 8 lowest eigenvectors of A and the energy 1/2 x^T A x) in the same pass.
@@ -36,29 +37,43 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+def progress(msg):
+    """One line per finished stage on stderr (stdout carries only the result line)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
 NX = NY = NZ = 128
 NCOMP = 3
 LEVELS = 6
 SAMPLES_PER_STEP = 8
 HBM_PEAK_GBS = 8000.0
 METRIC = "decorrelated 128³ field samples/s + p99 latency; achieved HBM GB/s"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rb_pass_128cubed_3comp_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_128cubed_3comp_fp64.json")
+# the sources each timed kernel class is compiled from: a traffic record applies only to them
+KERNEL_SOURCES = {
+    "fine_pass": ("kernels_fine.hip", "device_common.hpp", "philox.hpp", "kernels.hpp"),
+    "level1_block_pass": ("kernels_gal.hip", "device_common.hpp", "philox.hpp", "kernels.hpp"),
+}
 
 
-def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_1003_2680_amd", "csrc", "kernels_fine.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_source_hash(kind):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, "paper_1003_2680_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_per_launch):
-    """HBM bytes per fine colour-pass launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source; else None."""
+def measured_traffic(kind, chains):
+    """HBM bytes per launch of a kernel class from committed rocprofv3 counters, if they were
+    taken on the current sources and the same batch; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
-            rec = json.load(f)
+            rec = json.load(f).get("kernels", {}).get(kind)
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_hip_sha256_16") != kernel_source_hash():
+    if not rec or rec.get("sources_sha256_16") != kernel_source_hash(kind) \
+            or rec.get("chains") != chains:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -316,7 +331,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--solves", type=int, default=10)
-    ap.add_argument("--chains", type=int, default=4)
+    ap.add_argument("--chains", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refined", action="store_true",
                     help="skip the FP32-refined measurement")
@@ -348,6 +363,7 @@ def main():
           for i in range(max(args.solves, 1))]
 
     r64 = measure("fp64", args, fs, dev)
+    progress("fp64 sampling, kernel timing and solves done")
     rho_solve = r64["rho"]
     rho_obs = lag1(r64["obs"])
     rho = max(rho_solve, float(np.max(np.abs(rho_obs))))
@@ -370,11 +386,12 @@ def main():
 
     # level-0 colour pass (b = 0): read the other colour, write this colour, 8 B per value
     fine = roof(kern["fine_pass"], "k_rb_pass (level-0 colour pass, 128^3)", nact * N0 * 8)
-    fine["traffic"] = measured_traffic(fine["algorithmic_bytes_per_launch"])
+    fine["traffic"] = measured_traffic("fine_pass", C)
     # level-1 block colour pass: read x of the whole level, b and the noise of this colour's
     # cells, write x of this colour's cells: N1 * 8 B * (1 + 3/8)
     blk = roof(kern["level1_block_pass"], "k_block_tile (level-1 block colour pass, 64^3)",
                nact * N1 * 8 * 11 // 8)
+    blk["traffic"] = measured_traffic("level1_block_pass", C)
     # the dominant kernel class by GPU time per cycle carries `roofline`
     dominant = max((fine, blk), key=lambda r: r["us_per_cycle"])
     other = blk if dominant is fine else fine
@@ -416,6 +433,7 @@ def main():
         del H64, H32, a, b
         torch.cuda.empty_cache()
         r32 = measure("fp32_refined", args, fs, dev)
+        progress("fp32-refined form done")
         r_sps = C * SAMPLES_PER_STEP / (r32["ms_per_step"] / 1e3)
         line["fp32_refined"] = {
             "value": round(r_sps / k_dec, 3), "samples_per_s": round(r_sps, 2),
@@ -431,10 +449,13 @@ def main():
 
     if not args.no_batched:
         line["batched"] = measure_batched(dev)
+        progress("batched instances done")
     if not args.no_serving:
         line["serving"] = measure_serving(dev, stride=k_dec)
+        progress("serving done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(k_dec)
+        progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 

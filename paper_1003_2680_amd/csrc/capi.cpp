@@ -516,12 +516,15 @@ int load_modes(Hierarchy& h, const int32_t* modes, int k, hipStream_t s) {
   double* tx = tab.data();
   double* tr = tx + (size_t)kMaxModes * v.nx;
   std::vector<double> wz(v.nz);
+  // row factors row-major with the stride the kernel sums over (8 or kMaxModes): the factors
+  // of one row share a scalar cache line
+  const size_t ks = k <= 8 ? 8 : kMaxModes;
   for (int q = 0; q < k; ++q) {
     for (int i = 0; i < v.nx; ++i) tx[q * v.nx + i] = periodic_factor(v.nx, modes[3 * q], i);
     wall_vector(v.nz, modes[3 * q + 2], wz.data());
     for (int z = 0; z < v.nz; ++z)
       for (int y = 0; y < v.ny; ++y)
-        tr[q * rows + (size_t)z * v.ny + y] = periodic_factor(v.ny, modes[3 * q + 1], y) * wz[z];
+        tr[((size_t)z * v.ny + y) * ks + q] = periodic_factor(v.ny, modes[3 * q + 1], y) * wz[z];
   }
   SMG_HIP(hipMemcpyAsync(h.ws + h.off_mtab, tab.data(), tab.size() * sizeof(double),
                          hipMemcpyHostToDevice, s));

@@ -48,12 +48,14 @@ __device__ __forceinline__ Blk3 xcd_block() {
   return b;
 }
 
-// v mod n for v >= -n (one or two corrections cover every tile narrower than the level)
+// Periodic index of a staged halo position: v mod n for -n <= v < 2n.  A tile that overhangs
+// a small level may stage positions further out; no cell inside the level reads them (a
+// stencil reaches at most two cells, and n >= 4), so they are clamped into range instead of
+// reduced by a division.
 __device__ __forceinline__ int wrap_near(int v, int n) {
   if (v < 0) v += n;
   if (v >= n) v -= n;
-  if (v >= n) v %= n;
-  return v;
+  return v < n ? v : n - 1;
 }
 
 // (A x) at cell (cx, cy, cz) of a Galerkin level.  The Galerkin operator of the wall-bounded

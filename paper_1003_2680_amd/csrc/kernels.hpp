@@ -157,8 +157,9 @@ hipError_t launch_advance_chains(ChainKey* dst, int n, uint64_t cycles, hipStrea
 
 // Statistics of one emitted sample of level 0 (FP64 state), fused with its emission.
 constexpr int kMaxModes = 32;
-constexpr int STATS_CPT = 4;                 // cells per thread
-constexpr int STATS_CELLS = STATS_CPT * 256;  // cells per work-group
+constexpr int STATS_CPT = 4;                            // cells per thread and batch
+constexpr int STATS_NB = 4;                             // batches per thread
+constexpr int STATS_CELLS = STATS_NB * STATS_CPT * 256;  // cells per work-group
 struct StatsArgs {
   const double* xr;   // split layout: colour-0 half [ncomp][N/2]; natural layout: [ncomp][N]
   const double* xb;   // split layout: colour-1 half; null for the natural layout
@@ -167,7 +168,8 @@ struct StatsArgs {
   int nmodes;         // 0..kMaxModes projections (with obs)
   int nblk;           // work-groups per component: ceil(N / STATS_CELLS)
   const double* tx;   // [kMaxModes][nx]: x factor e_a(x) of each mode
-  const double* trow; // [kMaxModes][ny*nz]: row factor e_b(y) w_m(z) of each mode
+  const double* trow; // [ny*nz][KB]: row factor e_b(y) w_m(z) of each mode, KB = 8 when
+                      // nmodes <= 8 else kMaxModes
   void* out;          // [ncomp][N] natural emission (float or double) or null
   int out_f32;
   double* m1;         // [ncomp][N] running sum of x and of x^2, or null

@@ -106,7 +106,8 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
   for (int p = 0; p < PPT; ++p) {
     const int pos = tid + p * TILE_TPB;
     const int sx = pos % TILE_W, sy = pos / TILE_W;
-    loff[p] = pos < PLANE ? sy * TILE_W + sx : -1;
+    // positions past the plane store into its pad element (TP = PLANE + 1): no branch
+    loff[p] = pos < PLANE ? pos : PLANE;
     goff[p] = pos < PLANE ? wrap_near(y0 + sy, ny) * nx + wrap_near(x0 + sx, nx) : 0;
   }
   T stage[TILE_D][PPT];
@@ -121,8 +122,7 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
 #pragma unroll
   for (int sz = 0; sz < TILE_D; ++sz)
 #pragma unroll
-    for (int p = 0; p < PPT; ++p)
-      if (loff[p] >= 0) Tl[sz * TP + loff[p]] = stage[sz][p];
+    for (int p = 0; p < PPT; ++p) Tl[sz * TP + loff[p]] = stage[sz][p];
   __syncthreads();
   {
     // The two z-layers of a block reach the same six staged planes (tile planes 0..5).  Lane

@@ -2,13 +2,14 @@
 // onto eigenvectors of A and the energy 1/2 x^T A x (the observables whose lag-k correlation
 // measures how fast the chain decorrelates, Sec. "Stochastic Iterative Methods").
 //
-// A work-group takes STATS_CELLS consecutive cells of one component, STATS_CPT per thread
-// (256 apart, all loads issued before any arithmetic), so every wave keeps its whole working
-// set in flight at once.  An eigenvector is a product e_a(x) e_b(y) w_m(z): when rows are a
+// A work-group takes STATS_CELLS consecutive cells of one component; a thread takes
+// STATS_NB batches of STATS_CPT cells (256 apart, all loads of a batch issued before its
+// arithmetic), so every wave keeps a batch in flight and the cross-lane sums at the end are
+// paid once per 16 cells.  An eigenvector is a product e_a(x) e_b(y) w_m(z): when rows are a
 // multiple of 64 cells a wavefront lies in one row and the (y, z) factor of each mode (a
-// per-row table) is a uniform (scalar) load.  Sums run in a fixed order -- thread, butterfly over the lanes, the
-// four waves of a work-group, then a tree over the work-groups -- so results do not depend on
-// timing.
+// per-row table) is a uniform (scalar) load.  Sums run in a fixed order -- thread, butterfly
+// over the lanes, the four waves of a work-group, then a tree over the work-groups -- so
+// results do not depend on timing.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
@@ -49,78 +50,87 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   typedef const __attribute__((address_space(4))) double* cptr;
   const double* __restrict__ tx = a.tx;
   const cptr trow = (cptr)a.trow;
-  const uint32_t rows = (uint32_t)ny * nz;
   const uint32_t base = blockIdx.x * STATS_CELLS;
-  // all loads of this thread's cells first.  When a wavefront lies in one row (UROW) the +x
-  // neighbour of a cell is the next lane's value and only the wave's last lane loads it; when
-  // the thread's cells are whole rows apart (XSAME) they share their x, hence the x factors.
-  double v[STATS_CPT], nb[STATS_CPT][3];
-  int cx[STATS_CPT], cy[STATS_CPT], cz[STATS_CPT];
-  double txs[KB > 0 ? KB : 1];
-#pragma unroll
-  for (int c = 0; c < STATS_CPT; ++c) {
-    const uint32_t cell = base + c * TPB + threadIdx.x;
-    const bool in = cell < N;
-    const uint32_t cc = in ? cell : 0;
-    const uint32_t row = udiv(cc, nx, a.lgx);
-    const int x = cc - row * nx;
-    const uint32_t zz = udiv(row, ny, a.lgy);
-    const int y = row - zz * ny, z = zz;
-    cx[c] = x;
-    cy[c] = y;
-    cz[c] = in ? z : -1;
-    v[c] = in ? load(x, y, z) : 0.0;
-    if (KB > 0) {
-      const int xp = x + 1 == nx ? 0 : x + 1;
-      nb[c][0] = (in && (!UROW || lane == 63)) ? load(xp, y, z) : 0.0;
-      nb[c][1] = in ? load(x, y + 1 == ny ? 0 : y + 1, z) : 0.0;
-      nb[c][2] = (in && z + 1 < nz) ? load(x, y, z + 1) : 0.0;
-    }
-  }
-  if (KB > 0 && XSAME) {
-#pragma unroll
-    for (int q = 0; q < KB; ++q) txs[q] = q < K ? tx[q * nx + cx[0]] : 0.0;
-  }
-  if (KB > 0 && UROW) {
-#pragma unroll
-    for (int c = 0; c < STATS_CPT; ++c) {
-      const double nxt = __shfl_down(v[c], 1, 64);
-      if (lane != 63) nb[c][0] = nxt;
-    }
-  }
+  // A thread takes STATS_NB batches of STATS_CPT cells (TPB apart), all loads of a batch
+  // before its arithmetic.  When a wavefront lies in one row (UROW) the +x neighbour of a cell
+  // is the next lane's value and only the wave's last lane loads it, and a wave's cells are all
+  // inside the grid or all outside; when a thread's cells are whole rows apart (XSAME) they
+  // share their x, hence the x factors of the modes.  Mode tables are zero beyond the K modes
+  // in use, so the first KB <= 8 sums need no guard.
   double acc[KB > 0 ? KB : 1];
 #pragma unroll
   for (int q = 0; q < (KB > 0 ? KB : 1); ++q) acc[q] = 0.0;
   double accE = 0.0;
+  double txs[KB > 0 ? KB : 1];
+  if (KB > 0 && XSAME) {
+    const uint32_t c0 = base + threadIdx.x;
+    const int x0 = (int)(c0 - udiv(c0, nx, a.lgx) * nx);
 #pragma unroll
-  for (int c = 0; c < STATS_CPT; ++c) {
-    if (cz[c] < 0) continue;
-    const size_t gi = (size_t)comp * N + base + c * TPB + threadIdx.x;
-    const double x0 = v[c];
-    if (out) out[gi] = (TO)x0;
-    if (MOM) {
-      a.m1[gi] += x0;
-      a.m2[gi] = fma(x0, x0, a.m2[gi]);
-    }
-    if (KB > 0) {
-      const int z = cz[c];
-      uint32_t row = (uint32_t)z * ny + cy[c];
-      if (UROW) row = __builtin_amdgcn_readfirstlane(row);  // the wavefront lies in one row
+    for (int q = 0; q < KB; ++q) txs[q] = (KB <= 8 || q < K) ? tx[q * nx + x0] : 0.0;
+  }
+#pragma unroll 1
+  for (int bt = 0; bt < STATS_NB; ++bt) {
+    const uint32_t bbase = base + bt * (STATS_CPT * TPB);
+    double v[STATS_CPT], nb[STATS_CPT][3];
+    int cx[STATS_CPT], cy[STATS_CPT], cz[STATS_CPT];
 #pragma unroll
-      for (int q = 0; q < KB; ++q)
-        if (q < K)
-          acc[q] = fma((XSAME ? txs[q] : tx[q * nx + cx[c]]) * trow[q * rows + row], x0, acc[q]);
-      // faces +x, +y (periodic) and +z (interior), plus the wall faces (ghost = -v)
-      const double d1 = x0 - nb[c][0];
-      const double d2 = x0 - nb[c][1];
-      double e = fma(d1, d1, d2 * d2);
-      if (z + 1 < nz) {
-        const double d3 = x0 - nb[c][2];
-        e = fma(d3, d3, e);
+    for (int c = 0; c < STATS_CPT; ++c) {
+      const uint32_t cell = bbase + c * TPB + threadIdx.x;
+      const bool in = UROW ? __builtin_amdgcn_readfirstlane(cell) < N : cell < N;
+      const uint32_t cc = in ? cell : 0;
+      const uint32_t row = udiv(cc, nx, a.lgx);
+      const int x = cc - row * nx;
+      const uint32_t zz = udiv(row, ny, a.lgy);
+      const int y = row - zz * ny, z = zz;
+      cx[c] = x;
+      cy[c] = y;
+      cz[c] = in ? z : -1;
+      v[c] = in ? load(x, y, z) : 0.0;
+      if (KB > 0) {
+        const int xp = x + 1 == nx ? 0 : x + 1;
+        nb[c][0] = (in && (!UROW || lane == 63)) ? load(xp, y, z) : 0.0;
+        nb[c][1] = in ? load(x, y + 1 == ny ? 0 : y + 1, z) : 0.0;
+        nb[c][2] = (in && z + 1 < nz) ? load(x, y, z + 1) : 0.0;
       }
-      if (z == 0) e = fma(2.0 * x0, x0, e);
-      if (z == nz - 1) e = fma(2.0 * x0, x0, e);
-      accE += e;
+    }
+    if (KB > 0 && UROW) {
+#pragma unroll
+      for (int c = 0; c < STATS_CPT; ++c) {
+        const double nxt = __shfl_down(v[c], 1, 64);
+        if (lane != 63) nb[c][0] = nxt;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < STATS_CPT; ++c) {
+      if (cz[c] < 0) continue;
+      const size_t gi = (size_t)comp * N + bbase + c * TPB + threadIdx.x;
+      const double x0 = v[c];
+      if (out) out[gi] = (TO)x0;
+      if (MOM) {
+        a.m1[gi] += x0;
+        a.m2[gi] = fma(x0, x0, a.m2[gi]);
+      }
+      if (KB > 0) {
+        const int z = cz[c];
+        uint32_t row = (uint32_t)z * ny + cy[c];
+        if (UROW) row = __builtin_amdgcn_readfirstlane(row);  // the wavefront lies in one row
+#pragma unroll
+        for (int q = 0; q < KB; ++q)
+          if (KB <= 8 || q < K)
+            acc[q] = fma((XSAME ? txs[q] : tx[q * nx + cx[c]]) * trow[(size_t)row * KB + q], x0,
+                         acc[q]);
+        // faces +x, +y (periodic) and +z (interior), plus the wall faces (ghost = -v)
+        const double d1 = x0 - nb[c][0];
+        const double d2 = x0 - nb[c][1];
+        double e = fma(d1, d1, d2 * d2);
+        if (z + 1 < nz) {
+          const double d3 = x0 - nb[c][2];
+          e = fma(d3, d3, e);
+        }
+        if (z == 0) e = fma(2.0 * x0, x0, e);
+        if (z == nz - 1) e = fma(2.0 * x0, x0, e);
+        accE += e;
+      }
     }
   }
   if (KB == 0) return;
