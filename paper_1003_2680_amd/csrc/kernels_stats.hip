@@ -26,7 +26,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 template <int KB, bool SPLIT, bool MOM, typename TO, bool UROW, bool XSAME>
 __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
-  const uint32_t comp = blockIdx.y;
+  // XCD-aware numbering: the +z neighbours of a work-group's cells belong to a work-group a
+  // few ids on, which then runs on the same XCD and finds them in its L2
+  const Blk3 wg = xcd_block();
+  const uint32_t comp = wg.y;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   typedef const __attribute__((address_space(4))) double* cptr;
   const double* __restrict__ tx = a.tx;
   const cptr trow = (cptr)a.trow;
-  const uint32_t base = blockIdx.x * STATS_CELLS;
+  const uint32_t base = wg.x * STATS_CELLS;
   // A thread takes STATS_NB batches of STATS_CPT cells (TPB apart), all loads of a batch
   // before its arithmetic.  When a wavefront lies in one row (UROW) the +x neighbour of a cell
   // is the next lane's value and only the wave's last lane loads it, and a wave's cells are all
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   const int q = threadIdx.x;
   if (q <= K) {
     const int qi = q == K ? KB : q;
-    a.part[((size_t)comp * a.nblk + blockIdx.x) * (K + 1) + q] =
+    a.part[((size_t)comp * a.nblk + wg.x) * (K + 1) + q] =
         ((red[0][qi] + red[1][qi]) + red[2][qi]) + red[3][qi];
   }
 }

@@ -34,6 +34,22 @@ struct BoxMullerCoef {
   double cs[8];  // (-1)^k pi^(2k)/(2k)!, k = 8 .. 1
 };
 
+// sum_{i < n} c[n-1-i] z^i, lowest power first with the powers formed on the way.  Each term
+// is one FMA whose coefficient is the scalar multiplicand (a nested Horner step would need
+// every coefficient copied into vector registers as the addend).  The series here converge
+// fast (z <= 1/16), so the order of summation costs nothing in accuracy.
+template <int n>
+__device__ __forceinline__ double poly_scalar_coef(const double (&c)[n], double z) {
+  double acc = c[n - 1];
+  double zp = z;
+#pragma unroll
+  for (int i = 1; i < n; ++i) {
+    acc = fma(c[n - 1 - i], zp, acc);
+    if (i + 1 < n) zp *= z;
+  }
+  return acc;
+}
+
 struct NoiseArgs {
   uint32_t k0, k1;   // seed low / high (one chain)
   uint32_t sid;      // level | slot<<4 | colour<<12 | kind<<24 (component added per thread)
@@ -121,9 +137,7 @@ __device__ __forceinline__ double log_unit(double u, const BoxMullerCoef& c) {
   double s = f * r;
   s = fma(fma(-d, s, f), r, s);
   const double z = s * s;
-  double p = c.lg[0];
-#pragma unroll
-  for (int i = 1; i < 9; ++i) p = fma(p, z, c.lg[i]);
+  const double p = poly_scalar_coef(c.lg, z);
   const double s2 = 2.0 * s;
   const double lm = fma(s2 * z, p, s2);
   constexpr double LN2_HI = 0x1.62e42fef00000p-1;  // ln 2 with the low 20 bits cleared
@@ -141,14 +155,8 @@ __device__ __forceinline__ void sincospi_turns(double t, const BoxMullerCoef& c,
   const double n = rint(2.0 * t);
   const double r = fma(-0.5, n, t);
   const double z = r * r;
-  double ps = c.sn[0];
-#pragma unroll
-  for (int i = 1; i < 9; ++i) ps = fma(ps, z, c.sn[i]);
-  const double S = r * ps;
-  double pc = c.cs[0];
-#pragma unroll
-  for (int i = 1; i < 8; ++i) pc = fma(pc, z, c.cs[i]);
-  const double C = fma(pc, z, 1.0);
+  const double S = r * poly_scalar_coef(c.sn, z);
+  const double C = fma(poly_scalar_coef(c.cs, z), z, 1.0);
   const int q = (int)n & 3;
   const double a = (q & 1) ? C : S;  // sin(pi (r + n/2))
   const double b = (q & 1) ? S : C;  // cos(pi (r + n/2))
