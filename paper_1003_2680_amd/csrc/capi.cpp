@@ -189,7 +189,7 @@ int sweep(Run& r, int l, int slot, bool post) {
       const T* zn = r.noise ? noise + (size_t)slot * nc * v.n : nullptr;
       SMG_HIP(launch_block_pass<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
                                    (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz, r.nc,
-                                   colour, zn, std::sqrt(h.desc.kT), h.block_tile, r.s));
+                                   colour, zn, h.block_tile, r.s));
     }
     SMG_TRY(ts.close());
   }
@@ -275,6 +275,7 @@ int gen_level_noise(Run& r, int only_level = -1, int only_slot = 0) {
     e.nslot = only_level >= 0 ? 1 : h.prm.nu1 + h.prm.nu2;
     e.slot0 = only_level >= 0 ? only_slot : 0;
     e.out = v.noise_d;
+    e.bfac = v.bfac_d;
     e.lg_bx = log2_exact(v.nx / 2);
     e.lg_bxy = log2_exact((v.nx / 2) * (v.ny / 2));
     e.calls_before = calls;
@@ -1043,7 +1044,7 @@ int smg_debug_smooth(smg_hierarchy* hh, int32_t level, int32_t colour, void* x, 
                                       (const double*)v.zt_d, (const double*)v.bfac_d, v.nx, v.ny,
                                       v.nz, h.desc.ncomp, colour,
                                       r.noise ? (const double*)v.noise_d : nullptr,
-                                      std::sqrt(h.desc.kT), h.block_tile, s));
+                                      h.block_tile, s));
   }
   return SMG_OK;
 }

@@ -148,14 +148,14 @@ __device__ __forceinline__ void plane_window(int kz, const T (&q)[3], const T (&
 //   rhs_j  = b_j - (A x)_j + sum_i A_BB[j][i] x_B[i]   (= b_j - A_{j,rest} x_rest).
 // The eight lanes of a block must be consecutive lanes of one wave (shuffle width 8) and all
 // lanes of the wave must call this together; inactive lanes pass active = false.
-// The lane's standard normal comes from a pregenerated noise field Z (natural layout of the
-// level: one normal per cell and sweep, drawn from the stream of the cell's block colour).
+// The lane's noise comes from a pregenerated field Z (natural layout of the level, one value
+// per cell and sweep): the block's normals already multiplied by sqrt(kT) L_BB^-T.
 template <typename T, bool NOISE>
 __device__ __forceinline__ T block_lane(const T* __restrict__ X, int sy, int sz,
                                         const T* __restrict__ Bv, const T* s1d,
                                         const T* __restrict__ zt, const T* __restrict__ bfac,
                                         int nx, int ny, int nz, int bx, int by, int bz, int k,
-                                        bool active, const T* __restrict__ Z, T sqkT,
+                                        bool active, const T* __restrict__ Z,
                                         uint32_t& cell_out) {
   const int cx = 2 * bx + (k & 1);
   const int cy = 2 * by + ((k >> 1) & 1);
@@ -205,24 +205,17 @@ __device__ __forceinline__ T block_lane(const T* __restrict__ X, int sy, int sz,
       ax = acc0 + acc1;
     }
   }
+  // x_B + A_BB^-1 (b_B - (A x)_B) equals A_BB^-1 (b_B - A_B,rest x_rest): the block's own
+  // coupling cancels, so only the residual needs to be shared across the block's lanes
   const T* F = bfac + (size_t)(active ? bz : 0) * 192;
-  T inb = 0;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) inb = fma(F[128 + k * 8 + j], __shfl(xk, j, 8), inb);
-  const T rhs = bk - ax + inb;
-  T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
+  const T res = bk - ax;
+  T v0 = xk, v1 = NOISE ? nrm : T(0);
 #pragma unroll
   for (int j = 0; j < 8; j += 2) {
-    v0 = fma(F[k * 8 + j], __shfl(rhs, j, 8), v0);
-    v1 = fma(F[k * 8 + j + 1], __shfl(rhs, j + 1, 8), v1);
-    if (NOISE) {
-      w0 = fma(F[64 + k * 8 + j], __shfl(nrm, j, 8), w0);
-      w1 = fma(F[64 + k * 8 + j + 1], __shfl(nrm, j + 1, 8), w1);
-    }
+    v0 = fma(F[k * 8 + j], __shfl(res, j, 8), v0);
+    v1 = fma(F[k * 8 + j + 1], __shfl(res, j + 1, 8), v1);
   }
-  T v = v0 + v1;
-  if (NOISE) v = fma(sqkT, w0 + w1, v);
-  return v;
+  return v0 + v1;
 }
 
 // b_c = P^T r at coarse cell (X,Y,Z): 4x4x4 fine window 2J-1..2J+2 per axis, weights

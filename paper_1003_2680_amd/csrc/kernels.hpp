@@ -26,6 +26,7 @@ struct NoiseLevel {
   int level, nx, ny, nz, nslot, slot0;
   int lg_bx, lg_bxy;      // log2 of nx/2 and of (nx/2)(ny/2) when powers of two, else -1
   void* out;              // T[nslot][ncomp][N]
+  const void* bfac;       // T[nz/2][192]: the level's block factors (L_BB^-T at offset 64)
   uint32_t calls_before;  // prefix sum of nslot*nact*N/2 over the previous entries
 };
 struct NoiseGenArgs {
@@ -57,12 +58,14 @@ struct BotArgs {
   const double* w;     // coarsest L_c^-1
 };
 
-// LDS strides of a bottom level: rows padded to 2 mod 4 and planes to 1 mod 4 elements on the
-// block levels (bank spread of the 8 cells x 8 blocks of a wave); the coarsest stays natural.
+// LDS strides of a bottom level: on the block levels rows are padded by 2 elements and
+// planes to the first count that is 16 mod 32 elements, which spreads a wave's reads of one
+// window offset (8 cells x 8 blocks, the two z-layers of a block three planes apart) over the
+// 64 banks; the coarsest stays natural.
 inline void bot_strides(int kind, int nx, int ny, int& sy, int& sz) {
   if (kind == KIND_BLOCK) {
     sy = nx + 2;
-    sz = ny * (nx + 2) + 1;
+    sz = ny * sy + (48 - (ny * sy) % 32) % 32;
   } else {
     sy = nx;
     sz = nx * ny;
@@ -100,12 +103,13 @@ hipError_t launch_restrict(T* bc, T* xc, const T* r, int nxf, int nyf, int nzf, 
                            hipStream_t s);
 template <typename T>
 hipError_t launch_prolong(T* x, const T* e, int nxf, int nyf, int nzf, int ncomp, hipStream_t s);
-// z: pregenerated noise of this pass's sweep, [ncomp][N] (null without noise); tile: one of
-// the SMG_TILE_* shapes of smg.h (SMG_TILE_AUTO picks by work-group count)
+// z: pregenerated noise of this pass's sweep, [ncomp][N], each block's normals already
+// multiplied by sqrt(kT) L_BB^-T (null without noise); tile: one of the SMG_TILE_* shapes of
+// smg.h (SMG_TILE_AUTO picks by work-group count)
 template <typename T>
 hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
-                             int ny, int nz, int ncomp, int colour, const T* z, double sqkT,
-                             int tile, hipStream_t s);
+                             int ny, int nz, int ncomp, int colour, const T* z, int tile,
+                             hipStream_t s);
 template <typename T>
 hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStream_t s);
 // `a` points to a BotArgs in device memory

@@ -178,14 +178,16 @@ __global__ __launch_bounds__(TPB) void k_residual0(T* __restrict__ r, const T* _
 // the 18 x 18 window of the column, and every coarse cell of the column takes that plane's
 // 4x4 window sum (weights 1/4, 3/4, 3/4, 1/4 per axis; 1/2 for a fine cell next to a wall)
 // into the running sums of the two coarse layers the plane belongs to: four lanes per coarse
-// cell, one window row each, joined by shuffles.  Each x plane is loaded once per column and
+// cell, one window column each, joined by shuffles.  Each x plane is loaded once per column and
 // each residual plane formed once, instead of once per coarse layer pair.  Also zeroes the
 // coarse iterate when xc is not null.
 constexpr int RR_X = 8, RR_Y = 8, RR_Z = 8;
 constexpr int RR_FX = 2 * RR_X + 2, RR_FY = 2 * RR_Y + 2;  // residual window of a plane
 constexpr int RR_SX = RR_FX + 2, RR_SY = RR_FY + 2;        // x box of a plane
 constexpr int RR_XP = RR_SX * RR_SY;                       // x plane in LDS
-constexpr int RR_RP = RR_FX * RR_FY;                       // residual plane in LDS
+// The residual window is formed and stored with the x box's row stride RR_SX (two idle
+// lanes per row), so consecutive lanes touch consecutive LDS words: no bank conflicts.
+constexpr int RR_RP = RR_SX * RR_FY;                       // residual plane in LDS
 constexpr int RR_PPT = (RR_XP + TPB - 1) / TPB;            // x positions per thread
 constexpr int RR_RPT = (RR_RP + TPB - 1) / TPB;            // residual positions per thread
 static_assert(RR_X * RR_Y * 4 == TPB, "four lanes per coarse cell of the column");
@@ -221,8 +223,8 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
 #pragma unroll
   for (int p = 0; p < RR_RPT; ++p) {
     const int q = tid + p * TPB;
-    const int rx = q % RR_FX, ry = q / RR_FX;
-    roff[p] = q < RR_RP ? q : -1;
+    const int rx = q % RR_SX, ry = q / RR_SX;
+    roff[p] = (q < RR_RP && rx < RR_FX) ? q : -1;
     rxo[p] = (ry + 1) * RR_SX + rx + 1;  // centre of the 7-point star in an x plane
   }
   const int f0 = 2 * Z0 - 1, f1 = 2 * (Z0 + zc);  // residual planes of the column
@@ -242,12 +244,12 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
 #pragma unroll
     for (int p = 0; p < RR_RPT; ++p) {
       const int q = roff[p] < 0 ? 0 : roff[p];
-      const int fx = wrap_near(2 * X0 - 1 + q % RR_FX, nx);
-      const int fy = wrap_near(2 * Y0 - 1 + q / RR_FX, ny);
+      const int fx = wrap_near(2 * X0 - 1 + q % RR_SX, nx);
+      const int fy = wrap_near(2 * Y0 - 1 + q / RR_SX, ny);
       reg[p] = HAS_B ? split_at(br, bb, cb, fx, fy, g, nh, ny) : T(0);
     }
   };
-  // this lane's coarse cell and window row
+  // this lane's coarse cell and window column
   const int wb = tid & 3, cell = tid >> 2;
   const int lx = cell % RR_X, ly = cell / RR_X;
   const int X = X0 + lx, Y = Y0 + ly;
@@ -280,10 +282,12 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
     if (HAS_B && f + 2 <= f1) load_b(bcur, f + 2);
     __syncthreads();
     if (f < 0 || f >= nz) return;
-    const T* Rr = R + (2 * ly + wb) * RR_FX + 2 * lx;
+    // lane wb takes window column wb (x offset) down the four rows: the lanes of a wave read
+    // one contiguous run of the row at a time
+    const T* Rr = R + 2 * ly * RR_SX + 2 * lx + wb;
     T s = 0;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) s = fma(pw<T>(a), Rr[a], s);
+    for (int b = 0; b < 4; ++b) s = fma(pw<T>(b), Rr[b * RR_SX], s);
     s *= pw<T>(wb);
     s += __shfl_xor(s, 1, 4);
     s += __shfl_xor(s, 2, 4);

@@ -8,6 +8,8 @@
 // block is redrawn from its exact 8-variable conditional law.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -16,36 +18,60 @@ namespace {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
 
-// Block-level noise for whole sweeps: thread = one Philox call = the two cells (in-block k = 2m,
-// 2m+1) of one block.  Grid: x over the calls of one (sweep slot, component) of the largest
-// level, y = level entry, z = slot * nact + component, so every index below is uniform per
-// work-group except the call number.
+// Block-level noise for whole sweeps, ready for the block passes: one thread per block draws
+// the block's eight normals (Philox calls 4 bid .. 4 bid + 3, cells k = 2m, 2m+1 of call m) and
+// writes sqrt(kT) L_BB^-T n, L_BB^-T being upper triangular.  When a wave's 64 blocks lie in
+// one block row (the level's blocks per layer a multiple of 64) the factor rows are uniform
+// and are read with scalar loads as FMA operands.  Grid: x over the blocks of one (sweep slot,
+// component) of the largest level, y = level entry, z = slot * nact + component.
+template <typename T, bool UNIFORM>
+__device__ __forceinline__ void colour_block_noise(const T* __restrict__ W, const T (&n)[8],
+                                                   T (&e)[8]) {
+  typedef const __attribute__((address_space(4))) T* cptr;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    T acc = 0;
+#pragma unroll
+    for (int j = k; j < 8; ++j) acc = fma(UNIFORM ? ((cptr)W)[k * 8 + j] : W[k * 8 + j], n[j], acc);
+    e[k] = acc;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_level_noise(NoiseGenArgs a, NoiseArgs na) {
+  using V2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
   const NoiseLevel& L = a.lv[blockIdx.y];
   const uint32_t N = (uint32_t)L.nx * L.ny * L.nz;
-  const uint32_t half = N >> 1;
-  const uint32_t q = blockIdx.x * TPB + threadIdx.x;  // call within (slot, comp)
+  const uint32_t bid = blockIdx.x * TPB + threadIdx.x;  // block within (slot, comp)
   const uint32_t s = blockIdx.z / (uint32_t)a.nact;
   const uint32_t comp = blockIdx.z - s * (uint32_t)a.nact;
-  if (q >= half || (int)s >= L.nslot) return;
-  const uint32_t bid = q >> 2;
-  const int m = q & 3;
+  if (bid >= (N >> 3) || (int)s >= L.nslot) return;
   const uint32_t nbx = (uint32_t)L.nx >> 1, nby = (uint32_t)L.ny >> 1;
-  const uint32_t bxy = udiv(bid, nbx * nby, L.lg_bxy);
-  const uint32_t rem = bid - bxy * nbx * nby;
+  const uint32_t bz = udiv(bid, nbx * nby, L.lg_bxy);
+  const uint32_t rem = bid - bz * nbx * nby;
   const uint32_t by = udiv(rem, nbx, L.lg_bx);
   const uint32_t bx = rem - by * nbx;
-  const uint32_t bz = bxy;
   const int colour = (bx & 1) + 2 * (by & 1) + 4 * (bz & 1);
   const uint32_t sid = (uint32_t)L.level | ((uint32_t)(L.slot0 + s) << 4) | ((uint32_t)colour << 12);
-  T z0, z1;
-  normal_pair_t<T>(na, sid, comp, q, z0, z1);
-  const int dy = m & 1, dz = m >> 1;  // in-block index k = 2m + dx
-  const uint32_t c0 = ((2 * bz + dz) * L.ny + (2 * by + dy)) * L.nx + 2 * bx;
+  T n[8], e[8];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) normal_pair_t<T>(na, sid, comp, 4 * bid + m, n[2 * m], n[2 * m + 1]);
+  if ((nbx * nby) % 64 == 0) {
+    const uint32_t bzu = __builtin_amdgcn_readfirstlane(bz);
+    colour_block_noise<T, true>((const T*)L.bfac + (size_t)bzu * 192 + 64, n, e);
+  } else {
+    colour_block_noise<T, false>((const T*)L.bfac + (size_t)bz * 192 + 64, n, e);
+  }
+  const T sq = (T)na.sqkT;
   T* out = (T*)L.out + ((size_t)s * a.ncomp + comp) * N;
-  out[c0] = z0;
-  out[c0 + 1] = z1;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {  // cells k = 2m, 2m+1: one row of the block (dy, dz) = (m&1, m>>1)
+    const uint32_t c0 = ((2 * bz + (m >> 1)) * L.ny + (2 * by + (m & 1))) * L.nx + 2 * bx;
+    V2 v;
+    v.x = sq * e[2 * m];
+    v.y = sq * e[2 * m + 1];
+    *reinterpret_cast<V2*>(out + c0) = v;
+  }
 }
 
 // One block-colour pass, LDS-staged.  A work-group owns a TI x TJ tile of the colour's blocks in
@@ -66,10 +92,13 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
                                                           const T* __restrict__ bfac, int nx,
                                                           int ny, int nz, uint32_t N, int colour,
                                                           int nbx2, int nby2, int ntx,
-                                                          const T* __restrict__ zn, T sqkT) {
+                                                          const T* __restrict__ zn) {
   constexpr int TILE_W = 4 * TILE_I + 2, TILE_H = 4 * TILE_J + 2;
   constexpr int TILE_TPB = TILE_I * TILE_J * 8;
-  constexpr int TP = TILE_H * TILE_W + 1;  // plane stride: 1 mod 4 elements
+  // plane stride: the first count >= the plane that is 16 mod 32 elements.  The two z-layers
+  // of a block read planes three apart, so their lanes then fall on opposite halves of the
+  // 64 LDS banks and a wave's reads of one window offset are free of bank conflicts (FP64).
+  constexpr int TP = TILE_H * TILE_W + ((48 - (TILE_H * TILE_W) % 32) % 32);
   __shared__ T Tl[TILE_D * TP];
   const Blk3 wg = xcd_block();
   const uint32_t comp = wg.z;
@@ -154,23 +183,18 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
       xk = Tl[tz * TP + ty * TILE_W + tx];
     }
   }
+  // x_B + A_BB^-1 (b_B - (A x)_B) equals A_BB^-1 (b_B - A_B,rest x_rest): the block's own
+  // coupling cancels, so only the residual needs to be shared across the block's lanes
   const T* F = bfac + (size_t)bz * 192;
-  T inb = 0;
-#pragma unroll
-  for (int jj = 0; jj < 8; ++jj) inb = fma(F[128 + k * 8 + jj], __shfl(xk, jj, 8), inb);
-  const T rhs = bk - ax + inb;
-  T v0 = 0, v1 = 0, w0 = 0, w1 = 0;
+  const T res = bk - ax;
+  // the noise field already holds sqrt(kT) L_BB^-T n for the block
+  T v0 = xk, v1 = NOISE ? nrm : T(0);
 #pragma unroll
   for (int jj = 0; jj < 8; jj += 2) {
-    v0 = fma(F[k * 8 + jj], __shfl(rhs, jj, 8), v0);
-    v1 = fma(F[k * 8 + jj + 1], __shfl(rhs, jj + 1, 8), v1);
-    if (NOISE) {
-      w0 = fma(F[64 + k * 8 + jj], __shfl(nrm, jj, 8), w0);
-      w1 = fma(F[64 + k * 8 + jj + 1], __shfl(nrm, jj + 1, 8), w1);
-    }
+    v0 = fma(F[k * 8 + jj], __shfl(res, jj, 8), v0);
+    v1 = fma(F[k * 8 + jj + 1], __shfl(res, jj + 1, 8), v1);
   }
-  T v = v0 + v1;
-  if (NOISE) v = fma(sqkT, w0 + w1, v);
+  const T v = v0 + v1;
   if (active) X[cell] = v;
 }
 
@@ -326,7 +350,7 @@ constexpr int BOT_TPB = 512;
 
 template <typename T, bool NOISE>
 __device__ __forceinline__ void bot_block_pass(T* X, const T* Bv, const BotLevel& L, const T* tab,
-                                               int colour, const T* Z, T sqkT) {
+                                               int colour, const T* Z) {
   // the 1D stencils are the same for every lane: scalar loads from the level descriptor
   T s1d[20];
 #pragma unroll
@@ -349,7 +373,7 @@ __device__ __forceinline__ void bot_block_pass(T* X, const T* Bv, const BotLevel
     uint32_t cell;
     const T v = block_lane<T, NOISE>(X, L.sy, L.sz, Bv, s1d, zt, bfac, L.nx, L.ny, L.nz,
                                      2 * i + (colour & 1), 2 * j + ((colour >> 1) & 1),
-                                     2 * l + (colour >> 2), k, active, Z, sqkT, cell);
+                                     2 * l + (colour >> 2), k, active, Z, cell);
     if (active) X[cell] = v;
   }
   __syncthreads();
@@ -357,13 +381,13 @@ __device__ __forceinline__ void bot_block_pass(T* X, const T* Bv, const BotLevel
 
 template <typename T, bool NOISE>
 __device__ __forceinline__ void bot_sweep(T* X, const T* Bv, const BotLevel& L, const T* tab,
-                                          int slot, bool post, int ncomp, uint32_t comp, T sqkT) {
+                                          int slot, bool post, int ncomp, uint32_t comp) {
   const int n = L.nx * L.ny * L.nz;
   const T* Z = NOISE ? (const T*)L.noise + ((size_t)slot * ncomp + comp) * n : nullptr;
 #pragma unroll 1
   for (int t = 0; t < 8; ++t) {
     const int colour = post ? 7 - t : t;
-    bot_block_pass<T, NOISE>(X, Bv, L, tab, colour, Z, sqkT);
+    bot_block_pass<T, NOISE>(X, Bv, L, tab, colour, Z);
   }
 }
 
@@ -380,7 +404,6 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
   const BotArgs& a = *ap;
   const uint32_t comp = blockIdx.x;
   const int tid = threadIdx.x;
-  const T sqkT = (T)na.sqkT;
   const BotLevel& L0 = a.lv[0];
   const int n0 = L0.nx * L0.ny * L0.nz;
   const int f0 = L0.nz * L0.sz;
@@ -444,11 +467,11 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
     }
     const T* tab = sm + a.tab_off[i];
     for (int s = 0; s < a.nu1; ++s)
-      bot_sweep<T, NOISE>(xi, bi, L, tab, s, false, a.ncomp, comp, sqkT);
+      bot_sweep<T, NOISE>(xi, bi, L, tab, s, false, a.ncomp, comp);
     if (i == a.nlev - 1) {
       // smoothing-only coarsest level: the post-sweeps follow at once
       for (int s = 0; s < a.nu2; ++s)
-        bot_sweep<T, NOISE>(xi, bi, L, tab, a.nu1 + s, true, a.ncomp, comp, sqkT);
+        bot_sweep<T, NOISE>(xi, bi, L, tab, a.nu1 + s, true, a.ncomp, comp);
       last = i;
       break;
     }
@@ -488,7 +511,7 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
     __syncthreads();
     for (int s = 0; s < a.nu2; ++s)
       bot_sweep<T, NOISE>(xi, xi + L.nz * L.sz, L, sm + a.tab_off[i], a.nu1 + s, true, a.ncomp,
-                          comp, sqkT);
+                          comp);
   }
   for (int q = tid; q < n0; q += BOT_TPB)
     ((T*)a.x_out)[(size_t)comp * n0 + q] = sm[a.lds_off[0] + bot_pos(L0, q)];
@@ -498,22 +521,22 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
 
 template <typename T, int TI, int TJ>
 void launch_block_tile(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx, int ny,
-                       int nz, int ncomp, int colour, const T* zn, double sqkT, int nbx2,
+                       int nz, int ncomp, int colour, const T* zn, int nbx2,
                        int nby2, int nbzc, hipStream_t s) {
   const uint32_t N = (uint32_t)nx * ny * nz;
   const int ntx = (nbx2 + TI - 1) / TI, nty = (nby2 + TJ - 1) / TJ;
   dim3 grid(ntx * nty, nbzc, ncomp);
   if (zn)
     k_block_tile<T, true, TI, TJ><<<grid, TI * TJ * 8, 0, s>>>(
-        x, b, s1d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, (T)sqkT);
+        x, b, s1d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn);
   else
     k_block_tile<T, false, TI, TJ><<<grid, TI * TJ * 8, 0, s>>>(
-        x, b, s1d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn, (T)sqkT);
+        x, b, s1d, zt, bfac, nx, ny, nz, N, colour, nbx2, nby2, ntx, zn);
 }
 
 template <typename T>
 hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
-                             int ny, int nz, int ncomp, int colour, const T* zn, double sqkT,
+                             int ny, int nz, int ncomp, int colour, const T* zn,
                              int tile, hipStream_t s) {
   const int nbx2 = nx / 4, nby2 = ny / 4;
   const int nbz = nz / 2;
@@ -525,11 +548,11 @@ hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const 
     tile = wg >= 512 ? SMG_TILE_4X4 : SMG_TILE_4X2;
   }
   if (tile == SMG_TILE_4X2)
-    launch_block_tile<T, 4, 2>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, sqkT, nbx2, nby2, nbzc, s);
+    launch_block_tile<T, 4, 2>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, nbx2, nby2, nbzc, s);
   else if (tile == SMG_TILE_8X4)
-    launch_block_tile<T, 8, 4>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, sqkT, nbx2, nby2, nbzc, s);
+    launch_block_tile<T, 8, 4>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, nbx2, nby2, nbzc, s);
   else
-    launch_block_tile<T, 4, 4>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, sqkT, nbx2, nby2, nbzc, s);
+    launch_block_tile<T, 4, 4>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, nbx2, nby2, nbzc, s);
   return hipGetLastError();
 }
 
@@ -573,14 +596,14 @@ hipError_t launch_coarsest(T* x, const T* b, const double* ainv, const double* w
 template <typename T>
 hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStream_t s) {
   if (a.total == 0 || a.nlev == 0) return hipSuccess;
-  uint32_t maxhalf = 0;
+  uint32_t maxblk = 0;
   int maxslot = 0;
   for (int e = 0; e < a.nlev; ++e) {
-    const uint32_t h = (uint32_t)a.lv[e].nx * a.lv[e].ny * a.lv[e].nz / 2;
-    maxhalf = h > maxhalf ? h : maxhalf;
+    const uint32_t nb = (uint32_t)a.lv[e].nx * a.lv[e].ny * a.lv[e].nz / 8;
+    maxblk = nb > maxblk ? nb : maxblk;
     maxslot = a.lv[e].nslot > maxslot ? a.lv[e].nslot : maxslot;
   }
-  dim3 grid(blocks_for(maxhalf), a.nlev, maxslot * a.nact);
+  dim3 grid(blocks_for(maxblk), a.nlev, maxslot * a.nact);
   k_level_noise<T><<<grid, TPB, 0, s>>>(a, na);
   return hipGetLastError();
 }
@@ -605,7 +628,7 @@ hipError_t launch_bottom(const BotArgs* a, int ncomp, size_t lds, bool noise, co
 
 #define SMG_INST(T)                                                                            \
   template hipError_t launch_block_pass<T>(T*, const T*, const T*, const T*, const T*, int, int, \
-                                           int, int, int, const T*, double, int, hipStream_t);  \
+                                           int, int, int, const T*, int, hipStream_t);          \
   template hipError_t launch_residual_gal<T>(T*, const T*, const T*, const T*, const T*, int,    \
                                              int, int, int, hipStream_t);                        \
   template hipError_t launch_restrict<T>(T*, T*, const T*, int, int, int, int, hipStream_t);    \
