@@ -18,9 +18,31 @@
 namespace smg {
 namespace {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// One DPP step of a wave reduction on a double: v + (v moved by CTRL), lanes outside ROW_MASK
+// adding zero.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long u = __double_as_longlong(v);
+  int lo, hi;
+  if (ROW_MASK == 0xf) {  // every lane is written: no old value to preset
+    lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xf, 0xf, false);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, ROW_MASK, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+  }
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes in a fixed order (pairs, quads, eighths, rows, then rows 0+1 into
+// row 1 and 2+3 into row 3, and the two halves into row 3); the total is in lane 63.
+__device__ __forceinline__ double wave_sum63(double v) {
+  v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
@@ -34,18 +56,18 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const uint32_t N = (uint32_t)nx * ny * nz;
-  const uint32_t hN = N >> 1;
-  const int nh = nx >> 1;
-  const double* Xr = a.xr + (size_t)comp * (SPLIT ? hN : N);
-  const double* Xb = SPLIT ? a.xb + (size_t)comp * hN : nullptr;
-  auto load = [&](int x, int y, int z) -> double {
-    if (SPLIT) {
-      const uint32_t i = ((uint32_t)z * ny + y) * nh + (x >> 1);
-      return ((x + y + z) & 1) ? Xb[i] : Xr[i];
-    }
-    return Xr[((uint32_t)z * ny + y) * nx + x];
+  const uint32_t plane = (uint32_t)nx * ny;
+  // Split storage: the cell with natural index i sits at entry i >> 1 of its colour's array
+  // (nx is even), and every face neighbour has the other colour.
+  const double* __restrict__ Xr = a.xr + (size_t)comp * (SPLIT ? N >> 1 : N);
+  const double* __restrict__ Xb = SPLIT ? a.xb + (size_t)comp * (N >> 1) : nullptr;
+  auto load = [&](uint32_t cell, int par) -> double {
+    if (SPLIT) return (par ? Xb : Xr)[cell >> 1];
+    return Xr[cell];
   };
-  TO* out = (TO*)a.out;
+  TO* __restrict__ out = a.out ? (TO*)a.out + (size_t)comp * N : nullptr;
+  double* __restrict__ m1 = MOM ? a.m1 + (size_t)comp * N : nullptr;
+  double* __restrict__ m2 = MOM ? a.m2 + (size_t)comp * N : nullptr;
   const int K = a.nmodes;
   // the mode tables are read-only for the kernel's lifetime: through the constant address
   // space the row factor of a mode (a uniform address when a wave lies in one row) becomes a
@@ -55,84 +77,141 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   const cptr trow = (cptr)a.trow;
   const uint32_t base = wg.x * STATS_CELLS;
   // A thread takes STATS_NB batches of STATS_CPT cells (TPB apart), all loads of a batch
-  // before its arithmetic.  When a wavefront lies in one row (UROW) the +x neighbour of a cell
-  // is the next lane's value and only the wave's last lane loads it, and a wave's cells are all
-  // inside the grid or all outside; when a thread's cells are whole rows apart (XSAME) they
-  // share their x, hence the x factors of the modes.  Mode tables are zero beyond the K modes
-  // in use, so the first KB <= 8 sums need no guard.
+  // before its arithmetic.  When a wavefront lies in one row (UROW) its row, y, z and the
+  // wall and range tests are wave-uniform (scalar), the +x neighbour of a cell is the next
+  // lane's value and only the wave's last lane loads it.  When a thread's cells are whole rows
+  // apart (XSAME) they share their x: the x factor of a mode multiplies the thread's sum once
+  // at the end.  Mode tables are zero beyond the K modes in use, so the first KB <= 8 sums
+  // need no guard.
   double acc[KB > 0 ? KB : 1];
 #pragma unroll
   for (int q = 0; q < (KB > 0 ? KB : 1); ++q) acc[q] = 0.0;
   double accE = 0.0;
-  double txs[KB > 0 ? KB : 1];
-  if (KB > 0 && XSAME) {
-    const uint32_t c0 = base + threadIdx.x;
-    const int x0 = (int)(c0 - udiv(c0, nx, a.lgx) * nx);
-#pragma unroll
-    for (int q = 0; q < KB; ++q) txs[q] = (KB <= 8 || q < K) ? tx[q * nx + x0] : 0.0;
-  }
+  if constexpr (UROW) {
 #pragma unroll 1
-  for (int bt = 0; bt < STATS_NB; ++bt) {
-    const uint32_t bbase = base + bt * (STATS_CPT * TPB);
-    double v[STATS_CPT], nb[STATS_CPT][3];
-    int cx[STATS_CPT], cy[STATS_CPT], cz[STATS_CPT];
-#pragma unroll
-    for (int c = 0; c < STATS_CPT; ++c) {
-      const uint32_t cell = bbase + c * TPB + threadIdx.x;
-      const bool in = UROW ? __builtin_amdgcn_readfirstlane(cell) < N : cell < N;
-      const uint32_t cc = in ? cell : 0;
-      const uint32_t row = udiv(cc, nx, a.lgx);
-      const int x = cc - row * nx;
-      const uint32_t zz = udiv(row, ny, a.lgy);
-      const int y = row - zz * ny, z = zz;
-      cx[c] = x;
-      cy[c] = y;
-      cz[c] = in ? z : -1;
-      v[c] = in ? load(x, y, z) : 0.0;
-      if (KB > 0) {
-        const int xp = x + 1 == nx ? 0 : x + 1;
-        nb[c][0] = (in && (!UROW || lane == 63)) ? load(xp, y, z) : 0.0;
-        nb[c][1] = in ? load(x, y + 1 == ny ? 0 : y + 1, z) : 0.0;
-        nb[c][2] = (in && z + 1 < nz) ? load(x, y, z + 1) : 0.0;
-      }
-    }
-    if (KB > 0 && UROW) {
+    for (int bt = 0; bt < STATS_NB; ++bt) {
+      const uint32_t bbase = base + bt * (STATS_CPT * TPB);
+      double v[STATS_CPT], ny1[STATS_CPT], nz1[STATS_CPT], nx1[STATS_CPT];
+      int xs[STATS_CPT];
+      uint32_t rows[STATS_CPT], zs[STATS_CPT];
 #pragma unroll
       for (int c = 0; c < STATS_CPT; ++c) {
-        const double nxt = __shfl_down(v[c], 1, 64);
-        if (lane != 63) nb[c][0] = nxt;
+        const uint32_t cell = bbase + c * TPB + threadIdx.x;
+        const uint32_t cell0 = __builtin_amdgcn_readfirstlane(cell - lane);  // the wave's row
+        const bool in = cell0 < N;
+        const uint32_t row = udiv(in ? cell0 : 0, nx, a.lgx);
+        const uint32_t z = udiv(row, ny, a.lgy);
+        const uint32_t y = row - z * ny;
+        const int x = (int)(cell - row * nx);
+        const int par = (x + (int)(y + z)) & 1;
+        rows[c] = in ? row : 0xffffffffu;
+        zs[c] = z;
+        xs[c] = x;
+        v[c] = 0.0;
+        nx1[c] = ny1[c] = nz1[c] = 0.0;
+        if (in) {
+          v[c] = load(cell, par);
+          if (KB > 0) {
+            ny1[c] = load(y + 1 == (uint32_t)ny ? cell - (plane - nx) : cell + nx, par ^ 1);
+            if (z + 1 < (uint32_t)nz) nz1[c] = load(cell + plane, par ^ 1);
+            if (lane == 63) nx1[c] = load(x + 1 == nx ? cell + 1 - nx : cell + 1, par ^ 1);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < STATS_CPT; ++c) {
+        if (rows[c] == 0xffffffffu) continue;
+        const uint32_t cell = bbase + c * TPB + threadIdx.x;
+        const double x0 = v[c];
+        if (out) out[cell] = (TO)x0;
+        if (MOM) {
+          m1[cell] += x0;
+          m2[cell] = fma(x0, x0, m2[cell]);
+        }
+        if (KB > 0) {
+          const uint32_t row = rows[c], z = zs[c];
+          const cptr tr = trow + (size_t)row * KB;
+#pragma unroll
+          for (int q = 0; q < KB; ++q)
+            if (KB <= 8 || q < K)
+              acc[q] = XSAME ? fma(tr[q], x0, acc[q])
+                             : fma(tx[q * nx + xs[c]] * tr[q], x0, acc[q]);
+          // faces +x, +y (periodic) and +z (interior), plus the wall faces (ghost = -v)
+          const double nxt = __shfl_down(x0, 1, 64);
+          const double d1 = x0 - (lane == 63 ? nx1[c] : nxt);
+          const double d2 = x0 - ny1[c];
+          double e = fma(d1, d1, d2 * d2);
+          if (z + 1 < (uint32_t)nz) {
+            const double d3 = x0 - nz1[c];
+            e = fma(d3, d3, e);
+          }
+          if (z == 0) e = fma(2.0 * x0, x0, e);
+          if (z == (uint32_t)nz - 1) e = fma(2.0 * x0, x0, e);
+          accE += e;
+        }
       }
     }
+    if (KB > 0 && XSAME) {
+      const uint32_t c0 = base + threadIdx.x;
+      const int x0 = (int)(c0 - udiv(c0, nx, a.lgx) * nx);
 #pragma unroll
-    for (int c = 0; c < STATS_CPT; ++c) {
-      if (cz[c] < 0) continue;
-      const size_t gi = (size_t)comp * N + bbase + c * TPB + threadIdx.x;
-      const double x0 = v[c];
-      if (out) out[gi] = (TO)x0;
-      if (MOM) {
-        a.m1[gi] += x0;
-        a.m2[gi] = fma(x0, x0, a.m2[gi]);
-      }
-      if (KB > 0) {
-        const int z = cz[c];
-        uint32_t row = (uint32_t)z * ny + cy[c];
-        if (UROW) row = __builtin_amdgcn_readfirstlane(row);  // the wavefront lies in one row
+      for (int q = 0; q < KB; ++q)
+        if (KB <= 8 || q < K) acc[q] *= tx[q * nx + x0];
+    }
+  } else {
+#pragma unroll 1
+    for (int bt = 0; bt < STATS_NB; ++bt) {
+      const uint32_t bbase = base + bt * (STATS_CPT * TPB);
+      double v[STATS_CPT], nb[STATS_CPT][3];
+      int cx[STATS_CPT], cz[STATS_CPT];
+      uint32_t rows[STATS_CPT];
 #pragma unroll
-        for (int q = 0; q < KB; ++q)
-          if (KB <= 8 || q < K)
-            acc[q] = fma((XSAME ? txs[q] : tx[q * nx + cx[c]]) * trow[(size_t)row * KB + q], x0,
-                         acc[q]);
-        // faces +x, +y (periodic) and +z (interior), plus the wall faces (ghost = -v)
-        const double d1 = x0 - nb[c][0];
-        const double d2 = x0 - nb[c][1];
-        double e = fma(d1, d1, d2 * d2);
-        if (z + 1 < nz) {
-          const double d3 = x0 - nb[c][2];
-          e = fma(d3, d3, e);
+      for (int c = 0; c < STATS_CPT; ++c) {
+        const uint32_t cell = bbase + c * TPB + threadIdx.x;
+        const bool in = cell < N;
+        const uint32_t cc = in ? cell : 0;
+        const uint32_t row = udiv(cc, nx, a.lgx);
+        const int x = cc - row * nx;
+        const uint32_t zz = udiv(row, ny, a.lgy);
+        const int y = row - zz * ny, z = zz;
+        const int par = (x + y + z) & 1;
+        cx[c] = x;
+        rows[c] = row;
+        cz[c] = in ? z : -1;
+        v[c] = in ? load(cc, par) : 0.0;
+        if (KB > 0) {
+          nb[c][0] = in ? load(x + 1 == nx ? cc + 1 - nx : cc + 1, par ^ 1) : 0.0;
+          nb[c][1] = in ? load(y + 1 == ny ? cc - (plane - nx) : cc + nx, par ^ 1) : 0.0;
+          nb[c][2] = (in && z + 1 < nz) ? load(cc + plane, par ^ 1) : 0.0;
         }
-        if (z == 0) e = fma(2.0 * x0, x0, e);
-        if (z == nz - 1) e = fma(2.0 * x0, x0, e);
-        accE += e;
+      }
+#pragma unroll
+      for (int c = 0; c < STATS_CPT; ++c) {
+        if (cz[c] < 0) continue;
+        const uint32_t cell = bbase + c * TPB + threadIdx.x;
+        const double x0 = v[c];
+        if (out) out[cell] = (TO)x0;
+        if (MOM) {
+          m1[cell] += x0;
+          m2[cell] = fma(x0, x0, m2[cell]);
+        }
+        if (KB > 0) {
+          const int z = cz[c];
+#pragma unroll
+          for (int q = 0; q < KB; ++q)
+            if (KB <= 8 || q < K)
+              acc[q] = fma(tx[q * nx + cx[c]] * a.trow[(size_t)rows[c] * KB + q], x0, acc[q]);
+          const double d1 = x0 - nb[c][0];
+          const double d2 = x0 - nb[c][1];
+          double e = fma(d1, d1, d2 * d2);
+          if (z + 1 < nz) {
+            const double d3 = x0 - nb[c][2];
+            e = fma(d3, d3, e);
+          }
+          if (z == 0) e = fma(2.0 * x0, x0, e);
+          if (z == nz - 1) e = fma(2.0 * x0, x0, e);
+          accE += e;
+        }
       }
     }
   }
@@ -140,8 +219,9 @@ __global__ __launch_bounds__(TPB) void k_stats(StatsArgs a) {
   __shared__ double red[4][KB + 1];
 #pragma unroll
   for (int q = 0; q <= KB; ++q) {
-    const double s = wave_sum(q < KB ? acc[q] : accE);
-    if (lane == 0) red[w][q] = s;
+    if (q < KB && !(KB <= 8 || q < K)) continue;
+    const double s = wave_sum63(q < KB ? acc[q] : accE);
+    if (lane == 63) red[w][q] = s;
   }
   __syncthreads();
   const int q = threadIdx.x;
