@@ -197,7 +197,7 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
     T* __restrict__ bc, T* __restrict__ xc, const T* __restrict__ xr, const T* __restrict__ xb,
     const T* __restrict__ br, const T* __restrict__ bb, int nx, int ny, int nz, int ntx,
     T inv_h2) {
-  __shared__ T Xs[4 * RR_XP];
+  __shared__ T Xs[4 * RR_XP + 1];  // + a pad element for positions past the plane
   __shared__ T Rs[2 * RR_RP];
   const Blk3 wg = xcd_block();
   const uint32_t comp = wg.z;
@@ -210,15 +210,21 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
   const int tid = threadIdx.x;
   // x positions this thread stages (box origin 2X0-2, 2Y0-2) and residual positions it forms
   // (window origin 2X0-1, 2Y0-1)
-  int gxs[RR_PPT], gys[RR_PPT], xoff[RR_PPT];
+  // per staged position: its entry within a plane of the split arrays and its colour in
+  // plane 0 (the colour alternates with the plane)
+  uint32_t xent[RR_PPT];
+  int xpar[RR_PPT], xoff[RR_PPT];
 #pragma unroll
   for (int p = 0; p < RR_PPT; ++p) {
     const int pos = tid + p * TPB;
     const int sx = pos % RR_SX, sy = pos / RR_SX;
     xoff[p] = pos < RR_XP ? pos : -1;
-    gxs[p] = wrap_near(2 * X0 - 2 + sx, nx);
-    gys[p] = pos < RR_XP ? wrap_near(2 * Y0 - 2 + sy, ny) : 0;
+    const int gx = wrap_near(2 * X0 - 2 + sx, nx);
+    const int gy = pos < RR_XP ? wrap_near(2 * Y0 - 2 + sy, ny) : 0;
+    xent[p] = (uint32_t)gy * nh + (gx >> 1);
+    xpar[p] = (gx + gy) & 1;
   }
+  const uint32_t hplane = (uint32_t)nh * ny;
   int roff[RR_RPT], rxo[RR_RPT];
 #pragma unroll
   for (int p = 0; p < RR_RPT; ++p) {
@@ -230,14 +236,16 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
   const int f0 = 2 * Z0 - 1, f1 = 2 * (Z0 + zc);  // residual planes of the column
   auto load_plane = [&](T (&reg)[RR_PPT], int g) {
     g = g < 0 ? 0 : (g >= nz ? nz - 1 : g);  // planes beyond the walls are never read
+    const T* pr = xr + cb + (size_t)g * hplane;
+    const T* pb = xb + cb + (size_t)g * hplane;
 #pragma unroll
-    for (int p = 0; p < RR_PPT; ++p) reg[p] = split_at(xr, xb, cb, gxs[p], gys[p], g, nh, ny);
+    for (int p = 0; p < RR_PPT; ++p) reg[p] = ((xpar[p] ^ g) & 1 ? pb : pr)[xent[p]];
   };
   auto store_plane = [&](const T (&reg)[RR_PPT], int g) {
-    T* P = Xs + (g & 3) * RR_XP;
+    const int slot = (g & 3) * RR_XP;
 #pragma unroll
-    for (int p = 0; p < RR_PPT; ++p)
-      if (xoff[p] >= 0) P[xoff[p]] = reg[p];
+    for (int p = 0; p < RR_PPT; ++p)  // positions past the plane store into the pad element
+      Xs[xoff[p] >= 0 ? slot + xoff[p] : 4 * RR_XP] = reg[p];
   };
   auto load_b = [&](T (&reg)[RR_RPT], int f) {
     const int g = f < 0 ? 0 : (f >= nz ? nz - 1 : f);
@@ -412,6 +420,59 @@ __global__ __launch_bounds__(TPB) void k_prolong0(T* __restrict__ xr, T* __restr
   X[p] += prolong_at<T>(e + (size_t)comp * Nc, nxc, nxc * nyc, xf, yf, zf, nxc, nyc, nzf >> 1);
 }
 
+// The same for nx/2 even, two sites per thread: sites j0 = 2jp and j0 + 1 of a colour row sit
+// two cells apart, so their trilinear windows share the coarse row pairs and two of three
+// coarse columns (12 loads of e for both), and x moves with one 16-byte load and store.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_prolong0_pair(T* __restrict__ xr, T* __restrict__ xb,
+                                                        const T* __restrict__ e, int nxf, int nyf,
+                                                        int nzf, uint32_t npairs, uint32_t Nc,
+                                                        int cfirst) {
+  using V2 = typename Vec2<T>::type;
+  const uint32_t comp = blockIdx.y;
+  const int colour = cfirst + blockIdx.z;
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= npairs) return;
+  const int nh = nxf >> 1, nhp = nh >> 1;
+  const uint32_t row = t / nhp;
+  const int jp = t - row * nhp;
+  const int yf = row % nyf;
+  const int zf = row / nyf;
+  const int sx = (yf + zf + colour) & 1;  // x = 2j + sx
+  const int j0 = 2 * jp;
+  const int nxc = nxf >> 1, nyc = nyf >> 1, nzc = nzf >> 1;
+  // coarse columns: own parents j0, j0+1; the other parent of each lies on the side of sx
+  const int Xm = j0 == 0 ? nxc - 1 : j0 - 1, Xa = j0, Xb = j0 + 1;
+  const int Xp = j0 + 2 == nxc ? 0 : j0 + 2;
+  const int Y0 = yf >> 1;
+  const int Y1 = (yf & 1) ? (Y0 + 1 == nyc ? 0 : Y0 + 1) : (Y0 == 0 ? nyc - 1 : Y0 - 1);
+  const int Z0 = zf >> 1;
+  int Z1 = (zf & 1) ? Z0 + 1 : Z0 - 1;
+  T wz0 = T(0.75), wz1 = T(0.25);
+  if (Z1 < 0 || Z1 >= nzc) {
+    wz0 = T(0.5);
+    wz1 = T(0);
+    Z1 = Z0;
+  }
+  const T* E = e + (size_t)comp * Nc;
+  const T* r00 = E + ((size_t)Z0 * nyc + Y0) * nxc;
+  const T* r01 = E + ((size_t)Z0 * nyc + Y1) * nxc;
+  const T* r10 = E + ((size_t)Z1 * nyc + Y0) * nxc;
+  const T* r11 = E + ((size_t)Z1 * nyc + Y1) * nxc;
+  T* X = (colour ? xb : xr) + (size_t)comp * (npairs * 2);
+  V2 xv = *reinterpret_cast<const V2*>(X + 2 * t);
+  // site a: own Xa, other (sx ? Xb : Xm); site b: own Xb, other (sx ? Xp : Xa)
+  const int Xoa = sx ? Xb : Xm, Xob = sx ? Xp : Xa;
+  const T q = T(0.75), o = T(0.25);
+  const T pa0 = q * (q * r00[Xa] + o * r00[Xoa]) + o * (q * r01[Xa] + o * r01[Xoa]);
+  const T pa1 = q * (q * r10[Xa] + o * r10[Xoa]) + o * (q * r11[Xa] + o * r11[Xoa]);
+  const T pb0 = q * (q * r00[Xb] + o * r00[Xob]) + o * (q * r01[Xb] + o * r01[Xob]);
+  const T pb1 = q * (q * r10[Xb] + o * r10[Xob]) + o * (q * r11[Xb] + o * r11[Xob]);
+  xv.x += wz0 * pa0 + wz1 * pa1;
+  xv.y += wz0 * pb0 + wz1 * pb1;
+  *reinterpret_cast<V2*>(X + 2 * t) = xv;
+}
+
 __global__ __launch_bounds__(TPB) void k_to_split(double* __restrict__ xr,
                                                    double* __restrict__ xb,
                                                    const double* __restrict__ nat, int nx,
@@ -519,6 +580,12 @@ hipError_t launch_prolong0(T* xr, T* xb, const T* e, int nxf, int nyf, int nzf, 
   const uint32_t Nc = (uint32_t)(nxf / 2) * (nyf / 2) * (nzf / 2);
   colours &= 3;
   if (colours == 0) return hipSuccess;
+  if ((nxf / 2) % 2 == 0) {
+    dim3 grid(blocks_for(nsite / 2), ncomp, colours == 3 ? 2 : 1);
+    k_prolong0_pair<T><<<grid, TPB, 0, s>>>(xr, xb, e, nxf, nyf, nzf, nsite / 2, Nc,
+                                            colours == 2 ? 1 : 0);
+    return hipGetLastError();
+  }
   dim3 grid(blocks_for(nsite), ncomp, colours == 3 ? 2 : 1);
   k_prolong0<T><<<grid, TPB, 0, s>>>(xr, xb, e, nxf, nyf, nzf, nsite, Nc, colours == 2 ? 1 : 0);
   return hipGetLastError();

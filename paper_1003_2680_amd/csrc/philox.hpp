@@ -73,13 +73,17 @@ inline __host__ __device__ BoxMullerCoef box_muller_coef() {
        -0x1.3bd3cc9be45dep+2}};
 }
 
-// Philox key, counter words 1..3 for component `comp` of stream `sid`.
+// Philox key, counter words 1..3 for component `comp` of stream `sid`.  Every caller draws
+// for one component per work-group, so `comp` is wave-uniform: taking it from the first lane
+// lets the chain lookup, the key and the key schedule of the rounds run on the scalar unit.
 __device__ __forceinline__ void noise_key(const NoiseArgs& na, uint32_t sid, uint32_t comp,
                                           uint32_t& k0, uint32_t& k1, uint32_t& w1, uint32_t& w2,
                                           uint32_t& w3) {
+  comp = __builtin_amdgcn_readfirstlane(comp);
   if (na.chains) {
     const uint32_t ch = comp / na.comps_per_chain;
-    const ChainKey key = na.chains[ch];
+    // the chain table is read-only while kernels run: a scalar load through the constant space
+    const ChainKey key = ((const __attribute__((address_space(4))) ChainKey*)na.chains)[ch];
     const uint64_t cyc = (((uint64_t)key.c1 << 32) | key.c0) + (((uint64_t)na.c3 << 32) | na.c2);
     k0 = key.k0;
     k1 = key.k1;
