@@ -96,6 +96,62 @@ __device__ __forceinline__ T gal_plane(const T* __restrict__ P, int sy, const in
   return p0;
 }
 
+// v of the lane two apart in the same quad (lane ^ 2) by one DPP move per 32-bit half.
+__device__ __forceinline__ double dpp_xor2(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)u, 0x4E, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0x4E, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float dpp_xor2(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xf, 0xf, false));
+}
+
+// The in-plane sums of gal_plane for the two cells (x, y) and (x, y+1) of a block column,
+// shared by the lanes ky = 0, 1 (lane ^ 2).  Together they need the six rows y-2 .. y+3; each
+// lane reduces three of them along x, rows[i] = y_lane + s (i - 2) with s = +1 for ky = 0 and
+// -1 for ky = 1, i.e. the outer three rows of its own window listed from its far edge inwards.
+// The periodic 1D factors m_y, a_y are symmetric, so in that order both lanes weight rows i by
+// factor i for their own cell, and rows 1, 2 by factors 0, 1 for the partner's cell; the
+// partner's share arrives by one DPP move.  15 LDS reads and 51 instructions per lane instead
+// of 25 and 65.  Every lane of the quad must call this.
+template <typename T>
+__device__ __forceinline__ void gal_plane_pair(const T* __restrict__ P, int sy, const int* xs,
+                                               const int (&rows)[3], const T* s1d, T& q0,
+                                               T& q1) {
+  T rm[3], ra[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T* row = P + (size_t)rows[i] * sy;
+    T sm = 0, sa = 0;
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx) {
+      const T v = row[xs[dx]];
+      sm = fma(s1d[dx], v, sm);
+      sa = fma(s1d[5 + dx], v, sa);
+    }
+    rm[i] = sm;
+    ra[i] = sa;
+  }
+  const T* my = s1d + 10;
+  const T* ay = s1d + 15;
+  T o0 = 0, o1 = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    o0 = fma(my[i], rm[i], o0);
+    o1 = fma(ay[i], rm[i], o1);
+    o1 = fma(my[i], ra[i], o1);
+  }
+  T p0 = my[0] * rm[1];
+  p0 = fma(my[1], rm[2], p0);
+  T p1 = ay[0] * rm[1];
+  p1 = fma(ay[1], rm[2], p1);
+  p1 = fma(my[0], ra[1], p1);
+  p1 = fma(my[1], ra[2], p1);
+  q0 = o0 + dpp_xor2(p0);
+  q1 = o1 + dpp_xor2(p1);
+}
+
 // UNROLL_Z: all five planes in flight at once (global-memory operands, where load latency
 // dominates); otherwise one plane at a time (LDS operands, fewer registers).
 template <typename T, bool UNROLL_Z = false>
@@ -173,18 +229,19 @@ __device__ __forceinline__ T block_lane(const T* __restrict__ X, int sy, int sz,
     // walls, where their factors vanish): lane kz reduces planes 3kz .. 3kz+2 and trades them
     // with its partner lane ^ 4.  Every lane takes part (the shuffles need the partner).
     const int kz = k >> 2;
-    int xs[5], ys[5];
+    int xs[5];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      xs[d] = wrapm(cx + d - 2, nx);
-      ys[d] = wrapm(cy + d - 2, ny);
-    }
+    for (int d = 0; d < 5; ++d) xs[d] = wrapm(cx + d - 2, nx);
+    const int ky = (k >> 1) & 1;
+    int rows[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rows[i] = wrapm(cy + (ky ? 2 - i : i - 2), ny);
     T q0[3], q1[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       int pz = 2 * bz - 2 + 3 * kz + j;
       pz = pz < 0 ? 0 : (pz >= nz ? nz - 1 : pz);
-      q0[j] = gal_plane<T>(X + (size_t)pz * sz, sy, xs, ys, s1d, q1[j]);
+      gal_plane_pair<T>(X + (size_t)pz * sz, sy, xs, rows, s1d, q0[j], q1[j]);
     }
     T o0[3], o1[3], w0[5], w1[5];
 #pragma unroll

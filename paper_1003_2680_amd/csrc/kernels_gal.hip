@@ -157,11 +157,13 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
     // The two z-layers of a block reach the same six staged planes (tile planes 0..5).  Lane
     // kz computes the in-plane sums of planes 3kz .. 3kz+2 and trades them with its partner
     // (lane ^ 4, same x and y), so each plane is reduced once per (x, y) pair, not twice.
+    // and each plane's rows are shared with the y-partner (lane ^ 2) the same way
     const int xs[5] = {tx - 2, tx - 1, tx, tx + 1, tx + 2};
-    const int ys[5] = {ty - 2, ty - 1, ty, ty + 1, ty + 2};
+    const int rows[3] = {ky ? ty + 2 : ty - 2, ty + (ky ? 1 : -1), ty};
     T q0[3], q1[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) q0[j] = gal_plane<T>(Tl + (3 * kz + j) * TP, TILE_W, xs, ys, s1d, q1[j]);
+    for (int j = 0; j < 3; ++j)
+      gal_plane_pair<T>(Tl + (3 * kz + j) * TP, TILE_W, xs, rows, s1d, q0[j], q1[j]);
     T o0[3], o1[3], w0[5], w1[5];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {

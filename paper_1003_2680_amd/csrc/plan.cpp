@@ -36,6 +36,9 @@ void coarsen_stencil(const double s[5], double out[5]) {
       }
     out[D + 2] = acc;
   }
+  // the coarse stencil is symmetric; make it so to the last bit (the block kernels rely on it)
+  out[3] = out[1];
+  out[4] = out[0];
 }
 
 // Dense wall-axis prolongation (2nc x nc, row-major); the ghost beyond a wall is -c_J.
