@@ -63,28 +63,40 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_v2(T* __restrict__ xc, const T*
   const int ys = (y == 0) ? ny - 1 : y - 1;
   const V2 n2 = *reinterpret_cast<const V2*>(o + (z * ny + yn) * nh + j0);
   const V2 s2 = *reinterpret_cast<const V2*>(o + (z * ny + ys) * nh + j0);
-  V2 u2, d2;
-  u2.x = u2.y = d2.x = d2.y = T(0);
-  int nw = 0;
-  if (z + 1 < (uint32_t)nz) u2 = *reinterpret_cast<const V2*>(o + rb + plane + j0); else ++nw;
-  if (z > 0) d2 = *reinterpret_cast<const V2*>(o + rb - plane + j0); else ++nw;
+  // the planes above and below, clamped at the walls (a wall side is masked after the loads,
+  // so that no load sits in a branch and every load is in flight at once)
+  const bool top = z + 1 >= (uint32_t)nz, bottom = z == 0;
+  V2 u2 = *reinterpret_cast<const V2*>(o + rb + (top ? 0 : plane) + j0);
+  V2 d2 = *reinterpret_cast<const V2*>(o + rb - (bottom ? 0 : plane) + j0);
+  const int nw = (int)top + (int)bottom;
+  const T idg = dg.inv_d[nw], sgm = dg.sig[nw];  // loaded now, used after the noise
+  V2 b2;
+  if (HAS_B) b2 = *reinterpret_cast<const V2*>(bc + base + rb + j0);
+  // The normals depend on no load: with every load issued above, the Philox and Box-Muller
+  // arithmetic runs while they are in flight (the scheduling barriers keep the compiler from
+  // hoisting the sums, which wait for the loads, in front of it).
+  T z0 = T(0), z1 = T(0);
+  if (NOISE) {
+    __builtin_amdgcn_sched_barrier(0);
+    normal_pair_t<T>(na, comp, row * nhp + jp, z0, z1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (top) u2.x = u2.y = T(0);
+  if (bottom) d2.x = d2.y = T(0);
   // x-neighbour pairs: xs == 0 -> (j-1, j), xs == 1 -> (j, j+1)
   const T xa0 = xs ? c2.x : ex, xb0 = xs ? c2.y : c2.x;
   const T xa1 = xs ? c2.y : c2.x, xb1 = xs ? ex : c2.y;
   T v0 = ((xa0 + xb0) + (n2.x + s2.x) + (u2.x + d2.x)) * inv_h2;
   T v1 = ((xa1 + xb1) + (n2.y + s2.y) + (u2.y + d2.y)) * inv_h2;
   if (HAS_B) {
-    const V2 b2 = *reinterpret_cast<const V2*>(bc + base + rb + j0);
     v0 += b2.x;
     v1 += b2.y;
   }
-  v0 *= dg.inv_d[nw];
-  v1 *= dg.inv_d[nw];
+  v0 *= idg;
+  v1 *= idg;
   if (NOISE) {
-    T z0, z1;
-    normal_pair_t<T>(na, comp, row * nhp + jp, z0, z1);
-    v0 = fma(dg.sig[nw], z0, v0);
-    v1 = fma(dg.sig[nw], z1, v1);
+    v0 = fma(sgm, z0, v0);
+    v1 = fma(sgm, z1, v1);
   }
   V2 out;
   out.x = v0;

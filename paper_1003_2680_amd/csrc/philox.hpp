@@ -82,8 +82,14 @@ __device__ __forceinline__ void noise_key(const NoiseArgs& na, uint32_t sid, uin
   comp = __builtin_amdgcn_readfirstlane(comp);
   if (na.chains) {
     const uint32_t ch = comp / na.comps_per_chain;
-    // the chain table is read-only while kernels run: a scalar load through the constant space
-    const ChainKey key = ((const __attribute__((address_space(4))) ChainKey*)na.chains)[ch];
+    // the chain table is read-only while kernels run: scalar loads through the constant space
+    typedef const __attribute__((address_space(4))) uint32_t* cword;
+    const cword kw = (cword)(const void*)(na.chains + ch);
+    ChainKey key;
+    key.k0 = kw[0];
+    key.k1 = kw[1];
+    key.c0 = kw[2];
+    key.c1 = kw[3];
     const uint64_t cyc = (((uint64_t)key.c1 << 32) | key.c0) + (((uint64_t)na.c3 << 32) | na.c2);
     k0 = key.k0;
     k1 = key.k1;
