@@ -186,13 +186,13 @@ __global__ __launch_bounds__(TPB) void k_residual0(T* __restrict__ r, const T* _
 // A work-group owns an RR_X x RR_Y column of coarse cells over up to RR_Z coarse layers and
 // marches up through the fine planes of their restriction windows, [2Z0-1, 2Z0+2RZ].  For
 // each fine plane f it stages x plane f+1 into a ring of four LDS planes (the global loads
-// of the planes two steps ahead are in flight meanwhile), forms the residual of plane f over
-// the 18 x 18 window of the column, and every coarse cell of the column takes that plane's
-// 4x4 window sum (weights 1/4, 3/4, 3/4, 1/4 per axis; 1/2 for a fine cell next to a wall)
-// into the running sums of the two coarse layers the plane belongs to: four lanes per coarse
-// cell, one window column each, joined by shuffles.  Each x plane is loaded once per column and
-// each residual plane formed once, instead of once per coarse layer pair.  Also zeroes the
-// coarse iterate when xc is not null.
+// of the planes up to four steps ahead are in flight meanwhile), forms the residual of
+// plane f over the 18 x 18 window of the column, and every coarse cell of the column takes
+// that plane's 4x4 window sum (weights 1/4, 3/4, 3/4, 1/4 per axis; 1/2 for a fine cell next
+// to a wall) into the running sums of the two coarse layers the plane belongs to: four lanes
+// per coarse cell, one window column each, joined by shuffles.  Each x plane is loaded once
+// per column and each residual plane formed once, instead of once per coarse layer pair.
+// Also zeroes the coarse iterate when xc is not null.
 constexpr int RR_X = 8, RR_Y = 8, RR_Z = 8;
 constexpr int RR_FX = 2 * RR_X + 2, RR_FY = 2 * RR_Y + 2;  // residual window of a plane
 constexpr int RR_SX = RR_FX + 2, RR_SY = RR_FY + 2;        // x box of a plane
@@ -202,6 +202,7 @@ constexpr int RR_XP = RR_SX * RR_SY;                       // x plane in LDS
 constexpr int RR_RP = RR_SX * RR_FY;                       // residual plane in LDS
 constexpr int RR_PPT = (RR_XP + TPB - 1) / TPB;            // x positions per thread
 constexpr int RR_RPT = (RR_RP + TPB - 1) / TPB;            // residual positions per thread
+constexpr int RR_PF = 4;                                   // x planes loaded ahead
 static_assert(RR_X * RR_Y * 4 == TPB, "four lanes per coarse cell of the column");
 
 template <typename T, bool HAS_B>
@@ -275,11 +276,11 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
   const int X = X0 + lx, Y = Y0 + ly;
   const bool owner = wb == 0 && X < nxc && Y < nyc;
   T acc0 = 0, acc1 = 0;  // running sums of the even and the odd coarse layer
-  // one fine plane f: stage x plane f+1 (held in `cur`), start loading plane f+3 into `cur`
-  // once stored, form the residual of plane f, and take its window sums
+  // one fine plane f: stage x plane f+1 (held in `cur`), start loading plane f+1+RR_PF into
+  // `cur` once stored, form the residual of plane f, and take its window sums
   auto step = [&](int f, T (&cur)[RR_PPT], T (&bcur)[RR_RPT]) {
     store_plane(cur, f + 1);
-    if (f + 3 <= f1 + 1) load_plane(cur, f + 3);
+    if (f + 1 + RR_PF <= f1 + 1) load_plane(cur, f + 1 + RR_PF);
     __syncthreads();
     T* R = Rs + (f & 1) * RR_RP;
     if (f >= 0 && f < nz) {
@@ -336,25 +337,34 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
     if (Z & 1) acc1 = T(0);
     else acc0 = T(0);
   };
-  // prologue: planes f0-1 and f0 in the ring, f0+1 and f0+2 in registers
-  T ra[RR_PPT], rb[RR_PPT], ba[RR_RPT], bbn[RR_RPT];
-  load_plane(ra, f0 - 1);
-  load_plane(rb, f0);
+  // prologue: planes f0-1 and f0 in the ring, f0+1 .. f0+RR_PF in the register sets
+  T r0[RR_PPT], r1[RR_PPT], r2[RR_PPT], r3[RR_PPT], ba[RR_RPT], bbn[RR_RPT];
+  load_plane(r0, f0 - 1);
+  load_plane(r1, f0);
   if (HAS_B) {
     load_b(ba, f0);
     load_b(bbn, f0 + 1);
   }
-  store_plane(ra, f0 - 1);
-  store_plane(rb, f0);
-  load_plane(ra, f0 + 1);
-  load_plane(rb, f0 + 2);
-  // the column has 2 zc + 2 planes: an even count, taken two at a time so the two register
-  // sets keep their roles
-  for (int f = f0; f <= f1; f += 2) {
-    step(f, ra, ba);
+  store_plane(r0, f0 - 1);
+  store_plane(r1, f0);
+  load_plane(r0, f0 + 1);
+  load_plane(r1, f0 + 2);
+  if (f0 + 3 <= f1 + 1) load_plane(r2, f0 + 3);
+  if (f0 + 4 <= f1 + 1) load_plane(r3, f0 + 4);
+  // RR_PF planes at a time, so that the register sets keep their roles (x planes RR_PF ahead,
+  // b two ahead)
+  for (int f = f0; f <= f1; f += RR_PF) {
+    step(f, r0, ba);
     finish(f);
-    step(f + 1, rb, bbn);
+    if (f + 1 > f1) break;
+    step(f + 1, r1, bbn);
     finish(f + 1);
+    if (f + 2 > f1) break;
+    step(f + 2, r2, ba);
+    finish(f + 2);
+    if (f + 3 > f1) break;
+    step(f + 3, r3, bbn);
+    finish(f + 3);
   }
 }
 
