@@ -15,7 +15,9 @@ value = decorrelated samples/s = emitted samples/s / k_dec with
 k_dec = max(1, ceil(ln 0.01 / ln rho)), rho the larger of the measured contraction of the
 deterministic cycle (the lag-k correlation of the stochastic iteration is R^k applied to the
 stationary covariance) and the largest measured lag-1 autocorrelation of the observables.
-Also reported: per-step p50/p99 latency; 10 solves to 1e-12 (batched throughput and single
+Also reported: the integrated autocorrelation time of each observable; per-step p50/p99
+latency; one FP64 chain on a single 512x512x256 grid, whose fields exceed the 256 MB Infinity
+Cache (cycles/s and the level-0 pass against HBM); 10 solves to 1e-12 (batched throughput and single
 latency); the roofline of the dominant kernel class (per-launch time from HIP events around
 each sweep's launches) and of the other; and the CPU oracle on a bounded sample.
 
@@ -96,7 +98,7 @@ def cpu_baseline(k_dec, cycles=3):
         dt = (time.perf_counter() - t0) / cycles
     per_field_cycle = dt * NCOMP
     return {"value": round(1.0 / per_field_cycle / k_dec, 6), "unit": "decorrelated samples/s",
-            "cores": 1, "kind": "oracle",
+            "cores": 1, "kind": "oracle", "host": host_info(),
             "sample": "%d V(2,2) cycles of one component of the 128^3 6-level FP64 chain "
                       "(%.2f s/cycle), scaled to the 3-component field; hierarchy set-up "
                       "excluded; NumPy/SciPy limited to one thread" % (cycles, dt)}
@@ -124,6 +126,40 @@ def lag1(obs):
     num = (o[:-1] * o[1:]).sum(axis=(0, 1))
     den = (o * o).sum(axis=(0, 1))
     return num / den
+
+
+def tau_int(obs, c=5.0):
+    """Integrated autocorrelation time 1 + 2 sum_k rho(k) of each observable (pooled over
+    components), summed up to the first lag k >= c tau(k) (Sokal's self-consistent window)."""
+    import numpy as np
+    o = obs - obs.mean(axis=0, keepdims=True)
+    den = (o * o).sum(axis=(0, 1))
+    T = o.shape[0]
+    taus = []
+    for q in range(o.shape[2]):
+        tau = 1.0
+        for k in range(1, T // 2):
+            rho = float((o[:-k, :, q] * o[k:, :, q]).sum() / den[q])
+            tau += 2.0 * rho
+            if k >= c * tau:
+                break
+        taus.append(tau)
+    return np.array(taus)
+
+
+def host_info():
+    """The host cores the CPU baseline ran on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model,
+            "threads_used": 1, "blas": "NumPy/SciPy BLAS limited to one thread"}
 
 
 def run_batch(H, nchains, steps, warmup, spp, out):
@@ -222,6 +258,42 @@ def measure(precision, args, fs, dev):
     del Hs, Hb
     torch.cuda.empty_cache()
     return res
+
+
+def measure_hbm_point(dev, dims=(512, 512, 256), cycles=10):
+    """One FP64 chain on a single 512x512x256 grid (537 MB per field, beyond the 256 MB
+    Infinity Cache): cycles/s of the 7-level V(2,2) cycle and the level-0 colour pass
+    against the HBM roofline (8 B per cell per pass)."""
+    import torch
+    from paper_1003_2680_amd.api import Hierarchy
+    nx, ny, nz = dims
+    H = Hierarchy(nx, ny, nz, ncomp=1, kT=1.0, levels=0, nu1=2, nu2=2)
+    state = torch.zeros(H.shape, dtype=torch.float64, device=dev)
+    H.sample_batch(0, seeds=[0], comps_per_chain=1, state=state)
+    H.sample_batch(2, nchains=1, comps_per_chain=1, state=state, emit=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.sample_batch(cycles, nchains=1, comps_per_chain=1, state=state, emit=False)
+    torch.cuda.synchronize()
+    cyc_s = (time.perf_counter() - t0) / cycles
+    H.kernel_timing(True, "fine_pass")
+    H.sample_batch(cycles, nchains=1, comps_per_chain=1, state=state, emit=False)
+    torch.cuda.synchronize()
+    n_l, k_ms = H.kernel_timing_read()
+    H.kernel_timing(False, "fine_pass")
+    avg = k_ms / 1e3 / max(n_l, 1)
+    nbytes = nx * ny * nz * 8
+    ach = nbytes / avg / 1e9
+    levels = H.n_levels
+    del H, state
+    torch.cuda.empty_cache()
+    return {"workload": "%dx%dx%d, 1 component, FP64, auto depth (coarsest <= 512 unknowns), "
+                        "V(2,2)" % dims,
+            "levels": levels, "cycles_per_s": round(1.0 / cyc_s, 2),
+            "ms_per_cycle": round(cyc_s * 1e3, 3),
+            "fine_pass": {"avg_launch_us": round(avg * 1e6, 2),
+                          "algorithmic_bytes_per_launch": nbytes,
+                          "achieved_GBs": round(ach, 1), "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}}
 
 
 def measure_batched(dev, n_instances=64, n_samples=100):
@@ -337,6 +409,8 @@ def main():
                     help="skip the FP32-refined measurement")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-instance batched measurement")
+    ap.add_argument("--no-hbm-point", action="store_true",
+                    help="skip the single 512x512x256 grid (beyond the Infinity Cache)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-loop measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -412,6 +486,7 @@ def main():
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "rho": round(rho, 5), "rho_solve": round(rho_solve, 5),
         "rho_obs_lag1": [round(float(v), 4) for v in rho_obs],
+        "tau_int_obs": [round(float(v), 3) for v in tau_int(r64["obs"])],
         "solves_per_s": round(len(fs) / r64["solve_batch_s"], 3),
         "solve_ms_single": round(r64["solve_single_s"] * 1e3, 3),
         "solve_cycles": round(r64["solve_cycles"], 2),
@@ -447,6 +522,9 @@ def main():
             "rho_obs_lag1_max": round(float(np.max(np.abs(lag1(r32["obs"])))), 4),
             "rel_rms_vs_fp64_2_cycles": float("%.3e" % rel_rms)}
 
+    if not args.no_hbm_point:
+        line["hbm_point"] = measure_hbm_point(dev)
+        progress("512x512x256 HBM point done")
     if not args.no_batched:
         line["batched"] = measure_batched(dev)
         progress("batched instances done")
