@@ -400,7 +400,7 @@ def measure_serving(dev, stride, rate=200.0, n=300):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=125)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--solves", type=int, default=10)
     ap.add_argument("--chains", type=int, default=8)

@@ -321,3 +321,49 @@ def simulate(server, timed_requests, make_f, timeout=120.0):
     wall = time.perf_counter() - t0
     lat = np.array([r.t_done - r.t_arrival for r in server.done])
     return ok, wall, lat
+
+
+def main(argv=None):
+    """Rate sweep of the serving loop: one JSON line per arrival rate."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--rates", default="50,100,200,500,1000,2000")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--stride", type=int, default=2, help="burn-in = stride of sample requests")
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--budget-gb", type=float, default=32.0)
+    ap.add_argument("--precision", default="fp32_refined")
+    ap.add_argument("--timeout", type=float, default=300.0)
+    args = ap.parse_args(argv)
+    from .inputs import gaussian_field_device
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    for rate in [float(r) for r in args.rates.split(",")]:
+        srv = Server(budget_bytes=int(args.budget_gb * (1 << 30)), slots=args.slots,
+                     stride=args.stride, precision=args.precision, device=dev)
+        reqs = make_requests(args.requests, rate, seed=7)
+        ok, wall, lat = simulate(
+            srv, reqs, lambda r: gaussian_field_device(r.dims[::-1], r.seed, dev),
+            timeout=args.timeout)
+        kinds = {"sample": [], "solve": []}
+        for r in srv.done:
+            kinds[r.kind].append(r.t_done - r.t_arrival)
+        errors = sum(1 for r in srv.done if r.error)
+        line = {"rate_req_s": rate, "requests": args.requests, "completed": len(lat),
+                "errors": errors, "all_completed": bool(ok),
+                "throughput_req_s": round(len(lat) / wall, 2),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                "sample_p50_ms": round(float(np.percentile(kinds["sample"], 50)) * 1e3, 2)
+                if kinds["sample"] else None,
+                "solve_p50_ms": round(float(np.percentile(kinds["solve"], 50)) * 1e3, 2)
+                if kinds["solve"] else None,
+                "pools_created": len(srv.pools) + srv.evictions, "evictions": srv.evictions}
+        srv.shutdown()
+        torch.cuda.empty_cache()
+        print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
