@@ -80,3 +80,29 @@ def integrated_autocorrelation_time(series, max_lag=None):
             break
         tau += rho[k]
     return tau
+
+
+def extract_linear_part(mg):
+    """T of one cycle x -> T x + G n (b = 0): the cycle applied to the unit vectors, noise off."""
+    N = mg.levels[0].n
+    zero = np.zeros(N)
+    T = np.empty((N, N))
+    for i in range(N):
+        e = np.zeros(N)
+        e[i] = 1.0
+        T[:, i] = mg.vcycle(e, zero, None, 0, 0)
+    return T
+
+
+def exact_lag_correlation(T, C, phi, max_lag):
+    """Lag-k correlation of the observable phi^T x of the stationary chain x' = T x + G n with
+    stationary covariance C: Cov(phi^T x_{t+k}, phi^T x_t) = phi^T T^k C phi, normalised by
+    phi^T C phi, for k = 0 .. max_lag (the lag-k correlation of Sec. "Stochastic Iterative
+    Methods", R^k applied to the stationary covariance)."""
+    v = C @ phi
+    den = float(phi @ v)
+    out = np.empty(max_lag + 1)
+    for k in range(max_lag + 1):
+        out[k] = float(phi @ v) / den
+        v = T @ v
+    return out

@@ -1,0 +1,121 @@
+"""Decorrelation of the stochastic multigrid chain against the plain stochastic Gauss-Seidel
+sampler, as the grid grows (Sec. "Stochastic Iterative Methods" and the paper's comparison of
+the two samplers).
+
+Both chains run in the library: the multigrid chain is the V(nu1, nu2) cycle; the
+Gauss-Seidel chain is the same hierarchy reduced to one level whose "coarsest" step is nu1 +
+nu2 red-black heat-bath sweeps (no coarse correction).  Each emitted cycle's observables --
+projections onto the lowest eigenvectors of A and the energy -- come from the library's fused
+statistics; this module only estimates lag-k autocorrelations and integrated autocorrelation
+times from them (host arithmetic on the observable series, not on any field).
+"""
+import json
+import time
+
+import numpy as np
+import torch
+
+from .api import Hierarchy, lowest_modes
+
+
+def make_chain(dims, kind, nchains=8, kT=1.0, nu=(2, 2), burn_in=0, device=None):
+    """'mg': the multigrid cycle (automatic depth); 'gs': one level, heat-bath sweeps only.
+    The hierarchy's components are independent chains (the component enters the counters)."""
+    if kind == "mg":
+        return Hierarchy(*dims, ncomp=nchains, kT=kT, levels=0, nu1=nu[0], nu2=nu[1],
+                         burn_in=burn_in, device=device)
+    if kind == "gs":
+        return Hierarchy(*dims, ncomp=nchains, kT=kT, levels=1, coarsest="smooth",
+                         nu1=nu[0], nu2=nu[1], burn_in=burn_in, device=device)
+    raise ValueError("kind must be 'mg' or 'gs'")
+
+
+def observables(H, n, seed=0, modes=None):
+    """n emitted cycles after the hierarchy's burn-in, from the zero state:
+    [n, nchains, len(modes) + 1] (float64, host)."""
+    dims = (H.desc.nx, H.desc.ny, H.desc.nz)
+    if modes is None:
+        modes = lowest_modes(*dims, 4)
+    obs, _ = H.sample_stats(n, seed, modes=modes)
+    torch.cuda.synchronize(H.device)
+    return obs.cpu().numpy()
+
+
+def autocorrelation(obs, max_lag):
+    """Lag-k autocorrelation of each observable pooled over chains: [max_lag + 1, Q]."""
+    o = obs - obs.mean(axis=0, keepdims=True)
+    den = (o * o).sum(axis=(0, 1))
+    T = o.shape[0]
+    return np.stack([(o[:T - k] * o[k:]).sum(axis=(0, 1)) / den for k in range(max_lag + 1)])
+
+
+def tau_int(obs, c=5.0):
+    """1 + 2 sum_k rho(k) per observable, up to the first lag k >= c tau(k) (Sokal)."""
+    o = obs - obs.mean(axis=0, keepdims=True)
+    den = (o * o).sum(axis=(0, 1))
+    T = o.shape[0]
+    taus = []
+    for q in range(o.shape[2]):
+        tau = 1.0
+        for k in range(1, T // 2):
+            tau += 2.0 * float((o[:T - k, :, q] * o[k:, :, q]).sum() / den[q])
+            if k >= c * tau:
+                break
+        taus.append(tau)
+    return np.array(taus)
+
+
+def study(sizes=((16, 16, 16), (32, 32, 32), (64, 64, 64)), nchains=8, n_mg=2000,
+          gs_cycles_per_tau=200, device=None, seed=0):
+    """One row per (grid, sampler): lag-1 correlation and tau_int of the lowest mode and the
+    energy, cycles/s, and the cost of one decorrelated sample in cycles and in seconds.  The
+    Gauss-Seidel chains run for about gs_cycles_per_tau times their expected tau (a first
+    estimate from the grid's lowest eigenvalue) after a burn-in of ten of them."""
+    rows = []
+    for dims in sizes:
+        nz = dims[2]
+        # lowest mode's heat-bath contraction per sweep ~ 1 - lambda_min / 3 (red-black)
+        lam = 4.0 * np.sin(np.pi / (2 * nz)) ** 2
+        tau_guess = max(2.0, 2.0 / (4 * lam / 3.0))
+        for kind in ("mg", "gs"):
+            n = n_mg if kind == "mg" else int(gs_cycles_per_tau * tau_guess)
+            burn = 20 if kind == "mg" else int(10 * tau_guess)
+            H = make_chain(dims, kind, nchains=nchains, burn_in=burn, device=device)
+            torch.cuda.synchronize(H.device)
+            t0 = time.perf_counter()
+            obs = observables(H, n, seed=seed)
+            secs = time.perf_counter() - t0
+            tau = tau_int(obs)
+            rho1 = autocorrelation(obs, 1)[1]
+            rate = (n + burn) / secs
+            k_tau = max(tau[0], tau[-1])
+            rows.append({"grid": list(dims), "sampler": kind, "levels": H.n_levels,
+                         "cycles": n, "chains": nchains,
+                         "lag1_lowest_mode": round(float(rho1[0]), 4),
+                         "lag1_energy": round(float(rho1[-1]), 4),
+                         "tau_int_lowest_mode": round(float(tau[0]), 2),
+                         "tau_int_energy": round(float(tau[-1]), 2),
+                         "cycles_per_s": round(rate, 1),
+                         "seconds_per_decorrelated_sample": float("%.4g" % (k_tau / rate))})
+            print(json.dumps(rows[-1]), flush=True)
+            del H
+            torch.cuda.empty_cache()
+    return rows
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="multigrid vs Gauss-Seidel decorrelation study")
+    ap.add_argument("--sizes", default="16,32,64", help="cubic grid edges")
+    ap.add_argument("--chains", type=int, default=8)
+    ap.add_argument("--mg-cycles", type=int, default=2000)
+    ap.add_argument("--gs-cycles-per-tau", type=int, default=200)
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    sizes = [(int(e), int(e), int(e)) for e in args.sizes.split(",")]
+    study(sizes, nchains=args.chains, n_mg=args.mg_cycles,
+          gs_cycles_per_tau=args.gs_cycles_per_tau, device=torch.device("cuda", 0))
+
+
+if __name__ == "__main__":
+    main()
