@@ -242,7 +242,8 @@ int smg_debug_host_table(const smg_hierarchy* h, int32_t level, int32_t which, d
  *   colour pass, or the LDS-resident bottom launch. */
 enum { SMG_OPT_BOTTOM_KERNEL = 1, SMG_OPT_TIMED_KERNEL = 2, SMG_OPT_BLOCK_TILE = 3 };
 /* SMG_OPT_BLOCK_TILE: blocks per work-group (x by y) of the Galerkin-level block passes;
- * SMG_TILE_AUTO (default) takes 4x4 unless that gives fewer than 512 work-groups. */
+ * SMG_TILE_AUTO (default) takes the largest of 8x4, 4x4, 4x2 that gives at least 512
+ * work-groups for the pass. */
 enum { SMG_TILE_AUTO = 0, SMG_TILE_4X4 = 1, SMG_TILE_4X2 = 2, SMG_TILE_8X4 = 3 };
 enum { SMG_TIMED_FINE_PASS = 0, SMG_TIMED_LEVEL1_BLOCK_PASS = 1, SMG_TIMED_BOTTOM = 2 };
 int smg_set_option(smg_hierarchy* h, int32_t option, int64_t value);

@@ -545,9 +545,12 @@ hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const 
   const int nbzc = (nbz + 1 - (colour >> 2)) / 2;
   if (nbx2 * nby2 * nbzc == 0) return hipSuccess;
   if (tile == SMG_TILE_AUTO) {
-    // 4x4 tiles unless that leaves fewer than two work-groups per compute unit
-    const int64_t wg = (int64_t)((nbx2 + 3) / 4) * ((nby2 + 3) / 4) * nbzc * ncomp;
-    tile = wg >= 512 ? SMG_TILE_4X4 : SMG_TILE_4X2;
+    // the largest tile (least halo per block) that still gives every compute unit two
+    // work-groups
+    const int64_t layers = (int64_t)nbzc * ncomp;
+    const int64_t wg84 = (int64_t)((nbx2 + 7) / 8) * ((nby2 + 3) / 4) * layers;
+    const int64_t wg44 = (int64_t)((nbx2 + 3) / 4) * ((nby2 + 3) / 4) * layers;
+    tile = wg84 >= 512 ? SMG_TILE_8X4 : (wg44 >= 512 ? SMG_TILE_4X4 : SMG_TILE_4X2);
   }
   if (tile == SMG_TILE_4X2)
     launch_block_tile<T, 4, 2>(x, b, s1d, zt, bfac, nx, ny, nz, ncomp, colour, zn, nbx2, nby2, nbzc, s);
