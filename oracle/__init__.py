@@ -18,6 +18,10 @@ written so that each step can be checked against the paper by eye:
                    (FFT in x,y and DST-II in z), used as an independent reference.
 * ``analysis``  -- affine-map extraction, the stationary-covariance (Lyapunov) check of
                    eq. J_eq_C_R, autocorrelation estimates.
+* ``composite`` -- the spatially adaptive composite grid (one box refined by two): the
+                   operator L = DG with the coarse-fine face gradient, the base-to-composite
+                   prolongation and the stochastic FAC cycle (Algs. 1-3) with Galerkin
+                   base levels.
 * ``observables`` -- projections onto eigenvectors of A, the energy 1/2 x^T A x and
                    per-cell moments of the samples (the decorrelation observables).
 
