@@ -257,6 +257,103 @@ int smg_set_option(smg_hierarchy* h, int32_t option, int64_t value);
 int smg_kernel_timing(smg_hierarchy* h, int32_t enable);
 int smg_kernel_timing_read(smg_hierarchy* h, int64_t* count, double* total_ms);
 
+
+/* ==== Spatially adaptive composite grid: the FAC sampler and solver ====================
+ * Mesh (Sec. "Spatially Adaptive Discretizations"): a base grid nx x ny x nz of width h,
+ * periodic in x and y, no-slip walls at z = 0 and z = nz*h, with one box of base cells
+ * [box[0], box[1]) x [box[2], box[3]) x [box[4], box[5]) refined by two.  Neighbouring cells
+ * differ by at most one level.  Operator L = D G (eq. def_L): same-level face gradients
+ * (eq. def_discr_grad0); on a coarse-fine face the gradient of the mean of the four fine cells
+ * on the coarse face minus the coarse value over 3/4 h, shared by those four cells, with the
+ * coarse face value their mean (eqs. def_discr_grad .. def_discr_grad_last, read in 3D);
+ * walls by the antisymmetric ghost.  S = diag(volume) L is symmetric; the library samples
+ * x ~ N(A^-1 b, kT A^-1) with A = -S/h^3 (on coarse cells the uniform-grid rows of -L, on fine
+ * cells -L/8), which is C = -2 L^-1 Ccal (Sec. "Performance of the Stochastic Samplers in
+ * Practice") with Ccal = (kT/2) h^3 diag(volume)^-1, and solves A u = f.
+ *
+ * FAC cycle (Algs. 1-3 with the variational property): the coarse space of the composite mesh
+ * is the whole base grid, mapped onto the composite unknowns by P (identity on coarse cells,
+ * trilinear onto fine cells); b_0 = P^T (b - A x); a stochastic V(mu1, mu2) cycle on the
+ * Galerkin base hierarchy A_0 = P^T A P, A_{l+1} = P_l^T A_l P_l (2x2x2 block heat baths,
+ * exact coarsest draw) from y = 0; x += P y; then nu composite sweeps, each a point heat bath
+ * over twelve uncoupled classes (coarse cells by parity; fine cells off the interface layer by
+ * parity; interface-layer fine cells by the eight parities (x%2) + 2(y%2) + 4(z%2)).
+ *
+ * Fields: coarse part on the whole base grid, float64 [nz][ny][nx] (entries of covered cells
+ * are ignored on input; outputs write them as 0 only where stated); fine part float64
+ * [2(box[5]-box[4])][2(box[3]-box[2])][2(box[1]-box[0])].  One component per field.  Noise
+ * streams as for the uniform grid with kind 2 (composite passes: level 0, colour = class,
+ * slot = sweep, site = index in its own array), kind 3 (base block levels) and kind 4 (the
+ * coarsest base level).  Memory, stream and error conventions as above. */
+typedef struct smg_composite smg_composite;
+
+typedef struct {
+  int32_t nx, ny, nz;   /* base grid: nx, ny even and >= 4 */
+  int32_t box[6];       /* x0, x1, y0, y1, z0, z1 (base cells), not spanning a periodic extent */
+  double h;
+  double kT;
+} smg_composite_desc;
+
+typedef struct {
+  int32_t nu;           /* composite sweeps per cycle (Alg. 2 step 5) */
+  int32_t mu1, mu2;     /* pre/post sweeps of the base V-cycle (Alg. 3) */
+  int32_t levels;       /* base levels (0 = automatic by coarsest_max) */
+  int32_t coarsest_max; /* automatic-depth threshold, 1..4096 */
+} smg_fac_params;
+
+typedef struct {
+  size_t workspace_bytes;
+  int64_t base_cells;       /* nx*ny*nz: length of a coarse-part field */
+  int64_t fine_cells;       /* length of a fine-part field */
+  int64_t unknowns;         /* composite unknowns: uncovered base cells + fine cells */
+  int32_t fine_dims[3];     /* (fx, fy, fz) */
+  int32_t n_levels;         /* base levels, finest first */
+  int32_t dims[16][3];
+  int32_t stencils[16];     /* distinct rows per base level */
+  int32_t block_types[16];  /* distinct 2x2x2 diagonal blocks per block level */
+  int32_t layer_cells;
+  int32_t coarsest_unknowns;
+} smg_composite_info;
+
+/* Plans the composite hierarchy on the host: the Galerkin base operators (rows near the box
+ * cell by cell, the rest per z-plane, equal rows shared), block factors and the dense coarsest
+ * factor.  No device work.  Errors: SMG_EINVAL (shape, box, parameters, a base level that
+ * cannot be coarsened or block-smoothed), SMG_ENOMEM. */
+int smg_composite_create(const smg_composite_desc* desc, const smg_fac_params* params,
+                         smg_composite** out);
+int smg_composite_get_info(const smg_composite* h, smg_composite_info* info);
+/* Binds caller-owned device memory (>= workspace_bytes, 256-byte aligned) and uploads the
+ * tables on `stream`, then synchronises it. */
+int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stream);
+/* One FAC cycle in place on (xc, xf) with right-hand side (bc, bf) (both NULL = 0), noise
+ * counters (seed, cycle); with_noise == 0 gives the deterministic cycle. */
+int smg_composite_cycle(smg_composite* h, void* xc, void* xf, const void* bc, const void* bf,
+                        uint64_t seed, uint64_t cycle, int32_t with_noise, void* stream);
+/* ncycles stochastic cycles with b = 0 in place, cycle indices first_cycle, first_cycle+1, ... */
+int smg_composite_sample(smg_composite* h, int64_t ncycles, uint64_t seed, uint64_t first_cycle,
+                         void* xc, void* xf, void* stream);
+/* (rc, rf) = (bc, bf) - A (xc, xf); rc is written on every base cell, 0 on covered cells. */
+int smg_composite_residual(smg_composite* h, const void* xc, const void* xf, const void* bc,
+                           const void* bf, void* rc, void* rf, void* stream);
+/* Solves A u = f from u = 0 with noise-free cycles until ||f - A u||_2 <= rtol ||f||_2 (norms
+ * over the composite unknowns; covered entries of fc are ignored).  Synchronises `stream`
+ * after every cycle.  Errors as smg_solve. */
+int smg_composite_solve(smg_composite* h, const void* fc, const void* ff, void* uc, void* uf,
+                        double rtol, int32_t max_cycles, void* stream, smg_solve_info* info);
+/* Component entry points for the parity tests: one class pass (0..11) of a composite sweep;
+ * one block-colour pass (0..7) on base level `level` (x, b natural layout of that level, b
+ * NULL = 0); the stored row of base cell `cell` on level `level` (host only, up to 125
+ * entries: absolute target cells and coefficients). */
+int smg_composite_debug_pass(smg_composite* h, int32_t cls, void* xc, void* xf, const void* bc,
+                             const void* bf, uint64_t seed, uint64_t cycle, int32_t slot,
+                             int32_t with_noise, void* stream);
+int smg_composite_debug_base_pass(smg_composite* h, int32_t level, int32_t colour, void* x,
+                                  const void* b, uint64_t seed, uint64_t cycle, int32_t slot,
+                                  int32_t with_noise, void* stream);
+int smg_composite_debug_row(const smg_composite* h, int32_t level, int64_t cell,
+                            int64_t* targets, double* vals, int32_t* count);
+void smg_composite_destroy(smg_composite* h);
+
 #ifdef __cplusplus
 }
 #endif

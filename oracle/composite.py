@@ -425,16 +425,21 @@ class FACSampler:
                 mg._setup_block(L)
         return mg
 
+    def class_pass(self, x, b, c, slot, noise, cycle, comp=0):
+        """Heat bath of class c in place: x_i = (b_i - sum_j A_ij x_j)/A_ii + sqrt(kT/A_ii) n_i."""
+        ids, sites = self.cls[c]
+        if ids.size == 0:
+            return
+        rest, sub = self.sub[c]
+        d = self.diag[ids]
+        x[ids] = (b[ids] - sub @ x[rest]) / d
+        if noise is not None:
+            n = noise.draw(cycle, 0, slot, c, comp, KIND_COMPOSITE, sites)
+            x[ids] += np.sqrt(self.kT / d) * n
+
     def sweep(self, x, b, slot, noise, cycle, comp):
-        for c, (ids, sites) in enumerate(self.cls):
-            if ids.size == 0:
-                continue
-            rest, sub = self.sub[c]
-            d = self.diag[ids]
-            x[ids] = (b[ids] - sub @ x[rest]) / d
-            if noise is not None:
-                n = noise.draw(cycle, 0, slot, c, comp, KIND_COMPOSITE, sites)
-                x[ids] += np.sqrt(self.kT / d) * n
+        for c in range(len(self.cls)):
+            self.class_pass(x, b, c, slot, noise, cycle, comp)
 
     def cycle(self, x, b, noise=None, cycle=0, comp=0):
         """One FAC cycle (returns the new iterate; x is not modified)."""
@@ -481,3 +486,80 @@ class FACSampler:
             v[k] = 1.0
             G[:, k] = self.cycle(zero, zero, _InjectedNoise(v))
         return T, G
+
+
+def row_of(nx, ny, nz, box, h, kind, idx):
+    """Row of A for one composite cell, from the face rules alone (no assembly), for sampled
+    checks on grids too large to assemble here.  kind 'c': base cell index idx (uncovered);
+    kind 'f': fine cell index idx in the box.  Returns {('c', base index) or ('f', fine
+    index): coefficient}."""
+    x0, x1, y0, y1, z0, z1 = box
+    fx, fy, fz = 2 * (x1 - x0), 2 * (y1 - y0), 2 * (z1 - z0)
+    ih2 = 1.0 / (h * h)
+    out = {}
+
+    def add(key, v):
+        out[key] = out.get(key, 0.0) + v * ih2
+
+    def cov(x, y, z):
+        return x0 <= x < x1 and y0 <= y < y1 and z0 <= z < z1
+
+    def fkey(i, j, k):
+        return ("f", i + fx * (j + fy * k))
+
+    if kind == "c":
+        x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+        me = ("c", idx)
+        for axis in range(3):
+            for sgn in (1, -1):
+                q = [x, y, z]
+                q[axis] += sgn
+                if axis == 2 and not 0 <= q[2] < nz:
+                    add(me, 2.0)                     # wall face: ghost -c at distance h
+                    continue
+                q[0] %= nx
+                q[1] %= ny
+                if cov(*q):
+                    # coarse-fine face: gradient (mean of 4 fine - c) / (3h/4) on area h^2
+                    base = [2 * (q[0] - x0), 2 * (q[1] - y0), 2 * (q[2] - z0)]
+                    base[axis] += 1 if sgn < 0 else 0
+                    t = [a for a in range(3) if a != axis]
+                    add(me, 4.0 / 3.0)
+                    for a in (0, 1):
+                        for b in (0, 1):
+                            c = list(base)
+                            c[t[0]] += a
+                            c[t[1]] += b
+                            add(fkey(*c), -1.0 / 3.0)
+                else:
+                    add(me, 1.0)
+                    add(("c", q[0] + nx * (q[1] + ny * q[2])), -1.0)
+        return out
+    i, j, k = idx % fx, (idx // fx) % fy, idx // (fx * fy)
+    me = ("f", idx)
+    ext = (fx, fy, fz)
+    for axis in range(3):
+        for sgn in (1, -1):
+            p = [i, j, k]
+            p[axis] += sgn
+            if 0 <= p[axis] < ext[axis]:
+                add(me, 0.5)                         # fine face: area h^2/4, distance h/2
+                add(fkey(*p), -0.5)
+                continue
+            A = [x0 + i // 2, y0 + j // 2, z0 + k // 2]
+            A[axis] += sgn
+            if axis == 2 and not 0 <= A[2] < nz:
+                add(me, 1.0)                         # fine wall face
+                continue
+            A[0] %= nx
+            A[1] %= ny
+            # this cell's share (a quarter of the coarse face) of the coarse-fine gradient
+            add(("c", A[0] + nx * (A[1] + ny * A[2])), -1.0 / 3.0)
+            t = [a for a in range(3) if a != axis]
+            for a in (0, 1):
+                for b in (0, 1):
+                    c = [i, j, k]
+                    c[t[0]] = (c[t[0]] // 2) * 2 + a
+                    c[t[1]] = (c[t[1]] // 2) * 2 + b
+                    add(fkey(*c), 1.0 / 12.0)
+    return out

@@ -38,7 +38,11 @@ EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
             "smg_debug_smooth", "smg_debug_restrict_residual", "smg_debug_prolong_add",
             "smg_debug_coarsest", "smg_debug_host_table", "smg_set_option",
             "smg_kernel_timing", "smg_kernel_timing_read", "smg_lowest_modes",
-            "smg_sample_stats", "smg_sample_batch", "smg_solve_batch"]
+            "smg_sample_stats", "smg_sample_batch", "smg_solve_batch",
+            "smg_composite_create", "smg_composite_get_info", "smg_composite_bind",
+            "smg_composite_cycle", "smg_composite_sample", "smg_composite_residual",
+            "smg_composite_solve", "smg_composite_debug_pass", "smg_composite_debug_base_pass",
+            "smg_composite_debug_row", "smg_composite_destroy"]
 
 
 class GridDesc(ctypes.Structure):
@@ -62,6 +66,25 @@ class Info(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("relres", ctypes.c_double),
                 ("last_ratio", ctypes.c_double)]
+
+
+class CompositeDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("box", ctypes.c_int32 * 6), ("h", ctypes.c_double), ("kT", ctypes.c_double)]
+
+
+class FACParams(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_int32), ("mu1", ctypes.c_int32), ("mu2", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("coarsest_max", ctypes.c_int32)]
+
+
+class CompositeInfo(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_size_t), ("base_cells", ctypes.c_int64),
+                ("fine_cells", ctypes.c_int64), ("unknowns", ctypes.c_int64),
+                ("fine_dims", ctypes.c_int32 * 3), ("n_levels", ctypes.c_int32),
+                ("dims", (ctypes.c_int32 * 3) * 16), ("stencils", ctypes.c_int32 * 16),
+                ("block_types", ctypes.c_int32 * 16), ("layer_cells", ctypes.c_int32),
+                ("coarsest_unknowns", ctypes.c_int32)]
 
 
 class SMGError(RuntimeError):
@@ -116,6 +139,24 @@ def load():
         "smg_solve_batch": ([H, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_double,
                              ctypes.c_int32, P, P], ctypes.c_int),
     }
+    U64, I32 = ctypes.c_uint64, ctypes.c_int32
+    sig.update({
+        "smg_composite_create": ([ctypes.POINTER(CompositeDesc), ctypes.POINTER(FACParams),
+                                  ctypes.POINTER(H)], ctypes.c_int),
+        "smg_composite_get_info": ([H, ctypes.POINTER(CompositeInfo)], ctypes.c_int),
+        "smg_composite_bind": ([H, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg_composite_cycle": ([H, P, P, P, P, U64, U64, I32, P], ctypes.c_int),
+        "smg_composite_sample": ([H, ctypes.c_int64, U64, U64, P, P, P], ctypes.c_int),
+        "smg_composite_residual": ([H, P, P, P, P, P, P, P], ctypes.c_int),
+        "smg_composite_solve": ([H, P, P, P, P, ctypes.c_double, I32, P,
+                                 ctypes.POINTER(SolveInfo)], ctypes.c_int),
+        "smg_composite_debug_pass": ([H, I32, P, P, P, P, U64, U64, I32, I32, P], ctypes.c_int),
+        "smg_composite_debug_base_pass": ([H, I32, I32, P, P, U64, U64, I32, I32, P],
+                                          ctypes.c_int),
+        "smg_composite_debug_row": ([H, I32, ctypes.c_int64, P, P, ctypes.POINTER(I32)],
+                                    ctypes.c_int),
+        "smg_composite_destroy": ([H], None),
+    })
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args

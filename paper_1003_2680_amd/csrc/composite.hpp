@@ -1,0 +1,76 @@
+// Spatially adaptive composite grid (one box refined by two) and its FAC cycle: device-side
+// descriptors and kernel launchers.
+//
+// Mesh and operator (Sec. "Spatially Adaptive Discretizations"): base cells of width h outside
+// the box, fine cells of width h/2 inside it; L = D G with the same-level face gradient
+// (eq. def_discr_grad0), the coarse-fine face gradient (eq. def_discr_grad, read in 3D as the
+// mean of the four fine cells on the coarse face minus the coarse value over 3/4 h) and the
+// conservative coarse face value (eq. def_discr_grad_last); walls by the antisymmetric ghost.
+// The sampling precision is A = -S/h^3 with S = diag(volume) L symmetric, so in units of 1/h^2:
+//   coarse row: +1 per coarse neighbour face (-1 off-diagonal), +2 per wall face, +4/3 per
+//               coarse-fine face (-1/3 to each of its four fine cells);
+//   fine row:   +1/2 per fine neighbour face (-1/2), +1 per wall face, and per coarse-fine
+//               face +1/12 on the diagonal, +1/12 to each of the three other fine cells of that
+//               face, -1/3 to the coarse cell.
+// Storage: the coarse field uses the whole base grid [nz][ny][nx] (entries of covered cells are
+// never read and are written as zero by the residual); the fine field is the box [fz][fy][fx].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.hpp"
+
+namespace smg {
+
+struct CompGeom {
+  int nx, ny, nz;              // base grid
+  int x0, x1, y0, y1, z0, z1;  // refined box in base cells (0 <= x0 < x1 <= nx, x1-x0 < nx, ...)
+  int fx, fy, fz;              // fine extents 2(x1-x0), 2(y1-y0), 2(z1-z0)
+  double ih2;                  // 1/h^2
+};
+
+// Operator of a Galerkin base level as a dictionary of sparse stencils: every 2x2x2 block has a
+// block type, a block type names the stencil of each of its 8 cells (in-block index
+// dx + 2dy + 4dz) and carries the factors of its 8x8 diagonal block; a stencil is a list of
+// (offset code, coefficient), code = (dz+2)*25 + (dy+2)*5 + (dx+2), offsets periodic in x, y.
+struct GStencil {
+  const int32_t* btype;   // [n/8]
+  const int32_t* bt_sid;  // [types][8]
+  const double* bt_fac;   // [types][128]: A_BB^-1 then L_BB^-T, row-major
+  const int32_t* st_off;  // [stencils + 1]
+  const int32_t* st_code;
+  const double* st_val;
+  int nx, ny, nz;
+};
+
+// Point heat bath of one class of the composite sweep (x_i = (b_i - sum_j A_ij x_j)/A_ii +
+// sqrt(kT/A_ii) n_i), b null = 0.  Classes: coarse cells of parity `colour`; fine cells off the
+// interface layer of parity `colour`; the listed layer cells (one parity class per list).
+hipError_t launch_comp_coarse_pass(double* xc, const double* bc, const double* xf,
+                                   const CompGeom& g, int colour, bool noise, const NoiseArgs& na,
+                                   hipStream_t s);
+hipError_t launch_comp_fine_pass(double* xf, const double* bf, const CompGeom& g, int colour,
+                                 bool noise, const NoiseArgs& na, hipStream_t s);
+hipError_t launch_comp_layer_pass(double* xf, const double* bf, const double* xc,
+                                  const CompGeom& g, const int32_t* cells, int count, bool noise,
+                                  const NoiseArgs& na, hipStream_t s);
+// rc = bc - (A x)_coarse on every base cell (covered cells: 0), rf = bf - (A x)_fine
+hipError_t launch_comp_residual(double* rc, double* rf, const double* xc, const double* xf,
+                                const double* bc, const double* bf, const CompGeom& g,
+                                hipStream_t s);
+// b0 = P^T (rc, rf) over the base grid and x0 = 0 (P: identity on coarse cells, trilinear
+// onto fine cells)
+hipError_t launch_comp_restrict(double* b0, double* x0, const double* rc, const double* rf,
+                                const CompGeom& g, hipStream_t s);
+// (xc, xf) += P y
+hipError_t launch_comp_prolong(double* xc, double* xf, const double* y, const CompGeom& g,
+                               hipStream_t s);
+// 2x2x2 block heat bath of one block colour on a Galerkin base level (b null = 0)
+hipError_t launch_gblock_pass(double* x, const double* b, const GStencil& st, int colour,
+                              bool noise, const NoiseArgs& na, hipStream_t s);
+// r = b - A x on a Galerkin base level
+hipError_t launch_gresidual(double* r, const double* x, const double* b, const GStencil& st,
+                            hipStream_t s);
+
+}  // namespace smg

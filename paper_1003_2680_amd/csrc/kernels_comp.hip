@@ -1,0 +1,486 @@
+// Kernels of the composite-grid FAC cycle: point heat-bath classes of the composite sweep, the
+// composite residual, the transfers between the composite unknowns and the base grid, and the
+// 2x2x2 block heat bath and residual of the Galerkin base levels (sparse stencil dictionary).
+// Operator, classes and noise streams as described in composite.hpp; FP64 throughout.
+#include "composite.hpp"
+#include "device_common.hpp"
+
+namespace smg {
+namespace {
+
+inline uint32_t grid_for(int64_t n) { return (uint32_t)((n + TPB - 1) / TPB); }
+
+__device__ __forceinline__ bool covered(const CompGeom& g, int x, int y, int z) {
+  return x >= g.x0 && x < g.x1 && y >= g.y0 && y < g.y1 && z >= g.z0 && z < g.z1;
+}
+
+// fine cells with a face on the box boundary towards coarse cells
+__device__ __forceinline__ bool on_layer(const CompGeom& g, int i, int j, int k) {
+  return i == 0 || i == g.fx - 1 || j == 0 || j == g.fy - 1 || (k == 0 && g.z0 > 0) ||
+         (k == g.fz - 1 && g.z1 < g.nz);
+}
+
+__device__ __forceinline__ int fidx(const CompGeom& g, int i, int j, int k) {
+  return i + g.fx * (j + g.fy * k);
+}
+
+// the normal of `site` in the stream of na: call site/2, first or second of the pair
+__device__ __forceinline__ double normal_at(const NoiseArgs& na, uint32_t site) {
+  double z0, z1;
+  normal_pair(na, na.sid, 0u, site >> 1, z0, z1);
+  return (site & 1) ? z1 : z0;
+}
+
+// Row of coarse cell (x,y,z) in units of 1/h^2: diag = A_ii, off = sum_j (-A_ij) x_j.
+__device__ __forceinline__ void coarse_row(const double* __restrict__ xc,
+                                           const double* __restrict__ xf, const CompGeom& g,
+                                           int x, int y, int z, double& diag, double& off) {
+  diag = 0.0;
+  off = 0.0;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const int axis = d >> 1;
+    const int sgn = (d & 1) ? -1 : 1;
+    int qx = x, qy = y, qz = z;
+    if (axis == 0) {
+      qx = wrapm(x + sgn, g.nx);
+    } else if (axis == 1) {
+      qy = wrapm(y + sgn, g.ny);
+    } else {
+      qz = z + sgn;
+      if (qz < 0 || qz >= g.nz) {
+        diag += 2.0;
+        continue;
+      }
+    }
+    if (covered(g, qx, qy, qz)) {
+      // the four children of q on its face towards (x, y, z)
+      const int i0 = 2 * (qx - g.x0), j0 = 2 * (qy - g.y0), k0 = 2 * (qz - g.z0);
+      const int side = sgn > 0 ? 0 : 1;
+      double s = 0.0;
+      if (axis == 0) {
+        s = xf[fidx(g, i0 + side, j0, k0)] + xf[fidx(g, i0 + side, j0 + 1, k0)] +
+            xf[fidx(g, i0 + side, j0, k0 + 1)] + xf[fidx(g, i0 + side, j0 + 1, k0 + 1)];
+      } else if (axis == 1) {
+        s = xf[fidx(g, i0, j0 + side, k0)] + xf[fidx(g, i0 + 1, j0 + side, k0)] +
+            xf[fidx(g, i0, j0 + side, k0 + 1)] + xf[fidx(g, i0 + 1, j0 + side, k0 + 1)];
+      } else {
+        s = xf[fidx(g, i0, j0, k0 + side)] + xf[fidx(g, i0 + 1, j0, k0 + side)] +
+            xf[fidx(g, i0, j0 + 1, k0 + side)] + xf[fidx(g, i0 + 1, j0 + 1, k0 + side)];
+      }
+      diag += 4.0 / 3.0;
+      off = fma(s, 1.0 / 3.0, off);
+    } else {
+      diag += 1.0;
+      off += xc[qx + g.nx * (qy + g.ny * qz)];
+    }
+  }
+}
+
+// Row of fine cell (i,j,k) (box coordinates) in units of 1/h^2.
+__device__ __forceinline__ void fine_row(const double* __restrict__ xf,
+                                         const double* __restrict__ xc, const CompGeom& g, int i,
+                                         int j, int k, double& diag, double& off) {
+  diag = 0.0;
+  off = 0.0;
+  const double self = xf[fidx(g, i, j, k)];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const int axis = d >> 1;
+    const int sgn = (d & 1) ? -1 : 1;
+    const int c = (axis == 0 ? i : (axis == 1 ? j : k)) + sgn;
+    const int n = axis == 0 ? g.fx : (axis == 1 ? g.fy : g.fz);
+    if (c >= 0 && c < n) {
+      const int ni = axis == 0 ? c : i, nj = axis == 1 ? c : j, nk = axis == 2 ? c : k;
+      diag += 0.5;
+      off = fma(0.5, xf[fidx(g, ni, nj, nk)], off);
+      continue;
+    }
+    int ax = g.x0 + (i >> 1), ay = g.y0 + (j >> 1), az = g.z0 + (k >> 1);
+    if (axis == 0) {
+      ax = sgn > 0 ? (g.x1 == g.nx ? 0 : g.x1) : (g.x0 == 0 ? g.nx - 1 : g.x0 - 1);
+    } else if (axis == 1) {
+      ay = sgn > 0 ? (g.y1 == g.ny ? 0 : g.y1) : (g.y0 == 0 ? g.ny - 1 : g.y0 - 1);
+    } else {
+      az = sgn > 0 ? g.z1 : g.z0 - 1;
+      if (az < 0 || az >= g.nz) {  // wall face of a fine cell
+        diag += 1.0;
+        continue;
+      }
+    }
+    // coarse-fine face: the three other fine cells of the parent's face share its gradient
+    const int ib = i & ~1, jb = j & ~1, kb = k & ~1;
+    double s;
+    if (axis == 0) {
+      s = xf[fidx(g, i, jb, kb)] + xf[fidx(g, i, jb + 1, kb)] + xf[fidx(g, i, jb, kb + 1)] +
+          xf[fidx(g, i, jb + 1, kb + 1)];
+    } else if (axis == 1) {
+      s = xf[fidx(g, ib, j, kb)] + xf[fidx(g, ib + 1, j, kb)] + xf[fidx(g, ib, j, kb + 1)] +
+          xf[fidx(g, ib + 1, j, kb + 1)];
+    } else {
+      s = xf[fidx(g, ib, jb, k)] + xf[fidx(g, ib + 1, jb, k)] + xf[fidx(g, ib, jb + 1, k)] +
+          xf[fidx(g, ib + 1, jb + 1, k)];
+    }
+    diag += 1.0 / 12.0;
+    off = fma(xc[ax + g.nx * (ay + g.ny * az)], 1.0 / 3.0, off);
+    off = fma(s - self, -1.0 / 12.0, off);
+  }
+}
+
+template <bool NOISE>
+__global__ __launch_bounds__(TPB) void k_comp_coarse_pass(double* __restrict__ xc,
+                                                          const double* __restrict__ bc,
+                                                          const double* __restrict__ xf,
+                                                          CompGeom g, int colour, NoiseArgs na) {
+  const int hx = g.nx >> 1;
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= (uint32_t)hx * g.ny * g.nz) return;
+  const int jx = t % hx;
+  const int row = t / hx;
+  const int y = row % g.ny, z = row / g.ny;
+  const int x = 2 * jx + ((y + z + colour) & 1);
+  if (covered(g, x, y, z)) return;
+  double diag, off;
+  coarse_row(xc, xf, g, x, y, z, diag, off);
+  const uint32_t site = x + g.nx * (y + g.ny * z);
+  const double a = diag * g.ih2;
+  double v = ((bc ? bc[site] : 0.0) + off * g.ih2) / a;
+  if (NOISE) v = fma(na.sqkT / sqrt(a), normal_at(na, site), v);
+  xc[site] = v;
+}
+
+template <bool NOISE>
+__device__ __forceinline__ void fine_update(double* __restrict__ xf, const double* __restrict__ bf,
+                                            const double* __restrict__ xc, const CompGeom& g,
+                                            int i, int j, int k, const NoiseArgs& na) {
+  double diag, off;
+  fine_row(xf, xc, g, i, j, k, diag, off);
+  const uint32_t site = fidx(g, i, j, k);
+  const double a = diag * g.ih2;
+  double v = ((bf ? bf[site] : 0.0) + off * g.ih2) / a;
+  if (NOISE) v = fma(na.sqkT / sqrt(a), normal_at(na, site), v);
+  xf[site] = v;
+}
+
+template <bool NOISE>
+__global__ __launch_bounds__(TPB) void k_comp_fine_pass(double* __restrict__ xf,
+                                                        const double* __restrict__ bf,
+                                                        CompGeom g, int colour, NoiseArgs na) {
+  const int hx = g.fx >> 1;
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= (uint32_t)hx * g.fy * g.fz) return;
+  const int jx = t % hx;
+  const int row = t / hx;
+  const int j = row % g.fy, k = row / g.fy;
+  const int i = 2 * jx + ((j + k + colour) & 1);
+  if (on_layer(g, i, j, k)) return;
+  // off the layer every neighbour is a fine cell or a wall: the coarse field is never read
+  fine_update<NOISE>(xf, bf, nullptr, g, i, j, k, na);
+}
+
+template <bool NOISE>
+__global__ __launch_bounds__(TPB) void k_comp_layer_pass(double* __restrict__ xf,
+                                                         const double* __restrict__ bf,
+                                                         const double* __restrict__ xc,
+                                                         CompGeom g,
+                                                         const int32_t* __restrict__ cells,
+                                                         int count, NoiseArgs na) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= count) return;
+  const int site = cells[t];
+  const int i = site % g.fx;
+  const int row = site / g.fx;
+  fine_update<NOISE>(xf, bf, xc, g, i, row % g.fy, row / g.fy, na);
+}
+
+__global__ __launch_bounds__(TPB) void k_comp_res_coarse(double* __restrict__ rc,
+                                                         const double* __restrict__ xc,
+                                                         const double* __restrict__ xf,
+                                                         const double* __restrict__ bc,
+                                                         CompGeom g) {
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= (uint32_t)g.nx * g.ny * g.nz) return;
+  const int x = t % g.nx;
+  const int row = t / g.nx;
+  const int y = row % g.ny, z = row / g.ny;
+  if (covered(g, x, y, z)) {
+    rc[t] = 0.0;
+    return;
+  }
+  double diag, off;
+  coarse_row(xc, xf, g, x, y, z, diag, off);
+  rc[t] = (bc ? bc[t] : 0.0) - (diag * xc[t] - off) * g.ih2;
+}
+
+__global__ __launch_bounds__(TPB) void k_comp_res_fine(double* __restrict__ rf,
+                                                       const double* __restrict__ xf,
+                                                       const double* __restrict__ xc,
+                                                       const double* __restrict__ bf,
+                                                       CompGeom g) {
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= (uint32_t)g.fx * g.fy * g.fz) return;
+  const int i = t % g.fx;
+  const int row = t / g.fx;
+  double diag, off;
+  fine_row(xf, xc, g, i, row % g.fy, row / g.fy, diag, off);
+  rf[t] = (bf ? bf[t] : 0.0) - (diag * xf[t] - off) * g.ih2;
+}
+
+// 1D weights P(p, J) of the fine cells p = 2J-1 .. 2J+2 (absolute fine coordinates) around base
+// cell J; on the wall axis the child next to a wall takes 3/4 - 1/4 (antisymmetric ghost).
+// Returns the count of fine cells inside [lo, lo + n) with their box coordinates.
+__device__ __forceinline__ int restrict_1d(int J, int nbase, bool periodic, int lo, int n,
+                                           int* idx, double* w) {
+  int cnt = 0;
+#pragma unroll
+  for (int d = -1; d <= 2; ++d) {
+    int p = 2 * J + d;
+    if (periodic) {
+      p = p < 0 ? p + 2 * nbase : (p >= 2 * nbase ? p - 2 * nbase : p);
+    } else if (p < 0 || p >= 2 * nbase) {
+      continue;
+    }
+    const int q = p - lo;
+    if (q < 0 || q >= n) continue;
+    double wt = (d == 0 || d == 1) ? 0.75 : 0.25;
+    if (!periodic && ((d == 0 && J == 0) || (d == 1 && J == nbase - 1))) wt -= 0.25;
+    idx[cnt] = q;
+    w[cnt] = wt;
+    ++cnt;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(TPB) void k_comp_restrict(double* __restrict__ b0,
+                                                       double* __restrict__ x0,
+                                                       const double* __restrict__ rc,
+                                                       const double* __restrict__ rf,
+                                                       CompGeom g) {
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= (uint32_t)g.nx * g.ny * g.nz) return;
+  const int X = t % g.nx;
+  const int row = t / g.nx;
+  const int Y = row % g.ny, Z = row / g.ny;
+  double v = rc[t];
+  int ix[4], iy[4], iz[4];
+  double wx[4], wy[4], wz[4];
+  const int cx = restrict_1d(X, g.nx, true, 2 * g.x0, g.fx, ix, wx);
+  if (cx > 0) {
+    const int cy = restrict_1d(Y, g.ny, true, 2 * g.y0, g.fy, iy, wy);
+    const int cz = cy > 0 ? restrict_1d(Z, g.nz, false, 2 * g.z0, g.fz, iz, wz) : 0;
+    for (int c = 0; c < cz; ++c)
+      for (int b = 0; b < cy; ++b) {
+        double s = 0.0;
+        for (int a = 0; a < cx; ++a) s = fma(wx[a], rf[fidx(g, ix[a], iy[b], iz[c])], s);
+        v = fma(wz[c] * wy[b], s, v);
+      }
+  }
+  b0[t] = v;
+  x0[t] = 0.0;
+}
+
+// trilinear 1D entries of fine coordinate p: (J, 3/4) and (neighbour, 1/4); at a wall the
+// neighbour is the ghost -c_J
+__device__ __forceinline__ void prolong_1d(int p, int nbase, bool periodic, int* J, double* w) {
+  const int j = p >> 1;
+  int o = (p & 1) ? j + 1 : j - 1;
+  J[0] = j;
+  w[0] = 0.75;
+  if (periodic) {
+    J[1] = wrapm(o, nbase);
+    w[1] = 0.25;
+  } else if (o >= 0 && o < nbase) {
+    J[1] = o;
+    w[1] = 0.25;
+  } else {
+    J[1] = j;
+    w[1] = -0.25;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_comp_prolong_coarse(double* __restrict__ xc,
+                                                             const double* __restrict__ y,
+                                                             CompGeom g) {
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= (uint32_t)g.nx * g.ny * g.nz) return;
+  const int x = t % g.nx;
+  const int row = t / g.nx;
+  if (!covered(g, x, row % g.ny, row / g.ny)) xc[t] += y[t];
+}
+
+__global__ __launch_bounds__(TPB) void k_comp_prolong_fine(double* __restrict__ xf,
+                                                           const double* __restrict__ y,
+                                                           CompGeom g) {
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= (uint32_t)g.fx * g.fy * g.fz) return;
+  const int i = t % g.fx;
+  const int row = t / g.fx;
+  const int j = row % g.fy, k = row / g.fy;
+  int JX[2], JY[2], JZ[2];
+  double wx[2], wy[2], wz[2];
+  prolong_1d(2 * g.x0 + i, g.nx, true, JX, wx);
+  prolong_1d(2 * g.y0 + j, g.ny, true, JY, wy);
+  prolong_1d(2 * g.z0 + k, g.nz, false, JZ, wz);
+  double v = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const double* yr = y + (size_t)g.nx * (JY[b] + g.ny * JZ[c]);
+      const double s = fma(wx[0], yr[JX[0]], wx[1] * yr[JX[1]]);
+      v = fma(wz[c] * wy[b], s, v);
+    }
+  xf[t] += v;
+}
+
+// ---------------------------------------------------------------- Galerkin base levels
+__device__ __forceinline__ void decode(int code, int& dx, int& dy, int& dz) {
+  dz = code / 25 - 2;
+  dy = (code / 5) % 5 - 2;
+  dx = code % 5 - 2;
+}
+
+// Eight lanes per 2x2x2 block (lane k = in-block index dx + 2dy + 4dz): each forms its cell's
+// residual against the cells outside the block, the eight are exchanged within the group, and
+// the block is drawn from its conditional law x_B = A_BB^-1 r_B + sqrt(kT) L_BB^-T n_B.
+template <bool NOISE>
+__global__ __launch_bounds__(TPB) void k_gblock_pass(double* __restrict__ x,
+                                                     const double* __restrict__ b, GStencil st,
+                                                     int colour, NoiseArgs na) {
+  const int nbx = st.nx >> 1, nby = st.ny >> 1, nbz = st.nz >> 1;
+  const int hbx = nbx >> 1, hby = nby >> 1;
+  const int pz = colour >> 2;
+  const int nbzc = (nbz + 1 - pz) >> 1;
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  // the total is a multiple of 8 and so is TPB: a group of eight lanes is active as a whole
+  if (t >= (uint32_t)hbx * hby * nbzc * 8) return;
+  const int k = t & 7;
+  const uint32_t q = t >> 3;
+  const int i = q % hbx;
+  const uint32_t q2 = q / hbx;
+  const int bx = 2 * i + (colour & 1);
+  const int by = 2 * (int)(q2 % hby) + ((colour >> 1) & 1);
+  const int bz = 2 * (int)(q2 / hby) + pz;
+  const int cx = 2 * bx + (k & 1), cy = 2 * by + ((k >> 1) & 1), cz = 2 * bz + (k >> 2);
+  const uint32_t blk = bx + nbx * (by + nby * bz);
+  const int typ = st.btype[blk];
+  const int sid = st.bt_sid[typ * 8 + k];
+  const uint32_t cell = cx + st.nx * (cy + st.ny * cz);
+  double r = b ? b[cell] : 0.0;
+  const int e1 = st.st_off[sid + 1];
+  for (int e = st.st_off[sid]; e < e1; ++e) {
+    int dx, dy, dz;
+    decode(st.st_code[e], dx, dy, dz);
+    const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
+    if ((tx >> 1) == bx && (ty >> 1) == by && (tz >> 1) == bz) continue;
+    r = fma(-st.st_val[e], x[tx + st.nx * (ty + st.ny * tz)], r);
+  }
+  const double* F = st.bt_fac + (size_t)typ * 128;
+  double v = 0.0;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) v = fma(F[k * 8 + m], __shfl(r, m, 8), v);
+  if (NOISE) {
+    double z0, z1;
+    normal_pair(na, na.sid, 0u, (8u * blk + k) >> 1, z0, z1);
+    const double nk = (k & 1) ? z1 : z0;
+    double w = 0.0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) w = fma(F[64 + k * 8 + m], __shfl(nk, m, 8), w);
+    v = fma(na.sqkT, w, v);
+  }
+  x[cell] = v;
+}
+
+__global__ __launch_bounds__(TPB) void k_gresidual(double* __restrict__ r,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ b, GStencil st) {
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= (uint32_t)st.nx * st.ny * st.nz) return;
+  const int cx = t % st.nx;
+  const int row = t / st.nx;
+  const int cy = row % st.ny, cz = row / st.ny;
+  const uint32_t blk = (cx >> 1) + (st.nx >> 1) * ((cy >> 1) + (st.ny >> 1) * (cz >> 1));
+  const int k = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+  const int sid = st.bt_sid[st.btype[blk] * 8 + k];
+  double v = b ? b[t] : 0.0;
+  const int e1 = st.st_off[sid + 1];
+  for (int e = st.st_off[sid]; e < e1; ++e) {
+    int dx, dy, dz;
+    decode(st.st_code[e], dx, dy, dz);
+    const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
+    v = fma(-st.st_val[e], x[tx + st.nx * (ty + st.ny * tz)], v);
+  }
+  r[t] = v;
+}
+
+}  // namespace
+
+hipError_t launch_comp_coarse_pass(double* xc, const double* bc, const double* xf,
+                                   const CompGeom& g, int colour, bool noise, const NoiseArgs& na,
+                                   hipStream_t s) {
+  const uint32_t grid = grid_for((int64_t)(g.nx / 2) * g.ny * g.nz);
+  if (noise) k_comp_coarse_pass<true><<<grid, TPB, 0, s>>>(xc, bc, xf, g, colour, na);
+  else k_comp_coarse_pass<false><<<grid, TPB, 0, s>>>(xc, bc, xf, g, colour, na);
+  return hipGetLastError();
+}
+
+hipError_t launch_comp_fine_pass(double* xf, const double* bf, const CompGeom& g, int colour,
+                                 bool noise, const NoiseArgs& na, hipStream_t s) {
+  const uint32_t grid = grid_for((int64_t)(g.fx / 2) * g.fy * g.fz);
+  if (noise) k_comp_fine_pass<true><<<grid, TPB, 0, s>>>(xf, bf, g, colour, na);
+  else k_comp_fine_pass<false><<<grid, TPB, 0, s>>>(xf, bf, g, colour, na);
+  return hipGetLastError();
+}
+
+hipError_t launch_comp_layer_pass(double* xf, const double* bf, const double* xc,
+                                  const CompGeom& g, const int32_t* cells, int count, bool noise,
+                                  const NoiseArgs& na, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const uint32_t grid = grid_for(count);
+  if (noise) k_comp_layer_pass<true><<<grid, TPB, 0, s>>>(xf, bf, xc, g, cells, count, na);
+  else k_comp_layer_pass<false><<<grid, TPB, 0, s>>>(xf, bf, xc, g, cells, count, na);
+  return hipGetLastError();
+}
+
+hipError_t launch_comp_residual(double* rc, double* rf, const double* xc, const double* xf,
+                                const double* bc, const double* bf, const CompGeom& g,
+                                hipStream_t s) {
+  k_comp_res_coarse<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(rc, xc, xf, bc, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_comp_res_fine<<<grid_for((int64_t)g.fx * g.fy * g.fz), TPB, 0, s>>>(rf, xf, xc, bf, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_comp_restrict(double* b0, double* x0, const double* rc, const double* rf,
+                                const CompGeom& g, hipStream_t s) {
+  k_comp_restrict<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(b0, x0, rc, rf, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_comp_prolong(double* xc, double* xf, const double* y, const CompGeom& g,
+                               hipStream_t s) {
+  k_comp_prolong_coarse<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(xc, y, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_comp_prolong_fine<<<grid_for((int64_t)g.fx * g.fy * g.fz), TPB, 0, s>>>(xf, y, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gblock_pass(double* x, const double* b, const GStencil& st, int colour,
+                              bool noise, const NoiseArgs& na, hipStream_t s) {
+  const int nbz = st.nz / 2;
+  const int64_t total = (int64_t)(st.nx / 4) * (st.ny / 4) * ((nbz + 1 - (colour >> 2)) / 2) * 8;
+  if (total <= 0) return hipSuccess;
+  if (noise) k_gblock_pass<true><<<grid_for(total), TPB, 0, s>>>(x, b, st, colour, na);
+  else k_gblock_pass<false><<<grid_for(total), TPB, 0, s>>>(x, b, st, colour, na);
+  return hipGetLastError();
+}
+
+hipError_t launch_gresidual(double* r, const double* x, const double* b, const GStencil& st,
+                            hipStream_t s) {
+  k_gresidual<<<grid_for((int64_t)st.nx * st.ny * st.nz), TPB, 0, s>>>(r, x, b, st);
+  return hipGetLastError();
+}
+
+}  // namespace smg

@@ -149,3 +149,19 @@ def test_fac_solve_matches_direct():
     assert rel <= 1e-11 and k <= 14
     ref = spla.spsolve(g.A.tocsc(), f)
     assert np.abs(u - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_row_of_matches_assembly():
+    from oracle.composite import row_of
+    nx, ny, nz, box, h = 12, 8, 6, (0, 5, 3, 7, 0, 6), 0.8
+    g = CompositeGrid(nx, ny, nz, box, h=h)
+    A = g.A.toarray()
+    for r in range(g.n):
+        if r < g.nc:
+            row = row_of(nx, ny, nz, box, h, "c", int(g.coarse_cells[r]))
+        else:
+            row = row_of(nx, ny, nz, box, h, "f", r - g.nc)
+        dense = np.zeros(g.n)
+        for (kind, q), v in row.items():
+            dense[g.coarse_id[q] if kind == "c" else g.nc + q] += v
+        assert np.abs(dense - A[r]).max() < 1e-13 * np.abs(A[r]).max()
