@@ -73,8 +73,10 @@ struct GLevel {
   std::unordered_map<std::string, int32_t> dedup;
   std::vector<int32_t> btype, bt_sid;
   std::vector<double> bt_fac;
+  std::vector<StEntry> ent;  // device form of (st_code, st_val)
+  int split = 1;
   size_t off_x = 0, off_b = 0, off_r = 0, off_btype = 0, off_btsid = 0, off_btfac = 0,
-         off_stoff = 0, off_stcode = 0, off_stval = 0;
+         off_stoff = 0, off_ent = 0;
   double* x = nullptr;
   double* b = nullptr;
   double* r = nullptr;
@@ -711,9 +713,14 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
     L.off_btype = take(L.btype.size() * 4);
     L.off_btsid = take(L.bt_sid.size() * 4);
     L.off_btfac = take(L.bt_fac.size() * 8);
+    L.ent.resize(L.st_code.size());
+    for (size_t e = 0; e < L.st_code.size(); ++e) L.ent[e] = StEntry{L.st_val[e], L.st_code[e], 0};
+    // rows longer than 16 entries on average over the cells: eight lanes per row
+    double tot = 0.0;
+    for (int64_t c = 0; c < L.n; ++c) tot += L.st_off[L.sid[c] + 1] - L.st_off[L.sid[c]];
+    L.split = tot > 16.0 * (double)L.n ? 8 : 1;
     L.off_stoff = take(L.st_off.size() * 4);
-    L.off_stcode = take(std::max<size_t>(1, L.st_code.size()) * 4);
-    L.off_stval = take(std::max<size_t>(1, L.st_val.size()) * 8);
+    L.off_ent = take(std::max<size_t>(1, L.ent.size()) * sizeof(StEntry));
   }
   C.off_ainv = take((size_t)C.ncd * C.ncd * 8);
   C.off_w = take((size_t)C.ncd * C.ncd * 8);
@@ -916,14 +923,13 @@ int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stre
     CMP_HIP(up(L.off_btsid, L.bt_sid.data(), L.bt_sid.size() * 4));
     CMP_HIP(up(L.off_btfac, L.bt_fac.data(), L.bt_fac.size() * 8));
     CMP_HIP(up(L.off_stoff, L.st_off.data(), L.st_off.size() * 4));
-    CMP_HIP(up(L.off_stcode, L.st_code.data(), L.st_code.size() * 4));
-    CMP_HIP(up(L.off_stval, L.st_val.data(), L.st_val.size() * 8));
+    CMP_HIP(up(L.off_ent, L.ent.data(), L.ent.size() * sizeof(smg::StEntry)));
     L.dev.btype = (const int32_t*)(ws + L.off_btype);
     L.dev.bt_sid = (const int32_t*)(ws + L.off_btsid);
     L.dev.bt_fac = (const double*)(ws + L.off_btfac);
     L.dev.st_off = (const int32_t*)(ws + L.off_stoff);
-    L.dev.st_code = (const int32_t*)(ws + L.off_stcode);
-    L.dev.st_val = (const double*)(ws + L.off_stval);
+    L.dev.ent = (const smg::StEntry*)(ws + L.off_ent);
+    L.dev.split = L.split;
     L.dev.nx = L.nx;
     L.dev.ny = L.ny;
     L.dev.nz = L.nz;

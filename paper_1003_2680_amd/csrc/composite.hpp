@@ -34,14 +34,19 @@ struct CompGeom {
 // block type, a block type names the stencil of each of its 8 cells (in-block index
 // dx + 2dy + 4dz) and carries the factors of its 8x8 diagonal block; a stencil is a list of
 // (offset code, coefficient), code = (dz+2)*25 + (dy+2)*5 + (dx+2), offsets periodic in x, y.
+struct StEntry {
+  double a;      // coefficient
+  int32_t code;  // offset code
+  int32_t pad;
+};
 struct GStencil {
   const int32_t* btype;   // [n/8]
   const int32_t* bt_sid;  // [types][8]
   const double* bt_fac;   // [types][128]: A_BB^-1 then L_BB^-T, row-major
   const int32_t* st_off;  // [stencils + 1]
-  const int32_t* st_code;
-  const double* st_val;
+  const StEntry* ent;     // entries of every stencil
   int nx, ny, nz;
+  int split;              // lanes per row in the kernels: 1 or 8 (long rows)
 };
 
 // Point heat bath of one class of the composite sweep (x_i = (b_i - sum_j A_ij x_j)/A_ii +

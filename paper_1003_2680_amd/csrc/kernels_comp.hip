@@ -340,10 +340,57 @@ __device__ __forceinline__ void decode(int code, int& dx, int& dy, int& dz) {
   dx = code % 5 - 2;
 }
 
-// Eight lanes per 2x2x2 block (lane k = in-block index dx + 2dy + 4dz): each forms its cell's
-// residual against the cells outside the block, the eight are exchanged within the group, and
-// the block is drawn from its conditional law x_B = A_BB^-1 r_B + sqrt(kT) L_BB^-T n_B.
-template <bool NOISE>
+// Partial sum over the stencil entries e0 + sub, e0 + sub + S, ... of cell (cx, cy, cz):
+// r -= a_e x[target_e], skipping targets inside block (bx, by, bz) when SKIP.  Entries are read
+// as (coefficient, code) records and processed eight at a time with independent loads, so the
+// latency of the gathers overlaps instead of forming one chain per entry.
+template <int S, bool SKIP>
+__device__ __forceinline__ double stencil_partial(const GStencil& st, const double* __restrict__ x,
+                                                  int sid, int sub, int cx, int cy, int cz,
+                                                  int bx, int by, int bz, double r) {
+  const int e1 = st.st_off[sid + 1];
+  int e = st.st_off[sid] + sub;
+  for (; e + 7 * S < e1; e += 8 * S) {
+    double a[8], xv[8];
+    bool use[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const StEntry en = st.ent[e + q * S];
+      int dx, dy, dz;
+      decode(en.code, dx, dy, dz);
+      const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
+      use[q] = !SKIP || !((tx >> 1) == bx && (ty >> 1) == by && (tz >> 1) == bz);
+      a[q] = en.a;
+      xv[q] = x[tx + st.nx * (ty + st.ny * tz)];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (use[q]) r = fma(-a[q], xv[q], r);
+  }
+  for (; e < e1; e += S) {
+    const StEntry en = st.ent[e];
+    int dx, dy, dz;
+    decode(en.code, dx, dy, dz);
+    const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
+    if (SKIP && (tx >> 1) == bx && (ty >> 1) == by && (tz >> 1) == bz) continue;
+    r = fma(-en.a, x[tx + st.nx * (ty + st.ny * tz)], r);
+  }
+  return r;
+}
+
+// sum over the S consecutive lanes of a row
+template <int S>
+__device__ __forceinline__ double row_reduce(double r) {
+#pragma unroll
+  for (int m = 1; m < S; m <<= 1) r += __shfl_xor(r, m, S);
+  return r;
+}
+
+// 8*S lanes per 2x2x2 block: S lanes share the row of each of its 8 cells (in-block index
+// k = dx + 2dy + 4dz).  The cells' residuals against everything outside the block are
+// exchanged within the group and the block is drawn from its conditional law
+// x_B = A_BB^-1 r_B + sqrt(kT) L_BB^-T n_B; the first lane of each row writes it.
+template <bool NOISE, int S>
 __global__ __launch_bounds__(TPB) void k_gblock_pass(double* __restrict__ x,
                                                      const double* __restrict__ b, GStencil st,
                                                      int colour, NoiseArgs na) {
@@ -352,10 +399,11 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(double* __restrict__ x,
   const int pz = colour >> 2;
   const int nbzc = (nbz + 1 - pz) >> 1;
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
-  // the total is a multiple of 8 and so is TPB: a group of eight lanes is active as a whole
-  if (t >= (uint32_t)hbx * hby * nbzc * 8) return;
-  const int k = t & 7;
-  const uint32_t q = t >> 3;
+  // the total is a multiple of 8*S and so is TPB: a block's group of lanes is active as a whole
+  if (t >= (uint32_t)hbx * hby * nbzc * 8 * S) return;
+  const int sub = t % S;
+  const int k = (t / S) & 7;
+  const uint32_t q = t / (8 * S);
   const int i = q % hbx;
   const uint32_t q2 = q / hbx;
   const int bx = 2 * i + (colour & 1);
@@ -366,51 +414,41 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(double* __restrict__ x,
   const int typ = st.btype[blk];
   const int sid = st.bt_sid[typ * 8 + k];
   const uint32_t cell = cx + st.nx * (cy + st.ny * cz);
-  double r = b ? b[cell] : 0.0;
-  const int e1 = st.st_off[sid + 1];
-  for (int e = st.st_off[sid]; e < e1; ++e) {
-    int dx, dy, dz;
-    decode(st.st_code[e], dx, dy, dz);
-    const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
-    if ((tx >> 1) == bx && (ty >> 1) == by && (tz >> 1) == bz) continue;
-    r = fma(-st.st_val[e], x[tx + st.nx * (ty + st.ny * tz)], r);
-  }
+  double r = (b && sub == 0) ? b[cell] : 0.0;
+  r = row_reduce<S>(stencil_partial<S, true>(st, x, sid, sub, cx, cy, cz, bx, by, bz, r));
   const double* F = st.bt_fac + (size_t)typ * 128;
   double v = 0.0;
 #pragma unroll
-  for (int m = 0; m < 8; ++m) v = fma(F[k * 8 + m], __shfl(r, m, 8), v);
+  for (int m = 0; m < 8; ++m) v = fma(F[k * 8 + m], __shfl(r, m * S, 8 * S), v);
   if (NOISE) {
     double z0, z1;
     normal_pair(na, na.sid, 0u, (8u * blk + k) >> 1, z0, z1);
     const double nk = (k & 1) ? z1 : z0;
     double w = 0.0;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) w = fma(F[64 + k * 8 + m], __shfl(nk, m, 8), w);
+    for (int m = 0; m < 8; ++m) w = fma(F[64 + k * 8 + m], __shfl(nk, m * S, 8 * S), w);
     v = fma(na.sqkT, w, v);
   }
-  x[cell] = v;
+  if (sub == 0) x[cell] = v;
 }
 
+template <int S>
 __global__ __launch_bounds__(TPB) void k_gresidual(double* __restrict__ r,
                                                    const double* __restrict__ x,
                                                    const double* __restrict__ b, GStencil st) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
-  if (t >= (uint32_t)st.nx * st.ny * st.nz) return;
-  const int cx = t % st.nx;
-  const int row = t / st.nx;
+  if (t >= (uint32_t)st.nx * st.ny * st.nz * S) return;
+  const int sub = t % S;
+  const uint32_t c = t / S;
+  const int cx = c % st.nx;
+  const int row = c / st.nx;
   const int cy = row % st.ny, cz = row / st.ny;
   const uint32_t blk = (cx >> 1) + (st.nx >> 1) * ((cy >> 1) + (st.ny >> 1) * (cz >> 1));
   const int k = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
   const int sid = st.bt_sid[st.btype[blk] * 8 + k];
-  double v = b ? b[t] : 0.0;
-  const int e1 = st.st_off[sid + 1];
-  for (int e = st.st_off[sid]; e < e1; ++e) {
-    int dx, dy, dz;
-    decode(st.st_code[e], dx, dy, dz);
-    const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
-    v = fma(-st.st_val[e], x[tx + st.nx * (ty + st.ny * tz)], v);
-  }
-  r[t] = v;
+  double v = (b && sub == 0) ? b[c] : 0.0;
+  v = row_reduce<S>(stencil_partial<S, false>(st, x, sid, sub, cx, cy, cz, 0, 0, 0, v));
+  if (sub == 0) r[c] = v;
 }
 
 }  // namespace
@@ -470,16 +508,23 @@ hipError_t launch_comp_prolong(double* xc, double* xf, const double* y, const Co
 hipError_t launch_gblock_pass(double* x, const double* b, const GStencil& st, int colour,
                               bool noise, const NoiseArgs& na, hipStream_t s) {
   const int nbz = st.nz / 2;
-  const int64_t total = (int64_t)(st.nx / 4) * (st.ny / 4) * ((nbz + 1 - (colour >> 2)) / 2) * 8;
-  if (total <= 0) return hipSuccess;
-  if (noise) k_gblock_pass<true><<<grid_for(total), TPB, 0, s>>>(x, b, st, colour, na);
-  else k_gblock_pass<false><<<grid_for(total), TPB, 0, s>>>(x, b, st, colour, na);
+  const int64_t groups = (int64_t)(st.nx / 4) * (st.ny / 4) * ((nbz + 1 - (colour >> 2)) / 2) * 8;
+  if (groups <= 0) return hipSuccess;
+  if (st.split == 8) {
+    if (noise) k_gblock_pass<true, 8><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
+    else k_gblock_pass<false, 8><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
+  } else {
+    if (noise) k_gblock_pass<true, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
+    else k_gblock_pass<false, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_gresidual(double* r, const double* x, const double* b, const GStencil& st,
                             hipStream_t s) {
-  k_gresidual<<<grid_for((int64_t)st.nx * st.ny * st.nz), TPB, 0, s>>>(r, x, b, st);
+  const int64_t n = (int64_t)st.nx * st.ny * st.nz;
+  if (st.split == 8) k_gresidual<8><<<grid_for(n * 8), TPB, 0, s>>>(r, x, b, st);
+  else k_gresidual<1><<<grid_for(n), TPB, 0, s>>>(r, x, b, st);
   return hipGetLastError();
 }
 

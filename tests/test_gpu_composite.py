@@ -4,8 +4,8 @@ Every piece is compared element by element with the oracle on the same seeded in
 same counter-based noise: the composite residual, each of the twelve point classes of a
 composite sweep, the block passes of the Galerkin base levels, whole stochastic and
 deterministic FAC cycles, a sampling run and the solve.  Cases cover a box on the bottom wall,
-an interior box with three base levels, and a box on the periodic seam touching both walls
-(ny = 12, not a power of two).  FP64 on both sides; the tolerance covers summation order only.
+an interior box with three base levels, a box on the periodic seam touching both walls
+(ny = 12, not a power of two), and a small box in a larger base grid (short rows).  FP64 on both sides; the tolerance covers summation order only.
 """
 import numpy as np
 import pytest
@@ -20,6 +20,8 @@ CASES = {
     "wall_box": (8, 8, 4, (2, 6, 2, 6, 0, 2), 64),
     "interior_3lev": (16, 16, 8, (4, 12, 3, 11, 1, 5), 64),
     "seam_walls": (16, 12, 8, (0, 6, 5, 12, 0, 8), 64),
+    # small box in a larger base grid: most base rows are 7-point (one lane per row)
+    "small_box_32": (32, 32, 16, (12, 20, 12, 20, 4, 8), 512),
 }
 TOL = 1e-11
 
