@@ -296,6 +296,113 @@ def measure_hbm_point(dev, dims=(512, 512, 256), cycles=10):
                           "achieved_GBs": round(ach, 1), "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)}}
 
 
+COMP_BASE = (256, 256, 128)
+COMP_BOX = (64, 192, 64, 192, 0, 32)
+
+
+def composite_cpu_baseline(seconds=10.0):
+    """The oracle's FAC cycle (oracle.composite, unmodified) on the 16^3-base copy of the
+    adaptive workload (box [4,12)^2 x [0,4), 5888 unknowns): unknown-cycles/s on the host."""
+    import numpy as np
+    import threadpoolctl
+    from oracle.composite import CompositeGrid, FACSampler
+    from oracle.philox import PhiloxNoise
+    g = CompositeGrid(16, 16, 16, (4, 12, 4, 12, 0, 4))
+    fac = FACSampler(g, kT=1.0)
+    x = np.zeros(g.n)
+    zero = np.zeros(g.n)
+    noise = PhiloxNoise(0)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        x = fac.cycle(x, zero, noise, n)
+        n += 1
+    dt = time.perf_counter() - t0
+    info = threadpoolctl.threadpool_info()
+    cores = max([i.get("num_threads", 1) for i in info] + [1])
+    return {"value": round(g.n * n / dt, 1), "unit": "unknown-cycles/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d stochastic FAC cycles of the oracle on the 16^3-base copy (%d unknowns), "
+                      "%.1f s; NumPy/SciPy sparse, BLAS threads as listed" % (n, g.n, dt)}
+
+
+def measure_composite(dev, cycles=20, with_cpu=True):
+    """Spatially adaptive composite grid: 256x256x128 base, box [64,192)^2 x [0,32) refined by
+    two (12.06 M unknowns), stochastic FAC cycle nu=2 with a V(2,2) base cycle, FP64."""
+    import numpy as np
+    import torch
+    from paper_1003_2680_amd.composite import CompositeSampler
+    from paper_1003_2680_amd.inputs import gaussian_field
+    t0 = time.perf_counter()
+    S = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0)
+    plan_s = time.perf_counter() - t0
+    info = S.info
+    xc, xf = S.zeros()
+    S.sample(xc, xf, 5, seed=0, first_cycle=0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.sample(xc, xf, cycles, seed=0, first_cycle=5)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / cycles
+    rc, rf = S.residual(xc, xf)
+    energy = -(xc.reshape(-1) @ rc.reshape(-1) + xf.reshape(-1) @ rf.reshape(-1)).item()
+    n = int(info.unknowns)
+    fc = torch.from_numpy(gaussian_field(S.base_shape, 7)).to(dev)
+    ff = torch.from_numpy(gaussian_field(S.fine_shape, 8)).to(dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, _, si = S.solve(fc, ff, rtol=1e-10, max_cycles=60)
+    solve_s = time.perf_counter() - t1
+    rho = max(float(si.last_ratio), 1e-3)
+    k_dec = max(1, math.ceil(math.log(0.01) / math.log(rho)))
+    # dominant kernel: the block colour pass of the finest base level (A_0 = P^T A P on
+    # 256x256x128), timed live on the stream it runs on
+    nb = info.dims[0][0] * info.dims[0][1] * info.dims[0][2]
+    x0 = torch.from_numpy(gaussian_field((nb,), 9)).to(dev)
+    b0 = torch.from_numpy(gaussian_field((nb,), 10)).to(dev)
+    S.debug_base_pass(0, 0, x0, b0, seed=1, cycle=0)
+    reps = 10
+    torch.cuda.synchronize()
+    e0.record()
+    for r in range(reps):
+        for c in range(8):
+            S.debug_base_pass(0, c, x0, b0, seed=1, cycle=r, slot=0)
+    e1.record()
+    torch.cuda.synchronize()
+    avg_s = e0.elapsed_time(e1) / 1e3 / (8 * reps)
+    # algorithmic bytes of one colour pass: x of the three neighbouring block colours (3/8 of
+    # the level), b and x of this colour's cells (read b, write x: 2/8), 8 B per value
+    nbytes = nb * 8 * 5 // 8
+    ach = nbytes / avg_s / 1e9
+    out = {
+        "workload": "adaptive composite grid: 256x256x128 base (periodic x,y; no-slip z walls) "
+                    "with the box [64,192)^2 x [0,32) refined by two; FAC cycle nu=2, base "
+                    "V(2,2) on Galerkin levels, exact coarsest; FP64",
+        "unknowns": n, "base_levels": [list(info.dims[l]) for l in range(info.n_levels)],
+        "distinct_rows_per_level": list(info.stencils[:info.n_levels]),
+        "plan_s": round(plan_s, 2),
+        "ms_per_cycle": round(ms, 3), "cycles_per_s": round(1e3 / ms, 2),
+        "unknown_cycles_per_s": float("%.4e" % (n * 1e3 / ms)),
+        "rho_solve": round(rho, 4), "k_dec": k_dec,
+        "decorrelated_samples_per_s": round(1e3 / ms / k_dec, 3),
+        "solve_ms": round(solve_s * 1e3, 2), "solve_cycles": int(si.cycles),
+        "solve_relres": float("%.3e" % si.relres),
+        "energy_over_n_kT": round(energy / n, 5),
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_gblock_pass (block colour pass, finest base level)",
+                     "avg_launch_us": round(avg_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": nbytes},
+    }
+    del S, xc, xf, rc, rf, fc, ff, x0, b0
+    torch.cuda.empty_cache()
+    if with_cpu:
+        out["cpu_baseline"] = composite_cpu_baseline()
+    return out
+
+
 def measure_batched(dev, n_instances=64, n_samples=100):
     """64 uneven instances ({32,48,64,96}^3 drawn by seed), FP32-refined, tuned per grid:
     100 samples (float32, in HBM) and one solve to 1e-10 per instance, grouped launches; beside
@@ -413,6 +520,10 @@ def main():
                     help="skip the single 512x512x256 grid (beyond the Infinity Cache)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-loop measurement")
+    ap.add_argument("--no-composite", action="store_true",
+                    help="skip the adaptive composite-grid leg")
+    ap.add_argument("--composite-only", action="store_true",
+                    help="only run the adaptive composite-grid leg (prints its object)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -422,6 +533,13 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.composite_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"composite": measure_composite(torch.device("cuda", 0),
+                                                         with_cpu=not args.no_cpu_baseline)}),
+              flush=True)
         return
 
     import numpy as np
@@ -525,6 +643,9 @@ def main():
     if not args.no_hbm_point:
         line["hbm_point"] = measure_hbm_point(dev)
         progress("512x512x256 HBM point done")
+    if not args.no_composite:
+        line["composite"] = measure_composite(dev, with_cpu=not args.no_cpu_baseline)
+        progress("adaptive composite grid done")
     if not args.no_batched:
         line["batched"] = measure_batched(dev)
         progress("batched instances done")
