@@ -298,6 +298,9 @@ def measure_hbm_point(dev, dims=(512, 512, 256), cycles=10):
 
 COMP_BASE = (256, 256, 128)
 COMP_BOX = (64, 192, 64, 192, 0, 32)
+# sweeps of the FAC cycle: the contraction is set by the composite sweeps (nu) -- base V-cycles
+# V(2,2) and V(1,0) give the same rate -- so the bench runs nu = 3 with one base pre-sweep
+COMP_NU, COMP_MU1, COMP_MU2 = 3, 1, 0
 
 
 def composite_cpu_baseline(seconds=10.0):
@@ -308,7 +311,7 @@ def composite_cpu_baseline(seconds=10.0):
     from oracle.composite import CompositeGrid, FACSampler
     from oracle.philox import PhiloxNoise
     g = CompositeGrid(16, 16, 16, (4, 12, 4, 12, 0, 4))
-    fac = FACSampler(g, kT=1.0)
+    fac = FACSampler(g, kT=1.0, nu=COMP_NU, mu1=COMP_MU1, mu2=COMP_MU2)
     x = np.zeros(g.n)
     zero = np.zeros(g.n)
     noise = PhiloxNoise(0)
@@ -328,13 +331,14 @@ def composite_cpu_baseline(seconds=10.0):
 
 def measure_composite(dev, cycles=20, with_cpu=True):
     """Spatially adaptive composite grid: 256x256x128 base, box [64,192)^2 x [0,32) refined by
-    two (12.06 M unknowns), stochastic FAC cycle nu=2 with a V(2,2) base cycle, FP64."""
+    two (12.06 M unknowns), stochastic FAC cycle (COMP_NU composite sweeps, base V-cycle
+    V(COMP_MU1, COMP_MU2)), FP64."""
     import numpy as np
     import torch
     from paper_1003_2680_amd.composite import CompositeSampler
     from paper_1003_2680_amd.inputs import gaussian_field
     t0 = time.perf_counter()
-    S = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0)
+    S = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0, nu=COMP_NU, mu1=COMP_MU1, mu2=COMP_MU2)
     plan_s = time.perf_counter() - t0
     info = S.info
     xc, xf = S.zeros()
@@ -378,8 +382,9 @@ def measure_composite(dev, cycles=20, with_cpu=True):
     ach = nbytes / avg_s / 1e9
     out = {
         "workload": "adaptive composite grid: 256x256x128 base (periodic x,y; no-slip z walls) "
-                    "with the box [64,192)^2 x [0,32) refined by two; FAC cycle nu=2, base "
-                    "V(2,2) on Galerkin levels, exact coarsest; FP64",
+                    "with the box [64,192)^2 x [0,32) refined by two; FAC cycle nu=%d, base "
+                    "V(%d,%d) on Galerkin levels, exact coarsest; FP64" % (COMP_NU, COMP_MU1,
+                                                                            COMP_MU2),
         "unknowns": n, "base_levels": [list(info.dims[l]) for l in range(info.n_levels)],
         "distinct_rows_per_level": list(info.stencils[:info.n_levels]),
         "plan_s": round(plan_s, 2),

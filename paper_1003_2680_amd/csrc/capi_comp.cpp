@@ -74,9 +74,10 @@ struct GLevel {
   std::vector<int32_t> btype, bt_sid;
   std::vector<double> bt_fac;
   std::vector<StEntry> ent;  // device form of (st_code, st_val)
+  std::vector<double> bt_c7, bt_diag;
   int split = 1;
   size_t off_x = 0, off_b = 0, off_r = 0, off_btype = 0, off_btsid = 0, off_btfac = 0,
-         off_stoff = 0, off_ent = 0;
+         off_stoff = 0, off_ent = 0, off_btc7 = 0, off_btdiag = 0;
   double* x = nullptr;
   double* b = nullptr;
   double* r = nullptr;
@@ -97,11 +98,11 @@ struct Composite {
   int nu = 2, mu1 = 2, mu2 = 2;
   std::vector<GLevel> lv;
   int ncd = 0;
-  std::vector<double> ainv, w;
+  std::vector<double> ainv, w;  // A_c^-1 and L_c^-T (row-major)
   std::vector<int32_t> layer;  // layer cells grouped by parity class
   int layer_off[9] = {0};
   size_t ws_bytes = 0, off_rc = 0, off_rf = 0, off_layer = 0, off_ainv = 0, off_w = 0,
-         off_part = 0, off_norm = 0;
+         off_part = 0, off_norm = 0, off_znoise = 0;
   char* ws = nullptr;
   int device = -1;
   double* rc = nullptr;
@@ -110,6 +111,7 @@ struct Composite {
   double* w_d = nullptr;
   double* part = nullptr;
   double* norm = nullptr;
+  double* znoise = nullptr;
   int32_t* layer_d = nullptr;
 };
 
@@ -518,6 +520,55 @@ bool build_blocks(GLevel& L, std::string& err) {
         }
         L.btype[bx + (size_t)nbx * (by + (size_t)nby * bz)] = t;
       }
+  // plain 7-point block types: every row holds the centre plus face offsets only, all
+  // off-diagonal coefficients equal; a row may lack a z face only where that face is a wall
+  const size_t ntypes = L.bt_sid.size() / 8;
+  L.bt_c7.assign(ntypes, 0.0);
+  L.bt_diag.assign(ntypes * 8, 0.0);
+  std::vector<int> zmask(ntypes * 8, 0);  // bit 0: row has -z, bit 1: row has +z
+  for (size_t t = 0; t < ntypes; ++t) {
+    double c7 = 0.0;
+    bool plain = true;
+    for (int k = 0; k < 8 && plain; ++k) {
+      const int s = L.bt_sid[t * 8 + k];
+      int faces = 0;
+      for (int e = L.st_off[s]; e < L.st_off[s + 1]; ++e) {
+        const int code = L.st_code[e];
+        const int dx = code % 5 - 2, dy = (code / 5) % 5 - 2, dz = code / 25 - 2;
+        const int ad = std::abs(dx) + std::abs(dy) + std::abs(dz);
+        if (ad == 0) {
+          L.bt_diag[t * 8 + k] = L.st_val[e];
+          continue;
+        }
+        if (ad != 1) {
+          plain = false;
+          break;
+        }
+        if (c7 == 0.0) c7 = L.st_val[e];
+        if (L.st_val[e] != c7) plain = false;
+        if (dz == -1) faces |= 1;
+        if (dz == 1) faces |= 2;
+        if (dx != 0 || dy != 0) faces |= 4 << ((dx + 1) + 3 * (dy + 1));
+      }
+      // all four x/y faces present
+      const int xy = (4 << (0 + 3)) | (4 << (2 + 3)) | (4 << (1 + 0)) | (4 << (1 + 6));
+      if ((faces & xy) != xy) plain = false;
+      zmask[t * 8 + k] = faces & 3;
+    }
+    if (plain && c7 != 0.0) L.bt_c7[t] = c7;
+  }
+  // a missing z face must be a wall for every block of the type
+  for (int bz = 0; bz < nbz; ++bz)
+    for (int by = 0; by < nby; ++by)
+      for (int bx = 0; bx < nbx; ++bx) {
+        const int t = L.btype[bx + (size_t)nbx * (by + (size_t)nby * bz)];
+        if (L.bt_c7[t] == 0.0) continue;
+        for (int k = 0; k < 8; ++k) {
+          const int cz = 2 * bz + (k >> 2);
+          const int want = (cz > 0 ? 1 : 0) | (cz + 1 < L.nz ? 2 : 0);
+          if (zmask[t * 8 + k] != want) L.bt_c7[t] = 0.0;
+        }
+      }
   return true;
 }
 
@@ -666,14 +717,17 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
       err = "coarsest operator is not positive definite";
       return SMG_EINVAL;
     }
-    C.w = lower_inv(A, n);
+    const std::vector<double> W = lower_inv(A, n);  // L_c^-1
     C.ainv.assign((size_t)n * n, 0.0);
     for (int k = 0; k < n; ++k)
       for (int i = 0; i <= k; ++i) {
-        const double a = C.w[(size_t)k * n + i];
+        const double a = W[(size_t)k * n + i];
         if (a == 0.0) continue;
-        for (int j = 0; j <= k; ++j) C.ainv[(size_t)i * n + j] += a * C.w[(size_t)k * n + j];
+        for (int j = 0; j <= k; ++j) C.ainv[(size_t)i * n + j] += a * W[(size_t)k * n + j];
       }
+    C.w.assign((size_t)n * n, 0.0);  // L_c^-T = W^T
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j <= i; ++j) C.w[(size_t)j * n + i] = W[(size_t)i * n + j];
     C.ncd = n;
   }
   // layer cells by parity class
@@ -719,6 +773,8 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
     double tot = 0.0;
     for (int64_t c = 0; c < L.n; ++c) tot += L.st_off[L.sid[c] + 1] - L.st_off[L.sid[c]];
     L.split = tot > 16.0 * (double)L.n ? 8 : 1;
+    L.off_btc7 = take(L.bt_c7.size() * 8);
+    L.off_btdiag = take(L.bt_diag.size() * 8);
     L.off_stoff = take(L.st_off.size() * 4);
     L.off_ent = take(std::max<size_t>(1, L.ent.size()) * sizeof(StEntry));
   }
@@ -726,6 +782,7 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
   C.off_w = take((size_t)C.ncd * C.ncd * 8);
   C.off_part = take((size_t)((std::max(nbase, nf) + 255) / 256 + 1) * 8);
   C.off_norm = take(64);
+  C.off_znoise = take((size_t)C.ncd * 8);
   C.ws_bytes = off;
   return SMG_OK;
 }
@@ -781,7 +838,7 @@ int base_vcycle(const CRun& r, int l) {
   GLevel& L = C.lv[l];
   if (L.coarsest) {
     const NoiseArgs na = comp_noise(C, r.seed, r.cycle, l, 0, 0, KIND_FAC_COARSEST);
-    CMP_HIP(launch_coarsest<double>(L.x, L.b, C.ainv_d, C.w_d, C.ncd, 1, r.noise, na, r.s));
+    CMP_HIP(launch_dense_draw(L.x, L.b, C.ainv_d, C.w_d, C.znoise, C.ncd, r.noise, na, r.s));
     return SMG_OK;
   }
   for (int s = 0; s < C.mu1; ++s)
@@ -802,8 +859,7 @@ int base_vcycle(const CRun& r, int l) {
 int fac_cycle(const CRun& r, double* xc, double* xf, const double* bc, const double* bf) {
   Composite& C = *r.c;
   GLevel& L0 = C.lv[0];
-  CMP_HIP(launch_comp_residual(C.rc, C.rf, xc, xf, bc, bf, C.g, r.s));
-  CMP_HIP(launch_comp_restrict(L0.b, L0.x, C.rc, C.rf, C.g, r.s));
+  CMP_HIP(launch_comp_residual_restrict(L0.b, L0.x, C.rf, xc, xf, bc, bf, C.g, r.s));
   if (int rc = base_vcycle(r, 0)) return rc;
   CMP_HIP(launch_comp_prolong(xc, xf, L0.x, C.g, r.s));
   for (int s = 0; s < C.nu; ++s)
@@ -924,12 +980,16 @@ int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stre
     CMP_HIP(up(L.off_btfac, L.bt_fac.data(), L.bt_fac.size() * 8));
     CMP_HIP(up(L.off_stoff, L.st_off.data(), L.st_off.size() * 4));
     CMP_HIP(up(L.off_ent, L.ent.data(), L.ent.size() * sizeof(smg::StEntry)));
+    CMP_HIP(up(L.off_btc7, L.bt_c7.data(), L.bt_c7.size() * 8));
+    CMP_HIP(up(L.off_btdiag, L.bt_diag.data(), L.bt_diag.size() * 8));
     L.dev.btype = (const int32_t*)(ws + L.off_btype);
     L.dev.bt_sid = (const int32_t*)(ws + L.off_btsid);
     L.dev.bt_fac = (const double*)(ws + L.off_btfac);
     L.dev.st_off = (const int32_t*)(ws + L.off_stoff);
     L.dev.ent = (const smg::StEntry*)(ws + L.off_ent);
     L.dev.split = L.split;
+    L.dev.bt_c7 = (const double*)(ws + L.off_btc7);
+    L.dev.bt_diag = (const double*)(ws + L.off_btdiag);
     L.dev.nx = L.nx;
     L.dev.ny = L.ny;
     L.dev.nz = L.nz;
@@ -946,6 +1006,7 @@ int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stre
   C.w_d = (double*)(ws + C.off_w);
   C.part = (double*)(ws + C.off_part);
   C.norm = (double*)(ws + C.off_norm);
+  C.znoise = (double*)(ws + C.off_znoise);
   return SMG_OK;
 }
 

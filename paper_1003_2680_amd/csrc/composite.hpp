@@ -45,6 +45,10 @@ struct GStencil {
   const double* bt_fac;   // [types][128]: A_BB^-1 then L_BB^-T, row-major
   const int32_t* st_off;  // [stencils + 1]
   const StEntry* ent;     // entries of every stencil
+  // block types whose 8 rows are plain 7-point (the centre and every in-grid face neighbour,
+  // one common off-diagonal coefficient): that coefficient, else 0; and the 8 diagonals
+  const double* bt_c7;    // [types]
+  const double* bt_diag;  // [types][8]
   int nx, ny, nz;
   int split;              // lanes per row in the kernels: 1 or 8 (long rows)
 };
@@ -68,12 +72,21 @@ hipError_t launch_comp_residual(double* rc, double* rf, const double* xc, const 
 // onto fine cells)
 hipError_t launch_comp_restrict(double* b0, double* x0, const double* rc, const double* rf,
                                 const CompGeom& g, hipStream_t s);
+// the two above fused for the cycle: rf = bf - (A x)_fine, then b0 = P^T (b - A x) with the
+// coarse residual formed inside the restriction (never stored), x0 = 0
+hipError_t launch_comp_residual_restrict(double* b0, double* x0, double* rf, const double* xc,
+                                         const double* xf, const double* bc, const double* bf,
+                                         const CompGeom& g, hipStream_t s);
 // (xc, xf) += P y
 hipError_t launch_comp_prolong(double* xc, double* xf, const double* y, const CompGeom& g,
                                hipStream_t s);
 // 2x2x2 block heat bath of one block colour on a Galerkin base level (b null = 0)
 hipError_t launch_gblock_pass(double* x, const double* b, const GStencil& st, int colour,
                               bool noise, const NoiseArgs& na, hipStream_t s);
+// coarsest base level: x = A_c^-1 b (+ sqrt(kT) L_c^-T z), z (n doubles of scratch) filled with
+// the level's normals; wt = L_c^-T row-major
+hipError_t launch_dense_draw(double* x, const double* b, const double* ainv, const double* wt,
+                             double* z, int n, bool noise, const NoiseArgs& na, hipStream_t s);
 // r = b - A x on a Galerkin base level
 hipError_t launch_gresidual(double* r, const double* x, const double* b, const GStencil& st,
                             hipStream_t s);

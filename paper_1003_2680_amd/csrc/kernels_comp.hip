@@ -251,17 +251,31 @@ __device__ __forceinline__ int restrict_1d(int J, int nbase, bool periodic, int 
   return cnt;
 }
 
+// b0 = P^T r over the base grid and x0 = 0.  The coarse residual either comes from rc or (rc
+// null) is formed here from (xc, xf, bc), so the cycle never stores it.
 __global__ __launch_bounds__(TPB) void k_comp_restrict(double* __restrict__ b0,
                                                        double* __restrict__ x0,
                                                        const double* __restrict__ rc,
                                                        const double* __restrict__ rf,
+                                                       const double* __restrict__ xc,
+                                                       const double* __restrict__ xf,
+                                                       const double* __restrict__ bc,
                                                        CompGeom g) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)g.nx * g.ny * g.nz) return;
   const int X = t % g.nx;
   const int row = t / g.nx;
   const int Y = row % g.ny, Z = row / g.ny;
-  double v = rc[t];
+  double v;
+  if (rc) {
+    v = rc[t];
+  } else if (covered(g, X, Y, Z)) {
+    v = 0.0;
+  } else {
+    double diag, off;
+    coarse_row(xc, xf, g, X, Y, Z, diag, off);
+    v = (bc ? bc[t] : 0.0) - (diag * xc[t] - off) * g.ih2;
+  }
   int ix[4], iy[4], iz[4];
   double wx[4], wy[4], wz[4];
   const int cx = restrict_1d(X, g.nx, true, 2 * g.x0, g.fx, ix, wx);
@@ -349,31 +363,28 @@ __device__ __forceinline__ double stencil_partial(const GStencil& st, const doub
                                                   int sid, int sub, int cx, int cy, int cz,
                                                   int bx, int by, int bz, double r) {
   const int e1 = st.st_off[sid + 1];
-  int e = st.st_off[sid] + sub;
-  for (; e + 7 * S < e1; e += 8 * S) {
+  for (int e = st.st_off[sid] + sub; e < e1; e += 8 * S) {
     double a[8], xv[8];
     bool use[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const StEntry en = st.ent[e + q * S];
-      int dx, dy, dz;
-      decode(en.code, dx, dy, dz);
-      const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
-      use[q] = !SKIP || !((tx >> 1) == bx && (ty >> 1) == by && (tz >> 1) == bz);
-      a[q] = en.a;
-      xv[q] = x[tx + st.nx * (ty + st.ny * tz)];
+      const int eq = e + q * S;
+      use[q] = eq < e1;
+      a[q] = 0.0;
+      xv[q] = 0.0;
+      if (use[q]) {
+        const StEntry en = st.ent[eq];
+        int dx, dy, dz;
+        decode(en.code, dx, dy, dz);
+        const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
+        if (SKIP && (tx >> 1) == bx && (ty >> 1) == by && (tz >> 1) == bz) use[q] = false;
+        a[q] = en.a;
+        xv[q] = x[tx + st.nx * (ty + st.ny * tz)];
+      }
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q)
       if (use[q]) r = fma(-a[q], xv[q], r);
-  }
-  for (; e < e1; e += S) {
-    const StEntry en = st.ent[e];
-    int dx, dy, dz;
-    decode(en.code, dx, dy, dz);
-    const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
-    if (SKIP && (tx >> 1) == bx && (ty >> 1) == by && (tz >> 1) == bz) continue;
-    r = fma(-en.a, x[tx + st.nx * (ty + st.ny * tz)], r);
   }
   return r;
 }
@@ -412,10 +423,21 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(double* __restrict__ x,
   const int cx = 2 * bx + (k & 1), cy = 2 * by + ((k >> 1) & 1), cz = 2 * bz + (k >> 2);
   const uint32_t blk = bx + nbx * (by + nby * bz);
   const int typ = st.btype[blk];
-  const int sid = st.bt_sid[typ * 8 + k];
   const uint32_t cell = cx + st.nx * (cy + st.ny * cz);
   double r = (b && sub == 0) ? b[cell] : 0.0;
-  r = row_reduce<S>(stencil_partial<S, true>(st, x, sid, sub, cx, cy, cz, bx, by, bz, r));
+  const double c7 = S == 1 ? st.bt_c7[typ] : 0.0;
+  if (c7 != 0.0) {
+    // plain 7-point rows: the three face neighbours away from the block, one coefficient
+    const int tx = wrapm(cx + ((k & 1) ? 1 : -1), st.nx);
+    const int ty = wrapm(cy + ((k & 2) ? 1 : -1), st.ny);
+    const int tz = cz + ((k & 4) ? 1 : -1);
+    double sum = x[tx + st.nx * (cy + st.ny * cz)] + x[cx + st.nx * (ty + st.ny * cz)];
+    if (tz >= 0 && tz < st.nz) sum += x[cx + st.nx * (cy + st.ny * tz)];
+    r = fma(-c7, sum, r);
+  } else {
+    const int sid = st.bt_sid[typ * 8 + k];
+    r = row_reduce<S>(stencil_partial<S, true>(st, x, sid, sub, cx, cy, cz, bx, by, bz, r));
+  }
   const double* F = st.bt_fac + (size_t)typ * 128;
   double v = 0.0;
 #pragma unroll
@@ -445,13 +467,74 @@ __global__ __launch_bounds__(TPB) void k_gresidual(double* __restrict__ r,
   const int cy = row % st.ny, cz = row / st.ny;
   const uint32_t blk = (cx >> 1) + (st.nx >> 1) * ((cy >> 1) + (st.ny >> 1) * (cz >> 1));
   const int k = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
-  const int sid = st.bt_sid[st.btype[blk] * 8 + k];
+  const int typ = st.btype[blk];
   double v = (b && sub == 0) ? b[c] : 0.0;
-  v = row_reduce<S>(stencil_partial<S, false>(st, x, sid, sub, cx, cy, cz, 0, 0, 0, v));
+  const double c7 = S == 1 ? st.bt_c7[typ] : 0.0;
+  if (c7 != 0.0) {
+    const int xm = wrapm(cx - 1, st.nx), xp = wrapm(cx + 1, st.nx);
+    const int ym = wrapm(cy - 1, st.ny), yp = wrapm(cy + 1, st.ny);
+    const size_t rowo = (size_t)st.nx * (cy + st.ny * cz);
+    double sum = x[xm + rowo] + x[xp + rowo] + x[cx + st.nx * (ym + st.ny * cz)] +
+                 x[cx + st.nx * (yp + st.ny * cz)];
+    if (cz > 0) sum += x[c - (size_t)st.nx * st.ny];
+    if (cz + 1 < st.nz) sum += x[c + (size_t)st.nx * st.ny];
+    v = fma(-st.bt_diag[typ * 8 + k], x[c], fma(-c7, sum, v));
+  } else {
+    const int sid = st.bt_sid[typ * 8 + k];
+    v = row_reduce<S>(stencil_partial<S, false>(st, x, sid, sub, cx, cy, cz, 0, 0, 0, v));
+  }
   if (sub == 0) r[c] = v;
 }
 
+// Coarsest base level: z = the n normals of the level's stream (call j/2, first or second of the
+// pair), then x = A_c^-1 b (+ sqrt(kT) L_c^-T z) with one wave per row (A_c^-1 symmetric and
+// L_c^-T stored row-major, so every lane reads along a row).
+__global__ __launch_bounds__(TPB) void k_dense_noise(double* __restrict__ z, int n, NoiseArgs na) {
+  const int q = blockIdx.x * TPB + threadIdx.x;
+  if (2 * q >= n) return;
+  double z0, z1;
+  normal_pair(na, na.sid, 0u, (uint32_t)q, z0, z1);
+  z[2 * q] = z0;
+  if (2 * q + 1 < n) z[2 * q + 1] = z1;
+}
+
+template <bool NOISE>
+__global__ __launch_bounds__(TPB) void k_dense_draw(double* __restrict__ x,
+                                                    const double* __restrict__ b,
+                                                    const double* __restrict__ ainv,
+                                                    const double* __restrict__ wt,
+                                                    const double* __restrict__ z, int n,
+                                                    double sqkT) {
+  const int row = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* a = ainv + (size_t)row * n;
+  double acc = 0.0, an = 0.0;
+  for (int j = lane; j < n; j += 64) acc = fma(a[j], b[j], acc);
+  if (NOISE) {
+    const double* w = wt + (size_t)row * n;
+    for (int j = row + lane; j < n; j += 64) an = fma(w[j], z[j], an);
+    acc = fma(sqkT, an, acc);
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  if (lane == 0) x[row] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_dense_draw(double* x, const double* b, const double* ainv, const double* wt,
+                             double* z, int n, bool noise, const NoiseArgs& na, hipStream_t s) {
+  if (noise) {
+    k_dense_noise<<<grid_for((n + 1) / 2), TPB, 0, s>>>(z, n, na);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_dense_draw<true><<<(n + 3) / 4, TPB, 0, s>>>(x, b, ainv, wt, z, n, na.sqkT);
+  } else {
+    k_dense_draw<false><<<(n + 3) / 4, TPB, 0, s>>>(x, b, ainv, wt, z, n, na.sqkT);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_comp_coarse_pass(double* xc, const double* bc, const double* xf,
                                    const CompGeom& g, int colour, bool noise, const NoiseArgs& na,
@@ -492,7 +575,19 @@ hipError_t launch_comp_residual(double* rc, double* rf, const double* xc, const 
 
 hipError_t launch_comp_restrict(double* b0, double* x0, const double* rc, const double* rf,
                                 const CompGeom& g, hipStream_t s) {
-  k_comp_restrict<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(b0, x0, rc, rf, g);
+  k_comp_restrict<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(b0, x0, rc, rf, nullptr,
+                                                                         nullptr, nullptr, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_comp_residual_restrict(double* b0, double* x0, double* rf, const double* xc,
+                                         const double* xf, const double* bc, const double* bf,
+                                         const CompGeom& g, hipStream_t s) {
+  k_comp_res_fine<<<grid_for((int64_t)g.fx * g.fy * g.fz), TPB, 0, s>>>(rf, xf, xc, bf, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_comp_restrict<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(b0, x0, nullptr, rf, xc,
+                                                                         xf, bc, g);
   return hipGetLastError();
 }
 
