@@ -299,6 +299,8 @@ typedef struct {
   int32_t mu1, mu2;     /* pre/post sweeps of the base V-cycle (Alg. 3) */
   int32_t levels;       /* base levels (0 = automatic by coarsest_max) */
   int32_t coarsest_max; /* automatic-depth threshold, 1..4096 */
+  int32_t gs_only;      /* 1: composite sweeps only -- the stochastic Gauss-Seidel sampler on the
+                           composite mesh, without the coarse correction (for comparisons) */
 } smg_fac_params;
 
 typedef struct {

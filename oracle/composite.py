@@ -376,8 +376,13 @@ class _KindMap:
 class FACSampler:
     """Stochastic FAC cycle and deterministic FAC solve on a CompositeGrid."""
 
-    def __init__(self, grid, kT=1.0, nu=2, mu1=2, mu2=2, levels=0, coarsest_max=512):
+    def __init__(self, grid, kT=1.0, nu=2, mu1=2, mu2=2, levels=0, coarsest_max=512,
+                 gs_only=False):
+        """gs_only: the cycle is the nu composite sweeps alone (stochastic Gauss-Seidel on the
+        composite mesh, Sec. "Stochastic Iterative Methods"), for the comparison of the two
+        samplers."""
         self.g = grid
+        self.gs_only = bool(gs_only)
         self.kT = float(kT)
         self.nu = int(nu)
         self.A = grid.A
@@ -445,10 +450,11 @@ class FACSampler:
         """One FAC cycle (returns the new iterate; x is not modified)."""
         x = np.array(x, dtype=np.float64, copy=True)
         b = np.asarray(b, dtype=np.float64)
-        b0 = self.P.T @ (b - self.A @ x)
-        nz = None if noise is None else _KindMap(noise)
-        y = self.base.vcycle(np.zeros(b0.size), b0, nz, cycle, comp, 0)
-        x += self.P @ y
+        if not self.gs_only:
+            b0 = self.P.T @ (b - self.A @ x)
+            nz = None if noise is None else _KindMap(noise)
+            y = self.base.vcycle(np.zeros(b0.size), b0, nz, cycle, comp, 0)
+            x += self.P @ y
         for s in range(self.nu):
             self.sweep(x, b, s, noise, cycle, comp)
         return x

@@ -96,6 +96,7 @@ struct Composite {
   CompGeom g{};
   double h = 1.0, kT = 1.0;
   int nu = 2, mu1 = 2, mu2 = 2;
+  bool gs_only = false;
   std::vector<GLevel> lv;
   int ncd = 0;
   std::vector<double> ainv, w;  // A_c^-1 and L_c^-T (row-major)
@@ -633,6 +634,7 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
   C.nu = p.nu;
   C.mu1 = p.mu1;
   C.mu2 = p.mu2;
+  C.gs_only = p.gs_only != 0;
   // base level plan (block smoothing needs nx, ny multiples of 4 and nz even)
   std::vector<std::array<int, 3>> dims{{g.nx, g.ny, g.nz}};
   for (;;) {
@@ -855,13 +857,16 @@ int base_vcycle(const CRun& r, int l) {
   return SMG_OK;
 }
 
-// One FAC cycle in place: b_0 = P^T (b - A x); y = V-cycle_0(0, b_0); x += P y; nu sweeps.
+// One FAC cycle in place: b_0 = P^T (b - A x); y = V-cycle_0(0, b_0); x += P y; nu sweeps
+// (gs_only: the nu sweeps alone).
 int fac_cycle(const CRun& r, double* xc, double* xf, const double* bc, const double* bf) {
   Composite& C = *r.c;
   GLevel& L0 = C.lv[0];
-  CMP_HIP(launch_comp_residual_restrict(L0.b, L0.x, C.rf, xc, xf, bc, bf, C.g, r.s));
-  if (int rc = base_vcycle(r, 0)) return rc;
-  CMP_HIP(launch_comp_prolong(xc, xf, L0.x, C.g, r.s));
+  if (!C.gs_only) {
+    CMP_HIP(launch_comp_residual_restrict(L0.b, L0.x, C.rf, xc, xf, bc, bf, C.g, r.s));
+    if (int rc = base_vcycle(r, 0)) return rc;
+    CMP_HIP(launch_comp_prolong(xc, xf, L0.x, C.g, r.s));
+  }
   for (int s = 0; s < C.nu; ++s)
     for (int cls = 0; cls < 12; ++cls)
       if (int rc = comp_class_pass(r, cls, s, xc, xf, bc, bf)) return rc;

@@ -103,6 +103,67 @@ def study(sizes=((16, 16, 16), (32, 32, 32), (64, 64, 64)), nchains=8, n_mg=2000
     return rows
 
 
+def composite_weights(S):
+    """Observable of the composite-grid study: the volume-weighted lowest wall mode
+    sin(pi z / (nz h)) over the composite unknowns (a smooth field, slowest to relax under
+    Gauss-Seidel), as (coarse weights with zeros on covered cells, fine weights)."""
+    nz, ny, nx = S.base_shape
+    fz, fy, fx = S.fine_shape
+    x0, x1, y0, y1, z0, z1 = S.box
+    zc = np.sin(np.pi * (np.arange(nz) + 0.5) / nz)
+    wc = np.broadcast_to(zc[:, None, None], (nz, ny, nx)).copy()
+    wc[z0:z1, y0:y1, x0:x1] = 0.0
+    zf = np.sin(np.pi * (z0 + (np.arange(fz) + 0.5) / 2.0) / nz) / 8.0
+    wf = np.broadcast_to(zf[:, None, None], (fz, fy, fx)).copy()
+    return (torch.tensor(wc, device=S.device), torch.tensor(wf, device=S.device))
+
+
+def composite_study(edges=(16, 32, 64), n_mg=4000, gs_cycles_per_tau=100, nu=2, seed=0):
+    """The paper's comparison on an adaptive mesh: base e x e x e/2 with the box
+    [e/4, 3e/4)^2 x [0, e/8) refined by two (the shape of the full adaptive workload), the FAC
+    chain (nu composite sweeps after a V(2,2) base cycle) against the Gauss-Seidel-only chain
+    (the same nu composite sweeps per cycle, no coarse correction).  One row per (grid,
+    sampler): lag-1 correlation and tau_int of the observable, cycles/s and seconds per
+    decorrelated sample."""
+    from .composite import CompositeSampler
+    rows = []
+    for e in edges:
+        base = (e, e, e // 2)
+        box = (e // 4, 3 * e // 4, e // 4, 3 * e // 4, 0, max(1, e // 8))
+        lam = 4.0 * np.sin(np.pi / (2 * base[2])) ** 2
+        tau_guess = max(2.0, 3.0 / lam)
+        for kind in ("mg", "gs"):
+            gs = kind == "gs"
+            n = int(gs_cycles_per_tau * tau_guess) if gs else n_mg
+            burn = int(10 * tau_guess) if gs else 20
+            S = CompositeSampler(*base, box, nu=nu, gs_only=gs)
+            wc, wf = composite_weights(S)
+            xc, xf = S.zeros()
+            S.sample(xc, xf, burn, seed=seed)
+            y = torch.empty(n, dtype=torch.float64, device=S.device)
+            torch.cuda.synchronize(S.device)
+            t0 = time.perf_counter()
+            for t in range(n):
+                S.sample(xc, xf, 1, seed=seed, first_cycle=burn + t)
+                y[t] = (xc * wc).sum() + (xf * wf).sum()
+            torch.cuda.synchronize(S.device)
+            secs = time.perf_counter() - t0
+            obs = y.cpu().numpy().reshape(n, 1, 1)
+            tau = float(tau_int(obs)[0])
+            rho1 = float(autocorrelation(obs, 1)[1][0])
+            rate = n / secs
+            rows.append({"base": list(base), "box": list(box), "unknowns": int(S.info.unknowns),
+                         "sampler": "fac" if not gs else "gauss-seidel", "nu": nu,
+                         "cycles": n, "lag1": round(rho1, 4), "tau_int": round(tau, 2),
+                         "cycles_per_s": round(rate, 1),
+                         "seconds_per_decorrelated_sample": float("%.4g" % (max(tau, 1.0) /
+                                                                            rate))})
+            print(json.dumps(rows[-1]), flush=True)
+            del S
+            torch.cuda.empty_cache()
+    return rows
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="multigrid vs Gauss-Seidel decorrelation study")
@@ -110,8 +171,14 @@ def main(argv=None):
     ap.add_argument("--chains", type=int, default=8)
     ap.add_argument("--mg-cycles", type=int, default=2000)
     ap.add_argument("--gs-cycles-per-tau", type=int, default=200)
+    ap.add_argument("--composite", action="store_true",
+                    help="run the comparison on adaptive composite grids (base e x e x e/2)")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
+    if args.composite:
+        composite_study(tuple(int(e) for e in args.sizes.split(",")), n_mg=args.mg_cycles,
+                        gs_cycles_per_tau=args.gs_cycles_per_tau)
+        return
     sizes = [(int(e), int(e), int(e)) for e in args.sizes.split(",")]
     study(sizes, nchains=args.chains, n_mg=args.mg_cycles,
           gs_cycles_per_tau=args.gs_cycles_per_tau, device=torch.device("cuda", 0))

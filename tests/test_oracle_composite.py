@@ -165,3 +165,17 @@ def test_row_of_matches_assembly():
         for (kind, q), v in row.items():
             dense[g.coarse_id[q] if kind == "c" else g.nc + q] += v
         assert np.abs(dense - A[r]).max() < 1e-13 * np.abs(A[r]).max()
+
+
+def test_gauss_seidel_only_composite_chain_is_exact_but_slow():
+    """The composite sweeps alone (no coarse correction) also leave kT A^-1 invariant (every
+    class pass is an exact conditional draw), but contract far more slowly than the FAC
+    cycle: spectral radius 0.78 against 0.105 on this grid."""
+    g = CompositeGrid(8, 8, 4, (2, 6, 2, 6, 0, 2))
+    gs = FACSampler(g, kT=0.7, coarsest_max=64, gs_only=True)
+    T, G = gs.affine_map()
+    C = stationary_covariance(T, G @ G.T)
+    target = 0.7 * np.linalg.inv(g.A.toarray())
+    assert np.abs(C - target).max() < 1e-11 * np.abs(target).max()
+    rho_gs = max(abs(np.linalg.eigvals(T)))
+    assert 0.7 < rho_gs < 0.85
