@@ -401,7 +401,37 @@ def measure_composite(dev, cycles=20, with_cpu=True):
                      "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": nbytes},
     }
-    del S, xc, xf, rc, rf, fc, ff, x0, b0
+    del S, xc, xf, rc, rf, x0, b0
+    torch.cuda.empty_cache()
+    # FP32-refined form of the same cycle (FP32 sweeps and transfers, FP64 residual, update and
+    # coarsest draw), same noise streams; its error against the FP64 form after two cycles
+    S64 = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0, nu=COMP_NU, mu1=COMP_MU1, mu2=COMP_MU2)
+    a, af = S64.zeros()
+    S64.sample(a, af, 2, seed=0)
+    del S64
+    S32 = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0, nu=COMP_NU, mu1=COMP_MU1, mu2=COMP_MU2,
+                           precision="fp32_refined")
+    b_, bf_ = S32.zeros()
+    S32.sample(b_, bf_, 2, seed=0)
+    num = ((a - b_).square().sum() + (af - bf_).square().sum()).item()
+    den = (a.square().sum() + af.square().sum()).item()
+    del a, af
+    S32.sample(b_, bf_, 3, seed=0, first_cycle=2)
+    torch.cuda.synchronize()
+    e0.record()
+    S32.sample(b_, bf_, cycles, seed=0, first_cycle=5)
+    e1.record()
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1) / cycles
+    _, _, si32 = S32.solve(fc, ff, rtol=1e-10, max_cycles=60)
+    rho32 = max(float(si32.last_ratio), 1e-3)
+    k32 = max(1, math.ceil(math.log(0.01) / math.log(rho32)))
+    out["fp32_refined"] = {"ms_per_cycle": round(ms32, 3), "cycles_per_s": round(1e3 / ms32, 2),
+                           "rho_solve": round(rho32, 4), "k_dec": k32,
+                           "decorrelated_samples_per_s": round(1e3 / ms32 / k32, 3),
+                           "solve_cycles": int(si32.cycles),
+                           "rel_rms_vs_fp64_2_cycles": float("%.3e" % math.sqrt(num / den))}
+    del S32, b_, bf_, fc, ff
     torch.cuda.empty_cache()
     if with_cpu:
         out["cpu_baseline"] = composite_cpu_baseline()

@@ -301,6 +301,9 @@ typedef struct {
   int32_t coarsest_max; /* automatic-depth threshold, 1..4096 */
   int32_t gs_only;      /* 1: composite sweeps only -- the stochastic Gauss-Seidel sampler on the
                            composite mesh, without the coarse correction (for comparisons) */
+  int32_t precision;    /* SMG_FP64, or SMG_FP32_REFINED: FP32 sweeps and transfers of the cycle in
+                           the correction form, with the residual b - A x, the update of x and the
+                           coarsest draw in FP64 (Alg. 1); the component entry points need FP64 */
 } smg_fac_params;
 
 typedef struct {

@@ -16,12 +16,16 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+PRECISIONS = {"fp64": abi.SMG_FP64, "fp32_refined": abi.SMG_FP32_REFINED}
+
+
 def plan(nx, ny, nz, box, h=1.0, kT=1.0, nu=2, mu1=2, mu2=2, levels=0, coarsest_max=512,
-         gs_only=False):
+         gs_only=False, precision="fp64"):
     """Host-only plan: (handle, info).  The caller destroys the handle (destroy_plan)."""
     lib = abi.load()
     desc = abi.CompositeDesc(nx, ny, nz, (ctypes.c_int32 * 6)(*box), h, kT)
-    prm = abi.FACParams(nu, mu1, mu2, levels, coarsest_max, int(bool(gs_only)))
+    prm = abi.FACParams(nu, mu1, mu2, levels, coarsest_max, int(bool(gs_only)),
+                        PRECISIONS[precision])
     hd = ctypes.c_void_p()
     abi.check(lib.smg_composite_create(ctypes.byref(desc), ctypes.byref(prm), ctypes.byref(hd)))
     info = abi.CompositeInfo()
@@ -47,7 +51,7 @@ class CompositeSampler:
     """A planned composite hierarchy bound to a device workspace."""
 
     def __init__(self, nx, ny, nz, box, h=1.0, kT=1.0, nu=2, mu1=2, mu2=2, levels=0,
-                 coarsest_max=512, gs_only=False, device=None):
+                 coarsest_max=512, gs_only=False, precision="fp64", device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no ROCm device: the composite FAC library runs only on the GPU")
@@ -58,7 +62,8 @@ class CompositeSampler:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         self._h, self.info = plan(nx, ny, nz, box, h, kT, nu, mu1, mu2, levels, coarsest_max,
-                                  gs_only)
+                                  gs_only, precision)
+        self.precision = precision
         self.base_shape = (nz, ny, nx)
         fd = self.info.fine_dims
         self.fine_shape = (fd[2], fd[1], fd[0])

@@ -73,15 +73,20 @@ struct GLevel {
   std::unordered_map<std::string, int32_t> dedup;
   std::vector<int32_t> btype, bt_sid;
   std::vector<double> bt_fac;
-  std::vector<StEntry> ent;  // device form of (st_code, st_val)
   std::vector<double> bt_c7, bt_diag;
   int split = 1;
-  size_t off_x = 0, off_b = 0, off_r = 0, off_btype = 0, off_btsid = 0, off_btfac = 0,
-         off_stoff = 0, off_ent = 0, off_btc7 = 0, off_btdiag = 0;
+  // device copies: fields x, b, r and the coefficient tables in the sweep precision (double, or
+  // float in the FP32-refined form); the integer tables are shared
+  size_t off_x = 0, off_b = 0, off_r = 0, off_btype = 0, off_btsid = 0, off_stoff = 0,
+         off_btfac = 0, off_ent = 0, off_btc7 = 0, off_btdiag = 0;
   double* x = nullptr;
   double* b = nullptr;
   double* r = nullptr;
-  GStencil dev{};
+  float* x32 = nullptr;
+  float* b32 = nullptr;
+  float* r32 = nullptr;
+  GStencilT<double> dev{};
+  GStencilT<float> dev32{};
 };
 
 // A row as a dense 5x5x5 accumulator over canonical offsets (exact zeros dropped on encoding).
@@ -97,13 +102,15 @@ struct Composite {
   double h = 1.0, kT = 1.0;
   int nu = 2, mu1 = 2, mu2 = 2;
   bool gs_only = false;
+  int prec = SMG_FP64;
   std::vector<GLevel> lv;
   int ncd = 0;
   std::vector<double> ainv, w;  // A_c^-1 and L_c^-T (row-major)
   std::vector<int32_t> layer;  // layer cells grouped by parity class
   int layer_off[9] = {0};
   size_t ws_bytes = 0, off_rc = 0, off_rf = 0, off_layer = 0, off_ainv = 0, off_w = 0,
-         off_part = 0, off_norm = 0, off_znoise = 0;
+         off_part = 0, off_norm = 0, off_znoise = 0, off_e32c = 0, off_e32f = 0, off_r32c = 0,
+         off_r32f = 0, off_rf32 = 0;
   char* ws = nullptr;
   int device = -1;
   double* rc = nullptr;
@@ -114,6 +121,13 @@ struct Composite {
   double* norm = nullptr;
   double* znoise = nullptr;
   int32_t* layer_d = nullptr;
+  // FP32-refined form: the correction e and the FP32 right-hand side of the inner cycle
+  // (coarse part on the base grid, fine part on the box) and the inner fine residual
+  float* e32c = nullptr;
+  float* e32f = nullptr;
+  float* r32c = nullptr;
+  float* r32f = nullptr;
+  float* rf32 = nullptr;
 };
 
 }  // namespace smg
@@ -635,6 +649,11 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
   C.mu1 = p.mu1;
   C.mu2 = p.mu2;
   C.gs_only = p.gs_only != 0;
+  if (p.precision != SMG_FP64 && p.precision != SMG_FP32_REFINED) {
+    err = "precision must be SMG_FP64 or SMG_FP32_REFINED";
+    return SMG_EINVAL;
+  }
+  C.prec = p.precision;
   // base level plan (block smoothing needs nx, ny multiples of 4 and nz even)
   std::vector<std::array<int, 3>> dims{{g.nx, g.ny, g.nz}};
   for (;;) {
@@ -758,27 +777,35 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
   };
   const int64_t nbase = (int64_t)g.nx * g.ny * g.nz;
   const int64_t nf = (int64_t)g.fx * g.fy * g.fz;
+  const bool f32 = C.prec == SMG_FP32_REFINED;
+  const size_t es = f32 ? 4 : 8;  // bytes of a value of the sweep precision
   C.off_rc = take(nbase * 8);
   C.off_rf = take(nf * 8);
   C.off_layer = take(std::max<size_t>(1, C.layer.size()) * 4);
+  if (f32) {
+    C.off_e32c = take(nbase * 4);
+    C.off_e32f = take(nf * 4);
+    C.off_r32c = take(nbase * 4);
+    C.off_r32f = take(nf * 4);
+    C.off_rf32 = take(nf * 4);
+  }
   for (auto& L : C.lv) {
-    L.off_x = take(L.n * 8);
-    L.off_b = take(L.n * 8);
-    L.off_r = take(L.n * 8);
+    L.off_x = take(L.n * es);
+    L.off_b = take(L.n * es);
+    L.off_r = take(L.n * es);
     if (L.coarsest) continue;
     L.off_btype = take(L.btype.size() * 4);
     L.off_btsid = take(L.bt_sid.size() * 4);
-    L.off_btfac = take(L.bt_fac.size() * 8);
-    L.ent.resize(L.st_code.size());
-    for (size_t e = 0; e < L.st_code.size(); ++e) L.ent[e] = StEntry{L.st_val[e], L.st_code[e], 0};
+    L.off_btfac = take(L.bt_fac.size() * es);
     // rows longer than 16 entries on average over the cells: eight lanes per row
     double tot = 0.0;
     for (int64_t c = 0; c < L.n; ++c) tot += L.st_off[L.sid[c] + 1] - L.st_off[L.sid[c]];
     L.split = tot > 16.0 * (double)L.n ? 8 : 1;
-    L.off_btc7 = take(L.bt_c7.size() * 8);
-    L.off_btdiag = take(L.bt_diag.size() * 8);
+    L.off_btc7 = take(L.bt_c7.size() * es);
+    L.off_btdiag = take(L.bt_diag.size() * es);
     L.off_stoff = take(L.st_off.size() * 4);
-    L.off_ent = take(std::max<size_t>(1, L.ent.size()) * sizeof(StEntry));
+    L.off_ent = take(std::max<size_t>(1, L.st_code.size()) *
+                     (f32 ? sizeof(StEntryT<float>) : sizeof(StEntryT<double>)));
   }
   C.off_ainv = take((size_t)C.ncd * C.ncd * 8);
   C.off_w = take((size_t)C.ncd * C.ncd * 8);
@@ -811,65 +838,108 @@ struct CRun {
   uint64_t seed, cycle;
 };
 
-int comp_class_pass(const CRun& r, int cls, int slot, double* xc, double* xf, const double* bc,
-                    const double* bf) {
+// fields and tables of a base level in the sweep precision
+template <typename T>
+struct LvF;
+template <>
+struct LvF<double> {
+  static double* x(GLevel& L) { return L.x; }
+  static double* b(GLevel& L) { return L.b; }
+  static double* r(GLevel& L) { return L.r; }
+  static const GStencilT<double>& st(GLevel& L) { return L.dev; }
+};
+template <>
+struct LvF<float> {
+  static float* x(GLevel& L) { return L.x32; }
+  static float* b(GLevel& L) { return L.b32; }
+  static float* r(GLevel& L) { return L.r32; }
+  static const GStencilT<float>& st(GLevel& L) { return L.dev32; }
+};
+
+template <typename T>
+int comp_class_pass(const CRun& r, int cls, int slot, T* xc, T* xf, const T* bc, const T* bf) {
   Composite& C = *r.c;
   const NoiseArgs na = comp_noise(C, r.seed, r.cycle, 0, slot, cls, KIND_COMP);
   if (cls < 2) {
-    CMP_HIP(launch_comp_coarse_pass(xc, bc, xf, C.g, cls, r.noise, na, r.s));
+    CMP_HIP(launch_comp_coarse_pass<T>(xc, bc, xf, C.g, cls, r.noise, na, r.s));
   } else if (cls < 4) {
-    CMP_HIP(launch_comp_fine_pass(xf, bf, C.g, cls - 2, r.noise, na, r.s));
+    CMP_HIP(launch_comp_fine_pass<T>(xf, bf, C.g, cls - 2, r.noise, na, r.s));
   } else {
     const int p = cls - 4;
-    CMP_HIP(launch_comp_layer_pass(xf, bf, xc, C.g, C.layer_d + C.layer_off[p],
-                                   C.layer_off[p + 1] - C.layer_off[p], r.noise, na, r.s));
+    CMP_HIP(launch_comp_layer_pass<T>(xf, bf, xc, C.g, C.layer_d + C.layer_off[p],
+                                      C.layer_off[p + 1] - C.layer_off[p], r.noise, na, r.s));
   }
   return SMG_OK;
 }
 
+template <typename T>
 int base_block_pass(const CRun& r, int l, int colour, int slot) {
   Composite& C = *r.c;
   GLevel& L = C.lv[l];
   const NoiseArgs na = comp_noise(C, r.seed, r.cycle, l, slot, colour, KIND_FAC_BASE);
-  CMP_HIP(launch_gblock_pass(L.x, L.b, L.dev, colour, r.noise, na, r.s));
+  CMP_HIP(launch_gblock_pass<T>(LvF<T>::x(L), LvF<T>::b(L), LvF<T>::st(L), colour, r.noise, na,
+                                r.s));
   return SMG_OK;
 }
 
+template <typename T>
 int base_vcycle(const CRun& r, int l) {
   Composite& C = *r.c;
   GLevel& L = C.lv[l];
   if (L.coarsest) {
     const NoiseArgs na = comp_noise(C, r.seed, r.cycle, l, 0, 0, KIND_FAC_COARSEST);
-    CMP_HIP(launch_dense_draw(L.x, L.b, C.ainv_d, C.w_d, C.znoise, C.ncd, r.noise, na, r.s));
+    CMP_HIP(launch_dense_draw<T>(LvF<T>::x(L), LvF<T>::b(L), C.ainv_d, C.w_d, C.znoise, C.ncd,
+                                 r.noise, na, r.s));
     return SMG_OK;
   }
   for (int s = 0; s < C.mu1; ++s)
     for (int c = 0; c < 8; ++c)
-      if (int rc = base_block_pass(r, l, c, s)) return rc;
+      if (int rc = base_block_pass<T>(r, l, c, s)) return rc;
   GLevel& K = C.lv[l + 1];
-  CMP_HIP(launch_gresidual(L.r, L.x, L.b, L.dev, r.s));
-  CMP_HIP(launch_restrict<double>(K.b, K.x, L.r, L.nx, L.ny, L.nz, 1, r.s));
-  if (int rc = base_vcycle(r, l + 1)) return rc;
-  CMP_HIP(launch_prolong<double>(L.x, K.x, L.nx, L.ny, L.nz, 1, r.s));
+  CMP_HIP(launch_gresidual<T>(LvF<T>::r(L), LvF<T>::x(L), LvF<T>::b(L), LvF<T>::st(L), r.s));
+  CMP_HIP(launch_restrict<T>(LvF<T>::b(K), LvF<T>::x(K), LvF<T>::r(L), L.nx, L.ny, L.nz, 1, r.s));
+  if (int rc = base_vcycle<T>(r, l + 1)) return rc;
+  CMP_HIP(launch_prolong<T>(LvF<T>::x(L), LvF<T>::x(K), L.nx, L.ny, L.nz, 1, r.s));
   for (int s = 0; s < C.mu2; ++s)
     for (int c = 7; c >= 0; --c)
-      if (int rc = base_block_pass(r, l, c, C.mu1 + s)) return rc;
+      if (int rc = base_block_pass<T>(r, l, c, C.mu1 + s)) return rc;
   return SMG_OK;
 }
 
-// One FAC cycle in place: b_0 = P^T (b - A x); y = V-cycle_0(0, b_0); x += P y; nu sweeps
-// (gs_only: the nu sweeps alone).
-int fac_cycle(const CRun& r, double* xc, double* xf, const double* bc, const double* bf) {
+// One FAC cycle in place in the sweep precision: b_0 = P^T (b - A x); y = V-cycle_0(0, b_0);
+// x += P y; nu composite sweeps (gs_only: the sweeps alone).  rf: fine-residual scratch.
+template <typename T>
+int fac_cycle(const CRun& r, T* xc, T* xf, const T* bc, const T* bf, T* rf) {
   Composite& C = *r.c;
   GLevel& L0 = C.lv[0];
   if (!C.gs_only) {
-    CMP_HIP(launch_comp_residual_restrict(L0.b, L0.x, C.rf, xc, xf, bc, bf, C.g, r.s));
-    if (int rc = base_vcycle(r, 0)) return rc;
-    CMP_HIP(launch_comp_prolong(xc, xf, L0.x, C.g, r.s));
+    CMP_HIP(launch_comp_residual_restrict<T>(LvF<T>::b(L0), LvF<T>::x(L0), rf, xc, xf, bc, bf,
+                                             C.g, r.s));
+    if (int rc = base_vcycle<T>(r, 0)) return rc;
+    CMP_HIP(launch_comp_prolong<T>(xc, xf, LvF<T>::x(L0), C.g, r.s));
   }
   for (int s = 0; s < C.nu; ++s)
     for (int cls = 0; cls < 12; ++cls)
-      if (int rc = comp_class_pass(r, cls, s, xc, xf, bc, bf)) return rc;
+      if (int rc = comp_class_pass<T>(r, cls, s, xc, xf, bc, bf)) return rc;
+  return SMG_OK;
+}
+
+// The cycle on the caller's FP64 fields.  FP64 form: the cycle itself.  FP32-refined form (the
+// correction form of the same affine cycle): r = b - A x in FP64, e = cycle_FP32(0, (float) r)
+// with the same noise streams, x += e in FP64.
+int run_cycle(const CRun& r, double* xc, double* xf, const double* bc, const double* bf) {
+  Composite& C = *r.c;
+  if (C.prec == SMG_FP64) return fac_cycle<double>(r, xc, xf, bc, bf, C.rf);
+  const int64_t nbase = (int64_t)C.g.nx * C.g.ny * C.g.nz;
+  const int64_t nf = (int64_t)C.g.fx * C.g.fy * C.g.fz;
+  CMP_HIP(launch_comp_residual<double>(C.rc, C.rf, xc, xf, bc, bf, C.g, r.s));
+  CMP_HIP(launch_cast(C.r32c, 1, C.rc, nbase, r.s));
+  CMP_HIP(launch_cast(C.r32f, 1, C.rf, nf, r.s));
+  CMP_HIP(launch_zero<float>(C.e32c, nbase, r.s));
+  CMP_HIP(launch_zero<float>(C.e32f, nf, r.s));
+  if (int rc = fac_cycle<float>(r, C.e32c, C.e32f, C.r32c, C.r32f, C.rf32)) return rc;
+  CMP_HIP(launch_refine_update(xc, C.e32c, nbase, r.s));
+  CMP_HIP(launch_refine_update(xf, C.e32f, nf, r.s));
   return SMG_OK;
 }
 
@@ -975,23 +1045,69 @@ int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stre
     return hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s);
   };
   CMP_HIP(up(C.off_layer, C.layer.data(), C.layer.size() * 4));
+  const bool f32 = C.prec == SMG_FP32_REFINED;
+  // host staging of converted tables, alive until the synchronisation below
+  std::vector<std::vector<float>> keep32;
+  std::vector<std::vector<smg::StEntryT<float>>> keepe32;
+  std::vector<std::vector<smg::StEntryT<double>>> keepe64;
+  keep32.reserve(4 * C.lv.size());
+  keepe32.reserve(C.lv.size());
+  keepe64.reserve(C.lv.size());
+  auto as32 = [&](const std::vector<double>& v) -> const float* {
+    keep32.emplace_back(v.begin(), v.end());
+    return keep32.back().data();
+  };
   for (auto& L : C.lv) {
-    L.x = (double*)(ws + L.off_x);
-    L.b = (double*)(ws + L.off_b);
-    L.r = (double*)(ws + L.off_r);
+    if (f32) {
+      L.x32 = (float*)(ws + L.off_x);
+      L.b32 = (float*)(ws + L.off_b);
+      L.r32 = (float*)(ws + L.off_r);
+    } else {
+      L.x = (double*)(ws + L.off_x);
+      L.b = (double*)(ws + L.off_b);
+      L.r = (double*)(ws + L.off_r);
+    }
     if (L.coarsest) continue;
     CMP_HIP(up(L.off_btype, L.btype.data(), L.btype.size() * 4));
     CMP_HIP(up(L.off_btsid, L.bt_sid.data(), L.bt_sid.size() * 4));
+    if (f32) {
+      CMP_HIP(up(L.off_stoff, L.st_off.data(), L.st_off.size() * 4));
+      CMP_HIP(up(L.off_btfac, as32(L.bt_fac), L.bt_fac.size() * 4));
+      CMP_HIP(up(L.off_btc7, as32(L.bt_c7), L.bt_c7.size() * 4));
+      CMP_HIP(up(L.off_btdiag, as32(L.bt_diag), L.bt_diag.size() * 4));
+      keepe32.emplace_back(L.st_code.size());
+      for (size_t e = 0; e < L.st_code.size(); ++e)
+        keepe32.back()[e] = smg::StEntryT<float>{(float)L.st_val[e], L.st_code[e]};
+      CMP_HIP(up(L.off_ent, keepe32.back().data(),
+                 L.st_code.size() * sizeof(smg::StEntryT<float>)));
+      smg::GStencilT<float>& d = L.dev32;
+      d.btype = (const int32_t*)(ws + L.off_btype);
+      d.bt_sid = (const int32_t*)(ws + L.off_btsid);
+      d.st_off = (const int32_t*)(ws + L.off_stoff);
+      d.bt_fac = (const float*)(ws + L.off_btfac);
+      d.ent = (const smg::StEntryT<float>*)(ws + L.off_ent);
+      d.bt_c7 = (const float*)(ws + L.off_btc7);
+      d.bt_diag = (const float*)(ws + L.off_btdiag);
+      d.nx = L.nx;
+      d.ny = L.ny;
+      d.nz = L.nz;
+      d.split = L.split;
+      continue;
+    }
     CMP_HIP(up(L.off_btfac, L.bt_fac.data(), L.bt_fac.size() * 8));
+
     CMP_HIP(up(L.off_stoff, L.st_off.data(), L.st_off.size() * 4));
-    CMP_HIP(up(L.off_ent, L.ent.data(), L.ent.size() * sizeof(smg::StEntry)));
+    keepe64.emplace_back(L.st_code.size());
+    for (size_t e = 0; e < L.st_code.size(); ++e)
+      keepe64.back()[e] = smg::StEntryT<double>{L.st_val[e], L.st_code[e]};
+    CMP_HIP(up(L.off_ent, keepe64.back().data(), L.st_code.size() * sizeof(smg::StEntryT<double>)));
     CMP_HIP(up(L.off_btc7, L.bt_c7.data(), L.bt_c7.size() * 8));
     CMP_HIP(up(L.off_btdiag, L.bt_diag.data(), L.bt_diag.size() * 8));
     L.dev.btype = (const int32_t*)(ws + L.off_btype);
     L.dev.bt_sid = (const int32_t*)(ws + L.off_btsid);
     L.dev.bt_fac = (const double*)(ws + L.off_btfac);
     L.dev.st_off = (const int32_t*)(ws + L.off_stoff);
-    L.dev.ent = (const smg::StEntry*)(ws + L.off_ent);
+    L.dev.ent = (const smg::StEntryT<double>*)(ws + L.off_ent);
     L.dev.split = L.split;
     L.dev.bt_c7 = (const double*)(ws + L.off_btc7);
     L.dev.bt_diag = (const double*)(ws + L.off_btdiag);
@@ -1012,6 +1128,13 @@ int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stre
   C.part = (double*)(ws + C.off_part);
   C.norm = (double*)(ws + C.off_norm);
   C.znoise = (double*)(ws + C.off_znoise);
+  if (f32) {
+    C.e32c = (float*)(ws + C.off_e32c);
+    C.e32f = (float*)(ws + C.off_e32f);
+    C.r32c = (float*)(ws + C.off_r32c);
+    C.r32f = (float*)(ws + C.off_r32f);
+    C.rf32 = (float*)(ws + C.off_rf32);
+  }
   return SMG_OK;
 }
 
@@ -1024,7 +1147,7 @@ int smg_composite_cycle(smg_composite* h, void* xc, void* xf, const void* bc, co
     return SMG_EINVAL;
   }
   smg::CRun r{&h->c, (hipStream_t)stream, with_noise != 0, seed, cycle};
-  return smg::fac_cycle(r, (double*)xc, (double*)xf, (const double*)bc, (const double*)bf);
+  return smg::run_cycle(r, (double*)xc, (double*)xf, (const double*)bc, (const double*)bf);
 }
 
 int smg_composite_sample(smg_composite* h, int64_t ncycles, uint64_t seed, uint64_t first_cycle,
@@ -1036,7 +1159,7 @@ int smg_composite_sample(smg_composite* h, int64_t ncycles, uint64_t seed, uint6
   }
   for (int64_t k = 0; k < ncycles; ++k) {
     smg::CRun r{&h->c, (hipStream_t)stream, true, seed, first_cycle + (uint64_t)k};
-    if (int rc = smg::fac_cycle(r, (double*)xc, (double*)xf, nullptr, nullptr)) return rc;
+    if (int rc = smg::run_cycle(r, (double*)xc, (double*)xf, nullptr, nullptr)) return rc;
   }
   return SMG_OK;
 }
@@ -1096,7 +1219,7 @@ int smg_composite_solve(smg_composite* h, const void* fc, const void* ff, void* 
   double rel = 1.0;
   while (k < max_cycles) {
     smg::CRun r{&C, s, false, 0, 0};
-    if (int e = smg::fac_cycle(r, (double*)uc, (double*)uf, (const double*)fc, (const double*)ff))
+    if (int e = smg::run_cycle(r, (double*)uc, (double*)uf, (const double*)fc, (const double*)ff))
       return e;
     ++k;
     if (int e = resnorm(rn)) return e;
@@ -1123,12 +1246,16 @@ int smg_composite_debug_pass(smg_composite* h, int32_t cls, void* xc, void* xf, 
                              const void* bf, uint64_t seed, uint64_t cycle, int32_t slot,
                              int32_t with_noise, void* stream) {
   if (int e = smg::check_bound(h)) return e;
+  if (h->c.prec != SMG_FP64) {
+    set_error("component entry points need a composite created with SMG_FP64");
+    return SMG_EINVAL;
+  }
   if (cls < 0 || cls >= 12 || slot < 0 || slot > 255 || !smg::aligned(xc) || !smg::aligned(xf)) {
     set_error("invalid class, slot or field pointers");
     return SMG_EINVAL;
   }
   smg::CRun r{&h->c, (hipStream_t)stream, with_noise != 0, seed, cycle};
-  return smg::comp_class_pass(r, cls, slot, (double*)xc, (double*)xf, (const double*)bc,
+  return smg::comp_class_pass<double>(r, cls, slot, (double*)xc, (double*)xf, (const double*)bc,
                               (const double*)bf);
 }
 
@@ -1137,6 +1264,10 @@ int smg_composite_debug_base_pass(smg_composite* h, int32_t level, int32_t colou
                                   int32_t with_noise, void* stream) {
   if (int e = smg::check_bound(h)) return e;
   Composite& C = h->c;
+  if (C.prec != SMG_FP64) {
+    set_error("component entry points need a composite created with SMG_FP64");
+    return SMG_EINVAL;
+  }
   if (level < 0 || level >= (int)C.lv.size() || C.lv[level].coarsest || colour < 0 ||
       colour > 7 || slot < 0 || slot > 255 || !smg::aligned(x) || (b && !smg::aligned(b))) {
     set_error("invalid level, colour, slot or field pointers");
@@ -1145,7 +1276,7 @@ int smg_composite_debug_base_pass(smg_composite* h, int32_t level, int32_t colou
   smg::GLevel& L = C.lv[level];
   const smg::NoiseArgs na =
       smg::comp_noise(C, seed, cycle, level, slot, colour, smg::KIND_FAC_BASE);
-  CMP_HIP(smg::launch_gblock_pass((double*)x, (const double*)b, L.dev, colour, with_noise != 0,
+  CMP_HIP(smg::launch_gblock_pass<double>((double*)x, (const double*)b, L.dev, colour, with_noise != 0,
                                   na, (hipStream_t)stream));
   return SMG_OK;
 }

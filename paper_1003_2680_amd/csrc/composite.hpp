@@ -33,22 +33,25 @@ struct CompGeom {
 // Operator of a Galerkin base level as a dictionary of sparse stencils: every 2x2x2 block has a
 // block type, a block type names the stencil of each of its 8 cells (in-block index
 // dx + 2dy + 4dz) and carries the factors of its 8x8 diagonal block; a stencil is a list of
-// (offset code, coefficient), code = (dz+2)*25 + (dy+2)*5 + (dx+2), offsets periodic in x, y.
-struct StEntry {
-  double a;      // coefficient
+// (coefficient, offset code) records, code = (dz+2)*25 + (dy+2)*5 + (dx+2), offsets periodic in
+// x, y.  T: double (FP64 sweeps) or float (the inner cycle of the FP32-refined form).
+template <typename T>
+struct StEntryT {
+  T a;           // coefficient
   int32_t code;  // offset code
-  int32_t pad;
 };
-struct GStencil {
+using StEntry = StEntryT<double>;
+template <typename T>
+struct GStencilT {
   const int32_t* btype;   // [n/8]
   const int32_t* bt_sid;  // [types][8]
-  const double* bt_fac;   // [types][128]: A_BB^-1 then L_BB^-T, row-major
+  const T* bt_fac;        // [types][128]: A_BB^-1 then L_BB^-T, row-major
   const int32_t* st_off;  // [stencils + 1]
-  const StEntry* ent;     // entries of every stencil
+  const StEntryT<T>* ent; // entries of every stencil
   // block types whose 8 rows are plain 7-point (the centre and every in-grid face neighbour,
   // one common off-diagonal coefficient): that coefficient, else 0; and the 8 diagonals
-  const double* bt_c7;    // [types]
-  const double* bt_diag;  // [types][8]
+  const T* bt_c7;         // [types]
+  const T* bt_diag;       // [types][8]
   int nx, ny, nz;
   int split;              // lanes per row in the kernels: 1 or 8 (long rows)
 };
@@ -56,39 +59,45 @@ struct GStencil {
 // Point heat bath of one class of the composite sweep (x_i = (b_i - sum_j A_ij x_j)/A_ii +
 // sqrt(kT/A_ii) n_i), b null = 0.  Classes: coarse cells of parity `colour`; fine cells off the
 // interface layer of parity `colour`; the listed layer cells (one parity class per list).
-hipError_t launch_comp_coarse_pass(double* xc, const double* bc, const double* xf,
-                                   const CompGeom& g, int colour, bool noise, const NoiseArgs& na,
-                                   hipStream_t s);
-hipError_t launch_comp_fine_pass(double* xf, const double* bf, const CompGeom& g, int colour,
-                                 bool noise, const NoiseArgs& na, hipStream_t s);
-hipError_t launch_comp_layer_pass(double* xf, const double* bf, const double* xc,
-                                  const CompGeom& g, const int32_t* cells, int count, bool noise,
-                                  const NoiseArgs& na, hipStream_t s);
+template <typename T>
+hipError_t launch_comp_coarse_pass(T* xc, const T* bc, const T* xf, const CompGeom& g, int colour,
+                                   bool noise, const NoiseArgs& na, hipStream_t s);
+template <typename T>
+hipError_t launch_comp_fine_pass(T* xf, const T* bf, const CompGeom& g, int colour, bool noise,
+                                 const NoiseArgs& na, hipStream_t s);
+template <typename T>
+hipError_t launch_comp_layer_pass(T* xf, const T* bf, const T* xc, const CompGeom& g,
+                                  const int32_t* cells, int count, bool noise, const NoiseArgs& na,
+                                  hipStream_t s);
 // rc = bc - (A x)_coarse on every base cell (covered cells: 0), rf = bf - (A x)_fine
-hipError_t launch_comp_residual(double* rc, double* rf, const double* xc, const double* xf,
-                                const double* bc, const double* bf, const CompGeom& g,
-                                hipStream_t s);
+template <typename T>
+hipError_t launch_comp_residual(T* rc, T* rf, const T* xc, const T* xf, const T* bc, const T* bf,
+                                const CompGeom& g, hipStream_t s);
 // b0 = P^T (rc, rf) over the base grid and x0 = 0 (P: identity on coarse cells, trilinear
 // onto fine cells)
-hipError_t launch_comp_restrict(double* b0, double* x0, const double* rc, const double* rf,
-                                const CompGeom& g, hipStream_t s);
+template <typename T>
+hipError_t launch_comp_restrict(T* b0, T* x0, const T* rc, const T* rf, const CompGeom& g,
+                                hipStream_t s);
 // the two above fused for the cycle: rf = bf - (A x)_fine, then b0 = P^T (b - A x) with the
 // coarse residual formed inside the restriction (never stored), x0 = 0
-hipError_t launch_comp_residual_restrict(double* b0, double* x0, double* rf, const double* xc,
-                                         const double* xf, const double* bc, const double* bf,
-                                         const CompGeom& g, hipStream_t s);
+template <typename T>
+hipError_t launch_comp_residual_restrict(T* b0, T* x0, T* rf, const T* xc, const T* xf,
+                                         const T* bc, const T* bf, const CompGeom& g,
+                                         hipStream_t s);
 // (xc, xf) += P y
-hipError_t launch_comp_prolong(double* xc, double* xf, const double* y, const CompGeom& g,
-                               hipStream_t s);
+template <typename T>
+hipError_t launch_comp_prolong(T* xc, T* xf, const T* y, const CompGeom& g, hipStream_t s);
 // 2x2x2 block heat bath of one block colour on a Galerkin base level (b null = 0)
-hipError_t launch_gblock_pass(double* x, const double* b, const GStencil& st, int colour,
-                              bool noise, const NoiseArgs& na, hipStream_t s);
-// coarsest base level: x = A_c^-1 b (+ sqrt(kT) L_c^-T z), z (n doubles of scratch) filled with
-// the level's normals; wt = L_c^-T row-major
-hipError_t launch_dense_draw(double* x, const double* b, const double* ainv, const double* wt,
-                             double* z, int n, bool noise, const NoiseArgs& na, hipStream_t s);
+template <typename T>
+hipError_t launch_gblock_pass(T* x, const T* b, const GStencilT<T>& st, int colour, bool noise,
+                              const NoiseArgs& na, hipStream_t s);
+// coarsest base level (FP64 arithmetic, T storage): x = A_c^-1 b (+ sqrt(kT) L_c^-T z), z (n
+// doubles of scratch) filled with the level's FP64 normals; wt = L_c^-T row-major
+template <typename T>
+hipError_t launch_dense_draw(T* x, const T* b, const double* ainv, const double* wt, double* z,
+                             int n, bool noise, const NoiseArgs& na, hipStream_t s);
 // r = b - A x on a Galerkin base level
-hipError_t launch_gresidual(double* r, const double* x, const double* b, const GStencil& st,
-                            hipStream_t s);
+template <typename T>
+hipError_t launch_gresidual(T* r, const T* x, const T* b, const GStencilT<T>& st, hipStream_t s);
 
 }  // namespace smg

@@ -1,7 +1,10 @@
 // Kernels of the composite-grid FAC cycle: point heat-bath classes of the composite sweep, the
-// composite residual, the transfers between the composite unknowns and the base grid, and the
-// 2x2x2 block heat bath and residual of the Galerkin base levels (sparse stencil dictionary).
-// Operator, classes and noise streams as described in composite.hpp; FP64 throughout.
+// composite residual, the transfers between the composite unknowns and the base grid, the
+// 2x2x2 block heat bath and residual of the Galerkin base levels (sparse stencil dictionary)
+// and the dense draw of the coarsest base level.  Operator, classes and noise streams as
+// described in composite.hpp.  T is the storage and arithmetic type of a sweep: double in the
+// FP64 form, float for the inner cycle of the FP32-refined form (whose residual, refinement and
+// coarsest draw stay FP64).
 #include "composite.hpp"
 #include "device_common.hpp"
 
@@ -25,18 +28,20 @@ __device__ __forceinline__ int fidx(const CompGeom& g, int i, int j, int k) {
 }
 
 // the normal of `site` in the stream of na: call site/2, first or second of the pair
-__device__ __forceinline__ double normal_at(const NoiseArgs& na, uint32_t site) {
-  double z0, z1;
-  normal_pair(na, na.sid, 0u, site >> 1, z0, z1);
+template <typename T>
+__device__ __forceinline__ T normal_at(const NoiseArgs& na, uint32_t site) {
+  T z0, z1;
+  normal_pair_t<T>(na, na.sid, 0u, site >> 1, z0, z1);
   return (site & 1) ? z1 : z0;
 }
 
 // Row of coarse cell (x,y,z) in units of 1/h^2: diag = A_ii, off = sum_j (-A_ij) x_j.
-__device__ __forceinline__ void coarse_row(const double* __restrict__ xc,
-                                           const double* __restrict__ xf, const CompGeom& g,
-                                           int x, int y, int z, double& diag, double& off) {
-  diag = 0.0;
-  off = 0.0;
+template <typename T>
+__device__ __forceinline__ void coarse_row(const T* __restrict__ xc, const T* __restrict__ xf,
+                                           const CompGeom& g, int x, int y, int z, T& diag,
+                                           T& off) {
+  diag = T(0);
+  off = T(0);
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     const int axis = d >> 1;
@@ -49,7 +54,7 @@ __device__ __forceinline__ void coarse_row(const double* __restrict__ xc,
     } else {
       qz = z + sgn;
       if (qz < 0 || qz >= g.nz) {
-        diag += 2.0;
+        diag += T(2);
         continue;
       }
     }
@@ -57,7 +62,7 @@ __device__ __forceinline__ void coarse_row(const double* __restrict__ xc,
       // the four children of q on its face towards (x, y, z)
       const int i0 = 2 * (qx - g.x0), j0 = 2 * (qy - g.y0), k0 = 2 * (qz - g.z0);
       const int side = sgn > 0 ? 0 : 1;
-      double s = 0.0;
+      T s;
       if (axis == 0) {
         s = xf[fidx(g, i0 + side, j0, k0)] + xf[fidx(g, i0 + side, j0 + 1, k0)] +
             xf[fidx(g, i0 + side, j0, k0 + 1)] + xf[fidx(g, i0 + side, j0 + 1, k0 + 1)];
@@ -68,22 +73,23 @@ __device__ __forceinline__ void coarse_row(const double* __restrict__ xc,
         s = xf[fidx(g, i0, j0, k0 + side)] + xf[fidx(g, i0 + 1, j0, k0 + side)] +
             xf[fidx(g, i0, j0 + 1, k0 + side)] + xf[fidx(g, i0 + 1, j0 + 1, k0 + side)];
       }
-      diag += 4.0 / 3.0;
-      off = fma(s, 1.0 / 3.0, off);
+      diag += T(4.0 / 3.0);
+      off = fma(s, T(1.0 / 3.0), off);
     } else {
-      diag += 1.0;
+      diag += T(1);
       off += xc[qx + g.nx * (qy + g.ny * qz)];
     }
   }
 }
 
 // Row of fine cell (i,j,k) (box coordinates) in units of 1/h^2.
-__device__ __forceinline__ void fine_row(const double* __restrict__ xf,
-                                         const double* __restrict__ xc, const CompGeom& g, int i,
-                                         int j, int k, double& diag, double& off) {
-  diag = 0.0;
-  off = 0.0;
-  const double self = xf[fidx(g, i, j, k)];
+template <typename T>
+__device__ __forceinline__ void fine_row(const T* __restrict__ xf, const T* __restrict__ xc,
+                                         const CompGeom& g, int i, int j, int k, T& diag,
+                                         T& off) {
+  diag = T(0);
+  off = T(0);
+  const T self = xf[fidx(g, i, j, k)];
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     const int axis = d >> 1;
@@ -92,8 +98,8 @@ __device__ __forceinline__ void fine_row(const double* __restrict__ xf,
     const int n = axis == 0 ? g.fx : (axis == 1 ? g.fy : g.fz);
     if (c >= 0 && c < n) {
       const int ni = axis == 0 ? c : i, nj = axis == 1 ? c : j, nk = axis == 2 ? c : k;
-      diag += 0.5;
-      off = fma(0.5, xf[fidx(g, ni, nj, nk)], off);
+      diag += T(0.5);
+      off = fma(T(0.5), xf[fidx(g, ni, nj, nk)], off);
       continue;
     }
     int ax = g.x0 + (i >> 1), ay = g.y0 + (j >> 1), az = g.z0 + (k >> 1);
@@ -104,13 +110,13 @@ __device__ __forceinline__ void fine_row(const double* __restrict__ xf,
     } else {
       az = sgn > 0 ? g.z1 : g.z0 - 1;
       if (az < 0 || az >= g.nz) {  // wall face of a fine cell
-        diag += 1.0;
+        diag += T(1);
         continue;
       }
     }
     // coarse-fine face: the three other fine cells of the parent's face share its gradient
     const int ib = i & ~1, jb = j & ~1, kb = k & ~1;
-    double s;
+    T s;
     if (axis == 0) {
       s = xf[fidx(g, i, jb, kb)] + xf[fidx(g, i, jb + 1, kb)] + xf[fidx(g, i, jb, kb + 1)] +
           xf[fidx(g, i, jb + 1, kb + 1)];
@@ -121,17 +127,17 @@ __device__ __forceinline__ void fine_row(const double* __restrict__ xf,
       s = xf[fidx(g, ib, jb, k)] + xf[fidx(g, ib + 1, jb, k)] + xf[fidx(g, ib, jb + 1, k)] +
           xf[fidx(g, ib + 1, jb + 1, k)];
     }
-    diag += 1.0 / 12.0;
-    off = fma(xc[ax + g.nx * (ay + g.ny * az)], 1.0 / 3.0, off);
-    off = fma(s - self, -1.0 / 12.0, off);
+    diag += T(1.0 / 12.0);
+    off = fma(xc[ax + g.nx * (ay + g.ny * az)], T(1.0 / 3.0), off);
+    off = fma(s - self, T(-1.0 / 12.0), off);
   }
 }
 
-template <bool NOISE>
-__global__ __launch_bounds__(TPB) void k_comp_coarse_pass(double* __restrict__ xc,
-                                                          const double* __restrict__ bc,
-                                                          const double* __restrict__ xf,
-                                                          CompGeom g, int colour, NoiseArgs na) {
+template <typename T, bool NOISE>
+__global__ __launch_bounds__(TPB) void k_comp_coarse_pass(T* __restrict__ xc,
+                                                          const T* __restrict__ bc,
+                                                          const T* __restrict__ xf, CompGeom g,
+                                                          int colour, NoiseArgs na) {
   const int hx = g.nx >> 1;
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)hx * g.ny * g.nz) return;
@@ -140,32 +146,34 @@ __global__ __launch_bounds__(TPB) void k_comp_coarse_pass(double* __restrict__ x
   const int y = row % g.ny, z = row / g.ny;
   const int x = 2 * jx + ((y + z + colour) & 1);
   if (covered(g, x, y, z)) return;
-  double diag, off;
-  coarse_row(xc, xf, g, x, y, z, diag, off);
+  T diag, off;
+  coarse_row<T>(xc, xf, g, x, y, z, diag, off);
   const uint32_t site = x + g.nx * (y + g.ny * z);
-  const double a = diag * g.ih2;
-  double v = ((bc ? bc[site] : 0.0) + off * g.ih2) / a;
-  if (NOISE) v = fma(na.sqkT / sqrt(a), normal_at(na, site), v);
+  const T ih2 = (T)g.ih2;
+  const T a = diag * ih2;
+  T v = ((bc ? bc[site] : T(0)) + off * ih2) / a;
+  if (NOISE) v = fma((T)na.sqkT / sqrt(a), normal_at<T>(na, site), v);
   xc[site] = v;
 }
 
-template <bool NOISE>
-__device__ __forceinline__ void fine_update(double* __restrict__ xf, const double* __restrict__ bf,
-                                            const double* __restrict__ xc, const CompGeom& g,
-                                            int i, int j, int k, const NoiseArgs& na) {
-  double diag, off;
-  fine_row(xf, xc, g, i, j, k, diag, off);
+template <typename T, bool NOISE>
+__device__ __forceinline__ void fine_update(T* __restrict__ xf, const T* __restrict__ bf,
+                                            const T* __restrict__ xc, const CompGeom& g, int i,
+                                            int j, int k, const NoiseArgs& na) {
+  T diag, off;
+  fine_row<T>(xf, xc, g, i, j, k, diag, off);
   const uint32_t site = fidx(g, i, j, k);
-  const double a = diag * g.ih2;
-  double v = ((bf ? bf[site] : 0.0) + off * g.ih2) / a;
-  if (NOISE) v = fma(na.sqkT / sqrt(a), normal_at(na, site), v);
+  const T ih2 = (T)g.ih2;
+  const T a = diag * ih2;
+  T v = ((bf ? bf[site] : T(0)) + off * ih2) / a;
+  if (NOISE) v = fma((T)na.sqkT / sqrt(a), normal_at<T>(na, site), v);
   xf[site] = v;
 }
 
-template <bool NOISE>
-__global__ __launch_bounds__(TPB) void k_comp_fine_pass(double* __restrict__ xf,
-                                                        const double* __restrict__ bf,
-                                                        CompGeom g, int colour, NoiseArgs na) {
+template <typename T, bool NOISE>
+__global__ __launch_bounds__(TPB) void k_comp_fine_pass(T* __restrict__ xf,
+                                                        const T* __restrict__ bf, CompGeom g,
+                                                        int colour, NoiseArgs na) {
   const int hx = g.fx >> 1;
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)hx * g.fy * g.fz) return;
@@ -175,14 +183,13 @@ __global__ __launch_bounds__(TPB) void k_comp_fine_pass(double* __restrict__ xf,
   const int i = 2 * jx + ((j + k + colour) & 1);
   if (on_layer(g, i, j, k)) return;
   // off the layer every neighbour is a fine cell or a wall: the coarse field is never read
-  fine_update<NOISE>(xf, bf, nullptr, g, i, j, k, na);
+  fine_update<T, NOISE>(xf, bf, nullptr, g, i, j, k, na);
 }
 
-template <bool NOISE>
-__global__ __launch_bounds__(TPB) void k_comp_layer_pass(double* __restrict__ xf,
-                                                         const double* __restrict__ bf,
-                                                         const double* __restrict__ xc,
-                                                         CompGeom g,
+template <typename T, bool NOISE>
+__global__ __launch_bounds__(TPB) void k_comp_layer_pass(T* __restrict__ xf,
+                                                         const T* __restrict__ bf,
+                                                         const T* __restrict__ xc, CompGeom g,
                                                          const int32_t* __restrict__ cells,
                                                          int count, NoiseArgs na) {
   const int t = blockIdx.x * TPB + threadIdx.x;
@@ -190,47 +197,48 @@ __global__ __launch_bounds__(TPB) void k_comp_layer_pass(double* __restrict__ xf
   const int site = cells[t];
   const int i = site % g.fx;
   const int row = site / g.fx;
-  fine_update<NOISE>(xf, bf, xc, g, i, row % g.fy, row / g.fy, na);
+  fine_update<T, NOISE>(xf, bf, xc, g, i, row % g.fy, row / g.fy, na);
 }
 
-__global__ __launch_bounds__(TPB) void k_comp_res_coarse(double* __restrict__ rc,
-                                                         const double* __restrict__ xc,
-                                                         const double* __restrict__ xf,
-                                                         const double* __restrict__ bc,
-                                                         CompGeom g) {
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_comp_res_coarse(T* __restrict__ rc,
+                                                         const T* __restrict__ xc,
+                                                         const T* __restrict__ xf,
+                                                         const T* __restrict__ bc, CompGeom g) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)g.nx * g.ny * g.nz) return;
   const int x = t % g.nx;
   const int row = t / g.nx;
   const int y = row % g.ny, z = row / g.ny;
   if (covered(g, x, y, z)) {
-    rc[t] = 0.0;
+    rc[t] = T(0);
     return;
   }
-  double diag, off;
-  coarse_row(xc, xf, g, x, y, z, diag, off);
-  rc[t] = (bc ? bc[t] : 0.0) - (diag * xc[t] - off) * g.ih2;
+  T diag, off;
+  coarse_row<T>(xc, xf, g, x, y, z, diag, off);
+  rc[t] = (bc ? bc[t] : T(0)) - (diag * xc[t] - off) * (T)g.ih2;
 }
 
-__global__ __launch_bounds__(TPB) void k_comp_res_fine(double* __restrict__ rf,
-                                                       const double* __restrict__ xf,
-                                                       const double* __restrict__ xc,
-                                                       const double* __restrict__ bf,
-                                                       CompGeom g) {
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_comp_res_fine(T* __restrict__ rf,
+                                                       const T* __restrict__ xf,
+                                                       const T* __restrict__ xc,
+                                                       const T* __restrict__ bf, CompGeom g) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)g.fx * g.fy * g.fz) return;
   const int i = t % g.fx;
   const int row = t / g.fx;
-  double diag, off;
-  fine_row(xf, xc, g, i, row % g.fy, row / g.fy, diag, off);
-  rf[t] = (bf ? bf[t] : 0.0) - (diag * xf[t] - off) * g.ih2;
+  T diag, off;
+  fine_row<T>(xf, xc, g, i, row % g.fy, row / g.fy, diag, off);
+  rf[t] = (bf ? bf[t] : T(0)) - (diag * xf[t] - off) * (T)g.ih2;
 }
 
 // 1D weights P(p, J) of the fine cells p = 2J-1 .. 2J+2 (absolute fine coordinates) around base
 // cell J; on the wall axis the child next to a wall takes 3/4 - 1/4 (antisymmetric ghost).
 // Returns the count of fine cells inside [lo, lo + n) with their box coordinates.
+template <typename T>
 __device__ __forceinline__ int restrict_1d(int J, int nbase, bool periodic, int lo, int n,
-                                           int* idx, double* w) {
+                                           int* idx, T* w) {
   int cnt = 0;
 #pragma unroll
   for (int d = -1; d <= 2; ++d) {
@@ -242,8 +250,8 @@ __device__ __forceinline__ int restrict_1d(int J, int nbase, bool periodic, int 
     }
     const int q = p - lo;
     if (q < 0 || q >= n) continue;
-    double wt = (d == 0 || d == 1) ? 0.75 : 0.25;
-    if (!periodic && ((d == 0 && J == 0) || (d == 1 && J == nbase - 1))) wt -= 0.25;
+    T wt = (d == 0 || d == 1) ? T(0.75) : T(0.25);
+    if (!periodic && ((d == 0 && J == 0) || (d == 1 && J == nbase - 1))) wt -= T(0.25);
     idx[cnt] = q;
     w[cnt] = wt;
     ++cnt;
@@ -253,67 +261,68 @@ __device__ __forceinline__ int restrict_1d(int J, int nbase, bool periodic, int 
 
 // b0 = P^T r over the base grid and x0 = 0.  The coarse residual either comes from rc or (rc
 // null) is formed here from (xc, xf, bc), so the cycle never stores it.
-__global__ __launch_bounds__(TPB) void k_comp_restrict(double* __restrict__ b0,
-                                                       double* __restrict__ x0,
-                                                       const double* __restrict__ rc,
-                                                       const double* __restrict__ rf,
-                                                       const double* __restrict__ xc,
-                                                       const double* __restrict__ xf,
-                                                       const double* __restrict__ bc,
-                                                       CompGeom g) {
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_comp_restrict(T* __restrict__ b0, T* __restrict__ x0,
+                                                       const T* __restrict__ rc,
+                                                       const T* __restrict__ rf,
+                                                       const T* __restrict__ xc,
+                                                       const T* __restrict__ xf,
+                                                       const T* __restrict__ bc, CompGeom g) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)g.nx * g.ny * g.nz) return;
   const int X = t % g.nx;
   const int row = t / g.nx;
   const int Y = row % g.ny, Z = row / g.ny;
-  double v;
+  T v;
   if (rc) {
     v = rc[t];
   } else if (covered(g, X, Y, Z)) {
-    v = 0.0;
+    v = T(0);
   } else {
-    double diag, off;
-    coarse_row(xc, xf, g, X, Y, Z, diag, off);
-    v = (bc ? bc[t] : 0.0) - (diag * xc[t] - off) * g.ih2;
+    T diag, off;
+    coarse_row<T>(xc, xf, g, X, Y, Z, diag, off);
+    v = (bc ? bc[t] : T(0)) - (diag * xc[t] - off) * (T)g.ih2;
   }
   int ix[4], iy[4], iz[4];
-  double wx[4], wy[4], wz[4];
-  const int cx = restrict_1d(X, g.nx, true, 2 * g.x0, g.fx, ix, wx);
+  T wx[4], wy[4], wz[4];
+  const int cx = restrict_1d<T>(X, g.nx, true, 2 * g.x0, g.fx, ix, wx);
   if (cx > 0) {
-    const int cy = restrict_1d(Y, g.ny, true, 2 * g.y0, g.fy, iy, wy);
-    const int cz = cy > 0 ? restrict_1d(Z, g.nz, false, 2 * g.z0, g.fz, iz, wz) : 0;
+    const int cy = restrict_1d<T>(Y, g.ny, true, 2 * g.y0, g.fy, iy, wy);
+    const int cz = cy > 0 ? restrict_1d<T>(Z, g.nz, false, 2 * g.z0, g.fz, iz, wz) : 0;
     for (int c = 0; c < cz; ++c)
       for (int b = 0; b < cy; ++b) {
-        double s = 0.0;
+        T s = T(0);
         for (int a = 0; a < cx; ++a) s = fma(wx[a], rf[fidx(g, ix[a], iy[b], iz[c])], s);
         v = fma(wz[c] * wy[b], s, v);
       }
   }
   b0[t] = v;
-  x0[t] = 0.0;
+  x0[t] = T(0);
 }
 
 // trilinear 1D entries of fine coordinate p: (J, 3/4) and (neighbour, 1/4); at a wall the
 // neighbour is the ghost -c_J
-__device__ __forceinline__ void prolong_1d(int p, int nbase, bool periodic, int* J, double* w) {
+template <typename T>
+__device__ __forceinline__ void prolong_1d(int p, int nbase, bool periodic, int* J, T* w) {
   const int j = p >> 1;
   int o = (p & 1) ? j + 1 : j - 1;
   J[0] = j;
-  w[0] = 0.75;
+  w[0] = T(0.75);
   if (periodic) {
     J[1] = wrapm(o, nbase);
-    w[1] = 0.25;
+    w[1] = T(0.25);
   } else if (o >= 0 && o < nbase) {
     J[1] = o;
-    w[1] = 0.25;
+    w[1] = T(0.25);
   } else {
     J[1] = j;
-    w[1] = -0.25;
+    w[1] = T(-0.25);
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_comp_prolong_coarse(double* __restrict__ xc,
-                                                             const double* __restrict__ y,
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_comp_prolong_coarse(T* __restrict__ xc,
+                                                             const T* __restrict__ y,
                                                              CompGeom g) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)g.nx * g.ny * g.nz) return;
@@ -322,26 +331,26 @@ __global__ __launch_bounds__(TPB) void k_comp_prolong_coarse(double* __restrict_
   if (!covered(g, x, row % g.ny, row / g.ny)) xc[t] += y[t];
 }
 
-__global__ __launch_bounds__(TPB) void k_comp_prolong_fine(double* __restrict__ xf,
-                                                           const double* __restrict__ y,
-                                                           CompGeom g) {
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_comp_prolong_fine(T* __restrict__ xf,
+                                                           const T* __restrict__ y, CompGeom g) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)g.fx * g.fy * g.fz) return;
   const int i = t % g.fx;
   const int row = t / g.fx;
   const int j = row % g.fy, k = row / g.fy;
   int JX[2], JY[2], JZ[2];
-  double wx[2], wy[2], wz[2];
-  prolong_1d(2 * g.x0 + i, g.nx, true, JX, wx);
-  prolong_1d(2 * g.y0 + j, g.ny, true, JY, wy);
-  prolong_1d(2 * g.z0 + k, g.nz, false, JZ, wz);
-  double v = 0.0;
+  T wx[2], wy[2], wz[2];
+  prolong_1d<T>(2 * g.x0 + i, g.nx, true, JX, wx);
+  prolong_1d<T>(2 * g.y0 + j, g.ny, true, JY, wy);
+  prolong_1d<T>(2 * g.z0 + k, g.nz, false, JZ, wz);
+  T v = T(0);
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const double* yr = y + (size_t)g.nx * (JY[b] + g.ny * JZ[c]);
-      const double s = fma(wx[0], yr[JX[0]], wx[1] * yr[JX[1]]);
+      const T* yr = y + (size_t)g.nx * (JY[b] + g.ny * JZ[c]);
+      const T s = fma(wx[0], yr[JX[0]], wx[1] * yr[JX[1]]);
       v = fma(wz[c] * wy[b], s, v);
     }
   xf[t] += v;
@@ -356,24 +365,24 @@ __device__ __forceinline__ void decode(int code, int& dx, int& dy, int& dz) {
 
 // Partial sum over the stencil entries e0 + sub, e0 + sub + S, ... of cell (cx, cy, cz):
 // r -= a_e x[target_e], skipping targets inside block (bx, by, bz) when SKIP.  Entries are read
-// as (coefficient, code) records and processed eight at a time with independent loads, so the
-// latency of the gathers overlaps instead of forming one chain per entry.
-template <int S, bool SKIP>
-__device__ __forceinline__ double stencil_partial(const GStencil& st, const double* __restrict__ x,
-                                                  int sid, int sub, int cx, int cy, int cz,
-                                                  int bx, int by, int bz, double r) {
+// as (coefficient, code) records, eight at a time with independent loads, so the latency of the
+// gathers overlaps instead of forming one chain per entry.
+template <typename T, int S, bool SKIP>
+__device__ __forceinline__ T stencil_partial(const GStencilT<T>& st, const T* __restrict__ x,
+                                             int sid, int sub, int cx, int cy, int cz, int bx,
+                                             int by, int bz, T r) {
   const int e1 = st.st_off[sid + 1];
   for (int e = st.st_off[sid] + sub; e < e1; e += 8 * S) {
-    double a[8], xv[8];
+    T a[8], xv[8];
     bool use[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int eq = e + q * S;
       use[q] = eq < e1;
-      a[q] = 0.0;
-      xv[q] = 0.0;
+      a[q] = T(0);
+      xv[q] = T(0);
       if (use[q]) {
-        const StEntry en = st.ent[eq];
+        const StEntryT<T> en = st.ent[eq];
         int dx, dy, dz;
         decode(en.code, dx, dy, dz);
         const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
@@ -390,8 +399,8 @@ __device__ __forceinline__ double stencil_partial(const GStencil& st, const doub
 }
 
 // sum over the S consecutive lanes of a row
-template <int S>
-__device__ __forceinline__ double row_reduce(double r) {
+template <typename T, int S>
+__device__ __forceinline__ T row_reduce(T r) {
 #pragma unroll
   for (int m = 1; m < S; m <<= 1) r += __shfl_xor(r, m, S);
   return r;
@@ -401,10 +410,9 @@ __device__ __forceinline__ double row_reduce(double r) {
 // k = dx + 2dy + 4dz).  The cells' residuals against everything outside the block are
 // exchanged within the group and the block is drawn from its conditional law
 // x_B = A_BB^-1 r_B + sqrt(kT) L_BB^-T n_B; the first lane of each row writes it.
-template <bool NOISE, int S>
-__global__ __launch_bounds__(TPB) void k_gblock_pass(double* __restrict__ x,
-                                                     const double* __restrict__ b, GStencil st,
-                                                     int colour, NoiseArgs na) {
+template <typename T, bool NOISE, int S>
+__global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T* __restrict__ b,
+                                                     GStencilT<T> st, int colour, NoiseArgs na) {
   const int nbx = st.nx >> 1, nby = st.ny >> 1, nbz = st.nz >> 1;
   const int hbx = nbx >> 1, hby = nby >> 1;
   const int pz = colour >> 2;
@@ -424,40 +432,39 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(double* __restrict__ x,
   const uint32_t blk = bx + nbx * (by + nby * bz);
   const int typ = st.btype[blk];
   const uint32_t cell = cx + st.nx * (cy + st.ny * cz);
-  double r = (b && sub == 0) ? b[cell] : 0.0;
-  const double c7 = S == 1 ? st.bt_c7[typ] : 0.0;
-  if (c7 != 0.0) {
+  T r = (b && sub == 0) ? b[cell] : T(0);
+  const T c7 = S == 1 ? st.bt_c7[typ] : T(0);
+  if (c7 != T(0)) {
     // plain 7-point rows: the three face neighbours away from the block, one coefficient
     const int tx = wrapm(cx + ((k & 1) ? 1 : -1), st.nx);
     const int ty = wrapm(cy + ((k & 2) ? 1 : -1), st.ny);
     const int tz = cz + ((k & 4) ? 1 : -1);
-    double sum = x[tx + st.nx * (cy + st.ny * cz)] + x[cx + st.nx * (ty + st.ny * cz)];
+    T sum = x[tx + st.nx * (cy + st.ny * cz)] + x[cx + st.nx * (ty + st.ny * cz)];
     if (tz >= 0 && tz < st.nz) sum += x[cx + st.nx * (cy + st.ny * tz)];
     r = fma(-c7, sum, r);
   } else {
     const int sid = st.bt_sid[typ * 8 + k];
-    r = row_reduce<S>(stencil_partial<S, true>(st, x, sid, sub, cx, cy, cz, bx, by, bz, r));
+    r = row_reduce<T, S>(stencil_partial<T, S, true>(st, x, sid, sub, cx, cy, cz, bx, by, bz, r));
   }
-  const double* F = st.bt_fac + (size_t)typ * 128;
-  double v = 0.0;
+  const T* F = st.bt_fac + (size_t)typ * 128;
+  T v = T(0);
 #pragma unroll
   for (int m = 0; m < 8; ++m) v = fma(F[k * 8 + m], __shfl(r, m * S, 8 * S), v);
   if (NOISE) {
-    double z0, z1;
-    normal_pair(na, na.sid, 0u, (8u * blk + k) >> 1, z0, z1);
-    const double nk = (k & 1) ? z1 : z0;
-    double w = 0.0;
+    T z0, z1;
+    normal_pair_t<T>(na, na.sid, 0u, (8u * blk + k) >> 1, z0, z1);
+    const T nk = (k & 1) ? z1 : z0;
+    T w = T(0);
 #pragma unroll
     for (int m = 0; m < 8; ++m) w = fma(F[64 + k * 8 + m], __shfl(nk, m * S, 8 * S), w);
-    v = fma(na.sqkT, w, v);
+    v = fma((T)na.sqkT, w, v);
   }
   if (sub == 0) x[cell] = v;
 }
 
-template <int S>
-__global__ __launch_bounds__(TPB) void k_gresidual(double* __restrict__ r,
-                                                   const double* __restrict__ x,
-                                                   const double* __restrict__ b, GStencil st) {
+template <typename T, int S>
+__global__ __launch_bounds__(TPB) void k_gresidual(T* __restrict__ r, const T* __restrict__ x,
+                                                   const T* __restrict__ b, GStencilT<T> st) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)st.nx * st.ny * st.nz * S) return;
   const int sub = t % S;
@@ -468,27 +475,27 @@ __global__ __launch_bounds__(TPB) void k_gresidual(double* __restrict__ r,
   const uint32_t blk = (cx >> 1) + (st.nx >> 1) * ((cy >> 1) + (st.ny >> 1) * (cz >> 1));
   const int k = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
   const int typ = st.btype[blk];
-  double v = (b && sub == 0) ? b[c] : 0.0;
-  const double c7 = S == 1 ? st.bt_c7[typ] : 0.0;
-  if (c7 != 0.0) {
+  T v = (b && sub == 0) ? b[c] : T(0);
+  const T c7 = S == 1 ? st.bt_c7[typ] : T(0);
+  if (c7 != T(0)) {
     const int xm = wrapm(cx - 1, st.nx), xp = wrapm(cx + 1, st.nx);
     const int ym = wrapm(cy - 1, st.ny), yp = wrapm(cy + 1, st.ny);
     const size_t rowo = (size_t)st.nx * (cy + st.ny * cz);
-    double sum = x[xm + rowo] + x[xp + rowo] + x[cx + st.nx * (ym + st.ny * cz)] +
-                 x[cx + st.nx * (yp + st.ny * cz)];
+    T sum = x[xm + rowo] + x[xp + rowo] + x[cx + st.nx * (ym + st.ny * cz)] +
+            x[cx + st.nx * (yp + st.ny * cz)];
     if (cz > 0) sum += x[c - (size_t)st.nx * st.ny];
     if (cz + 1 < st.nz) sum += x[c + (size_t)st.nx * st.ny];
     v = fma(-st.bt_diag[typ * 8 + k], x[c], fma(-c7, sum, v));
   } else {
     const int sid = st.bt_sid[typ * 8 + k];
-    v = row_reduce<S>(stencil_partial<S, false>(st, x, sid, sub, cx, cy, cz, 0, 0, 0, v));
+    v = row_reduce<T, S>(stencil_partial<T, S, false>(st, x, sid, sub, cx, cy, cz, 0, 0, 0, v));
   }
   if (sub == 0) r[c] = v;
 }
 
 // Coarsest base level: z = the n normals of the level's stream (call j/2, first or second of the
-// pair), then x = A_c^-1 b (+ sqrt(kT) L_c^-T z) with one wave per row (A_c^-1 symmetric and
-// L_c^-T stored row-major, so every lane reads along a row).
+// pair, FP64 in every form), then x = A_c^-1 b (+ sqrt(kT) L_c^-T z) in FP64 with one wave per
+// row (A_c^-1 symmetric and L_c^-T stored row-major, so every lane reads along a row).
 __global__ __launch_bounds__(TPB) void k_dense_noise(double* __restrict__ z, int n, NoiseArgs na) {
   const int q = blockIdx.x * TPB + threadIdx.x;
   if (2 * q >= n) return;
@@ -498,9 +505,8 @@ __global__ __launch_bounds__(TPB) void k_dense_noise(double* __restrict__ z, int
   if (2 * q + 1 < n) z[2 * q + 1] = z1;
 }
 
-template <bool NOISE>
-__global__ __launch_bounds__(TPB) void k_dense_draw(double* __restrict__ x,
-                                                    const double* __restrict__ b,
+template <typename T, bool NOISE>
+__global__ __launch_bounds__(TPB) void k_dense_draw(T* __restrict__ x, const T* __restrict__ b,
                                                     const double* __restrict__ ainv,
                                                     const double* __restrict__ wt,
                                                     const double* __restrict__ z, int n,
@@ -510,7 +516,7 @@ __global__ __launch_bounds__(TPB) void k_dense_draw(double* __restrict__ x,
   if (row >= n) return;
   const double* a = ainv + (size_t)row * n;
   double acc = 0.0, an = 0.0;
-  for (int j = lane; j < n; j += 64) acc = fma(a[j], b[j], acc);
+  for (int j = lane; j < n; j += 64) acc = fma(a[j], (double)b[j], acc);
   if (NOISE) {
     const double* w = wt + (size_t)row * n;
     for (int j = row + lane; j < n; j += 64) an = fma(w[j], z[j], an);
@@ -518,109 +524,143 @@ __global__ __launch_bounds__(TPB) void k_dense_draw(double* __restrict__ x,
   }
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-  if (lane == 0) x[row] = acc;
+  if (lane == 0) x[row] = (T)acc;
 }
 
 }  // namespace
 
-hipError_t launch_dense_draw(double* x, const double* b, const double* ainv, const double* wt,
-                             double* z, int n, bool noise, const NoiseArgs& na, hipStream_t s) {
+template <typename T>
+hipError_t launch_dense_draw(T* x, const T* b, const double* ainv, const double* wt, double* z,
+                             int n, bool noise, const NoiseArgs& na, hipStream_t s) {
   if (noise) {
     k_dense_noise<<<grid_for((n + 1) / 2), TPB, 0, s>>>(z, n, na);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_dense_draw<true><<<(n + 3) / 4, TPB, 0, s>>>(x, b, ainv, wt, z, n, na.sqkT);
+    k_dense_draw<T, true><<<(n + 3) / 4, TPB, 0, s>>>(x, b, ainv, wt, z, n, na.sqkT);
   } else {
-    k_dense_draw<false><<<(n + 3) / 4, TPB, 0, s>>>(x, b, ainv, wt, z, n, na.sqkT);
+    k_dense_draw<T, false><<<(n + 3) / 4, TPB, 0, s>>>(x, b, ainv, wt, z, n, na.sqkT);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_comp_coarse_pass(double* xc, const double* bc, const double* xf,
-                                   const CompGeom& g, int colour, bool noise, const NoiseArgs& na,
-                                   hipStream_t s) {
+template <typename T>
+hipError_t launch_comp_coarse_pass(T* xc, const T* bc, const T* xf, const CompGeom& g, int colour,
+                                   bool noise, const NoiseArgs& na, hipStream_t s) {
   const uint32_t grid = grid_for((int64_t)(g.nx / 2) * g.ny * g.nz);
-  if (noise) k_comp_coarse_pass<true><<<grid, TPB, 0, s>>>(xc, bc, xf, g, colour, na);
-  else k_comp_coarse_pass<false><<<grid, TPB, 0, s>>>(xc, bc, xf, g, colour, na);
+  if (noise) k_comp_coarse_pass<T, true><<<grid, TPB, 0, s>>>(xc, bc, xf, g, colour, na);
+  else k_comp_coarse_pass<T, false><<<grid, TPB, 0, s>>>(xc, bc, xf, g, colour, na);
   return hipGetLastError();
 }
 
-hipError_t launch_comp_fine_pass(double* xf, const double* bf, const CompGeom& g, int colour,
-                                 bool noise, const NoiseArgs& na, hipStream_t s) {
+template <typename T>
+hipError_t launch_comp_fine_pass(T* xf, const T* bf, const CompGeom& g, int colour, bool noise,
+                                 const NoiseArgs& na, hipStream_t s) {
   const uint32_t grid = grid_for((int64_t)(g.fx / 2) * g.fy * g.fz);
-  if (noise) k_comp_fine_pass<true><<<grid, TPB, 0, s>>>(xf, bf, g, colour, na);
-  else k_comp_fine_pass<false><<<grid, TPB, 0, s>>>(xf, bf, g, colour, na);
+  if (noise) k_comp_fine_pass<T, true><<<grid, TPB, 0, s>>>(xf, bf, g, colour, na);
+  else k_comp_fine_pass<T, false><<<grid, TPB, 0, s>>>(xf, bf, g, colour, na);
   return hipGetLastError();
 }
 
-hipError_t launch_comp_layer_pass(double* xf, const double* bf, const double* xc,
-                                  const CompGeom& g, const int32_t* cells, int count, bool noise,
-                                  const NoiseArgs& na, hipStream_t s) {
+template <typename T>
+hipError_t launch_comp_layer_pass(T* xf, const T* bf, const T* xc, const CompGeom& g,
+                                  const int32_t* cells, int count, bool noise, const NoiseArgs& na,
+                                  hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const uint32_t grid = grid_for(count);
-  if (noise) k_comp_layer_pass<true><<<grid, TPB, 0, s>>>(xf, bf, xc, g, cells, count, na);
-  else k_comp_layer_pass<false><<<grid, TPB, 0, s>>>(xf, bf, xc, g, cells, count, na);
+  if (noise) k_comp_layer_pass<T, true><<<grid, TPB, 0, s>>>(xf, bf, xc, g, cells, count, na);
+  else k_comp_layer_pass<T, false><<<grid, TPB, 0, s>>>(xf, bf, xc, g, cells, count, na);
   return hipGetLastError();
 }
 
-hipError_t launch_comp_residual(double* rc, double* rf, const double* xc, const double* xf,
-                                const double* bc, const double* bf, const CompGeom& g,
-                                hipStream_t s) {
-  k_comp_res_coarse<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(rc, xc, xf, bc, g);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_comp_res_fine<<<grid_for((int64_t)g.fx * g.fy * g.fz), TPB, 0, s>>>(rf, xf, xc, bf, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_comp_restrict(double* b0, double* x0, const double* rc, const double* rf,
+template <typename T>
+hipError_t launch_comp_residual(T* rc, T* rf, const T* xc, const T* xf, const T* bc, const T* bf,
                                 const CompGeom& g, hipStream_t s) {
-  k_comp_restrict<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(b0, x0, rc, rf, nullptr,
-                                                                         nullptr, nullptr, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_comp_residual_restrict(double* b0, double* x0, double* rf, const double* xc,
-                                         const double* xf, const double* bc, const double* bf,
-                                         const CompGeom& g, hipStream_t s) {
-  k_comp_res_fine<<<grid_for((int64_t)g.fx * g.fy * g.fz), TPB, 0, s>>>(rf, xf, xc, bf, g);
+  k_comp_res_coarse<T><<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(rc, xc, xf, bc, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_comp_restrict<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(b0, x0, nullptr, rf, xc,
-                                                                         xf, bc, g);
+  k_comp_res_fine<T><<<grid_for((int64_t)g.fx * g.fy * g.fz), TPB, 0, s>>>(rf, xf, xc, bf, g);
   return hipGetLastError();
 }
 
-hipError_t launch_comp_prolong(double* xc, double* xf, const double* y, const CompGeom& g,
-                               hipStream_t s) {
-  k_comp_prolong_coarse<<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(xc, y, g);
+template <typename T>
+hipError_t launch_comp_restrict(T* b0, T* x0, const T* rc, const T* rf, const CompGeom& g,
+                                hipStream_t s) {
+  k_comp_restrict<T><<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(
+      b0, x0, rc, rf, nullptr, nullptr, nullptr, g);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_comp_residual_restrict(T* b0, T* x0, T* rf, const T* xc, const T* xf,
+                                         const T* bc, const T* bf, const CompGeom& g,
+                                         hipStream_t s) {
+  k_comp_res_fine<T><<<grid_for((int64_t)g.fx * g.fy * g.fz), TPB, 0, s>>>(rf, xf, xc, bf, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_comp_prolong_fine<<<grid_for((int64_t)g.fx * g.fy * g.fz), TPB, 0, s>>>(xf, y, g);
+  k_comp_restrict<T><<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(b0, x0, nullptr, rf,
+                                                                            xc, xf, bc, g);
   return hipGetLastError();
 }
 
-hipError_t launch_gblock_pass(double* x, const double* b, const GStencil& st, int colour,
-                              bool noise, const NoiseArgs& na, hipStream_t s) {
+template <typename T>
+hipError_t launch_comp_prolong(T* xc, T* xf, const T* y, const CompGeom& g, hipStream_t s) {
+  k_comp_prolong_coarse<T><<<grid_for((int64_t)g.nx * g.ny * g.nz), TPB, 0, s>>>(xc, y, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_comp_prolong_fine<T><<<grid_for((int64_t)g.fx * g.fy * g.fz), TPB, 0, s>>>(xf, y, g);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gblock_pass(T* x, const T* b, const GStencilT<T>& st, int colour, bool noise,
+                              const NoiseArgs& na, hipStream_t s) {
   const int nbz = st.nz / 2;
   const int64_t groups = (int64_t)(st.nx / 4) * (st.ny / 4) * ((nbz + 1 - (colour >> 2)) / 2) * 8;
   if (groups <= 0) return hipSuccess;
   if (st.split == 8) {
-    if (noise) k_gblock_pass<true, 8><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
-    else k_gblock_pass<false, 8><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
+    if (noise)
+      k_gblock_pass<T, true, 8><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
+    else
+      k_gblock_pass<T, false, 8><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
   } else {
-    if (noise) k_gblock_pass<true, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
-    else k_gblock_pass<false, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
+    if (noise) k_gblock_pass<T, true, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
+    else k_gblock_pass<T, false, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_gresidual(double* r, const double* x, const double* b, const GStencil& st,
-                            hipStream_t s) {
+template <typename T>
+hipError_t launch_gresidual(T* r, const T* x, const T* b, const GStencilT<T>& st, hipStream_t s) {
   const int64_t n = (int64_t)st.nx * st.ny * st.nz;
-  if (st.split == 8) k_gresidual<8><<<grid_for(n * 8), TPB, 0, s>>>(r, x, b, st);
-  else k_gresidual<1><<<grid_for(n), TPB, 0, s>>>(r, x, b, st);
+  if (st.split == 8) k_gresidual<T, 8><<<grid_for(n * 8), TPB, 0, s>>>(r, x, b, st);
+  else k_gresidual<T, 1><<<grid_for(n), TPB, 0, s>>>(r, x, b, st);
   return hipGetLastError();
 }
+
+#define SMG_COMP_INSTANTIATE(T)                                                                 \
+  template hipError_t launch_dense_draw<T>(T*, const T*, const double*, const double*, double*,   \
+                                           int, bool, const NoiseArgs&, hipStream_t);           \
+  template hipError_t launch_comp_coarse_pass<T>(T*, const T*, const T*, const CompGeom&, int,  \
+                                                 bool, const NoiseArgs&, hipStream_t);          \
+  template hipError_t launch_comp_fine_pass<T>(T*, const T*, const CompGeom&, int, bool,        \
+                                               const NoiseArgs&, hipStream_t);                  \
+  template hipError_t launch_comp_layer_pass<T>(T*, const T*, const T*, const CompGeom&,        \
+                                                const int32_t*, int, bool, const NoiseArgs&,    \
+                                                hipStream_t);                                   \
+  template hipError_t launch_comp_residual<T>(T*, T*, const T*, const T*, const T*, const T*,   \
+                                              const CompGeom&, hipStream_t);                    \
+  template hipError_t launch_comp_restrict<T>(T*, T*, const T*, const T*, const CompGeom&,      \
+                                              hipStream_t);                                     \
+  template hipError_t launch_comp_residual_restrict<T>(T*, T*, T*, const T*, const T*,          \
+                                                       const T*, const T*, const CompGeom&,     \
+                                                       hipStream_t);                            \
+  template hipError_t launch_comp_prolong<T>(T*, T*, const T*, const CompGeom&, hipStream_t);   \
+  template hipError_t launch_gblock_pass<T>(T*, const T*, const GStencilT<T>&, int, bool,       \
+                                            const NoiseArgs&, hipStream_t);                     \
+  template hipError_t launch_gresidual<T>(T*, const T*, const T*, const GStencilT<T>&,          \
+                                          hipStream_t);
+
+SMG_COMP_INSTANTIATE(double)
+SMG_COMP_INSTANTIATE(float)
 
 }  // namespace smg
