@@ -35,30 +35,52 @@ __device__ __forceinline__ T normal_at(const NoiseArgs& na, uint32_t site) {
   return (site & 1) ? z1 : z0;
 }
 
-// Row of coarse cell (x,y,z) in units of 1/h^2: diag = A_ii, off = sum_j (-A_ij) x_j.
+// Row of coarse cell (x,y,z) in units of 1/h^2: diag = A_ii, off = sum_j (-A_ij) x_j.  The six
+// neighbour values are loaded back to back (a covered or wall neighbour loads the cell itself,
+// an in-range address, and is discarded); the rare coarse-fine faces are added afterwards.
 template <typename T>
 __device__ __forceinline__ void coarse_row(const T* __restrict__ xc, const T* __restrict__ xf,
                                            const CompGeom& g, int x, int y, int z, T& diag,
                                            T& off) {
-  diag = T(0);
-  off = T(0);
+  const int self = x + g.nx * (y + g.ny * z);
+  int q[6];
+  bool wall[6], cov[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     const int axis = d >> 1;
     const int sgn = (d & 1) ? -1 : 1;
-    int qx = x, qy = y, qz = z;
-    if (axis == 0) {
-      qx = wrapm(x + sgn, g.nx);
-    } else if (axis == 1) {
-      qy = wrapm(y + sgn, g.ny);
-    } else {
-      qz = z + sgn;
-      if (qz < 0 || qz >= g.nz) {
-        diag += T(2);
-        continue;
-      }
+    const int qx = axis == 0 ? wrapm(x + sgn, g.nx) : x;
+    const int qy = axis == 1 ? wrapm(y + sgn, g.ny) : y;
+    const int qz = axis == 2 ? z + sgn : z;
+    wall[d] = qz < 0 || qz >= g.nz;
+    cov[d] = !wall[d] && covered(g, qx, qy, qz);
+    q[d] = (wall[d] || cov[d]) ? self : qx + g.nx * (qy + g.ny * qz);
+  }
+  T v[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) v[d] = xc[q[d]];
+  diag = T(0);
+  off = T(0);
+  bool any_cov = false;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    any_cov |= cov[d];
+    if (wall[d]) {
+      diag += T(2);
+    } else if (!cov[d]) {
+      diag += T(1);
+      off += v[d];
     }
-    if (covered(g, qx, qy, qz)) {
+  }
+  if (any_cov) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (!cov[d]) continue;
+      const int axis = d >> 1;
+      const int sgn = (d & 1) ? -1 : 1;
+      const int qx = axis == 0 ? wrapm(x + sgn, g.nx) : x;
+      const int qy = axis == 1 ? wrapm(y + sgn, g.ny) : y;
+      const int qz = axis == 2 ? z + sgn : z;
       // the four children of q on its face towards (x, y, z)
       const int i0 = 2 * (qx - g.x0), j0 = 2 * (qy - g.y0), k0 = 2 * (qz - g.z0);
       const int side = sgn > 0 ? 0 : 1;
@@ -75,33 +97,51 @@ __device__ __forceinline__ void coarse_row(const T* __restrict__ xc, const T* __
       }
       diag += T(4.0 / 3.0);
       off = fma(s, T(1.0 / 3.0), off);
-    } else {
-      diag += T(1);
-      off += xc[qx + g.nx * (qy + g.ny * qz)];
     }
   }
 }
 
-// Row of fine cell (i,j,k) (box coordinates) in units of 1/h^2.
+// Row of fine cell (i,j,k) (box coordinates) in units of 1/h^2, loads first as above: the six
+// neighbours inside the box (an outside neighbour loads the cell itself), then the faces on the
+// box boundary (walls, or coarse-fine faces, only on the interface layer).
 template <typename T>
 __device__ __forceinline__ void fine_row(const T* __restrict__ xf, const T* __restrict__ xc,
                                          const CompGeom& g, int i, int j, int k, T& diag,
                                          T& off) {
-  diag = T(0);
-  off = T(0);
-  const T self = xf[fidx(g, i, j, k)];
+  const int me = fidx(g, i, j, k);
+  int q[6];
+  bool in[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     const int axis = d >> 1;
     const int sgn = (d & 1) ? -1 : 1;
     const int c = (axis == 0 ? i : (axis == 1 ? j : k)) + sgn;
     const int n = axis == 0 ? g.fx : (axis == 1 ? g.fy : g.fz);
-    if (c >= 0 && c < n) {
-      const int ni = axis == 0 ? c : i, nj = axis == 1 ? c : j, nk = axis == 2 ? c : k;
+    in[d] = c >= 0 && c < n;
+    const int ni = axis == 0 ? c : i, nj = axis == 1 ? c : j, nk = axis == 2 ? c : k;
+    q[d] = in[d] ? fidx(g, ni, nj, nk) : me;
+  }
+  T v[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) v[d] = xf[q[d]];
+  const T self = xf[me];
+  diag = T(0);
+  off = T(0);
+  bool edge = false;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    edge |= !in[d];
+    if (in[d]) {
       diag += T(0.5);
-      off = fma(T(0.5), xf[fidx(g, ni, nj, nk)], off);
-      continue;
+      off = fma(T(0.5), v[d], off);
     }
+  }
+  if (!edge) return;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    if (in[d]) continue;
+    const int axis = d >> 1;
+    const int sgn = (d & 1) ? -1 : 1;
     int ax = g.x0 + (i >> 1), ay = g.y0 + (j >> 1), az = g.z0 + (k >> 1);
     if (axis == 0) {
       ax = sgn > 0 ? (g.x1 == g.nx ? 0 : g.x1) : (g.x0 == 0 ? g.nx - 1 : g.x0 - 1);
@@ -433,15 +473,23 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T*
   const int typ = st.btype[blk];
   const uint32_t cell = cx + st.nx * (cy + st.ny * cz);
   T r = (b && sub == 0) ? b[cell] : T(0);
-  const T c7 = S == 1 ? st.bt_c7[typ] : T(0);
-  if (c7 != T(0)) {
-    // plain 7-point rows: the three face neighbours away from the block, one coefficient
+  // the three face neighbours away from the block, loaded before the block type resolves (a
+  // wall neighbour loads the cell itself and is dropped)
+  T xn0 = T(0), xn1 = T(0), xn2 = T(0);
+  bool zin = false;
+  if (S == 1) {
     const int tx = wrapm(cx + ((k & 1) ? 1 : -1), st.nx);
     const int ty = wrapm(cy + ((k & 2) ? 1 : -1), st.ny);
     const int tz = cz + ((k & 4) ? 1 : -1);
-    T sum = x[tx + st.nx * (cy + st.ny * cz)] + x[cx + st.nx * (ty + st.ny * cz)];
-    if (tz >= 0 && tz < st.nz) sum += x[cx + st.nx * (cy + st.ny * tz)];
-    r = fma(-c7, sum, r);
+    zin = tz >= 0 && tz < st.nz;
+    xn0 = x[tx + st.nx * (cy + st.ny * cz)];
+    xn1 = x[cx + st.nx * (ty + st.ny * cz)];
+    xn2 = x[zin ? cx + st.nx * (cy + st.ny * tz) : cell];
+  }
+  const T c7 = S == 1 ? st.bt_c7[typ] : T(0);
+  if (c7 != T(0)) {
+    // plain 7-point rows: one coefficient for every off-block face neighbour
+    r = fma(-c7, xn0 + xn1 + (zin ? xn2 : T(0)), r);
   } else {
     const int sid = st.bt_sid[typ * 8 + k];
     r = row_reduce<T, S>(stencil_partial<T, S, true>(st, x, sid, sub, cx, cy, cz, bx, by, bz, r));
@@ -476,16 +524,23 @@ __global__ __launch_bounds__(TPB) void k_gresidual(T* __restrict__ r, const T* _
   const int k = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
   const int typ = st.btype[blk];
   T v = (b && sub == 0) ? b[c] : T(0);
-  const T c7 = S == 1 ? st.bt_c7[typ] : T(0);
-  if (c7 != T(0)) {
+  T sum = T(0), xs = T(0);
+  if (S == 1) {
+    // the six neighbours and the cell, loaded before the block type resolves
     const int xm = wrapm(cx - 1, st.nx), xp = wrapm(cx + 1, st.nx);
     const int ym = wrapm(cy - 1, st.ny), yp = wrapm(cy + 1, st.ny);
     const size_t rowo = (size_t)st.nx * (cy + st.ny * cz);
-    T sum = x[xm + rowo] + x[xp + rowo] + x[cx + st.nx * (ym + st.ny * cz)] +
-            x[cx + st.nx * (yp + st.ny * cz)];
-    if (cz > 0) sum += x[c - (size_t)st.nx * st.ny];
-    if (cz + 1 < st.nz) sum += x[c + (size_t)st.nx * st.ny];
-    v = fma(-st.bt_diag[typ * 8 + k], x[c], fma(-c7, sum, v));
+    const size_t pl = (size_t)st.nx * st.ny;
+    const T zm = x[cz > 0 ? c - pl : c];
+    const T zp = x[cz + 1 < st.nz ? c + pl : c];
+    xs = x[c];
+    sum = x[xm + rowo] + x[xp + rowo] + x[cx + st.nx * (ym + st.ny * cz)] +
+          x[cx + st.nx * (yp + st.ny * cz)] + (cz > 0 ? zm : T(0)) +
+          (cz + 1 < st.nz ? zp : T(0));
+  }
+  const T c7 = S == 1 ? st.bt_c7[typ] : T(0);
+  if (c7 != T(0)) {
+    v = fma(-st.bt_diag[typ * 8 + k], xs, fma(-c7, sum, v));
   } else {
     const int sid = st.bt_sid[typ * 8 + k];
     v = row_reduce<T, S>(stencil_partial<T, S, false>(st, x, sid, sub, cx, cy, cz, 0, 0, 0, v));
