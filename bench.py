@@ -301,6 +301,8 @@ COMP_BOX = (64, 192, 64, 192, 0, 32)
 # sweeps of the FAC cycle: the contraction is set by the composite sweeps (nu) -- base V-cycles
 # V(2,2) and V(1,0) give the same rate -- so the bench runs nu = 3 with one base pre-sweep
 COMP_NU, COMP_MU1, COMP_MU2 = 3, 1, 0
+# automatic base depth: coarsen while a level has more than 512 cells (8x8x4 drawn exactly)
+COMP_COARSEST = 512
 
 
 def composite_cpu_baseline(seconds=10.0):
@@ -338,7 +340,8 @@ def measure_composite(dev, cycles=20, with_cpu=True):
     from paper_1003_2680_amd.composite import CompositeSampler
     from paper_1003_2680_amd.inputs import gaussian_field
     t0 = time.perf_counter()
-    S = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0, nu=COMP_NU, mu1=COMP_MU1, mu2=COMP_MU2)
+    S = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0, nu=COMP_NU, mu1=COMP_MU1, mu2=COMP_MU2,
+                         coarsest_max=COMP_COARSEST)
     plan_s = time.perf_counter() - t0
     info = S.info
     xc, xf = S.zeros()
@@ -383,8 +386,8 @@ def measure_composite(dev, cycles=20, with_cpu=True):
     out = {
         "workload": "adaptive composite grid: 256x256x128 base (periodic x,y; no-slip z walls) "
                     "with the box [64,192)^2 x [0,32) refined by two; FAC cycle nu=%d, base "
-                    "V(%d,%d) on Galerkin levels, exact coarsest; FP64" % (COMP_NU, COMP_MU1,
-                                                                            COMP_MU2),
+                    "V(%d,%d) on Galerkin levels, exact coarsest (<= %d unknowns); FP64" % (
+                        COMP_NU, COMP_MU1, COMP_MU2, COMP_COARSEST),
         "unknowns": n, "base_levels": [list(info.dims[l]) for l in range(info.n_levels)],
         "distinct_rows_per_level": list(info.stencils[:info.n_levels]),
         "plan_s": round(plan_s, 2),
@@ -405,12 +408,13 @@ def measure_composite(dev, cycles=20, with_cpu=True):
     torch.cuda.empty_cache()
     # FP32-refined form of the same cycle (FP32 sweeps and transfers, FP64 residual, update and
     # coarsest draw), same noise streams; its error against the FP64 form after two cycles
-    S64 = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0, nu=COMP_NU, mu1=COMP_MU1, mu2=COMP_MU2)
+    S64 = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0, nu=COMP_NU, mu1=COMP_MU1, mu2=COMP_MU2,
+                           coarsest_max=COMP_COARSEST)
     a, af = S64.zeros()
     S64.sample(a, af, 2, seed=0)
     del S64
     S32 = CompositeSampler(*COMP_BASE, COMP_BOX, kT=1.0, nu=COMP_NU, mu1=COMP_MU1, mu2=COMP_MU2,
-                           precision="fp32_refined")
+                           coarsest_max=COMP_COARSEST, precision="fp32_refined")
     b_, bf_ = S32.zeros()
     S32.sample(b_, bf_, 2, seed=0)
     num = ((a - b_).square().sum() + (af - bf_).square().sum()).item()

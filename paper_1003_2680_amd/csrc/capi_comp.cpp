@@ -447,18 +447,36 @@ bool chol8(double* A) {
   return true;
 }
 
-// W = L^-1 (lower, n x n row-major)
+// W = L^-1 (lower, n x n row-major), row by row: W[i][c] = -(sum_{c<=k<i} L[i][k] W[k][c]) / L[i][i]
+// accumulated over k with contiguous rows of W
 std::vector<double> lower_inv(const std::vector<double>& Lm, int n) {
   std::vector<double> W((size_t)n * n, 0.0);
-  for (int c = 0; c < n; ++c) {
-    W[(size_t)c * n + c] = 1.0 / Lm[(size_t)c * n + c];
-    for (int i = c + 1; i < n; ++i) {
-      double s = 0.0;
-      for (int k = c; k < i; ++k) s += Lm[(size_t)i * n + k] * W[(size_t)k * n + c];
-      W[(size_t)i * n + c] = -s / Lm[(size_t)i * n + i];
+  std::vector<double> acc(n);
+  for (int i = 0; i < n; ++i) {
+    std::fill(acc.begin(), acc.begin() + i, 0.0);
+    for (int k = 0; k < i; ++k) {
+      const double a = Lm[(size_t)i * n + k];
+      if (a == 0.0) continue;
+      const double* wk = &W[(size_t)k * n];
+      for (int c = 0; c <= k; ++c) acc[c] += a * wk[c];
     }
+    const double d = Lm[(size_t)i * n + i];
+    for (int c = 0; c < i; ++c) W[(size_t)i * n + c] = -acc[c] / d;
+    W[(size_t)i * n + i] = 1.0 / d;
   }
   return W;
+}
+
+// rows [0, n) split over host threads
+void parallel_rows(int n, const std::function<void(int)>& fn) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  std::atomic<int> next{0};
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (int i = next++; i < n; i = next++) fn(i);
+    });
+  for (auto& t : th) t.join();
 }
 
 bool chol_dense(std::vector<double>& A, int n) {
@@ -739,13 +757,17 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
       return SMG_EINVAL;
     }
     const std::vector<double> W = lower_inv(A, n);  // L_c^-1
+    // A_c^-1 = W^T W: row i = sum_{k >= i} W[k][i] W[k][:]
     C.ainv.assign((size_t)n * n, 0.0);
-    for (int k = 0; k < n; ++k)
-      for (int i = 0; i <= k; ++i) {
+    parallel_rows(n, [&](int i) {
+      double* row = &C.ainv[(size_t)i * n];
+      for (int k = i; k < n; ++k) {
         const double a = W[(size_t)k * n + i];
         if (a == 0.0) continue;
-        for (int j = 0; j <= k; ++j) C.ainv[(size_t)i * n + j] += a * W[(size_t)k * n + j];
+        const double* wk = &W[(size_t)k * n];
+        for (int j = 0; j <= k; ++j) row[j] += a * wk[j];
       }
+    });
     C.w.assign((size_t)n * n, 0.0);  // L_c^-T = W^T
     for (int i = 0; i < n; ++i)
       for (int j = 0; j <= i; ++j) C.w[(size_t)j * n + i] = W[(size_t)i * n + j];
