@@ -75,6 +75,9 @@ struct GLevel {
   std::vector<double> bt_fac;
   std::vector<double> bt_c7, bt_diag;
   int split = 1;
+  std::vector<int32_t> list;  // split == 1: blocks of non-plain type, grouped by block colour
+  int list_off[9] = {0};
+  size_t off_list = 0;
   // device copies: fields x, b, r and the coefficient tables in the sweep precision (double, or
   // float in the FP32-refined form); the integer tables are shared
   size_t off_x = 0, off_b = 0, off_r = 0, off_btype = 0, off_btsid = 0, off_stoff = 0,
@@ -823,6 +826,24 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
     double tot = 0.0;
     for (int64_t c = 0; c < L.n; ++c) tot += L.st_off[L.sid[c] + 1] - L.st_off[L.sid[c]];
     L.split = tot > 16.0 * (double)L.n ? 8 : 1;
+    L.list.clear();
+    if (L.split == 1) {
+      const int nbx = L.nx / 2, nby = L.ny / 2, nbz = L.nz / 2;
+      std::vector<int32_t> by_col[8];
+      for (int bz = 0; bz < nbz; ++bz)
+        for (int by = 0; by < nby; ++by)
+          for (int bx = 0; bx < nbx; ++bx) {
+            const int blk = bx + nbx * (by + nby * bz);
+            if (L.bt_c7[L.btype[blk]] == 0.0)
+              by_col[(bx & 1) + 2 * (by & 1) + 4 * (bz & 1)].push_back(blk);
+          }
+      for (int c = 0; c < 8; ++c) {
+        L.list_off[c] = (int)L.list.size();
+        L.list.insert(L.list.end(), by_col[c].begin(), by_col[c].end());
+      }
+      L.list_off[8] = (int)L.list.size();
+    }
+    L.off_list = take(std::max<size_t>(1, L.list.size()) * 4);
     L.off_btc7 = take(L.bt_c7.size() * es);
     L.off_btdiag = take(L.bt_diag.size() * es);
     L.off_stoff = take(L.st_off.size() * 4);
@@ -1092,6 +1113,13 @@ int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stre
     if (L.coarsest) continue;
     CMP_HIP(up(L.off_btype, L.btype.data(), L.btype.size() * 4));
     CMP_HIP(up(L.off_btsid, L.bt_sid.data(), L.bt_sid.size() * 4));
+    CMP_HIP(up(L.off_list, L.list.data(), L.list.size() * 4));
+    for (int c = 0; c < 9; ++c) {
+      L.dev.list_off[c] = L.list_off[c];
+      L.dev32.list_off[c] = L.list_off[c];
+    }
+    L.dev.list = (const int32_t*)(ws + L.off_list);
+    L.dev32.list = (const int32_t*)(ws + L.off_list);
     if (f32) {
       CMP_HIP(up(L.off_stoff, L.st_off.data(), L.st_off.size() * 4));
       CMP_HIP(up(L.off_btfac, as32(L.bt_fac), L.bt_fac.size() * 4));

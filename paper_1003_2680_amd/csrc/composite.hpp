@@ -54,6 +54,10 @@ struct GStencilT {
   const T* bt_diag;       // [types][8]
   int nx, ny, nz;
   int split;              // lanes per row in the kernels: 1 or 8 (long rows)
+  // split == 1 levels: the blocks whose type is not plain 7-point, by block colour
+  // (list[list_off[c] .. list_off[c+1])), run by a second launch with eight lanes per row
+  const int32_t* list;
+  int list_off[9];
 };
 
 // Point heat bath of one class of the composite sweep (x_i = (b_i - sum_j A_ij x_j)/A_ii +

@@ -450,7 +450,9 @@ __device__ __forceinline__ T row_reduce(T r) {
 // k = dx + 2dy + 4dz).  The cells' residuals against everything outside the block are
 // exchanged within the group and the block is drawn from its conditional law
 // x_B = A_BB^-1 r_B + sqrt(kT) L_BB^-T n_B; the first lane of each row writes it.
-template <typename T, bool NOISE, int S>
+// MODE 0: every block of the colour; MODE 1: the plain 7-point blocks of the colour only (the
+// others are left to MODE 2); MODE 2: the listed blocks of the colour.
+template <typename T, bool NOISE, int S, int MODE>
 __global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T* __restrict__ b,
                                                      GStencilT<T> st, int colour, NoiseArgs na) {
   const int nbx = st.nx >> 1, nby = st.ny >> 1, nbz = st.nz >> 1;
@@ -459,18 +461,29 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T*
   const int nbzc = (nbz + 1 - pz) >> 1;
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   // the total is a multiple of 8*S and so is TPB: a block's group of lanes is active as a whole
-  if (t >= (uint32_t)hbx * hby * nbzc * 8 * S) return;
+  const uint32_t nblocks = MODE == 2 ? (uint32_t)(st.list_off[colour + 1] - st.list_off[colour])
+                                     : (uint32_t)hbx * hby * nbzc;
+  if (t >= nblocks * 8 * S) return;
   const int sub = t % S;
   const int k = (t / S) & 7;
   const uint32_t q = t / (8 * S);
-  const int i = q % hbx;
-  const uint32_t q2 = q / hbx;
-  const int bx = 2 * i + (colour & 1);
-  const int by = 2 * (int)(q2 % hby) + ((colour >> 1) & 1);
-  const int bz = 2 * (int)(q2 / hby) + pz;
+  int bx, by, bz;
+  if (MODE == 2) {
+    const int lb = st.list[st.list_off[colour] + q];
+    bx = lb % nbx;
+    by = (lb / nbx) % nby;
+    bz = lb / (nbx * nby);
+  } else {
+    const int i = q % hbx;
+    const uint32_t q2 = q / hbx;
+    bx = 2 * i + (colour & 1);
+    by = 2 * (int)(q2 % hby) + ((colour >> 1) & 1);
+    bz = 2 * (int)(q2 / hby) + pz;
+  }
   const int cx = 2 * bx + (k & 1), cy = 2 * by + ((k >> 1) & 1), cz = 2 * bz + (k >> 2);
   const uint32_t blk = bx + nbx * (by + nby * bz);
   const int typ = st.btype[blk];
+  if (MODE == 1 && st.bt_c7[typ] == T(0)) return;  // the whole group shares the type
   const uint32_t cell = cx + st.nx * (cy + st.ny * cz);
   T r = (b && sub == 0) ? b[cell] : T(0);
   // the three face neighbours away from the block, loaded before the block type resolves (a
@@ -510,19 +523,37 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T*
   if (sub == 0) x[cell] = v;
 }
 
-template <typename T, int S>
+// MODE 0: every cell with S lanes per row; MODE 1: the cells of plain 7-point blocks only;
+// MODE 2: the cells of the listed blocks (all colours), eight lanes per row.
+template <typename T, int S, int MODE>
 __global__ __launch_bounds__(TPB) void k_gresidual(T* __restrict__ r, const T* __restrict__ x,
                                                    const T* __restrict__ b, GStencilT<T> st) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
-  if (t >= (uint32_t)st.nx * st.ny * st.nz * S) return;
   const int sub = t % S;
-  const uint32_t c = t / S;
-  const int cx = c % st.nx;
-  const int row = c / st.nx;
-  const int cy = row % st.ny, cz = row / st.ny;
-  const uint32_t blk = (cx >> 1) + (st.nx >> 1) * ((cy >> 1) + (st.ny >> 1) * (cz >> 1));
-  const int k = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+  uint32_t c, blk;
+  int cx, cy, cz, k;
+  if (MODE == 2) {
+    if (t >= (uint32_t)st.list_off[8] * 8 * S) return;
+    k = (t / S) & 7;
+    const int lb = st.list[t / (8 * S)];
+    const int nbx = st.nx >> 1, nby = st.ny >> 1;
+    cx = 2 * (lb % nbx) + (k & 1);
+    cy = 2 * ((lb / nbx) % nby) + ((k >> 1) & 1);
+    cz = 2 * (lb / (nbx * nby)) + (k >> 2);
+    c = cx + st.nx * (cy + st.ny * cz);
+    blk = lb;
+  } else {
+    if (t >= (uint32_t)st.nx * st.ny * st.nz * S) return;
+    c = t / S;
+    cx = c % st.nx;
+    const int row = c / st.nx;
+    cy = row % st.ny;
+    cz = row / st.ny;
+    blk = (cx >> 1) + (st.nx >> 1) * ((cy >> 1) + (st.ny >> 1) * (cz >> 1));
+    k = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
+  }
   const int typ = st.btype[blk];
+  if (MODE == 1 && st.bt_c7[typ] == T(0)) return;
   T v = (b && sub == 0) ? b[c] : T(0);
   T sum = T(0), xs = T(0);
   if (S == 1) {
@@ -674,12 +705,19 @@ hipError_t launch_gblock_pass(T* x, const T* b, const GStencilT<T>& st, int colo
   if (groups <= 0) return hipSuccess;
   if (st.split == 8) {
     if (noise)
-      k_gblock_pass<T, true, 8><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
+      k_gblock_pass<T, true, 8, 0><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
     else
-      k_gblock_pass<T, false, 8><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
-  } else {
-    if (noise) k_gblock_pass<T, true, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
-    else k_gblock_pass<T, false, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
+      k_gblock_pass<T, false, 8, 0><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
+    return hipGetLastError();
+  }
+  if (noise) k_gblock_pass<T, true, 1, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
+  else k_gblock_pass<T, false, 1, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t listed = (int64_t)(st.list_off[colour + 1] - st.list_off[colour]) * 64;
+  if (listed > 0) {
+    if (noise) k_gblock_pass<T, true, 8, 2><<<grid_for(listed), TPB, 0, s>>>(x, b, st, colour, na);
+    else k_gblock_pass<T, false, 8, 2><<<grid_for(listed), TPB, 0, s>>>(x, b, st, colour, na);
   }
   return hipGetLastError();
 }
@@ -687,8 +725,15 @@ hipError_t launch_gblock_pass(T* x, const T* b, const GStencilT<T>& st, int colo
 template <typename T>
 hipError_t launch_gresidual(T* r, const T* x, const T* b, const GStencilT<T>& st, hipStream_t s) {
   const int64_t n = (int64_t)st.nx * st.ny * st.nz;
-  if (st.split == 8) k_gresidual<T, 8><<<grid_for(n * 8), TPB, 0, s>>>(r, x, b, st);
-  else k_gresidual<T, 1><<<grid_for(n), TPB, 0, s>>>(r, x, b, st);
+  if (st.split == 8) {
+    k_gresidual<T, 8, 0><<<grid_for(n * 8), TPB, 0, s>>>(r, x, b, st);
+    return hipGetLastError();
+  }
+  k_gresidual<T, 1, 1><<<grid_for(n), TPB, 0, s>>>(r, x, b, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t listed = (int64_t)st.list_off[8] * 64;
+  if (listed > 0) k_gresidual<T, 8, 2><<<grid_for(listed), TPB, 0, s>>>(r, x, b, st);
   return hipGetLastError();
 }
 
