@@ -25,7 +25,14 @@ The FP32-refined form of the same workload (FP32 sweeps and transfers, FP64 resi
 correction and coarsest arithmetic) is measured beside it under "fp32_refined", with its
 relative RMS difference from the FP64 chain on the same Philox streams.
 
+The spatially adaptive composite workload (256x256x128 base with the box [64,192)^2 x [0,32)
+refined by two, 12.06 M unknowns; stochastic FAC cycle, FP64 and FP32-refined) is measured under
+"composite": cycles/s, decorrelated samples/s, the solve, equipartition, the live-timed block
+pass of its finest base level against HBM, and the oracle's FAC cycle on its 16^3-base copy.
+
 Run: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-refined]
+                     [--no-composite]
+     python bench.py --composite-only   (the adaptive workload alone)
      python bench.py --copy-calibration   (a plain 1 GiB copy, for counter calibration)
 """
 import argparse
