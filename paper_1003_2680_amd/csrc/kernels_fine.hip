@@ -31,9 +31,23 @@ struct Diag3 {
   T sig[3];    // sqrt(kT h^2 / (6 + walls))
 };
 
+// Normals of the level-0 colour passes: FP64 without the table load (the field loads issued
+// before them stay in flight), FP32 as everywhere.
+template <typename T>
+__device__ __forceinline__ void level0_normals(const NoiseArgs& na, uint32_t comp, uint32_t call,
+                                               T& z0, T& z1) {
+  if constexpr (sizeof(T) == 8) {
+    normal_pair_notable(na, na.sid, comp, call, z0, z1);
+  } else {
+    normal_pair_t<T>(na, comp, call, z0, z1);
+  }
+}
+
 // Colour pass, nh = nx/2 even: thread (row, jp) owns the two sites j = 2jp, 2jp+1 of a row,
-// i.e. Philox call q = row*nh/2 + jp, and moves them with one vector load/store each.
-template <typename T, bool HAS_B, bool NOISE>
+// i.e. Philox call q = row*nh/2 + jp, and moves them with one vector load/store each.  ZU: the
+// launch guarantees that every wave stays in one z-plane (nh/2 * ny a multiple of 64), so the
+// wall tests and the diagonal of the plane are taken once per wave on the scalar unit.
+template <typename T, bool HAS_B, bool NOISE, bool ZU = false>
 __global__ __launch_bounds__(TPB) void k_rb_pass_v2(T* __restrict__ xc, const T* __restrict__ xo,
                                                      const T* __restrict__ bc, int nh, int ny,
                                                      int nz, uint32_t nrowpairs, int lg_nhp,
@@ -55,6 +69,7 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_v2(T* __restrict__ xc, const T*
   const uint32_t rb = row * nh;
   const int j0 = 2 * jp;
   const int xs = (y + (int)z + colour) & 1;
+
   // own row: entries j0, j0+1 and the one beyond on the side the x-neighbours lie
   const V2 c2 = *reinterpret_cast<const V2*>(o + rb + j0);
   const int jx = xs ? (j0 + 2 == nh ? 0 : j0 + 2) : (j0 == 0 ? nh - 1 : j0 - 1);
@@ -65,7 +80,8 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_v2(T* __restrict__ xc, const T*
   const V2 s2 = *reinterpret_cast<const V2*>(o + (z * ny + ys) * nh + j0);
   // the planes above and below, clamped at the walls (a wall side is masked after the loads,
   // so that no load sits in a branch and every load is in flight at once)
-  const bool top = z + 1 >= (uint32_t)nz, bottom = z == 0;
+  const uint32_t zw = ZU ? __builtin_amdgcn_readfirstlane(z) : z;
+  const bool top = zw + 1 >= (uint32_t)nz, bottom = zw == 0;
   V2 u2 = *reinterpret_cast<const V2*>(o + rb + (top ? 0 : plane) + j0);
   V2 d2 = *reinterpret_cast<const V2*>(o + rb - (bottom ? 0 : plane) + j0);
   const int nw = (int)top + (int)bottom;
@@ -78,7 +94,7 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_v2(T* __restrict__ xc, const T*
   T z0 = T(0), z1 = T(0);
   if (NOISE) {
     __builtin_amdgcn_sched_barrier(0);
-    normal_pair_t<T>(na, comp, row * nhp + jp, z0, z1);
+    level0_normals<T>(na, comp, row * nhp + jp, z0, z1);
     __builtin_amdgcn_sched_barrier(0);
   }
   if (top) u2.x = u2.y = T(0);
@@ -117,7 +133,7 @@ __global__ __launch_bounds__(TPB) void k_rb_pass(T* __restrict__ xc, const T* __
   const size_t base = (size_t)comp * nsite;
   const T* __restrict__ o = xo + base;
   T z0 = 0, z1 = 0;
-  if (NOISE) normal_pair_t<T>(na, comp, q, z0, z1);
+  if (NOISE) level0_normals<T>(na, comp, q, z0, z1);
   const uint32_t plane = (uint32_t)nh * ny;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -553,11 +569,17 @@ hipError_t launch_rb_pass(T* xc, const T* xo, const T* bc, int nx, int ny, int n
     const uint32_t npairs = nsite / 2;
     const int lg_nhp = ilog2_exact((uint32_t)nh / 2), lg_ny = ilog2_exact((uint32_t)ny);
     dim3 grid(blocks_for(npairs), ncomp);
-#define SMG_RB2(HB, NZ)                                                                        \
-  k_rb_pass_v2<T, HB, NZ><<<grid, TPB, 0, s>>>(xc, xo, bc, nh, ny, nz, npairs, lg_nhp, lg_ny, \
-                                               colour, ih2, dg, na)
-    if (bc) { if (noise) SMG_RB2(true, true); else SMG_RB2(true, false); }
-    else { if (noise) SMG_RB2(false, true); else SMG_RB2(false, false); }
+    const bool zu = ((uint64_t)(nh / 2) * ny) % 64 == 0;
+#define SMG_RB2(HB, NZ, ZU)                                                               \
+  k_rb_pass_v2<T, HB, NZ, ZU><<<grid, TPB, 0, s>>>(xc, xo, bc, nh, ny, nz, npairs, lg_nhp, \
+                                                   lg_ny, colour, ih2, dg, na)
+    if (zu) {
+      if (bc) { if (noise) SMG_RB2(true, true, true); else SMG_RB2(true, false, true); }
+      else { if (noise) SMG_RB2(false, true, true); else SMG_RB2(false, false, true); }
+    } else {
+      if (bc) { if (noise) SMG_RB2(true, true, false); else SMG_RB2(true, false, false); }
+      else { if (noise) SMG_RB2(false, true, false); else SMG_RB2(false, false, false); }
+    }
 #undef SMG_RB2
   } else {
     dim3 grid(blocks_for((nsite + 1) / 2), ncomp);

@@ -8,13 +8,15 @@
 //
 // Box-Muller turns words (w0,w1) and (w2,w3) into two 53-bit uniforms in (0,1] and then
 // into two standard normals: sqrt(-2 ln u1) cos(2 pi u2) and sqrt(-2 ln u1) sin(2 pi u2).
-// The FP64 logarithm and the sine/cosine of pi t are evaluated here (below) from their
-// series, with a bounded argument range: the general-purpose library routines spend about
-// twice the instructions on full-range reduction and extra-precise arithmetic.
+// The FP64 logarithm, square root and sine/cosine of pi t are evaluated here (below) for the
+// bounded arguments Box-Muller produces: the general-purpose library routines spend about
+// twice the instructions on full-range reduction, scaling and extra-precise arithmetic.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "sincos_table.hpp"
 
 namespace smg {
 
@@ -29,9 +31,11 @@ struct ChainKey {
 // travel in the kernel arguments so that a wave reads them with scalar loads and the FMAs take
 // them as scalar operands, instead of materialising every 64-bit literal in vector registers.
 struct BoxMullerCoef {
-  double lg[9];  // 1/19, 1/17, ..., 1/3
-  double sn[9];  // (-1)^k pi^(2k+1)/(2k+1)!, k = 8 .. 0
-  double cs[8];  // (-1)^k pi^(2k)/(2k)!, k = 8 .. 1
+  double lg[9];   // 1/19, 1/17, ..., 1/3
+  double sn[4];   // pi, -pi^3/3!, pi^5/5!, -pi^7/7!   (sin(pi r) = r (sn0 + z (sn1 + ...)), z = r^2)
+  double cs[3];   // -pi^2/2!, pi^4/4!, -pi^6/6!        (cos(pi r) = 1 + z (cs0 + z (cs1 + ...)))
+  double snq[9];  // (-1)^k pi^(2k+1)/(2k+1)!, k = 8 .. 0   (quarter-turn form, no table)
+  double csq[8];  // (-1)^k pi^(2k)/(2k)!, k = 8 .. 1
 };
 
 // sum_{i < n} c[n-1-i] z^i, lowest power first with the powers formed on the way.  Each term
@@ -65,6 +69,8 @@ inline __host__ __device__ BoxMullerCoef box_muller_coef() {
   return BoxMullerCoef{
       {1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0, 1.0 / 9.0, 1.0 / 7.0,
        1.0 / 5.0, 1.0 / 3.0},
+      {0x1.921fb54442d18p+1, -0x1.4abbce625be53p+2, 0x1.466bc6775aae2p+1, -0x1.32d2cce62bd86p-1},
+      {-0x1.3bd3cc9be45dep+2, 0x1.03c1f081b5ac4p+2, -0x1.55d3c7e3cbffap+0},
       {0x1.aaec32af93359p-21, -0x1.6fadb9f155744p-16, 0x1.e8f434d018d63p-12,
        -0x1.e3074fde8871fp-8, 0x1.50783487ee782p-4, -0x1.32d2cce62bd86p-1, 0x1.466bc6775aae2p+1,
        -0x1.4abbce625be53p+2, 0x1.921fb54442d18p+1},
@@ -122,9 +128,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& w0, uint32_t& w1, uint32
   }
 }
 
+// ((a 2^32 + b) >> 11) + 1/2, times 2^-53: the two parts a 2^-32 and ((b >> 11) + 1/2) 2^-53 are
+// exact doubles, so one rounding of their sum gives the correctly rounded value
 __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
-  uint64_t v = (((uint64_t)a << 32) | b) >> 11;
-  return ((double)v + 0.5) * 0x1p-53;
+  const double lo = fma((double)(b >> 11), 0x1p-53, 0x1p-54);
+  return fma((double)a, 0x1p-32, lo);
 }
 
 // ln(u) for u in (0, 1], FP64, within a few ulp.  u = m 2^e with m in [sqrt(1/2), sqrt(2));
@@ -155,18 +163,34 @@ __device__ __forceinline__ double log_unit(double u, const BoxMullerCoef& c) {
   return fma((double)e, LN2_HI, fma((double)e, LN2_LO, lm));
 }
 
-// sin(pi t) and cos(pi t) for t in [0, 2], FP64, within a few ulp: t = n/2 + r with n the
-// nearest integer to 2t and |r| <= 1/4 (exact); sin(pi r) and cos(pi r) from their Taylor
-// series to degree 17 and 16 (|pi r| <= pi/4: the first omitted terms are below 2^-56); then
-// the quarter-turn rotation by n.  Coefficients: (-1)^k pi^(2k+1)/(2k+1)! and
-// (-1)^k pi^(2k)/(2k)!, rounded to double.
+// sin(pi t) and cos(pi t) for t in [0, 2], FP64, within a few ulp: k = rint(128 t) and
+// r = t - k/128 (exact, |r| <= 1/256); sin(pi r) and cos(pi r) from their Taylor series to
+// degree 7 and 6 (|pi r| <= 0.0123: the first omitted terms are below 2^-70 relative); then the
+// angle addition with the tabulated sin(pi k/128), cos(pi k/128) (correctly rounded doubles).
 __device__ __forceinline__ void sincospi_turns(double t, const BoxMullerCoef& c, double& sn,
                                                double& cs) {
+  const double kf = rint(128.0 * t);
+  const double r = fma(-0.0078125, kf, t);
+  const int k = (int)kf & 255;
+  const double z = r * r;
+  const double S = r * fma(z, fma(z, fma(z, c.sn[3], c.sn[2]), c.sn[1]), c.sn[0]);
+  const double C = fma(z, fma(z, fma(z, c.cs[2], c.cs[1]), c.cs[0]), 1.0);
+  const double sk = kSinCosPi128[k][0], ck = kSinCosPi128[k][1];
+  sn = fma(sk, C, ck * S);
+  cs = fma(ck, C, -(sk * S));
+}
+
+// sin(pi t) and cos(pi t) for t in [0, 2] without a table (for kernels whose own loads should
+// stay in flight during the noise arithmetic): t = n/2 + r with n the nearest integer to 2t and
+// |r| <= 1/4 (exact); sin(pi r) and cos(pi r) from their Taylor series to degree 17 and 16
+// (|pi r| <= pi/4: the first omitted terms are below 2^-56); then the quarter-turn rotation by n.
+__device__ __forceinline__ void sincospi_quarter(double t, const BoxMullerCoef& c, double& sn,
+                                                 double& cs) {
   const double n = rint(2.0 * t);
   const double r = fma(-0.5, n, t);
   const double z = r * r;
-  const double S = r * poly_scalar_coef(c.sn, z);
-  const double C = fma(poly_scalar_coef(c.cs, z), z, 1.0);
+  const double S = r * poly_scalar_coef(c.snq, z);
+  const double C = fma(poly_scalar_coef(c.csq, z), z, 1.0);
   const int q = (int)n & 3;
   const double a = (q & 1) ? C : S;  // sin(pi (r + n/2))
   const double b = (q & 1) ? S : C;  // cos(pi (r + n/2))
@@ -174,19 +198,76 @@ __device__ __forceinline__ void sincospi_turns(double t, const BoxMullerCoef& c,
   cs = ((q + 1) & 2) ? -b : b;
 }
 
-// Two normals of call `call` in stream (sid | comp<<16) at the given cycle.
-__device__ __forceinline__ void normal_pair(const NoiseArgs& na, uint32_t sid, uint32_t comp,
-                                            uint32_t call, double& z0, double& z1) {
+// sqrt(a) for a in [0, 2^10] (Box-Muller's -2 ln u1 <= 75): the hardware reciprocal square
+// root refined by a Goldschmidt step and two residual corrections; no scaling is needed in this
+// range, and a = 0 gives 0.
+__device__ __forceinline__ double sqrt_bm(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, a);
+  g = fma(d, h, g);
+  d = fma(-g, g, a);
+  g = fma(d, h, g);
+  return a > 0.0 ? g : 0.0;
+}
+
+// The FP64 normal pair in two stages, so that a kernel can issue its own loads in between:
+// normal_start runs Philox, forms both uniforms and issues the load of the angle's table entry;
+// normal_finish evaluates the logarithm, the square root and the short sine/cosine series.
+struct PendingNormals {
+  double u1, r;  // radial uniform; angle remainder r = t - k/128
+  double sk, ck; // sin(pi k/128), cos(pi k/128)
+};
+
+__device__ __forceinline__ void normal_start(const NoiseArgs& na, uint32_t sid, uint32_t comp,
+                                             uint32_t call, PendingNormals& p) {
   uint32_t w0 = call, w1, w2, w3, k0, k1;
   noise_key(na, sid, comp, k0, k1, w1, w2, w3);
   philox4x32_10(w0, w1, w2, w3, k0, k1);
-  double u1 = uniform53(w0, w1);
-  double u2 = uniform53(w2, w3);
-  double r = sqrt(-2.0 * log_unit(u1, na.bm));
+  p.u1 = uniform53(w0, w1);
+  const double t = 2.0 * uniform53(w2, w3);
+  const double kf = rint(128.0 * t);
+  p.r = fma(-0.0078125, kf, t);
+  const int k = (int)kf & 255;
+  p.sk = kSinCosPi128[k][0];
+  p.ck = kSinCosPi128[k][1];
+}
+
+__device__ __forceinline__ void normal_finish(const NoiseArgs& na, const PendingNormals& p,
+                                              double& z0, double& z1) {
+  const BoxMullerCoef& c = na.bm;
+  const double rad = sqrt_bm(-2.0 * log_unit(p.u1, c));
+  const double z = p.r * p.r;
+  const double S = p.r * fma(z, fma(z, fma(z, c.sn[3], c.sn[2]), c.sn[1]), c.sn[0]);
+  const double C = fma(z, fma(z, fma(z, c.cs[2], c.cs[1]), c.cs[0]), 1.0);
+  z0 = rad * fma(p.ck, C, -(p.sk * S));
+  z1 = rad * fma(p.sk, C, p.ck * S);
+}
+
+// Two normals of call `call` in stream (sid | comp<<16) at the given cycle.
+__device__ __forceinline__ void normal_pair(const NoiseArgs& na, uint32_t sid, uint32_t comp,
+                                            uint32_t call, double& z0, double& z1) {
+  PendingNormals p;
+  normal_start(na, sid, comp, call, p);
+  normal_finish(na, p, z0, z1);
+}
+
+// The same normals (to rounding) without the table load: the level-0 colour passes use this form
+// so that the angle never waits behind their field loads.
+__device__ __forceinline__ void normal_pair_notable(const NoiseArgs& na, uint32_t sid,
+                                                    uint32_t comp, uint32_t call, double& z0,
+                                                    double& z1) {
+  uint32_t w0 = call, w1, w2, w3, k0, k1;
+  noise_key(na, sid, comp, k0, k1, w1, w2, w3);
+  philox4x32_10(w0, w1, w2, w3, k0, k1);
+  const double rad = sqrt_bm(-2.0 * log_unit(uniform53(w0, w1), na.bm));
   double s, c;
-  sincospi_turns(2.0 * u2, na.bm, s, c);
-  z0 = r * c;
-  z1 = r * s;
+  sincospi_quarter(2.0 * uniform53(w2, w3), na.bm, s, c);
+  z0 = rad * c;
+  z1 = rad * s;
 }
 
 // FP32 variant for the FP32 sweeps of the refined mode: the same Philox words and the same
