@@ -29,6 +29,12 @@ template <typename T>
 struct Diag3 {
   T inv_d[3];  // h^2 / (6 + walls)
   T sig[3];    // sqrt(kT h^2 / (6 + walls))
+  T inv_n[3];  // 1 / (6 + walls): the neighbour sum's weight when b = 0
+};
+
+template <typename T, int S>
+struct Arr {
+  T v[S];
 };
 
 // Normals of the level-0 colour passes: FP64 without the table load (the field loads issued
@@ -43,81 +49,121 @@ __device__ __forceinline__ void level0_normals(const NoiseArgs& na, uint32_t com
   }
 }
 
-// Colour pass, nh = nx/2 even: thread (row, jp) owns the two sites j = 2jp, 2jp+1 of a row,
-// i.e. Philox call q = row*nh/2 + jp, and moves them with one vector load/store each.  ZU: the
-// launch guarantees that every wave stays in one z-plane (nh/2 * ny a multiple of 64), so the
-// wall tests and the diagonal of the plane are taken once per wave on the scalar unit.
+// 16 bytes of consecutive colour entries: the unit of a thread's loads and stores
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+};
+
+// Colour pass, nh = nx/2 a multiple of S = 16/sizeof(T): thread (row, jt) owns the S sites
+// j = S jt .. S jt + S-1 of a row (FP64: one pair, FP32: two pairs; pair p of the row is
+// Philox call row*nh/2 + p, whatever the launch) and moves them with one 16-byte load per
+// neighbour row and one 16-byte store.  The first site's entry is S t; every access is a
+// 32-bit byte offset from the component's base (the launch checks that a component's colour
+// array is below 4 GiB), so the loads take a scalar base and a 32-bit lane offset.  ZU: the
+// launch guarantees that every wave stays in one z-plane (nh/S * ny a multiple of 64), so the
+// wall tests and the diagonal of the plane are taken once per wave on the scalar unit.  A wall
+// side enters the z-sum with weight 0.
 template <typename T, bool HAS_B, bool NOISE, bool ZU = false>
-__global__ __launch_bounds__(TPB) void k_rb_pass_v2(T* __restrict__ xc, const T* __restrict__ xo,
-                                                     const T* __restrict__ bc, int nh, int ny,
-                                                     int nz, uint32_t nrowpairs, int lg_nhp,
-                                                     int lg_ny, int colour, T inv_h2,
-                                                     Diag3<T> dg, NoiseArgs na) {
-  using V2 = typename Vec2<T>::type;
+__global__ __launch_bounds__(TPB) void k_rb_pass_vec(T* __restrict__ xc, const T* __restrict__ xo,
+                                                      const T* __restrict__ bc, int nh, int ny,
+                                                      int nz, uint32_t nthreads, int lg_nht,
+                                                      int lg_ny, int colour, T inv_h2,
+                                                      Diag3<T> dg, NoiseArgs na) {
+  using V = typename Vec16<T>::type;
+  constexpr uint32_t W = sizeof(T), S = 16 / W;
   const uint32_t comp = blockIdx.y;
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
-  if (t >= nrowpairs) return;
-  const uint32_t nhp = (uint32_t)nh >> 1;
-  const uint32_t row = udiv(t, nhp, lg_nhp);
-  const int jp = (int)(t - row * nhp);
-  const uint32_t z = udiv(row, (uint32_t)ny, lg_ny);
-  const int y = (int)(row - z * ny);
+  if (t >= nthreads) return;
+  const uint32_t nht = (uint32_t)nh / S;
+  uint32_t row, jt, z, y;
+  if (lg_nht >= 0) {
+    row = t >> lg_nht;
+    jt = t & (nht - 1);
+  } else {
+    row = t / nht;
+    jt = t - row * nht;
+  }
+  if (lg_ny >= 0) {
+    z = row >> lg_ny;
+    y = row & ((uint32_t)ny - 1);
+  } else {
+    z = row / (uint32_t)ny;
+    y = row - z * (uint32_t)ny;
+  }
   const uint32_t nsite = (uint32_t)nh * ny * nz;
   const size_t base = (size_t)comp * nsite;
-  const T* __restrict__ o = xo + base;
+  const char* __restrict__ ob = reinterpret_cast<const char*>(xo + base);
   const uint32_t plane = (uint32_t)nh * ny;
-  const uint32_t rb = row * nh;
-  const int j0 = 2 * jp;
-  const int xs = (y + (int)z + colour) & 1;
+  const uint32_t ic = S * t;          // row * nh + S jt
+  const uint32_t rb = ic - S * jt;    // row * nh
+  const uint32_t xs = (y + z + (uint32_t)colour) & 1u;
+  auto ld = [&](uint32_t e) {
+    T v[S];
+    *reinterpret_cast<V*>(v) = *reinterpret_cast<const V*>(ob + e * W);
+    return *reinterpret_cast<const Arr<T, S>*>(v);
+  };
 
-  // own row: entries j0, j0+1 and the one beyond on the side the x-neighbours lie
-  const V2 c2 = *reinterpret_cast<const V2*>(o + rb + j0);
-  const int jx = xs ? (j0 + 2 == nh ? 0 : j0 + 2) : (j0 == 0 ? nh - 1 : j0 - 1);
-  const T ex = o[rb + jx];
-  const int yn = (y + 1 == ny) ? 0 : y + 1;
-  const int ys = (y == 0) ? ny - 1 : y - 1;
-  const V2 n2 = *reinterpret_cast<const V2*>(o + (z * ny + yn) * nh + j0);
-  const V2 s2 = *reinterpret_cast<const V2*>(o + (z * ny + ys) * nh + j0);
-  // the planes above and below, clamped at the walls (a wall side is masked after the loads,
-  // so that no load sits in a branch and every load is in flight at once)
+  // own row: the S entries and the one beyond on the side the x-neighbours lie
+  const Arr<T, S> c = ld(ic);
+  const uint32_t ie = xs ? (jt + 1 == nht ? rb : ic + S) : (jt == 0 ? rb + (uint32_t)nh - 1 : ic - 1);
+  const T ex = *reinterpret_cast<const T*>(ob + ie * W);
+  const uint32_t in = ic + (y + 1 == (uint32_t)ny ? (uint32_t)nh - plane : (uint32_t)nh);
+  const uint32_t is = ic + (y == 0 ? plane - (uint32_t)nh : 0u - (uint32_t)nh);
+  const Arr<T, S> n = ld(in), so = ld(is);
+  // the planes above and below, clamped at the walls (all loads unconditional and in flight
+  // at once)
   const uint32_t zw = ZU ? __builtin_amdgcn_readfirstlane(z) : z;
   const bool top = zw + 1 >= (uint32_t)nz, bottom = zw == 0;
-  V2 u2 = *reinterpret_cast<const V2*>(o + rb + (top ? 0 : plane) + j0);
-  V2 d2 = *reinterpret_cast<const V2*>(o + rb - (bottom ? 0 : plane) + j0);
+  const Arr<T, S> u = ld(ic + (top ? 0u : plane)), d = ld(ic - (bottom ? 0u : plane));
+  Arr<T, S> b;
+  if (HAS_B) {
+    *reinterpret_cast<V*>(b.v) =
+        *reinterpret_cast<const V*>(reinterpret_cast<const char*>(bc + base) + ic * W);
+  }
   const int nw = (int)top + (int)bottom;
-  const T idg = dg.inv_d[nw], sgm = dg.sig[nw];  // loaded now, used after the noise
-  V2 b2;
-  if (HAS_B) b2 = *reinterpret_cast<const V2*>(bc + base + rb + j0);
+  const T wu = top ? T(0) : T(1), wd = bottom ? T(0) : T(1);
+  const T idg = dg.inv_d[nw], sgm = dg.sig[nw], inn = dg.inv_n[nw];
   // The normals depend on no load: with every load issued above, the Philox and Box-Muller
   // arithmetic runs while they are in flight (the scheduling barriers keep the compiler from
   // hoisting the sums, which wait for the loads, in front of it).
-  T z0 = T(0), z1 = T(0);
+  T zn[S];
+#pragma unroll
+  for (uint32_t k = 0; k < S; ++k) zn[k] = T(0);
   if (NOISE) {
     __builtin_amdgcn_sched_barrier(0);
-    level0_normals<T>(na, comp, row * nhp + jp, z0, z1);
+#pragma unroll
+    for (uint32_t p = 0; p < S / 2; ++p)
+      level0_normals<T>(na, comp, (S / 2) * t + p, zn[2 * p], zn[2 * p + 1]);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (top) u2.x = u2.y = T(0);
-  if (bottom) d2.x = d2.y = T(0);
-  // x-neighbour pairs: xs == 0 -> (j-1, j), xs == 1 -> (j, j+1)
-  const T xa0 = xs ? c2.x : ex, xb0 = xs ? c2.y : c2.x;
-  const T xa1 = xs ? c2.y : c2.x, xb1 = xs ? ex : c2.y;
-  T v0 = ((xa0 + xb0) + (n2.x + s2.x) + (u2.x + d2.x)) * inv_h2;
-  T v1 = ((xa1 + xb1) + (n2.y + s2.y) + (u2.y + d2.y)) * inv_h2;
-  if (HAS_B) {
-    v0 += b2.x;
-    v1 += b2.y;
+  // x-neighbour sums: xs == 1 -> (j, j+1), xs == 0 -> (j-1, j); the entry beyond the owned
+  // ones closes the last pair on the side it lies
+  T a[S];
+#pragma unroll
+  for (uint32_t k = 0; k + 1 < S; ++k) a[k] = c.v[k] + c.v[k + 1];
+  const T ed = ex + (xs ? c.v[S - 1] : c.v[0]);
+  T out[S];
+#pragma unroll
+  for (uint32_t k = 0; k < S; ++k) {
+    const T sx = xs ? (k + 1 < S ? a[k] : ed) : (k > 0 ? a[k - 1] : ed);
+    const T sum = (sx + (n.v[k] + so.v[k])) + fma(u.v[k], wu, d.v[k] * wd);
+    T v;
+    if (HAS_B)
+      v = fma(sum, inv_h2, b.v[k]) * idg;
+    else
+      v = sum * inn;
+    if (NOISE) v = fma(sgm, zn[k], v);
+    out[k] = v;
   }
-  v0 *= idg;
-  v1 *= idg;
-  if (NOISE) {
-    v0 = fma(sgm, z0, v0);
-    v1 = fma(sgm, z1, v1);
-  }
-  V2 out;
-  out.x = v0;
-  out.y = v1;
-  *reinterpret_cast<V2*>(xc + base + rb + j0) = out;
+  *reinterpret_cast<V*>(reinterpret_cast<char*>(xc + base) + ic * W) =
+      *reinterpret_cast<const V*>(out);
 }
 
 // Generic colour pass (any even nx): thread q owns colour sites 2q and 2q+1 (one Philox call).
@@ -563,24 +609,26 @@ hipError_t launch_rb_pass(T* xc, const T* xo, const T* bc, int nx, int ny, int n
   for (int w = 0; w < 3; ++w) {
     dg.inv_d[w] = (T)(h * h / (6.0 + w));
     dg.sig[w] = (T)sqrt(kT * h * h / (6.0 + w));
+    dg.inv_n[w] = (T)(1.0 / (6.0 + w));
   }
   const T ih2 = (T)(1.0 / (h * h));
-  if (nh % 2 == 0) {
-    const uint32_t npairs = nsite / 2;
-    const int lg_nhp = ilog2_exact((uint32_t)nh / 2), lg_ny = ilog2_exact((uint32_t)ny);
-    dim3 grid(blocks_for(npairs), ncomp);
-    const bool zu = ((uint64_t)(nh / 2) * ny) % 64 == 0;
-#define SMG_RB2(HB, NZ, ZU)                                                               \
-  k_rb_pass_v2<T, HB, NZ, ZU><<<grid, TPB, 0, s>>>(xc, xo, bc, nh, ny, nz, npairs, lg_nhp, \
-                                                   lg_ny, colour, ih2, dg, na)
+  constexpr int S = 16 / (int)sizeof(T);
+  if (nh % S == 0 && (uint64_t)nsite * sizeof(T) < (1ull << 32)) {
+    const uint32_t nthreads = nsite / S;
+    const int lg_nht = ilog2_exact((uint32_t)(nh / S)), lg_ny = ilog2_exact((uint32_t)ny);
+    dim3 grid(blocks_for(nthreads), ncomp);
+    const bool zu = ((uint64_t)(nh / S) * ny) % 64 == 0;
+#define SMG_RBV(HB, NZ, ZU)                                                                  \
+  k_rb_pass_vec<T, HB, NZ, ZU><<<grid, TPB, 0, s>>>(xc, xo, bc, nh, ny, nz, nthreads, lg_nht, \
+                                                    lg_ny, colour, ih2, dg, na)
     if (zu) {
-      if (bc) { if (noise) SMG_RB2(true, true, true); else SMG_RB2(true, false, true); }
-      else { if (noise) SMG_RB2(false, true, true); else SMG_RB2(false, false, true); }
+      if (bc) { if (noise) SMG_RBV(true, true, true); else SMG_RBV(true, false, true); }
+      else { if (noise) SMG_RBV(false, true, true); else SMG_RBV(false, false, true); }
     } else {
-      if (bc) { if (noise) SMG_RB2(true, true, false); else SMG_RB2(true, false, false); }
-      else { if (noise) SMG_RB2(false, true, false); else SMG_RB2(false, false, false); }
+      if (bc) { if (noise) SMG_RBV(true, true, false); else SMG_RBV(true, false, false); }
+      else { if (noise) SMG_RBV(false, true, false); else SMG_RBV(false, false, false); }
     }
-#undef SMG_RB2
+#undef SMG_RBV
   } else {
     dim3 grid(blocks_for((nsite + 1) / 2), ncomp);
 #define SMG_RB(HB, NZ) \

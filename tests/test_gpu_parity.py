@@ -45,8 +45,13 @@ def _announce(msg):
 
 
 # ----------------------------------------------------------------------------- components
+# (12,8,6), (4,2,1): two sites per thread; (10,6,5), (2,4,3): one pair per Philox call over odd
+# rows; the rest four sites per thread: (16,8,6) waves across planes, (24,6,5) row and plane
+# counts not powers of two, (8,4,1) both walls on one plane, (32,32,4) and (64,16,9) every wave
+# in one plane, the latter with a ragged last work-group
 @pytest.mark.parametrize("dims,ncomp", [((12, 8, 6), 2), ((10, 6, 5), 1), ((4, 2, 1), 1),
-                                        ((2, 4, 3), 3)])
+                                        ((2, 4, 3), 3), ((16, 8, 6), 2), ((24, 6, 5), 2),
+                                        ((8, 4, 1), 1), ((32, 32, 4), 1), ((64, 16, 9), 3)])
 @pytest.mark.parametrize("with_b", [False, True])
 def test_point_pass(dims, ncomp, with_b):
     _announce("point pass %s ncomp=%d b=%s" % (dims, ncomp, with_b))
