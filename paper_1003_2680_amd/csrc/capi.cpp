@@ -78,6 +78,7 @@ NoiseArgs make_noise(const Run& r, int level, int slot, int colour, uint32_t kin
   na.sqkT = std::sqrt(r.h->desc.kT);
   na.chains = r.chains;
   na.comps_per_chain = r.cpc;
+  na.cpc_magic = chain_divisor_magic((uint32_t)r.cpc);
   na.bm = box_muller_coef();
   return na;
 }

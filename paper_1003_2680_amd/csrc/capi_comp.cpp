@@ -870,6 +870,7 @@ NoiseArgs comp_noise(const Composite& C, uint64_t seed, uint64_t cycle, int leve
   na.sqkT = std::sqrt(C.kT);
   na.chains = nullptr;
   na.comps_per_chain = 1;
+  na.cpc_magic = 0;
   na.bm = box_muller_coef();
   return na;
 }

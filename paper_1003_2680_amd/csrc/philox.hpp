@@ -61,8 +61,16 @@ struct NoiseArgs {
   double sqkT;       // sqrt(kT)
   const ChainKey* chains;    // null: one chain keyed by (k0, k1)
   uint32_t comps_per_chain;
+  // floor(2^32 / comps_per_chain) + 1 (0 when comps_per_chain is 1): comp / comps_per_chain is
+  // the high word of comp * cpc_magic for comp and comps_per_chain below 2^16
+  uint32_t cpc_magic;
   BoxMullerCoef bm;
 };
+
+// The multiplier that turns the division by comps_per_chain into a multiply-high (host).
+inline uint32_t chain_divisor_magic(uint32_t comps_per_chain) {
+  return comps_per_chain <= 1 ? 0u : (uint32_t)((1ull << 32) / comps_per_chain) + 1u;
+}
 
 // The coefficient values (host and device).
 inline __host__ __device__ BoxMullerCoef box_muller_coef() {
@@ -87,7 +95,7 @@ __device__ __forceinline__ void noise_key(const NoiseArgs& na, uint32_t sid, uin
                                           uint32_t& w3) {
   comp = __builtin_amdgcn_readfirstlane(comp);
   if (na.chains) {
-    const uint32_t ch = comp / na.comps_per_chain;
+    const uint32_t ch = na.cpc_magic ? __umulhi(comp, na.cpc_magic) : comp;
     // the chain table is read-only while kernels run: scalar loads through the constant space
     typedef const __attribute__((address_space(4))) uint32_t* cword;
     const cword kw = (cword)(const void*)(na.chains + ch);
@@ -117,8 +125,17 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& w0, uint32_t& w1, uint32
   for (int r = 0; r < 10; ++r) {
     uint64_t p0 = (uint64_t)0xD2511F53u * w0;
     uint64_t p1 = (uint64_t)0xCD9E8D57u * w2;
-    uint32_t n0 = (uint32_t)(p1 >> 32) ^ w1 ^ k0;
-    uint32_t n2 = (uint32_t)(p0 >> 32) ^ w3 ^ k1;
+    uint32_t n0, n2;
+    if (r < 2) {
+      // the counter words w1..w3 are usually uniform across a wave, so the first two rounds
+      // keep plain exclusive ors, which the compiler moves to the scalar unit where it can
+      n0 = (uint32_t)(p1 >> 32) ^ w1 ^ k0;
+      n2 = (uint32_t)(p0 >> 32) ^ w3 ^ k1;
+    } else {
+      // three-input exclusive or in one instruction (truth table 0x96: odd parity)
+      n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), w1, k0, 0x96);
+      n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), w3, k1, 0x96);
+    }
     w1 = (uint32_t)p1;
     w3 = (uint32_t)p0;
     w0 = n0;
