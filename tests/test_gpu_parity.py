@@ -300,3 +300,29 @@ def test_bottom_kernel_matches_per_pass_launches(dims, levels, ncomp):
         u, cycles, relres = H.solve(_dev(f), rtol=1e-11)
         sols.append(_host(u))
     assert _relerr(sols[0], sols[1]) <= 1e-12
+
+
+@pytest.mark.gpu
+def test_level0_normals_close_to_oracle():
+    """With x = 0, b = 0 and kT = 6 h^2 an interior site's update is exactly its normal, so
+    the FP64 Box-Muller of the kernels is compared with the oracle's (NumPy log, cos, sin)
+    value by value: 1e-14 absolute, far tighter than the field bar (the oracle rounds 2 pi u2,
+    worth a few 1e-16 times the radius)."""
+    dims = (64, 16, 8)
+    _announce("level-0 normals %s" % (dims,))
+    H = _hier(*dims, ncomp=1, kT=6.0, levels=1, coarsest="smooth")
+    mg = StochasticMG(*dims, kT=6.0, levels=1, coarsest="smooth")
+    L = mg.levels[0]
+    N = L.n
+    nx, ny, nz = dims
+    interior = (np.arange(N) // (nx * ny) > 0) & (np.arange(N) // (nx * ny) < nz - 1)
+    seed, cycle, slot = 987654321, 5, 1
+    for colour in (0, 1):
+        xg = torch.zeros(H.shape, dtype=torch.float64, device="cuda")
+        H.debug_smooth(0, colour, xg, None, seed=seed, cycle=cycle, slot=slot)
+        got = _host(xg).reshape(N)
+        ref = np.zeros(N)
+        mg._point_pass(L, ref, np.zeros(N), colour, PhiloxNoise(seed), (cycle, slot, 0))
+        sel = interior & (ref != 0.0)
+        assert sel.sum() == (nz - 2) * nx * ny // 2   # the colour's interior sites
+        assert np.max(np.abs(got[sel] - ref[sel])) <= 1e-14
