@@ -161,8 +161,8 @@ hipError_t launch_advance_chains(ChainKey* dst, int n, uint64_t cycles, hipStrea
 
 // Statistics of one emitted sample of level 0 (FP64 state), fused with its emission.
 constexpr int kMaxModes = 32;
-constexpr int STATS_CPT = 4;                            // cells per thread and batch
-constexpr int STATS_NB = 4;                             // batches per thread
+constexpr int STATS_CPT = 2;                            // cells per thread and batch
+constexpr int STATS_NB = 8;                             // batches per thread
 constexpr int STATS_CELLS = STATS_NB * STATS_CPT * 256;  // cells per work-group
 struct StatsArgs {
   const double* xr;   // split layout: colour-0 half [ncomp][N/2]; natural layout: [ncomp][N]
