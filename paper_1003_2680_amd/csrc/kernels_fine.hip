@@ -506,31 +506,45 @@ __global__ __launch_bounds__(TPB) void k_prolong0(T* __restrict__ xr, T* __restr
 
 // The same for nx/2 even, two sites per thread: sites j0 = 2jp and j0 + 1 of a colour row sit
 // two cells apart, so their trilinear windows share the coarse row pairs and two of three
-// coarse columns (12 loads of e for both), and x moves with one 16-byte load and store.
+// coarse columns: per coarse row one 16-byte load of columns (j0, j0+1) and one load of the
+// column beyond on the side of the sites' x offset (8 loads of e for both sites), and x moves
+// with one 16-byte load and store.  Row and plane come by shifts when the row counts are powers
+// of two.
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_prolong0_pair(T* __restrict__ xr, T* __restrict__ xb,
                                                         const T* __restrict__ e, int nxf, int nyf,
                                                         int nzf, uint32_t npairs, uint32_t Nc,
-                                                        int cfirst) {
+                                                        int cfirst, int lg_nhp, int lg_ny) {
   using V2 = typename Vec2<T>::type;
   const uint32_t comp = blockIdx.y;
   const int colour = cfirst + blockIdx.z;
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= npairs) return;
-  const int nh = nxf >> 1, nhp = nh >> 1;
-  const uint32_t row = t / nhp;
-  const int jp = t - row * nhp;
-  const int yf = row % nyf;
-  const int zf = row / nyf;
-  const int sx = (yf + zf + colour) & 1;  // x = 2j + sx
-  const int j0 = 2 * jp;
-  const int nxc = nxf >> 1, nyc = nyf >> 1, nzc = nzf >> 1;
-  // coarse columns: own parents j0, j0+1; the other parent of each lies on the side of sx
-  const int Xm = j0 == 0 ? nxc - 1 : j0 - 1, Xa = j0, Xb = j0 + 1;
-  const int Xp = j0 + 2 == nxc ? 0 : j0 + 2;
-  const int Y0 = yf >> 1;
+  const int nh = nxf >> 1;
+  const uint32_t nhp = (uint32_t)nh >> 1;
+  uint32_t row, jp, zf, yf;
+  if (lg_nhp >= 0) {
+    row = t >> lg_nhp;
+    jp = t & (nhp - 1);
+  } else {
+    row = t / nhp;
+    jp = t - row * nhp;
+  }
+  if (lg_ny >= 0) {
+    zf = row >> lg_ny;
+    yf = row & ((uint32_t)nyf - 1);
+  } else {
+    zf = row / (uint32_t)nyf;
+    yf = row - zf * (uint32_t)nyf;
+  }
+  const int sx = (int)((yf + zf + (uint32_t)colour) & 1u);  // x = 2j + sx
+  const int j0 = 2 * (int)jp;
+  const int nxc = nh, nyc = nyf >> 1, nzc = nzf >> 1;
+  // the coarse column beyond the pair on the side of sx
+  const int Xo = sx ? (j0 + 2 == nxc ? 0 : j0 + 2) : (j0 == 0 ? nxc - 1 : j0 - 1);
+  const int Y0 = (int)(yf >> 1);
   const int Y1 = (yf & 1) ? (Y0 + 1 == nyc ? 0 : Y0 + 1) : (Y0 == 0 ? nyc - 1 : Y0 - 1);
-  const int Z0 = zf >> 1;
+  const int Z0 = (int)(zf >> 1);
   int Z1 = (zf & 1) ? Z0 + 1 : Z0 - 1;
   T wz0 = T(0.75), wz1 = T(0.25);
   if (Z1 < 0 || Z1 >= nzc) {
@@ -545,13 +559,23 @@ __global__ __launch_bounds__(TPB) void k_prolong0_pair(T* __restrict__ xr, T* __
   const T* r11 = E + ((size_t)Z1 * nyc + Y1) * nxc;
   T* X = (colour ? xb : xr) + (size_t)comp * (npairs * 2);
   V2 xv = *reinterpret_cast<const V2*>(X + 2 * t);
-  // site a: own Xa, other (sx ? Xb : Xm); site b: own Xb, other (sx ? Xp : Xa)
-  const int Xoa = sx ? Xb : Xm, Xob = sx ? Xp : Xa;
+  const V2 v00 = *reinterpret_cast<const V2*>(r00 + j0), v01 = *reinterpret_cast<const V2*>(r01 + j0);
+  const V2 v10 = *reinterpret_cast<const V2*>(r10 + j0), v11 = *reinterpret_cast<const V2*>(r11 + j0);
+  const T u00 = r00[Xo], u01 = r01[Xo], u10 = r10[Xo], u11 = r11[Xo];
+  // site a: own column j0, other (sx ? j0+1 : the outer one); site b: own j0+1, other
+  // (sx ? the outer one : j0)
   const T q = T(0.75), o = T(0.25);
-  const T pa0 = q * (q * r00[Xa] + o * r00[Xoa]) + o * (q * r01[Xa] + o * r01[Xoa]);
-  const T pa1 = q * (q * r10[Xa] + o * r10[Xoa]) + o * (q * r11[Xa] + o * r11[Xoa]);
-  const T pb0 = q * (q * r00[Xb] + o * r00[Xob]) + o * (q * r01[Xb] + o * r01[Xob]);
-  const T pb1 = q * (q * r10[Xb] + o * r10[Xob]) + o * (q * r11[Xb] + o * r11[Xob]);
+  auto w = [&](const V2& v, T u, T& a, T& b) {
+    a = q * v.x + o * (sx ? v.y : u);
+    b = q * v.y + o * (sx ? u : v.x);
+  };
+  T a00, b00, a01, b01, a10, b10, a11, b11;
+  w(v00, u00, a00, b00);
+  w(v01, u01, a01, b01);
+  w(v10, u10, a10, b10);
+  w(v11, u11, a11, b11);
+  const T pa0 = q * a00 + o * a01, pa1 = q * a10 + o * a11;
+  const T pb0 = q * b00 + o * b01, pb1 = q * b10 + o * b11;
   xv.x += wz0 * pa0 + wz1 * pa1;
   xv.y += wz0 * pb0 + wz1 * pb1;
   *reinterpret_cast<V2*>(X + 2 * t) = xv;
@@ -672,10 +696,11 @@ hipError_t launch_prolong0(T* xr, T* xb, const T* e, int nxf, int nyf, int nzf, 
   const uint32_t Nc = (uint32_t)(nxf / 2) * (nyf / 2) * (nzf / 2);
   colours &= 3;
   if (colours == 0) return hipSuccess;
-  if ((nxf / 2) % 2 == 0) {
+  if ((nxf / 2) % 2 == 0 && ((uintptr_t)e & 15) == 0) {
     dim3 grid(blocks_for(nsite / 2), ncomp, colours == 3 ? 2 : 1);
     k_prolong0_pair<T><<<grid, TPB, 0, s>>>(xr, xb, e, nxf, nyf, nzf, nsite / 2, Nc,
-                                            colours == 2 ? 1 : 0);
+                                            colours == 2 ? 1 : 0, ilog2_exact((uint32_t)nxf / 4),
+                                            ilog2_exact((uint32_t)nyf));
     return hipGetLastError();
   }
   dim3 grid(blocks_for(nsite), ncomp, colours == 3 ? 2 : 1);

@@ -45,10 +45,10 @@ def _announce(msg):
 
 
 # ----------------------------------------------------------------------------- components
-# (12,8,6), (4,2,1): two sites per thread; (10,6,5), (2,4,3): one pair per Philox call over odd
-# rows; the rest four sites per thread: (16,8,6) waves across planes, (24,6,5) row and plane
-# counts not powers of two, (8,4,1) both walls on one plane, (32,32,4) and (64,16,9) every wave
-# in one plane, the latter with a ragged last work-group
+# (10,6,5), (2,4,3): odd colour rows, the generic form; every other case one 16-byte vector per
+# thread: (12,8,6), (16,8,6) waves across planes, (24,6,5) row and plane counts not powers of
+# two, (4,2,1), (8,4,1) both walls on one plane, (32,32,4) and (64,16,9) every wave in one
+# plane, the latter with a ragged last work-group
 @pytest.mark.parametrize("dims,ncomp", [((12, 8, 6), 2), ((10, 6, 5), 1), ((4, 2, 1), 1),
                                         ((2, 4, 3), 3), ((16, 8, 6), 2), ((24, 6, 5), 2),
                                         ((8, 4, 1), 1), ((32, 32, 4), 1), ((64, 16, 9), 3)])
@@ -101,7 +101,8 @@ def test_block_pass(dims, levels, level, noise):
             assert _relerr(got[c], xo) <= RTOL
 
 
-@pytest.mark.parametrize("dims,levels", [((16, 16, 12), 3), ((16, 16, 8), 4), ((12, 8, 6), 2)])
+@pytest.mark.parametrize("dims,levels", [((16, 16, 12), 3), ((16, 16, 8), 4), ((12, 8, 6), 2),
+                                         ((24, 12, 10), 2)])
 def test_transfers(dims, levels):
     _announce("transfers %s L=%d" % (dims, levels))
     ncomp = 2
