@@ -79,7 +79,8 @@ def test_refined_chain_16cubed_200_cycles():
 
 @pytest.mark.parametrize("dims,ncomp,levels,coarsest", [
     ((8, 8, 16), 3, 3, "cholesky"), ((12, 8, 6), 2, 2, "cholesky"),
-    ((32, 32, 16), 1, 4, "smooth"), ((6, 4, 3), 1, 1, "smooth"), ((32, 16, 8), 1, 0, "cholesky")])
+    ((32, 32, 16), 1, 4, "smooth"), ((6, 4, 3), 1, 1, "smooth"), ((32, 16, 8), 1, 0, "cholesky"),
+    ((24, 12, 10), 2, 2, "cholesky")])  # 16-byte colour passes over 3 (FP32) / 6 (FP64) per row
 def test_refined_chain_shapes(dims, ncomp, levels, coarsest):
     _refined_chain(dims, ncomp, levels, 6, 31, kT=1.3, coarsest=coarsest, coarsest_max=64)
 
