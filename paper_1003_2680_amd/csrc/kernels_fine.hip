@@ -104,10 +104,12 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_vec(T* __restrict__ xc, const T
   const uint32_t ic = S * t;          // row * nh + S jt
   const uint32_t rb = ic - S * jt;    // row * nh
   const uint32_t xs = (y + z + (uint32_t)colour) & 1u;
+  // 16-byte vector <-> S scalars by value copies (no type punning of registers)
   auto ld = [&](uint32_t e) {
-    T v[S];
-    *reinterpret_cast<V*>(v) = *reinterpret_cast<const V*>(ob + e * W);
-    return *reinterpret_cast<const Arr<T, S>*>(v);
+    const V t = *reinterpret_cast<const V*>(ob + e * W);
+    Arr<T, S> a;
+    __builtin_memcpy(a.v, &t, sizeof(V));
+    return a;
   };
 
   // own row: the S entries and the one beyond on the side the x-neighbours lie
@@ -124,8 +126,8 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_vec(T* __restrict__ xc, const T
   const Arr<T, S> u = ld(ic + (top ? 0u : plane)), d = ld(ic - (bottom ? 0u : plane));
   Arr<T, S> b;
   if (HAS_B) {
-    *reinterpret_cast<V*>(b.v) =
-        *reinterpret_cast<const V*>(reinterpret_cast<const char*>(bc + base) + ic * W);
+    const V t = *reinterpret_cast<const V*>(reinterpret_cast<const char*>(bc + base) + ic * W);
+    __builtin_memcpy(b.v, &t, sizeof(V));
   }
   const int nw = (int)top + (int)bottom;
   const T wu = top ? T(0) : T(1), wd = bottom ? T(0) : T(1);
@@ -162,8 +164,9 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_vec(T* __restrict__ xc, const T
     if (NOISE) v = fma(sgm, zn[k], v);
     out[k] = v;
   }
-  *reinterpret_cast<V*>(reinterpret_cast<char*>(xc + base) + ic * W) =
-      *reinterpret_cast<const V*>(out);
+  V ov;
+  __builtin_memcpy(&ov, out, sizeof(V));
+  *reinterpret_cast<V*>(reinterpret_cast<char*>(xc + base) + ic * W) = ov;
 }
 
 // Generic colour pass (any even nx): thread q owns colour sites 2q and 2q+1 (one Philox call).
