@@ -53,11 +53,28 @@ enum { SMG_COARSEST_CHOLESKY = 0, SMG_COARSEST_SMOOTH = 1 };
 enum { SMG_FP64 = 0, SMG_FP32_REFINED = 1 };
 enum { SMG_OUT_F64 = 0, SMG_OUT_F32 = 1 };
 
-/* Grid: nx, ny even (red-black periodicity), nz >= 1, ncomp in [1, 255], h > 0, kT >= 0. */
+/* Boundary condition of one axis (Sec. 2: the fluid is periodic along the walls and satisfies
+ * u = 0 on the no-slip walls; Sec. "Spatially Adaptive Discretizations": the discrete operator
+ * takes the boundary through ghost cells).
+ *   SMG_BC_DEFAULT         the problem's own condition on that axis: periodic on x and y,
+ *                          no-slip walls on the z faces (so a zero-initialised descriptor
+ *                          describes the wall-bounded problem).
+ *   SMG_BC_PERIODIC        periodic axis.
+ *   SMG_BC_DIRICHLET_FACE  homogeneous Dirichlet (no-slip) walls on the two cell faces that
+ *                          bound the axis, through an antisymmetric ghost cell (u_ghost =
+ *                          -u_wall-cell), so the wall-layer diagonal is 7/h^2.
+ * Implemented combination: x and y periodic, z Dirichlet-face (the wall-bounded channel);
+ * any other combination is rejected with SMG_EINVAL (a fully periodic grid has the singular
+ * constant mode, so it has no Gaussian law with covariance A^-1). */
+enum { SMG_BC_DEFAULT = 0, SMG_BC_PERIODIC = 1, SMG_BC_DIRICHLET_FACE = 2 };
+
+/* Grid: nx, ny even (red-black periodicity), nz >= 1, ncomp in [1, 255], h > 0, kT >= 0;
+ * bc_x, bc_y, bc_z one of SMG_BC_* per axis (see above). */
 typedef struct {
   int32_t nx, ny, nz, ncomp;
   double h;
   double kT;
+  int32_t bc_x, bc_y, bc_z;
 } smg_grid_desc;
 
 /* Cycle parameters (Alg. 3 V(nu1, nu2); the paper leaves depth and coarsest handling open).
@@ -106,7 +123,8 @@ typedef struct smg_hierarchy smg_hierarchy;
  * 1D recurrences, the 2x2x2 block factors of every Galerkin level and the dense Cholesky
  * factor of the coarsest level.  *out receives a host object owned by the caller (free it
  * with smg_destroy_hierarchy).  No device work.  Errors: SMG_EINVAL for unsupported
- * shapes (nx or ny odd, levels not reachable, coarsest above 4096 unknowns). */
+ * shapes (nx or ny odd, levels not reachable, coarsest above 4096 unknowns) or boundary
+ * conditions other than periodic x, y and Dirichlet-face z. */
 int smg_create_hierarchy(const smg_grid_desc* desc, const smg_cycle_params* params,
                          smg_hierarchy** out);
 

@@ -62,24 +62,14 @@ def stationary_covariance(T, Sigma):
 
 
 def autocorrelation(series, max_lag):
-    """Normalised autocorrelation of a scalar series for lags 0..max_lag."""
+    """Normalised sample autocorrelation of a scalar series for lags 0..max_lag: the lag-k
+    sample autocovariance (1/n) sum_t (s_t - mean)(s_{t+k} - mean), with the full-length 1/n
+    weight at every lag, divided by the lag-0 value (the estimator of the lag-k correlation
+    of Sec. "Stochastic Iterative Methods")."""
     s = np.asarray(series, dtype=np.float64)
     s = s - s.mean()
     var = np.dot(s, s) / s.size
     return np.array([np.dot(s[:s.size - k], s[k:]) / s.size / var for k in range(max_lag + 1)])
-
-
-def integrated_autocorrelation_time(series, max_lag=None):
-    """tau_int = 1/2 + sum_k rho(k), summed until rho first drops below zero."""
-    s = np.asarray(series)
-    max_lag = max_lag or max(1, s.size // 10)
-    rho = autocorrelation(s, max_lag)
-    tau = 0.5
-    for k in range(1, rho.size):
-        if rho[k] <= 0.0:
-            break
-        tau += rho[k]
-    return tau
 
 
 def extract_linear_part(mg):

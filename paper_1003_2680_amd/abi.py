@@ -29,6 +29,9 @@ SMG_TILE_AUTO = 0
 SMG_TILE_4X4 = 1
 SMG_TILE_4X2 = 2
 SMG_TILE_8X4 = 3
+SMG_BC_DEFAULT = 0
+SMG_BC_PERIODIC = 1
+SMG_BC_DIRICHLET_FACE = 2
 
 ERROR_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_ENOTCONV",
                -4: "SMG_ENONFINITE", -5: "SMG_EHIP", -6: "SMG_ESTATE"}
@@ -47,7 +50,8 @@ EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
 
 class GridDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("ncomp", ctypes.c_int32), ("h", ctypes.c_double), ("kT", ctypes.c_double)]
+                ("ncomp", ctypes.c_int32), ("h", ctypes.c_double), ("kT", ctypes.c_double),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32)]
 
 
 class CycleParams(ctypes.Structure):

@@ -58,7 +58,8 @@ class Hierarchy:
         if dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
-        self.desc = abi.GridDesc(nx, ny, nz, ncomp, h, kT)
+        self.desc = abi.GridDesc(nx, ny, nz, ncomp, h, kT, abi.SMG_BC_PERIODIC,
+                                 abi.SMG_BC_PERIODIC, abi.SMG_BC_DIRICHLET_FACE)
         mode = {"cholesky": abi.SMG_COARSEST_CHOLESKY, "smooth": abi.SMG_COARSEST_SMOOTH}[coarsest]
         prec = {"fp64": abi.SMG_FP64, "fp32_refined": abi.SMG_FP32_REFINED}[precision]
         self.params = abi.CycleParams(levels, nu1, nu2, coarsest_max, mode, prec, stride, burn_in)

@@ -739,9 +739,10 @@ int solve_impl(smg_hierarchy* hh, const Batch& bt, const void* f, void* u, doubl
                                        s));
       SMG_HIP(launch_sumsq(h.norm_d, h.part_d, v0.r, v0.n, nc, s));
     } else {
-      // a level 0 that is drawn exactly has no residual buffer: u serves as scratch
-      SMG_HIP(launch_residual7_nat((double*)u, v0.x, v0.b, v0.nx, v0.ny, v0.nz, nc, h.desc.h, s));
-      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)u, v0.n, nc, s));
+      // a level 0 drawn exactly (one level) is stored in natural layout; its residual goes to
+      // its own buffer, never to u (which holds the exported solutions of finished chains)
+      SMG_HIP(launch_residual7_nat(v0.r, v0.x, v0.b, v0.nx, v0.ny, v0.nz, nc, h.desc.h, s));
+      SMG_HIP(launch_sumsq(h.norm_d, h.part_d, v0.r, v0.n, nc, s));
     }
     SMG_HIP(hipMemcpyAsync(rn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
     SMG_HIP(hipStreamSynchronize(s));
@@ -883,7 +884,7 @@ int smg_bind_workspace(smg_hierarchy* hh, void* dev_ptr, size_t bytes, void* str
       v.b = (double*)(ws + v.off_b);
     }
     if (!f32) {
-      v.r = v.kind == KIND_CHOL ? nullptr : (double*)(ws + v.off_r);
+      v.r = (v.kind == KIND_CHOL && l > 0) ? nullptr : (double*)(ws + v.off_r);
     } else {
       v.xf = (float*)(ws + v.off_xf);
       v.bf = (float*)(ws + v.off_bf);

@@ -150,6 +150,15 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
     err = "ncomp must be in [1,255], h > 0, kT >= 0";
     return SMG_EINVAL;
   }
+  {
+    auto is = [](int32_t bc, int32_t want) { return bc == SMG_BC_DEFAULT || bc == want; };
+    if (!is(d.bc_x, SMG_BC_PERIODIC) || !is(d.bc_y, SMG_BC_PERIODIC) ||
+        !is(d.bc_z, SMG_BC_DIRICHLET_FACE)) {
+      err = "boundary conditions: only periodic x and y with Dirichlet-face (no-slip) walls "
+            "in z are implemented";
+      return SMG_EINVAL;
+    }
+  }
   if (p.levels < 0 || p.levels > 15 || p.nu1 < 0 || p.nu2 < 0 || p.nu1 + p.nu2 > 255 ||
       p.stride < 1 || p.burn_in < 0 || p.coarsest_max < 1 || p.coarsest_max > 4096 ||
       (p.coarsest_mode != SMG_COARSEST_CHOLESKY && p.coarsest_mode != SMG_COARSEST_SMOOTH) ||
@@ -332,7 +341,9 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
     if (!f32) {
       v.off_x = take(n * sizeof(double));
       v.off_b = take(n * sizeof(double));
-      if (v.kind != KIND_CHOL) v.off_r = take(n * sizeof(double));
+      // level 0 always has a residual buffer (the solve's norms); a drawn-exact level 0 (one
+      // level) needs it for nothing else
+      if (v.kind != KIND_CHOL || l == 0) v.off_r = take(n * sizeof(double));
     } else {
       if (l == 0) {
         v.off_x = take(n * sizeof(double));

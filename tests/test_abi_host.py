@@ -151,6 +151,24 @@ def test_invalid_params_rejected(lib):
     assert rc == abi.SMG_EINVAL
 
 
+def test_boundary_conditions(lib):
+    """The wall-bounded channel (periodic x, y; Dirichlet-face z) is accepted spelled out or
+    by the zero defaults; every other combination is rejected with SMG_EINVAL."""
+    prm = abi.CycleParams(0, 2, 2, 512, 0, 0, 1, 0)
+    P, D, DEF = abi.SMG_BC_PERIODIC, abi.SMG_BC_DIRICHLET_FACE, abi.SMG_BC_DEFAULT
+    ok = [(DEF, DEF, DEF), (P, P, D), (DEF, P, D), (P, DEF, DEF)]
+    bad = [(P, P, P), (D, P, D), (P, D, D), (P, P, 7), (-1, P, D), (D, D, D)]
+    for bc, want in [(b, abi.SMG_OK) for b in ok] + [(b, abi.SMG_EINVAL) for b in bad]:
+        desc = abi.GridDesc(8, 8, 8, 1, 1.0, 1.0, *bc)
+        hd = ctypes.c_void_p()
+        rc = lib.smg_create_hierarchy(ctypes.byref(desc), ctypes.byref(prm), ctypes.byref(hd))
+        assert rc == want, (bc, rc)
+        if rc == abi.SMG_OK:
+            lib.smg_destroy_hierarchy(hd)
+        else:
+            assert "boundary" in lib.smg_last_error().decode()
+
+
 def test_unbound_hierarchy_refuses_work(lib):
     rc, hd = _create(lib, 8, 8, 8, levels=3)
     abi.check(rc)

@@ -121,3 +121,35 @@ def test_batch_errors():
         H.sample_batch(1, nchains=4, comps_per_chain=1)   # table of another shape
     assert e.value.code == SMG_ESTATE
     assert SMG_EINVAL == -1
+
+
+def test_batch_solve_one_level_cholesky_chains_finish_apart():
+    """One-level hierarchy (level 0 drawn exactly by the dense Cholesky factor): a chain that
+    reaches rtol a cycle before the others keeps its exported solution.  rtol is set between
+    the two chains' relative residuals after one cycle (read from solves alone), so one chain
+    stops after cycle 1 while the other runs on; the stopped chain's u must equal its solve
+    alone bit for bit (the residual passes of later cycles go to the library's own buffer)."""
+    from paper_1003_2680_amd.inputs import gaussian_field
+    _announce("batch solve one-level cholesky, chains finishing apart")
+    dims = (8, 8, 8)
+    f = gaussian_field((2, dims[2], dims[1], dims[0]), 21)
+    f[1] += 50.0 * np.cos(np.arange(8) * np.pi / 4.0)[None, None, :]  # another residual floor
+    fd = torch.from_numpy(f).cuda()
+    rel = []
+    for c in range(2):
+        H = _hier(*dims, ncomp=1, levels=1)
+        _, _, r1 = H.solve(fd[c:c + 1].contiguous(), rtol=0.0, max_cycles=1,
+                           raise_on_notconv=False)
+        rel.append(r1)
+    if rel[0] == rel[1]:
+        pytest.skip("equal one-cycle residuals; no rtol separates the chains")
+    lo = int(np.argmin(rel))
+    rtol = float(np.sqrt(rel[0] * rel[1]))
+    HB = _hier(*dims, ncomp=2, levels=1)
+    u, infos = HB.solve_batch(fd, nchains=2, comps_per_chain=1, rtol=rtol, max_cycles=3,
+                              raise_on_notconv=False)
+    assert infos[lo][0] == 1
+    H = _hier(*dims, ncomp=1, levels=1)
+    ul, cyc, _ = H.solve(fd[lo:lo + 1].contiguous(), rtol=rtol, max_cycles=1)
+    assert cyc == 1 and torch.equal(ul, u[lo:lo + 1]), "stopped chain's solution overwritten"
+    assert float(ul.abs().max()) > 1e-3  # a solution, not a residual of roundoff size

@@ -72,3 +72,40 @@ def test_gauss_seidel_decorrelates_slower_than_multigrid():
     mg = exact_lag_correlation(extract_linear_part(StochasticMG(*dims, levels=2)), C, phi, 3)
     assert gs[1] > 0.3 and abs(mg[1]) < 0.1
     assert np.all(np.diff(gs) < 0)
+
+
+def test_autocorrelation_hand_computed_series():
+    """s = (1, 2, 3, 4): deviations (-1.5, -0.5, 0.5, 1.5), lag-0 sum 5/4 with the 1/n
+    weight; lag-1 sum (0.75 - 0.25 + 0.75)/4, lag-2 (-0.75 - 0.75)/4, lag-3 -2.25/4, so the
+    normalised values are 1, 1/4, -3/10, -9/20 (dividing by n - k instead, or skipping the
+    mean, gives other numbers)."""
+    from oracle.analysis import autocorrelation
+    r = autocorrelation([1.0, 2.0, 3.0, 4.0], 3)
+    assert np.allclose(r, [1.0, 0.25, -0.3, -0.45], rtol=0, atol=1e-15)
+    # a shifted and scaled copy has the same correlations; a constant offset is removed
+    assert np.allclose(autocorrelation([7.0, 9.0, 11.0, 13.0], 3), r, rtol=0, atol=1e-15)
+    # alternating series: lag-k correlation (-1)^k (n - k)/n
+    alt = np.array([1.0, -1.0] * 5)
+    ra = autocorrelation(alt, 4)
+    assert np.allclose(ra, [(-1) ** k * (10 - k) / 10 for k in range(5)], rtol=0, atol=1e-15)
+
+
+def test_autocorrelation_of_simulated_ar1_matches_exact():
+    """x' = a x + sqrt(1 - a^2) n, simulated directly: the estimator's lag-k values match the
+    exact a^k (exact_lag_correlation of the scalar chain) within four Bartlett standard
+    deviations sqrt((1 + a^2)(1 - a^(2k)) / (1 - a^2) - 2k a^(2k)) / sqrt(n)."""
+    from oracle.analysis import autocorrelation
+    a, n = 0.8, 200000
+    rng = np.random.default_rng(11)
+    e = rng.standard_normal(n) * np.sqrt(1 - a * a)
+    x = np.empty(n)
+    v = rng.standard_normal()
+    for t in range(n):
+        v = a * v + e[t]
+        x[t] = v
+    est = autocorrelation(x, 6)
+    exact = exact_lag_correlation(np.array([[a]]), np.array([[1.0]]), np.array([1.0]), 6)
+    assert np.allclose(exact, a ** np.arange(7), rtol=1e-14)
+    for k in range(1, 7):
+        var = ((1 + a * a) * (1 - a ** (2 * k)) / (1 - a * a) - 2 * k * a ** (2 * k)) / n
+        assert abs(est[k] - exact[k]) < 4 * np.sqrt(var), (k, est[k], exact[k])
