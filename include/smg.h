@@ -215,6 +215,23 @@ int smg_solve_batch(smg_hierarchy* h, int32_t nchains, int32_t comps_per_chain, 
                     void* u, double rtol, int32_t max_cycles, void* stream,
                     smg_solve_info* infos);
 
+/* ---- Allocation-free sampling (for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). ----
+ * smg_sample_field_static: smg_sample_field on a hierarchy whose workspace is the library's own
+ * device array of SMG_STATIC_SCRATCH_BYTES (one copy per device, held until the process ends)
+ * instead of caller-bound memory; smg_bind_workspace is not needed.  It calls no hipMalloc,
+ * hipFree or allocating library routine.  state and out are the caller's, as for
+ * smg_sample_field, and results are the same bit for bit.  Every call on a device shares that
+ * device's array, which keeps the last call's contents: the tables of a hierarchy are uploaded
+ * (and the stream synchronised) when another hierarchy used the array last; calls that overlap
+ * on one device (different streams or threads with work in flight) race on the array and must
+ * be serialised by the caller.  A hierarchy bound with smg_bind_workspace keeps that binding
+ * for its other calls.  Errors: SMG_ENOMEM when the hierarchy's workspace_bytes exceeds
+ * SMG_STATIC_SCRATCH_BYTES; otherwise as smg_sample_field. */
+#define SMG_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int smg_sample_field_static(smg_hierarchy* h, int64_t n, uint64_t seed, uint64_t first_cycle,
+                            void* state, void* out, int32_t out_dtype, void* stream);
+
 /* Frees the host object.  Never touches the caller's device memory. */
 void smg_destroy_hierarchy(smg_hierarchy* h);
 

@@ -32,6 +32,7 @@ SMG_TILE_8X4 = 3
 SMG_BC_DEFAULT = 0
 SMG_BC_PERIODIC = 1
 SMG_BC_DIRICHLET_FACE = 2
+SMG_STATIC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 ERROR_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_ENOTCONV",
                -4: "SMG_ENONFINITE", -5: "SMG_EHIP", -6: "SMG_ESTATE"}
@@ -45,7 +46,7 @@ EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
             "smg_composite_create", "smg_composite_get_info", "smg_composite_bind",
             "smg_composite_cycle", "smg_composite_sample", "smg_composite_residual",
             "smg_composite_solve", "smg_composite_debug_pass", "smg_composite_debug_base_pass",
-            "smg_composite_debug_row", "smg_composite_destroy"]
+            "smg_composite_debug_row", "smg_composite_destroy", "smg_sample_field_static"]
 
 
 class GridDesc(ctypes.Structure):
@@ -121,6 +122,8 @@ def load():
                               ctypes.c_int32, P], ctypes.c_int),
         "smg_solve": ([H, P, P, ctypes.c_double, ctypes.c_int32, P, ctypes.POINTER(SolveInfo)],
                       ctypes.c_int),
+        "smg_sample_field_static": ([H, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, P, P,
+                                     ctypes.c_int32, P], ctypes.c_int),
         "smg_destroy_hierarchy": ([H], None),
         "smg_last_error": ([], ctypes.c_char_p),
         "smg_debug_smooth": ([H, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_uint64,

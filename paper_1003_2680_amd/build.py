@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libsmg.so")
 SOURCES = ["plan.cpp", "capi.cpp", "kernels_fine.hip", "kernels_gal.hip", "kernels_util.hip",
-           "kernels_stats.hip", "capi_comp.cpp", "kernels_comp.hip"]
+           "kernels_stats.hip", "capi_comp.cpp", "kernels_comp.hip", "capi_static.hip"]
 ARCH = os.environ.get("SMG_OFFLOAD_ARCH", "gfx950")
 
 

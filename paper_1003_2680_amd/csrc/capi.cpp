@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -23,10 +24,6 @@
 
 #include "kernels.hpp"
 #include "smg_internal.hpp"
-
-struct smg_hierarchy {
-  smg::Hierarchy h;
-};
 
 namespace smg {
 namespace {
@@ -814,6 +811,76 @@ int solve_impl(smg_hierarchy* hh, const Batch& bt, const void* f, void* u, doubl
 
 void set_error(const std::string& msg) { g_err = msg; }
 
+// Points every device field and table of the hierarchy into ws (at least ws_bytes, 256-byte
+// aligned, on the current device); with `upload` also copies the operator tables, factors and
+// bottom-kernel descriptors there on stream s and synchronises it.  Without `upload` only the
+// host-side pointers change: ws must already hold this hierarchy's tables.
+int bind_impl(Hierarchy& h, char* ws, bool upload, hipStream_t s) {
+  const bool f32 = refined(h);
+  SMG_HIP(hipGetDevice(&h.device));
+  for (size_t l = 0; l < h.lv.size(); ++l) {
+    Level& v = h.lv[l];
+    if (!f32 || l == 0) {
+      v.x = (double*)(ws + v.off_x);
+      v.b = (double*)(ws + v.off_b);
+    }
+    if (!f32) {
+      v.r = (v.kind == KIND_CHOL && l > 0) ? nullptr : (double*)(ws + v.off_r);
+    } else {
+      v.xf = (float*)(ws + v.off_xf);
+      v.bf = (float*)(ws + v.off_bf);
+      v.rf = v.kind == KIND_CHOL ? nullptr : (float*)(ws + v.off_rf);
+    }
+    if (v.kind == KIND_BLOCK) {
+      v.s1d_d = ws + v.off_s1d;
+      v.zt_d = ws + v.off_zt;
+      v.bfac_d = ws + v.off_bfac;
+      v.noise_d = ws + v.off_noise;
+      if (upload) {
+        if (f32) SMG_TRY(upload_tables<float>(v, ws, s));
+        else SMG_TRY(upload_tables<double>(v, ws, s));
+      }
+    }
+  }
+  if (h.nc > 0) {
+    h.ainv_d = (double*)(ws + h.off_ainv);
+    h.w_d = (double*)(ws + h.off_w);
+    if (upload) {
+      SMG_HIP(hipMemcpyAsync(h.ainv_d, h.ainv.data(), h.ainv.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      SMG_HIP(hipMemcpyAsync(h.w_d, h.w.data(), h.w.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+    }
+  }
+  h.part_d = (double*)(ws + h.off_part);
+  h.norm_d = (double*)(ws + h.off_norm);
+  h.chains_d = (ChainKey*)(ws + h.off_chains);
+  // the chain table and mode tables are workspace contents: taken as absent after a re-bind
+  h.chains_set = 0;
+  h.modes_valid = false;
+  if (h.bottom >= 0) {
+    h.botargs_d = (BotArgs*)(ws + h.off_botargs);
+    if (upload) {
+      BotArgs ba = make_botargs(h);
+      SMG_HIP(hipMemcpyAsync(h.botargs_d, &ba, sizeof(BotArgs), hipMemcpyHostToDevice, s));
+      SMG_HIP(hipStreamSynchronize(s));  // ba dies on return
+    }
+  }
+  if (upload) SMG_HIP(hipStreamSynchronize(s));
+  h.ws = ws;
+  return SMG_OK;
+}
+
+int sample_field_impl(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
+                      void* state, void* out, int32_t out_dtype, void* stream) {
+  if (n > 0 && !out) {
+    set_error("out is null");
+    return SMG_EINVAL;
+  }
+  return sample_impl(hh, Batch{}, nullptr, nullptr, n, seed, first_cycle, state, out, out_dtype,
+                     nullptr, 0, nullptr, nullptr, stream);
+}
+
 }  // namespace smg
 
 using namespace smg;
@@ -832,6 +899,8 @@ int smg_create_hierarchy(const smg_grid_desc* desc, const smg_cycle_params* para
     set_error("host allocation failed");
     return SMG_ENOMEM;
   }
+  static std::atomic<uint64_t> next_uid{1};
+  hh->h.uid = next_uid.fetch_add(1);
   std::string err;
   int rc = build_plan(*desc, *params, hh->h, err);
   if (rc != SMG_OK) {
@@ -873,60 +942,12 @@ int smg_bind_workspace(smg_hierarchy* hh, void* dev_ptr, size_t bytes, void* str
     set_error("workspace too small: need " + std::to_string(h.ws_bytes) + " bytes");
     return SMG_ENOMEM;
   }
-  hipStream_t s = (hipStream_t)stream;
-  char* ws = (char*)dev_ptr;
-  const bool f32 = refined(h);
-  SMG_HIP(hipGetDevice(&h.device));
-  for (size_t l = 0; l < h.lv.size(); ++l) {
-    Level& v = h.lv[l];
-    if (!f32 || l == 0) {
-      v.x = (double*)(ws + v.off_x);
-      v.b = (double*)(ws + v.off_b);
-    }
-    if (!f32) {
-      v.r = (v.kind == KIND_CHOL && l > 0) ? nullptr : (double*)(ws + v.off_r);
-    } else {
-      v.xf = (float*)(ws + v.off_xf);
-      v.bf = (float*)(ws + v.off_bf);
-      v.rf = v.kind == KIND_CHOL ? nullptr : (float*)(ws + v.off_rf);
-    }
-    if (v.kind == KIND_BLOCK) {
-      if (f32) SMG_TRY(upload_tables<float>(v, ws, s));
-      else SMG_TRY(upload_tables<double>(v, ws, s));
-    }
-  }
-  if (h.nc > 0) {
-    h.ainv_d = (double*)(ws + h.off_ainv);
-    h.w_d = (double*)(ws + h.off_w);
-    SMG_HIP(hipMemcpyAsync(h.ainv_d, h.ainv.data(), h.ainv.size() * sizeof(double),
-                           hipMemcpyHostToDevice, s));
-    SMG_HIP(hipMemcpyAsync(h.w_d, h.w.data(), h.w.size() * sizeof(double),
-                           hipMemcpyHostToDevice, s));
-  }
-  h.part_d = (double*)(ws + h.off_part);
-  h.norm_d = (double*)(ws + h.off_norm);
-  h.chains_d = (ChainKey*)(ws + h.off_chains);
-  h.chains_set = 0;
-  h.modes_valid = false;
-  BotArgs ba{};
-  if (h.bottom >= 0) {
-    h.botargs_d = (BotArgs*)(ws + h.off_botargs);
-    ba = make_botargs(h);
-    SMG_HIP(hipMemcpyAsync(h.botargs_d, &ba, sizeof(BotArgs), hipMemcpyHostToDevice, s));
-  }
-  SMG_HIP(hipStreamSynchronize(s));
-  h.ws = ws;
-  return SMG_OK;
+  return bind_impl(h, (char*)dev_ptr, true, (hipStream_t)stream);
 }
 
 int smg_sample_field(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
                      void* state, void* out, int32_t out_dtype, void* stream) {
-  if (n > 0 && !out) {
-    set_error("out is null");
-    return SMG_EINVAL;
-  }
-  return sample_impl(hh, Batch{}, nullptr, nullptr, n, seed, first_cycle, state, out, out_dtype,
-                     nullptr, 0, nullptr, nullptr, stream);
+  return sample_field_impl(hh, n, seed, first_cycle, state, out, out_dtype, stream);
 }
 
 int smg_sample_stats(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,

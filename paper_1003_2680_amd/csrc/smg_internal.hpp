@@ -50,6 +50,7 @@ struct Level {
 };
 
 struct Hierarchy {
+  uint64_t uid = 0;              // unique per created hierarchy (never reused in a process)
   smg_grid_desc desc{};
   smg_cycle_params prm{};
   std::vector<Level> lv;
@@ -96,4 +97,15 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
 // error helpers (capi.cpp)
 void set_error(const std::string& msg);
 
+// capi.cpp: point (and with `upload` fill) the hierarchy's device fields and tables at ws;
+// the sampling path of smg_sample_field
+int bind_impl(Hierarchy& h, char* ws, bool upload, hipStream_t s);
+int sample_field_impl(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
+                      void* state, void* out, int32_t out_dtype, void* stream);
+
 }  // namespace smg
+
+// The opaque handle of the C-ABI.
+struct smg_hierarchy {
+  smg::Hierarchy h;
+};
