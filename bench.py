@@ -237,23 +237,25 @@ def measure(precision, args, fs, dev):
                       device=dev)
     ms, lat, obs, state = run_batch(H, C, args.steps, args.warmup, SAMPLES_PER_STEP, out)
     res = {"ms_per_step": ms, "lat": lat, "obs": obs}
-    if precision == "fp64":
-        # per-launch kernel times: HIP events bracketing each sweep's colour passes (or the
-        # bottom launch) on the batch's stream, over the same number of further steps
-        cyc_timed = args.steps * SAMPLES_PER_STEP
-        kern = {}
-        for name in ("fine_pass", "level1_block_pass", "bottom"):
-            H.kernel_timing(True, name)
-            torch.cuda.synchronize()
-            for _ in range(args.steps):
-                H.sample_batch(SAMPLES_PER_STEP, nchains=C, comps_per_chain=NCOMP, state=state,
-                               out=out)
-            torch.cuda.synchronize()
-            n_l, k_ms = H.kernel_timing_read()
-            H.kernel_timing(False, name)
-            kern[name] = {"launches": n_l, "avg_launch_s": k_ms / 1e3 / max(n_l, 1),
-                          "per_cycle_s": k_ms / 1e3 / cyc_timed}
-        res["kern"] = kern
+    # per-launch kernel times: HIP events bracketing each sweep's colour passes (or the
+    # bottom launch) on the batch's stream, over the same number of further steps (the
+    # FP32-refined form: its FP32 level-0 colour pass only)
+    cyc_timed = args.steps * SAMPLES_PER_STEP
+    kern = {}
+    names = ("fine_pass", "level1_block_pass", "bottom") if precision == "fp64" \
+        else ("fine_pass",)
+    for name in names:
+        H.kernel_timing(True, name)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            H.sample_batch(SAMPLES_PER_STEP, nchains=C, comps_per_chain=NCOMP, state=state,
+                           out=out)
+        torch.cuda.synchronize()
+        n_l, k_ms = H.kernel_timing_read()
+        H.kernel_timing(False, name)
+        kern[name] = {"launches": n_l, "avg_launch_s": k_ms / 1e3 / max(n_l, 1),
+                      "per_cycle_s": k_ms / 1e3 / cyc_timed}
+    res["kern"] = kern
     del H, out, state
     torch.cuda.empty_cache()
     Hs = Hierarchy(NX, NY, NZ, ncomp=NCOMP, kT=1.0, levels=LEVELS, precision=precision)
@@ -547,7 +549,9 @@ def measure_serving(dev, stride, rate=200.0, n=300):
             "all_completed": bool(ok), "throughput_req_s": round(len(lat) / wall, 2),
             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-            "pools_created": pools, "evictions": srv.evictions}
+            "pools_created": pools, "evictions": srv.evictions,
+            "latency_from": "scheduled Poisson arrival",
+            "max_submit_lag_ms": round(srv.max_submit_lag * 1e3, 2)}
 
 
 def main():
@@ -685,6 +689,11 @@ def main():
             "rho_solve": round(r32["rho"], 5),
             "rho_obs_lag1_max": round(float(np.max(np.abs(lag1(r32["obs"])))), 4),
             "rel_rms_vs_fp64_2_cycles": float("%.3e" % rel_rms)}
+        # the FP32 level-0 colour pass of the inner cycle (b = the FP32 residual): read the
+        # other colour and this colour's b, write this colour, 4 B per value
+        line["fp32_refined"]["roofline"] = roof(
+            r32["kern"]["fine_pass"], "k_rb_pass (FP32 level-0 colour pass, 128^3, with b)",
+            nact * N0 * 4 * 3 // 2)
 
     if not args.no_hbm_point:
         line["hbm_point"] = measure_hbm_point(dev)

@@ -11,12 +11,20 @@
   others run joins at the next round in a free slot; a finished chain's slot is refilled
   immediately (the last active chain moves into it, so active slots stay contiguous).  Queued
   solves of a shape are solved together in one batched solve between rounds.
-* Each pool has its own host thread and HIP stream, so pools overlap on the device.
+* Each pool has its own host thread and HIP stream, so pools overlap on the device.  A pool is
+  built (host plan, workspace, table upload) on its own thread; requests routed to it wait in
+  its queue meanwhile.
+* Admission runs on the server's own thread: submitting a request only queues it, so the
+  thread that receives requests never waits for a plan, an upload, an eviction or the device.
+  A solve's right-hand side may come as a generator (`make_f`) that the pool calls on its own
+  stream.
 
 A sample request of k samples on seed s gets exactly what a hierarchy of one component with
 stride = burn_in = `stride` produces alone: samples at cycles 2*stride, 3*stride, ... of chain
 (s, first cycle 0).  A solve gets exactly the result of solving alone.  Latency is measured
-from arrival to the end of the round (or solve) that completes the request.
+from the request's arrival time (in the simulated stream: its scheduled Poisson arrival, not
+the moment the submitting thread got to it) to the end of the round (or solve) that completes
+it, so time spent queued anywhere is counted.
 """
 import collections
 import threading
@@ -30,10 +38,10 @@ from .api import Hierarchy, plan_bytes
 
 
 class Request:
-    __slots__ = ("rid", "dims", "kind", "k", "seed", "rtol", "f", "t_arrival", "t_done",
-                 "result", "info", "error")
+    __slots__ = ("rid", "dims", "kind", "k", "seed", "rtol", "f", "make_f", "t_arrival",
+                 "t_done", "result", "info", "error")
 
-    def __init__(self, rid, dims, kind, seed, k=1, rtol=1e-10, f=None):
+    def __init__(self, rid, dims, kind, seed, k=1, rtol=1e-10, f=None, make_f=None):
         self.rid = rid
         self.dims = tuple(int(d) for d in dims)
         self.kind = kind              # "sample" or "solve"
@@ -41,6 +49,7 @@ class Request:
         self.seed = int(seed)
         self.rtol = float(rtol)
         self.f = f                    # solve right-hand side, device float64 [nz, ny, nx]
+        self.make_f = make_f          # or a generator of it, called by the pool on its stream
         self.t_arrival = None
         self.t_done = None
         self.result = None            # samples [k, nz, ny, nx] float32, or u [nz, ny, nx]
@@ -62,13 +71,10 @@ class Pool:
     def __init__(self, server, dims):
         self.server = server
         self.dims = dims
-        S = server.slots
-        self.H = Hierarchy(*dims, ncomp=S, kT=server.kT, levels=0, nu1=2, nu2=2,
-                           stride=server.stride, precision=server.precision,
-                           device=server.device)
-        self.bytes = pool_bytes(dims, S, server.precision)
-        self.stream = torch.cuda.Stream(device=server.device)
-        self.state = torch.zeros(self.H.shape, dtype=torch.float64, device=server.device)
+        self.bytes = server.pool_bytes(dims)
+        self.H = None                          # built on the pool's own thread
+        self.stream = None
+        self.state = None
         self.chains = []                       # active sample chains, slot = index
         self._fresh = []                       # slots admitted since the last round
         self.samples = collections.deque()     # waiting sample requests
@@ -95,9 +101,20 @@ class Pool:
         self.thread.join()
 
     # ---------------------------------------------------------------- worker
+    def _build(self):
+        server = self.server
+        self.stream = torch.cuda.Stream(device=server.device)
+        with torch.cuda.stream(self.stream):
+            self.H = Hierarchy(*self.dims, ncomp=server.slots, kT=server.kT, levels=0, nu1=2,
+                               nu2=2, stride=server.stride, precision=server.precision,
+                               device=server.device)
+            self.state = torch.zeros(self.H.shape, dtype=torch.float64, device=server.device)
+        self.stream.synchronize()
+
     def _run(self):
         try:
             torch.cuda.set_device(self.server.device)
+            self._build()
             self._loop()
         except Exception as e:  # a dead worker must not leave requests pending
             with self.cv:
@@ -138,6 +155,9 @@ class Pool:
 
     def _solve(self, reqs):
         n = len(reqs)
+        for r in reqs:
+            if r.f is None:
+                r.f = r.make_f(r)   # drawn on this pool's stream
         f = torch.stack([r.f for r in reqs]).contiguous()
         u, infos = self.H.solve_batch(f, nchains=n, comps_per_chain=1, rtol=reqs[0].rtol,
                                       raise_on_notconv=False)
@@ -208,27 +228,48 @@ class Server:
         self.pools = collections.OrderedDict()   # dims -> Pool (LRU order)
         self.waiting = collections.deque()       # requests whose shape has no pool yet
         self.lock = threading.Lock()
+        self.admit_cv = threading.Condition(self.lock)
         self.done = []
         self.done_cv = threading.Condition()
         self.evictions = 0
+        self._bytes = {}                         # dims -> pool bytes (host planning, cached)
+        self._stop = False
+        self._admitter = threading.Thread(target=self._admit_loop, daemon=True)
+        self._admitter.start()
+
+    def pool_bytes(self, dims):
+        b = self._bytes.get(dims)
+        if b is None:
+            b = self._bytes[dims] = pool_bytes(dims, self.slots, self.precision)
+        return b
 
     def used_bytes(self):
         return sum(p.bytes for p in self.pools.values())
 
     def submit(self, req):
+        """Queue a request for admission (never blocks on the device or on planning)."""
         req.t_arrival = time.perf_counter() if req.t_arrival is None else req.t_arrival
         with self.lock:
             self.waiting.append(req)
-            self._dispatch()
+            self.admit_cv.notify()
+
+    def _admit_loop(self):
+        with self.lock:
+            while not self._stop:
+                if self.waiting:
+                    self._dispatch()
+                # woken by a submission or a completion (a pool may have gone idle)
+                self.admit_cv.wait(0.002 if self.waiting else None)
 
     def _dispatch(self):
-        """Route waiting requests to pools, creating pools inside the budget (lock held)."""
+        """Route waiting requests to pools, creating pools inside the budget (lock held, on
+        the admission thread)."""
         keep = collections.deque()
         while self.waiting:
             req = self.waiting.popleft()
             pool = self.pools.get(req.dims)
             if pool is None:
-                need = pool_bytes(req.dims, self.slots, self.precision)
+                need = self.pool_bytes(req.dims)
                 if need > self.budget:
                     req.error = "request does not fit the HBM budget"
                     self._complete(req)
@@ -251,34 +292,30 @@ class Server:
         self.waiting = keep
 
     def _complete(self, req):
-        # called from pool threads: never dispatches (an eviction joins pool threads); the
-        # submitting thread retries waiting requests in poll()
+        # called from pool threads (or the admission thread, lock held): never dispatches
+        # itself; waiting requests are retried by the admission thread, which polls while any
+        # wait
         req.t_done = time.perf_counter()
         with self.done_cv:
             self.done.append(req)
             self.done_cv.notify_all()
 
-    def poll(self):
-        """Retry the admission of waiting requests (a pool may have gone idle)."""
-        with self.lock:
-            if self.waiting:
-                self._dispatch()
-
     def wait(self, n, timeout=120.0, poll=0.002):
-        """Block until n requests completed (retrying admission of waiting ones)."""
+        """Block until n requests completed."""
         t_end = time.perf_counter() + timeout
         while True:
             with self.done_cv:
                 if len(self.done) >= n:
                     return True
                 self.done_cv.wait(poll)
-            with self.lock:
-                if self.waiting:
-                    self._dispatch()
             if time.perf_counter() > t_end:
                 return False
 
     def shutdown(self):
+        with self.lock:
+            self._stop = True
+            self.admit_cv.notify()
+        self._admitter.join()
         with self.lock:
             for p in self.pools.values():
                 p.shutdown()
@@ -301,22 +338,25 @@ def make_requests(n, rate, seed=7, nxy=(32, 64, 128, 256), nzs=(16, 32, 64, 128)
 
 
 def simulate(server, timed_requests, make_f, timeout=120.0):
-    """Submit requests at their arrival offsets (real time); returns the completed requests,
-    the wall time from the first arrival to the last completion and the latencies (s)."""
+    """Submit requests at their arrival offsets (real time).  A request's arrival time is its
+    scheduled time t0 + offset, whenever the submitting thread gets to it, so a late submission
+    still counts its delay; solve right-hand sides are drawn by the pools (make_f).  Returns
+    (all completed, wall time from the start to the last completion, latencies in s); the
+    largest lag of a submission behind its schedule is left in server.max_submit_lag (s)."""
     t0 = time.perf_counter()
+    lag = 0.0
     for off, req in timed_requests:
         while True:
             now = time.perf_counter() - t0
             if off <= now:
                 break
-            server.poll()
             time.sleep(min(0.002, off - now))
-        if req.kind == "solve" and req.f is None:
-            req.f = make_f(req)
-            # the pools use their own (non-blocking) streams
-            torch.cuda.current_stream().synchronize()
-        req.t_arrival = time.perf_counter()
+        if req.kind == "solve" and req.f is None and req.make_f is None:
+            req.make_f = make_f
+        req.t_arrival = t0 + off
+        lag = max(lag, time.perf_counter() - req.t_arrival)
         server.submit(req)
+    server.max_submit_lag = lag
     ok = server.wait(len(timed_requests), timeout=timeout)
     wall = time.perf_counter() - t0
     lat = np.array([r.t_done - r.t_arrival for r in server.done])
@@ -359,7 +399,8 @@ def main(argv=None):
                 if kinds["sample"] else None,
                 "solve_p50_ms": round(float(np.percentile(kinds["solve"], 50)) * 1e3, 2)
                 if kinds["solve"] else None,
-                "pools_created": len(srv.pools) + srv.evictions, "evictions": srv.evictions}
+                "pools_created": len(srv.pools) + srv.evictions, "evictions": srv.evictions,
+                "max_submit_lag_ms": round(srv.max_submit_lag * 1e3, 2)}
         srv.shutdown()
         torch.cuda.empty_cache()
         print(json.dumps(line), flush=True)

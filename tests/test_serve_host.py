@@ -7,6 +7,7 @@ import time
 
 import pytest
 
+torch = pytest.importorskip("torch")
 serve = pytest.importorskip("paper_1003_2680_amd.serve")
 
 
@@ -16,7 +17,7 @@ class FakePool:
     def __init__(self, server, dims):
         self.server = server
         self.dims = dims
-        self.bytes = serve.pool_bytes(dims, server.slots, server.precision)
+        self.bytes = server.pool_bytes(dims)
         self.q = collections.deque()
         self.cv = threading.Condition()
         self.busy = 0
@@ -59,25 +60,26 @@ class FakePool:
 
 
 def test_admission_eviction_and_completion(monkeypatch):
+    """Also: a submission never waits for planning or pool creation (the stand-in plan takes
+    0.1 s per shape and runs on the admission thread)."""
     sizes = {(16, 16, 8): 100, (32, 32, 8): 200, (16, 16, 16): 300, (64, 64, 64): 10 ** 9}
-    monkeypatch.setattr(serve, "pool_bytes", lambda dims, slots, prec: sizes[dims])
+    def slow_plan(dims, slots, prec):   # host planning that takes a while
+        time.sleep(0.1)
+        return sizes[dims]
+    monkeypatch.setattr(serve, "pool_bytes", slow_plan)
     monkeypatch.setattr(serve, "Pool", FakePool)
     FakePool.created = []
-    srv = serve.Server.__new__(serve.Server)
-    srv.device = None
-    srv.budget = 520          # any two of the three small pools, never all three
-    srv.slots, srv.stride, srv.precision, srv.kT = 4, 2, "fp32_refined", 1.0
-    srv.pools = collections.OrderedDict()
-    srv.waiting = collections.deque()
-    srv.lock = threading.Lock()
-    srv.done = []
-    srv.done_cv = threading.Condition()
-    srv.evictions = 0
+    # any two of the three small pools fit the budget, never all three
+    srv = serve.Server(budget_bytes=520, slots=4, stride=2, precision="fp32_refined",
+                       device=torch.device("cuda", 0))
     shapes = [(16, 16, 8), (32, 32, 8), (16, 16, 16)]
     reqs = [serve.Request(i, shapes[i % 3], "sample", seed=i) for i in range(30)]
     reqs.append(serve.Request(30, (64, 64, 64), "solve", seed=1))   # larger than the budget
+    t0 = time.perf_counter()
     for r in reqs:
         srv.submit(r)
+    # submitting only queues: the admission thread plans and creates pools
+    assert time.perf_counter() - t0 < 0.2
     assert srv.wait(len(reqs), timeout=20.0)
     srv.shutdown()
     assert len(srv.done) == len(reqs) and len({r.rid for r in srv.done}) == len(reqs)
