@@ -232,6 +232,47 @@ int smg_solve_batch(smg_hierarchy* h, int32_t nchains, int32_t comps_per_chain, 
 int smg_sample_field_static(smg_hierarchy* h, int64_t n, uint64_t seed, uint64_t first_cycle,
                             void* state, void* out, int32_t out_dtype, void* stream);
 
+/* ---- Uneven instances in one call (a workload of many grids of different sizes). ----
+ * smg_batch_run runs a list of operations on distinct bound hierarchies (each hierarchy at most
+ * once), all on `stream`:
+ *   SMG_OP_SAMPLE: smg_sample_field (nchains == 0: one chain of all components keyed by seed,
+ *     first_cycle) or smg_sample_batch without statistics (nchains >= 1: seeds/first_cycles
+ *     host [nchains], seeds NULL = continue the table); state, out, out_dtype, n as there
+ *     (out NULL: the cycles run without writing samples).
+ *   SMG_OP_SOLVE: smg_solve (nchains == 0) or smg_solve_batch (nchains >= 1) of f into u to
+ *     rtol within max_cycles; infos (host, [max(nchains, 1)], or NULL) filled.
+ * Sampling items run first, cycle by cycle in step (cycle k of every item before cycle k + 1 of
+ * any); then the solve items cycle in step until each has converged or run out of cycles.  In
+ * every cycle the levels that each hierarchy runs in its LDS-resident bottom launch (the levels
+ * of at most 4096 cells and the coarsest draw: Sec. "Stochastic Multigrid Methods", Alg. 3,
+ * below the tiled levels) are run for all items in as few launches as possible (one per sweep
+ * precision and noise setting, up to 16 hierarchies and 256 components each), instead of one
+ * latency-bound launch per hierarchy.  Every item's result is bit for bit that of its own call
+ * alone.  Without solve items the call is asynchronous (and can be captured in a graph); solve
+ * items synchronise the stream once per cycle for all of them.  status receives each item's
+ * return code; the function returns SMG_OK or the first failing item's code (SMG_EINVAL for a
+ * repeated hierarchy or unknown op, before any work). */
+enum { SMG_OP_SAMPLE = 0, SMG_OP_SOLVE = 1 };
+typedef struct {
+  smg_hierarchy* h;
+  int32_t op;
+  int32_t nchains, comps_per_chain;
+  int32_t out_dtype;
+  int64_t n;
+  uint64_t seed, first_cycle;
+  const uint64_t* seeds;
+  const uint64_t* first_cycles;
+  void* state;
+  void* out;
+  const void* f;
+  void* u;
+  double rtol;
+  int32_t max_cycles;
+  smg_solve_info* infos;
+  int32_t status;
+} smg_batch_item;
+int smg_batch_run(smg_batch_item* items, int32_t n_items, void* stream);
+
 /* Frees the host object.  Never touches the caller's device memory. */
 void smg_destroy_hierarchy(smg_hierarchy* h);
 

@@ -33,6 +33,8 @@ SMG_BC_DEFAULT = 0
 SMG_BC_PERIODIC = 1
 SMG_BC_DIRICHLET_FACE = 2
 SMG_STATIC_SCRATCH_BYTES = 64 * 1024 * 1024
+SMG_OP_SAMPLE = 0
+SMG_OP_SOLVE = 1
 
 ERROR_NAMES = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_ENOTCONV",
                -4: "SMG_ENONFINITE", -5: "SMG_EHIP", -6: "SMG_ESTATE"}
@@ -46,7 +48,8 @@ EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
             "smg_composite_create", "smg_composite_get_info", "smg_composite_bind",
             "smg_composite_cycle", "smg_composite_sample", "smg_composite_residual",
             "smg_composite_solve", "smg_composite_debug_pass", "smg_composite_debug_base_pass",
-            "smg_composite_debug_row", "smg_composite_destroy", "smg_sample_field_static"]
+            "smg_composite_debug_row", "smg_composite_destroy", "smg_sample_field_static",
+            "smg_batch_run"]
 
 
 class GridDesc(ctypes.Structure):
@@ -71,6 +74,17 @@ class Info(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("relres", ctypes.c_double),
                 ("last_ratio", ctypes.c_double)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_void_p), ("op", ctypes.c_int32), ("nchains", ctypes.c_int32),
+                ("comps_per_chain", ctypes.c_int32), ("out_dtype", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("seed", ctypes.c_uint64), ("first_cycle", ctypes.c_uint64),
+                ("seeds", ctypes.POINTER(ctypes.c_uint64)),
+                ("first_cycles", ctypes.POINTER(ctypes.c_uint64)),
+                ("state", ctypes.c_void_p), ("out", ctypes.c_void_p), ("f", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int32),
+                ("infos", ctypes.POINTER(SolveInfo)), ("status", ctypes.c_int32)]
 
 
 class CompositeDesc(ctypes.Structure):
@@ -146,6 +160,7 @@ def load():
                               ctypes.c_int32, P, ctypes.c_int32, P, P, P], ctypes.c_int),
         "smg_solve_batch": ([H, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_double,
                              ctypes.c_int32, P, P], ctypes.c_int),
+        "smg_batch_run": ([ctypes.POINTER(BatchItem), ctypes.c_int32, P], ctypes.c_int),
     }
     U64, I32 = ctypes.c_uint64, ctypes.c_int32
     sig.update({

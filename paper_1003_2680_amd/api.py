@@ -42,6 +42,65 @@ def plan_bytes(dims, ncomp, precision="fp64", levels=0, coarsest_max=512):
         lib.smg_destroy_hierarchy(h)
 
 
+def batch_run(items, device=None):
+    """One library call over several hierarchies (C-ABI smg_batch_run): sampling items cycle in
+    step, then solve items, with the small levels of all of them in merged launches.
+
+    items: dicts with "H" (a Hierarchy; each at most once), "op" ("sample" or "solve"),
+    "nchains" (0: one chain over all components) and "comps_per_chain"; sample items also
+    "n", "state", "out" (or None), "out_dtype" (torch dtype), "seed"/"first_cycle" (one chain)
+    or "seeds"/"first_cycles" (host lists; None continues the chain table); solve items "f",
+    "u", "rtol", "max_cycles".  Returns, per item, (status, [(cycles, relres, last_ratio)])."""
+    lib = abi.load()
+    n = len(items)
+    arr = (abi.BatchItem * max(n, 1))()
+    keep = []
+    for k, it in enumerate(items):
+        H = it["H"]
+        e = arr[k]
+        e.h = H._h
+        e.op = abi.SMG_OP_SAMPLE if it["op"] == "sample" else abi.SMG_OP_SOLVE
+        e.nchains = int(it.get("nchains", 0))
+        e.comps_per_chain = int(it.get("comps_per_chain", 1))
+        if it["op"] == "sample":
+            e.n = int(it["n"])
+            e.out_dtype = abi.SMG_OUT_F32 if it.get("out_dtype") == torch.float32 else abi.SMG_OUT_F64
+            e.seed = int(it.get("seed", 0))
+            e.first_cycle = int(it.get("first_cycle", 0))
+            if it.get("seeds") is not None:
+                sd = (ctypes.c_uint64 * len(it["seeds"]))(*[int(v) for v in it["seeds"]])
+                e.seeds = sd
+                keep.append(sd)
+                if it.get("first_cycles") is not None:
+                    fc = (ctypes.c_uint64 * len(it["first_cycles"]))(
+                        *[int(v) for v in it["first_cycles"]])
+                    e.first_cycles = fc
+                    keep.append(fc)
+            e.state = it["state"].data_ptr()
+            e.out = it["out"].data_ptr() if it.get("out") is not None else None
+        else:
+            e.f = it["f"].data_ptr()
+            e.u = it["u"].data_ptr()
+            e.rtol = float(it.get("rtol", 1e-12))
+            e.max_cycles = int(it.get("max_cycles", 100))
+            inf = (abi.SolveInfo * max(e.nchains, 1))()
+            e.infos = inf
+            keep.append(inf)
+    dev = items[0]["H"].device if items else device
+    rc = lib.smg_batch_run(arr, n, _stream(dev))
+    out = []
+    for k, it in enumerate(items):
+        e = arr[k]
+        infos = None
+        if it["op"] == "solve":
+            infos = [(e.infos[i].cycles, e.infos[i].relres, e.infos[i].last_ratio)
+                     for i in range(max(e.nchains, 1))]
+        out.append((e.status, infos))
+    if rc not in (abi.SMG_OK, abi.SMG_ENOTCONV):
+        abi.check(rc)
+    return out
+
+
 class Hierarchy:
     """A planned multigrid hierarchy bound to a device workspace.
 

@@ -2,11 +2,13 @@
 
 Instances with the same grid and cycle configuration form a group: one hierarchy whose
 components are the group's chains, so every launch of the cycle covers all of them (each
-chain draws exactly what it draws alone: seeds and cycle counters are per chain).  Groups run
-concurrently, each on its own HIP stream.  A group's sampling call can be captured once as a
-HIP graph and replayed (the chain table on the device advances with every replay), which takes
-the host out of the many small coarse-level launches.  The cycle configuration of each grid
-comes from the autotuner (or is given).
+chain draws exactly what it draws alone: seeds and cycle counters are per chain).  With the
+default engine ("library") every call goes to the library's batch entry point, which steps all
+groups through their cycles together on one stream and runs the small levels of every group
+(the LDS-resident bottom of each V-cycle) in merged launches; the whole sampling call can be
+captured once as a HIP graph and replayed (the chain tables on the device advance with every
+replay).  The "streams" engine runs each group's calls on its own HIP stream instead (kept for
+comparison).  The cycle configuration of each grid comes from the autotuner (or is given).
 
 Only orchestration lives here; every step runs in the library's kernels.
 """
@@ -14,7 +16,7 @@ from collections import OrderedDict
 
 import torch
 
-from .api import Hierarchy
+from .api import Hierarchy, batch_run
 from . import autotune
 
 
@@ -49,11 +51,15 @@ class BatchRunner:
     depth with V(2,2)."""
 
     def __init__(self, instances, precision="fp32_refined", configs=None, tune=False,
-                 device=None):
+                 device=None, engine="library"):
         dev = torch.device(device if device is not None else "cuda")
         if dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
+        if engine not in ("library", "streams"):
+            raise ValueError("engine must be 'library' or 'streams'")
+        self.engine = engine
+        self.graph = None
         self.instances = list(instances)
         self.precision = precision
         by_dims = OrderedDict()
@@ -94,8 +100,21 @@ class BatchRunner:
         [n, nz, ny, nx]} (views into the group's output) or {} when emit is False."""
         if not self._started:
             self.start()
-        cur = torch.cuda.current_stream(self.device)
         outs = {}
+        if self.engine == "library":
+            items = []
+            for g in self.groups:
+                o = None
+                if emit:
+                    o = torch.empty((n,) + g.H.shape, dtype=out_dtype, device=self.device)
+                items.append({"H": g.H, "op": "sample", "nchains": g.n, "comps_per_chain": 1,
+                              "n": n, "state": g.state, "out": o, "out_dtype": out_dtype})
+                if emit:
+                    for k, i in enumerate(g.members):
+                        outs[i] = o[:, k]
+            self._check(batch_run(items))
+            return outs
+        cur = torch.cuda.current_stream(self.device)
         for g in self.groups:
             g.stream.wait_stream(cur)
             with torch.cuda.stream(g.stream):
@@ -110,12 +129,29 @@ class BatchRunner:
                     outs[i] = o[:, k]
         return outs
 
+    @staticmethod
+    def _check(results):
+        bad = [st for st, _ in results if st != 0]
+        if bad:
+            raise RuntimeError("batch item failed with status %d" % bad[0])
+
     def capture(self, n):
-        """Capture, per group, one call that advances its chains by n cycles (no emission) as
-        a HIP graph; replay() then reruns them, continuing every chain."""
+        """Capture one call that advances every chain by n cycles (no emission) as a HIP graph
+        (library engine: one graph of the whole batch; streams engine: one per group);
+        replay() then reruns it, continuing every chain."""
         if not self._started:
             self.start()
         torch.cuda.synchronize(self.device)
+        if self.engine == "library":
+            items = [{"H": g.H, "op": "sample", "nchains": g.n, "comps_per_chain": 1, "n": n,
+                      "state": g.state, "out": None} for g in self.groups]
+            # captured on a side stream (the chain tables advance on the device per replay)
+            side = torch.cuda.Stream(device=self.device)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=side):
+                self._check(batch_run(items))
+            self.graph = graph
+            return
         for g in self.groups:
             graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(graph, stream=g.stream):
@@ -123,6 +159,9 @@ class BatchRunner:
             g.graphs = [graph]
 
     def replay(self):
+        if self.engine == "library":
+            self.graph.replay()
+            return
         cur = torch.cuda.current_stream(self.device)
         for g in self.groups:
             g.stream.wait_stream(cur)
@@ -137,6 +176,24 @@ class BatchRunner:
         one host thread and one stream each (a solve reads its residual norms every cycle)."""
         from concurrent.futures import ThreadPoolExecutor
         torch.cuda.synchronize(self.device)
+        if self.engine == "library":
+            items, us_g = [], []
+            for g in self.groups:
+                f = torch.stack([fs[i] for i in g.members]).contiguous()
+                u = torch.empty_like(f)
+                us_g.append(u)
+                items.append({"H": g.H, "op": "solve", "nchains": g.n, "comps_per_chain": 1,
+                              "f": f, "u": u, "rtol": rtol, "max_cycles": max_cycles})
+            res = batch_run(items)
+            torch.cuda.synchronize(self.device)
+            us, infos = {}, {}
+            for g, u, (st, inf) in zip(self.groups, us_g, res):
+                if st not in (0, -3):
+                    raise RuntimeError("batch solve failed with status %d" % st)
+                for k, i in enumerate(g.members):
+                    us[i] = u[k]
+                    infos[i] = inf[k]
+            return us, infos
 
         def run(g):
             with torch.cuda.device(self.device), torch.cuda.stream(g.stream):

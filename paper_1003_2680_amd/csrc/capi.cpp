@@ -358,29 +358,134 @@ int vcycle(Run& r, int l) {
   return SMG_OK;
 }
 
-// One cycle on the FP64 level-0 state x.  Refined mode: residual_ready says that lv[0].bf
-// already holds the FP32 residual of the current x (the solve computes it with the norms).
-int full_cycle(Run& r, bool residual_ready = false) {
+// The cycle split around the LDS-resident bottom: the down-leg (levels above the bottom: pre-
+// sweeps and restrictions) and the up-leg (prolongations and post-sweeps), in the order of
+// vcycle, so that down-leg + bottom + up-leg is vcycle(0) exactly.
+bool split_bottom(const Hierarchy& h) { return h.use_bottom && h.bottom > 0; }
+
+template <typename T>
+int vdown(Run& r) {
+  Hierarchy& h = *r.h;
+  for (int l = 0; l < h.bottom; ++l) {
+    for (int s = 0; s < h.prm.nu1; ++s) SMG_TRY(sweep<T>(r, l, s, false));
+    SMG_TRY(restrict_residual<T>(r, l));
+  }
+  return SMG_OK;
+}
+
+template <typename T>
+int vup(Run& r) {
+  Hierarchy& h = *r.h;
+  for (int l = h.bottom - 1; l >= 0; --l) {
+    SMG_TRY(prolong_add<T>(r, l));
+    for (int s = 0; s < h.prm.nu2; ++s) SMG_TRY(sweep<T>(r, l, h.prm.nu1 + s, true));
+  }
+  return SMG_OK;
+}
+
+// Phases of one cycle on the FP64 level-0 state x: PH_PRE (noise, the refined bridge in, the
+// down-leg), PH_BOTTOM (the bottom launch) and PH_POST (the up-leg, the refined bridge out).
+// A hierarchy without a split bottom runs its whole cycle in PH_PRE (and the refined bridge out
+// in PH_POST).  Refined mode: residual_ready says that lv[0].bf already holds the FP32
+// residual of the current x (the solve computes it with the norms).
+enum { PH_PRE = 1, PH_BOTTOM = 2, PH_POST = 4, PH_ALL = 7 };
+
+int cycle_phases(Run& r, int phases, bool residual_ready = false) {
   Hierarchy& h = *r.h;
   Level& v0 = h.lv[0];
+  const bool split = split_bottom(h);
   if (!refined(h)) {
-    if (r.noise) SMG_TRY(gen_level_noise<double>(r));
-    return vcycle<double>(r, 0);
+    if (phases & PH_PRE) {
+      if (r.noise) SMG_TRY(gen_level_noise<double>(r));
+      SMG_TRY(split ? vdown<double>(r) : vcycle<double>(r, 0));
+    }
+    if (split && (phases & PH_BOTTOM)) SMG_TRY(bottom_cycle<double>(r));
+    if (split && (phases & PH_POST)) SMG_TRY(vup<double>(r));
+    return SMG_OK;
   }
-  if (r.noise) SMG_TRY(gen_level_noise<float>(r));
-  if (!residual_ready)
-    SMG_HIP(launch_refine_residual(v0.bf, v0.x, r.has_b0 ? v0.b : nullptr, v0.nx, v0.ny, v0.nz,
-                                   r.nc, h.desc.ncomp, h.desc.h, nullptr, nullptr, r.s));
   // the processed components of both colour arrays
   const int64_t act = (int64_t)r.nc * (v0.n / 2);
   const size_t half = half_field(h);
-  SMG_HIP(launch_zero<float>(v0.xf, act, r.s));
-  SMG_HIP(launch_zero<float>(v0.xf + half, act, r.s));
   Run ri = r;
   ri.has_b0 = true;
-  SMG_TRY(vcycle<float>(ri, 0));
-  SMG_HIP(launch_refine_update(v0.x, v0.xf, act, r.s));
-  SMG_HIP(launch_refine_update(v0.x + half, v0.xf + half, act, r.s));
+  if (phases & PH_PRE) {
+    if (r.noise) SMG_TRY(gen_level_noise<float>(r));
+    if (!residual_ready)
+      SMG_HIP(launch_refine_residual(v0.bf, v0.x, r.has_b0 ? v0.b : nullptr, v0.nx, v0.ny,
+                                     v0.nz, r.nc, h.desc.ncomp, h.desc.h, nullptr, nullptr, r.s));
+    SMG_HIP(launch_zero<float>(v0.xf, act, r.s));
+    SMG_HIP(launch_zero<float>(v0.xf + half, act, r.s));
+    SMG_TRY(split ? vdown<float>(ri) : vcycle<float>(ri, 0));
+  }
+  if (split && (phases & PH_BOTTOM)) SMG_TRY(bottom_cycle<float>(ri));
+  if (phases & PH_POST) {
+    if (split) SMG_TRY(vup<float>(ri));
+    SMG_HIP(launch_refine_update(v0.x, v0.xf, act, r.s));
+    SMG_HIP(launch_refine_update(v0.x + half, v0.xf + half, act, r.s));
+  }
+  return SMG_OK;
+}
+
+int full_cycle(Run& r, bool residual_ready = false) {
+  return cycle_phases(r, PH_ALL, residual_ready);
+}
+
+// One cycle of several runs on one stream (distinct hierarchies): every run's down-leg, then
+// the LDS-resident bottoms of all runs that have one in as few launches as possible (one per
+// sweep precision and noise setting, up to kBotMultiItems hierarchies and kBotMultiWG
+// components each), then every run's up-leg.  Each run's own kernels keep their order and the
+// runs touch disjoint memory, so every run computes exactly what full_cycle computes.
+int batch_cycle(const std::vector<Run*>& runs, const std::vector<char>& ready) {
+  for (size_t i = 0; i < runs.size(); ++i) SMG_TRY(cycle_phases(*runs[i], PH_PRE, ready[i]));
+  for (int f32 = 0; f32 < 2; ++f32)
+    for (int nz = 0; nz < 2; ++nz) {
+      BotMultiArgs m{};
+      m.bm = box_muller_coef();
+      int nwg = 0;
+      size_t lds = 0;
+      hipStream_t s = nullptr;
+      auto flush = [&]() -> int {
+        if (m.nitems == 0) return SMG_OK;
+        hipError_t e = f32 ? launch_bottom_multi<float>(m, nwg, lds, nz != 0, s)
+                           : launch_bottom_multi<double>(m, nwg, lds, nz != 0, s);
+        if (e != hipSuccess) {
+          set_error(std::string("launch_bottom_multi: ") + hipGetErrorString(e));
+          return SMG_EHIP;
+        }
+        m.nitems = 0;
+        nwg = 0;
+        lds = 0;
+        return SMG_OK;
+      };
+      for (Run* r : runs) {
+        Hierarchy& h = *r->h;
+        if (!split_bottom(h) || (int)refined(h) != f32 || (int)r->noise != nz) continue;
+        if (r->nc > kBotMultiWG) {  // more components than one launch holds: its own launch
+          Run ri = *r;
+          ri.has_b0 = ri.has_b0 || refined(h);
+          SMG_TRY(f32 ? bottom_cycle<float>(ri) : bottom_cycle<double>(ri));
+          continue;
+        }
+        if (m.nitems == kBotMultiItems || nwg + r->nc > kBotMultiWG) SMG_TRY(flush());
+        const NoiseArgs na = make_noise(*r, 0, 0, 0, KIND_SMOOTH_NOISE);
+        BotMultiItem& it = m.it[m.nitems];
+        it.args = h.botargs_d;
+        it.k0 = na.k0;
+        it.k1 = na.k1;
+        it.c2 = na.c2;
+        it.c3 = na.c3;
+        it.chains = na.chains;
+        it.cpc = na.comps_per_chain;
+        it.cpc_magic = na.cpc_magic;
+        it.sqkT = na.sqkT;
+        for (int c = 0; c < r->nc; ++c) m.wg[nwg++] = (uint32_t)m.nitems | ((uint32_t)c << 16);
+        ++m.nitems;
+        lds = std::max(lds, h.bottom_lds);
+        s = r->s;
+      }
+      SMG_TRY(flush());
+    }
+  for (size_t i = 0; i < runs.size(); ++i) SMG_TRY(cycle_phases(*runs[i], PH_POST, ready[i]));
   return SMG_OK;
 }
 
@@ -601,132 +706,233 @@ int set_chains(Hierarchy& h, const Batch& bt, const uint64_t* seeds, const uint6
   return SMG_OK;
 }
 
+// A sampling call as a job: begin() checks the arguments, writes the chain table and the mode
+// tables and imports the chain state; cycle(k) runs cycle k (k = 0 .. total-1) and emits when
+// due; finish() exports the state.  smg_sample_* run one job; smg_batch_run interleaves
+// several, cycle by cycle, with their bottoms merged.
+struct SampleJob {
+  smg_hierarchy* hh = nullptr;
+  Batch bt;
+  int64_t n = 0, total = 0;
+  uint64_t first_cycle = 0;
+  void* state = nullptr;
+  void* out = nullptr;
+  int32_t out_dtype = SMG_OUT_F64;
+  double* obs = nullptr;
+  double* m1 = nullptr;
+  double* m2 = nullptr;
+  int n_modes = 0;
+  int nc = 0;
+  int64_t field = 0;
+  Run r{};
+
+  int begin(smg_hierarchy* h_, const Batch& bt_, const uint64_t* seeds,
+            const uint64_t* first_cycles, int64_t n_, uint64_t seed, uint64_t first_cycle_,
+            void* state_, void* out_, int32_t out_dtype_, const int32_t* modes,
+            int32_t n_modes_, void* obs_, void* moments, hipStream_t s) {
+    hh = h_;
+    bt = bt_;
+    SMG_TRY(check_bound(hh));
+    SMG_TRY(check_ptr(state_, "state"));
+    if (n_ < 0 || (out_dtype_ != SMG_OUT_F64 && out_dtype_ != SMG_OUT_F32)) {
+      set_error("invalid n / out_dtype");
+      return SMG_EINVAL;
+    }
+    if (n_ > 0 && out_) SMG_TRY(check_ptr(out_, "out"));
+    if (moments) SMG_TRY(check_ptr(moments, "moments"));
+    if (obs_ && ((uintptr_t)obs_ & 7u)) {
+      set_error("obs must be 8-byte aligned");
+      return SMG_EINVAL;
+    }
+    Hierarchy& h = hh->h;
+    SMG_TRY(check_batch(h, bt));
+    if (bt.nchains > 0) {
+      if (seeds) {
+        SMG_TRY(set_chains(h, bt, seeds, first_cycles, s));
+      } else if (h.chains_set != bt.nchains || h.chains_cpc != bt.cpc) {
+        set_error("no chain table of this shape was set (pass seeds)");
+        return SMG_ESTATE;
+      }
+    }
+    if (obs_) {
+      SMG_TRY(check_modes(h, modes, n_modes_));
+      SMG_TRY(load_modes(h, modes, n_modes_, s));
+    }
+    n = n_;
+    first_cycle = first_cycle_;
+    state = state_;
+    out = out_;
+    out_dtype = out_dtype_;
+    obs = (double*)obs_;
+    n_modes = n_modes_;
+    Level& v0 = h.lv[0];
+    nc = bt.nc(h);
+    field = (int64_t)nc * v0.n;
+    SMG_TRY(import_level0(h, v0.x, (const double*)state, s, nc));
+    if (v0.kind == KIND_CHOL) SMG_HIP(launch_zero<double>(v0.b, field, s));
+    r = make_run(h, s, h.desc.kT > 0.0, false, seed, first_cycle);
+    r.nc = nc;
+    if (bt.nchains > 0) {
+      r.chains = h.chains_d;
+      r.cpc = (uint32_t)bt.cpc;
+    }
+    total = (int64_t)h.prm.burn_in + n * (int64_t)h.prm.stride;
+    m1 = (double*)moments;
+    m2 = m1 ? m1 + field : nullptr;
+    return SMG_OK;
+  }
+
+  void set_cycle(int64_t k) { r.cycle = bt.nchains > 0 ? (uint64_t)k : first_cycle + (uint64_t)k; }
+
+  // emission after cycle k, when it is due
+  int emit_after(int64_t k) {
+    Hierarchy& h = hh->h;
+    const int64_t after = k + 1 - h.prm.burn_in;
+    if (after <= 0 || after % h.prm.stride != 0) return SMG_OK;
+    const int64_t idx = after / h.prm.stride - 1;
+    const size_t out_elem = out_dtype == SMG_OUT_F32 ? sizeof(float) : sizeof(double);
+    const size_t obs_stride = (size_t)nc * (n_modes + 1);
+    return emit(h, out ? (char*)out + (size_t)idx * field * out_elem : nullptr,
+                out_dtype == SMG_OUT_F32, obs ? obs + (size_t)idx * obs_stride : nullptr, m1,
+                m2, n_modes, nc, r.s);
+  }
+
+  int finish() {
+    Hierarchy& h = hh->h;
+    SMG_TRY(export_level0(h, state, 0, h.lv[0].x, r.s, nc));
+    // the chains continue from here: a repeated (or replayed) call draws the next cycles
+    if (bt.nchains > 0)
+      SMG_HIP(launch_advance_chains(h.chains_d, bt.nchains, (uint64_t)total, r.s));
+    return SMG_OK;
+  }
+};
+
 int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
                 const uint64_t* first_cycles, int64_t n, uint64_t seed, uint64_t first_cycle,
                 void* state, void* out, int32_t out_dtype, const int32_t* modes,
                 int32_t n_modes, void* obs, void* moments, void* stream) {
-  SMG_TRY(check_bound(hh));
-  SMG_TRY(check_ptr(state, "state"));
-  if (n < 0 || (out_dtype != SMG_OUT_F64 && out_dtype != SMG_OUT_F32)) {
-    set_error("invalid n / out_dtype");
-    return SMG_EINVAL;
+  SampleJob j;
+  SMG_TRY(j.begin(hh, bt, seeds, first_cycles, n, seed, first_cycle, state, out, out_dtype,
+                  modes, n_modes, obs, moments, (hipStream_t)stream));
+  for (int64_t k = 0; k < j.total; ++k) {
+    j.set_cycle(k);
+    SMG_TRY(full_cycle(j.r));
+    SMG_TRY(j.emit_after(k));
   }
-  if (n > 0 && out) SMG_TRY(check_ptr(out, "out"));
-  if (moments) SMG_TRY(check_ptr(moments, "moments"));
-  if (obs && ((uintptr_t)obs & 7u)) {
-    set_error("obs must be 8-byte aligned");
-    return SMG_EINVAL;
-  }
-  Hierarchy& h = hh->h;
-  SMG_TRY(check_batch(h, bt));
-  hipStream_t s = (hipStream_t)stream;
-  if (bt.nchains > 0) {
-    if (seeds) {
-      SMG_TRY(set_chains(h, bt, seeds, first_cycles, s));
-    } else if (h.chains_set != bt.nchains || h.chains_cpc != bt.cpc) {
-      set_error("no chain table of this shape was set (pass seeds)");
-      return SMG_ESTATE;
-    }
-  }
-  if (obs) {
-    SMG_TRY(check_modes(h, modes, n_modes));
-    SMG_TRY(load_modes(h, modes, n_modes, s));
-  }
-  Level& v0 = h.lv[0];
-  const int nc = bt.nc(h);
-  const int64_t field = (int64_t)nc * v0.n;
-  SMG_TRY(import_level0(h, v0.x, (const double*)state, s, nc));
-  if (v0.kind == KIND_CHOL) SMG_HIP(launch_zero<double>(v0.b, field, s));
-  Run r = make_run(h, s, h.desc.kT > 0.0, false, seed, first_cycle);
-  r.nc = nc;
-  if (bt.nchains > 0) {
-    r.chains = h.chains_d;
-    r.cpc = (uint32_t)bt.cpc;
-  }
-  const int64_t total = (int64_t)h.prm.burn_in + n * (int64_t)h.prm.stride;
-  const size_t out_elem = out_dtype == SMG_OUT_F32 ? sizeof(float) : sizeof(double);
-  const size_t obs_stride = (size_t)nc * (n_modes + 1);
-  double* m1 = (double*)moments;
-  double* m2 = m1 ? m1 + field : nullptr;
-  for (int64_t k = 0; k < total; ++k) {
-    r.cycle = bt.nchains > 0 ? (uint64_t)k : first_cycle + (uint64_t)k;
-    SMG_TRY(full_cycle(r));
-    const int64_t after = k + 1 - h.prm.burn_in;
-    if (after > 0 && after % h.prm.stride == 0) {
-      const int64_t idx = after / h.prm.stride - 1;
-      SMG_TRY(emit(h, out ? (char*)out + (size_t)idx * field * out_elem : nullptr,
-                   out_dtype == SMG_OUT_F32, obs ? (double*)obs + (size_t)idx * obs_stride : nullptr,
-                   m1, m2, n_modes, nc, s));
-    }
-  }
-  SMG_TRY(export_level0(h, state, 0, v0.x, s, nc));
-  // the chains continue from here: a repeated (or replayed) call draws the next cycles
-  if (bt.nchains > 0) SMG_HIP(launch_advance_chains(h.chains_d, bt.nchains, (uint64_t)total, s));
-  return SMG_OK;
+  return j.finish();
 }
 
-// Solves for every chain (one chain = cpc components, or all components when nchains == 0).
-// A chain stops counting once all its components reach rtol: its u is written at that cycle,
-// so each result equals that of a solve of the chain alone.
-int solve_impl(smg_hierarchy* hh, const Batch& bt, const void* f, void* u, double rtol,
-               int32_t max_cycles, void* stream, smg_solve_info* infos) {
-  SMG_TRY(check_bound(hh));
-  SMG_TRY(check_ptr(f, "f"));
-  SMG_TRY(check_ptr(u, "u"));
-  if (!(rtol >= 0.0) || max_cycles < 0) {
-    set_error("rtol must be >= 0 and max_cycles >= 0");
-    return SMG_EINVAL;
-  }
-  Hierarchy& h = hh->h;
-  SMG_TRY(check_batch(h, bt));
-  hipStream_t s = (hipStream_t)stream;
-  Level& v0 = h.lv[0];
-  const int nc = bt.nc(h);
-  const int nch = bt.nchains > 0 ? bt.nchains : 1;
-  const int cpc = bt.nchains > 0 ? bt.cpc : nc;
-  const int64_t field = (int64_t)nc * v0.n;
-  const bool f32 = refined(h);
-  std::vector<double> fn(nc), rn(nc), rprev(nc, 0.0);
-  SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)f, v0.n, nc, s));
-  SMG_HIP(hipMemcpyAsync(fn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
-  SMG_HIP(hipStreamSynchronize(s));
-  for (int c = 0; c < nc; ++c)
-    if (!std::isfinite(fn[c])) {
-      set_error("f is not finite");
-      return SMG_ENONFINITE;
-    }
-  SMG_TRY(import_level0(h, v0.b, (const double*)f, s, nc));
-  if (v0.kind == KIND_POINT) {
-    // split storage: the processed components of both colour arrays (colour 1 starts after
-    // all components of colour 0, not after the processed ones)
-    const int64_t act = (int64_t)nc * (v0.n / 2);
-    SMG_HIP(launch_zero<double>(v0.x, act, s));
-    SMG_HIP(launch_zero<double>(v0.x + half_field(h), act, s));
-  } else {
-    SMG_HIP(launch_zero<double>(v0.x, field, s));
-  }
-  Run r = make_run(h, s, false, true, 0, 0);
-  r.nc = nc;
+// A solve as a job (one chain = cpc components, or all components when nchains == 0).  A chain
+// stops counting once all its components reach rtol: its u is written at that cycle, so each
+// result equals that of a solve of the chain alone.  The host reads norms after each stream
+// synchronisation; the steps between synchronisations are split so that smg_batch_run can
+// run several jobs with one synchronisation per cycle for all of them:
+//   enqueue_fnorm / [sync] / after_fnorm (+ enqueue_norms when initial_norms) / [sync] /
+//   after_initial_norms, then per cycle: full_cycle / enqueue_norms / [sync] / after_norms;
+//   finish.
+struct SolveJob {
   struct ChainState {
     bool done = false, all_zero = true;
     int cycles = 0;
     double relres = 0.0, last_ratio = 0.0;
   };
-  std::vector<ChainState> cs(nch);
-  int pending = 0;
-  for (int ch = 0; ch < nch; ++ch) {
-    for (int c = ch * cpc; c < (ch + 1) * cpc; ++c) cs[ch].all_zero = cs[ch].all_zero && fn[c] == 0.0;
-    if (cs[ch].all_zero) {
-      cs[ch].done = true;  // u = 0 after zero cycles
-      SMG_TRY(export_level0(h, (double*)u + (size_t)ch * cpc * v0.n, 0, v0.x, s, cpc, ch * cpc));
-    } else {
-      cs[ch].relres = 1.0;
-      ++pending;
+  smg_hierarchy* hh = nullptr;
+  Batch bt;
+  const void* f = nullptr;
+  void* u = nullptr;
+  double rtol = 0.0;
+  int max_cycles = 0;
+  smg_solve_info* infos = nullptr;
+  int nc = 0, nch = 1, cpc = 1;
+  bool f32 = false;
+  std::vector<double> fn, rn, rprev;
+  std::vector<ChainState> cs;
+  int pending = 0, cycles = 0;
+  bool ready = false;          // refined mode: lv[0].bf holds the FP32 residual of x
+  bool initial_norms = false;  // refined mode: the residual of u = 0 is taken before cycle 1
+  Run r{};
+
+  int begin(smg_hierarchy* h_, const Batch& bt_, const void* f_, void* u_, double rtol_,
+            int32_t max_cycles_, smg_solve_info* infos_, hipStream_t s) {
+    hh = h_;
+    bt = bt_;
+    SMG_TRY(check_bound(hh));
+    SMG_TRY(check_ptr(f_, "f"));
+    SMG_TRY(check_ptr(u_, "u"));
+    if (!(rtol_ >= 0.0) || max_cycles_ < 0) {
+      set_error("rtol must be >= 0 and max_cycles >= 0");
+      return SMG_EINVAL;
     }
+    Hierarchy& h = hh->h;
+    SMG_TRY(check_batch(h, bt));
+    f = f_;
+    u = u_;
+    rtol = rtol_;
+    max_cycles = max_cycles_;
+    infos = infos_;
+    nc = bt.nc(h);
+    nch = bt.nchains > 0 ? bt.nchains : 1;
+    cpc = bt.nchains > 0 ? bt.cpc : nc;
+    f32 = refined(h);
+    fn.assign(nc, 0.0);
+    rn.assign(nc, 0.0);
+    rprev.assign(nc, 0.0);
+    cs.assign(nch, ChainState());
+    r = make_run(h, s, false, true, 0, 0);
+    r.nc = nc;
+    return SMG_OK;
   }
-  int cycles = 0;
-  // residual norms of the current iterate (refined mode leaves the FP32 residual in lv[0].bf)
-  auto residual_norms = [&]() -> int {
+
+  int enqueue_fnorm() {
+    Hierarchy& h = hh->h;
+    SMG_HIP(launch_sumsq(h.norm_d, h.part_d, (const double*)f, h.lv[0].n, nc, r.s));
+    SMG_HIP(hipMemcpyAsync(fn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost,
+                           r.s));
+    return SMG_OK;
+  }
+
+  int after_fnorm() {
+    Hierarchy& h = hh->h;
+    Level& v0 = h.lv[0];
+    hipStream_t s = r.s;
+    for (int c = 0; c < nc; ++c)
+      if (!std::isfinite(fn[c])) {
+        set_error("f is not finite");
+        return SMG_ENONFINITE;
+      }
+    SMG_TRY(import_level0(h, v0.b, (const double*)f, s, nc));
+    if (v0.kind == KIND_POINT) {
+      // split storage: the processed components of both colour arrays (colour 1 starts after
+      // all components of colour 0, not after the processed ones)
+      const int64_t act = (int64_t)nc * (v0.n / 2);
+      SMG_HIP(launch_zero<double>(v0.x, act, s));
+      SMG_HIP(launch_zero<double>(v0.x + half_field(h), act, s));
+    } else {
+      SMG_HIP(launch_zero<double>(v0.x, (int64_t)nc * v0.n, s));
+    }
+    for (int ch = 0; ch < nch; ++ch) {
+      for (int c = ch * cpc; c < (ch + 1) * cpc; ++c)
+        cs[ch].all_zero = cs[ch].all_zero && fn[c] == 0.0;
+      if (cs[ch].all_zero) {
+        cs[ch].done = true;  // u = 0 after zero cycles
+        SMG_TRY(export_level0(h, (double*)u + (size_t)ch * cpc * v0.n, 0, v0.x, s, cpc,
+                              ch * cpc));
+      } else {
+        cs[ch].relres = 1.0;
+        ++pending;
+      }
+    }
+    initial_norms = pending > 0 && f32 && max_cycles > 0;
+    if (initial_norms) SMG_TRY(enqueue_norms());  // residual of u = 0, i.e. f, in FP32
+    return SMG_OK;
+  }
+
+  // residual norms of the current iterate into rn (refined mode leaves the FP32 residual in
+  // lv[0].bf)
+  int enqueue_norms() {
+    Hierarchy& h = hh->h;
+    Level& v0 = h.lv[0];
+    hipStream_t s = r.s;
     if (f32) {
       SMG_HIP(launch_refine_residual(v0.bf, v0.x, v0.b, v0.nx, v0.ny, v0.nz, nc, h.desc.ncomp,
                                      h.desc.h, h.part_d, h.norm_d, s));
@@ -742,69 +948,106 @@ int solve_impl(smg_hierarchy* hh, const Batch& bt, const void* f, void* u, doubl
       SMG_HIP(launch_sumsq(h.norm_d, h.part_d, v0.r, v0.n, nc, s));
     }
     SMG_HIP(hipMemcpyAsync(rn.data(), h.norm_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
-    SMG_HIP(hipStreamSynchronize(s));
+    return SMG_OK;
+  }
+
+  int check_norms() {
     for (int c = 0; c < nc; ++c)
       if (!std::isfinite(rn[c])) {
         set_error("residual is not finite");
         return SMG_ENONFINITE;
       }
     return SMG_OK;
-  };
-  // per-chain relres and contraction of the last cycle from rn (rprev: previous cycle)
-  auto chain_norms = [&](int ch, double& relres, double& ratio) {
-    relres = 0.0;
-    ratio = 0.0;
-    for (int c = ch * cpc; c < (ch + 1) * cpc; ++c) {
-      const double rr = fn[c] > 0.0 ? std::sqrt(rn[c] / fn[c]) : (rn[c] > 0.0 ? INFINITY : 0.0);
-      relres = rr > relres ? rr : relres;
-      if (cycles >= 2 && rprev[c] > 0.0) {
-        const double q = std::sqrt(rn[c] / rprev[c]);
-        ratio = q > ratio ? q : ratio;
-      }
-    }
-  };
-  if (pending > 0) {
-    bool ready = false;
-    if (f32 && max_cycles > 0) {
-      SMG_TRY(residual_norms());  // residual of u = 0, i.e. f, rounded to FP32
-      rprev = rn;
-      ready = true;
-    }
-    while (pending > 0 && cycles < max_cycles) {
-      SMG_TRY(full_cycle(r, ready));
-      ++cycles;
-      SMG_TRY(residual_norms());
-      for (int ch = 0; ch < nch; ++ch) {
-        if (cs[ch].done) continue;
-        chain_norms(ch, cs[ch].relres, cs[ch].last_ratio);
-        cs[ch].cycles = cycles;
-        if (cs[ch].relres <= rtol) {
-          cs[ch].done = true;
-          --pending;
-          SMG_TRY(export_level0(h, (double*)u + (size_t)ch * cpc * v0.n, 0, v0.x, s, cpc,
-                                ch * cpc));
+  }
+
+  int after_initial_norms() {
+    SMG_TRY(check_norms());
+    rprev = rn;
+    ready = true;
+    return SMG_OK;
+  }
+
+  bool wants_cycle() const { return pending > 0 && cycles < max_cycles; }
+
+  // after the norms of cycle `cycles` (already counted) are on the host
+  int after_norms() {
+    Hierarchy& h = hh->h;
+    SMG_TRY(check_norms());
+    for (int ch = 0; ch < nch; ++ch) {
+      if (cs[ch].done) continue;
+      double relres = 0.0, ratio = 0.0;
+      for (int c = ch * cpc; c < (ch + 1) * cpc; ++c) {
+        const double rr =
+            fn[c] > 0.0 ? std::sqrt(rn[c] / fn[c]) : (rn[c] > 0.0 ? INFINITY : 0.0);
+        relres = rr > relres ? rr : relres;
+        if (cycles >= 2 && rprev[c] > 0.0) {
+          const double q = std::sqrt(rn[c] / rprev[c]);
+          ratio = q > ratio ? q : ratio;
         }
       }
-      rprev = rn;
+      cs[ch].relres = relres;
+      cs[ch].last_ratio = ratio;
+      cs[ch].cycles = cycles;
+      if (relres <= rtol) {
+        cs[ch].done = true;
+        --pending;
+        SMG_TRY(export_level0(h, (double*)u + (size_t)ch * cpc * h.lv[0].n, 0, h.lv[0].x, r.s,
+                              cpc, ch * cpc));
+      }
     }
+    rprev = rn;
+    return SMG_OK;
   }
-  for (int ch = 0; ch < nch; ++ch)
-    if (!cs[ch].done)
-      SMG_TRY(export_level0(h, (double*)u + (size_t)ch * cpc * v0.n, 0, v0.x, s, cpc, ch * cpc));
+
+  // exports the chains that did not converge; the caller synchronises before reading infos
+  int finish_enqueue() {
+    Hierarchy& h = hh->h;
+    for (int ch = 0; ch < nch; ++ch)
+      if (!cs[ch].done)
+        SMG_TRY(export_level0(h, (double*)u + (size_t)ch * cpc * h.lv[0].n, 0, h.lv[0].x, r.s,
+                              cpc, ch * cpc));
+    return SMG_OK;
+  }
+
+  int finish_report() {
+    if (infos)
+      for (int ch = 0; ch < nch; ++ch) {
+        infos[ch].cycles = cs[ch].cycles;
+        infos[ch].relres = cs[ch].relres;
+        infos[ch].last_ratio = cs[ch].last_ratio;
+      }
+    if (pending > 0) {
+      double worst = 0.0;
+      for (const auto& c : cs) worst = c.relres > worst ? c.relres : worst;
+      set_error("solve did not converge: relres " + std::to_string(worst));
+      return SMG_ENOTCONV;
+    }
+    return SMG_OK;
+  }
+};
+
+int solve_impl(smg_hierarchy* hh, const Batch& bt, const void* f, void* u, double rtol,
+               int32_t max_cycles, void* stream, smg_solve_info* infos) {
+  SolveJob j;
+  hipStream_t s = (hipStream_t)stream;
+  SMG_TRY(j.begin(hh, bt, f, u, rtol, max_cycles, infos, s));
+  SMG_TRY(j.enqueue_fnorm());
   SMG_HIP(hipStreamSynchronize(s));
-  if (infos)
-    for (int ch = 0; ch < nch; ++ch) {
-      infos[ch].cycles = cs[ch].cycles;
-      infos[ch].relres = cs[ch].relres;
-      infos[ch].last_ratio = cs[ch].last_ratio;
-    }
-  if (pending > 0) {
-    double worst = 0.0;
-    for (const auto& c : cs) worst = c.relres > worst ? c.relres : worst;
-    set_error("solve did not converge: relres " + std::to_string(worst));
-    return SMG_ENOTCONV;
+  SMG_TRY(j.after_fnorm());
+  if (j.initial_norms) {
+    SMG_HIP(hipStreamSynchronize(s));
+    SMG_TRY(j.after_initial_norms());
   }
-  return SMG_OK;
+  while (j.wants_cycle()) {
+    SMG_TRY(full_cycle(j.r, j.ready));
+    ++j.cycles;
+    SMG_TRY(j.enqueue_norms());
+    SMG_HIP(hipStreamSynchronize(s));
+    SMG_TRY(j.after_norms());
+  }
+  SMG_TRY(j.finish_enqueue());
+  SMG_HIP(hipStreamSynchronize(s));
+  return j.finish_report();
 }
 
 }  // namespace
@@ -983,6 +1226,161 @@ int smg_solve_batch(smg_hierarchy* hh, int32_t nchains, int32_t comps_per_chain,
   bt.nchains = nchains;
   bt.cpc = comps_per_chain;
   return solve_impl(hh, bt, f, u, rtol, max_cycles, stream, infos);
+}
+
+int smg_batch_run(smg_batch_item* items, int32_t n_items, void* stream) {
+  if (n_items < 0 || (n_items > 0 && !items)) {
+    set_error("invalid item list");
+    return SMG_EINVAL;
+  }
+  for (int i = 0; i < n_items; ++i) {
+    items[i].status = SMG_OK;
+    for (int j = 0; j < i; ++j)
+      if (items[i].h == items[j].h) {
+        set_error("a hierarchy may appear only once in a batch");
+        return SMG_EINVAL;
+      }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int first_err = SMG_OK;
+  std::vector<char> alive(n_items, 0);
+  auto fail = [&](int i, int rc) {
+    items[i].status = rc;
+    alive[i] = 0;
+    if (first_err == SMG_OK) first_err = rc;
+  };
+  auto batch_of = [](const smg_batch_item& it) {
+    Batch bt;
+    if (it.nchains > 0) {
+      bt.nchains = it.nchains;
+      bt.cpc = it.comps_per_chain;
+    }
+    return bt;
+  };
+  for (int i = 0; i < n_items; ++i)
+    if (items[i].op != SMG_OP_SAMPLE && items[i].op != SMG_OP_SOLVE) {
+      set_error("unknown batch op");
+      fail(i, SMG_EINVAL);
+    } else if (items[i].nchains < 0) {
+      set_error("nchains must be >= 0");
+      fail(i, SMG_EINVAL);
+    }
+  // ---- sampling items: every cycle of every item, the bottoms of one cycle merged
+  std::vector<SampleJob> sj(n_items);
+  int64_t kmax = 0;
+  for (int i = 0; i < n_items; ++i) {
+    smg_batch_item& it = items[i];
+    if (it.op != SMG_OP_SAMPLE || items[i].status != SMG_OK) continue;
+    const int rc = sj[i].begin(it.h, batch_of(it), it.seeds, it.first_cycles, it.n, it.seed,
+                               it.first_cycle, it.state, it.out, it.out_dtype, nullptr, 0,
+                               nullptr, nullptr, s);
+    if (rc != SMG_OK) {
+      fail(i, rc);
+      continue;
+    }
+    alive[i] = 1;
+    kmax = std::max(kmax, sj[i].total);
+  }
+  for (int64_t k = 0; k < kmax; ++k) {
+    std::vector<Run*> runs;
+    std::vector<int> who;
+    for (int i = 0; i < n_items; ++i)
+      if (alive[i] && items[i].op == SMG_OP_SAMPLE && k < sj[i].total) {
+        sj[i].set_cycle(k);
+        runs.push_back(&sj[i].r);
+        who.push_back(i);
+      }
+    if (runs.empty()) break;
+    const int rc = batch_cycle(runs, std::vector<char>(runs.size(), 0));
+    for (int i : who) {
+      if (rc != SMG_OK) {
+        fail(i, rc);
+        continue;
+      }
+      const int re = sj[i].emit_after(k);
+      if (re != SMG_OK) fail(i, re);
+    }
+  }
+  for (int i = 0; i < n_items; ++i)
+    if (alive[i] && items[i].op == SMG_OP_SAMPLE) {
+      const int rc = sj[i].finish();
+      if (rc != SMG_OK) fail(i, rc);
+      alive[i] = 0;
+    }
+  // ---- solve items: every cycle of every unfinished item, one synchronisation per cycle
+  std::vector<SolveJob> vj(n_items);
+  bool any = false;
+  for (int i = 0; i < n_items; ++i) {
+    smg_batch_item& it = items[i];
+    if (it.op != SMG_OP_SOLVE || items[i].status != SMG_OK) continue;
+    int rc = vj[i].begin(it.h, batch_of(it), it.f, it.u, it.rtol, it.max_cycles, it.infos, s);
+    if (rc == SMG_OK) rc = vj[i].enqueue_fnorm();
+    if (rc != SMG_OK) {
+      fail(i, rc);
+      continue;
+    }
+    alive[i] = 1;
+    any = true;
+  }
+  if (any) {
+    SMG_HIP(hipStreamSynchronize(s));
+    bool init = false;
+    for (int i = 0; i < n_items; ++i)
+      if (alive[i]) {
+        const int rc = vj[i].after_fnorm();
+        if (rc != SMG_OK) fail(i, rc);
+        init = init || (alive[i] && vj[i].initial_norms);
+      }
+    if (init) {
+      SMG_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i < n_items; ++i)
+        if (alive[i] && vj[i].initial_norms) {
+          const int rc = vj[i].after_initial_norms();
+          if (rc != SMG_OK) fail(i, rc);
+        }
+    }
+    for (;;) {
+      std::vector<Run*> runs;
+      std::vector<char> ready;
+      std::vector<int> who;
+      for (int i = 0; i < n_items; ++i)
+        if (alive[i] && vj[i].wants_cycle()) {
+          runs.push_back(&vj[i].r);
+          ready.push_back(vj[i].ready);
+          who.push_back(i);
+        }
+      if (runs.empty()) break;
+      const int rc = batch_cycle(runs, ready);
+      for (int i : who) {
+        if (rc != SMG_OK) {
+          fail(i, rc);
+          continue;
+        }
+        ++vj[i].cycles;
+        const int re = vj[i].enqueue_norms();
+        if (re != SMG_OK) fail(i, re);
+      }
+      SMG_HIP(hipStreamSynchronize(s));
+      for (int i : who)
+        if (alive[i]) {
+          const int re = vj[i].after_norms();
+          if (re != SMG_OK) fail(i, re);
+        }
+    }
+    for (int i = 0; i < n_items; ++i)
+      if (alive[i]) {
+        const int rc = vj[i].finish_enqueue();
+        if (rc != SMG_OK) fail(i, rc);
+      }
+    SMG_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n_items; ++i)
+      if (alive[i]) {
+        const int rc = vj[i].finish_report();
+        if (rc != SMG_OK) fail(i, rc);
+        alive[i] = 0;
+      }
+  }
+  return first_err;
 }
 
 int smg_lowest_modes(int32_t nx, int32_t ny, int32_t nz, int32_t k, int32_t* modes) {

@@ -116,6 +116,27 @@ hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStr
 template <typename T>
 hipError_t launch_bottom(const BotArgs* a, int ncomp, size_t lds, bool noise, const NoiseArgs& na,
                          hipStream_t s);
+// The bottoms of several hierarchies in one launch (kernel arguments only): item i brings its
+// device BotArgs and its noise keys; work-group w runs component wg[w] >> 16 of item
+// wg[w] & 0xffff.  lds: the largest bottom LDS size of the items.
+constexpr int kBotMultiItems = 16;
+constexpr int kBotMultiWG = 256;
+struct BotMultiItem {
+  const BotArgs* args;
+  uint32_t k0, k1, c2, c3;   // as NoiseArgs
+  const ChainKey* chains;
+  uint32_t cpc, cpc_magic;
+  double sqkT;
+};
+struct BotMultiArgs {
+  BoxMullerCoef bm;
+  int nitems;
+  BotMultiItem it[kBotMultiItems];
+  uint32_t wg[kBotMultiWG];
+};
+template <typename T>
+hipError_t launch_bottom_multi(const BotMultiArgs& m, int nwg, size_t lds, bool noise,
+                               hipStream_t s);
 // x = A_c^-1 b (+ sqrt(kT) L_c^-T n), FP64 arithmetic, T storage
 template <typename T>
 hipError_t launch_coarsest(T* x, const T* b, const double* ainv, const double* w, int n,

@@ -400,11 +400,10 @@ __device__ __forceinline__ int bot_pos(const BotLevel& L, int q) {
 }
 
 template <typename T, bool NOISE>
-__global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ ap, NoiseArgs na) {
+__device__ __forceinline__ void bottom_body(const BotArgs& a, const uint32_t comp,
+                                            const NoiseArgs& na) {
   extern __shared__ char smraw[];
   T* sm = reinterpret_cast<T*>(smraw);
-  const BotArgs& a = *ap;
-  const uint32_t comp = blockIdx.x;
   const int tid = threadIdx.x;
   const BotLevel& L0 = a.lv[0];
   const int n0 = L0.nx * L0.ny * L0.nz;
@@ -519,6 +518,33 @@ __global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ 
     ((T*)a.x_out)[(size_t)comp * n0 + q] = sm[a.lds_off[0] + bot_pos(L0, q)];
 }
 
+// One hierarchy, one work-group per component.
+template <typename T, bool NOISE>
+__global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ ap, NoiseArgs na) {
+  bottom_body<T, NOISE>(*ap, blockIdx.x, na);
+}
+
+// Several hierarchies (of any sizes) in one launch: work-group w runs component wg >> 16 of
+// item wg & 0xffff, with that item's level descriptors and noise keys, so the latency-bound
+// bottoms of uneven instances overlap instead of running one launch after another.
+template <typename T, bool NOISE>
+__global__ __launch_bounds__(BOT_TPB) void k_bottom_multi(BotMultiArgs m) {
+  const uint32_t w = m.wg[blockIdx.x];
+  const BotMultiItem& it = m.it[w & 0xffffu];
+  NoiseArgs na;
+  na.k0 = it.k0;
+  na.k1 = it.k1;
+  na.sid = 0;
+  na.c2 = it.c2;
+  na.c3 = it.c3;
+  na.sqkT = it.sqkT;
+  na.chains = it.chains;
+  na.comps_per_chain = it.cpc;
+  na.cpc_magic = it.cpc_magic;
+  na.bm = m.bm;
+  bottom_body<T, NOISE>(*it.args, w >> 16, na);
+}
+
 }  // namespace
 
 template <typename T, int TI, int TJ>
@@ -631,6 +657,26 @@ hipError_t launch_bottom(const BotArgs* a, int ncomp, size_t lds, bool noise, co
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_bottom_multi(const BotMultiArgs& m, int nwg, size_t lds, bool noise,
+                               hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_bottom_multi<T, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_bottom_multi<T, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (nwg <= 0) return hipSuccess;
+  if (nwg > kBotMultiWG || m.nitems > kBotMultiItems) return hipErrorInvalidValue;
+  if (noise) k_bottom_multi<T, true><<<nwg, BOT_TPB, lds, s>>>(m);
+  else k_bottom_multi<T, false><<<nwg, BOT_TPB, lds, s>>>(m);
+  return hipGetLastError();
+}
+
 #define SMG_INST(T)                                                                            \
   template hipError_t launch_block_pass<T>(T*, const T*, const T*, const T*, const T*, int, int, \
                                            int, int, int, const T*, int, hipStream_t);          \
@@ -642,7 +688,8 @@ hipError_t launch_bottom(const BotArgs* a, int ncomp, size_t lds, bool noise, co
                                          bool, const NoiseArgs&, hipStream_t);                  \
   template hipError_t launch_level_noise<T>(const NoiseGenArgs&, const NoiseArgs&, hipStream_t); \
   template hipError_t launch_bottom<T>(const BotArgs*, int, size_t, bool, const NoiseArgs&,     \
-                                       hipStream_t);
+                                       hipStream_t);                                             \
+  template hipError_t launch_bottom_multi<T>(const BotMultiArgs&, int, size_t, bool, hipStream_t);
 SMG_INST(double)
 SMG_INST(float)
 #undef SMG_INST

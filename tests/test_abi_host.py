@@ -169,6 +169,32 @@ def test_boundary_conditions(lib):
             assert "boundary" in lib.smg_last_error().decode()
 
 
+def test_batch_run_argument_checks(lib):
+    """smg_batch_run refuses a repeated hierarchy before any work, reports an unknown op and an
+    unbound hierarchy per item (status), and returns the first failing item's code."""
+    hs = []
+    for dims in ((8, 8, 8), (16, 16, 8)):
+        rc, hd = _create(lib, *dims, levels=2)
+        abi.check(rc)
+        hs.append(hd)
+    try:
+        items = (abi.BatchItem * 2)()
+        for k in range(2):
+            items[k].h = hs[0].value
+            items[k].op = abi.SMG_OP_SAMPLE
+        assert lib.smg_batch_run(items, 2, None) == abi.SMG_EINVAL
+        assert b"once" in lib.smg_last_error()
+        items[1].h = hs[1].value
+        items[1].op = 7
+        rc = lib.smg_batch_run(items, 2, None)
+        assert items[0].status == abi.SMG_ESTATE and items[1].status == abi.SMG_EINVAL
+        assert rc in (abi.SMG_ESTATE, abi.SMG_EINVAL)
+        assert lib.smg_batch_run(items, 0, None) == abi.SMG_OK
+    finally:
+        for hd in hs:
+            lib.smg_destroy_hierarchy(hd)
+
+
 def test_unbound_hierarchy_refuses_work(lib):
     rc, hd = _create(lib, 8, 8, 8, levels=3)
     abi.check(rc)

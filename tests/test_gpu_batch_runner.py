@@ -26,13 +26,15 @@ def _alone(inst, precision, cfg, n):
     return H, H.sample(n, inst.seed, first_cycle=inst.first_cycle, out_dtype=torch.float32)[0]
 
 
+@pytest.mark.parametrize("engine", ["library", "streams"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
-def test_runner_samples_and_solves_equal_alone(precision):
+def test_runner_samples_and_solves_equal_alone(precision, engine):
     from paper_1003_2680_amd.batch import BatchRunner
     from paper_1003_2680_amd.inputs import gaussian_field
-    _announce("batch runner %s" % precision)
+    _announce("batch runner %s %s" % (precision, engine))
     insts = _instances()
-    R = BatchRunner(insts, precision=precision, configs={i.dims: CFG for i in insts})
+    R = BatchRunner(insts, precision=precision, configs={i.dims: CFG for i in insts},
+                    engine=engine)
     assert len(R.groups) == 3
     outs = R.sample(3)
     torch.cuda.synchronize()
