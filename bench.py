@@ -7,19 +7,23 @@ bath on the fine level, 2x2x2 block heat bath on the Galerkin levels, exact Chol
 the 4^3 coarsest level).  The chains of seeds 0..CHAINS-1 (--chains, default 8) are batched
 into every launch (one hierarchy carrying CHAINS x 3 components; each chain draws exactly what
 it draws alone).
-One step = one batched call that advances every chain by SAMPLES_PER_STEP cycles, writes
-every cycle's fields to an output buffer in HBM and takes their observables (projections on
-the 8 lowest eigenvectors of A and the energy 1/2 x^T A x) in the same pass.
+k_dec = max(1, ceil(ln 0.01 / ln rho)) with rho the contraction of the cycle measured by the
+deterministic solves (the lag-k correlation of the stochastic iteration is R^k applied to the
+stationary covariance): k_dec cycles separate nearly independent draws.  One step = one batched
+call that advances every chain by SAMPLES_PER_STEP * k_dec cycles and emits a sample every
+k_dec cycles -- each emitted sample a decorrelated one -- writing its fields to an output buffer
+in HBM and taking their observables (projections on the 8 lowest eigenvectors of A and the
+energy 1/2 x^T A x) in the same pass.
 
-value = decorrelated samples/s = emitted samples/s / k_dec with
-k_dec = max(1, ceil(ln 0.01 / ln rho)), rho the larger of the measured contraction of the
-deterministic cycle (the lag-k correlation of the stochastic iteration is R^k applied to the
-stationary covariance) and the largest measured lag-1 autocorrelation of the observables.
-Also reported: the integrated autocorrelation time of each observable; per-step p50/p99
-latency; one FP64 chain on a single 512x512x256 grid, whose fields exceed the 256 MB Infinity
-Cache (cycles/s and the level-0 pass against HBM); 10 solves to 1e-12 (batched throughput and single
-latency); the roofline of the dominant kernel class (per-launch time from HIP events around
-each sweep's launches) and of the other; and the CPU oracle on a bounded sample.
+value = decorrelated samples/s = emitted samples/s.  The lag-1 correlation of the emitted
+observables (the chain's lag-k_dec correlation) is checked against 0.01 within its standard
+error.  Also reported: one 3-component chain alone (no batching of chains); the integrated
+autocorrelation time of each observable; per-step p50/p99 latency; the whole cycle against the
+algorithmic-byte roofline; one FP64 chain on a single 512x512x256 grid, whose fields exceed the
+256 MB Infinity Cache (cycles/s and the level-0 pass against HBM); 10 solves to 1e-12 (batched
+throughput and single latency); the roofline of the dominant kernel class (per-launch time from
+HIP events around each sweep's launches) and of the other; and the CPU oracle on a bounded
+sample.
 
 The FP32-refined form of the same workload (FP32 sweeps and transfers, FP64 residual,
 correction and coarsest arithmetic) is measured beside it under "fp32_refined", with its
@@ -33,6 +37,7 @@ pass of its finest base level against HBM, and the oracle's FAC cycle on its 16^
 Run: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-refined]
                      [--no-composite]
      python bench.py --composite-only   (the adaptive workload alone)
+     python bench.py --batched-only     (the 64-instance batched workload alone)
      python bench.py --copy-calibration   (a plain 1 GiB copy, for counter calibration)
 """
 import argparse
@@ -87,7 +92,7 @@ def measured_traffic(kind, chains):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(k_dec, cycles=3):
+def cpu_baseline(k_dec, cycles=15):
     """The CPU oracle (FP64 NumPy/SciPy, one thread) on a bounded sample of the workload."""
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -224,47 +229,56 @@ def time_solves(Hsingle, Hbatch, fs, rtol):
     return single_s, batch_s, ratios, cyc
 
 
-def measure(precision, args, fs, dev):
-    """Sampling, kernel timing and solves of one precision mode."""
+def measure_solves(precision, fs, rtol=1e-12):
+    """Latency of one 3-component solve and the batched throughput of all right-hand sides;
+    the contraction each solve measures."""
     import numpy as np
     import torch
     from paper_1003_2680_amd.api import Hierarchy
-
-    C = max(1, args.chains)
-    H = Hierarchy(NX, NY, NZ, ncomp=NCOMP * C, kT=1.0, levels=LEVELS, nu1=2, nu2=2,
-                  precision=precision)
-    out = torch.empty((SAMPLES_PER_STEP, NCOMP * C, NZ, NY, NX), dtype=torch.float64,
-                      device=dev)
-    ms, lat, obs, state = run_batch(H, C, args.steps, args.warmup, SAMPLES_PER_STEP, out)
-    res = {"ms_per_step": ms, "lat": lat, "obs": obs}
-    # per-launch kernel times: HIP events bracketing each sweep's colour passes (or the
-    # bottom launch) on the batch's stream, over the same number of further steps (the
-    # FP32-refined form: its FP32 level-0 colour pass only)
-    cyc_timed = args.steps * SAMPLES_PER_STEP
-    kern = {}
-    names = ("fine_pass", "level1_block_pass", "bottom") if precision == "fp64" \
-        else ("fine_pass",)
-    for name in names:
-        H.kernel_timing(True, name)
-        torch.cuda.synchronize()
-        for _ in range(args.steps):
-            H.sample_batch(SAMPLES_PER_STEP, nchains=C, comps_per_chain=NCOMP, state=state,
-                           out=out)
-        torch.cuda.synchronize()
-        n_l, k_ms = H.kernel_timing_read()
-        H.kernel_timing(False, name)
-        kern[name] = {"launches": n_l, "avg_launch_s": k_ms / 1e3 / max(n_l, 1),
-                      "per_cycle_s": k_ms / 1e3 / cyc_timed}
-    res["kern"] = kern
-    del H, out, state
-    torch.cuda.empty_cache()
     Hs = Hierarchy(NX, NY, NZ, ncomp=NCOMP, kT=1.0, levels=LEVELS, precision=precision)
     Hb = Hierarchy(NX, NY, NZ, ncomp=NCOMP * len(fs), kT=1.0, levels=LEVELS,
                    precision=precision)
-    single_s, batch_s, ratios, cyc = time_solves(Hs, Hb, fs, 1e-12)
-    res.update({"solve_single_s": single_s, "solve_batch_s": batch_s, "rho": max(ratios),
-                "solve_cycles": float(np.mean(cyc))})
+    single_s, batch_s, ratios, cyc = time_solves(Hs, Hb, fs, rtol)
     del Hs, Hb
+    torch.cuda.empty_cache()
+    return {"solve_single_s": single_s, "solve_batch_s": batch_s, "rho": max(ratios),
+            "solve_cycles": float(np.mean(cyc))}
+
+
+def measure(precision, args, dev, stride, chains, steps, timing=True):
+    """Sampling (and per-launch kernel times) of one precision mode: `chains` chains of the
+    3-component field batched, one emitted sample every `stride` cycles."""
+    import torch
+    from paper_1003_2680_amd.api import Hierarchy
+
+    C = chains
+    H = Hierarchy(NX, NY, NZ, ncomp=NCOMP * C, kT=1.0, levels=LEVELS, nu1=2, nu2=2,
+                  precision=precision, stride=stride, burn_in=0)
+    out = torch.empty((SAMPLES_PER_STEP, NCOMP * C, NZ, NY, NX), dtype=torch.float64,
+                      device=dev)
+    ms, lat, obs, state = run_batch(H, C, steps, args.warmup, SAMPLES_PER_STEP, out)
+    res = {"ms_per_step": ms, "lat": lat, "obs": obs}
+    if timing:
+        # per-launch kernel times: HIP events bracketing each sweep's colour passes (or the
+        # bottom launch) on the batch's stream, over the same number of further steps (the
+        # FP32-refined form: its FP32 level-0 colour pass only)
+        cyc_timed = steps * SAMPLES_PER_STEP * stride
+        kern = {}
+        names = ("fine_pass", "level1_block_pass", "bottom") if precision == "fp64" \
+            else ("fine_pass",)
+        for name in names:
+            H.kernel_timing(True, name)
+            torch.cuda.synchronize()
+            for _ in range(steps):
+                H.sample_batch(SAMPLES_PER_STEP, nchains=C, comps_per_chain=NCOMP,
+                               state=state, out=out)
+            torch.cuda.synchronize()
+            n_l, k_ms = H.kernel_timing_read()
+            H.kernel_timing(False, name)
+            kern[name] = {"launches": n_l, "avg_launch_s": k_ms / 1e3 / max(n_l, 1),
+                          "per_cycle_s": k_ms / 1e3 / cyc_timed}
+        res["kern"] = kern
+    del H, out, state
     torch.cuda.empty_cache()
     return res
 
@@ -452,10 +466,12 @@ def measure_composite(dev, cycles=20, with_cpu=True):
 
 
 def measure_batched(dev, n_instances=64, n_samples=100):
-    """64 uneven instances ({32,48,64,96}^3 drawn by seed), FP32-refined, tuned per grid:
-    100 samples (float32, in HBM) and one solve to 1e-10 per instance, grouped launches; beside
-    it the plain FP64 V(2,2) form run instance by instance (timed on 10 cycles each, scaled),
-    and the refined form's error against FP64 on the same streams."""
+    """64 uneven instances ({32,48,64,96}^3 drawn by seed), tuned per grid: 100 samples
+    (float32, in HBM) and one solve to 1e-10 per instance.  The FP32-refined form through the
+    library's batch call (cycles in step, the small levels of all instances in merged
+    launches), eager and as one replayed graph; the same through one stream per grid group;
+    the batched plain FP64 form at the same configuration and solve tolerance; and the
+    refined form's error against FP64 on the same streams."""
     import numpy as np
     import torch
     from paper_1003_2680_amd.api import Hierarchy
@@ -464,17 +480,35 @@ def measure_batched(dev, n_instances=64, n_samples=100):
 
     sizes = batched_sizes(n_instances)
     insts = [Instance((e, e, e), seed=1000 + i) for i, e in enumerate(sizes)]
+
+    def timed_sample(R, emit=True):
+        R.start()
+        R.sample(2, emit=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = R.sample(n_samples, out_dtype=torch.float32, emit=emit)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        del outs
+        return dt
+
+    def timed_solve(R):
+        fs = {i: gaussian_field_device(inst.dims[::-1], 2000 + i, dev)
+              for i, inst in enumerate(insts)}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        us, infos = R.solve(fs, rtol=1e-10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cyc = max(v[0] for v in infos.values())
+        del us, fs
+        return dt, cyc
+
     t0 = time.perf_counter()
     R = BatchRunner(insts, precision="fp32_refined", tune=True, device=dev)
     tune_s = time.perf_counter() - t0
-    R.start()
-    R.sample(2, emit=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = R.sample(n_samples, out_dtype=torch.float32)
-    torch.cuda.synchronize()
-    sample_s = time.perf_counter() - t0
-    del outs
+    configs = R.configs
+    sample_s = timed_sample(R)
     R.capture(n_samples)
     R.replay()
     torch.cuda.synchronize()
@@ -482,18 +516,23 @@ def measure_batched(dev, n_instances=64, n_samples=100):
     R.replay()
     torch.cuda.synchronize()
     graph_s = time.perf_counter() - t0
-    fs = {i: gaussian_field_device(inst.dims[::-1], 2000 + i, dev) for i, inst in enumerate(insts)}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    us, infos = R.solve(fs, rtol=1e-10)
-    torch.cuda.synchronize()
-    solve_s = time.perf_counter() - t0
+    solve_s, solve_cyc = timed_solve(R)
+    cells = R.cells()
+    del R
+    torch.cuda.empty_cache()
+    Rs = BatchRunner(insts, precision="fp32_refined", configs=configs, device=dev,
+                     engine="streams")
+    streams_s = timed_sample(Rs)
+    del Rs
+    torch.cuda.empty_cache()
+    R64 = BatchRunner(insts, precision="fp64", configs=configs, device=dev)
+    fp64_s = timed_sample(R64)
+    fp64_solve_s, fp64_solve_cyc = timed_solve(R64)
+    del R64
+    torch.cuda.empty_cache()
     cfgs = {"%dx%dx%d" % d: {k: (round(v, 6) if isinstance(v, float) else v)
                              for k, v in c.items() if k != "table"}
-            for d, c in R.configs.items()}
-    cells = R.cells()
-    del R, us, fs
-    torch.cuda.empty_cache()
+            for d, c in configs.items()}
     # plain FP64 form, one instance at a time (10 cycles each, scaled to n_samples cycles)
     plain_s = 0.0
     err = {}
@@ -515,15 +554,36 @@ def measure_batched(dev, n_instances=64, n_samples=100):
         err["%d^3" % e] = float("%.3e" % float(((a - b).norm() / a.norm()).item()))
         del H, H32, a, b, o, st
     torch.cuda.empty_cache()
+    # algorithmic bytes per cell-cycle of the sample cycle: ~106 (FP32-refined) and ~108.6
+    # (FP64) bytes per cell
+    def roof(seconds, bpc):
+        ach = cells * n_samples * bpc / seconds / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "bytes_per_cell_cycle": bpc}
     return {"workload": "%d instances, grids {32,48,64,96}^3 drawn by seed 2026, scalar, "
-                        "FP32-refined, tuned per grid" % n_instances,
+                        "tuned per grid" % n_instances,
             "cells": cells, "groups": len(cfgs), "configs": cfgs,
             "tune_s": round(tune_s, 2),
-            "instance_samples_per_s": round(n_instances * n_samples / sample_s, 1),
-            "sample_s": round(sample_s, 4), "graph_replay_cycles_s": round(graph_s, 4),
-            "solve_all_s": round(solve_s, 4),
+            "fp32_refined": {
+                "engine": "smg_batch_run (one stream, merged bottom launches)",
+                "instance_samples_per_s": round(n_instances * n_samples / sample_s, 1),
+                "sample_s": round(sample_s, 4),
+                "graph_replay_cycles_s": round(graph_s, 4),
+                "per_group_streams_sample_s": round(streams_s, 4),
+                "solve_all_s": round(solve_s, 4), "solve_cycles_max": solve_cyc,
+                "roofline": roof(sample_s, 106.0),
+                "roofline_graph": roof(graph_s, 106.0)},
+            "fp64": {
+                "engine": "smg_batch_run (one stream, merged bottom launches)",
+                "instance_samples_per_s": round(n_instances * n_samples / fp64_s, 1),
+                "sample_s": round(fp64_s, 4),
+                "solve_all_s": round(fp64_solve_s, 4), "solve_cycles_max": fp64_solve_cyc,
+                "roofline": roof(fp64_s, 108.6)},
+            "equal_accuracy": "both solve to 1e-10; samples of the refined form differ from the "
+                              "FP64 form on the same streams by the relative RMS below",
             "plain_fp64_sequential_s_est": round(plain_s, 3),
-            "speedup_vs_plain_fp64_sequential": round(plain_s / sample_s, 2),
+            "speedup_refined_vs_plain_fp64_sequential": round(plain_s / sample_s, 2),
             "refined_rel_rms_vs_fp64_2_cycles": err}
 
 
@@ -574,6 +634,8 @@ def main():
                     help="skip the adaptive composite-grid leg")
     ap.add_argument("--composite-only", action="store_true",
                     help="only run the adaptive composite-grid leg (prints its object)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 64-instance batched leg (prints its object)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -583,6 +645,11 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batched_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"batched": measure_batched(torch.device("cuda", 0))}), flush=True)
         return
     if args.composite_only:
         import torch
@@ -604,14 +671,29 @@ def main():
     fs = [torch.from_numpy(gaussian_field(shape, 100 + i)).to(dev)
           for i in range(max(args.solves, 1))]
 
-    r64 = measure("fp64", args, fs, dev)
+    # the contraction of the cycle, measured by the deterministic solves, fixes the stride of
+    # decorrelated samples: the lag-k correlation of the chain is R^k applied to its stationary
+    # covariance, so k_dec = ceil(ln 0.01 / ln rho) cycles separate nearly independent draws
+    s64 = measure_solves("fp64", fs)
+    rho_solve = s64["rho"]
+    k_dec = max(1, math.ceil(math.log(0.01) / math.log(rho_solve)))
+    r64 = measure("fp64", args, dev, k_dec, C, args.steps)
+    r64.update(s64)
     progress("fp64 sampling, kernel timing and solves done")
-    rho_solve = r64["rho"]
+    # every emitted sample is k_dec cycles after the previous one: its observables' lag-1
+    # correlation is the chain's lag-k_dec correlation, which must be below 0.01 up to the
+    # estimate's standard error
     rho_obs = lag1(r64["obs"])
-    rho = max(rho_solve, float(np.max(np.abs(rho_obs))))
-    k_dec = max(1, math.ceil(math.log(0.01) / math.log(rho)))
-    samples_per_s = C * SAMPLES_PER_STEP / (r64["ms_per_step"] / 1e3)
-    value = samples_per_s / k_dec
+    n_obs = r64["obs"].shape[0] * r64["obs"].shape[1]
+    se_obs = 1.0 / math.sqrt(n_obs)
+    decor = {"lag": k_dec, "max_abs_lag_corr": round(float(np.max(np.abs(rho_obs))), 4),
+             "bound": 0.01, "standard_error": round(se_obs, 4),
+             "ok": bool(float(np.max(np.abs(rho_obs))) <= 0.01 + 3.0 * se_obs)}
+    value = C * SAMPLES_PER_STEP / (r64["ms_per_step"] / 1e3)
+    samples_per_s = value
+    cycles_per_s = value * k_dec / C
+    r1 = measure("fp64", args, dev, k_dec, 1, max(10, args.steps // 4), timing=False)
+    progress("single 3-component chain done")
 
     N0 = NX * NY * NZ
     N1 = N0 // 8
@@ -648,13 +730,31 @@ def main():
                                "V(2,2) cycle, FP64; the chains of seeds 0..%d batched into "
                                "every launch" % (C - 1),
                    "grid": [NX, NY, NZ], "ncomp": NCOMP, "levels": LEVELS, "nu": [2, 2],
-                   "chains": C, "samples_per_step": C * SAMPLES_PER_STEP, "k_dec": k_dec},
+                   "chains": C, "samples_per_step": C * SAMPLES_PER_STEP, "k_dec": k_dec,
+                   "cycles_per_step": SAMPLES_PER_STEP * k_dec},
         "samples_per_s": round(samples_per_s, 2),
+        "emission": "one sample per chain every k_dec cycles (each emitted sample is a "
+                    "decorrelated one); value = emitted samples/s",
+        "cycles_per_s_3comp": round(cycles_per_s, 2),
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
-        "rho": round(rho, 5), "rho_solve": round(rho_solve, 5),
-        "rho_obs_lag1": [round(float(v), 4) for v in rho_obs],
-        "tau_int_obs": [round(float(v), 3) for v in tau_int(r64["obs"])],
+        "rho_solve": round(rho_solve, 5),
+        "decorrelation_check": decor,
+        "obs_lag1_of_emitted": [round(float(v), 4) for v in rho_obs],
+        "tau_int_obs_emitted": [round(float(v), 3) for v in tau_int(r64["obs"])],
+        "single_instance": {
+            "workload": "one chain of the 3-component 128^3 field (no batching of chains)",
+            "value": round(SAMPLES_PER_STEP / (r1["ms_per_step"] / 1e3), 3),
+            "ms_per_step": round(r1["ms_per_step"], 4),
+            "p99_ms": round(float(np.percentile(r1["lat"], 99)), 4)},
+        "cycle_roofline": {
+            "bound": "hbm", "bytes_per_component_cycle": round(108.6 * N0),
+            "achieved": round(cycles_per_s * C * NCOMP * 108.6 * N0 / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(cycles_per_s * C * NCOMP * 108.6 * N0 / 1e9 / HBM_PEAK_GBS, 4),
+            "model": "read and write x once per sweep on every level, b where present, the "
+                     "level-0 transfers (108.6 N bytes per FP64 component-cycle); emission "
+                     "time included"},
         "solves_per_s": round(len(fs) / r64["solve_batch_s"], 3),
         "solve_ms_single": round(r64["solve_single_s"] * 1e3, 3),
         "solve_cycles": round(r64["solve_cycles"], 2),
@@ -675,11 +775,12 @@ def main():
         rel_rms = float(((a - b).norm() / a.norm()).item())
         del H64, H32, a, b
         torch.cuda.empty_cache()
-        r32 = measure("fp32_refined", args, fs, dev)
+        r32 = measure("fp32_refined", args, dev, k_dec, C, args.steps)
+        r32.update(measure_solves("fp32_refined", fs))
         progress("fp32-refined form done")
         r_sps = C * SAMPLES_PER_STEP / (r32["ms_per_step"] / 1e3)
         line["fp32_refined"] = {
-            "value": round(r_sps / k_dec, 3), "samples_per_s": round(r_sps, 2),
+            "value": round(r_sps, 3), "samples_per_s": round(r_sps, 2),
             "ms_per_step": round(r32["ms_per_step"], 4),
             "p50_ms": round(float(np.percentile(r32["lat"], 50)), 4),
             "p99_ms": round(float(np.percentile(r32["lat"], 99)), 4),
@@ -687,7 +788,7 @@ def main():
             "solve_ms_single": round(r32["solve_single_s"] * 1e3, 3),
             "solve_cycles": round(r32["solve_cycles"], 2),
             "rho_solve": round(r32["rho"], 5),
-            "rho_obs_lag1_max": round(float(np.max(np.abs(lag1(r32["obs"])))), 4),
+            "obs_lag1_of_emitted_max": round(float(np.max(np.abs(lag1(r32["obs"])))), 4),
             "rel_rms_vs_fp64_2_cycles": float("%.3e" % rel_rms)}
         # the FP32 level-0 colour pass of the inner cycle (b = the FP32 residual): read the
         # other colour and this colour's b, write this colour, 4 B per value
