@@ -24,6 +24,9 @@ written so that each step can be checked against the paper by eye:
                    base levels.
 * ``observables`` -- projections onto eigenvectors of A, the energy 1/2 x^T A x and
                    per-cell moments of the samples (the decorrelation observables).
+* ``sampled``   -- the same steps evaluated cell by cell (a row of A, a heat-bath colour
+                   pass, the residual restriction, the prolongation) for parity at sampled
+                   cells of grids too large to assemble.
 
 The oracle shares no code with the HIP path; the two meet only on seeded inputs.
 """

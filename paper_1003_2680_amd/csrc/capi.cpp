@@ -1489,11 +1489,14 @@ int smg_debug_restrict_residual(smg_hierarchy* hh, int32_t level, const void* x,
   hipStream_t s = (hipStream_t)stream;
   const int nc = h.desc.ncomp;
   if (v.kind == KIND_POINT) {
+    // level 0: the cycle's own fused residual + restriction (the fine residual is never stored)
     SMG_TRY(import_level0(h, v.x, (const double*)x, s));
     if (b) SMG_TRY(import_level0(h, v.b, (const double*)b, s));
-    SMG_HIP(launch_residual0<double>(v.r, v.x, v.x + half_field(h), b ? v.b : nullptr,
-                                     b ? v.b + half_field(h) : nullptr, v.nx, v.ny, v.nz, nc,
-                                     h.desc.h, s));
+    SMG_HIP(launch_restrict_residual0<double>((double*)b_coarse, nullptr, v.x,
+                                              v.x + half_field(h), b ? v.b : nullptr,
+                                              b ? v.b + half_field(h) : nullptr, v.nx, v.ny,
+                                              v.nz, nc, h.desc.h, s));
+    return SMG_OK;
   } else {
     SMG_HIP(launch_residual_gal<double>(v.r, (const double*)x, (const double*)b,
                                         (const double*)v.s1d_d, (const double*)v.zt_d, v.nx,
