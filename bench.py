@@ -587,6 +587,52 @@ def measure_batched(dev, n_instances=64, n_samples=100):
             "refined_rel_rms_vs_fp64_2_cycles": err}
 
 
+def measure_selm(dev, dims=(128, 128, 128), m=64, steps=10):
+    """SELM coupling on the 128^3 channel with m structure points (Peskin 4-point coupling,
+    projection through the multigrid solve): mobility H F, driving field g (the stochastic
+    multigrid chain, stride 2) and Euler-Maruyama steps of a harmonic bead chain."""
+    import numpy as np
+    import torch
+    from paper_1003_2680_amd.selm import SELM
+    S = SELM(*dims, mu=1.0, kT=1.0, stride=2, max_points=m, device=dev)
+    rng = np.random.default_rng(8)
+    X0 = np.column_stack([rng.uniform(0, dims[0], m), rng.uniform(0, dims[1], m),
+                          rng.uniform(4.0, dims[2] - 4.0, m)])
+    X = torch.from_numpy(X0).to(dev)
+    x0 = X.clone()
+    F = torch.from_numpy(rng.standard_normal((m, 3))).to(dev)
+    state = S.new_state()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_mob = timed(lambda: S.mobility(X, F, rtol=1e-10), 3)
+    cyc = [0]
+
+    def drv():
+        S.drive(X, 5, cyc[0], state, rtol=1e-10)
+        cyc[0] += 2
+    t_drv = timed(drv, 3)
+    k = [0]
+
+    def stp():
+        S.step(X, -1.0 * (X - x0), 0.5, 7, k[0], state, rtol=1e-10)
+        k[0] += 1
+    t_step = timed(stp, steps)
+    del S, state
+    torch.cuda.empty_cache()
+    return {"workload": "SELM coupling: %dx%dx%d wall-bounded channel, 3-component Stokes "
+                        "velocity, %d structure points, FP64, solves to 1e-10" % (dims + (m,)),
+            "mobility_ms": round(t_mob * 1e3, 3), "drive_ms": round(t_drv * 1e3, 3),
+            "em_step_ms": round(t_step * 1e3, 3), "em_steps_per_s": round(1.0 / t_step, 2)}
+
+
 def measure_serving(dev, stride, rate=200.0, n=300):
     """Poisson arrivals (seed 7) of sample (k ~ U{1..16}, stride = burn-in = k_dec) and solve
     (1e-10) requests on grids nx = ny in {32..256}, nz in {16..128}, FP32-refined, 32 GB HBM
@@ -628,6 +674,8 @@ def main():
                     help="skip the 64-instance batched measurement")
     ap.add_argument("--no-hbm-point", action="store_true",
                     help="skip the single 512x512x256 grid (beyond the Infinity Cache)")
+    ap.add_argument("--no-selm", action="store_true",
+                    help="skip the SELM coupling leg")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-loop measurement")
     ap.add_argument("--no-composite", action="store_true",
@@ -805,6 +853,9 @@ def main():
     if not args.no_batched:
         line["batched"] = measure_batched(dev)
         progress("batched instances done")
+    if not args.no_selm:
+        line["selm"] = measure_selm(dev)
+        progress("SELM coupling done")
     if not args.no_serving:
         line["serving"] = measure_serving(dev, stride=k_dec)
         progress("serving done")

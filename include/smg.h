@@ -435,6 +435,60 @@ int smg_composite_debug_row(const smg_composite* h, int32_t level, int64_t cell,
                             int64_t* targets, double* vals, int32_t* count);
 void smg_composite_destroy(smg_composite* h);
 
+/* ==== SELM coupling of elastic structures to the wall-bounded Stokes fluid ===============
+ * Sec. "Stochastic Eulerian-Lagrangian Method for Fluid-Structure Interactions", Sec.
+ * "Discretization of SELM Hydrodynamic Coupling Tensor", Sec. "Generation of the Stochastic
+ * Driving Fields Accounting for Thermal Fluctuations" and the algorithm "Stochastic Dynamics of
+ * Elastic Structures with Hydrodynamic Coupling".  Fluid: three cell-centred velocity
+ * components on the grid of smg_grid_desc (periodic x, y; no-slip walls on the z faces), each
+ * with the viscous operator L = -mu A.  Structure points X: device float64 [m][3] positions with
+ * 0 < z < nz h (points outside get zero weights).
+ *   P = I - D^T A^-1 D with D = delta_x u_x + delta_y u_y + a_z^{1/2} u_z (periodic forward
+ *     differences, the symmetric square root of the 1D wall operator), so D D^T = A: P is
+ *     symmetric, idempotent, D P = 0, and P commutes with L (the properties the paper asks of
+ *     the discrete projection); applying it takes one multigrid solve to rtol.
+ *   Gamma: Peskin's 4-point interpolation (cells beyond a wall enter as antisymmetric ghosts);
+ *     Lambda = alpha Gamma^T with alpha = 1/h^3.
+ *   H F = -Gamma P L^-1 P Lambda F (eq. H_selm_discr); g = sqrt(2 kT alpha) Gamma P xi with
+ *     xi ~ N(0, A^-1 / mu) drawn by the stochastic multigrid chain, so <g g^T> = 2 kT H
+ *     (eqs. G_special_form, g_gen_xi).
+ *   Step: X <- X + dt H(X) F + sqrt(dt) g(X) (Euler-Maruyama), F given by the caller. */
+typedef struct smg_selm smg_selm;
+typedef struct {
+  int32_t nx, ny, nz;   /* fluid grid: nx, ny even */
+  double h, mu, kT;     /* grid width, viscosity, temperature */
+  int32_t levels;       /* multigrid depth (0: automatic, coarsest <= 512 unknowns) */
+  int32_t stride;       /* chain cycles between successive driving fields (>= 1) */
+  int32_t max_points;   /* largest number of structure points per call */
+} smg_selm_desc;
+typedef struct {
+  size_t workspace_bytes;  /* device bytes smg_selm_bind needs */
+  size_t state_bytes;      /* bytes of the driving-field chain state: 3 nx ny nz float64 */
+  int32_t n_levels;
+} smg_selm_info;
+/* Plans the two hierarchies (the 3-component sampler/solver and the scalar projection solve)
+ * and the square root of the wall operator (from its closed-form eigenvectors).  Host only. */
+int smg_selm_create(const smg_selm_desc* desc, smg_selm** out);
+int smg_selm_get_info(const smg_selm* s, smg_selm_info* info);
+/* Binds caller-owned device memory (>= workspace_bytes, 256-byte aligned), uploads the tables
+ * on `stream` and synchronises it. */
+int smg_selm_bind(smg_selm* s, void* ws, size_t bytes, void* stream);
+/* pu = P u for a velocity field u [3][nz][ny][nx] (pu may be u).  Synchronises (solve). */
+int smg_selm_project(smg_selm* s, const void* u, void* pu, double rtol, void* stream);
+/* V = H F for m points (X, F, V device float64 [m][3]).  Synchronises (solves). */
+int smg_selm_mobility(smg_selm* s, int32_t m, const void* X, const void* F, void* V, double rtol,
+                      void* stream);
+/* g = sqrt(2 kT alpha) Gamma P xi: advances the driving-field chain `state` (device, state_bytes,
+ * zero for a new chain) by `stride` cycles of the stochastic multigrid sampler (noise counters
+ * from seed and first_cycle) and projects and interpolates its field.  Synchronises. */
+int smg_selm_drive(smg_selm* s, int32_t m, const void* X, uint64_t seed, uint64_t first_cycle,
+                   void* state, void* g, double rtol, void* stream);
+/* One Euler-Maruyama step: X <- X + dt H F + sqrt(dt) g with g from the chain at cycle
+ * step * stride.  Errors: SMG_EINVAL, SMG_ESTATE, SMG_EHIP, SMG_ENOTCONV (a solve). */
+int smg_selm_step(smg_selm* s, int32_t m, void* X, const void* F, double dt, uint64_t seed,
+                  uint64_t step, void* state, double rtol, void* stream);
+void smg_selm_destroy(smg_selm* s);
+
 #ifdef __cplusplus
 }
 #endif

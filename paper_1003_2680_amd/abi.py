@@ -49,7 +49,9 @@ EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
             "smg_composite_cycle", "smg_composite_sample", "smg_composite_residual",
             "smg_composite_solve", "smg_composite_debug_pass", "smg_composite_debug_base_pass",
             "smg_composite_debug_row", "smg_composite_destroy", "smg_sample_field_static",
-            "smg_batch_run"]
+            "smg_batch_run", "smg_selm_create", "smg_selm_get_info", "smg_selm_bind",
+            "smg_selm_project", "smg_selm_mobility", "smg_selm_drive", "smg_selm_step",
+            "smg_selm_destroy"]
 
 
 class GridDesc(ctypes.Structure):
@@ -105,6 +107,18 @@ class CompositeInfo(ctypes.Structure):
                 ("dims", (ctypes.c_int32 * 3) * 16), ("stencils", ctypes.c_int32 * 16),
                 ("block_types", ctypes.c_int32 * 16), ("layer_cells", ctypes.c_int32),
                 ("coarsest_unknowns", ctypes.c_int32)]
+
+
+class SelmDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double), ("mu", ctypes.c_double), ("kT", ctypes.c_double),
+                ("levels", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("max_points", ctypes.c_int32)]
+
+
+class SelmInfo(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_size_t), ("state_bytes", ctypes.c_size_t),
+                ("n_levels", ctypes.c_int32)]
 
 
 class SMGError(RuntimeError):
@@ -179,6 +193,15 @@ def load():
         "smg_composite_debug_row": ([H, I32, ctypes.c_int64, P, P, ctypes.POINTER(I32)],
                                     ctypes.c_int),
         "smg_composite_destroy": ([H], None),
+        "smg_selm_create": ([ctypes.POINTER(SelmDesc), ctypes.POINTER(H)], ctypes.c_int),
+        "smg_selm_get_info": ([H, ctypes.POINTER(SelmInfo)], ctypes.c_int),
+        "smg_selm_bind": ([H, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg_selm_project": ([H, P, P, ctypes.c_double, P], ctypes.c_int),
+        "smg_selm_mobility": ([H, I32, P, P, P, ctypes.c_double, P], ctypes.c_int),
+        "smg_selm_drive": ([H, I32, P, U64, U64, P, P, ctypes.c_double, P], ctypes.c_int),
+        "smg_selm_step": ([H, I32, P, P, ctypes.c_double, U64, U64, P, ctypes.c_double, P],
+                          ctypes.c_int),
+        "smg_selm_destroy": ([H], None),
     })
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

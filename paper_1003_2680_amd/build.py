@@ -12,7 +12,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libsmg.so")
 SOURCES = ["plan.cpp", "capi.cpp", "kernels_fine.hip", "kernels_gal.hip", "kernels_util.hip",
-           "kernels_stats.hip", "capi_comp.cpp", "kernels_comp.hip", "capi_static.hip"]
+           "kernels_stats.hip", "capi_comp.cpp", "kernels_comp.hip", "capi_static.hip",
+           "capi_selm.cpp", "kernels_selm.hip"]
 ARCH = os.environ.get("SMG_OFFLOAD_ARCH", "gfx950")
 
 
