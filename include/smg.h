@@ -435,6 +435,47 @@ int smg_composite_debug_row(const smg_composite* h, int32_t level, int64_t cell,
                             int64_t* targets, double* vals, int32_t* count);
 void smg_composite_destroy(smg_composite* h);
 
+/* ==== Two-dimensional wall-bounded grid ==================================================
+ * The paper compares the multigrid sampler with stochastic Gauss-Seidel on 2D and 3D meshes
+ * (Sec. "Performance of the Stochastic Samplers in Practice").  Cells (x, z) of width h on
+ * nx x nz, periodic in x, no-slip walls on the faces z = 0 and z = nz h (antisymmetric ghost);
+ * A = -L the 5-point operator.  Level 0 smooths by a red-black point heat bath (nx even); a
+ * Galerkin level (A_{l+1} = P^T A_l P, bilinear P) by a 2 x 2 block heat bath with block colour
+ * (bx % 2) + 2 (bz % 2) when nx_l % 4 == 0 and nz_l is even; the coarsest level is drawn exactly
+ * (dense Cholesky, <= 4096 unknowns) or smoothed (coarsest_mode); levels as for the 3D grid
+ * (0 = coarsen while a level has more than coarsest_max unknowns).  With levels = 1 and
+ * SMG_COARSEST_SMOOTH the chain is the plain stochastic Gauss-Seidel sampler.  Fields: device
+ * float64 [ncomp][nz][nx]; components are independent chains (comp id in the noise counter:
+ * site pair, level | slot<<4 | colour<<12 | comp<<16 | kind<<24, cycle; level-0 site =
+ * (x + nx z) >> 1, block-level site = 4 block + in-block index dx + 2 dz, coarsest site = row). */
+typedef struct smg2d smg2d;
+typedef struct {
+  int32_t nx, nz, ncomp;
+  double h, kT;
+  int32_t levels, nu1, nu2, coarsest_max, coarsest_mode;
+  int32_t stride;       /* cycles per emitted sample (>= 1) */
+} smg2d_desc;
+typedef struct {
+  size_t workspace_bytes;
+  int32_t n_levels;
+  int32_t dims[16][2];  /* (nx, nz) per level, finest first */
+} smg2d_info;
+/* Plans the 2D hierarchy on the host.  Errors: SMG_EINVAL (shape or parameters). */
+int smg2d_create(const smg2d_desc* desc, smg2d** out);
+int smg2d_get_info(const smg2d* h, smg2d_info* info);
+/* Binds caller-owned device memory (>= workspace_bytes, 256-byte aligned), uploads the tables
+ * on `stream` and synchronises it. */
+int smg2d_bind(smg2d* h, void* ws, size_t bytes, void* stream);
+/* n * stride cycles from `state` (read, and written at the end), cycle indices first_cycle, ...;
+ * out[i] (device [n][ncomp][nz][nx]) receives the field after cycle (i + 1) * stride. */
+int smg2d_sample(smg2d* h, int64_t n, uint64_t seed, uint64_t first_cycle, void* state,
+                 void* out, void* stream);
+/* A u = f by noise-free cycles from u = 0 until the largest relative residual over the
+ * components is <= rtol; synchronises every cycle.  Errors as smg_solve. */
+int smg2d_solve(smg2d* h, const void* f, void* u, double rtol, int32_t max_cycles, void* stream,
+                smg_solve_info* info);
+void smg2d_destroy(smg2d* h);
+
 /* ==== SELM coupling of elastic structures to the wall-bounded Stokes fluid ===============
  * Sec. "Stochastic Eulerian-Lagrangian Method for Fluid-Structure Interactions", Sec.
  * "Discretization of SELM Hydrodynamic Coupling Tensor", Sec. "Generation of the Stochastic

@@ -51,7 +51,8 @@ EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
             "smg_composite_debug_row", "smg_composite_destroy", "smg_sample_field_static",
             "smg_batch_run", "smg_selm_create", "smg_selm_get_info", "smg_selm_bind",
             "smg_selm_project", "smg_selm_mobility", "smg_selm_drive", "smg_selm_step",
-            "smg_selm_destroy"]
+            "smg_selm_destroy", "smg2d_create", "smg2d_get_info", "smg2d_bind", "smg2d_sample",
+            "smg2d_solve", "smg2d_destroy"]
 
 
 class GridDesc(ctypes.Structure):
@@ -119,6 +120,19 @@ class SelmDesc(ctypes.Structure):
 class SelmInfo(ctypes.Structure):
     _fields_ = [("workspace_bytes", ctypes.c_size_t), ("state_bytes", ctypes.c_size_t),
                 ("n_levels", ctypes.c_int32)]
+
+
+class Desc2D(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("ncomp", ctypes.c_int32),
+                ("h", ctypes.c_double), ("kT", ctypes.c_double), ("levels", ctypes.c_int32),
+                ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
+                ("coarsest_max", ctypes.c_int32), ("coarsest_mode", ctypes.c_int32),
+                ("stride", ctypes.c_int32)]
+
+
+class Info2D(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_size_t), ("n_levels", ctypes.c_int32),
+                ("dims", (ctypes.c_int32 * 2) * 16)]
 
 
 class SMGError(RuntimeError):
@@ -202,6 +216,13 @@ def load():
         "smg_selm_step": ([H, I32, P, P, ctypes.c_double, U64, U64, P, ctypes.c_double, P],
                           ctypes.c_int),
         "smg_selm_destroy": ([H], None),
+        "smg2d_create": ([ctypes.POINTER(Desc2D), ctypes.POINTER(H)], ctypes.c_int),
+        "smg2d_get_info": ([H, ctypes.POINTER(Info2D)], ctypes.c_int),
+        "smg2d_bind": ([H, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg2d_sample": ([H, ctypes.c_int64, U64, U64, P, P, P], ctypes.c_int),
+        "smg2d_solve": ([H, P, P, ctypes.c_double, I32, P, ctypes.POINTER(SolveInfo)],
+                        ctypes.c_int),
+        "smg2d_destroy": ([H], None),
     })
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

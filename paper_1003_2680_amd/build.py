@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libsmg.so")
 SOURCES = ["plan.cpp", "capi.cpp", "kernels_fine.hip", "kernels_gal.hip", "kernels_util.hip",
            "kernels_stats.hip", "capi_comp.cpp", "kernels_comp.hip", "capi_static.hip",
-           "capi_selm.cpp", "kernels_selm.hip"]
+           "capi_selm.cpp", "kernels_selm.hip", "capi_2d.cpp", "kernels_2d.hip"]
 ARCH = os.environ.get("SMG_OFFLOAD_ARCH", "gfx950")
 
 

@@ -25,6 +25,8 @@ bool can_smooth(int l, int nx, int ny, int nz) {
   return nx % 4 == 0 && ny % 4 == 0 && nz % 2 == 0;
 }
 
+}  // namespace
+
 // s'[D] = sum_{u,v in -1..2} p[u] p[v] s[2D + v - u]  (periodic-axis Galerkin step)
 void coarsen_stencil(const double s[5], double out[5]) {
   for (int D = -2; D <= 2; ++D) {
@@ -132,6 +134,8 @@ std::vector<double> ring_matrix(const double s[5], int n) {
     for (int d = -2; d <= 2; ++d) M[(size_t)i * n + (((i + d) % n) + n) % n] += s[d + 2];
   return M;
 }
+
+namespace {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 

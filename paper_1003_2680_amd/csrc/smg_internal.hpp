@@ -93,6 +93,19 @@ struct Hierarchy {
 
 // plan.cpp
 int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, std::string& err);
+// 1D Galerkin pieces and dense factors (plan.cpp), shared by the other planners:
+// the periodic-axis Galerkin step of a 5-entry stencil; the dense wall-axis prolongation
+// (2nc x nc, the ghost beyond a wall is -c); P^T M P; in-place lower Cholesky (false if not
+// positive definite); W = L^-1; A^-1 = W^T W.
+void coarsen_stencil(const double s[5], double out[5]);
+std::vector<double> prolong_wall(int nc);
+std::vector<double> galerkin_dense(const std::vector<double>& M, const std::vector<double>& P,
+                                   int nf, int nc);
+bool cholesky(std::vector<double>& A, int n);
+std::vector<double> lower_inverse(const std::vector<double>& L, int n);
+std::vector<double> inverse_from_w(const std::vector<double>& W, int n);
+// dense folded periodic matrix of a 5-entry stencil on an extent-n ring
+std::vector<double> ring_matrix(const double s[5], int n);
 
 // error helpers (capi.cpp)
 void set_error(const std::string& msg);

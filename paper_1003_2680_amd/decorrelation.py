@@ -1,6 +1,6 @@
 """Decorrelation of the stochastic multigrid chain against the plain stochastic Gauss-Seidel
 sampler, as the grid grows (Sec. "Stochastic Iterative Methods" and the paper's comparison of
-the two samplers).
+the two samplers, on 3D grids, on 2D grids and on adaptive composite grids).
 
 Both chains run in the library: the multigrid chain is the V(nu1, nu2) cycle; the
 Gauss-Seidel chain is the same hierarchy reduced to one level whose "coarsest" step is nu1 +
@@ -28,6 +28,93 @@ def make_chain(dims, kind, nchains=8, kT=1.0, nu=(2, 2), burn_in=0, device=None)
         return Hierarchy(*dims, ncomp=nchains, kT=kT, levels=1, coarsest="smooth",
                          nu1=nu[0], nu2=nu[1], burn_in=burn_in, device=device)
     raise ValueError("kind must be 'mg' or 'gs'")
+
+
+def make_chain_2d(dims, kind, nchains=8, kT=1.0, nu=(2, 2), stride=1, device=None):
+    """The 2D grid (nx, nz): 'mg' the multigrid cycle (automatic depth, coarsest <= 512
+    unknowns), 'gs' one level of heat-bath sweeps only; a sample every `stride` cycles."""
+    from .grid2d import Hierarchy2D
+    nx, nz = dims
+    if kind == "mg":
+        return Hierarchy2D(nx, nz, ncomp=nchains, kT=kT, levels=0, nu1=nu[0], nu2=nu[1],
+                           stride=stride, device=device)
+    if kind == "gs":
+        return Hierarchy2D(nx, nz, ncomp=nchains, kT=kT, levels=1, coarsest="smooth",
+                           nu1=nu[0], nu2=nu[1], stride=stride, device=device)
+    raise ValueError("kind must be 'mg' or 'gs'")
+
+
+def mode_vectors_2d(dims, modes, device):
+    """Real eigenvectors e_a(x) w_m(z) of the 2D operator (e_a as for the 3D observables, w_m the
+    normalised cell-centred sine), [len(modes), nz * nx] float64."""
+    nx, nz = dims
+    i = torch.arange(nx, dtype=torch.float64, device=device)
+    zc = torch.arange(nz, dtype=torch.float64, device=device) + 0.5
+    vecs = []
+    for a, m in modes:
+        if a == 0:
+            ex = torch.full((nx,), 1.0 / np.sqrt(nx), dtype=torch.float64, device=device)
+        elif a == nx - 1:
+            ex = torch.where(i.remainder(2) == 0, 1.0, -1.0) / np.sqrt(nx)
+        else:
+            j = (a + 1) // 2
+            ang = 2.0 * np.pi * j * i / nx
+            ex = np.sqrt(2.0 / nx) * (torch.cos(ang) if a % 2 else torch.sin(ang))
+        w = torch.sin(np.pi * m * zc / nz)
+        w = w / torch.linalg.norm(w)
+        vecs.append(torch.outer(w, ex).reshape(-1))
+    return torch.stack(vecs)
+
+
+def projections_2d(samples, dims, modes):
+    """Projections of 2D samples [n, nchains, nz, nx] on the given modes: [n, nchains, Q]
+    (observables of the study; not part of the sampler)."""
+    V = mode_vectors_2d(dims, modes, samples.device)
+    n, c = samples.shape[:2]
+    return (samples.reshape(n * c, -1) @ V.T).reshape(n, c, -1)
+
+
+def study_2d(sizes=((32, 32), (64, 64), (128, 128)), nchains=8, n_mg=2000,
+             gs_cycles_per_tau=100, device=None, seed=0):
+    """The 2D form of the comparison: per (grid, sampler) the lag-1 correlation (per cycle) and
+    tau_int (in cycles) of the lowest mode, cycles/s and the cost of one decorrelated sample.
+    The Gauss-Seidel chains emit every tau_guess/10 cycles (tau_guess from the lowest
+    eigenvalue) and run about gs_cycles_per_tau times tau_guess after ten of them of burn-in."""
+    rows = []
+    for dims in sizes:
+        nz = dims[1]
+        lam = 4.0 * np.sin(np.pi / (2 * nz)) ** 2
+        tau_guess = max(2.0, 2.0 / (4 * lam / 3.0))
+        for kind in ("mg", "gs"):
+            stride = 1 if kind == "mg" else max(1, int(tau_guess / 10))
+            H = make_chain_2d(dims, kind, nchains=nchains, stride=stride, device=device)
+            if kind == "mg":
+                burn, n = 20, n_mg
+            else:
+                burn = int(10 * tau_guess / stride) + 1
+                n = int(max(1000, gs_cycles_per_tau * tau_guess / stride))
+            _, st = H.sample(burn, seed)
+            torch.cuda.synchronize(H.device)
+            t0 = time.perf_counter()
+            xs, _ = H.sample(n, seed, first_cycle=burn * stride, state=st)
+            torch.cuda.synchronize(H.device)
+            dt = time.perf_counter() - t0
+            obs = projections_2d(xs, dims, [(0, 1), (1, 1)]).cpu().numpy()
+            del xs
+            rho_emit = float(autocorrelation(obs, 1)[1][0])
+            tau = float(tau_int(obs)[0]) * stride
+            cyc_s = n * stride / dt
+            rows.append({"grid": list(dims), "sampler": kind, "cycles": n * stride,
+                         "stride": stride,
+                         "rho1_lowest_mode": round(rho_emit ** (1.0 / stride)
+                                                   if rho_emit > 0 else rho_emit, 4),
+                         "tau_int_lowest_mode": round(tau, 2),
+                         "cycles_per_s": round(cyc_s, 1),
+                         "s_per_decorrelated_sample": round(tau / cyc_s, 6)})
+            print(json.dumps(rows[-1]), flush=True)
+            del H
+            torch.cuda.empty_cache()
+    return rows
 
 
 def observables(H, n, seed=0, modes=None):
@@ -173,8 +260,15 @@ def main(argv=None):
     ap.add_argument("--gs-cycles-per-tau", type=int, default=200)
     ap.add_argument("--composite", action="store_true",
                     help="run the comparison on adaptive composite grids (base e x e x e/2)")
+    ap.add_argument("--two-d", action="store_true",
+                    help="run the comparison on square 2D grids e x e (periodic x, walls in z)")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
+    if args.two_d:
+        study_2d(tuple((int(e), int(e)) for e in args.sizes.split(",")), nchains=args.chains,
+                 n_mg=args.mg_cycles, gs_cycles_per_tau=args.gs_cycles_per_tau,
+                 device=torch.device("cuda", 0))
+        return
     if args.composite:
         composite_study(tuple(int(e) for e in args.sizes.split(",")), n_mg=args.mg_cycles,
                         gs_cycles_per_tau=args.gs_cycles_per_tau)

@@ -52,7 +52,7 @@ def _table(lib, hd, level, which, count):
 
 def test_exports_match_header(lib):
     hdr = open(os.path.join(ROOT, "include", "smg.h")).read()
-    declared = set(re.findall(r"^(?:int|void|const char\*)\s+(smg_\w+)\(", hdr, re.M))
+    declared = set(re.findall(r"^(?:int|void|const char\*)\s+(smg\w+)\(", hdr, re.M))
     assert declared, "no declarations parsed"
     assert declared == set(abi.EXPORTED)
     for name in declared:
@@ -247,3 +247,24 @@ def test_lowest_modes_invalid(lib):
     arr = (ctypes.c_int32 * 3)()
     for args in ((7, 8, 8, 1), (8, 8, 8, 33), (8, 8, 8, -1), (2, 2, 1, 5)):
         assert lib.smg_lowest_modes(*args, arr) == abi.SMG_EINVAL
+
+
+def test_2d_plan_matches_oracle_levels(lib):
+    """The 2D planner takes the oracle's level plan; invalid shapes are refused."""
+    from oracle.mg2d import plan_levels
+    for (nx, nz, levels, cmax) in ((64, 32, 0, 512), (48, 16, 0, 64), (16, 8, 3, 512),
+                                   (12, 6, 0, 4096), (8, 5, 1, 512)):
+        d = abi.Desc2D(nx, nz, 1, 1.0, 1.0, levels, 2, 2, cmax, 0, 1)
+        hd = ctypes.c_void_p()
+        abi.check(lib.smg2d_create(ctypes.byref(d), ctypes.byref(hd)))
+        info = abi.Info2D()
+        abi.check(lib.smg2d_get_info(hd, ctypes.byref(info)))
+        got = [tuple(info.dims[l]) for l in range(info.n_levels)]
+        lib.smg2d_destroy(hd)
+        assert got == plan_levels(nx, nz, levels, cmax), (nx, nz, got)
+    for bad in (abi.Desc2D(7, 8, 1, 1.0, 1.0, 0, 2, 2, 512, 0, 1),
+                abi.Desc2D(8, 8, 0, 1.0, 1.0, 0, 2, 2, 512, 0, 1),
+                abi.Desc2D(8, 8, 1, 1.0, 1.0, 0, 2, 2, 512, 0, 0),
+                abi.Desc2D(12, 12, 1, 1.0, 1.0, 3, 2, 2, 512, 0, 1)):
+        hd = ctypes.c_void_p()
+        assert lib.smg2d_create(ctypes.byref(bad), ctypes.byref(hd)) == abi.SMG_EINVAL
