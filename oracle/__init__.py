@@ -27,6 +27,12 @@ written so that each step can be checked against the paper by eye:
 * ``sampled``   -- the same steps evaluated cell by cell (a row of A, a heat-bath colour
                    pass, the residual restriction, the prolongation) for parity at sampled
                    cells of grids too large to assemble.
+* ``selm``      -- the SELM coupling on the uniform grid: projection with D D^T = A,
+                   Peskin's 4-point interpolation, mobility and driving field, Euler-Maruyama.
+* ``mg2d``      -- the two-dimensional wall-bounded sampler (5-point operator, 2 x 2 blocks).
+* ``effective`` -- the effective structure dynamics of Appendix A for a non-symmetric L
+                   (drift, mobility, noise covariance, the Lyapunov relation of the forcing)
+                   and the composite-mesh field noise w = L^-1 Q eta.
 
 The oracle shares no code with the HIP path; the two meet only on seeded inputs.
 """
