@@ -421,6 +421,24 @@ int smg_composite_residual(smg_composite* h, const void* xc, const void* xf, con
  * after every cycle.  Errors as smg_solve. */
 int smg_composite_solve(smg_composite* h, const void* fc, const void* ff, void* uc, void* uf,
                         double rtol, int32_t max_cycles, void* stream, smg_solve_info* info);
+/* Field noise for a non-symmetric discretization (Appendix A).  On the composite mesh L = M^-1 S
+ * (M the diagonal of cell volumes) is not symmetric, and for a forcing Q = diag(q) that is not
+ * proportional to volume^-1/2 neither is L^-1 C (C the stationary covariance, L C + C L^T =
+ * -Q Q^T).  The appendix's noise covariance -(L^-1 C + C L^-T) equals L^-1 Q Q^T L^-T, so a
+ * draw is w = L^-1 Q eta with eta ~ N(0, I): this call forms b = -(volume/h^3) q eta (volume/h^3
+ * = 1 on coarse cells, 1/8 on fine cells) and solves A w = b like smg_composite_solve, once per
+ * draw.  Draw i uses eta from the streams (seed, counter cycle first_sample + i, level 0, slot 0,
+ * colour 0 for the coarse part with site = base cell, colour 1 for the fine part with site =
+ * fine index, component 0, kind 5).
+ * qc: base-grid float64 amplitudes (covered entries ignored), qf: fine-box float64 amplitudes,
+ * each NULL = 1.  wc: n x base_cells float64 (covered entries written 0), wf: n x fine_cells
+ * float64, the draws one after another.  infos: NULL or n records.  Uses the workspace's
+ * right-hand-side fields, so calls on one composite must not overlap.  Synchronises `stream`
+ * after every cycle.  Errors: SMG_EINVAL (arguments), SMG_ENOTCONV (a draw's solve did not
+ * reach rtol in max_cycles; earlier draws are complete), SMG_ENONFINITE, SMG_EHIP. */
+int smg_composite_forced_field(smg_composite* h, int64_t n, uint64_t seed, uint64_t first_sample,
+                               const void* qc, const void* qf, void* wc, void* wf, double rtol,
+                               int32_t max_cycles, void* stream, smg_solve_info* infos);
 /* Component entry points for the parity tests: one class pass (0..11) of a composite sweep;
  * one block-colour pass (0..7) on base level `level` (x, b natural layout of that level, b
  * NULL = 0); the stored row of base cell `cell` on level `level` (host only, up to 125

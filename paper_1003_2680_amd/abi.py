@@ -48,7 +48,8 @@ EXPORTED = ["smg_create_hierarchy", "smg_hierarchy_info", "smg_bind_workspace",
             "smg_composite_create", "smg_composite_get_info", "smg_composite_bind",
             "smg_composite_cycle", "smg_composite_sample", "smg_composite_residual",
             "smg_composite_solve", "smg_composite_debug_pass", "smg_composite_debug_base_pass",
-            "smg_composite_debug_row", "smg_composite_destroy", "smg_sample_field_static",
+            "smg_composite_debug_row", "smg_composite_destroy", "smg_composite_forced_field",
+            "smg_sample_field_static",
             "smg_batch_run", "smg_selm_create", "smg_selm_get_info", "smg_selm_bind",
             "smg_selm_project", "smg_selm_mobility", "smg_selm_drive", "smg_selm_step",
             "smg_selm_destroy", "smg2d_create", "smg2d_get_info", "smg2d_bind", "smg2d_sample",
@@ -207,6 +208,8 @@ def load():
         "smg_composite_debug_row": ([H, I32, ctypes.c_int64, P, P, ctypes.POINTER(I32)],
                                     ctypes.c_int),
         "smg_composite_destroy": ([H], None),
+        "smg_composite_forced_field": ([H, ctypes.c_int64, U64, U64, P, P, P, P, ctypes.c_double,
+                                        I32, P, ctypes.POINTER(SolveInfo)], ctypes.c_int),
         "smg_selm_create": ([ctypes.POINTER(SelmDesc), ctypes.POINTER(H)], ctypes.c_int),
         "smg_selm_get_info": ([H, ctypes.POINTER(SelmInfo)], ctypes.c_int),
         "smg_selm_bind": ([H, P, ctypes.c_size_t, P], ctypes.c_int),

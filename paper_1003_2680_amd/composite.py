@@ -113,6 +113,19 @@ class CompositeSampler:
                                                ctypes.byref(si)))
         return uc, uf, si
 
+    def forced_field(self, n, seed, first_sample=0, qc=None, qf=None, rtol=1e-10, max_cycles=100):
+        """n draws of the field noise w = L^-1 Q eta, Q = diag(q) (q None = 1): returns
+        (wc [n, nz, ny, nx], wf [n, fz, fy, fx], list of solve infos)."""
+        t = self.torch
+        self._chk(qc, qf)
+        wc = t.empty((n,) + self.base_shape, dtype=t.float64, device=self.device)
+        wf = t.empty((n,) + self.fine_shape, dtype=t.float64, device=self.device)
+        infos = (abi.SolveInfo * max(n, 1))()
+        abi.check(self.lib.smg_composite_forced_field(self._h, int(n), seed, first_sample,
+                                                      _ptr(qc), _ptr(qf), _ptr(wc), _ptr(wf),
+                                                      rtol, max_cycles, self._stream(), infos))
+        return wc, wf, list(infos)[:n]
+
     def debug_pass(self, cls, xc, xf, bc=None, bf=None, seed=0, cycle=0, slot=0, noise=True):
         self._chk(xc, xf, bc, bf)
         abi.check(self.lib.smg_composite_debug_pass(self._h, cls, _ptr(xc), _ptr(xf), _ptr(bc),

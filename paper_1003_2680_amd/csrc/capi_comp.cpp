@@ -35,6 +35,7 @@ namespace {
 constexpr uint32_t KIND_COMP = 2;
 constexpr uint32_t KIND_FAC_BASE = 3;
 constexpr uint32_t KIND_FAC_COARSEST = 4;
+constexpr uint32_t KIND_FORCING = 5;
 constexpr int kMaxCompLevels = 16;
 constexpr int kMaxDense = 4096;
 
@@ -113,7 +114,7 @@ struct Composite {
   int layer_off[9] = {0};
   size_t ws_bytes = 0, off_rc = 0, off_rf = 0, off_layer = 0, off_ainv = 0, off_w = 0,
          off_part = 0, off_norm = 0, off_znoise = 0, off_e32c = 0, off_e32f = 0, off_r32c = 0,
-         off_r32f = 0, off_rf32 = 0;
+         off_r32f = 0, off_rf32 = 0, off_fc = 0, off_ff = 0;
   char* ws = nullptr;
   int device = -1;
   double* rc = nullptr;
@@ -806,6 +807,8 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
   const size_t es = f32 ? 4 : 8;  // bytes of a value of the sweep precision
   C.off_rc = take(nbase * 8);
   C.off_rf = take(nf * 8);
+  C.off_fc = take(nbase * 8);  // right-hand side of the forced field
+  C.off_ff = take(nf * 8);
   C.off_layer = take(std::max<size_t>(1, C.layer.size()) * 4);
   if (f32) {
     C.off_e32c = take(nbase * 4);
@@ -997,6 +1000,63 @@ int check_bound(const smg_composite* h) {
   if (!h->c.ws) {
     set_error("composite has no workspace bound (call smg_composite_bind)");
     return SMG_ESTATE;
+  }
+  return SMG_OK;
+}
+
+// Solves A u = f from u = 0 with noise-free cycles until ||f - A u|| <= rtol ||f||; synchronises
+// s after every cycle (the residual norm decides whether to continue).
+int comp_solve(Composite& C, const double* fc, const double* ff, double* uc, double* uf,
+               double rtol, int max_cycles, hipStream_t s, smg_solve_info* info) {
+  const int64_t nbase = (int64_t)C.g.nx * C.g.ny * C.g.nz;
+  const int64_t nf = (int64_t)C.g.fx * C.g.fy * C.g.fz;
+  CMP_HIP(launch_zero<double>(uc, nbase, s));
+  CMP_HIP(launch_zero<double>(uf, nf, s));
+  auto resnorm = [&](double& out) -> int {
+    CMP_HIP(launch_comp_residual(C.rc, C.rf, (const double*)uc, (const double*)uf, fc, ff,
+                                 C.g, s));
+    CMP_HIP(launch_sumsq(C.norm, C.part, C.rc, nbase, 1, s));
+    CMP_HIP(launch_sumsq(C.norm + 1, C.part, C.rf, nf, 1, s));
+    double hn[2];
+    CMP_HIP(hipMemcpyAsync(hn, C.norm, 16, hipMemcpyDeviceToHost, s));
+    CMP_HIP(hipStreamSynchronize(s));
+    out = std::sqrt(hn[0] + hn[1]);
+    return SMG_OK;
+  };
+  double f0, rn, prev;
+  if (int e = resnorm(f0)) return e;
+  smg_solve_info loc{0, 0.0, 0.0};
+  if (!std::isfinite(f0)) {
+    set_error("f is not finite");
+    return SMG_ENONFINITE;
+  }
+  if (f0 == 0.0) {
+    if (info) *info = loc;
+    return SMG_OK;
+  }
+  prev = f0;
+  int k = 0;
+  double rel = 1.0;
+  while (k < max_cycles) {
+    CRun r{&C, s, false, 0, 0};
+    if (int e = run_cycle(r, uc, uf, fc, ff)) return e;
+    ++k;
+    if (int e = resnorm(rn)) return e;
+    if (!std::isfinite(rn)) {
+      set_error("residual is not finite");
+      return SMG_ENONFINITE;
+    }
+    rel = rn / f0;
+    loc.last_ratio = k >= 2 ? rn / prev : 0.0;
+    prev = rn;
+    if (rel <= rtol) break;
+  }
+  loc.cycles = k;
+  loc.relres = rel;
+  if (info) *info = loc;
+  if (rel > rtol) {
+    set_error("solve did not converge: relres " + std::to_string(rel));
+    return SMG_ENOTCONV;
   }
   return SMG_OK;
 }
@@ -1237,58 +1297,36 @@ int smg_composite_solve(smg_composite* h, const void* fc, const void* ff, void* 
     set_error("invalid solve arguments");
     return SMG_EINVAL;
   }
+  return smg::comp_solve(h->c, (const double*)fc, (const double*)ff, (double*)uc, (double*)uf,
+                         rtol, max_cycles, (hipStream_t)stream, info);
+}
+
+int smg_composite_forced_field(smg_composite* h, int64_t n, uint64_t seed, uint64_t first_sample,
+                               const void* qc, const void* qf, void* wc, void* wf, double rtol,
+                               int32_t max_cycles, void* stream, smg_solve_info* infos) {
+  if (int e = smg::check_bound(h)) return e;
+  if (n < 0 || (n > 0 && (!smg::aligned(wc) || !smg::aligned(wf))) ||
+      (qc && !smg::aligned(qc)) || (qf && !smg::aligned(qf)) || !(rtol >= 0.0) ||
+      max_cycles < 0) {
+    set_error("invalid forced-field arguments (n >= 0; wc, wf and given qc, qf 256-byte aligned "
+              "device pointers; rtol >= 0; max_cycles >= 0)");
+    return SMG_EINVAL;
+  }
   Composite& C = h->c;
   hipStream_t s = (hipStream_t)stream;
   const int64_t nbase = (int64_t)C.g.nx * C.g.ny * C.g.nz;
   const int64_t nf = (int64_t)C.g.fx * C.g.fy * C.g.fz;
-  CMP_HIP(smg::launch_zero<double>((double*)uc, nbase, s));
-  CMP_HIP(smg::launch_zero<double>((double*)uf, nf, s));
-  auto resnorm = [&](double& out) -> int {
-    CMP_HIP(smg::launch_comp_residual(C.rc, C.rf, (const double*)uc, (const double*)uf,
-                                      (const double*)fc, (const double*)ff, C.g, s));
-    CMP_HIP(smg::launch_sumsq(C.norm, C.part, C.rc, nbase, 1, s));
-    CMP_HIP(smg::launch_sumsq(C.norm + 1, C.part, C.rf, nf, 1, s));
-    double hn[2];
-    CMP_HIP(hipMemcpyAsync(hn, C.norm, 16, hipMemcpyDeviceToHost, s));
-    CMP_HIP(hipStreamSynchronize(s));
-    out = std::sqrt(hn[0] + hn[1]);
-    return SMG_OK;
-  };
-  double f0, rn, prev;
-  if (int e = resnorm(f0)) return e;
-  smg_solve_info loc{0, 0.0, 0.0};
-  if (!std::isfinite(f0)) {
-    set_error("f is not finite");
-    return SMG_ENONFINITE;
-  }
-  if (f0 == 0.0) {
-    if (info) *info = loc;
-    return SMG_OK;
-  }
-  prev = f0;
-  int k = 0;
-  double rel = 1.0;
-  while (k < max_cycles) {
-    smg::CRun r{&C, s, false, 0, 0};
-    if (int e = smg::run_cycle(r, (double*)uc, (double*)uf, (const double*)fc, (const double*)ff))
+  double* fc = (double*)(C.ws + C.off_fc);
+  double* ff = (double*)(C.ws + C.off_ff);
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t sample = first_sample + (uint64_t)i;
+    smg::NoiseArgs nac = smg::comp_noise(C, seed, sample, 0, 0, 0, smg::KIND_FORCING);
+    smg::NoiseArgs naf = smg::comp_noise(C, seed, sample, 0, 0, 1, smg::KIND_FORCING);
+    CMP_HIP(smg::launch_comp_forcing(fc, ff, (const double*)qc, (const double*)qf, C.g, nac, naf,
+                                     s));
+    if (int e = smg::comp_solve(C, fc, ff, (double*)wc + i * nbase, (double*)wf + i * nf, rtol,
+                                max_cycles, s, infos ? infos + i : nullptr))
       return e;
-    ++k;
-    if (int e = resnorm(rn)) return e;
-    if (!std::isfinite(rn)) {
-      set_error("residual is not finite");
-      return SMG_ENONFINITE;
-    }
-    rel = rn / f0;
-    loc.last_ratio = k >= 2 ? rn / prev : 0.0;
-    prev = rn;
-    if (rel <= rtol) break;
-  }
-  loc.cycles = k;
-  loc.relres = rel;
-  if (info) *info = loc;
-  if (rel > rtol) {
-    set_error("solve did not converge: relres " + std::to_string(rel));
-    return SMG_ENOTCONV;
   }
   return SMG_OK;
 }

@@ -103,5 +103,10 @@ hipError_t launch_dense_draw(T* x, const T* b, const double* ainv, const double*
 // r = b - A x on a Galerkin base level
 template <typename T>
 hipError_t launch_gresidual(T* r, const T* x, const T* b, const GStencilT<T>& st, hipStream_t s);
+// right-hand side of the forced field (Appendix A): (bc, bf) = -(volume/h^3) q eta, covered
+// base cells 0, eta from the streams nac (coarse part) and naf (fine part), q null = 1
+hipError_t launch_comp_forcing(double* bc, double* bf, const double* qc, const double* qf,
+                               const CompGeom& g, const NoiseArgs& nac, const NoiseArgs& naf,
+                               hipStream_t s);
 
 }  // namespace smg

@@ -613,6 +613,40 @@ __global__ __launch_bounds__(TPB) void k_dense_draw(T* __restrict__ x, const T* 
   if (lane == 0) x[row] = (T)acc;
 }
 
+
+// Right-hand side of the field noise w = L^-1 Q eta with Q = diag(q) (Appendix A): since
+// L = M^-1 S = -h^3 M^-1 A, the field solves A w = -(volume/h^3) q eta, with volume/h^3 = 1 on
+// coarse cells and 1/8 on fine cells; covered base cells get 0.  One thread per Philox call (two
+// sites): calls [0, nbase/2) fill the coarse part (stream nac, site = base cell), the rest the
+// fine part (stream naf, site = fine index).  q null = 1.  nbase and nfine are even (nx and the
+// fine extents are).
+__global__ __launch_bounds__(TPB) void k_comp_forcing(double* __restrict__ bc,
+                                                       double* __restrict__ bf,
+                                                       const double* __restrict__ qc,
+                                                       const double* __restrict__ qf, CompGeom g,
+                                                       NoiseArgs nac, NoiseArgs naf) {
+  const int64_t nbase = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t nf = (int64_t)g.fx * g.fy * g.fz;
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  double z[2];
+  if (t < (nbase >> 1)) {
+    normal_pair(nac, nac.sid, 0u, (uint32_t)t, z[0], z[1]);
+    for (int k = 0; k < 2; ++k) {
+      const int64_t i = 2 * t + k;
+      const int x = (int)(i % g.nx);
+      const int64_t row = i / g.nx;
+      const int y = (int)(row % g.ny), zz = (int)(row / g.ny);
+      bc[i] = covered(g, x, y, zz) ? 0.0 : -(qc ? qc[i] : 1.0) * z[k];
+    }
+  } else if (t - (nbase >> 1) < (nf >> 1)) {
+    const int64_t c = t - (nbase >> 1);
+    normal_pair(naf, naf.sid, 0u, (uint32_t)c, z[0], z[1]);
+    for (int k = 0; k < 2; ++k) {
+      const int64_t i = 2 * c + k;
+      bf[i] = -0.125 * (qf ? qf[i] : 1.0) * z[k];
+    }
+  }
+}
 }  // namespace
 
 template <typename T>
@@ -734,6 +768,14 @@ hipError_t launch_gresidual(T* r, const T* x, const T* b, const GStencilT<T>& st
   if (e != hipSuccess) return e;
   const int64_t listed = (int64_t)st.list_off[8] * 64;
   if (listed > 0) k_gresidual<T, 8, 2><<<grid_for(listed), TPB, 0, s>>>(r, x, b, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_comp_forcing(double* bc, double* bf, const double* qc, const double* qf,
+                               const CompGeom& g, const NoiseArgs& nac, const NoiseArgs& naf,
+                               hipStream_t s) {
+  const int64_t calls = ((int64_t)g.nx * g.ny * g.nz + (int64_t)g.fx * g.fy * g.fz) / 2;
+  k_comp_forcing<<<grid_for(calls), TPB, 0, s>>>(bc, bf, qc, qf, g, nac, naf);
   return hipGetLastError();
 }
 
