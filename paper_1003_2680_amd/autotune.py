@@ -1,6 +1,7 @@
 """Autotuner for the cycle configuration of a grid shape (depth, sweeps, tile shape, bottom).
 
-The paper leaves the V-cycle depth and the sweep counts open; every choice gives an exact
+The paper leaves the V-cycle depth (hence the size of the coarsest, exactly drawn level) and
+the sweep counts open; every choice gives an exact
 sampler of N(0, kT A^-1) (each move of the cycle is a heat-bath step), so the choice is a
 matter of cost.  The cost of one effectively independent sample is
 
@@ -14,10 +15,12 @@ change only the work distribution (never a result) and are then chosen on t_cycl
 
 Everything measured runs through the library's kernels; this module only orchestrates.
 """
+import ctypes
 import math
 
 import torch
 
+from . import abi
 from .api import Hierarchy
 from .inputs import gaussian_field
 
@@ -55,18 +58,34 @@ def _contraction(dims, levels, nu, precision, device):
     return H.last_ratio
 
 
+# coarsest sizes whose automatic plans are tried (the exact draw of the coarsest level is dense:
+# beyond about 2k unknowns its factors no longer fit the caches and its plan takes seconds)
+COARSEST_SIZES = (2048, 1024, 512, 256, 128, 64, 32, 16, 8)
+
+
 def depth_candidates(dims, precision="fp64"):
-    """Level counts worth trying: the automatic depth and one level deeper, if plannable."""
-    out = []
-    for cm in (512, 64):
-        try:
-            H = Hierarchy(*dims, ncomp=1, levels=0, coarsest_max=cm, precision=precision)
-        except Exception:
+    """The depths worth trying and the size of their coarsest level: the automatic plans for
+    every coarsest size in COARSEST_SIZES (each stops at the first level with at most that many
+    unknowns), so that the coarsest size is tuned through the depth.  Host planning only (the
+    library's planner; no device memory).  Returns [(levels, coarsest unknowns)], deepest last."""
+    lib = abi.load()
+    prec = {"fp64": abi.SMG_FP64, "fp32_refined": abi.SMG_FP32_REFINED}[precision]
+    desc = abi.GridDesc(*dims, 1, 1.0, 1.0, abi.SMG_BC_PERIODIC, abi.SMG_BC_PERIODIC,
+                        abi.SMG_BC_DIRICHLET_FACE)
+    out = {}
+    for cm in COARSEST_SIZES:
+        prm = abi.CycleParams(0, 2, 2, cm, abi.SMG_COARSEST_CHOLESKY, prec, 1, 0)
+        hd = ctypes.c_void_p()
+        if lib.smg_create_hierarchy(ctypes.byref(desc), ctypes.byref(prm), ctypes.byref(hd)):
             continue
-        if H.n_levels not in out:
-            out.append(H.n_levels)
-        del H
-    return out
+        info = abi.Info()
+        rc = lib.smg_hierarchy_info(hd, ctypes.byref(info))
+        lib.smg_destroy_hierarchy(hd)
+        if rc:
+            continue
+        c = info.dims[info.n_levels - 1]
+        out.setdefault(info.n_levels, c[0] * c[1] * c[2])
+    return sorted(out.items())
 
 
 def tune(dims, nchains, precision="fp32_refined", cycles=4, device=None):
@@ -78,7 +97,7 @@ def tune(dims, nchains, precision="fp32_refined", cycles=4, device=None):
     device = torch.device(device if device is not None else "cuda")
     table = []
     best = None
-    for levels in depth_candidates(dims, precision):
+    for levels, coarsest in depth_candidates(dims, precision):
         for nu in NU_CANDIDATES:
             H = Hierarchy(*dims, ncomp=nchains, levels=levels, nu1=nu[0], nu2=nu[1],
                           precision=precision, device=device)
@@ -86,8 +105,9 @@ def tune(dims, nchains, precision="fp32_refined", cycles=4, device=None):
             del H
             rho = _contraction(dims, levels, nu, precision, device)
             cost = t * _k_dec(rho)
-            row = {"levels": levels, "nu1": nu[0], "nu2": nu[1], "tile": "auto", "bottom": True,
-                   "t_cycle": t, "rho": rho, "k_dec": _k_dec(rho), "cost": cost}
+            row = {"levels": levels, "coarsest": coarsest, "nu1": nu[0], "nu2": nu[1],
+                   "tile": "auto", "bottom": True, "t_cycle": t, "rho": rho,
+                   "k_dec": _k_dec(rho), "cost": cost}
             table.append(row)
             if best is None or cost < best["cost"]:
                 best = dict(row)

@@ -11,6 +11,9 @@
 // when the extent is small); on the wall axis they are dense nz x nz matrices.
 #include <cmath>
 #include <cstring>
+#include <list>
+#include <memory>
+#include <mutex>
 
 #include "smg_internal.hpp"
 
@@ -142,6 +145,45 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 constexpr int64_t kBottomCells = 4096;
 constexpr size_t kBottomLdsMax = 160 * 1024;
 constexpr int kBottomLevelsMax = 6;
+
+// The dense factors of the coarsest level depend only on the finest grid, h and the depth (the
+// Galerkin recurrences are fixed by them), not on the component count, the sweeps or the
+// precision.  A small process-wide cache keeps the last few, so that plans of one shape that
+// differ only in those (an autotuner's candidates) factor the coarsest level once: at 1728
+// unknowns the factorisation and the two inverses take seconds on the host.
+struct CoarsestKey {
+  int nx, ny, nz, levels;
+  double h;
+  bool operator==(const CoarsestKey& o) const {
+    return nx == o.nx && ny == o.ny && nz == o.nz && levels == o.levels && h == o.h;
+  }
+};
+struct CoarsestFactors {
+  std::vector<double> w, ainv;
+};
+constexpr size_t kCoarsestCacheEntries = 4;
+std::mutex g_coarsest_mu;
+std::list<std::pair<CoarsestKey, std::shared_ptr<const CoarsestFactors>>> g_coarsest;
+
+std::shared_ptr<const CoarsestFactors> cached_coarsest(const CoarsestKey& k) {
+  std::lock_guard<std::mutex> lk(g_coarsest_mu);
+  for (auto it = g_coarsest.begin(); it != g_coarsest.end(); ++it)
+    if (it->first == k) {
+      g_coarsest.splice(g_coarsest.begin(), g_coarsest, it);  // most recent first
+      return g_coarsest.front().second;
+    }
+  return nullptr;
+}
+
+void store_coarsest(const CoarsestKey& k, const std::vector<double>& w,
+                    const std::vector<double>& ainv) {
+  auto f = std::make_shared<CoarsestFactors>();
+  f->w = w;
+  f->ainv = ainv;
+  std::lock_guard<std::mutex> lk(g_coarsest_mu);
+  g_coarsest.emplace_front(k, std::move(f));
+  while (g_coarsest.size() > kCoarsestCacheEntries) g_coarsest.pop_back();
+}
 
 }  // namespace
 
@@ -296,6 +338,13 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
         return SMG_EINVAL;
       }
       int n = (int)v.n;
+      const CoarsestKey key{d.nx, d.ny, d.nz, L, d.h};
+      if (std::shared_ptr<const CoarsestFactors> cf = cached_coarsest(key)) {
+        h.w = cf->w;
+        h.ainv = cf->ainv;
+        h.nc = n;
+        continue;
+      }
       std::vector<double> MX = ring_matrix(v.mx, v.nx), AX = ring_matrix(v.ax, v.nx);
       std::vector<double> MY = ring_matrix(v.my, v.ny), AY = ring_matrix(v.ay, v.ny);
       std::vector<double> A((size_t)n * n, 0.0);
@@ -323,6 +372,7 @@ int build_plan(const smg_grid_desc& d, const smg_cycle_params& p, Hierarchy& h, 
       h.w = lower_inverse(A, n);
       h.ainv = inverse_from_w(h.w, n);
       h.nc = n;
+      store_coarsest(key, h.w, h.ainv);
     }
   }
   // ---- workspace layout

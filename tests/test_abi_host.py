@@ -268,3 +268,16 @@ def test_2d_plan_matches_oracle_levels(lib):
                 abi.Desc2D(12, 12, 1, 1.0, 1.0, 3, 2, 2, 512, 0, 1)):
         hd = ctypes.c_void_p()
         assert lib.smg2d_create(ctypes.byref(bad), ctypes.byref(hd)) == abi.SMG_EINVAL
+
+
+def test_autotune_depth_candidates_cover_coarsest_sizes():
+    """The tuner's depths come from the planner's automatic plans over a sweep of coarsest sizes
+    (host planning only), so the exactly drawn coarsest level is tuned through the depth; plans
+    that differ only in depth-independent parameters reuse the coarsest factors."""
+    import time
+    from paper_1003_2680_amd import autotune
+    assert autotune.depth_candidates((32, 32, 32)) == [(3, 512), (4, 64), (5, 8)]
+    assert autotune.depth_candidates((48, 48, 48), "fp32_refined") == [(3, 1728), (4, 216)]
+    t = time.perf_counter()
+    assert autotune.depth_candidates((48, 48, 48)) == [(3, 1728), (4, 216)]
+    assert time.perf_counter() - t < 1.0   # the 1728-unknown factors come from the cache
