@@ -383,45 +383,176 @@ int vup(Run& r) {
   return SMG_OK;
 }
 
-// Phases of one cycle on the FP64 level-0 state x: PH_PRE (noise, the refined bridge in, the
-// down-leg), PH_BOTTOM (the bottom launch) and PH_POST (the up-leg, the refined bridge out).
-// A hierarchy without a split bottom runs its whole cycle in PH_PRE (and the refined bridge out
-// in PH_POST).  Refined mode: residual_ready says that lv[0].bf already holds the FP32
-// residual of the current x (the solve computes it with the norms).
-enum { PH_PRE = 1, PH_BOTTOM = 2, PH_POST = 4, PH_ALL = 7 };
+// Phases of one cycle on the FP64 level-0 state x: PH_IN (the block-level noise, the refined
+// bridge in), PH_DOWN (the down-leg), PH_BOTTOM (the bottom launch), PH_UP (the up-leg) and
+// PH_OUT (the refined bridge out); PH_PRE = PH_IN | PH_DOWN, PH_POST = PH_UP | PH_OUT.  A
+// hierarchy without a split bottom runs its whole V-cycle in PH_DOWN.  Refined mode:
+// residual_ready says that lv[0].bf already holds the FP32 residual of the current x (the solve
+// computes it with the norms).  The legs run on `leg_run(r)`, the run the cycle's levels see.
+enum {
+  PH_IN = 1,
+  PH_BOTTOM = 2,
+  PH_OUT = 4,
+  PH_DOWN = 8,
+  PH_UP = 16,
+  PH_PRE = PH_IN | PH_DOWN,
+  PH_POST = PH_UP | PH_OUT,
+  PH_ALL = 31
+};
+
+// The run the levels of a cycle see: in the refined form the inner cycle always has a
+// right-hand side (the FP64 residual).
+Run leg_run(const Run& r) {
+  Run ri = r;
+  if (refined(*r.h)) ri.has_b0 = true;
+  return ri;
+}
 
 int cycle_phases(Run& r, int phases, bool residual_ready = false) {
   Hierarchy& h = *r.h;
   Level& v0 = h.lv[0];
   const bool split = split_bottom(h);
+  Run ri = leg_run(r);
   if (!refined(h)) {
-    if (phases & PH_PRE) {
-      if (r.noise) SMG_TRY(gen_level_noise<double>(r));
-      SMG_TRY(split ? vdown<double>(r) : vcycle<double>(r, 0));
-    }
-    if (split && (phases & PH_BOTTOM)) SMG_TRY(bottom_cycle<double>(r));
-    if (split && (phases & PH_POST)) SMG_TRY(vup<double>(r));
+    if ((phases & PH_IN) && r.noise) SMG_TRY(gen_level_noise<double>(r));
+    if (phases & PH_DOWN) SMG_TRY(split ? vdown<double>(ri) : vcycle<double>(ri, 0));
+    if (split && (phases & PH_BOTTOM)) SMG_TRY(bottom_cycle<double>(ri));
+    if (split && (phases & PH_UP)) SMG_TRY(vup<double>(ri));
     return SMG_OK;
   }
   // the processed components of both colour arrays
   const int64_t act = (int64_t)r.nc * (v0.n / 2);
   const size_t half = half_field(h);
-  Run ri = r;
-  ri.has_b0 = true;
-  if (phases & PH_PRE) {
+  if (phases & PH_IN) {
     if (r.noise) SMG_TRY(gen_level_noise<float>(r));
     if (!residual_ready)
       SMG_HIP(launch_refine_residual(v0.bf, v0.x, r.has_b0 ? v0.b : nullptr, v0.nx, v0.ny,
                                      v0.nz, r.nc, h.desc.ncomp, h.desc.h, nullptr, nullptr, r.s));
     SMG_HIP(launch_zero<float>(v0.xf, act, r.s));
     SMG_HIP(launch_zero<float>(v0.xf + half, act, r.s));
-    SMG_TRY(split ? vdown<float>(ri) : vcycle<float>(ri, 0));
   }
+  if (phases & PH_DOWN) SMG_TRY(split ? vdown<float>(ri) : vcycle<float>(ri, 0));
   if (split && (phases & PH_BOTTOM)) SMG_TRY(bottom_cycle<float>(ri));
-  if (phases & PH_POST) {
-    if (split) SMG_TRY(vup<float>(ri));
+  if (split && (phases & PH_UP)) SMG_TRY(vup<float>(ri));
+  if (phases & PH_OUT) {
     SMG_HIP(launch_refine_update(v0.x, v0.xf, act, r.s));
     SMG_HIP(launch_refine_update(v0.x + half, v0.xf + half, act, r.s));
+  }
+  return SMG_OK;
+}
+
+// The block-colour pass of colour `colour` in sweep `t` (0-based; pre-sweeps first) of level l
+// for every listed run that has it (level l above its bottom, t < its nu1 + nu2 and on the
+// given leg), in one launch.
+template <typename T>
+int block_pass_lockstep(const std::vector<Run>& legs, int l, int t, bool post, int colour,
+                        bool noise, hipStream_t s) {
+  std::vector<BlockPassItem<T>> items;
+  int tile = -1;
+  for (const Run& r : legs) {
+    Hierarchy& h = *r.h;
+    if (r.noise != noise || l >= h.bottom) continue;
+    Level& v = h.lv[l];
+    if (v.kind != KIND_BLOCK) continue;
+    const int nsw = post ? h.prm.nu2 : h.prm.nu1;
+    if (t >= nsw) continue;
+    const int slot = post ? h.prm.nu1 + t : t;
+    BlockPassItem<T> it;
+    it.x = Fld<T>::x(v);
+    it.b = Fld<T>::b(v);
+    it.s1d = (const T*)v.s1d_d;
+    it.zt = (const T*)v.zt_d;
+    it.bfac = (const T*)v.bfac_d;
+    it.zn = noise ? (const T*)v.noise_d + (size_t)slot * h.desc.ncomp * v.n : nullptr;
+    it.nx = v.nx;
+    it.ny = v.ny;
+    it.nz = v.nz;
+    it.ncomp = r.nc;
+    items.push_back(it);
+    // one tile shape per launch: the common choice of the items, else by work-group count
+    tile = tile == -1 ? h.block_tile : (tile == h.block_tile ? tile : SMG_TILE_AUTO);
+  }
+  if (items.empty()) return SMG_OK;
+  SMG_HIP(launch_block_pass_multi<T>(items.data(), (int)items.size(), colour, noise, tile, s));
+  return SMG_OK;
+}
+
+// The down-leg (or up-leg) of several runs with a split bottom, of one sweep precision, in
+// lockstep: level by level and sweep by sweep, the colour passes of all runs at the same point
+// of their legs share one launch (level-0 point passes and Galerkin block passes alike); the
+// transfers stay per run.  The runs
+// touch disjoint memory and each keeps the order of its own vdown / vup, so each computes
+// exactly what vdown / vup computes.
+template <typename T>
+int legs_lockstep(const std::vector<Run>& legs, bool down) {
+  if (legs.empty()) return SMG_OK;
+  hipStream_t s = legs[0].s;
+  int maxb = 0, maxnu = 0;
+  for (const Run& r : legs) {
+    maxb = std::max(maxb, r.h->bottom);
+    maxnu = std::max(maxnu, down ? r.h->prm.nu1 : r.h->prm.nu2);
+  }
+  auto sweeps = [&](int l) -> int {
+    for (int t = 0; t < maxnu; ++t) {
+      // point-smoothed levels (level 0): each colour of all runs in one launch per (right-hand
+      // side present, noise) setting
+      for (int k = 0; k < 2; ++k) {
+        const int colour = down ? k : 1 - k;
+        for (int hb = 0; hb < 2; ++hb)
+          for (int nz = 0; nz < 2; ++nz) {
+            std::vector<RbPassItem<T>> items;
+            for (const Run& r : legs) {
+              Hierarchy& h = *r.h;
+              if (l >= h.bottom || h.lv[l].kind != KIND_POINT) continue;
+              if (t >= (down ? h.prm.nu1 : h.prm.nu2)) continue;
+              if ((int)r.has_b0 != hb || (int)r.noise != nz) continue;
+              Level& v = h.lv[l];
+              T* xr = Fld<T>::x(v);
+              T* xb = xr + half_field(h);
+              const T* br = Fld<T>::b(v);
+              const T* bb = br + half_field(h);
+              RbPassItem<T> it;
+              it.xc = colour ? xb : xr;
+              it.xo = colour ? xr : xb;
+              it.bc = r.has_b0 ? (colour ? bb : br) : nullptr;
+              it.nx = v.nx;
+              it.ny = v.ny;
+              it.nz = v.nz;
+              it.ncomp = r.nc;
+              it.h = h.desc.h;
+              it.kT = h.desc.kT;
+              it.na = make_noise(r, l, down ? t : h.prm.nu1 + t, colour, KIND_SMOOTH_NOISE);
+              items.push_back(it);
+            }
+            if (!items.empty())
+              SMG_HIP(launch_rb_pass_multi<T>(items.data(), (int)items.size(), colour, hb != 0,
+                                              nz != 0, s));
+          }
+      }
+      for (int k = 0; k < 8; ++k) {
+        const int colour = down ? k : 7 - k;
+        for (int nz = 0; nz < 2; ++nz)
+          SMG_TRY(block_pass_lockstep<T>(legs, l, t, !down, colour, nz != 0, s));
+      }
+    }
+    return SMG_OK;
+  };
+  if (down) {
+    for (int l = 0; l < maxb; ++l) {
+      SMG_TRY(sweeps(l));
+      for (const Run& r0 : legs) {
+        Run r = r0;
+        if (l < r.h->bottom) SMG_TRY(restrict_residual<T>(r, l));
+      }
+    }
+  } else {
+    for (int l = maxb - 1; l >= 0; --l) {
+      for (const Run& r0 : legs) {
+        Run r = r0;
+        if (l < r.h->bottom) SMG_TRY(prolong_add<T>(r, l));
+      }
+      SMG_TRY(sweeps(l));
+    }
   }
   return SMG_OK;
 }
@@ -436,7 +567,17 @@ int full_cycle(Run& r, bool residual_ready = false) {
 // components each), then every run's up-leg.  Each run's own kernels keep their order and the
 // runs touch disjoint memory, so every run computes exactly what full_cycle computes.
 int batch_cycle(const std::vector<Run*>& runs, const std::vector<char>& ready) {
-  for (size_t i = 0; i < runs.size(); ++i) SMG_TRY(cycle_phases(*runs[i], PH_PRE, ready[i]));
+  // the legs of the runs with a split bottom go in lockstep (one launch per block-colour pass
+  // for all of them, per sweep precision); the others run their whole V-cycle in PH_DOWN
+  std::vector<Run> legs64, legs32;
+  for (size_t i = 0; i < runs.size(); ++i) {
+    Run& r = *runs[i];
+    SMG_TRY(cycle_phases(r, PH_IN, ready[i]));
+    if (!split_bottom(*r.h)) SMG_TRY(cycle_phases(r, PH_DOWN, ready[i]));
+    else (refined(*r.h) ? legs32 : legs64).push_back(leg_run(r));
+  }
+  SMG_TRY(legs_lockstep<double>(legs64, true));
+  SMG_TRY(legs_lockstep<float>(legs32, true));
   for (int f32 = 0; f32 < 2; ++f32)
     for (int nz = 0; nz < 2; ++nz) {
       BotMultiArgs m{};
@@ -485,7 +626,9 @@ int batch_cycle(const std::vector<Run*>& runs, const std::vector<char>& ready) {
       }
       SMG_TRY(flush());
     }
-  for (size_t i = 0; i < runs.size(); ++i) SMG_TRY(cycle_phases(*runs[i], PH_POST, ready[i]));
+  SMG_TRY(legs_lockstep<double>(legs64, false));
+  SMG_TRY(legs_lockstep<float>(legs32, false));
+  for (size_t i = 0; i < runs.size(); ++i) SMG_TRY(cycle_phases(*runs[i], PH_OUT, ready[i]));
   return SMG_OK;
 }
 

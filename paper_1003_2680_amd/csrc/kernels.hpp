@@ -110,6 +110,60 @@ template <typename T>
 hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
                              int ny, int nz, int ncomp, int colour, const T* z, int tile,
                              hipStream_t s);
+// One level-0 colour pass over several hierarchies in one launch (up to 8 per launch): each
+// item as the arguments of launch_rb_pass (its colour arrays, right-hand side, shape, active
+// components, h, kT and noise keys); every item has a right-hand side iff has_b.  The result
+// of each item is that of launch_rb_pass on it alone.
+template <typename T>
+struct RbPassItem {
+  T* xc;
+  const T* xo;
+  const T* bc;
+  int nx, ny, nz, ncomp;
+  double h, kT;
+  NoiseArgs na;
+};
+template <typename T>
+hipError_t launch_rb_pass_multi(const RbPassItem<T>* items, int n, int colour, bool has_b,
+                               bool noise, hipStream_t s);
+
+// One block-colour pass over the levels of several hierarchies in one launch (up to
+// kBlockMultiItems per launch; more are split into several launches).  Each item is one level
+// of one hierarchy: its fields and tables as for launch_block_pass, its active components and
+// its own noise field (null when noise is off).  The items' passes are independent: the
+// result of each is that of launch_block_pass on it alone.
+template <typename T>
+struct BlockPassItem {
+  T* x;
+  const T* b;
+  const T* s1d;
+  const T* zt;
+  const T* bfac;
+  const T* zn;
+  int nx, ny, nz, ncomp;
+};
+constexpr int kBlockMultiItems = 16;
+template <typename T>
+struct BlockMultiItem {
+  T* x;
+  const T* b;
+  const T* s1d;
+  const T* zt;
+  const T* bfac;
+  const T* zn;
+  int nx, ny, nz;
+  uint32_t N;
+  int nbx2, nby2, nbzc, ntx, nty;
+};
+template <typename T>
+struct BlockMultiArgs {
+  int nitems, colour;
+  uint32_t begin[kBlockMultiItems + 1];  // first work-group of each item; begin[nitems] = total
+  BlockMultiItem<T> it[kBlockMultiItems];
+};
+template <typename T>
+hipError_t launch_block_pass_multi(const BlockPassItem<T>* items, int n, int colour, bool noise,
+                                   int tile, hipStream_t s);
 template <typename T>
 hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStream_t s);
 // `a` points to a BotArgs in device memory

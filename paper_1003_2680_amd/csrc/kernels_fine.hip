@@ -70,16 +70,17 @@ struct Vec16<float> {
 // launch guarantees that every wave stays in one z-plane (nh/S * ny a multiple of 64), so the
 // wall tests and the diagonal of the plane are taken once per wave on the scalar unit.  A wall
 // side enters the z-sum with weight 0.
-template <typename T, bool HAS_B, bool NOISE, bool ZU = false>
-__global__ __launch_bounds__(TPB) void k_rb_pass_vec(T* __restrict__ xc, const T* __restrict__ xo,
-                                                      const T* __restrict__ bc, int nh, int ny,
-                                                      int nz, uint32_t nthreads, int lg_nht,
-                                                      int lg_ny, int colour, T inv_h2,
-                                                      Diag3<T> dg, NoiseArgs na) {
+// The pass of work-group `blk` of component `comp`.
+template <typename T, bool HAS_B, bool NOISE, bool ZU>
+__device__ __forceinline__ void rb_pass_vec_body(T* __restrict__ xc, const T* __restrict__ xo,
+                                                 const T* __restrict__ bc, int nh, int ny, int nz,
+                                                 uint32_t nthreads, int lg_nht, int lg_ny,
+                                                 int colour, T inv_h2, const Diag3<T>& dg,
+                                                 const NoiseArgs& na, uint32_t blk,
+                                                 uint32_t comp) {
   using V = typename Vec16<T>::type;
   constexpr uint32_t W = sizeof(T), S = 16 / W;
-  const uint32_t comp = blockIdx.y;
-  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  const uint32_t t = blk * TPB + threadIdx.x;
   if (t >= nthreads) return;
   const uint32_t nht = (uint32_t)nh / S;
   uint32_t row, jt, z, y;
@@ -167,6 +168,67 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_vec(T* __restrict__ xc, const T
   V ov;
   __builtin_memcpy(&ov, out, sizeof(V));
   *reinterpret_cast<V*>(reinterpret_cast<char*>(xc + base) + ic * W) = ov;
+}
+
+template <typename T, bool HAS_B, bool NOISE, bool ZU = false>
+__global__ __launch_bounds__(TPB) void k_rb_pass_vec(T* __restrict__ xc, const T* __restrict__ xo,
+                                                      const T* __restrict__ bc, int nh, int ny,
+                                                      int nz, uint32_t nthreads, int lg_nht,
+                                                      int lg_ny, int colour, T inv_h2,
+                                                      Diag3<T> dg, NoiseArgs na) {
+  rb_pass_vec_body<T, HAS_B, NOISE, ZU>(xc, xo, bc, nh, ny, nz, nthreads, lg_nht, lg_ny, colour,
+                                        inv_h2, dg, na, blockIdx.x, blockIdx.y);
+}
+
+// The same colour pass on the level 0 of several hierarchies in one launch: the grid is the
+// concatenation of every item's (block, component) grid; a work-group finds its item from the
+// offsets.  Each item brings its own noise keys; the Box-Muller coefficients are shared.
+struct RbNoiseKey {
+  uint32_t k0, k1, sid, c2, c3, cpc, cpc_magic;
+  double sqkT;
+  const ChainKey* chains;
+};
+constexpr int kRbMultiItems = 8;
+template <typename T>
+struct RbMultiItem {
+  T* xc;
+  const T* xo;
+  const T* bc;
+  int nh, ny, nz, lg_nht, lg_ny;
+  uint32_t nthreads, nblk;
+  T inv_h2;
+  Diag3<T> dg;
+  RbNoiseKey nk;
+};
+template <typename T>
+struct RbMultiArgs {
+  int nitems, colour;
+  uint32_t begin[kRbMultiItems + 1];
+  BoxMullerCoef bm;
+  RbMultiItem<T> it[kRbMultiItems];
+};
+
+template <typename T, bool HAS_B, bool NOISE>
+__global__ __launch_bounds__(TPB) void k_rb_pass_vec_multi(RbMultiArgs<T> m) {
+  const uint32_t lin = blockIdx.x;
+  int i = 0;
+  while (i + 1 < m.nitems && lin >= m.begin[i + 1]) ++i;
+  const RbMultiItem<T>& it = m.it[i];
+  const uint32_t local = lin - m.begin[i];
+  NoiseArgs na;
+  na.k0 = it.nk.k0;
+  na.k1 = it.nk.k1;
+  na.sid = it.nk.sid;
+  na.c2 = it.nk.c2;
+  na.c3 = it.nk.c3;
+  na.sqkT = it.nk.sqkT;
+  na.chains = it.nk.chains;
+  na.comps_per_chain = it.nk.cpc;
+  na.cpc_magic = it.nk.cpc_magic;
+  na.bm = m.bm;
+  rb_pass_vec_body<T, HAS_B, NOISE, false>(it.xc, it.xo, it.bc, it.nh, it.ny, it.nz,
+                                           it.nthreads, it.lg_nht, it.lg_ny, m.colour, it.inv_h2,
+                                           it.dg, na, local % it.nblk, local / it.nblk);
 }
 
 // Generic colour pass (any even nx): thread q owns colour sites 2q and 2q+1 (one Philox call).
@@ -668,6 +730,75 @@ hipError_t launch_rb_pass(T* xc, const T* xo, const T* bc, int nx, int ny, int n
 }
 
 template <typename T>
+hipError_t launch_rb_pass_multi(const RbPassItem<T>* items, int n, int colour, bool has_b,
+                               bool noise, hipStream_t s) {
+  constexpr int S = 16 / (int)sizeof(T);
+  RbMultiArgs<T> m{};
+  m.colour = colour;
+  m.bm = box_muller_coef();
+  uint32_t total = 0;
+  auto flush = [&]() -> hipError_t {
+    if (m.nitems == 0) return hipSuccess;
+    m.begin[m.nitems] = total;
+#define SMG_RBM(HB, NZ) k_rb_pass_vec_multi<T, HB, NZ><<<total, TPB, 0, s>>>(m)
+    if (has_b) { if (noise) SMG_RBM(true, true); else SMG_RBM(true, false); }
+    else { if (noise) SMG_RBM(false, true); else SMG_RBM(false, false); }
+#undef SMG_RBM
+    m.nitems = 0;
+    total = 0;
+    return hipGetLastError();
+  };
+  for (int q = 0; q < n; ++q) {
+    const RbPassItem<T>& p = items[q];
+    const int nh = p.nx / 2;
+    const uint32_t nsite = (uint32_t)nh * p.ny * p.nz;
+    if ((p.bc != nullptr) != has_b) return hipErrorInvalidValue;
+    if (nh % S != 0 || (uint64_t)nsite * sizeof(T) >= (1ull << 32)) {
+      // shapes the vector pass does not take: a launch of their own
+      hipError_t e = launch_rb_pass<T>(p.xc, p.xo, p.bc, p.nx, p.ny, p.nz, p.ncomp, colour, p.h,
+                                       p.kT, noise, p.na, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    if (p.ncomp == 0) continue;
+    if (m.nitems == kRbMultiItems) {
+      hipError_t e = flush();
+      if (e != hipSuccess) return e;
+    }
+    RbMultiItem<T>& it = m.it[m.nitems];
+    it.xc = p.xc;
+    it.xo = p.xo;
+    it.bc = p.bc;
+    it.nh = nh;
+    it.ny = p.ny;
+    it.nz = p.nz;
+    it.nthreads = nsite / S;
+    it.lg_nht = ilog2_exact((uint32_t)(nh / S));
+    it.lg_ny = ilog2_exact((uint32_t)p.ny);
+    it.nblk = blocks_for(it.nthreads);
+    it.inv_h2 = (T)(1.0 / (p.h * p.h));
+    for (int w = 0; w < 3; ++w) {
+      it.dg.inv_d[w] = (T)(p.h * p.h / (6.0 + w));
+      it.dg.sig[w] = (T)sqrt(p.kT * p.h * p.h / (6.0 + w));
+      it.dg.inv_n[w] = (T)(1.0 / (6.0 + w));
+    }
+    it.nk.k0 = p.na.k0;
+    it.nk.k1 = p.na.k1;
+    it.nk.sid = p.na.sid;
+    it.nk.c2 = p.na.c2;
+    it.nk.c3 = p.na.c3;
+    it.nk.cpc = p.na.comps_per_chain;
+    it.nk.cpc_magic = p.na.cpc_magic;
+    it.nk.sqkT = p.na.sqkT;
+    it.nk.chains = p.na.chains;
+    m.begin[m.nitems] = total;
+    total += it.nblk * (uint32_t)p.ncomp;
+    ++m.nitems;
+  }
+  return flush();
+}
+
+template <typename T>
 hipError_t launch_residual0(T* r, const T* xr, const T* xb, const T* br, const T* bb, int nx,
                             int ny, int nz, int ncomp, double h, hipStream_t s) {
   const uint32_t N = (uint32_t)nx * ny * nz;
@@ -717,6 +848,10 @@ template hipError_t launch_rb_pass<double>(double*, const double*, const double*
 template hipError_t launch_rb_pass<float>(float*, const float*, const float*, int, int, int, int,
                                           int, double, double, bool, const NoiseArgs&,
                                           hipStream_t);
+template hipError_t launch_rb_pass_multi<double>(const RbPassItem<double>*, int, int, bool, bool,
+                                                 hipStream_t);
+template hipError_t launch_rb_pass_multi<float>(const RbPassItem<float>*, int, int, bool, bool,
+                                                hipStream_t);
 template hipError_t launch_residual0<double>(double*, const double*, const double*, const double*,
                                              const double*, int, int, int, int, double,
                                              hipStream_t);

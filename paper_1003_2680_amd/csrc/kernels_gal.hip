@@ -84,15 +84,15 @@ __global__ __launch_bounds__(TPB) void k_level_noise(NoiseGenArgs a, NoiseArgs n
 // 8x4 (256 threads); the shape changes only the work distribution, never a result.
 constexpr int TILE_D = 6;
 
+// The pass of one work-group: wg = (tile, block layer l, component).
 template <typename T, bool NOISE, int TILE_I, int TILE_J>
-__global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restrict__ xg,
-                                                          const T* __restrict__ bg,
-                                                          const T* __restrict__ s1d,
-                                                          const T* __restrict__ zt,
-                                                          const T* __restrict__ bfac, int nx,
-                                                          int ny, int nz, uint32_t N, int colour,
-                                                          int nbx2, int nby2, int ntx,
-                                                          const T* __restrict__ zn) {
+__device__ __forceinline__ void block_tile_body(T* __restrict__ xg, const T* __restrict__ bg,
+                                                const T* __restrict__ s1d,
+                                                const T* __restrict__ zt,
+                                                const T* __restrict__ bfac, int nx, int ny,
+                                                int nz, uint32_t N, int colour, int nbx2,
+                                                int nby2, int ntx, const T* __restrict__ zn,
+                                                const Blk3 wg) {
   constexpr int TILE_W = 4 * TILE_I + 2, TILE_H = 4 * TILE_J + 2;
   constexpr int TILE_TPB = TILE_I * TILE_J * 8;
   // plane stride: the first count >= the plane that is 16 mod 32 elements.  The two z-layers
@@ -100,7 +100,6 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
   // 64 LDS banks and a wave's reads of one window offset are free of bank conflicts (FP64).
   constexpr int TP = TILE_H * TILE_W + ((48 - (TILE_H * TILE_W) % 32) % 32);
   __shared__ T Tl[TILE_D * TP];
-  const Blk3 wg = xcd_block();
   const uint32_t comp = wg.z;
   const int l = wg.y;
   const int ti = wg.x % ntx, tj = wg.x / ntx;
@@ -198,6 +197,40 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
   }
   const T v = v0 + v1;
   if (active) X[cell] = v;
+}
+
+template <typename T, bool NOISE, int TILE_I, int TILE_J>
+__global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restrict__ xg,
+                                                          const T* __restrict__ bg,
+                                                          const T* __restrict__ s1d,
+                                                          const T* __restrict__ zt,
+                                                          const T* __restrict__ bfac, int nx,
+                                                          int ny, int nz, uint32_t N, int colour,
+                                                          int nbx2, int nby2, int ntx,
+                                                          const T* __restrict__ zn) {
+  block_tile_body<T, NOISE, TILE_I, TILE_J>(xg, bg, s1d, zt, bfac, nx, ny, nz, N, colour, nbx2,
+                                            nby2, ntx, zn, xcd_block());
+}
+
+// The same pass for several levels of different hierarchies (one colour) in one launch: the
+// one-dimensional grid is the concatenation of every item's (tile, layer, component) grid, in
+// XCD-aware order; a work-group finds its item from the offsets and runs the item's pass.
+template <typename T, bool NOISE, int TILE_I, int TILE_J>
+__global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile_multi(BlockMultiArgs<T> m) {
+  const uint32_t lin = xcd_block().x;
+  int i = 0;
+  while (i + 1 < m.nitems && lin >= m.begin[i + 1]) ++i;
+  const BlockMultiItem<T>& it = m.it[i];
+  const uint32_t local = lin - m.begin[i];
+  const uint32_t tiles = (uint32_t)it.ntx * (uint32_t)it.nty;
+  Blk3 wg;
+  wg.x = local % tiles;
+  const uint32_t rest = local / tiles;
+  wg.y = rest % (uint32_t)it.nbzc;
+  wg.z = rest / (uint32_t)it.nbzc;
+  block_tile_body<T, NOISE, TILE_I, TILE_J>(it.x, it.b, it.s1d, it.zt, it.bfac, it.nx, it.ny,
+                                            it.nz, it.N, m.colour, it.nbx2, it.nby2, it.ntx,
+                                            it.zn, wg);
 }
 
 // r = b - A x on a Galerkin level, LDS-tiled: a work-group owns GR_X x GR_Y x GR_Z cells and
@@ -587,6 +620,74 @@ hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const 
   return hipGetLastError();
 }
 
+template <typename T, int TI, int TJ>
+hipError_t launch_block_multi_tiled(const BlockPassItem<T>* items, int n, int colour, bool noise,
+                                    hipStream_t s) {
+  BlockMultiArgs<T> m{};
+  m.colour = colour;
+  uint32_t total = 0;
+  auto flush = [&]() -> hipError_t {
+    if (m.nitems == 0) return hipSuccess;
+    m.begin[m.nitems] = total;
+    if (noise) k_block_tile_multi<T, true, TI, TJ><<<total, TI * TJ * 8, 0, s>>>(m);
+    else k_block_tile_multi<T, false, TI, TJ><<<total, TI * TJ * 8, 0, s>>>(m);
+    m.nitems = 0;
+    total = 0;
+    return hipGetLastError();
+  };
+  for (int q = 0; q < n; ++q) {
+    const BlockPassItem<T>& p = items[q];
+    const int nbx2 = p.nx / 4, nby2 = p.ny / 4;
+    const int nbzc = (p.nz / 2 + 1 - (colour >> 2)) / 2;
+    if (nbx2 * nby2 * nbzc == 0 || p.ncomp == 0) continue;
+    const int ntx = (nbx2 + TI - 1) / TI, nty = (nby2 + TJ - 1) / TJ;
+    const uint32_t wgs = (uint32_t)ntx * nty * nbzc * p.ncomp;
+    if (m.nitems == kBlockMultiItems) {
+      hipError_t e = flush();
+      if (e != hipSuccess) return e;
+    }
+    BlockMultiItem<T>& it = m.it[m.nitems];
+    it.x = p.x;
+    it.b = p.b;
+    it.s1d = p.s1d;
+    it.zt = p.zt;
+    it.bfac = p.bfac;
+    it.zn = p.zn;
+    it.nx = p.nx;
+    it.ny = p.ny;
+    it.nz = p.nz;
+    it.N = (uint32_t)p.nx * p.ny * p.nz;
+    it.nbx2 = nbx2;
+    it.nby2 = nby2;
+    it.nbzc = nbzc;
+    it.ntx = ntx;
+    it.nty = nty;
+    m.begin[m.nitems] = total;
+    total += wgs;
+    ++m.nitems;
+  }
+  return flush();
+}
+
+template <typename T>
+hipError_t launch_block_pass_multi(const BlockPassItem<T>* items, int n, int colour, bool noise,
+                                   int tile, hipStream_t s) {
+  if (tile == SMG_TILE_AUTO) {
+    // the rule of launch_block_pass over the work-groups of all items together
+    int64_t wg84 = 0, wg44 = 0;
+    for (int q = 0; q < n; ++q) {
+      const int nbx2 = items[q].nx / 4, nby2 = items[q].ny / 4;
+      const int64_t layers = (int64_t)((items[q].nz / 2 + 1 - (colour >> 2)) / 2) * items[q].ncomp;
+      wg84 += (int64_t)((nbx2 + 7) / 8) * ((nby2 + 3) / 4) * layers;
+      wg44 += (int64_t)((nbx2 + 3) / 4) * ((nby2 + 3) / 4) * layers;
+    }
+    tile = wg84 >= 512 ? SMG_TILE_8X4 : (wg44 >= 512 ? SMG_TILE_4X4 : SMG_TILE_4X2);
+  }
+  if (tile == SMG_TILE_4X2) return launch_block_multi_tiled<T, 4, 2>(items, n, colour, noise, s);
+  if (tile == SMG_TILE_8X4) return launch_block_multi_tiled<T, 8, 4>(items, n, colour, noise, s);
+  return launch_block_multi_tiled<T, 4, 4>(items, n, colour, noise, s);
+}
+
 template <typename T>
 hipError_t launch_residual_gal(T* r, const T* x, const T* b, const T* s1d, const T* zt, int nx,
                                int ny, int nz, int ncomp, hipStream_t s) {
@@ -680,6 +781,8 @@ hipError_t launch_bottom_multi(const BotMultiArgs& m, int nwg, size_t lds, bool 
 #define SMG_INST(T)                                                                            \
   template hipError_t launch_block_pass<T>(T*, const T*, const T*, const T*, const T*, int, int, \
                                            int, int, int, const T*, int, hipStream_t);          \
+  template hipError_t launch_block_pass_multi<T>(const BlockPassItem<T>*, int, int, bool, int,    \
+                                                 hipStream_t);                                   \
   template hipError_t launch_residual_gal<T>(T*, const T*, const T*, const T*, const T*, int,    \
                                              int, int, int, hipStream_t);                        \
   template hipError_t launch_restrict<T>(T*, T*, const T*, int, int, int, int, hipStream_t);    \
