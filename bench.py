@@ -277,6 +277,9 @@ def measure(precision, args, dev, stride, chains, steps, timing=True):
             H.kernel_timing(False, name)
             kern[name] = {"launches": n_l, "avg_launch_s": k_ms / 1e3 / max(n_l, 1),
                           "per_cycle_s": k_ms / 1e3 / cyc_timed}
+            if name == "level1_block_pass":
+                # one or two colours per launch: 8 colour passes per sweep, 4 sweeps per cycle
+                kern[name]["colours_per_launch"] = max(1, round(cyc_timed * 32 / max(n_l, 1)))
         res["kern"] = kern
     del H, out, state
     torch.cuda.empty_cache()
@@ -760,9 +763,16 @@ def main():
     fine = roof(kern["fine_pass"], "k_rb_pass (level-0 colour pass, 128^3)", nact * N0 * 8)
     fine["traffic"] = measured_traffic("fine_pass", C)
     # level-1 block colour pass: read x of the whole level, b and the noise of this colour's
-    # cells, write x of this colour's cells: N1 * 8 B * (1 + 3/8)
-    blk = roof(kern["level1_block_pass"], "k_block_tile (level-1 block colour pass, 64^3)",
-               nact * N1 * 8 * 11 // 8)
+    # cells, write x of this colour's cells: N1 * 8 B * (1 + 3/8) per colour; a launch of two
+    # colours (k_block_pair) reads x once and b, noise and writes for both: N1 * 8 B * (1 + 6/8)
+    cpl = kern["level1_block_pass"].get("colours_per_launch", 1)
+    if cpl == 2:
+        blk = roof(kern["level1_block_pass"],
+                   "k_block_pair (two level-1 block colour passes per launch, 64^3)",
+                   nact * N1 * 8 * 14 // 8)
+    else:
+        blk = roof(kern["level1_block_pass"], "k_block_tile (level-1 block colour pass, 64^3)",
+                   nact * N1 * 8 * 11 // 8)
     blk["traffic"] = measured_traffic("level1_block_pass", C)
     # the dominant kernel class by GPU time per cycle carries `roofline`
     dominant = max((fine, blk), key=lambda r: r["us_per_cycle"])

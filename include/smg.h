@@ -315,8 +315,18 @@ int smg_debug_host_table(const smg_hierarchy* h, int32_t level, int32_t which, d
  *   SMG_OPT_BLOCK_TILE (default SMG_TILE_AUTO): see below.
  *   SMG_OPT_TIMED_KERNEL (default SMG_TIMED_FINE_PASS): the kernel class that
  *   smg_kernel_timing brackets with events: the level-0 colour pass, the level-1 block
- *   colour pass, or the LDS-resident bottom launch. */
-enum { SMG_OPT_BOTTOM_KERNEL = 1, SMG_OPT_TIMED_KERNEL = 2, SMG_OPT_BLOCK_TILE = 3 };
+ *   colour passes (one or two colours per launch, see SMG_OPT_BLOCK_PAIRS), or the
+ *   LDS-resident bottom launch. */
+enum {
+  SMG_OPT_BOTTOM_KERNEL = 1,
+  SMG_OPT_TIMED_KERNEL = 2,
+  SMG_OPT_BLOCK_TILE = 3,
+  SMG_OPT_BLOCK_PAIRS = 4
+};
+/* SMG_OPT_BLOCK_PAIRS (default 1): run the eight block colours of a sweep on a Galerkin level
+ * as four launches of two colours each (colours c and c ^ 1 differ only in the parity of bx,
+ * so one work-group owning whole x-rows draws both in turn from one staged tile); levels wider
+ * than 128 cells in x use one launch per colour.  0 = one launch per colour everywhere. */
 /* SMG_OPT_BLOCK_TILE: blocks per work-group (x by y) of the Galerkin-level block passes;
  * SMG_TILE_AUTO (default) takes the largest of 8x4, 4x4, 4x2 that gives at least 512
  * work-groups for the pass. */

@@ -25,6 +25,7 @@ SMG_TIMED_LEVEL1_BLOCK_PASS = 1
 SMG_TIMED_BOTTOM = 2
 SMG_MAX_MODES = 32
 SMG_OPT_BLOCK_TILE = 3
+SMG_OPT_BLOCK_PAIRS = 4
 SMG_TILE_AUTO = 0
 SMG_TILE_4X4 = 1
 SMG_TILE_4X2 = 2

@@ -300,6 +300,10 @@ class Hierarchy:
                 "8x4": abi.SMG_TILE_8X4}[tile]
         abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_BLOCK_TILE, code))
 
+    def set_block_pairs(self, enable):
+        """Two block colours per launch on Galerkin levels (default) or one."""
+        abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_BLOCK_PAIRS, int(bool(enable))))
+
     def kernel_timing(self, enable, kernel="fine_pass"):
         """Bracket every launch of one kernel class with HIP events: "fine_pass" (level-0
         colour pass), "level1_block_pass" or "bottom"."""

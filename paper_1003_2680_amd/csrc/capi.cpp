@@ -180,14 +180,21 @@ int sweep(Run& r, int l, int slot, bool post) {
     SMG_TRY(ts.close());
   } else {
     const T* noise = (const T*)v.noise_d;
-    TimedScope ts(h, r.s, l == 1 ? SMG_TIMED_LEVEL1_BLOCK_PASS : -1, 8);
+    const T* zn = r.noise ? noise + (size_t)slot * nc * v.n : nullptr;
+    const bool pairs = h.block_pairs && v.nx <= 128 && v.nx % 4 == 0 && v.ny % 4 == 0;
+    TimedScope ts(h, r.s, l == 1 ? SMG_TIMED_LEVEL1_BLOCK_PASS : -1, pairs ? 4 : 8);
     SMG_TRY(ts.rc);
-    for (int t = 0; t < 8; ++t) {
-      const int colour = post ? 7 - t : t;
-      const T* zn = r.noise ? noise + (size_t)slot * nc * v.n : nullptr;
-      SMG_HIP(launch_block_pass<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
-                                   (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz, r.nc,
-                                   colour, zn, h.block_tile, r.s));
+    for (int t = 0; t < 8; t += pairs ? 2 : 1) {
+      const int colour = post ? 7 - t : t;  // with pairs: colour, then colour ^ 1
+      if (pairs) {
+        SMG_HIP(launch_block_pair<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
+                                     (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz,
+                                     r.nc, colour, zn, r.s));
+      } else {
+        SMG_HIP(launch_block_pass<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
+                                     (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz,
+                                     r.nc, colour, zn, h.block_tile, r.s));
+      }
     }
     SMG_TRY(ts.close());
   }
@@ -1726,6 +1733,10 @@ int smg_set_option(smg_hierarchy* hh, int32_t option, int64_t value) {
   }
   if (option == SMG_OPT_BOTTOM_KERNEL && (value == 0 || value == 1)) {
     hh->h.use_bottom = value != 0;
+    return SMG_OK;
+  }
+  if (option == SMG_OPT_BLOCK_PAIRS && (value == 0 || value == 1)) {
+    hh->h.block_pairs = value != 0;
     return SMG_OK;
   }
   if (option == SMG_OPT_BLOCK_TILE && value >= SMG_TILE_AUTO && value <= SMG_TILE_8X4) {

@@ -72,8 +72,15 @@ extern "C" int smg_sample_field_static(smg_hierarchy* hh, int64_t n, uint64_t se
   // ones already there.  Fields that must start at zero are cleared by the sampling path itself.
   int rc = bind_impl(h, (char*)d.ptr, d.owner != h.uid, s);
   if (rc != SMG_OK) {
+    // the copy's tables are in an unknown state, and the hierarchy's device pointers may point
+    // into it: point them back at the caller's workspace (tables there are untouched)
     d.owner = 0;
-    h.ws = prev_ws;
+    if (prev_ws) {
+      bind_impl(h, prev_ws, false, s);
+      h.device = prev_dev;
+    } else {
+      h.ws = nullptr;
+    }
     return rc;
   }
   d.owner = h.uid;

@@ -110,6 +110,13 @@ template <typename T>
 hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
                              int ny, int nz, int ncomp, int colour, const T* z, int tile,
                              hipStream_t s);
+// Block colours c_first and then c_first ^ 1 of one sweep in one launch, with the result of
+// the two single-colour passes in that order; levels with nx <= 128 and nx, ny multiples of 4
+// (hipErrorNotSupported otherwise: the caller runs the two passes).
+template <typename T>
+hipError_t launch_block_pair(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
+                             int ny, int nz, int ncomp, int c_first, const T* z, hipStream_t s);
+
 // One level-0 colour pass over several hierarchies in one launch (up to 8 per launch): each
 // item as the arguments of launch_rb_pass (its colour arrays, right-hand side, shape, active
 // components, h, kT and noise keys); every item has a right-hand side iff has_b.  The result

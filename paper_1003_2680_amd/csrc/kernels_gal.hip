@@ -212,6 +212,136 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
                                             nby2, ntx, zn, xcd_block());
 }
 
+// Two block colours c and c ^ 1 in one launch.  They differ only in the parity of bx, so a
+// block of colour c ^ 1 depends on colour-c blocks only through its x-neighbours in the same
+// block row and layer.  A work-group owns PJ block rows by = 2 (j0 + jl) + cy of one block layer
+// bz = 2 l + cz over the whole x-extent (periodic, so no x-halo), stages the cells within two
+// of them (nx x (4 PJ + 2) x 6, wall planes clamped), draws colour c into the tile, then colour
+// c ^ 1 from the updated tile, and writes both.  No other work-group stages a cell that this
+// one writes (rows of parity cy are four cells apart, and rows and layers of the other parity
+// are not written), and every value is computed by the arithmetic of the single-colour pass
+// from the same inputs, so the result is that of the two single-colour passes in order.
+template <typename T, bool NOISE, int PJ>
+__global__ __launch_bounds__(512) void k_block_pair(T* __restrict__ xg, const T* __restrict__ bg,
+                                                    const T* __restrict__ s1d,
+                                                    const T* __restrict__ zt,
+                                                    const T* __restrict__ bfac, int nx, int ny,
+                                                    int nz, uint32_t N, int c_first, int nby2,
+                                                    int TP, const T* __restrict__ zn) {
+  extern __shared__ char smraw[];
+  T* Tl = reinterpret_cast<T*>(smraw);
+  const Blk3 wg = xcd_block();
+  const uint32_t comp = wg.z;
+  const int cy = (c_first >> 1) & 1, cz = c_first >> 2;
+  const int bz = 2 * (int)wg.y + cz;
+  const int j0 = (int)wg.x * PJ;
+  const int H = 4 * PJ + 2;  // staged rows
+  const int RS = nx;         // row stride of the tile (padding it measured slower)
+  const int y0 = 4 * j0 + 2 * cy - 2, z0 = 2 * bz - 2;
+  const int nthr = (nx >> 2) * PJ * 8;
+  T* X = xg + (size_t)comp * N;
+  const int tid = threadIdx.x;
+  const int k = tid & 7;
+  const int nbx2 = nx >> 2;
+  const int il = (tid >> 3) % nbx2, jl = (tid >> 3) / nbx2;
+  const bool active = j0 + jl < nby2;
+  const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
+  const int by = 2 * (j0 + jl) + cy;
+  const int ty = 4 * jl + 2 + ky, tz = 2 + kz;
+  const int gcy = 2 * by + ky, gcz = 2 * bz + kz;
+  // the lane's cell in each phase: bx = 2 il + (colour & 1)
+  const int cx0 = c_first & 1, cx1 = cx0 ^ 1;
+  const int gx0 = 2 * (2 * il + cx0) + kx, gx1 = 2 * (2 * il + cx1) + kx;
+  const uint32_t row = ((uint32_t)gcz * ny + gcy) * nx;
+  T bk0 = 0, bk1 = 0, n0 = 0, n1 = 0;
+  if (active) {
+    bk0 = bg[(size_t)comp * N + row + gx0];
+    bk1 = bg[(size_t)comp * N + row + gx1];
+    if (NOISE) {
+      n0 = zn[(size_t)comp * N + row + gx0];
+      n1 = zn[(size_t)comp * N + row + gx1];
+    }
+  }
+  // stage: a plane has nx (4 PJ + 2) positions and the group (nx / 4) PJ 8 threads, so every
+  // thread owns at most three positions (2 + 1/PJ per thread); all their loads in all six
+  // planes are issued before the first store, so the group waits for memory once
+  constexpr int PPT = 3;
+  const int plane = nx * H;
+  int goff[PPT], loff[PPT];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const int pos = tid + p * nthr;
+    const bool in = pos < plane;
+    loff[p] = in ? (pos / nx) * RS + pos % nx : -1;
+    goff[p] = in ? wrap_near(y0 + pos / nx, ny) * nx + pos % nx : 0;
+  }
+  T stage[TILE_D][PPT];
+#pragma unroll
+  for (int sz = 0; sz < TILE_D; ++sz) {
+    int gz = z0 + sz;
+    gz = gz < 0 ? 0 : (gz >= nz ? nz - 1 : gz);
+    const T* P = X + (size_t)gz * ny * nx;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) stage[sz][p] = P[goff[p]];  // goff = 0 (in range) if unused
+  }
+#pragma unroll
+  for (int sz = 0; sz < TILE_D; ++sz)
+#pragma unroll
+    for (int p = 0; p < PPT; ++p)
+      if (loff[p] >= 0) Tl[sz * TP + loff[p]] = stage[sz][p];
+  __syncthreads();
+  const T* F = bfac + (size_t)bz * 192;
+  const T* zr = zt + gcz * 10;
+  // one phase: the lane's block of colour bit cxp (tile x = global x, periodic)
+  auto lane_update = [&](int gx, T bk, T nrm) -> T {
+    int xs[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) xs[d] = wrapm(gx + d - 2, nx);
+    const int rows[3] = {ky ? ty + 2 : ty - 2, ty + (ky ? 1 : -1), ty};
+    T q0[3], q1[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      gal_plane_pair<T>(Tl + (3 * kz + j) * TP, RS, xs, rows, s1d, q0[j], q1[j]);
+    T o0[3], o1[3], w0[5], w1[5];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      o0[j] = __shfl_xor(q0[j], 4, 8);
+      o1[j] = __shfl_xor(q1[j], 4, 8);
+    }
+    plane_window(kz, q0, o0, w0);
+    plane_window(kz, q1, o1, w1);
+    T ax = 0, xk = 0;
+    if (active) {
+      T ax0 = 0, ax1 = 0;
+#pragma unroll
+      for (int dz = 0; dz < 5; ++dz) {
+        ax0 = fma(zr[dz], w0[dz], ax0);
+        ax1 = fma(zr[5 + dz], w1[dz], ax1);
+      }
+      ax = ax0 + ax1;
+      xk = Tl[tz * TP + ty * RS + gx];
+    }
+    const T res = bk - ax;
+    T v0 = xk, v1 = NOISE ? nrm : T(0);
+#pragma unroll
+    for (int jj = 0; jj < 8; jj += 2) {
+      v0 = fma(F[k * 8 + jj], __shfl(res, jj, 8), v0);
+      v1 = fma(F[k * 8 + jj + 1], __shfl(res, jj + 1, 8), v1);
+    }
+    return v0 + v1;
+  };
+  // colour c is written into the tile in place: blocks of one colour never read each other's
+  // cells, and the eight lanes of a block are one wave, whose reads precede its writes
+  const T va = lane_update(gx0, bk0, n0);
+  if (active) {
+    Tl[tz * TP + ty * RS + gx0] = va;
+    X[row + gx0] = va;
+  }
+  __syncthreads();
+  const T vb = lane_update(gx1, bk1, n1);
+  if (active) X[row + gx1] = vb;
+}
+
 // The same pass for several levels of different hierarchies (one colour) in one launch: the
 // one-dimensional grid is the concatenation of every item's (tile, layer, component) grid, in
 // XCD-aware order; a work-group finds its item from the offsets and runs the item's pass.
@@ -620,6 +750,32 @@ hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_block_pair(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
+                             int ny, int nz, int ncomp, int c_first, const T* zn,
+                             hipStream_t s) {
+  if (nx > 128 || nx % 4 || ny % 4) return hipErrorNotSupported;
+  const int nby2 = ny / 4, nbzc = (nz / 2 + 1 - (c_first >> 2)) / 2;
+  if (nby2 * nbzc == 0 || ncomp == 0) return hipSuccess;
+  const int PJ = nx <= 64 ? 4 : 2;
+  const int plane = nx * (4 * PJ + 2);
+  const int TP = plane + ((48 - plane % 32) % 32);
+  const size_t lds = (size_t)TILE_D * TP * sizeof(T);
+  const int nthr = (nx / 4) * PJ * 8;
+  dim3 grid((nby2 + PJ - 1) / PJ, nbzc, ncomp);
+  const uint32_t N = (uint32_t)nx * ny * nz;
+#define SMG_PAIR(NZ, P)                                                                   \
+  k_block_pair<T, NZ, P><<<grid, nthr, lds, s>>>(x, b, s1d, zt, bfac, nx, ny, nz, N, c_first, \
+                                                 nby2, TP, zn)
+  if (PJ == 4) {
+    if (zn) SMG_PAIR(true, 4); else SMG_PAIR(false, 4);
+  } else {
+    if (zn) SMG_PAIR(true, 2); else SMG_PAIR(false, 2);
+  }
+#undef SMG_PAIR
+  return hipGetLastError();
+}
+
 template <typename T, int TI, int TJ>
 hipError_t launch_block_multi_tiled(const BlockPassItem<T>* items, int n, int colour, bool noise,
                                     hipStream_t s) {
@@ -781,6 +937,8 @@ hipError_t launch_bottom_multi(const BotMultiArgs& m, int nwg, size_t lds, bool 
 #define SMG_INST(T)                                                                            \
   template hipError_t launch_block_pass<T>(T*, const T*, const T*, const T*, const T*, int, int, \
                                            int, int, int, const T*, int, hipStream_t);          \
+  template hipError_t launch_block_pair<T>(T*, const T*, const T*, const T*, const T*, int, int,  \
+                                           int, int, int, const T*, hipStream_t);               \
   template hipError_t launch_block_pass_multi<T>(const BlockPassItem<T>*, int, int, bool, int,    \
                                                  hipStream_t);                                   \
   template hipError_t launch_residual_gal<T>(T*, const T*, const T*, const T*, const T*, int,    \

@@ -58,6 +58,7 @@ struct Hierarchy {
   size_t bottom_lds = 0;         // its LDS bytes
   bool use_bottom = true;        // false: run those levels with one launch per pass instead
   int block_tile = SMG_TILE_AUTO;  // tile shape of the block-pass launches
+  bool block_pairs = true;         // two block colours per launch where the level allows
   size_t off_botargs = 0;
   BotArgs* botargs_d = nullptr;  // device copy of the bottom kernel's level descriptors
   int nc = 0;                    // unknowns of the coarsest level when it is drawn exactly
