@@ -181,7 +181,7 @@ int sweep(Run& r, int l, int slot, bool post) {
   } else {
     const T* noise = (const T*)v.noise_d;
     const T* zn = r.noise ? noise + (size_t)slot * nc * v.n : nullptr;
-    const bool pairs = h.block_pairs && v.nx <= 128 && v.nx % 4 == 0 && v.ny % 4 == 0;
+    const bool pairs = h.block_pairs && pair_level(v.nx, v.ny);
     TimedScope ts(h, r.s, l == 1 ? SMG_TIMED_LEVEL1_BLOCK_PASS : -1, pairs ? 4 : 8);
     SMG_TRY(ts.rc);
     for (int t = 0; t < 8; t += pairs ? 2 : 1) {
@@ -451,10 +451,13 @@ int cycle_phases(Run& r, int phases, bool residual_ready = false) {
 // The block-colour pass of colour `colour` in sweep `t` (0-based; pre-sweeps first) of level l
 // for every listed run that has it (level l above its bottom, t < its nu1 + nu2 and on the
 // given leg), in one launch.
+// The block-colour passes of colours `colour` and then colour ^ 1 (pairs), or of `colour`
+// alone, for the listed runs as in block_pass_lockstep: levels that take two-colour launches in
+// one pair launch per group, the others in single-colour launches.
 template <typename T>
 int block_pass_lockstep(const std::vector<Run>& legs, int l, int t, bool post, int colour,
-                        bool noise, hipStream_t s) {
-  std::vector<BlockPassItem<T>> items;
+                        bool noise, hipStream_t s, bool pairs) {
+  std::vector<BlockPassItem<T>> items, paired;
   int tile = -1;
   for (const Run& r : legs) {
     Hierarchy& h = *r.h;
@@ -475,12 +478,22 @@ int block_pass_lockstep(const std::vector<Run>& legs, int l, int t, bool post, i
     it.ny = v.ny;
     it.nz = v.nz;
     it.ncomp = r.nc;
+    if (pairs && h.block_pairs && pair_level(v.nx, v.ny)) {
+      paired.push_back(it);
+      continue;
+    }
     items.push_back(it);
     // one tile shape per launch: the common choice of the items, else by work-group count
     tile = tile == -1 ? h.block_tile : (tile == h.block_tile ? tile : SMG_TILE_AUTO);
   }
-  if (items.empty()) return SMG_OK;
-  SMG_HIP(launch_block_pass_multi<T>(items.data(), (int)items.size(), colour, noise, tile, s));
+  if (!paired.empty())
+    SMG_HIP(launch_block_pair_multi<T>(paired.data(), (int)paired.size(), colour, noise, s));
+  if (!items.empty()) {
+    SMG_HIP(launch_block_pass_multi<T>(items.data(), (int)items.size(), colour, noise, tile, s));
+    if (pairs)
+      SMG_HIP(launch_block_pass_multi<T>(items.data(), (int)items.size(), colour ^ 1, noise,
+                                         tile, s));
+  }
   return SMG_OK;
 }
 
@@ -536,10 +549,10 @@ int legs_lockstep(const std::vector<Run>& legs, bool down) {
                                               nz != 0, s));
           }
       }
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < 8; k += 2) {  // colour pairs (c, c ^ 1) in sweep order
         const int colour = down ? k : 7 - k;
         for (int nz = 0; nz < 2; ++nz)
-          SMG_TRY(block_pass_lockstep<T>(legs, l, t, !down, colour, nz != 0, s));
+          SMG_TRY(block_pass_lockstep<T>(legs, l, t, !down, colour, nz != 0, s, true));
       }
     }
     return SMG_OK;

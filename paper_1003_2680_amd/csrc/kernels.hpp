@@ -113,6 +113,8 @@ hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const 
 // Block colours c_first and then c_first ^ 1 of one sweep in one launch, with the result of
 // the two single-colour passes in that order; levels with nx <= 128 and nx, ny multiples of 4
 // (hipErrorNotSupported otherwise: the caller runs the two passes).
+// true where a Galerkin level's sweeps can run as two-colour launches
+inline bool pair_level(int nx, int ny) { return nx <= 128 && nx % 4 == 0 && ny % 4 == 0; }
 template <typename T>
 hipError_t launch_block_pair(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
                              int ny, int nz, int ncomp, int c_first, const T* z, hipStream_t s);
@@ -171,6 +173,30 @@ struct BlockMultiArgs {
 template <typename T>
 hipError_t launch_block_pass_multi(const BlockPassItem<T>* items, int n, int colour, bool noise,
                                    int tile, hipStream_t s);
+// Colours c_first, then c_first ^ 1, of several levels in as few launches as possible (items
+// grouped by rows per work-group); every item must satisfy pair_level (hipErrorNotSupported
+// otherwise, before any launch).
+template <typename T>
+struct PairMultiItem {
+  T* x;
+  const T* b;
+  const T* s1d;
+  const T* zt;
+  const T* bfac;
+  const T* zn;
+  int nx, ny, nz;
+  uint32_t N;
+  int nby2, nbzc, ngx, TP;
+};
+template <typename T>
+struct PairMultiArgs {
+  int nitems, c_first;
+  uint32_t begin[kBlockMultiItems + 1];
+  PairMultiItem<T> it[kBlockMultiItems];
+};
+template <typename T>
+hipError_t launch_block_pair_multi(const BlockPassItem<T>* items, int n, int c_first,
+                                   bool noise, hipStream_t s);
 template <typename T>
 hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStream_t s);
 // `a` points to a BotArgs in device memory

@@ -8,6 +8,8 @@
 // block is redrawn from its exact 8-variable conditional law.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "device_common.hpp"
@@ -221,16 +223,18 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
 // one writes (rows of parity cy are four cells apart, and rows and layers of the other parity
 // are not written), and every value is computed by the arithmetic of the single-colour pass
 // from the same inputs, so the result is that of the two single-colour passes in order.
+// The work of one work-group wg = (row group, layer, component); threads past the level's
+// (nx / 4) PJ 8 take part in the staging only.
 template <typename T, bool NOISE, int PJ>
-__global__ __launch_bounds__(512) void k_block_pair(T* __restrict__ xg, const T* __restrict__ bg,
-                                                    const T* __restrict__ s1d,
-                                                    const T* __restrict__ zt,
-                                                    const T* __restrict__ bfac, int nx, int ny,
-                                                    int nz, uint32_t N, int c_first, int nby2,
-                                                    int TP, const T* __restrict__ zn) {
+__device__ __forceinline__ void block_pair_body(T* __restrict__ xg, const T* __restrict__ bg,
+                                                const T* __restrict__ s1d,
+                                                const T* __restrict__ zt,
+                                                const T* __restrict__ bfac, int nx, int ny,
+                                                int nz, uint32_t N, int c_first, int nby2,
+                                                int TP, const T* __restrict__ zn,
+                                                const Blk3 wg) {
   extern __shared__ char smraw[];
   T* Tl = reinterpret_cast<T*>(smraw);
-  const Blk3 wg = xcd_block();
   const uint32_t comp = wg.z;
   const int cy = (c_first >> 1) & 1, cz = c_first >> 2;
   const int bz = 2 * (int)wg.y + cz;
@@ -238,16 +242,19 @@ __global__ __launch_bounds__(512) void k_block_pair(T* __restrict__ xg, const T*
   const int H = 4 * PJ + 2;  // staged rows
   const int RS = nx;         // row stride of the tile (padding it measured slower)
   const int y0 = 4 * j0 + 2 * cy - 2, z0 = 2 * bz - 2;
-  const int nthr = (nx >> 2) * PJ * 8;
+  const int nthr = (int)blockDim.x;  // >= (nx / 4) PJ 8
   T* X = xg + (size_t)comp * N;
   const int tid = threadIdx.x;
   const int k = tid & 7;
   const int nbx2 = nx >> 2;
   const int il = (tid >> 3) % nbx2, jl = (tid >> 3) / nbx2;
-  const bool active = j0 + jl < nby2;
+  const bool active = jl < PJ && j0 + jl < nby2;
+  // rows of inactive lanes past the group's PJ rows are taken as row 0 for addressing only,
+  // so that every tile read stays inside the staged rows
+  const int jr = jl < PJ ? jl : 0;
   const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
-  const int by = 2 * (j0 + jl) + cy;
-  const int ty = 4 * jl + 2 + ky, tz = 2 + kz;
+  const int by = 2 * (j0 + jr) + cy;
+  const int ty = 4 * jr + 2 + ky, tz = 2 + kz;
   const int gcy = 2 * by + ky, gcz = 2 * bz + kz;
   // the lane's cell in each phase: bx = 2 il + (colour & 1)
   const int cx0 = c_first & 1, cx1 = cx0 ^ 1;
@@ -340,6 +347,36 @@ __global__ __launch_bounds__(512) void k_block_pair(T* __restrict__ xg, const T*
   __syncthreads();
   const T vb = lane_update(gx1, bk1, n1);
   if (active) X[row + gx1] = vb;
+}
+
+template <typename T, bool NOISE, int PJ>
+__global__ __launch_bounds__(512) void k_block_pair(T* __restrict__ xg, const T* __restrict__ bg,
+                                                    const T* __restrict__ s1d,
+                                                    const T* __restrict__ zt,
+                                                    const T* __restrict__ bfac, int nx, int ny,
+                                                    int nz, uint32_t N, int c_first, int nby2,
+                                                    int TP, const T* __restrict__ zn) {
+  block_pair_body<T, NOISE, PJ>(xg, bg, s1d, zt, bfac, nx, ny, nz, N, c_first, nby2, TP, zn,
+                                xcd_block());
+}
+
+// Two-colour launches of several levels of different hierarchies (the same colour pair and
+// rows per group) in one launch: the flat grid concatenates the items' (row group, layer,
+// component) grids; the block size and the LDS are the largest the items need.
+template <typename T, bool NOISE, int PJ>
+__global__ __launch_bounds__(512) void k_block_pair_multi(PairMultiArgs<T> m) {
+  const uint32_t lin = xcd_block().x;
+  int i = 0;
+  while (i + 1 < m.nitems && lin >= m.begin[i + 1]) ++i;
+  const PairMultiItem<T>& it = m.it[i];
+  const uint32_t local = lin - m.begin[i];
+  Blk3 wg;
+  wg.x = local % (uint32_t)it.ngx;
+  const uint32_t rest = local / (uint32_t)it.ngx;
+  wg.y = rest % (uint32_t)it.nbzc;
+  wg.z = rest / (uint32_t)it.nbzc;
+  block_pair_body<T, NOISE, PJ>(it.x, it.b, it.s1d, it.zt, it.bfac, it.nx, it.ny, it.nz, it.N,
+                                m.c_first, it.nby2, it.TP, it.zn, wg);
 }
 
 // The same pass for several levels of different hierarchies (one colour) in one launch: the
@@ -776,6 +813,69 @@ hipError_t launch_block_pair(T* x, const T* b, const T* s1d, const T* zt, const 
   return hipGetLastError();
 }
 
+template <typename T, int PJ>
+hipError_t launch_pair_multi_pj(const BlockPassItem<T>* items, int n, int c_first, bool noise,
+                                hipStream_t s) {
+  PairMultiArgs<T> m{};
+  m.c_first = c_first;
+  uint32_t total = 0;
+  int nthr = 0;
+  size_t lds = 0;
+  auto flush = [&]() -> hipError_t {
+    if (m.nitems == 0) return hipSuccess;
+    m.begin[m.nitems] = total;
+    if (noise) k_block_pair_multi<T, true, PJ><<<total, nthr, lds, s>>>(m);
+    else k_block_pair_multi<T, false, PJ><<<total, nthr, lds, s>>>(m);
+    m.nitems = 0;
+    total = 0;
+    nthr = 0;
+    lds = 0;
+    return hipGetLastError();
+  };
+  for (int q = 0; q < n; ++q) {
+    const BlockPassItem<T>& p = items[q];
+    if ((p.nx <= 64 ? 4 : 2) != PJ) continue;
+    const int nby2 = p.ny / 4, nbzc = (p.nz / 2 + 1 - (c_first >> 2)) / 2;
+    if (nby2 * nbzc == 0 || p.ncomp == 0) continue;
+    if (m.nitems == kBlockMultiItems) {
+      hipError_t e = flush();
+      if (e != hipSuccess) return e;
+    }
+    PairMultiItem<T>& it = m.it[m.nitems];
+    it.x = p.x;
+    it.b = p.b;
+    it.s1d = p.s1d;
+    it.zt = p.zt;
+    it.bfac = p.bfac;
+    it.zn = p.zn;
+    it.nx = p.nx;
+    it.ny = p.ny;
+    it.nz = p.nz;
+    it.N = (uint32_t)p.nx * p.ny * p.nz;
+    it.nby2 = nby2;
+    it.nbzc = nbzc;
+    it.ngx = (nby2 + PJ - 1) / PJ;
+    const int plane = p.nx * (4 * PJ + 2);
+    it.TP = plane + ((48 - plane % 32) % 32);
+    m.begin[m.nitems] = total;
+    total += (uint32_t)it.ngx * nbzc * p.ncomp;
+    nthr = std::max(nthr, (p.nx / 4) * PJ * 8);
+    lds = std::max(lds, (size_t)TILE_D * it.TP * sizeof(T));
+    ++m.nitems;
+  }
+  return flush();
+}
+
+template <typename T>
+hipError_t launch_block_pair_multi(const BlockPassItem<T>* items, int n, int c_first,
+                                   bool noise, hipStream_t s) {
+  for (int q = 0; q < n; ++q)
+    if (!pair_level(items[q].nx, items[q].ny)) return hipErrorNotSupported;
+  hipError_t e = launch_pair_multi_pj<T, 4>(items, n, c_first, noise, s);
+  if (e != hipSuccess) return e;
+  return launch_pair_multi_pj<T, 2>(items, n, c_first, noise, s);
+}
+
 template <typename T, int TI, int TJ>
 hipError_t launch_block_multi_tiled(const BlockPassItem<T>* items, int n, int colour, bool noise,
                                     hipStream_t s) {
@@ -939,6 +1039,8 @@ hipError_t launch_bottom_multi(const BotMultiArgs& m, int nwg, size_t lds, bool 
                                            int, int, int, const T*, int, hipStream_t);          \
   template hipError_t launch_block_pair<T>(T*, const T*, const T*, const T*, const T*, int, int,  \
                                            int, int, int, const T*, hipStream_t);               \
+  template hipError_t launch_block_pair_multi<T>(const BlockPassItem<T>*, int, int, bool,          \
+                                                 hipStream_t);                                   \
   template hipError_t launch_block_pass_multi<T>(const BlockPassItem<T>*, int, int, bool, int,    \
                                                  hipStream_t);                                   \
   template hipError_t launch_residual_gal<T>(T*, const T*, const T*, const T*, const T*, int,    \
