@@ -369,8 +369,9 @@ int smg_kernel_timing_read(smg_hierarchy* h, int64_t* count, double* total_ms);
  * are ignored on input; outputs write them as 0 only where stated); fine part float64
  * [2(box[5]-box[4])][2(box[3]-box[2])][2(box[1]-box[0])].  One component per field.  Noise
  * streams as for the uniform grid with kind 2 (composite passes: level 0, colour = class,
- * slot = sweep, site = index in its own array), kind 3 (base block levels) and kind 4 (the
- * coarsest base level).  Memory, stream and error conventions as above. */
+ * slot = sweep, site = index in its own array, halved in the four parity classes 0..3, whose
+ * cells are one of each pair (2q, 2q+1) of their array), kind 3 (base block levels) and kind 4
+ * (the coarsest base level).  Memory, stream and error conventions as above. */
 typedef struct smg_composite smg_composite;
 
 typedef struct {

@@ -53,9 +53,11 @@ classes of mutually uncoupled cells, in this order:
 the eight parity classes).
 
 Noise streams (shared counter convention of the package, see oracle.philox): composite
-passes draw from (level 0, slot = sweep, colour = class, kind KIND_COMPOSITE) at site =
-the cell's natural index in its own array (base grid for coarse cells, box for fine
-cells); the base hierarchy draws with kind KIND_FAC_BASE (block levels) and
+passes draw from (level 0, slot = sweep, colour = class, kind KIND_COMPOSITE); the site of a
+cell is its natural index in its own array (base grid for coarse cells, box for fine cells),
+halved (index >> 1) in the four parity classes 0..3: a parity class holds one cell of every
+pair (2q, 2q + 1) of its array (nx and the fine extents are even), so the halved indices are
+distinct and consecutive cells of the class share a Philox call; the base hierarchy draws with kind KIND_FAC_BASE (block levels) and
 KIND_FAC_COARSEST (coarsest), level = base level index, sites as in oracle.mg.
 """
 import numpy as np
@@ -301,7 +303,7 @@ class CompositeGrid:
 
     # ------------------------------------------------------------- sweep classes
     def classes(self):
-        """The twelve point classes of a composite sweep: list of (composite ids, sites)."""
+        """The twelve point classes of a composite sweep: list of (composite ids, noise sites)."""
         out = []
         cx = self.coarse_cells % self.nx
         cy = (self.coarse_cells // self.nx) % self.ny
@@ -310,7 +312,7 @@ class CompositeGrid:
         ids = np.arange(self.nc)
         for c in range(2):
             sel = par == c
-            out.append((ids[sel], self.coarse_cells[sel]))
+            out.append((ids[sel], self.coarse_cells[sel] >> 1))
         if self.box is None:
             for _ in range(10):
                 out.append((np.zeros(0, np.int64), np.zeros(0, np.int64)))
@@ -322,7 +324,7 @@ class CompositeGrid:
         layer = self.layer_mask(i, j, k)
         for c in range(2):
             sel = (~layer) & ((i + j + k) % 2 == c)
-            out.append((self.nc + loc[sel], loc[sel]))
+            out.append((self.nc + loc[sel], loc[sel] >> 1))
         pc = (i % 2) + 2 * (j % 2) + 4 * (k % 2)
         for p in range(8):
             sel = layer & (pc == p)

@@ -27,6 +27,26 @@ __device__ __forceinline__ int fidx(const CompGeom& g, int i, int j, int k) {
   return i + g.fx * (j + g.fy * k);
 }
 
+// 1/sqrt(a) for a > 0: the hardware estimate refined by Newton steps y <- y (3/2 - (a/2) y^2),
+// each of which roughly squares the relative error (two for FP64, one for FP32), within a few
+// ulp.  The point passes take 1/a = r^2 and the noise scale sqrt(kT) r from it, instead of a
+// division, a square root and a second division per cell.
+template <typename T>
+__device__ __forceinline__ T rsqrt_refined(T a);
+template <>
+__device__ __forceinline__ double rsqrt_refined<double>(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  const double h = 0.5 * a;
+  y = y * fma(-h, y * y, 1.5);
+  y = y * fma(-h, y * y, 1.5);
+  return y;
+}
+template <>
+__device__ __forceinline__ float rsqrt_refined<float>(float a) {
+  float y = __builtin_amdgcn_rsqf(a);
+  return y * fmaf(-0.5f * a, y * y, 1.5f);
+}
+
 // the normal of `site` in the stream of na: call site/2, first or second of the pair
 template <typename T>
 __device__ __forceinline__ T normal_at(const NoiseArgs& na, uint32_t site) {
@@ -173,6 +193,9 @@ __device__ __forceinline__ void fine_row(const T* __restrict__ xf, const T* __re
   }
 }
 
+// Coarse class `colour` (cells with (x+y+z) % 2 == colour).  Its noise site is the cell's base
+// index halved, h = jx + (nx/2) row with x = 2 jx + ((y+z+colour) & 1); thread t takes the
+// sites 2t and 2t + 1, the two normals of Philox call t.
 template <typename T, bool NOISE>
 __global__ __launch_bounds__(TPB) void k_comp_coarse_pass(T* __restrict__ xc,
                                                           const T* __restrict__ bc,
@@ -180,50 +203,65 @@ __global__ __launch_bounds__(TPB) void k_comp_coarse_pass(T* __restrict__ xc,
                                                           int colour, NoiseArgs na) {
   const int hx = g.nx >> 1;
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
-  if (t >= (uint32_t)hx * g.ny * g.nz) return;
-  const int jx = t % hx;
-  const int row = t / hx;
-  const int y = row % g.ny, z = row / g.ny;
-  const int x = 2 * jx + ((y + z + colour) & 1);
-  if (covered(g, x, y, z)) return;
-  T diag, off;
-  coarse_row<T>(xc, xf, g, x, y, z, diag, off);
-  const uint32_t site = x + g.nx * (y + g.ny * z);
-  const T ih2 = (T)g.ih2;
-  const T a = diag * ih2;
-  T v = ((bc ? bc[site] : T(0)) + off * ih2) / a;
-  if (NOISE) v = fma((T)na.sqkT / sqrt(a), normal_at<T>(na, site), v);
-  xc[site] = v;
+  if (2 * t >= (uint32_t)hx * g.ny * g.nz) return;  // hx ny nz is even (ny is)
+  T z[2] = {T(0), T(0)};
+  if (NOISE) normal_pair_t<T>(na, na.sid, 0u, t, z[0], z[1]);
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t h = 2 * t + q;
+    const int jx = h % hx;
+    const int row = h / hx;
+    const int y = row % g.ny, zz = row / g.ny;
+    const int x = 2 * jx + ((y + zz + colour) & 1);
+    if (covered(g, x, y, zz)) continue;
+    T diag, off;
+    coarse_row<T>(xc, xf, g, x, y, zz, diag, off);
+    const uint32_t cell = x + g.nx * (y + g.ny * zz);
+    const T ih2 = (T)g.ih2;
+    const T ra = rsqrt_refined<T>(diag * ih2);
+    T v = ((bc ? bc[cell] : T(0)) + off * ih2) * (ra * ra);
+    if (NOISE) v = fma((T)na.sqkT * ra, z[q], v);
+    xc[cell] = v;
+  }
 }
 
+// Fine cell (i, j, k) with its normal n.
 template <typename T, bool NOISE>
 __device__ __forceinline__ void fine_update(T* __restrict__ xf, const T* __restrict__ bf,
                                             const T* __restrict__ xc, const CompGeom& g, int i,
-                                            int j, int k, const NoiseArgs& na) {
+                                            int j, int k, const NoiseArgs& na, T n) {
   T diag, off;
   fine_row<T>(xf, xc, g, i, j, k, diag, off);
-  const uint32_t site = fidx(g, i, j, k);
+  const uint32_t cell = fidx(g, i, j, k);
   const T ih2 = (T)g.ih2;
-  const T a = diag * ih2;
-  T v = ((bf ? bf[site] : T(0)) + off * ih2) / a;
-  if (NOISE) v = fma((T)na.sqkT / sqrt(a), normal_at<T>(na, site), v);
-  xf[site] = v;
+  const T ra = rsqrt_refined<T>(diag * ih2);
+  T v = ((bf ? bf[cell] : T(0)) + off * ih2) * (ra * ra);
+  if (NOISE) v = fma((T)na.sqkT * ra, n, v);
+  xf[cell] = v;
 }
 
+// Fine class 2 + colour off the interface layer: noise sites as for the coarse classes (the
+// box index halved), thread t the sites 2t and 2t + 1 of Philox call t.
 template <typename T, bool NOISE>
 __global__ __launch_bounds__(TPB) void k_comp_fine_pass(T* __restrict__ xf,
                                                         const T* __restrict__ bf, CompGeom g,
                                                         int colour, NoiseArgs na) {
   const int hx = g.fx >> 1;
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
-  if (t >= (uint32_t)hx * g.fy * g.fz) return;
-  const int jx = t % hx;
-  const int row = t / hx;
-  const int j = row % g.fy, k = row / g.fy;
-  const int i = 2 * jx + ((j + k + colour) & 1);
-  if (on_layer(g, i, j, k)) return;
-  // off the layer every neighbour is a fine cell or a wall: the coarse field is never read
-  fine_update<T, NOISE>(xf, bf, nullptr, g, i, j, k, na);
+  if (2 * t >= (uint32_t)hx * g.fy * g.fz) return;  // hx fy fz is even (fy is)
+  T z[2] = {T(0), T(0)};
+  if (NOISE) normal_pair_t<T>(na, na.sid, 0u, t, z[0], z[1]);
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t h = 2 * t + q;
+    const int jx = h % hx;
+    const int row = h / hx;
+    const int j = row % g.fy, k = row / g.fy;
+    const int i = 2 * jx + ((j + k + colour) & 1);
+    if (on_layer(g, i, j, k)) continue;
+    // off the layer every neighbour is a fine cell or a wall: the coarse field is never read
+    fine_update<T, NOISE>(xf, bf, nullptr, g, i, j, k, na, z[q]);
+  }
 }
 
 template <typename T, bool NOISE>
@@ -234,10 +272,11 @@ __global__ __launch_bounds__(TPB) void k_comp_layer_pass(T* __restrict__ xf,
                                                          int count, NoiseArgs na) {
   const int t = blockIdx.x * TPB + threadIdx.x;
   if (t >= count) return;
-  const int site = cells[t];
+  const int site = cells[t];  // layer classes: the noise site is the box index itself
   const int i = site % g.fx;
   const int row = site / g.fx;
-  fine_update<T, NOISE>(xf, bf, xc, g, i, row % g.fy, row / g.fy, na);
+  fine_update<T, NOISE>(xf, bf, xc, g, i, row % g.fy, row / g.fy, na,
+                        NOISE ? normal_at<T>(na, (uint32_t)site) : T(0));
 }
 
 template <typename T>
@@ -666,7 +705,7 @@ hipError_t launch_dense_draw(T* x, const T* b, const double* ainv, const double*
 template <typename T>
 hipError_t launch_comp_coarse_pass(T* xc, const T* bc, const T* xf, const CompGeom& g, int colour,
                                    bool noise, const NoiseArgs& na, hipStream_t s) {
-  const uint32_t grid = grid_for((int64_t)(g.nx / 2) * g.ny * g.nz);
+  const uint32_t grid = grid_for((int64_t)(g.nx / 2) * g.ny * g.nz / 2);  // two cells a thread
   if (noise) k_comp_coarse_pass<T, true><<<grid, TPB, 0, s>>>(xc, bc, xf, g, colour, na);
   else k_comp_coarse_pass<T, false><<<grid, TPB, 0, s>>>(xc, bc, xf, g, colour, na);
   return hipGetLastError();
@@ -675,7 +714,7 @@ hipError_t launch_comp_coarse_pass(T* xc, const T* bc, const T* xf, const CompGe
 template <typename T>
 hipError_t launch_comp_fine_pass(T* xf, const T* bf, const CompGeom& g, int colour, bool noise,
                                  const NoiseArgs& na, hipStream_t s) {
-  const uint32_t grid = grid_for((int64_t)(g.fx / 2) * g.fy * g.fz);
+  const uint32_t grid = grid_for((int64_t)(g.fx / 2) * g.fy * g.fz / 2);  // two cells a thread
   if (noise) k_comp_fine_pass<T, true><<<grid, TPB, 0, s>>>(xf, bf, g, colour, na);
   else k_comp_fine_pass<T, false><<<grid, TPB, 0, s>>>(xf, bf, g, colour, na);
   return hipGetLastError();

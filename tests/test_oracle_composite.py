@@ -129,6 +129,21 @@ def test_classes_partition_unknowns():
     assert np.array_equal(np.sort(ids), np.arange(g.n))
 
 
+def test_class_noise_sites_distinct():
+    """Every class draws distinct noise sites: the halved indices of the parity classes (one
+    cell of each pair (2q, 2q + 1) of its array) and the plain indices of the layer classes;
+    consecutive cells of a parity class in a row share a Philox call (sites 2m, 2m + 1)."""
+    for box in ((2, 6, 2, 6, 2, 6), (0, 4, 1, 7, 0, 8), (3, 5, 2, 4, 1, 3)):
+        g = CompositeGrid(8, 8, 8, box)
+        for c, (ids, sites) in enumerate(g.classes()):
+            assert np.unique(sites).size == sites.size, (box, c)
+        # coarse parity class 0: base cells (x, y, z) and (x + 2, y, z) are halved sites
+        # differing by one, so pairs of neighbours along x share a call
+        ids, sites = g.classes()[0]
+        cells = g.coarse_cells[ids]
+        assert np.array_equal(sites, cells >> 1)
+
+
 def test_fac_cycle_is_exact_and_fast():
     g = CompositeGrid(8, 8, 4, (2, 6, 2, 6, 0, 2))
     kT = 1.3
