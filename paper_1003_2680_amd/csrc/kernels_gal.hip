@@ -216,8 +216,9 @@ __global__ __launch_bounds__(TILE_I * TILE_J * 8) void k_block_tile(T* __restric
 
 // Two block colours c and c ^ 1 in one launch.  They differ only in the parity of bx, so a
 // block of colour c ^ 1 depends on colour-c blocks only through its x-neighbours in the same
-// block row and layer.  A work-group owns PJ block rows by = 2 (j0 + jl) + cy of one block layer
-// bz = 2 l + cz over the whole x-extent (periodic, so no x-halo), stages the cells within two
+// block row and layer.  A work-group owns PJ (4, 2 or 1: see pair_rows) block rows
+// by = 2 (j0 + jl) + cy of one block layer bz = 2 l + cz over the whole x-extent (periodic, so
+// no x-halo), stages the cells within two
 // of them (nx x (4 PJ + 2) x 6, wall planes clamped), draws colour c into the tile, then colour
 // c ^ 1 from the updated tile, and writes both.  No other work-group stages a cell that this
 // one writes (rows of parity cy are four cells apart, and rows and layers of the other parity
@@ -787,6 +788,16 @@ hipError_t launch_block_pass(T* x, const T* b, const T* s1d, const T* zt, const 
   return hipGetLastError();
 }
 
+// Block rows per work-group of a two-colour launch: the most (4, or 2 above 64 cells in x, for
+// the least staging overlap) that still gives the launch about eight work-groups per compute
+// unit, else one.
+inline int pair_rows(int nx, int ny, int nz, int ncomp, int c_first) {
+  const int nby2 = ny / 4, nbzc = (nz / 2 + 1 - (c_first >> 2)) / 2;
+  int pj = nx <= 64 ? 4 : 2;
+  while (pj > 1 && (int64_t)((nby2 + pj - 1) / pj) * nbzc * ncomp < 2048) pj /= 2;
+  return pj;
+}
+
 template <typename T>
 hipError_t launch_block_pair(T* x, const T* b, const T* s1d, const T* zt, const T* bfac, int nx,
                              int ny, int nz, int ncomp, int c_first, const T* zn,
@@ -794,7 +805,7 @@ hipError_t launch_block_pair(T* x, const T* b, const T* s1d, const T* zt, const 
   if (nx > 128 || nx % 4 || ny % 4) return hipErrorNotSupported;
   const int nby2 = ny / 4, nbzc = (nz / 2 + 1 - (c_first >> 2)) / 2;
   if (nby2 * nbzc == 0 || ncomp == 0) return hipSuccess;
-  const int PJ = nx <= 64 ? 4 : 2;
+  const int PJ = pair_rows(nx, ny, nz, ncomp, c_first);
   const int plane = nx * (4 * PJ + 2);
   const int TP = plane + ((48 - plane % 32) % 32);
   const size_t lds = (size_t)TILE_D * TP * sizeof(T);
@@ -806,8 +817,10 @@ hipError_t launch_block_pair(T* x, const T* b, const T* s1d, const T* zt, const 
                                                  nby2, TP, zn)
   if (PJ == 4) {
     if (zn) SMG_PAIR(true, 4); else SMG_PAIR(false, 4);
-  } else {
+  } else if (PJ == 2) {
     if (zn) SMG_PAIR(true, 2); else SMG_PAIR(false, 2);
+  } else {
+    if (zn) SMG_PAIR(true, 1); else SMG_PAIR(false, 1);
   }
 #undef SMG_PAIR
   return hipGetLastError();
@@ -834,7 +847,7 @@ hipError_t launch_pair_multi_pj(const BlockPassItem<T>* items, int n, int c_firs
   };
   for (int q = 0; q < n; ++q) {
     const BlockPassItem<T>& p = items[q];
-    if ((p.nx <= 64 ? 4 : 2) != PJ) continue;
+    if (pair_rows(p.nx, p.ny, p.nz, p.ncomp, c_first) != PJ) continue;
     const int nby2 = p.ny / 4, nbzc = (p.nz / 2 + 1 - (c_first >> 2)) / 2;
     if (nby2 * nbzc == 0 || p.ncomp == 0) continue;
     if (m.nitems == kBlockMultiItems) {
@@ -872,8 +885,9 @@ hipError_t launch_block_pair_multi(const BlockPassItem<T>* items, int n, int c_f
   for (int q = 0; q < n; ++q)
     if (!pair_level(items[q].nx, items[q].ny)) return hipErrorNotSupported;
   hipError_t e = launch_pair_multi_pj<T, 4>(items, n, c_first, noise, s);
-  if (e != hipSuccess) return e;
-  return launch_pair_multi_pj<T, 2>(items, n, c_first, noise, s);
+  if (e == hipSuccess) e = launch_pair_multi_pj<T, 2>(items, n, c_first, noise, s);
+  if (e == hipSuccess) e = launch_pair_multi_pj<T, 1>(items, n, c_first, noise, s);
+  return e;
 }
 
 template <typename T, int TI, int TJ>
