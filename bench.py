@@ -60,6 +60,7 @@ NX = NY = NZ = 128
 NCOMP = 3
 LEVELS = 6
 SAMPLES_PER_STEP = 8
+CHAIN_STREAMS = 2  # the batched chains run in this many groups, each on a stream of its own
 HBM_PEAK_GBS = 8000.0
 METRIC = "decorrelated 128³ field samples/s + p99 latency; achieved HBM GB/s"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_128cubed_3comp_fp64.json")
@@ -245,7 +246,8 @@ def measure_solves(precision, fs, rtol=1e-12):
             "solve_cycles": float(np.mean(cyc))}
 
 
-def measure(precision, args, dev, stride, chains, steps, timing=True):
+def measure(precision, args, dev, stride, chains, steps, timing=True,
+            chain_streams=CHAIN_STREAMS):
     """Sampling (and per-launch kernel times) of one precision mode: `chains` chains of the
     3-component field batched, one emitted sample every `stride` cycles."""
     import torch
@@ -254,6 +256,7 @@ def measure(precision, args, dev, stride, chains, steps, timing=True):
     C = chains
     H = Hierarchy(NX, NY, NZ, ncomp=NCOMP * C, kT=1.0, levels=LEVELS, nu1=2, nu2=2,
                   precision=precision, stride=stride, burn_in=0)
+    H.set_chain_streams(chain_streams)
     out = torch.empty((SAMPLES_PER_STEP, NCOMP * C, NZ, NY, NX), dtype=torch.float64,
                       device=dev)
     ms, lat, obs, state = run_batch(H, C, steps, args.warmup, SAMPLES_PER_STEP, out)
@@ -786,9 +789,11 @@ def main():
         "config": {"workload": "128x128x128 wall-bounded cell-centred Laplacian (periodic x,y; "
                                "no-slip z walls), 3-component field, 6-level stochastic "
                                "V(2,2) cycle, FP64; the chains of seeds 0..%d batched into "
-                               "every launch" % (C - 1),
+                               "every launch, in %d groups on streams of their own"
+                               % (C - 1, CHAIN_STREAMS),
                    "grid": [NX, NY, NZ], "ncomp": NCOMP, "levels": LEVELS, "nu": [2, 2],
-                   "chains": C, "samples_per_step": C * SAMPLES_PER_STEP, "k_dec": k_dec,
+                   "chains": C, "chain_streams": CHAIN_STREAMS,
+                   "samples_per_step": C * SAMPLES_PER_STEP, "k_dec": k_dec,
                    "cycles_per_step": SAMPLES_PER_STEP * k_dec},
         "samples_per_s": round(samples_per_s, 2),
         "emission": "one sample per chain every k_dec cycles (each emitted sample is a "

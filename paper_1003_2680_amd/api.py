@@ -154,13 +154,15 @@ class Hierarchy:
         return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
 
     def sample(self, n, seed, first_cycle=0, state=None, out_dtype=torch.float64, out=None):
-        """Run the chain; returns (samples [n, ncomp, nz, ny, nx], state)."""
+        """Run the chain; returns (samples [n, ncomp, nz, ny, nx], state).  A caller's `out`
+        (float64 or float32, contiguous) decides the type written; out_dtype only sets that of
+        a new one."""
         if state is None:
             state = self.new_state()
         self._check_field(state)
         if out is None and n > 0:
             out = torch.empty((n,) + self.shape, dtype=out_dtype, device=self.device)
-        code = abi.SMG_OUT_F32 if out_dtype == torch.float32 else abi.SMG_OUT_F64
+        code = self._out_code(out, n, self.shape) if out is not None else abi.SMG_OUT_F64
         abi.check(self.lib.smg_sample_field(self._h, int(n), int(seed), int(first_cycle),
                                             _ptr(state), _ptr(out) if n > 0 else None, code,
                                             _stream(self.device)))
@@ -185,10 +187,8 @@ class Hierarchy:
             obs = torch.empty((n, self.shape[0], len(modes) + 1), dtype=torch.float64,
                               device=self.device)
         if moments is not None:
-            if moments.dtype != torch.float64 or tuple(moments.shape) != (2,) + self.shape \
-                    or not moments.is_contiguous():
-                raise ValueError("moments must be a contiguous float64 (2,) + shape tensor")
-        code = abi.SMG_OUT_F32 if out_dtype == torch.float32 else abi.SMG_OUT_F64
+            self._check_moments(moments, self.shape)
+        code = self._out_code(out, n, self.shape) if out is not None else abi.SMG_OUT_F64
         abi.check(self.lib.smg_sample_stats(
             self._h, int(n), int(seed), int(first_cycle), _ptr(state),
             _ptr(out) if out is not None else None, code, marr, len(modes),
@@ -211,7 +211,8 @@ class Hierarchy:
         """Run nchains independent chains (seeds[c], first_cycles[c]) in the same launches.
 
         seeds=None continues the chains of the previous batched call (nchains required).
-        emit=False runs the cycles without writing samples (unless `out` is given).
+        emit=False runs the cycles without writing samples (unless `out` is given); a caller's
+        `out` decides the type written (float64 or float32).
         Returns (out [n, nact, nz, ny, nx] or None, obs or None, state [nact, nz, ny, nx])
         with nact = nchains * comps_per_chain."""
         if seeds is not None:
@@ -223,6 +224,8 @@ class Hierarchy:
             raise ValueError("state must be a contiguous float64 %s tensor" % (fshape,))
         if out is None and n > 0 and emit and not with_obs and moments is None:
             out = torch.empty((n,) + fshape, dtype=out_dtype, device=self.device)
+        if moments is not None:
+            self._check_moments(moments, fshape)
         sd = fc = None
         if seeds is not None:
             sd = (ctypes.c_uint64 * nchains)(*[int(v) for v in seeds])
@@ -235,7 +238,7 @@ class Hierarchy:
             nm = len(modes)
             marr = (ctypes.c_int32 * (3 * max(nm, 1)))(*[int(v) for md in modes for v in md])
             obs = torch.empty((n, fshape[0], nm + 1), dtype=torch.float64, device=self.device)
-        code = abi.SMG_OUT_F32 if out_dtype == torch.float32 else abi.SMG_OUT_F64
+        code = self._out_code(out, n, fshape) if out is not None else abi.SMG_OUT_F64
         abi.check(self.lib.smg_sample_batch(
             self._h, int(nchains), int(cpc), sd, fc, int(n), _ptr(state),
             _ptr(out) if out is not None else None, code, marr, nm,
@@ -304,6 +307,12 @@ class Hierarchy:
         """Two block colours per launch on Galerkin levels (default) or one."""
         abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_BLOCK_PAIRS, int(bool(enable))))
 
+    def set_chain_streams(self, n):
+        """Batched sampling calls run their chains in n staggered groups, each on a stream of
+        its own (1, the default: the caller's stream only; at most 4); results are
+        unchanged."""
+        abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_CHAIN_STREAMS, int(n)))
+
     def kernel_timing(self, enable, kernel="fine_pass"):
         """Bracket every launch of one kernel class with HIP events: "fine_pass" (level-0
         colour pass), "level1_block_pass" or "bottom"."""
@@ -318,6 +327,22 @@ class Hierarchy:
         ms = ctypes.c_double()
         abi.check(self.lib.smg_kernel_timing_read(self._h, ctypes.byref(cnt), ctypes.byref(ms)))
         return cnt.value, ms.value
+
+    def _out_code(self, out, n, fshape):
+        """The output dtype code of a caller's `out` ([n] + fshape, float64 or float32,
+        contiguous, on this device); the library writes exactly that many elements of that
+        type."""
+        if out.dtype not in (torch.float64, torch.float32) or not out.is_contiguous() \
+                or tuple(out.shape) != (n,) + tuple(fshape) or out.device != self.device:
+            raise ValueError("out must be a contiguous float64 or float32 %s tensor on %s"
+                             % ((n,) + tuple(fshape), self.device))
+        return abi.SMG_OUT_F32 if out.dtype == torch.float32 else abi.SMG_OUT_F64
+
+    def _check_moments(self, moments, fshape):
+        if moments.dtype != torch.float64 or tuple(moments.shape) != (2,) + tuple(fshape) \
+                or not moments.is_contiguous() or moments.device != self.device:
+            raise ValueError("moments must be a contiguous float64 %s tensor on %s"
+                             % ((2,) + tuple(fshape), self.device))
 
     def _check_field(self, t):
         if t.dtype != torch.float64 or tuple(t.shape) != self.shape or not t.is_contiguous() \

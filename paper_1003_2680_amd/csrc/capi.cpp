@@ -55,14 +55,23 @@ struct Run {
   bool has_b0;  // level-0 right-hand side present (solve, and the refined inner cycle)
   uint64_t seed;
   uint64_t cycle;  // with `chains`: cycles since each chain's first cycle
-  int nc;          // components processed: the first nc of the hierarchy's ncomp
+  int nc;          // components processed: c0 .. c0+nc-1 of the hierarchy's ncomp
   const ChainKey* chains;  // batched chains (device table) or null
   uint32_t cpc;            // components per chain
+  int c0;                  // first component (a multiple of cpc; 0 without chains)
 };
 
 Run make_run(Hierarchy& h, hipStream_t s, bool noise, bool has_b0, uint64_t seed,
              uint64_t cycle) {
-  return Run{&h, s, noise, has_b0, seed, cycle, h.desc.ncomp, nullptr, 1};
+  return Run{&h, s, noise, has_b0, seed, cycle, h.desc.ncomp, nullptr, 1, 0};
+}
+
+// The run's share of a component-major buffer with `per` elements per component (null stays
+// null).  Kernels index components from 0 on shifted pointers, so a run over components
+// c0 .. c0+nc-1 touches exactly the memory that a run over all of them gives to those.
+template <typename P>
+P* comp_at(P* base, int64_t per, const Run& r) {
+  return base ? base + (int64_t)r.c0 * per : nullptr;
 }
 
 NoiseArgs make_noise(const Run& r, int level, int slot, int colour, uint32_t kind) {
@@ -73,7 +82,9 @@ NoiseArgs make_noise(const Run& r, int level, int slot, int colour, uint32_t kin
   na.c2 = (uint32_t)r.cycle;
   na.c3 = (uint32_t)(r.cycle >> 32);
   na.sqkT = std::sqrt(r.h->desc.kT);
-  na.chains = r.chains;
+  // the kernels number the run's components from 0: start the chain table at the run's first
+  // chain, so that component c of the run draws as component c0 + c of the hierarchy
+  na.chains = r.chains ? r.chains + r.c0 / (int)r.cpc : nullptr;
   na.comps_per_chain = r.cpc;
   na.cpc_magic = chain_divisor_magic((uint32_t)r.cpc);
   na.bm = box_muller_coef();
@@ -165,10 +176,11 @@ int sweep(Run& r, int l, int slot, bool post) {
   Level& v = h.lv[l];
   const int nc = h.desc.ncomp;
   if (v.kind == KIND_POINT) {
-    T* xr = Fld<T>::x(v);
-    T* xb = xr + half_field(h);
-    const T* br = Fld<T>::b(v);
-    const T* bb = br + half_field(h);
+    const int64_t hn = v.n / 2;
+    T* xr = comp_at(Fld<T>::x(v), hn, r);
+    T* xb = comp_at(Fld<T>::x(v) + half_field(h), hn, r);
+    const T* br = comp_at(Fld<T>::b(v), hn, r);
+    const T* bb = comp_at(Fld<T>::b(v) + half_field(h), hn, r);
     TimedScope ts(h, r.s, SMG_TIMED_FINE_PASS, 2);
     SMG_TRY(ts.rc);
     for (int t = 0; t < 2; ++t) {
@@ -180,20 +192,22 @@ int sweep(Run& r, int l, int slot, bool post) {
     SMG_TRY(ts.close());
   } else {
     const T* noise = (const T*)v.noise_d;
-    const T* zn = r.noise ? noise + (size_t)slot * nc * v.n : nullptr;
+    const T* zn = r.noise ? noise + ((size_t)slot * nc + r.c0) * v.n : nullptr;
+    T* x = comp_at(Fld<T>::x(v), v.n, r);
+    const T* b = comp_at(Fld<T>::b(v), v.n, r);
     const bool pairs = h.block_pairs && pair_level(v.nx, v.ny);
     TimedScope ts(h, r.s, l == 1 ? SMG_TIMED_LEVEL1_BLOCK_PASS : -1, pairs ? 4 : 8);
     SMG_TRY(ts.rc);
     for (int t = 0; t < 8; t += pairs ? 2 : 1) {
       const int colour = post ? 7 - t : t;  // with pairs: colour, then colour ^ 1
       if (pairs) {
-        SMG_HIP(launch_block_pair<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
-                                     (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz,
-                                     r.nc, colour, zn, r.s));
+        SMG_HIP(launch_block_pair<T>(x, b, (const T*)v.s1d_d, (const T*)v.zt_d,
+                                     (const T*)v.bfac_d, v.nx, v.ny, v.nz, r.nc, colour, zn,
+                                     r.s));
       } else {
-        SMG_HIP(launch_block_pass<T>(Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
-                                     (const T*)v.zt_d, (const T*)v.bfac_d, v.nx, v.ny, v.nz,
-                                     r.nc, colour, zn, h.block_tile, r.s));
+        SMG_HIP(launch_block_pass<T>(x, b, (const T*)v.s1d_d, (const T*)v.zt_d,
+                                     (const T*)v.bfac_d, v.nx, v.ny, v.nz, r.nc, colour, zn,
+                                     h.block_tile, r.s));
       }
     }
     SMG_TRY(ts.close());
@@ -207,23 +221,26 @@ int restrict_residual(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   const int nc = r.nc;
-  T* rr = Fld<T>::r(v);
+  T* rr = comp_at(Fld<T>::r(v), v.n, r);
   Level& c = h.lv[l + 1];
   const bool bottom_next = (l + 1 == h.bottom) && h.use_bottom;
+  T* bc = comp_at(Fld<T>::b(c), c.n, r);
+  T* xc = bottom_next ? nullptr : comp_at(Fld<T>::x(c), c.n, r);
   if (v.kind == KIND_POINT) {
     // level 0: fused, the fine residual never goes to memory
+    const int64_t hn = v.n / 2;
     T* xr = Fld<T>::x(v);
     T* br = Fld<T>::b(v);
-    SMG_HIP(launch_restrict_residual0<T>(Fld<T>::b(c), bottom_next ? nullptr : Fld<T>::x(c), xr,
-                                         xr + half_field(h), r.has_b0 ? br : nullptr,
-                                         r.has_b0 ? br + half_field(h) : nullptr, v.nx, v.ny,
-                                         v.nz, nc, h.desc.h, r.s));
+    SMG_HIP(launch_restrict_residual0<T>(
+        bc, xc, comp_at(xr, hn, r), comp_at(xr + half_field(h), hn, r),
+        r.has_b0 ? comp_at(br, hn, r) : nullptr,
+        r.has_b0 ? comp_at(br + half_field(h), hn, r) : nullptr, v.nx, v.ny, v.nz, nc, h.desc.h,
+        r.s));
     return SMG_OK;
   }
-  SMG_HIP(launch_residual_gal<T>(rr, Fld<T>::x(v), Fld<T>::b(v), (const T*)v.s1d_d,
-                                 (const T*)v.zt_d, v.nx, v.ny, v.nz, nc, r.s));
-  SMG_HIP(launch_restrict<T>(Fld<T>::b(c), bottom_next ? nullptr : Fld<T>::x(c), rr, v.nx, v.ny,
-                             v.nz, nc, r.s));
+  SMG_HIP(launch_residual_gal<T>(rr, comp_at(Fld<T>::x(v), v.n, r), comp_at(Fld<T>::b(v), v.n, r),
+                                 (const T*)v.s1d_d, (const T*)v.zt_d, v.nx, v.ny, v.nz, nc, r.s));
+  SMG_HIP(launch_restrict<T>(bc, xc, rr, v.nx, v.ny, v.nz, nc, r.s));
   return SMG_OK;
 }
 
@@ -232,16 +249,18 @@ int prolong_add(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   const int nc = r.nc;
-  const T* e = Fld<T>::x(h.lv[l + 1]);
+  const T* e = comp_at(Fld<T>::x(h.lv[l + 1]), h.lv[l + 1].n, r);
   if (v.kind == KIND_POINT) {
     T* xr = Fld<T>::x(v);
+    const int64_t hn = v.n / 2;
     // The first post-sweep pass draws every colour-1 site afresh from its colour-0 neighbours
     // (a heat-bath update never reads the value it replaces), so with post-sweeps only the
     // colour-0 sites need the correction.
     const int colours = h.prm.nu2 > 0 ? 1 : 3;
-    SMG_HIP(launch_prolong0<T>(xr, xr + half_field(h), e, v.nx, v.ny, v.nz, nc, colours, r.s));
+    SMG_HIP(launch_prolong0<T>(comp_at(xr, hn, r), comp_at(xr + half_field(h), hn, r), e, v.nx,
+                               v.ny, v.nz, nc, colours, r.s));
   } else {
-    SMG_HIP(launch_prolong<T>(Fld<T>::x(v), e, v.nx, v.ny, v.nz, nc, r.s));
+    SMG_HIP(launch_prolong<T>(comp_at(Fld<T>::x(v), v.n, r), e, v.nx, v.ny, v.nz, nc, r.s));
   }
   return SMG_OK;
 }
@@ -251,8 +270,8 @@ int coarsest_step(Run& r, int l) {
   Hierarchy& h = *r.h;
   Level& v = h.lv[l];
   NoiseArgs na = make_noise(r, l, 0, 0, KIND_COARSEST_NOISE);
-  SMG_HIP(launch_coarsest<T>(Fld<T>::x(v), Fld<T>::b(v), h.ainv_d, h.w_d, h.nc, r.nc,
-                             r.noise, na, r.s));
+  SMG_HIP(launch_coarsest<T>(comp_at(Fld<T>::x(v), v.n, r), comp_at(Fld<T>::b(v), v.n, r),
+                             h.ainv_d, h.w_d, h.nc, r.nc, r.noise, na, r.s));
   return SMG_OK;
 }
 
@@ -279,7 +298,7 @@ int gen_level_noise(Run& r, int only_level = -1, int only_slot = 0) {
     e.nz = v.nz;
     e.nslot = only_level >= 0 ? 1 : h.prm.nu1 + h.prm.nu2;
     e.slot0 = only_level >= 0 ? only_slot : 0;
-    e.out = v.noise_d;
+    e.out = comp_at((T*)v.noise_d, v.n, r);
     e.bfac = v.bfac_d;
     e.lg_bx = log2_exact(v.nx / 2);
     e.lg_bxy = log2_exact((v.nx / 2) * (v.ny / 2));
@@ -339,9 +358,10 @@ template <typename T>
 int bottom_cycle(Run& r) {
   Hierarchy& h = *r.h;
   NoiseArgs na = make_noise(r, 0, 0, 0, KIND_SMOOTH_NOISE);
+  na.chains = r.chains;  // this kernel numbers components absolutely (from c0)
   TimedScope ts(h, r.s, SMG_TIMED_BOTTOM, 1);
   SMG_TRY(ts.rc);
-  SMG_HIP(launch_bottom<T>(h.botargs_d, r.nc, h.bottom_lds, r.noise, na, r.s));
+  SMG_HIP(launch_bottom<T>(h.botargs_d, r.nc, r.c0, h.bottom_lds, r.noise, na, r.s));
   return ts.close();
 }
 
@@ -357,7 +377,7 @@ int vcycle(Run& r, int l) {
     SMG_TRY(restrict_residual<T>(r, l));
     Level& c = h.lv[l + 1];
     if (l + 1 == h.bottom && !h.use_bottom)
-      SMG_HIP(launch_zero<T>(Fld<T>::x(c), (int64_t)r.nc * c.n, r.s));
+      SMG_HIP(launch_zero<T>(comp_at(Fld<T>::x(c), c.n, r), (int64_t)r.nc * c.n, r.s));
     SMG_TRY(vcycle<T>(r, l + 1));
     SMG_TRY(prolong_add<T>(r, l));
   }
@@ -428,22 +448,26 @@ int cycle_phases(Run& r, int phases, bool residual_ready = false) {
     return SMG_OK;
   }
   // the processed components of both colour arrays
-  const int64_t act = (int64_t)r.nc * (v0.n / 2);
+  const int64_t hn = v0.n / 2;
+  const int64_t act = (int64_t)r.nc * hn;
   const size_t half = half_field(h);
+  float* xf = comp_at(v0.xf, hn, r);
+  double* x = comp_at(v0.x, hn, r);
   if (phases & PH_IN) {
     if (r.noise) SMG_TRY(gen_level_noise<float>(r));
     if (!residual_ready)
-      SMG_HIP(launch_refine_residual(v0.bf, v0.x, r.has_b0 ? v0.b : nullptr, v0.nx, v0.ny,
+      SMG_HIP(launch_refine_residual(comp_at(v0.bf, hn, r), x,
+                                     r.has_b0 ? comp_at(v0.b, hn, r) : nullptr, v0.nx, v0.ny,
                                      v0.nz, r.nc, h.desc.ncomp, h.desc.h, nullptr, nullptr, r.s));
-    SMG_HIP(launch_zero<float>(v0.xf, act, r.s));
-    SMG_HIP(launch_zero<float>(v0.xf + half, act, r.s));
+    SMG_HIP(launch_zero<float>(xf, act, r.s));
+    SMG_HIP(launch_zero<float>(xf + half, act, r.s));
   }
   if (phases & PH_DOWN) SMG_TRY(split ? vdown<float>(ri) : vcycle<float>(ri, 0));
   if (split && (phases & PH_BOTTOM)) SMG_TRY(bottom_cycle<float>(ri));
   if (split && (phases & PH_UP)) SMG_TRY(vup<float>(ri));
   if (phases & PH_OUT) {
-    SMG_HIP(launch_refine_update(v0.x, v0.xf, act, r.s));
-    SMG_HIP(launch_refine_update(v0.x + half, v0.xf + half, act, r.s));
+    SMG_HIP(launch_refine_update(x, xf, act, r.s));
+    SMG_HIP(launch_refine_update(x + half, xf + half, act, r.s));
   }
   return SMG_OK;
 }
@@ -502,10 +526,15 @@ int block_pass_lockstep(const std::vector<Run>& legs, int l, int t, bool post, i
 // of their legs share one launch (level-0 point passes and Galerkin block passes alike); the
 // transfers stay per run.  The runs
 // touch disjoint memory and each keeps the order of its own vdown / vup, so each computes
-// exactly what vdown / vup computes.
+// exactly what vdown / vup computes.  Each run covers its hierarchy from component 0.
 template <typename T>
 int legs_lockstep(const std::vector<Run>& legs, bool down) {
   if (legs.empty()) return SMG_OK;
+  for (const Run& r : legs)
+    if (r.c0 != 0) {
+      set_error("lockstep legs take runs from component 0");
+      return SMG_EINVAL;
+    }
   hipStream_t s = legs[0].s;
   int maxb = 0, maxnu = 0;
   for (const Run& r : legs) {
@@ -804,16 +833,17 @@ int load_modes(Hierarchy& h, const int32_t* modes, int k, hipStream_t s) {
 // Emission of components c0 .. c0+nc-1 of the level-0 state with optional statistics (one
 // fused pass; obs, m1, m2 and out are laid out over those nc components).
 int emit(Hierarchy& h, void* out, int out_f32, double* obs, double* m1, double* m2, int k,
-         int nc, hipStream_t s) {
+         int nc, int c0, hipStream_t s) {
   Level& v0 = h.lv[0];
   if (!obs && !m1) {
-    if (out) SMG_TRY(export_level0(h, out, out_f32, v0.x, s, nc));
+    if (out) SMG_TRY(export_level0(h, out, out_f32, v0.x, s, nc, c0));
     return SMG_OK;
   }
   StatsArgs a{};
   const bool split = v0.kind == KIND_POINT;
-  a.xr = v0.x;
-  a.xb = split ? v0.x + half_field(h) : nullptr;
+  const int64_t per = split ? v0.n / 2 : v0.n;
+  a.xr = v0.x + (int64_t)c0 * per;
+  a.xb = split ? v0.x + half_field(h) + (int64_t)c0 * per : nullptr;
   a.nx = v0.nx;
   a.ny = v0.ny;
   a.nz = v0.nz;
@@ -827,7 +857,9 @@ int emit(Hierarchy& h, void* out, int out_f32, double* obs, double* m1, double* 
   a.out_f32 = out_f32;
   a.m1 = m1;
   a.m2 = m2;
-  a.part = (double*)(h.ws + h.off_spart);
+  // partial sums: [ncomp][stats_nblk][kMaxModes + 1] are allotted, so each component range has
+  // a region of its own
+  a.part = (double*)(h.ws + h.off_spart) + (size_t)c0 * h.stats_nblk * (kMaxModes + 1);
   SMG_HIP(launch_stats(a, nc, obs, 0.5 / (h.desc.h * h.desc.h), s));
   return SMG_OK;
 }
@@ -947,18 +979,24 @@ struct SampleJob {
 
   void set_cycle(int64_t k) { r.cycle = bt.nchains > 0 ? (uint64_t)k : first_cycle + (uint64_t)k; }
 
-  // emission after cycle k, when it is due
-  int emit_after(int64_t k) {
+  // emission after cycle k, when it is due, of the components of run g (the whole job, or one
+  // of its stream groups)
+  int emit_after(int64_t k, const Run& g) {
     Hierarchy& h = hh->h;
     const int64_t after = k + 1 - h.prm.burn_in;
     if (after <= 0 || after % h.prm.stride != 0) return SMG_OK;
     const int64_t idx = after / h.prm.stride - 1;
     const size_t out_elem = out_dtype == SMG_OUT_F32 ? sizeof(float) : sizeof(double);
     const size_t obs_stride = (size_t)nc * (n_modes + 1);
-    return emit(h, out ? (char*)out + (size_t)idx * field * out_elem : nullptr,
-                out_dtype == SMG_OUT_F32, obs ? obs + (size_t)idx * obs_stride : nullptr, m1,
-                m2, n_modes, nc, r.s);
+    const size_t n0 = (size_t)h.lv[0].n;
+    const size_t c0 = (size_t)g.c0;
+    return emit(h, out ? (char*)out + ((size_t)idx * field + c0 * n0) * out_elem : nullptr,
+                out_dtype == SMG_OUT_F32,
+                obs ? obs + (size_t)idx * obs_stride + c0 * (n_modes + 1) : nullptr,
+                m1 ? m1 + c0 * n0 : nullptr, m2 ? m2 + c0 * n0 : nullptr, n_modes, g.nc, g.c0,
+                g.s);
   }
+  int emit_after(int64_t k) { return emit_after(k, r); }
 
   int finish() {
     Hierarchy& h = hh->h;
@@ -970,6 +1008,30 @@ struct SampleJob {
   }
 };
 
+// Streams and events of ng chain groups: ng - 1 side streams (default priority) with their
+// join events, a fork event and ng - 1 stagger events, made on the current device (again when
+// the device changed).
+int ensure_side_streams(Hierarchy& h, int ng) {
+  int dev = -1;
+  SMG_HIP(hipGetDevice(&dev));
+  if (dev != h.side_device) release_side_streams(h);
+  if (!h.ev_fork) {
+    SMG_HIP(hipEventCreateWithFlags(&h.ev_fork, hipEventDisableTiming));
+    h.side_device = dev;
+  }
+  while ((int)h.side.size() < ng - 1) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    SMG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    h.side.push_back(st);
+    SMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    h.ev_join.push_back(ev);
+    SMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    h.ev_mid.push_back(ev);
+  }
+  return SMG_OK;
+}
+
 int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
                 const uint64_t* first_cycles, int64_t n, uint64_t seed, uint64_t first_cycle,
                 void* state, void* out, int32_t out_dtype, const int32_t* modes,
@@ -977,11 +1039,61 @@ int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
   SampleJob j;
   SMG_TRY(j.begin(hh, bt, seeds, first_cycles, n, seed, first_cycle, state, out, out_dtype,
                   modes, n_modes, obs, moments, (hipStream_t)stream));
-  for (int64_t k = 0; k < j.total; ++k) {
-    j.set_cycle(k);
-    SMG_TRY(full_cycle(j.r));
-    SMG_TRY(j.emit_after(k));
+  Hierarchy& h = hh->h;
+  const int ng = h.timing ? 1 : std::min(h.chain_streams, bt.nchains);
+  if (ng < 2) {
+    for (int64_t k = 0; k < j.total; ++k) {
+      j.set_cycle(k);
+      SMG_TRY(full_cycle(j.r));
+      SMG_TRY(j.emit_after(k));
+    }
+    return j.finish();
   }
+  // Chain groups on streams of their own: group g takes chains [g nchains / ng, (g+1) nchains /
+  // ng); group 0 runs on the caller's stream, the others on the hierarchy's side streams,
+  // which wait for the caller's stream first and which it waits for at the end.  The groups
+  // touch disjoint components (and regions of every shared buffer), and a component's work is
+  // the same whatever the group, so the results are those of one stream.
+  SMG_TRY(ensure_side_streams(h, ng));
+  std::vector<Run> g(ng, j.r);
+  for (int i = 0; i < ng; ++i) {
+    const int ch0 = i * bt.nchains / ng, ch1 = (i + 1) * bt.nchains / ng;
+    g[i].c0 = ch0 * bt.cpc;
+    g[i].nc = (ch1 - ch0) * bt.cpc;
+    if (i > 0) g[i].s = h.side[i - 1];
+  }
+  SMG_HIP(hipEventRecord(h.ev_fork, j.r.s));
+  for (int i = 1; i < ng; ++i) SMG_HIP(hipStreamWaitEvent(g[i].s, h.ev_fork, 0));
+  // Staggered: group i starts cycle k once group i-1 has finished the down-leg of cycle k, so
+  // that its down-leg runs beside the other group's bottom instead of all groups reaching their
+  // bottoms at once (identical groups issued together otherwise stay in phase).
+  int rc = SMG_OK;
+  for (int64_t k = 0; k < j.total && rc == SMG_OK; ++k)
+    for (int i = 0; i < ng && rc == SMG_OK; ++i) {
+      g[i].cycle = (uint64_t)k;
+      if (i > 0 && hipStreamWaitEvent(g[i].s, h.ev_mid[i - 1], 0) != hipSuccess) {
+        set_error("hipStreamWaitEvent failed");
+        rc = SMG_EHIP;
+        break;
+      }
+      rc = cycle_phases(g[i], PH_PRE);
+      if (rc == SMG_OK && i + 1 < ng && hipEventRecord(h.ev_mid[i], g[i].s) != hipSuccess) {
+        set_error("hipEventRecord failed");
+        rc = SMG_EHIP;
+      }
+      if (rc == SMG_OK) rc = cycle_phases(g[i], PH_BOTTOM | PH_POST);
+      if (rc == SMG_OK) rc = j.emit_after(k, g[i]);
+    }
+  // join even after an error, so that nothing the side streams hold outlives the call's stream
+  for (int i = 1; i < ng; ++i) {
+    const hipError_t e1 = hipEventRecord(h.ev_join[i - 1], g[i].s);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(j.r.s, h.ev_join[i - 1], 0) : e1;
+    if (e2 != hipSuccess && rc == SMG_OK) {
+      set_error(std::string("joining a chain-group stream: ") + hipGetErrorString(e2));
+      rc = SMG_EHIP;
+    }
+  }
+  SMG_TRY(rc);
   return j.finish();
 }
 
@@ -1589,6 +1701,7 @@ int smg_solve(smg_hierarchy* hh, const void* f, void* u, double rtol, int32_t ma
 void smg_destroy_hierarchy(smg_hierarchy* hh) {
   if (!hh) return;
   for (hipEvent_t e : hh->h.ev_pool) (void)hipEventDestroy(e);
+  release_side_streams(hh->h);
   delete hh;
 }
 
@@ -1750,6 +1863,10 @@ int smg_set_option(smg_hierarchy* hh, int32_t option, int64_t value) {
   }
   if (option == SMG_OPT_BLOCK_PAIRS && (value == 0 || value == 1)) {
     hh->h.block_pairs = value != 0;
+    return SMG_OK;
+  }
+  if (option == SMG_OPT_CHAIN_STREAMS && value >= 1 && value <= kMaxChainStreams) {
+    hh->h.chain_streams = (int)value;
     return SMG_OK;
   }
   if (option == SMG_OPT_BLOCK_TILE && value >= SMG_TILE_AUTO && value <= SMG_TILE_8X4) {

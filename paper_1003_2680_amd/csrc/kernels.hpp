@@ -199,10 +199,11 @@ hipError_t launch_block_pair_multi(const BlockPassItem<T>* items, int n, int c_f
                                    bool noise, hipStream_t s);
 template <typename T>
 hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStream_t s);
-// `a` points to a BotArgs in device memory
+// `a` points to a BotArgs in device memory; the launch runs components c0 .. c0+ncomp-1 (one
+// work-group each; the noise is keyed by those absolute component numbers)
 template <typename T>
-hipError_t launch_bottom(const BotArgs* a, int ncomp, size_t lds, bool noise, const NoiseArgs& na,
-                         hipStream_t s);
+hipError_t launch_bottom(const BotArgs* a, int ncomp, int c0, size_t lds, bool noise,
+                         const NoiseArgs& na, hipStream_t s);
 // The bottoms of several hierarchies in one launch (kernel arguments only): item i brings its
 // device BotArgs and its noise keys; work-group w runs component wg[w] >> 16 of item
 // wg[w] & 0xffff.  lds: the largest bottom LDS size of the items.

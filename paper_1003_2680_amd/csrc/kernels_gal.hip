@@ -721,8 +721,9 @@ __device__ __forceinline__ void bottom_body(const BotArgs& a, const uint32_t com
 
 // One hierarchy, one work-group per component.
 template <typename T, bool NOISE>
-__global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ ap, NoiseArgs na) {
-  bottom_body<T, NOISE>(*ap, blockIdx.x, na);
+__global__ __launch_bounds__(BOT_TPB) void k_bottom(const BotArgs* __restrict__ ap, int c0,
+                                                    NoiseArgs na) {
+  bottom_body<T, NOISE>(*ap, c0 + (int)blockIdx.x, na);
 }
 
 // Several hierarchies (of any sizes) in one launch: work-group w runs component wg >> 16 of
@@ -1011,8 +1012,8 @@ hipError_t launch_level_noise(const NoiseGenArgs& a, const NoiseArgs& na, hipStr
 }
 
 template <typename T>
-hipError_t launch_bottom(const BotArgs* a, int ncomp, size_t lds, bool noise, const NoiseArgs& na,
-                         hipStream_t s) {
+hipError_t launch_bottom(const BotArgs* a, int ncomp, int c0, size_t lds, bool noise,
+                         const NoiseArgs& na, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_bottom<T, true>,
@@ -1023,8 +1024,8 @@ hipError_t launch_bottom(const BotArgs* a, int ncomp, size_t lds, bool noise, co
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  if (noise) k_bottom<T, true><<<ncomp, BOT_TPB, lds, s>>>(a, na);
-  else k_bottom<T, false><<<ncomp, BOT_TPB, lds, s>>>(a, na);
+  if (noise) k_bottom<T, true><<<ncomp, BOT_TPB, lds, s>>>(a, c0, na);
+  else k_bottom<T, false><<<ncomp, BOT_TPB, lds, s>>>(a, c0, na);
   return hipGetLastError();
 }
 
@@ -1064,8 +1065,8 @@ hipError_t launch_bottom_multi(const BotMultiArgs& m, int nwg, size_t lds, bool 
   template hipError_t launch_coarsest<T>(T*, const T*, const double*, const double*, int, int,  \
                                          bool, const NoiseArgs&, hipStream_t);                  \
   template hipError_t launch_level_noise<T>(const NoiseGenArgs&, const NoiseArgs&, hipStream_t); \
-  template hipError_t launch_bottom<T>(const BotArgs*, int, size_t, bool, const NoiseArgs&,     \
-                                       hipStream_t);                                             \
+  template hipError_t launch_bottom<T>(const BotArgs*, int, int, size_t, bool,                 \
+                                       const NoiseArgs&, hipStream_t);                           \
   template hipError_t launch_bottom_multi<T>(const BotMultiArgs&, int, size_t, bool, hipStream_t);
 SMG_INST(double)
 SMG_INST(float)

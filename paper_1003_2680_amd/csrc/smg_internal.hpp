@@ -14,6 +14,7 @@ namespace smg {
 
 constexpr int STENCIL = 125;  // 5x5x5 offsets of a Galerkin operator row
 constexpr int kMaxChains = 255;  // batched chains per hierarchy (at most one per component)
+constexpr int kMaxChainStreams = 4;  // stream groups of a batched sampling call
 
 struct Level {
   int nx = 0, ny = 0, nz = 0;
@@ -59,6 +60,13 @@ struct Hierarchy {
   bool use_bottom = true;        // false: run those levels with one launch per pass instead
   int block_tile = SMG_TILE_AUTO;  // tile shape of the block-pass launches
   bool block_pairs = true;         // two block colours per launch where the level allows
+  // batched sampling: chain groups on streams of their own (1: the caller's stream only)
+  int chain_streams = 1;
+  std::vector<hipStream_t> side;     // side streams of groups 1 .. (made on first use)
+  std::vector<hipEvent_t> ev_join;   // one per side stream
+  std::vector<hipEvent_t> ev_mid;    // group i at the end of its down-leg (i < groups - 1)
+  hipEvent_t ev_fork = nullptr;
+  int side_device = -1;
   size_t off_botargs = 0;
   BotArgs* botargs_d = nullptr;  // device copy of the bottom kernel's level descriptors
   int nc = 0;                    // unknowns of the coarsest level when it is drawn exactly
@@ -110,6 +118,19 @@ std::vector<double> ring_matrix(const double s[5], int n);
 
 // error helpers (capi.cpp)
 void set_error(const std::string& msg);
+
+// Destroys the hierarchy's side streams and their events.
+inline void release_side_streams(Hierarchy& h) {
+  for (hipStream_t st : h.side) (void)hipStreamDestroy(st);
+  for (hipEvent_t e : h.ev_join) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h.ev_mid) (void)hipEventDestroy(e);
+  if (h.ev_fork) (void)hipEventDestroy(h.ev_fork);
+  h.side.clear();
+  h.ev_join.clear();
+  h.ev_mid.clear();
+  h.ev_fork = nullptr;
+  h.side_device = -1;
+}
 
 // capi.cpp: point (and with `upload` fill) the hierarchy's device fields and tables at ws;
 // the sampling path of smg_sample_field

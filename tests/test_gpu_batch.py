@@ -121,6 +121,30 @@ def test_batch_errors():
         H.sample_batch(1, nchains=4, comps_per_chain=1)   # table of another shape
     assert e.value.code == SMG_ESTATE
     assert SMG_EINVAL == -1
+    # caller outputs are checked before the library writes into them: their dtype decides the
+    # element type written, and a wrong shape, dtype or layout is refused
+    fshape = (4, 8, 16, 16)
+    for bad in (torch.empty((2,) + fshape, dtype=torch.float64, device="cuda"),
+                torch.empty((1, 2, 8, 16, 16), dtype=torch.float64, device="cuda"),
+                torch.empty((1,) + fshape, dtype=torch.float16, device="cuda"),
+                torch.empty((1, 4, 16, 16, 8), dtype=torch.float64, device="cuda")
+                .transpose(2, 4)):
+        with pytest.raises(ValueError):
+            H.sample_batch(1, nchains=2, comps_per_chain=2, out=bad)
+    with pytest.raises(ValueError):
+        H.sample_batch(1, nchains=2, comps_per_chain=2,
+                       moments=torch.zeros((2, 2, 8, 16, 16), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        H.sample(1, 3, out=torch.empty((1,) + fshape, dtype=torch.float32, device="cuda")[:, :2])
+    o32 = torch.empty((1,) + fshape, dtype=torch.float32, device="cuda")
+    H.sample_batch(1, nchains=2, comps_per_chain=2, out=o32)  # float32 written as float32
+    o64, _, _ = H.sample_batch(1, seeds=[1, 2], comps_per_chain=2)
+    st = torch.zeros(fshape, dtype=torch.float64, device="cuda")
+    H.sample_batch(0, seeds=[1, 2], comps_per_chain=2, state=st)
+    o32 = torch.empty((1,) + fshape, dtype=torch.float32, device="cuda")
+    H.sample_batch(1, nchains=2, comps_per_chain=2, state=st, out=o32)
+    torch.cuda.synchronize()
+    assert torch.equal(o32, o64.float())
 
 
 def test_batch_solve_one_level_cholesky_chains_finish_apart():
