@@ -322,19 +322,21 @@ enum {
   SMG_OPT_TIMED_KERNEL = 2,
   SMG_OPT_BLOCK_TILE = 3,
   SMG_OPT_BLOCK_PAIRS = 4,
-  SMG_OPT_CHAIN_STREAMS = 5
+  SMG_OPT_STREAM_GROUPS = 5
 };
-/* SMG_OPT_CHAIN_STREAMS (default 1, at most 4): smg_sample_batch with nchains >= 2 splits the
- * chains into this many contiguous groups (at most one group per chain) and runs each group's
- * cycles and emissions on a stream of its own: the first group on the caller's stream, the
- * others on side streams that the hierarchy creates on first use (on the current device, at
- * the default priority, destroyed with the hierarchy).  Group i starts each cycle once group
- * i - 1 has finished that cycle's down-leg, so the groups run staggered: the latency-bound
- * launches of one (the LDS-resident bottom, the small levels) overlap the bandwidth-bound ones
- * of another.  The side streams wait for the caller's stream at the start of the call and the
- * caller's stream waits for them before the call's last work (the state export), so the call
- * stays ordered on the caller's stream.  Every output is bit-identical to the one-stream run.
- * One stream while kernel timing is on; the other entry points ignore it. */
+/* SMG_OPT_STREAM_GROUPS (default 1, at most 4): smg_sample_field, smg_sample_stats and
+ * smg_sample_batch split the components they run into this many contiguous groups (at most
+ * one component per group; group i takes components [i nc / G, (i+1) nc / G)) and run each
+ * group's cycles and emissions on a stream of its own: the first group on the caller's stream,
+ * the others on side streams that the hierarchy creates on first use (on the current device,
+ * at the default priority, destroyed with the hierarchy).  Group i starts each cycle once
+ * group i - 1 has finished that cycle's down-leg, so the groups run staggered: the
+ * latency-bound launches of one (the LDS-resident bottom, the small levels) overlap the
+ * bandwidth-bound ones of another.  The side streams wait for the caller's stream at the start
+ * of the call and the caller's stream waits for them before the call's last work (the state
+ * export), so the call stays ordered on the caller's stream.  Every output is bit-identical to
+ * the one-stream run.  One stream while kernel timing is on, in smg_sample_field_static, and
+ * in the other entry points. */
 /* SMG_OPT_BLOCK_PAIRS (default 1): run the eight block colours of a sweep on a Galerkin level
  * as four launches of two colours each (colours c and c ^ 1 differ only in the parity of bx,
  * so one work-group owning whole x-rows draws both in turn from one staged tile); levels wider

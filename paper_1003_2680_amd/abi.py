@@ -26,7 +26,7 @@ SMG_TIMED_BOTTOM = 2
 SMG_MAX_MODES = 32
 SMG_OPT_BLOCK_TILE = 3
 SMG_OPT_BLOCK_PAIRS = 4
-SMG_OPT_CHAIN_STREAMS = 5
+SMG_OPT_STREAM_GROUPS = 5
 SMG_TILE_AUTO = 0
 SMG_TILE_4X4 = 1
 SMG_TILE_4X2 = 2

@@ -307,11 +307,10 @@ class Hierarchy:
         """Two block colours per launch on Galerkin levels (default) or one."""
         abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_BLOCK_PAIRS, int(bool(enable))))
 
-    def set_chain_streams(self, n):
-        """Batched sampling calls run their chains in n staggered groups, each on a stream of
-        its own (1, the default: the caller's stream only; at most 4); results are
-        unchanged."""
-        abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_CHAIN_STREAMS, int(n)))
+    def set_stream_groups(self, n):
+        """Sampling calls run their components in n staggered groups, each on a stream of its
+        own (1, the default: the caller's stream only; at most 4); results are unchanged."""
+        abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_STREAM_GROUPS, int(n)))
 
     def kernel_timing(self, enable, kernel="fine_pass"):
         """Bracket every launch of one kernel class with HIP events: "fine_pass" (level-0

@@ -58,7 +58,7 @@ struct Run {
   int nc;          // components processed: c0 .. c0+nc-1 of the hierarchy's ncomp
   const ChainKey* chains;  // batched chains (device table) or null
   uint32_t cpc;            // components per chain
-  int c0;                  // first component (a multiple of cpc; 0 without chains)
+  int c0;                  // first component
 };
 
 Run make_run(Hierarchy& h, hipStream_t s, bool noise, bool has_b0, uint64_t seed,
@@ -82,10 +82,11 @@ NoiseArgs make_noise(const Run& r, int level, int slot, int colour, uint32_t kin
   na.c2 = (uint32_t)r.cycle;
   na.c3 = (uint32_t)(r.cycle >> 32);
   na.sqkT = std::sqrt(r.h->desc.kT);
-  // the kernels number the run's components from 0: start the chain table at the run's first
-  // chain, so that component c of the run draws as component c0 + c of the hierarchy
-  na.chains = r.chains ? r.chains + r.c0 / (int)r.cpc : nullptr;
+  na.chains = r.chains;
   na.comps_per_chain = r.cpc;
+  // the kernels number the run's components from 0: component c of the run draws as
+  // component c0 + c of the hierarchy
+  na.comp0 = (uint32_t)r.c0;
   na.cpc_magic = chain_divisor_magic((uint32_t)r.cpc);
   na.bm = box_muller_coef();
   return na;
@@ -358,7 +359,7 @@ template <typename T>
 int bottom_cycle(Run& r) {
   Hierarchy& h = *r.h;
   NoiseArgs na = make_noise(r, 0, 0, 0, KIND_SMOOTH_NOISE);
-  na.chains = r.chains;  // this kernel numbers components absolutely (from c0)
+  na.comp0 = 0;  // this kernel numbers components absolutely (from c0)
   TimedScope ts(h, r.s, SMG_TIMED_BOTTOM, 1);
   SMG_TRY(ts.rc);
   SMG_HIP(launch_bottom<T>(h.botargs_d, r.nc, r.c0, h.bottom_lds, r.noise, na, r.s));
@@ -977,7 +978,11 @@ struct SampleJob {
     return SMG_OK;
   }
 
-  void set_cycle(int64_t k) { r.cycle = bt.nchains > 0 ? (uint64_t)k : first_cycle + (uint64_t)k; }
+  // the noise cycle of cycle k of the call (with chains: counted from each chain's first)
+  uint64_t cycle_of(int64_t k) const {
+    return bt.nchains > 0 ? (uint64_t)k : first_cycle + (uint64_t)k;
+  }
+  void set_cycle(int64_t k) { r.cycle = cycle_of(k); }
 
   // emission after cycle k, when it is due, of the components of run g (the whole job, or one
   // of its stream groups)
@@ -1032,15 +1037,16 @@ int ensure_side_streams(Hierarchy& h, int ng) {
   return SMG_OK;
 }
 
+// `groups`: the most stream groups the call may use (1: the caller's stream only).
 int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
                 const uint64_t* first_cycles, int64_t n, uint64_t seed, uint64_t first_cycle,
                 void* state, void* out, int32_t out_dtype, const int32_t* modes,
-                int32_t n_modes, void* obs, void* moments, void* stream) {
+                int32_t n_modes, void* obs, void* moments, void* stream, int groups) {
   SampleJob j;
   SMG_TRY(j.begin(hh, bt, seeds, first_cycles, n, seed, first_cycle, state, out, out_dtype,
                   modes, n_modes, obs, moments, (hipStream_t)stream));
   Hierarchy& h = hh->h;
-  const int ng = h.timing ? 1 : std::min(h.chain_streams, bt.nchains);
+  const int ng = h.timing ? 1 : std::min(groups, j.nc);
   if (ng < 2) {
     for (int64_t k = 0; k < j.total; ++k) {
       j.set_cycle(k);
@@ -1049,17 +1055,16 @@ int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
     }
     return j.finish();
   }
-  // Chain groups on streams of their own: group g takes chains [g nchains / ng, (g+1) nchains /
+  // Component groups on streams of their own: group i takes components [i nc / ng, (i+1) nc /
   // ng); group 0 runs on the caller's stream, the others on the hierarchy's side streams,
   // which wait for the caller's stream first and which it waits for at the end.  The groups
-  // touch disjoint components (and regions of every shared buffer), and a component's work is
-  // the same whatever the group, so the results are those of one stream.
+  // touch disjoint components (and regions of every shared buffer), and a component's work and
+  // noise are the same whatever the group, so the results are those of one stream.
   SMG_TRY(ensure_side_streams(h, ng));
   std::vector<Run> g(ng, j.r);
   for (int i = 0; i < ng; ++i) {
-    const int ch0 = i * bt.nchains / ng, ch1 = (i + 1) * bt.nchains / ng;
-    g[i].c0 = ch0 * bt.cpc;
-    g[i].nc = (ch1 - ch0) * bt.cpc;
+    g[i].c0 = i * j.nc / ng;
+    g[i].nc = (i + 1) * j.nc / ng - g[i].c0;
     if (i > 0) g[i].s = h.side[i - 1];
   }
   SMG_HIP(hipEventRecord(h.ev_fork, j.r.s));
@@ -1070,7 +1075,7 @@ int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
   int rc = SMG_OK;
   for (int64_t k = 0; k < j.total && rc == SMG_OK; ++k)
     for (int i = 0; i < ng && rc == SMG_OK; ++i) {
-      g[i].cycle = (uint64_t)k;
+      g[i].cycle = j.cycle_of(k);
       if (i > 0 && hipStreamWaitEvent(g[i].s, h.ev_mid[i - 1], 0) != hipSuccess) {
         set_error("hipStreamWaitEvent failed");
         rc = SMG_EHIP;
@@ -1390,13 +1395,13 @@ int bind_impl(Hierarchy& h, char* ws, bool upload, hipStream_t s) {
 }
 
 int sample_field_impl(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
-                      void* state, void* out, int32_t out_dtype, void* stream) {
+                      void* state, void* out, int32_t out_dtype, void* stream, int groups) {
   if (n > 0 && !out) {
     set_error("out is null");
     return SMG_EINVAL;
   }
   return sample_impl(hh, Batch{}, nullptr, nullptr, n, seed, first_cycle, state, out, out_dtype,
-                     nullptr, 0, nullptr, nullptr, stream);
+                     nullptr, 0, nullptr, nullptr, stream, groups);
 }
 
 }  // namespace smg
@@ -1465,14 +1470,23 @@ int smg_bind_workspace(smg_hierarchy* hh, void* dev_ptr, size_t bytes, void* str
 
 int smg_sample_field(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
                      void* state, void* out, int32_t out_dtype, void* stream) {
-  return sample_field_impl(hh, n, seed, first_cycle, state, out, out_dtype, stream);
+  if (!hh) {
+    set_error("null hierarchy");
+    return SMG_EINVAL;
+  }
+  return sample_field_impl(hh, n, seed, first_cycle, state, out, out_dtype, stream,
+                           hh->h.stream_groups);
 }
 
 int smg_sample_stats(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
                      void* state, void* out, int32_t out_dtype, const int32_t* modes,
                      int32_t n_modes, void* obs, void* moments, void* stream) {
+  if (!hh) {
+    set_error("null hierarchy");
+    return SMG_EINVAL;
+  }
   return sample_impl(hh, Batch{}, nullptr, nullptr, n, seed, first_cycle, state, out, out_dtype,
-                     modes, n_modes, obs, moments, stream);
+                     modes, n_modes, obs, moments, stream, hh->h.stream_groups);
 }
 
 int smg_sample_batch(smg_hierarchy* hh, int32_t nchains, int32_t comps_per_chain,
@@ -1483,11 +1497,15 @@ int smg_sample_batch(smg_hierarchy* hh, int32_t nchains, int32_t comps_per_chain
     set_error("nchains must be >= 1");
     return SMG_EINVAL;
   }
+  if (!hh) {
+    set_error("null hierarchy");
+    return SMG_EINVAL;
+  }
   Batch bt;
   bt.nchains = nchains;
   bt.cpc = comps_per_chain;
   return sample_impl(hh, bt, seeds, first_cycles, n, 0, 0, state, out, out_dtype, modes, n_modes,
-                     obs, moments, stream);
+                     obs, moments, stream, hh->h.stream_groups);
 }
 
 int smg_solve_batch(smg_hierarchy* hh, int32_t nchains, int32_t comps_per_chain, const void* f,
@@ -1865,8 +1883,8 @@ int smg_set_option(smg_hierarchy* hh, int32_t option, int64_t value) {
     hh->h.block_pairs = value != 0;
     return SMG_OK;
   }
-  if (option == SMG_OPT_CHAIN_STREAMS && value >= 1 && value <= kMaxChainStreams) {
-    hh->h.chain_streams = (int)value;
+  if (option == SMG_OPT_STREAM_GROUPS && value >= 1 && value <= kMaxStreamGroups) {
+    hh->h.stream_groups = (int)value;
     return SMG_OK;
   }
   if (option == SMG_OPT_BLOCK_TILE && value >= SMG_TILE_AUTO && value <= SMG_TILE_8X4) {

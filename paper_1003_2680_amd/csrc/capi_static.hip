@@ -84,7 +84,8 @@ extern "C" int smg_sample_field_static(smg_hierarchy* hh, int64_t n, uint64_t se
     return rc;
   }
   d.owner = h.uid;
-  rc = sample_field_impl(hh, n, seed, first_cycle, state, out, out_dtype, stream);
+  // one stream: side streams and events are not made here
+  rc = sample_field_impl(hh, n, seed, first_cycle, state, out, out_dtype, stream, 1);
   if (prev_ws) {
     const int rc2 = bind_impl(h, prev_ws, false, s);
     h.device = prev_dev;

@@ -61,6 +61,9 @@ struct NoiseArgs {
   double sqkT;       // sqrt(kT)
   const ChainKey* chains;    // null: one chain keyed by (k0, k1)
   uint32_t comps_per_chain;
+  // added to the component index of every draw: a launch over components c0 .. c0+n-1 of a
+  // hierarchy numbers them from 0 on shifted pointers and passes c0 here
+  uint32_t comp0 = 0;
   // floor(2^32 / comps_per_chain) + 1 (0 when comps_per_chain is 1): comp / comps_per_chain is
   // the high word of comp * cpc_magic for comp and comps_per_chain below 2^16
   uint32_t cpc_magic;
@@ -93,7 +96,7 @@ inline __host__ __device__ BoxMullerCoef box_muller_coef() {
 __device__ __forceinline__ void noise_key(const NoiseArgs& na, uint32_t sid, uint32_t comp,
                                           uint32_t& k0, uint32_t& k1, uint32_t& w1, uint32_t& w2,
                                           uint32_t& w3) {
-  comp = __builtin_amdgcn_readfirstlane(comp);
+  comp = __builtin_amdgcn_readfirstlane(comp) + na.comp0;
   if (na.chains) {
     const uint32_t ch = na.cpc_magic ? __umulhi(comp, na.cpc_magic) : comp;
     // the chain table is read-only while kernels run: scalar loads through the constant space

@@ -14,7 +14,7 @@ namespace smg {
 
 constexpr int STENCIL = 125;  // 5x5x5 offsets of a Galerkin operator row
 constexpr int kMaxChains = 255;  // batched chains per hierarchy (at most one per component)
-constexpr int kMaxChainStreams = 4;  // stream groups of a batched sampling call
+constexpr int kMaxStreamGroups = 4;  // stream groups of a sampling call
 
 struct Level {
   int nx = 0, ny = 0, nz = 0;
@@ -60,8 +60,8 @@ struct Hierarchy {
   bool use_bottom = true;        // false: run those levels with one launch per pass instead
   int block_tile = SMG_TILE_AUTO;  // tile shape of the block-pass launches
   bool block_pairs = true;         // two block colours per launch where the level allows
-  // batched sampling: chain groups on streams of their own (1: the caller's stream only)
-  int chain_streams = 1;
+  // sampling calls: component groups on streams of their own (1: the caller's stream only)
+  int stream_groups = 1;
   std::vector<hipStream_t> side;     // side streams of groups 1 .. (made on first use)
   std::vector<hipEvent_t> ev_join;   // one per side stream
   std::vector<hipEvent_t> ev_mid;    // group i at the end of its down-leg (i < groups - 1)
@@ -133,10 +133,10 @@ inline void release_side_streams(Hierarchy& h) {
 }
 
 // capi.cpp: point (and with `upload` fill) the hierarchy's device fields and tables at ws;
-// the sampling path of smg_sample_field
+// the sampling path of smg_sample_field (with at most `groups` stream groups)
 int bind_impl(Hierarchy& h, char* ws, bool upload, hipStream_t s);
 int sample_field_impl(smg_hierarchy* hh, int64_t n, uint64_t seed, uint64_t first_cycle,
-                      void* state, void* out, int32_t out_dtype, void* stream);
+                      void* state, void* out, int32_t out_dtype, void* stream, int groups);
 
 }  // namespace smg
 
