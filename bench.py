@@ -511,7 +511,8 @@ def measure_batched(dev, n_instances=64, n_samples=100):
         return dt, cyc
 
     t0 = time.perf_counter()
-    R = BatchRunner(insts, precision="fp32_refined", tune=True, device=dev)
+    R = BatchRunner(insts, precision="fp32_refined", tune=True, device=dev,
+                    stream_groups=STREAM_GROUPS)
     tune_s = time.perf_counter() - t0
     configs = R.configs
     sample_s = timed_sample(R)
@@ -531,7 +532,8 @@ def measure_batched(dev, n_instances=64, n_samples=100):
     streams_s = timed_sample(Rs)
     del Rs
     torch.cuda.empty_cache()
-    R64 = BatchRunner(insts, precision="fp64", configs=configs, device=dev)
+    R64 = BatchRunner(insts, precision="fp64", configs=configs, device=dev,
+                      stream_groups=STREAM_GROUPS)
     fp64_s = timed_sample(R64)
     fp64_solve_s, fp64_solve_cyc = timed_solve(R64)
     del R64
@@ -572,7 +574,8 @@ def measure_batched(dev, n_instances=64, n_samples=100):
             "cells": cells, "groups": len(cfgs), "configs": cfgs,
             "tune_s": round(tune_s, 2),
             "fp32_refined": {
-                "engine": "smg_batch_run (one stream, merged bottom launches)",
+                "engine": "smg_batch_run (%d staggered stream groups, merged bottom launches "
+                          "within a group)" % STREAM_GROUPS,
                 "instance_samples_per_s": round(n_instances * n_samples / sample_s, 1),
                 "sample_s": round(sample_s, 4),
                 "graph_replay_cycles_s": round(graph_s, 4),
@@ -581,7 +584,8 @@ def measure_batched(dev, n_instances=64, n_samples=100):
                 "roofline": roof(sample_s, 106.0),
                 "roofline_graph": roof(graph_s, 106.0)},
             "fp64": {
-                "engine": "smg_batch_run (one stream, merged bottom launches)",
+                "engine": "smg_batch_run (%d staggered stream groups, merged bottom launches "
+                          "within a group)" % STREAM_GROUPS,
                 "instance_samples_per_s": round(n_instances * n_samples / fp64_s, 1),
                 "sample_s": round(fp64_s, 4),
                 "solve_all_s": round(fp64_solve_s, 4), "solve_cycles_max": fp64_solve_cyc,

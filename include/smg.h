@@ -247,8 +247,12 @@ int smg_sample_field_static(smg_hierarchy* h, int64_t n, uint64_t seed, uint64_t
  * of at most 4096 cells and the coarsest draw: Sec. "Stochastic Multigrid Methods", Alg. 3,
  * below the tiled levels) are run for all items in as few launches as possible (one per sweep
  * precision and noise setting, up to 16 hierarchies and 256 components each), instead of one
- * latency-bound launch per hierarchy.  Every item's result is bit for bit that of its own call
- * alone.  Without solve items the call is asynchronous (and can be captured in a graph); solve
+ * latency-bound launch per hierarchy.  With SMG_OPT_STREAM_GROUPS above 1 on any sampling
+ * item's hierarchy (the largest setting counts), the sampling cycles run in that many staggered
+ * groups as in smg_sample_batch, group g taking its share of every item's components, on the
+ * side streams of the first sampling item's hierarchy.  Every item's result is bit for bit that
+ * of its own call alone.  Without solve items the call is asynchronous (and can be captured in
+ * a graph); solve
  * items synchronise the stream once per cycle for all of them.  status receives each item's
  * return code; the function returns SMG_OK or the first failing item's code (SMG_EINVAL for a
  * repeated hierarchy or unknown op, before any work). */
@@ -327,16 +331,20 @@ enum {
 /* SMG_OPT_STREAM_GROUPS (default 1, at most 4): smg_sample_field, smg_sample_stats and
  * smg_sample_batch split the components they run into this many contiguous groups (at most
  * one component per group; group i takes components [i nc / G, (i+1) nc / G)) and run each
- * group's cycles and emissions on a stream of its own: the first group on the caller's stream,
- * the others on side streams that the hierarchy creates on first use (on the current device,
- * at the default priority, destroyed with the hierarchy).  Group i starts each cycle once
+ * group's cycles and emissions on a side stream of its own, which the hierarchy creates on
+ * first use (G streams together, so that the runtime spreads them over its hardware queues; on
+ * the current device, at the default priority, destroyed with the hierarchy); the caller's
+ * stream only forks and joins.  Group i starts each cycle once
  * group i - 1 has finished that cycle's down-leg, so the groups run staggered: the
  * latency-bound launches of one (the LDS-resident bottom, the small levels) overlap the
  * bandwidth-bound ones of another.  The side streams wait for the caller's stream at the start
  * of the call and the caller's stream waits for them before the call's last work (the state
  * export), so the call stays ordered on the caller's stream.  Every output is bit-identical to
- * the one-stream run.  One stream while kernel timing is on, in smg_sample_field_static, and
- * in the other entry points. */
+ * the one-stream run.  smg_batch_run groups its sampling items likewise (see there).  One
+ * stream while kernel timing is on, in smg_sample_field_static, and in the other entry
+ * points.  A grouped call can be captured in a graph (the side streams join the capture through
+ * the fork event), but its replay measured slower than that of a one-stream capture: set 1
+ * before capturing. */
 /* SMG_OPT_BLOCK_PAIRS (default 1): run the eight block colours of a sweep on a Galerkin level
  * as four launches of two colours each (colours c and c ^ 1 differ only in the parity of bx,
  * so one work-group owning whole x-rows draws both in turn from one staged tile); levels wider

@@ -48,10 +48,12 @@ class BatchRunner:
 
     configs: {dims: config} (keys levels, nu1, nu2 and optionally tile, bottom); missing
     grids are tuned with autotune.tune for their group size (tune=True) or get the automatic
-    depth with V(2,2)."""
+    depth with V(2,2).  stream_groups: the library engine's staggered stream groups for eager
+    calls (each a share of every grid's instances; 1 = the call's stream only); a captured graph
+    takes the one-stream form."""
 
     def __init__(self, instances, precision="fp32_refined", configs=None, tune=False,
-                 device=None, engine="library"):
+                 device=None, engine="library", stream_groups=1):
         dev = torch.device(device if device is not None else "cuda")
         if dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
@@ -76,6 +78,10 @@ class BatchRunner:
                 else:
                     configs[dims] = {"levels": 0, "nu1": 2, "nu2": 2}
         self.groups = [Group(d, m, configs[d], precision, self.device) for d, m in by_dims.items()]
+        self.stream_groups = stream_groups
+        if engine == "library":
+            for g in self.groups:
+                g.H.set_stream_groups(stream_groups)
         self.configs = configs
         self._started = False
 
@@ -145,11 +151,19 @@ class BatchRunner:
         if self.engine == "library":
             items = [{"H": g.H, "op": "sample", "nchains": g.n, "comps_per_chain": 1, "n": n,
                       "state": g.state, "out": None} for g in self.groups]
-            # captured on a side stream (the chain tables advance on the device per replay)
+            # captured on a side stream (the chain tables advance on the device per replay), in
+            # the one-stream form: a replayed fork / join of stream groups measured slower than
+            # the one-stream graph
             side = torch.cuda.Stream(device=self.device)
             graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph, stream=side):
-                self._check(batch_run(items))
+            for g in self.groups:
+                g.H.set_stream_groups(1)
+            try:
+                with torch.cuda.graph(graph, stream=side):
+                    self._check(batch_run(items))
+            finally:
+                for g in self.groups:
+                    g.H.set_stream_groups(self.stream_groups)
             self.graph = graph
             return
         for g in self.groups:

@@ -493,12 +493,12 @@ int block_pass_lockstep(const std::vector<Run>& legs, int l, int t, bool post, i
     if (t >= nsw) continue;
     const int slot = post ? h.prm.nu1 + t : t;
     BlockPassItem<T> it;
-    it.x = Fld<T>::x(v);
-    it.b = Fld<T>::b(v);
+    it.x = comp_at(Fld<T>::x(v), v.n, r);
+    it.b = comp_at(Fld<T>::b(v), v.n, r);
     it.s1d = (const T*)v.s1d_d;
     it.zt = (const T*)v.zt_d;
     it.bfac = (const T*)v.bfac_d;
-    it.zn = noise ? (const T*)v.noise_d + (size_t)slot * h.desc.ncomp * v.n : nullptr;
+    it.zn = noise ? (const T*)v.noise_d + ((size_t)slot * h.desc.ncomp + r.c0) * v.n : nullptr;
     it.nx = v.nx;
     it.ny = v.ny;
     it.nz = v.nz;
@@ -527,15 +527,10 @@ int block_pass_lockstep(const std::vector<Run>& legs, int l, int t, bool post, i
 // of their legs share one launch (level-0 point passes and Galerkin block passes alike); the
 // transfers stay per run.  The runs
 // touch disjoint memory and each keeps the order of its own vdown / vup, so each computes
-// exactly what vdown / vup computes.  Each run covers its hierarchy from component 0.
+// exactly what vdown / vup computes.
 template <typename T>
 int legs_lockstep(const std::vector<Run>& legs, bool down) {
   if (legs.empty()) return SMG_OK;
-  for (const Run& r : legs)
-    if (r.c0 != 0) {
-      set_error("lockstep legs take runs from component 0");
-      return SMG_EINVAL;
-    }
   hipStream_t s = legs[0].s;
   int maxb = 0, maxnu = 0;
   for (const Run& r : legs) {
@@ -557,10 +552,11 @@ int legs_lockstep(const std::vector<Run>& legs, bool down) {
               if (t >= (down ? h.prm.nu1 : h.prm.nu2)) continue;
               if ((int)r.has_b0 != hb || (int)r.noise != nz) continue;
               Level& v = h.lv[l];
-              T* xr = Fld<T>::x(v);
-              T* xb = xr + half_field(h);
-              const T* br = Fld<T>::b(v);
-              const T* bb = br + half_field(h);
+              const int64_t hn = v.n / 2;
+              T* xr = comp_at(Fld<T>::x(v), hn, r);
+              T* xb = comp_at(Fld<T>::x(v) + half_field(h), hn, r);
+              const T* br = comp_at(Fld<T>::b(v), hn, r);
+              const T* bb = comp_at(Fld<T>::b(v) + half_field(h), hn, r);
               RbPassItem<T> it;
               it.xc = colour ? xb : xr;
               it.xo = colour ? xr : xb;
@@ -611,23 +607,10 @@ int full_cycle(Run& r, bool residual_ready = false) {
   return cycle_phases(r, PH_ALL, residual_ready);
 }
 
-// One cycle of several runs on one stream (distinct hierarchies): every run's down-leg, then
-// the LDS-resident bottoms of all runs that have one in as few launches as possible (one per
+// The LDS-resident bottoms of every run that has one, in as few launches as possible (one per
 // sweep precision and noise setting, up to kBotMultiItems hierarchies and kBotMultiWG
-// components each), then every run's up-leg.  Each run's own kernels keep their order and the
-// runs touch disjoint memory, so every run computes exactly what full_cycle computes.
-int batch_cycle(const std::vector<Run*>& runs, const std::vector<char>& ready) {
-  // the legs of the runs with a split bottom go in lockstep (one launch per block-colour pass
-  // for all of them, per sweep precision); the others run their whole V-cycle in PH_DOWN
-  std::vector<Run> legs64, legs32;
-  for (size_t i = 0; i < runs.size(); ++i) {
-    Run& r = *runs[i];
-    SMG_TRY(cycle_phases(r, PH_IN, ready[i]));
-    if (!split_bottom(*r.h)) SMG_TRY(cycle_phases(r, PH_DOWN, ready[i]));
-    else (refined(*r.h) ? legs32 : legs64).push_back(leg_run(r));
-  }
-  SMG_TRY(legs_lockstep<double>(legs64, true));
-  SMG_TRY(legs_lockstep<float>(legs32, true));
+// components each; a run with more components takes a launch of its own).
+int batch_bottoms(const std::vector<Run*>& runs) {
   for (int f32 = 0; f32 < 2; ++f32)
     for (int nz = 0; nz < 2; ++nz) {
       BotMultiArgs m{};
@@ -669,16 +652,50 @@ int batch_cycle(const std::vector<Run*>& runs, const std::vector<char>& ready) {
         it.cpc = na.comps_per_chain;
         it.cpc_magic = na.cpc_magic;
         it.sqkT = na.sqkT;
-        for (int c = 0; c < r->nc; ++c) m.wg[nwg++] = (uint32_t)m.nitems | ((uint32_t)c << 16);
+        // the bottom numbers components absolutely (its noise keys take the chain table as is)
+        for (int c = r->c0; c < r->c0 + r->nc; ++c)
+          m.wg[nwg++] = (uint32_t)m.nitems | ((uint32_t)c << 16);
         ++m.nitems;
         lds = std::max(lds, h.bottom_lds);
         s = r->s;
       }
       SMG_TRY(flush());
     }
-  SMG_TRY(legs_lockstep<double>(legs64, false));
-  SMG_TRY(legs_lockstep<float>(legs32, false));
-  for (size_t i = 0; i < runs.size(); ++i) SMG_TRY(cycle_phases(*runs[i], PH_OUT, ready[i]));
+  return SMG_OK;
+}
+
+// One cycle of several runs on one stream (distinct hierarchies): every run's down-leg, then
+// the LDS-resident bottoms of all runs that have one in as few launches as possible (one per
+// sweep precision and noise setting, up to kBotMultiItems hierarchies and kBotMultiWG
+// components each), then every run's up-leg.  Each run's own kernels keep their order and the
+// runs touch disjoint memory, so every run computes exactly what full_cycle computes.
+// `phases`: PH_PRE (noise, bridge in, down-legs), PH_BOTTOM, PH_POST (up-legs, bridge out), or
+// any union; a cycle is PH_PRE, then PH_BOTTOM, then PH_POST.
+int batch_cycle(const std::vector<Run*>& runs, const std::vector<char>& ready,
+                int phases = PH_ALL) {
+  // the legs of the runs with a split bottom go in lockstep (one launch per block-colour pass
+  // for all of them, per sweep precision); the others run their whole V-cycle in PH_DOWN
+  std::vector<Run> legs64, legs32;
+  for (size_t i = 0; i < runs.size(); ++i) {
+    Run& r = *runs[i];
+    if (phases & PH_IN) SMG_TRY(cycle_phases(r, PH_IN, ready[i]));
+    if (!split_bottom(*r.h)) {
+      if (phases & PH_DOWN) SMG_TRY(cycle_phases(r, PH_DOWN, ready[i]));
+    } else {
+      (refined(*r.h) ? legs32 : legs64).push_back(leg_run(r));
+    }
+  }
+  if (phases & PH_DOWN) {
+    SMG_TRY(legs_lockstep<double>(legs64, true));
+    SMG_TRY(legs_lockstep<float>(legs32, true));
+  }
+  if (phases & PH_BOTTOM) SMG_TRY(batch_bottoms(runs));
+  if (phases & PH_UP) {
+    SMG_TRY(legs_lockstep<double>(legs64, false));
+    SMG_TRY(legs_lockstep<float>(legs32, false));
+  }
+  if (phases & PH_OUT)
+    for (size_t i = 0; i < runs.size(); ++i) SMG_TRY(cycle_phases(*runs[i], PH_OUT, ready[i]));
   return SMG_OK;
 }
 
@@ -1013,9 +1030,12 @@ struct SampleJob {
   }
 };
 
-// Streams and events of ng chain groups: ng - 1 side streams (default priority) with their
-// join events, a fork event and ng - 1 stagger events, made on the current device (again when
-// the device changed).
+// Streams and events of ng stream groups: ng side streams (default priority), made together so
+// that the runtime spreads them over its hardware queues, with their join and stagger events
+// and a fork event; made on the current device (again when the device changed).  Every group
+// runs on a side stream and the caller's stream only forks and joins: a group left on the
+// caller's stream could share a hardware queue with a side stream, which serialises the two
+// groups behind the stagger's waits (measured 40 % slower than one stream).
 int ensure_side_streams(Hierarchy& h, int ng) {
   int dev = -1;
   SMG_HIP(hipGetDevice(&dev));
@@ -1024,7 +1044,7 @@ int ensure_side_streams(Hierarchy& h, int ng) {
     SMG_HIP(hipEventCreateWithFlags(&h.ev_fork, hipEventDisableTiming));
     h.side_device = dev;
   }
-  while ((int)h.side.size() < ng - 1) {
+  while ((int)h.side.size() < ng) {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
     SMG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -1056,8 +1076,8 @@ int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
     return j.finish();
   }
   // Component groups on streams of their own: group i takes components [i nc / ng, (i+1) nc /
-  // ng); group 0 runs on the caller's stream, the others on the hierarchy's side streams,
-  // which wait for the caller's stream first and which it waits for at the end.  The groups
+  // ng) on the hierarchy's side stream i; the side streams wait for the caller's stream first
+  // and it waits for them at the end.  The groups
   // touch disjoint components (and regions of every shared buffer), and a component's work and
   // noise are the same whatever the group, so the results are those of one stream.
   SMG_TRY(ensure_side_streams(h, ng));
@@ -1065,10 +1085,10 @@ int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
   for (int i = 0; i < ng; ++i) {
     g[i].c0 = i * j.nc / ng;
     g[i].nc = (i + 1) * j.nc / ng - g[i].c0;
-    if (i > 0) g[i].s = h.side[i - 1];
+    g[i].s = h.side[i];
   }
   SMG_HIP(hipEventRecord(h.ev_fork, j.r.s));
-  for (int i = 1; i < ng; ++i) SMG_HIP(hipStreamWaitEvent(g[i].s, h.ev_fork, 0));
+  for (int i = 0; i < ng; ++i) SMG_HIP(hipStreamWaitEvent(g[i].s, h.ev_fork, 0));
   // Staggered: group i starts cycle k once group i-1 has finished the down-leg of cycle k, so
   // that its down-leg runs beside the other group's bottom instead of all groups reaching their
   // bottoms at once (identical groups issued together otherwise stay in phase).
@@ -1090,9 +1110,9 @@ int sample_impl(smg_hierarchy* hh, const Batch& bt, const uint64_t* seeds,
       if (rc == SMG_OK) rc = j.emit_after(k, g[i]);
     }
   // join even after an error, so that nothing the side streams hold outlives the call's stream
-  for (int i = 1; i < ng; ++i) {
-    const hipError_t e1 = hipEventRecord(h.ev_join[i - 1], g[i].s);
-    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(j.r.s, h.ev_join[i - 1], 0) : e1;
+  for (int i = 0; i < ng; ++i) {
+    const hipError_t e1 = hipEventRecord(h.ev_join[i], g[i].s);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(j.r.s, h.ev_join[i], 0) : e1;
     if (e2 != hipSuccess && rc == SMG_OK) {
       set_error(std::string("joining a chain-group stream: ") + hipGetErrorString(e2));
       rc = SMG_EHIP;
@@ -1574,25 +1594,85 @@ int smg_batch_run(smg_batch_item* items, int32_t n_items, void* stream) {
     alive[i] = 1;
     kmax = std::max(kmax, sj[i].total);
   }
-  for (int64_t k = 0; k < kmax; ++k) {
-    std::vector<Run*> runs;
-    std::vector<int> who;
-    for (int i = 0; i < n_items; ++i)
-      if (alive[i] && items[i].op == SMG_OP_SAMPLE && k < sj[i].total) {
-        sj[i].set_cycle(k);
-        runs.push_back(&sj[i].r);
-        who.push_back(i);
-      }
-    if (runs.empty()) break;
-    const int rc = batch_cycle(runs, std::vector<char>(runs.size(), 0));
-    for (int i : who) {
-      if (rc != SMG_OK) {
-        fail(i, rc);
-        continue;
-      }
-      const int re = sj[i].emit_after(k);
-      if (re != SMG_OK) fail(i, re);
+  // Stream groups (the largest setting among the sampling items' hierarchies; one stream while
+  // any of them times kernels): group g takes components [g nc / ng, (g+1) nc / ng) of every
+  // item, on its own stream, and starts each cycle once group g - 1 has finished that cycle's
+  // down-legs, as in a single sampling call.
+  int ng = 1;
+  bool timing = false;
+  Hierarchy* hs = nullptr;
+  for (int i = 0; i < n_items; ++i)
+    if (alive[i] && items[i].op == SMG_OP_SAMPLE) {
+      Hierarchy& h = items[i].h->h;
+      if (!hs) hs = &h;
+      ng = std::max(ng, h.stream_groups);
+      timing = timing || h.timing;
     }
+  if (timing) ng = 1;
+  if (ng > 1) {
+    bool forked = ensure_side_streams(*hs, ng) == SMG_OK &&
+                  hipEventRecord(hs->ev_fork, s) == hipSuccess;
+    for (int g = 0; g < ng && forked; ++g)
+      forked = hipStreamWaitEvent(hs->side[g], hs->ev_fork, 0) == hipSuccess;
+    if (!forked) {
+      set_error("could not set up the stream groups");
+      for (int i = 0; i < n_items; ++i)
+        if (alive[i] && items[i].op == SMG_OP_SAMPLE) fail(i, SMG_EHIP);
+      ng = 1;
+    }
+  }
+  std::vector<std::vector<Run>> gr(ng, std::vector<Run>(n_items));
+  for (int g = 0; g < ng; ++g)
+    for (int i = 0; i < n_items; ++i)
+      if (alive[i] && items[i].op == SMG_OP_SAMPLE) {
+        Run& r = gr[g][i];
+        r = sj[i].r;
+        r.c0 = g * sj[i].nc / ng;
+        r.nc = (g + 1) * sj[i].nc / ng - r.c0;
+        if (ng > 1) r.s = hs->side[g];
+      }
+  for (int64_t k = 0; k < kmax; ++k) {
+    bool any_run = false;
+    for (int g = 0; g < ng; ++g) {
+      std::vector<Run*> runs;
+      std::vector<int> who;
+      for (int i = 0; i < n_items; ++i)
+        if (alive[i] && items[i].op == SMG_OP_SAMPLE && k < sj[i].total && gr[g][i].nc > 0) {
+          gr[g][i].cycle = sj[i].cycle_of(k);
+          runs.push_back(&gr[g][i]);
+          who.push_back(i);
+        }
+      if (runs.empty()) continue;
+      any_run = true;
+      const hipStream_t gs = runs[0]->s;
+      const std::vector<char> ready(runs.size(), 0);
+      int rc = SMG_OK;
+      if (g > 0 && hipStreamWaitEvent(gs, hs->ev_mid[g - 1], 0) != hipSuccess) {
+        set_error("hipStreamWaitEvent failed");
+        rc = SMG_EHIP;
+      }
+      if (rc == SMG_OK) rc = batch_cycle(runs, ready, PH_IN | PH_DOWN);
+      if (rc == SMG_OK && g + 1 < ng && hipEventRecord(hs->ev_mid[g], gs) != hipSuccess) {
+        set_error("hipEventRecord failed");
+        rc = SMG_EHIP;
+      }
+      if (rc == SMG_OK) rc = batch_cycle(runs, ready, PH_BOTTOM | PH_UP | PH_OUT);
+      for (size_t q = 0; q < who.size(); ++q) {
+        const int i = who[q];
+        if (rc != SMG_OK) {
+          fail(i, rc);
+          continue;
+        }
+        const int re = sj[i].emit_after(k, *runs[q]);
+        if (re != SMG_OK) fail(i, re);
+      }
+    }
+    if (!any_run) break;
+  }
+  // the call's stream waits for the side streams before the state exports
+  for (int g = 0; g < ng && ng > 1; ++g) {
+    SMG_HIP(hipEventRecord(hs->ev_join[g], hs->side[g]));
+    SMG_HIP(hipStreamWaitEvent(s, hs->ev_join[g], 0));
   }
   for (int i = 0; i < n_items; ++i)
     if (alive[i] && items[i].op == SMG_OP_SAMPLE) {

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_vec(T* __restrict__ xc, const T
 // concatenation of every item's (block, component) grid; a work-group finds its item from the
 // offsets.  Each item brings its own noise keys; the Box-Muller coefficients are shared.
 struct RbNoiseKey {
-  uint32_t k0, k1, sid, c2, c3, cpc, cpc_magic;
+  uint32_t k0, k1, sid, c2, c3, cpc, cpc_magic, comp0;
   double sqkT;
   const ChainKey* chains;
 };
@@ -225,6 +225,7 @@ __global__ __launch_bounds__(TPB) void k_rb_pass_vec_multi(RbMultiArgs<T> m) {
   na.chains = it.nk.chains;
   na.comps_per_chain = it.nk.cpc;
   na.cpc_magic = it.nk.cpc_magic;
+  na.comp0 = it.nk.comp0;
   na.bm = m.bm;
   rb_pass_vec_body<T, HAS_B, NOISE, false>(it.xc, it.xo, it.bc, it.nh, it.ny, it.nz,
                                            it.nthreads, it.lg_nht, it.lg_ny, m.colour, it.inv_h2,
@@ -791,6 +792,7 @@ hipError_t launch_rb_pass_multi(const RbPassItem<T>* items, int n, int colour, b
     it.nk.cpc_magic = p.na.cpc_magic;
     it.nk.sqkT = p.na.sqkT;
     it.nk.chains = p.na.chains;
+    it.nk.comp0 = p.na.comp0;
     m.begin[m.nitems] = total;
     total += it.nblk * (uint32_t)p.ncomp;
     ++m.nitems;

@@ -62,9 +62,9 @@ struct Hierarchy {
   bool block_pairs = true;         // two block colours per launch where the level allows
   // sampling calls: component groups on streams of their own (1: the caller's stream only)
   int stream_groups = 1;
-  std::vector<hipStream_t> side;     // side streams of groups 1 .. (made on first use)
+  std::vector<hipStream_t> side;     // one side stream per group (made on first use)
   std::vector<hipEvent_t> ev_join;   // one per side stream
-  std::vector<hipEvent_t> ev_mid;    // group i at the end of its down-leg (i < groups - 1)
+  std::vector<hipEvent_t> ev_mid;    // group i at the end of its down-leg
   hipEvent_t ev_fork = nullptr;
   int side_device = -1;
   size_t off_botargs = 0;

@@ -4,8 +4,9 @@ same operation called alone, bit for bit.
 Items differ in grid, depth, precision, chain batching and bottom handling: a one-chain FP64
 sampler, a batched FP32-refined sampler, a hierarchy whose small levels run one launch per pass
 (no merged bottom), a one-level hierarchy drawn exactly, and several hierarchies whose bottoms
-share a launch; sampling items run different numbers of cycles (stride, burn-in, n); solve
-items converge after different numbers of cycles (different rtol).
+share a launch; sampling items run different numbers of cycles (stride, burn-in, n), also in
+two and three staggered stream groups; solve items converge after different numbers of cycles
+(different rtol).
 """
 import pytest
 
@@ -33,11 +34,12 @@ SAMPLE_CASES = [
 ]
 
 
-def _items(seed_base, dtype):
+def _items(seed_base, dtype, groups=1):
     items, hs = [], []
     for k, (dims, kw, nch, cpc, n, bottom) in enumerate(SAMPLE_CASES):
         H = _H(dims, **kw)
         H.set_bottom_kernel(bottom)
+        H.set_stream_groups(groups)
         st = torch.zeros(H.shape, dtype=torch.float64, device="cuda")
         nact = nch * cpc if nch else H.shape[0]
         st = st[:nact].contiguous()
@@ -54,11 +56,14 @@ def _items(seed_base, dtype):
     return items
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_batch_run_samples_equal_alone(dtype):
+@pytest.mark.parametrize("dtype,groups", [(torch.float64, 1), (torch.float32, 1),
+                                          (torch.float64, 2), (torch.float32, 3)])
+def test_batch_run_samples_equal_alone(dtype, groups):
+    """groups > 1: the items' components in staggered stream groups (each group a share of
+    every item, lockstep legs and merged bottoms within the group)."""
     from paper_1003_2680_amd.api import batch_run
-    _announce("smg_batch_run samples %s" % dtype)
-    items = _items(300, dtype)
+    _announce("smg_batch_run samples %s, %d stream group(s)" % (dtype, groups))
+    items = _items(300, dtype, groups)
     res = batch_run(items)
     torch.cuda.synchronize()
     assert all(st == 0 for st, _ in res), res

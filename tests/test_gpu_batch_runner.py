@@ -51,12 +51,17 @@ def test_runner_samples_and_solves_equal_alone(precision, engine):
         assert torch.equal(us[i], u[0]) and infos[i][0] == cyc, i
 
 
-def test_runner_graph_replay_continues_chains():
+@pytest.mark.parametrize("groups", [1, 2])
+def test_runner_graph_replay_continues_chains(groups):
+    """The replayed graph (captured in the one-stream form whatever the runner's stream
+    groups) continues the chains as eager one-stream calls, and eager calls in stream groups
+    after the replays continue them the same way."""
     from paper_1003_2680_amd.batch import BatchRunner
-    _announce("batch runner graph replay")
+    _announce("batch runner graph replay, %d stream group(s)" % groups)
     insts = _instances()
     eager = BatchRunner(insts, precision="fp32_refined", configs={i.dims: CFG for i in insts})
-    graph = BatchRunner(insts, precision="fp32_refined", configs={i.dims: CFG for i in insts})
+    graph = BatchRunner(insts, precision="fp32_refined", configs={i.dims: CFG for i in insts},
+                        stream_groups=groups)
     eager.start()
     graph.start()
     graph.capture(2)
