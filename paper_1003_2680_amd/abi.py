@@ -155,6 +155,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libsmg.so not built: run __graft_entry__.build() or "
                            "python -m paper_1003_2680_amd.build")
+    # torch first: the library then binds to the HIP runtime torch loaded (same soname).  Loaded
+    # the other way round, torch would bring a second HIP runtime into the process, and the
+    # library's calls would find no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     H = ctypes.c_void_p
