@@ -8,7 +8,7 @@ offset added to the noise keys, so every output must match bit for bit.
 * Batched chains (smg_sample_batch): the emitted fields, the observables, the running moments
   and the final state, over two calls in a row (the second continues the chains from the device
   table).  Cases: the bottom kernel with FP64 sweeps, groups that cut chains apart (5 chains of
-  2 components in 3 groups), one component per chain in 4 groups with float32 output, the
+  2 components in 3 groups), one component per chain in 3 groups with float32 output, the
   FP32-refined form, the bottom kernel off (every level as launches), a one-level hierarchy
   (exact draws only), more groups than components, and one chain of three components split
   into three groups.
@@ -21,13 +21,13 @@ pytestmark = pytest.mark.gpu
 
 # (dims, hierarchy keywords, chains, comps per chain, groups, bottom kernel, out dtype)
 CASES = [
-    ((64, 64, 32), dict(levels=4), 8, 3, 4, True, torch.float64),
+    ((64, 64, 32), dict(levels=4), 8, 3, 3, True, torch.float64),
     ((32, 32, 16), dict(levels=3), 5, 2, 3, True, torch.float64),
-    ((32, 32, 32), dict(levels=3), 8, 1, 4, True, torch.float32),
+    ((32, 32, 32), dict(levels=3), 8, 1, 3, True, torch.float32),
     ((64, 64, 32), dict(levels=4, precision="fp32_refined"), 4, 3, 2, True, torch.float64),
-    ((32, 32, 16), dict(levels=3), 4, 2, 4, False, torch.float64),
+    ((32, 32, 16), dict(levels=3), 4, 2, 3, False, torch.float64),
     ((8, 8, 4), dict(levels=1), 6, 1, 3, True, torch.float64),
-    ((16, 16, 8), dict(levels=2), 1, 2, 4, True, torch.float64),
+    ((16, 16, 8), dict(levels=2), 1, 2, 3, True, torch.float64),
     ((64, 64, 32), dict(levels=4), 1, 3, 3, True, torch.float64),
 ]
 
@@ -96,8 +96,8 @@ def test_stream_groups_one_chain_equal_one_stream(precision):
 def test_stream_groups_option_range():
     from paper_1003_2680_amd import abi
     H = _hier((16, 16, 8), dict(levels=2), 2, 1)
-    for bad in (0, 5, -1):
+    for bad in (0, 4, -1):
         rc = H.lib.smg_set_option(H._h, abi.SMG_OPT_STREAM_GROUPS, bad)
         assert rc == abi.SMG_EINVAL
-    H.set_stream_groups(4)
+    H.set_stream_groups(3)
     H.close()
