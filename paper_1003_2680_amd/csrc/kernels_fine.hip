@@ -8,6 +8,8 @@
 // read(other colour) + write(own colour): the minimum traffic of a sweep.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -311,39 +313,49 @@ __global__ __launch_bounds__(TPB) void k_residual0(T* __restrict__ r, const T* _
 }
 
 // Fused residual and restriction from level 0: b_c = P^T (b - A x) without writing r.
-// A work-group owns an RR_X x RR_Y column of coarse cells over up to RR_Z coarse layers and
+// A work-group owns an RX x RY column of coarse cells over up to RR_Z coarse layers and
 // marches up through the fine planes of their restriction windows, [2Z0-1, 2Z0+2RZ].  For
 // each fine plane f it stages x plane f+1 into a ring of four LDS planes (the global loads
 // of the planes up to four steps ahead are in flight meanwhile), forms the residual of
-// plane f over the 18 x 18 window of the column, and every coarse cell of the column takes
-// that plane's 4x4 window sum (weights 1/4, 3/4, 3/4, 1/4 per axis; 1/2 for a fine cell next
-// to a wall) into the running sums of the two coarse layers the plane belongs to: four lanes
-// per coarse cell, one window column each, joined by shuffles.  Each x plane is loaded once
-// per column and each residual plane formed once, instead of once per coarse layer pair.
-// Also zeroes the coarse iterate when xc is not null.
-constexpr int RR_X = 8, RR_Y = 8, RR_Z = 8;
-constexpr int RR_FX = 2 * RR_X + 2, RR_FY = 2 * RR_Y + 2;  // residual window of a plane
-constexpr int RR_SX = RR_FX + 2, RR_SY = RR_FY + 2;        // x box of a plane
-constexpr int RR_XP = RR_SX * RR_SY;                       // x plane in LDS
-// The residual window is formed and stored with the x box's row stride RR_SX (two idle
-// lanes per row), so consecutive lanes touch consecutive LDS words: no bank conflicts.
-constexpr int RR_RP = RR_SX * RR_FY;                       // residual plane in LDS
-constexpr int RR_PPT = (RR_XP + TPB - 1) / TPB;            // x positions per thread
-constexpr int RR_RPT = (RR_RP + TPB - 1) / TPB;            // residual positions per thread
-constexpr int RR_PF = 4;                                   // x planes loaded ahead
-static_assert(RR_X * RR_Y * 4 == TPB, "four lanes per coarse cell of the column");
+// plane f over the (2RX+2) x (2RY+2) window of the column, and every coarse cell of the column
+// takes that plane's 4x4 window sum (weights 1/4, 3/4, 3/4, 1/4 per axis; 1/2 for a fine cell
+// next to a wall) into the running sums of the two coarse layers the plane belongs to: 4, 2 or
+// 1 lanes per coarse cell (TPB / (RX RY)), each summing 1, 2 or 4 window columns, joined by
+// shuffles in the same order for every shape.  Each x plane is loaded once per column and each
+// residual plane formed once, instead of once per coarse layer pair.  Also zeroes the coarse
+// iterate when xc is not null.
+constexpr int RR_Z = 8;
+constexpr int RR_PF = 4;  // x planes loaded ahead
+template <int RX, int RY>
+struct RRShape {
+  static constexpr int FX = 2 * RX + 2, FY = 2 * RY + 2;  // residual window of a plane
+  static constexpr int SX = FX + 2, SY = FY + 2;          // x box of a plane
+  static constexpr int XP = SX * SY;                      // x plane in LDS
+  // The residual window is formed and stored with the x box's row stride SX (two idle lanes
+  // per row), so consecutive lanes touch consecutive LDS words: no bank conflicts.
+  static constexpr int RP = SX * FY;                      // residual plane in LDS
+  static constexpr int PPT = (XP + TPB - 1) / TPB;        // x positions per thread
+  static constexpr int RPT = (RP + TPB - 1) / TPB;        // residual positions per thread
+  static constexpr int LPC = TPB / (RX * RY);             // lanes per coarse cell
+  static constexpr int CPL = 4 / LPC;                     // window columns per lane
+  static_assert(RX * RY * LPC == TPB && (LPC == 1 || LPC == 2 || LPC == 4),
+                "1, 2 or 4 lanes per coarse cell of the column");
+};
 
-template <typename T, bool HAS_B>
+template <typename T, bool HAS_B, int RX, int RY>
 __global__ __launch_bounds__(TPB) void k_restrict_residual0(
     T* __restrict__ bc, T* __restrict__ xc, const T* __restrict__ xr, const T* __restrict__ xb,
     const T* __restrict__ br, const T* __restrict__ bb, int nx, int ny, int nz, int ntx,
     T inv_h2) {
+  using Sh = RRShape<RX, RY>;
+  constexpr int RR_SX = Sh::SX, RR_XP = Sh::XP, RR_RP = Sh::RP, RR_FX = Sh::FX;
+  constexpr int RR_PPT = Sh::PPT, RR_RPT = Sh::RPT;
   __shared__ T Xs[4 * RR_XP + 1];  // + a pad element for positions past the plane
   __shared__ T Rs[2 * RR_RP];
   const Blk3 wg = xcd_block();
   const uint32_t comp = wg.z;
   const int nxc = nx >> 1, nyc = ny >> 1, nzc = nz >> 1;
-  const int X0 = (wg.x % ntx) * RR_X, Y0 = (wg.x / ntx) * RR_Y;
+  const int X0 = (wg.x % ntx) * RX, Y0 = (wg.x / ntx) * RY;
   const int Z0 = wg.y * RR_Z;
   const int zc = min(RR_Z, nzc - Z0);
   const int nh = nx >> 1;
@@ -398,9 +410,9 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
       reg[p] = HAS_B ? split_at(br, bb, cb, fx, fy, g, nh, ny) : T(0);
     }
   };
-  // this lane's coarse cell and window column
-  const int wb = tid & 3, cell = tid >> 2;
-  const int lx = cell % RR_X, ly = cell / RR_X;
+  // this lane's coarse cell and window columns
+  const int wb = tid % Sh::LPC, cell = tid / Sh::LPC;
+  const int lx = cell % RX, ly = cell / RX;
   const int X = X0 + lx, Y = Y0 + ly;
   const bool owner = wb == 0 && X < nxc && Y < nyc;
   T acc0 = 0, acc1 = 0;  // running sums of the even and the odd coarse layer
@@ -431,15 +443,30 @@ __global__ __launch_bounds__(TPB) void k_restrict_residual0(
     if (HAS_B && f + 2 <= f1) load_b(bcur, f + 2);
     __syncthreads();
     if (f < 0 || f >= nz) return;
-    // lane wb takes window column wb (x offset) down the four rows: the lanes of a wave read
-    // one contiguous run of the row at a time
-    const T* Rr = R + 2 * ly * RR_SX + 2 * lx + wb;
-    T s = 0;
+    // lane wb takes window columns wb CPL .. wb CPL + CPL - 1 (x offsets) down the four rows
+    // (with four lanes per cell the lanes of a wave read one contiguous run of the row at a
+    // time); the column sums join as ((c0 + c1) + (c2 + c3)) whatever the lanes per cell
+    T cs[Sh::CPL];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) s = fma(pw<T>(b), Rr[b * RR_SX], s);
-    s *= pw<T>(wb);
-    s += __shfl_xor(s, 1, 4);
-    s += __shfl_xor(s, 2, 4);
+    for (int q = 0; q < Sh::CPL; ++q) {
+      const int col = wb * Sh::CPL + q;
+      const T* Rr = R + 2 * ly * RR_SX + 2 * lx + col;
+      T c = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c = fma(pw<T>(b), Rr[b * RR_SX], c);
+      cs[q] = c * pw<T>(col);
+    }
+    T s;
+    if constexpr (Sh::LPC == 4) {
+      s = cs[0];
+      s += __shfl_xor(s, 1, 4);
+      s += __shfl_xor(s, 2, 4);
+    } else if constexpr (Sh::LPC == 2) {
+      s = cs[0] + cs[1];
+      s += __shfl_xor(s, 1, 2);
+    } else {
+      s = (cs[0] + cs[1]) + (cs[2] + cs[3]);
+    }
     // plane f is window plane c1 of coarse layer Z1 and plane c1 + 2 of layer Z1 - 1
     const int Z1 = (f + 1) >> 1, c1 = f - (2 * Z1 - 1);
 #pragma unroll
@@ -817,11 +844,25 @@ hipError_t launch_restrict_residual0(T* bc, T* xc, const T* xr, const T* xb, con
                                      hipStream_t s) {
   const int nxc = nx >> 1, nyc = ny >> 1, nzc = nz >> 1;
   if (nxc * nyc * nzc == 0) return hipSuccess;
-  const int ntx = (nxc + RR_X - 1) / RR_X, nty = (nyc + RR_Y - 1) / RR_Y;
-  dim3 grid(ntx * nty, (nzc + RR_Z - 1) / RR_Z, ncomp);
   const T ih2 = (T)(1.0 / (h * h));
-  if (br) k_restrict_residual0<T, true><<<grid, TPB, 0, s>>>(bc, xc, xr, xb, br, bb, nx, ny, nz, ntx, ih2);
-  else k_restrict_residual0<T, false><<<grid, TPB, 0, s>>>(bc, xc, xr, xb, br, bb, nx, ny, nz, ntx, ih2);
+  auto go = [&](auto rx, auto ry) {
+    constexpr int RX = decltype(rx)::value, RY = decltype(ry)::value;
+    const int ntx = (nxc + RX - 1) / RX, nty = (nyc + RY - 1) / RY;
+    dim3 grid(ntx * nty, (nzc + RR_Z - 1) / RR_Z, ncomp);
+    if (br)
+      k_restrict_residual0<T, true, RX, RY>
+          <<<grid, TPB, 0, s>>>(bc, xc, xr, xb, br, bb, nx, ny, nz, ntx, ih2);
+    else
+      k_restrict_residual0<T, false, RX, RY>
+          <<<grid, TPB, 0, s>>>(bc, xc, xr, xb, br, bb, nx, ny, nz, ntx, ih2);
+  };
+  // 16 x 8 coarse cells per work-group where the grid is that wide (less halo and scalar work
+  // per cell: 190 us against 229 us for 8 x 8 at 128^3 x 24; 16 x 16 took 219 us at half the
+  // occupancy), else 8 x 8
+  if (nxc >= 16)
+    go(std::integral_constant<int, 16>(), std::integral_constant<int, 8>());
+  else
+    go(std::integral_constant<int, 8>(), std::integral_constant<int, 8>());
   return hipGetLastError();
 }
 

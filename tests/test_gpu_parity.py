@@ -131,8 +131,10 @@ def test_transfers(dims, levels):
 
 
 # level-0 residual + restriction on grids whose coarse columns and coarse layers are ragged
-# (partial tiles in x and y, several z-runs per column with a short last one)
-@pytest.mark.parametrize("dims,levels", [((48, 24, 40), 3), ((20, 12, 36), 2)])
+# (partial tiles in x and y, several z-runs per column with a short last one), with 16 x 8
+# coarse tiles (coarse x-extent 24 and 20) and 8 x 8 ones (10)
+@pytest.mark.parametrize("dims,levels", [((48, 24, 40), 3), ((20, 12, 36), 2),
+                                         ((40, 16, 24), 3)])
 def test_restrict_residual0_ragged(dims, levels):
     _announce("restrict_residual0 %s L=%d" % (dims, levels))
     ncomp = 2
