@@ -412,6 +412,19 @@ def measure_composite(dev, cycles=20, with_cpu=True):
     # the level), b and x of this colour's cells (read b, write x: 2/8), 8 B per value
     nbytes = nb * 8 * 5 // 8
     ach = nbytes / avg_s / 1e9
+    # the field noise of Appendix A, w = L^-1 Q eta with q = 1 (a draw: the Philox forcing, then
+    # a FAC solve of A w = -(volume / h^3) q eta from zero to rtol 1e-8)
+    S.forced_field(1, 11, 0, rtol=1e-8, max_cycles=60)
+    torch.cuda.synchronize()
+    n_draws = 4
+    t2 = time.perf_counter()
+    _, _, finfos = S.forced_field(n_draws, 11, 1, rtol=1e-8, max_cycles=60)
+    torch.cuda.synchronize()
+    draw_s = (time.perf_counter() - t2) / n_draws
+    forced = {"rtol": 1e-8, "ms_per_draw": round(draw_s * 1e3, 3),
+              "draws_per_s": round(1.0 / draw_s, 2),
+              "cycles_per_draw": round(sum(i.cycles for i in finfos) / n_draws, 2),
+              "q": "1 on every cell (L^-1 C not symmetric: the composite mesh's L = M^-1 S)"}
     out = {
         "workload": "adaptive composite grid: 256x256x128 base (periodic x,y; no-slip z walls) "
                     "with the box [64,192)^2 x [0,32) refined by two; FAC cycle nu=%d, base "
@@ -432,6 +445,7 @@ def measure_composite(dev, cycles=20, with_cpu=True):
                      "kernel": "k_gblock_pass (block colour pass, finest base level)",
                      "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": nbytes},
+        "forced_field": forced,
     }
     del S, xc, xf, rc, rf, x0, b0
     torch.cuda.empty_cache()
