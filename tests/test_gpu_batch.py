@@ -79,10 +79,12 @@ def test_batch_solve_equals_alone(precision):
     assert infos[2][0] == 0 and float(u[4:6].abs().max()) == 0.0
 
 
-def test_batch_graph_replay_continues_chains():
-    """A captured batched call replayed K times equals K eager calls (trap check: every replay
-    compared, with eager work and synchronisation between replays)."""
-    _announce("batch graph replay")
+@pytest.mark.parametrize("groups", [1, 3])
+def test_batch_graph_replay_continues_chains(groups):
+    """A captured batched call replayed K times equals K eager one-stream calls (trap check:
+    every replay compared, with eager work and synchronisation between replays); with three
+    stream groups the side streams join the capture through the fork event."""
+    _announce("batch graph replay, %d stream group(s)" % groups)
     dims = (16, 16, 8)
     n = 2
     HE = _hier(*dims, ncomp=3, levels=3)
@@ -92,6 +94,7 @@ def test_batch_graph_replay_continues_chains():
         o, _, se = HE.sample_batch(n, nchains=3, comps_per_chain=1, state=se)
         ref.append(o.clone())
     HG = _hier(*dims, ncomp=3, levels=3)
+    HG.set_stream_groups(groups)
     b0, _, sg = HG.sample_batch(n, seeds=SEEDS, first_cycles=FIRST, comps_per_chain=1)
     assert torch.equal(a0, b0)
     out = torch.empty_like(ref[0])
