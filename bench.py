@@ -67,7 +67,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_128cubed_3comp_fp64.json"
 # the sources each timed kernel class is compiled from: a traffic record applies only to them
 KERNEL_SOURCES = {
     "fine_pass": ("kernels_fine.hip", "device_common.hpp", "philox.hpp", "kernels.hpp"),
+    "fine_pass_fp32": ("kernels_fine.hip", "device_common.hpp", "philox.hpp", "kernels.hpp"),
     "level1_block_pass": ("kernels_gal.hip", "device_common.hpp", "philox.hpp", "kernels.hpp"),
+    "composite_base_pass": ("kernels_comp.hip", "composite.hpp", "device_common.hpp",
+                            "philox.hpp", "kernels.hpp"),
 }
 
 
@@ -441,7 +444,8 @@ def measure_composite(dev, cycles=20, with_cpu=True):
         "solve_relres": float("%.3e" % si.relres),
         "energy_over_n_kT": round(energy / n, 5),
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("composite_base_pass", 1),
                      "kernel": "k_gblock_pass (block colour pass, finest base level)",
                      "avg_launch_us": round(avg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": nbytes},
@@ -877,7 +881,7 @@ def main():
         # other colour and this colour's b, write this colour, 4 B per value
         line["fp32_refined"]["roofline"] = roof(
             r32["kern"]["fine_pass"], "k_rb_pass (FP32 level-0 colour pass, 128^3, with b)",
-            nact * N0 * 4 * 3 // 2)
+            nact * N0 * 4 * 3 // 2, measured_traffic("fine_pass_fp32", C))
 
     if not args.no_hbm_point:
         line["hbm_point"] = measure_hbm_point(dev)
