@@ -570,6 +570,82 @@ __global__ __launch_bounds__(TPB) void k_refine_residual(float* __restrict__ r32
   }
 }
 
+// The same residual (without norms) two sites per thread, as the colour passes move the field:
+// thread (row, jt) of colour c owns sites 2 jt, 2 jt + 1 of its row, reads them and b with one
+// 16-byte load each and its neighbours in the other colour's array with one 16-byte load per
+// neighbour row (plus the entry beyond on the side its x-neighbours lie), and writes both
+// residuals with one 8-byte store.  The neighbour sums run in the order of k_refine_residual,
+// so both kernels give the same bits.
+template <bool HAS_B, bool ZU>
+__global__ __launch_bounds__(TPB) void k_refine_residual_vec(float* __restrict__ r32,
+                                                              const double* __restrict__ x64,
+                                                              const double* __restrict__ b64,
+                                                              int nh, int ny, int nz,
+                                                              uint32_t nthreads, int lg_nht,
+                                                              int lg_ny, double inv_h2,
+                                                              size_t half) {
+  constexpr uint32_t S = 2;
+  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  if (t >= nthreads) return;
+  const uint32_t comp = blockIdx.y;
+  const int colour = blockIdx.z;
+  const uint32_t nht = (uint32_t)nh / S;
+  uint32_t row, jt, z, y;
+  if (lg_nht >= 0) {
+    row = t >> lg_nht;
+    jt = t & (nht - 1);
+  } else {
+    row = t / nht;
+    jt = t - row * nht;
+  }
+  if (lg_ny >= 0) {
+    z = row >> lg_ny;
+    y = row & ((uint32_t)ny - 1);
+  } else {
+    z = row / (uint32_t)ny;
+    y = row - z * (uint32_t)ny;
+  }
+  const uint32_t nsite = (uint32_t)nh * ny * nz;
+  const size_t base = (size_t)comp * nsite;
+  const double* __restrict__ own = x64 + (size_t)colour * half + base;
+  const char* __restrict__ ob = reinterpret_cast<const char*>(x64 + (size_t)(colour ^ 1) * half + base);
+  const uint32_t plane = (uint32_t)nh * ny;
+  const uint32_t ic = S * t;
+  const uint32_t rb = ic - S * jt;
+  const uint32_t xs = (y + z + (uint32_t)colour) & 1u;
+  auto ld = [&](uint32_t e) {
+    const double2 v = *reinterpret_cast<const double2*>(ob + e * 8u);
+    return v;
+  };
+  const double2 c = ld(ic);
+  const uint32_t ie = xs ? (jt + 1 == nht ? rb : ic + S) : (jt == 0 ? rb + (uint32_t)nh - 1 : ic - 1);
+  const double ex = *reinterpret_cast<const double*>(ob + ie * 8u);
+  const uint32_t in = ic + (y + 1 == (uint32_t)ny ? (uint32_t)nh - plane : (uint32_t)nh);
+  const uint32_t is = ic + (y == 0 ? plane - (uint32_t)nh : 0u - (uint32_t)nh);
+  const double2 n = ld(in), so = ld(is);
+  const uint32_t zw = ZU ? __builtin_amdgcn_readfirstlane(z) : z;
+  const bool top = zw + 1 >= (uint32_t)nz, bottom = zw == 0;
+  const double2 u = ld(ic + (top ? 0u : plane)), d = ld(ic - (bottom ? 0u : plane));
+  const double2 xo = *reinterpret_cast<const double2*>(own + ic);
+  double2 bv = make_double2(0.0, 0.0);
+  if (HAS_B) bv = *reinterpret_cast<const double2*>(b64 + (size_t)colour * half + base + ic);
+  const int nw = (int)top + (int)bottom;
+  // x-neighbour sums (x - 1) + (x + 1): xs == 1 -> (j, j+1), xs == 0 -> (j-1, j); the entry
+  // beyond the owned ones closes the last pair on the side it lies
+  const double sx0 = xs ? c.x + c.y : ex + c.x;
+  const double sx1 = xs ? c.y + ex : c.x + c.y;
+  auto res = [&](double sx, double nv, double sv, double uv, double dv, double xv, double b) {
+    double s = (sx + sv) + nv;
+    if (!top) s += uv;
+    if (!bottom) s += dv;
+    return b - ((6 + nw) * xv - s) * inv_h2;
+  };
+  float2 out;
+  out.x = (float)res(sx0, n.x, so.x, u.x, d.x, xo.x, bv.x);
+  out.y = (float)res(sx1, n.y, so.y, u.y, d.y, xo.y, bv.y);
+  *reinterpret_cast<float2*>(r32 + (size_t)colour * half + base + ic) = out;
+}
+
 __global__ __launch_bounds__(TPB) void k_refine_update(double* __restrict__ x64,
                                                         const float* __restrict__ e32, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
@@ -919,6 +995,22 @@ hipError_t launch_refine_residual(float* r32, const double* x64, const double* b
   const uint32_t nblk = blocks_for(nsite);
   dim3 grid(nblk, ncomp, 2);
   const double ih2 = 1.0 / (h * h);
+  const int nh = nx / 2;
+  const size_t half = (size_t)ncomp_stride * nsite;
+  if (!norm && nh % 2 == 0 && (uint64_t)nsite * sizeof(double) < (1ull << 32)) {
+    // no norms: two sites per thread
+    const uint32_t nthreads = nsite / 2;
+    const int lg_nht = ilog2_exact((uint32_t)(nh / 2)), lg_ny = ilog2_exact((uint32_t)ny);
+    const bool zu = ((uint64_t)(nh / 2) * ny) % 64 == 0;
+    dim3 gv(blocks_for(nthreads), ncomp, 2);
+#define SMG_RRV(HB, ZU)                                                                     \
+  k_refine_residual_vec<HB, ZU><<<gv, TPB, 0, s>>>(r32, x64, b64, nh, ny, nz, nthreads, lg_nht, \
+                                                   lg_ny, ih2, half)
+    if (zu) { if (b64) SMG_RRV(true, true); else SMG_RRV(false, true); }
+    else { if (b64) SMG_RRV(true, false); else SMG_RRV(false, false); }
+#undef SMG_RRV
+    return hipGetLastError();
+  }
 #define SMG_RR(HB, NM) \
   k_refine_residual<HB, NM><<<grid, TPB, 0, s>>>(r32, x64, b64, nx, ny, nz, nsite, ih2, part, nblk, \
                                                  (size_t)ncomp_stride * nsite)
