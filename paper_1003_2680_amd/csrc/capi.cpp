@@ -59,11 +59,14 @@ struct Run {
   const ChainKey* chains;  // batched chains (device table) or null
   uint32_t cpc;            // components per chain
   int c0;                  // first component
+  // FP32-refined form: the correction e is known to be zero (the previous cycle of this run
+  // folded it into x and cleared it), so the next cycle need not clear it
+  bool e_zero;
 };
 
 Run make_run(Hierarchy& h, hipStream_t s, bool noise, bool has_b0, uint64_t seed,
              uint64_t cycle) {
-  return Run{&h, s, noise, has_b0, seed, cycle, h.desc.ncomp, nullptr, 1, 0};
+  return Run{&h, s, noise, has_b0, seed, cycle, h.desc.ncomp, nullptr, 1, 0, false};
 }
 
 // The run's share of a component-major buffer with `per` elements per component (null stays
@@ -460,15 +463,19 @@ int cycle_phases(Run& r, int phases, bool residual_ready = false) {
       SMG_HIP(launch_refine_residual(comp_at(v0.bf, hn, r), x,
                                      r.has_b0 ? comp_at(v0.b, hn, r) : nullptr, v0.nx, v0.ny,
                                      v0.nz, r.nc, h.desc.ncomp, h.desc.h, nullptr, nullptr, r.s));
-    SMG_HIP(launch_zero<float>(xf, act, r.s));
-    SMG_HIP(launch_zero<float>(xf + half, act, r.s));
+    if (!r.e_zero) {
+      SMG_HIP(launch_zero<float>(xf, act, r.s));
+      SMG_HIP(launch_zero<float>(xf + half, act, r.s));
+    }
+    r.e_zero = false;
   }
   if (phases & PH_DOWN) SMG_TRY(split ? vdown<float>(ri) : vcycle<float>(ri, 0));
   if (split && (phases & PH_BOTTOM)) SMG_TRY(bottom_cycle<float>(ri));
   if (split && (phases & PH_UP)) SMG_TRY(vup<float>(ri));
   if (phases & PH_OUT) {
-    SMG_HIP(launch_refine_update(x, xf, act, r.s));
-    SMG_HIP(launch_refine_update(x + half, xf + half, act, r.s));
+    // x += e on both colour arrays, clearing e for the next cycle
+    SMG_HIP(launch_refine_out(x, xf, act, (int64_t)half, r.s));
+    r.e_zero = true;
   }
   return SMG_OK;
 }

@@ -257,6 +257,9 @@ hipError_t launch_refine_residual(float* r32, const double* x64, const double* b
                                   double* part, double* norm, hipStream_t s);
 //   x64 += (double)e32 over n elements (both colour arrays)
 hipError_t launch_refine_update(double* x64, const float* e32, int64_t n, hipStream_t s);
+//   x64 += (double)e32, then e32 = 0, over the spans [0, n) and [stride, stride + n) (the two
+//   colour arrays of a component range), in one launch
+hipError_t launch_refine_out(double* x64, float* e32, int64_t n, int64_t stride, hipStream_t s);
 
 // Chain table of batched runs: dst[first .. first+count) = keys; advance adds `cycles` to the
 // first cycle of chains 0..n-1 (so that a replayed launch sequence continues the chains).

@@ -652,6 +652,32 @@ __global__ __launch_bounds__(TPB) void k_refine_update(double* __restrict__ x64,
   for (; i < n; i += (int64_t)gridDim.x * TPB) x64[i] += (double)e32[i];
 }
 
+// x += e and then e = 0 on the two colour arrays of a component range in one launch (span s of
+// n elements at offset s * stride), two elements per thread when n is even (16- and 8-byte
+// accesses).
+template <bool PAIR>
+__global__ __launch_bounds__(TPB) void k_refine_out(double* __restrict__ x64,
+                                                     float* __restrict__ e32, int64_t n,
+                                                     int64_t stride) {
+  const int64_t off = (int64_t)blockIdx.y * stride;
+  double* __restrict__ X = x64 + off;
+  float* __restrict__ E = e32 + off;
+  const int64_t m = PAIR ? n / 2 : n;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < m; i += (int64_t)gridDim.x * TPB) {
+    if (PAIR) {
+      double2 x = reinterpret_cast<double2*>(X)[i];
+      const float2 e = reinterpret_cast<float2*>(E)[i];
+      x.x += (double)e.x;
+      x.y += (double)e.y;
+      reinterpret_cast<double2*>(X)[i] = x;
+      reinterpret_cast<float2*>(E)[i] = make_float2(0.0f, 0.0f);
+    } else {
+      X[i] += (double)E[i];
+      E[i] = 0.0f;
+    }
+  }
+}
+
 // x += P e into the split level-0 storage (grid.z = colour).
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_prolong0(T* __restrict__ xr, T* __restrict__ xb,
@@ -1021,6 +1047,19 @@ hipError_t launch_refine_residual(float* r32, const double* x64, const double* b
   if (e != hipSuccess || !norm) return e;
   // second stage of the fixed-order sum over the 2*nblk partials of each component
   return launch_sumsq_final_parts(norm, part, 2 * nblk, ncomp, s);
+}
+
+hipError_t launch_refine_out(double* x64, float* e32, int64_t n, int64_t stride,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const bool pair = n % 2 == 0 && stride % 2 == 0 && ((uintptr_t)x64 & 15) == 0 &&
+                    ((uintptr_t)e32 & 7) == 0;
+  const int64_t m = pair ? n / 2 : n;
+  const int64_t b = (m + TPB - 1) / TPB;
+  dim3 grid((unsigned)(b < 32768 ? b : 32768), 2);
+  if (pair) k_refine_out<true><<<grid, TPB, 0, s>>>(x64, e32, n, stride);
+  else k_refine_out<false><<<grid, TPB, 0, s>>>(x64, e32, n, stride);
+  return hipGetLastError();
 }
 
 hipError_t launch_refine_update(double* x64, const float* e32, int64_t n, hipStream_t s) {
