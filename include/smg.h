@@ -328,7 +328,7 @@ enum {
   SMG_OPT_BLOCK_PAIRS = 4,
   SMG_OPT_STREAM_GROUPS = 5
 };
-/* SMG_OPT_STREAM_GROUPS (default 1, at most 3): smg_sample_field, smg_sample_stats and
+/* SMG_OPT_STREAM_GROUPS (default 1, at most 2): smg_sample_field, smg_sample_stats and
  * smg_sample_batch split the components they run into this many contiguous groups (at most
  * one component per group; group i takes components [i nc / G, (i+1) nc / G)) and run each
  * group's cycles and emissions on a side stream of its own, which the hierarchy creates on
@@ -342,9 +342,10 @@ enum {
  * export), so the call stays ordered on the caller's stream.  Every output is bit-identical to
  * the one-stream run.  smg_batch_run groups its sampling items likewise (see there).  One
  * stream while kernel timing is on, in smg_sample_field_static, and in the other entry
- * points.  At most 3: a process gets four hardware queues, shared by all its streams, and two
- * groups on one queue run one after the other behind the stagger's waits (4 groups measured 27 %
- * slower than 2).  A grouped call can be captured in a graph (the side streams join the capture through
+ * points.  At most 2: a process gets four hardware queues, shared by all its streams, and two
+ * groups on one queue run one after the other behind the stagger's waits (3 groups were never
+ * faster than 2 and once 55 % slower, 4 groups 27 % slower).  A grouped call can be captured in a
+ * graph (the side streams join the capture through
  * the fork event), but its replay measured slower than that of a one-stream capture: set 1
  * before capturing. */
 /* SMG_OPT_BLOCK_PAIRS (default 1): run the eight block colours of a sweep on a Galerkin level

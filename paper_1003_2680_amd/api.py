@@ -309,7 +309,7 @@ class Hierarchy:
 
     def set_stream_groups(self, n):
         """Sampling calls run their components in n staggered groups, each on a stream of its
-        own (1, the default: the caller's stream only; at most 3); results are unchanged."""
+        own (1, the default: the caller's stream only; at most 2); results are unchanged."""
         abi.check(self.lib.smg_set_option(self._h, abi.SMG_OPT_STREAM_GROUPS, int(n)))
 
     def kernel_timing(self, enable, kernel="fine_pass"):

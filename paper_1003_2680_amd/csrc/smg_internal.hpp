@@ -14,7 +14,7 @@ namespace smg {
 
 constexpr int STENCIL = 125;  // 5x5x5 offsets of a Galerkin operator row
 constexpr int kMaxChains = 255;  // batched chains per hierarchy (at most one per component)
-constexpr int kMaxStreamGroups = 3;  // stream groups of a sampling call
+constexpr int kMaxStreamGroups = 2;  // stream groups of a sampling call
 
 struct Level {
   int nx = 0, ny = 0, nz = 0;

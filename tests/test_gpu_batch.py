@@ -79,10 +79,10 @@ def test_batch_solve_equals_alone(precision):
     assert infos[2][0] == 0 and float(u[4:6].abs().max()) == 0.0
 
 
-@pytest.mark.parametrize("groups", [1, 3])
+@pytest.mark.parametrize("groups", [1, 2])
 def test_batch_graph_replay_continues_chains(groups):
     """A captured batched call replayed K times equals K eager one-stream calls (trap check:
-    every replay compared, with eager work and synchronisation between replays); with three
+    every replay compared, with eager work and synchronisation between replays); with two
     stream groups the side streams join the capture through the fork event."""
     _announce("batch graph replay, %d stream group(s)" % groups)
     dims = (16, 16, 8)

@@ -5,8 +5,8 @@ Items differ in grid, depth, precision, chain batching and bottom handling: a on
 sampler, a batched FP32-refined sampler, a hierarchy whose small levels run one launch per pass
 (no merged bottom), a one-level hierarchy drawn exactly, and several hierarchies whose bottoms
 share a launch; sampling items run different numbers of cycles (stride, burn-in, n), also in
-two and three staggered stream groups; solve items converge after different numbers of cycles
-(different rtol).
+two staggered stream groups; solve items converge after different numbers of cycles (different
+rtol).
 """
 import pytest
 
@@ -57,7 +57,7 @@ def _items(seed_base, dtype, groups=1):
 
 
 @pytest.mark.parametrize("dtype,groups", [(torch.float64, 1), (torch.float32, 1),
-                                          (torch.float64, 2), (torch.float32, 3)])
+                                          (torch.float64, 2), (torch.float32, 2)])
 def test_batch_run_samples_equal_alone(dtype, groups):
     """groups > 1: the items' components in staggered stream groups (each group a share of
     every item, lockstep legs and merged bottoms within the group)."""

@@ -8,10 +8,9 @@ offset added to the noise keys, so every output must match bit for bit.
 * Batched chains (smg_sample_batch): the emitted fields, the observables, the running moments
   and the final state, over two calls in a row (the second continues the chains from the device
   table).  Cases: the bottom kernel with FP64 sweeps, groups that cut chains apart (5 chains of
-  2 components in 3 groups), one component per chain in 3 groups with float32 output, the
-  FP32-refined form, the bottom kernel off (every level as launches), a one-level hierarchy
-  (exact draws only), more groups than components, and one chain of three components split
-  into three groups.
+  2 components in 2 groups), one component per chain with float32 output, the FP32-refined
+  form, the bottom kernel off (every level as launches), a one-level hierarchy (exact draws
+  only), more groups than components, and one chain of three components split 1 + 2.
 * One chain (smg_sample_field, smg_sample_stats from a nonzero first cycle).
 """
 import pytest
@@ -21,14 +20,14 @@ pytestmark = pytest.mark.gpu
 
 # (dims, hierarchy keywords, chains, comps per chain, groups, bottom kernel, out dtype)
 CASES = [
-    ((64, 64, 32), dict(levels=4), 8, 3, 3, True, torch.float64),
-    ((32, 32, 16), dict(levels=3), 5, 2, 3, True, torch.float64),
-    ((32, 32, 32), dict(levels=3), 8, 1, 3, True, torch.float32),
+    ((64, 64, 32), dict(levels=4), 8, 3, 2, True, torch.float64),
+    ((32, 32, 16), dict(levels=3), 5, 2, 2, True, torch.float64),
+    ((32, 32, 32), dict(levels=3), 8, 1, 2, True, torch.float32),
     ((64, 64, 32), dict(levels=4, precision="fp32_refined"), 4, 3, 2, True, torch.float64),
-    ((32, 32, 16), dict(levels=3), 4, 2, 3, False, torch.float64),
-    ((8, 8, 4), dict(levels=1), 6, 1, 3, True, torch.float64),
-    ((16, 16, 8), dict(levels=2), 1, 2, 3, True, torch.float64),
-    ((64, 64, 32), dict(levels=4), 1, 3, 3, True, torch.float64),
+    ((32, 32, 16), dict(levels=3), 4, 2, 2, False, torch.float64),
+    ((8, 8, 4), dict(levels=1), 6, 1, 2, True, torch.float64),
+    ((16, 16, 8), dict(levels=2), 1, 1, 2, True, torch.float64),
+    ((64, 64, 32), dict(levels=4), 1, 3, 2, True, torch.float64),
 ]
 
 
@@ -79,7 +78,7 @@ def test_stream_groups_one_chain_equal_one_stream(precision):
     dims, kw = (32, 32, 16), dict(levels=3, precision=precision)
     print("[gpu-case] stream groups one chain %s" % precision, flush=True)
     res = []
-    for groups in (1, 3):
+    for groups in (1, 2):
         H = _hier(dims, kw, 3, groups)
         x, st = H.sample(4, 21, first_cycle=6)
         out = torch.empty_like(x)
@@ -96,8 +95,8 @@ def test_stream_groups_one_chain_equal_one_stream(precision):
 def test_stream_groups_option_range():
     from paper_1003_2680_amd import abi
     H = _hier((16, 16, 8), dict(levels=2), 2, 1)
-    for bad in (0, 4, -1):
+    for bad in (0, 3, -1):
         rc = H.lib.smg_set_option(H._h, abi.SMG_OPT_STREAM_GROUPS, bad)
         assert rc == abi.SMG_EINVAL
-    H.set_stream_groups(3)
+    H.set_stream_groups(2)
     H.close()
