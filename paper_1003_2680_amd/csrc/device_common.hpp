@@ -48,6 +48,19 @@ __device__ __forceinline__ Blk3 xcd_block() {
   return b;
 }
 
+// q = v / d, r = v % d for v >= 0 and a wave-uniform d > 0: a shift and a mask when d is a power
+// of two (the usual level extents), else the division.
+__device__ __forceinline__ void divmod_uniform(int v, int d, int& q, int& r) {
+  if ((d & (d - 1)) == 0) {
+    const int lg = __builtin_ctz((unsigned)d);
+    q = v >> lg;
+    r = v & (d - 1);
+  } else {
+    q = v / d;
+    r = v - q * d;
+  }
+}
+
 // Periodic index of a staged halo position: v mod n for -n <= v < 2n.  A tile that overhangs
 // a small level may stage positions further out; no cell inside the level reads them (a
 // stencil reaches at most two cells, and n >= 4), so they are clamped into range instead of

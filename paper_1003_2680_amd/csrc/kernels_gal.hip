@@ -248,7 +248,8 @@ __device__ __forceinline__ void block_pair_body(T* __restrict__ xg, const T* __r
   const int tid = threadIdx.x;
   const int k = tid & 7;
   const int nbx2 = nx >> 2;
-  const int il = (tid >> 3) % nbx2, jl = (tid >> 3) / nbx2;
+  int il, jl;
+  divmod_uniform(tid >> 3, nbx2, jl, il);
   const bool active = jl < PJ && j0 + jl < nby2;
   // rows of inactive lanes past the group's PJ rows are taken as row 0 for addressing only,
   // so that every tile read stays inside the staged rows
@@ -280,8 +281,10 @@ __device__ __forceinline__ void block_pair_body(T* __restrict__ xg, const T* __r
   for (int p = 0; p < PPT; ++p) {
     const int pos = tid + p * nthr;
     const bool in = pos < plane;
-    loff[p] = in ? (pos / nx) * RS + pos % nx : -1;
-    goff[p] = in ? wrap_near(y0 + pos / nx, ny) * nx + pos % nx : 0;
+    int py, px;
+    divmod_uniform(pos, nx, py, px);
+    loff[p] = in ? py * RS + px : -1;
+    goff[p] = in ? wrap_near(y0 + py, ny) * nx + px : 0;
   }
   T stage[TILE_D][PPT];
 #pragma unroll
