@@ -3,7 +3,9 @@
 * path parity: the first cycles of the chain (seed 0, zero start) against the oracle, every
   value of components 0 and 2, 1e-12 relative;
 * solve: relative residual recomputed on the CPU with the oracle's stencil, and the solution
-  against the exact spectral solve (error bounded by cond(A) * rtol).
+  against the exact spectral solve (error bounded by cond(A) * rtol);
+* the bench's batched launch configuration (8 chains x 3 components, two stream groups,
+  emission with observables every 2 cycles) against the oracle's chains.
 """
 import numpy as np
 import pytest
@@ -113,3 +115,42 @@ def test_fullsize_stats(hier):
     m = mom.cpu().numpy().reshape(2, 3, -1)
     assert np.max(np.abs(m[0] - s.sum(0))) <= 1e-12 * np.max(np.abs(s.sum(0)))
     assert np.max(np.abs(m[1] - (s * s).sum(0))) <= 1e-12 * np.max((s * s).sum(0))
+
+
+def test_fullsize_bench_launch_configuration():
+    """The launch configuration bench.py times: 8 chains (seeds 0..7) x 3 components batched
+    into 24 components, two staggered stream groups, one emission every 2 cycles with the
+    observables.  The emitted fields of a chain in each group (chain 1 component 0, chain 6
+    component 2) against the oracle's chain of that seed, 1e-12 relative, and their observables
+    against the oracle's observables of the emitted field."""
+    print("[gpu-case] 128^3 x 8 chains x 3 comps, two stream groups, 4 cycles", flush=True)
+    from oracle import observables as ob
+    from oracle.philox import PhiloxNoise
+    from paper_1003_2680_amd.api import Hierarchy
+    H = Hierarchy(*N3, ncomp=24, kT=1.0, levels=6, stride=2, burn_in=0)
+    H.set_stream_groups(2)
+    state = torch.zeros((24,) + tuple(reversed(N3)), dtype=torch.float64, device="cuda")
+    H.sample_batch(0, seeds=list(range(8)), comps_per_chain=3, state=state)
+    out = torch.empty((2,) + tuple(state.shape), dtype=torch.float64, device="cuda")
+    _, obs, _ = H.sample_batch(2, nchains=8, comps_per_chain=3, state=state, out=out,
+                               with_obs=True)
+    torch.cuda.synchronize()
+    mg = StochasticMG(*N3, kT=1.0, levels=6)
+    modes = ob.lowest_modes(*N3, 8)
+    zero = np.zeros(mg.levels[0].n)
+    for chain, comp in ((1, 0), (6, 2)):
+        got = out[:, 3 * chain + comp].cpu().numpy().reshape(2, -1)
+        o = obs[:, 3 * chain + comp].cpu().numpy()
+        noise = PhiloxNoise(chain)
+        x = zero.copy()
+        for cyc in range(4):
+            x = mg.vcycle(x, zero, noise, cyc, comp)
+            if cyc % 2 == 1:
+                i = cyc // 2
+                err = np.max(np.abs(got[i] - x)) / np.max(np.abs(x))
+                print("  chain %d comp %d emission %d: %.3e" % (chain, comp, i, err), flush=True)
+                assert err <= 1e-12, (chain, comp, i, err)
+                want = ob.observables(got[i], *N3, modes)
+                assert np.max(np.abs(o[i, :8] - want[:8])) <= 1e-12 * np.linalg.norm(got[i])
+                assert abs(o[i, 8] - want[8]) <= 1e-12 * want[8]
+    H.close()
