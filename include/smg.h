@@ -416,6 +416,9 @@ typedef struct {
   int32_t precision;    /* SMG_FP64, or SMG_FP32_REFINED: FP32 sweeps and transfers of the cycle in
                            the correction form, with the residual b - A x, the update of x and the
                            coarsest draw in FP64 (Alg. 1); the component entry points need FP64 */
+  int32_t row_lanes;    /* lanes per row in the block passes and residuals over long Galerkin rows:
+                           0 = by the launch's row count (2 for large launches, 8 for small), or
+                           2 or 8 for every such launch; the results agree up to summation order */
 } smg_fac_params;
 
 typedef struct {

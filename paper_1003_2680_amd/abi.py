@@ -101,7 +101,8 @@ class CompositeDesc(ctypes.Structure):
 class FACParams(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_int32), ("mu1", ctypes.c_int32), ("mu2", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("coarsest_max", ctypes.c_int32),
-                ("gs_only", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("gs_only", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("row_lanes", ctypes.c_int32)]
 
 
 class CompositeInfo(ctypes.Structure):

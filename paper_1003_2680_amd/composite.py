@@ -20,12 +20,12 @@ PRECISIONS = {"fp64": abi.SMG_FP64, "fp32_refined": abi.SMG_FP32_REFINED}
 
 
 def plan(nx, ny, nz, box, h=1.0, kT=1.0, nu=2, mu1=2, mu2=2, levels=0, coarsest_max=512,
-         gs_only=False, precision="fp64"):
+         gs_only=False, precision="fp64", row_lanes=0):
     """Host-only plan: (handle, info).  The caller destroys the handle (destroy_plan)."""
     lib = abi.load()
     desc = abi.CompositeDesc(nx, ny, nz, (ctypes.c_int32 * 6)(*box), h, kT)
     prm = abi.FACParams(nu, mu1, mu2, levels, coarsest_max, int(bool(gs_only)),
-                        PRECISIONS[precision])
+                        PRECISIONS[precision], int(row_lanes))
     hd = ctypes.c_void_p()
     abi.check(lib.smg_composite_create(ctypes.byref(desc), ctypes.byref(prm), ctypes.byref(hd)))
     info = abi.CompositeInfo()
@@ -51,7 +51,7 @@ class CompositeSampler:
     """A planned composite hierarchy bound to a device workspace."""
 
     def __init__(self, nx, ny, nz, box, h=1.0, kT=1.0, nu=2, mu1=2, mu2=2, levels=0,
-                 coarsest_max=512, gs_only=False, precision="fp64", device=None):
+                 coarsest_max=512, gs_only=False, precision="fp64", device=None, row_lanes=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no ROCm device: the composite FAC library runs only on the GPU")
@@ -62,7 +62,7 @@ class CompositeSampler:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         self._h, self.info = plan(nx, ny, nz, box, h, kT, nu, mu1, mu2, levels, coarsest_max,
-                                  gs_only, precision)
+                                  gs_only, precision, row_lanes)
         self.precision = precision
         self.base_shape = (nz, ny, nx)
         fd = self.info.fine_dims

@@ -93,6 +93,24 @@ struct GLevel {
   GStencilT<float> dev32{};
 };
 
+// Device record of stencil entry e of level L: the coefficient, the linear offset of its target
+// (valid away from the periodic seams) and the offset code with the in-block mask (bit 8 + k set
+// when the target of a cell with in-block index k lies in that cell's 2x2x2 block; on a periodic
+// axis of even extent the target's block is the cell's exactly when k_a + d_a wraps to 0 or 1).
+template <typename T>
+smg::StEntryT<T> device_entry(const GLevel& L, size_t e) {
+  const int code = L.st_code[e];
+  const int dz = code / 25 - 2, dy = (code / 5) % 5 - 2, dx = code % 5 - 2;
+  uint32_t mask = 0;
+  for (int k = 0; k < 8; ++k) {
+    const bool in = wrap((k & 1) + dx, L.nx) < 2 && wrap(((k >> 1) & 1) + dy, L.ny) < 2 &&
+                    (unsigned)((k >> 2) + dz) < 2u;
+    if (in) mask |= 1u << k;
+  }
+  return smg::StEntryT<T>{(T)L.st_val[e], dx + L.nx * (dy + L.ny * dz),
+                          (int32_t)(code | (mask << 8))};
+}
+
 // A row as a dense 5x5x5 accumulator over canonical offsets (exact zeros dropped on encoding).
 struct Acc {
   double v[125];
@@ -106,6 +124,7 @@ struct Composite {
   double h = 1.0, kT = 1.0;
   int nu = 2, mu1 = 2, mu2 = 2;
   bool gs_only = false;
+  int row_lanes = 0;  // lanes per long row (0: by launch size)
   int prec = SMG_FP64;
   std::vector<GLevel> lv;
   int ncd = 0;
@@ -676,6 +695,11 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
     return SMG_EINVAL;
   }
   C.prec = p.precision;
+  if (p.row_lanes != 0 && p.row_lanes != 2 && p.row_lanes != 8) {
+    err = "row_lanes must be 0, 2 or 8";
+    return SMG_EINVAL;
+  }
+  C.row_lanes = p.row_lanes;
   // base level plan (block smoothing needs nx, ny multiples of 4 and nz even)
   std::vector<std::array<int, 3>> dims{{g.nx, g.ny, g.nz}};
   for (;;) {
@@ -850,7 +874,7 @@ int plan(Composite& C, const smg_composite_desc& d, const smg_fac_params& p, std
     L.off_btc7 = take(L.bt_c7.size() * es);
     L.off_btdiag = take(L.bt_diag.size() * es);
     L.off_stoff = take(L.st_off.size() * 4);
-    L.off_ent = take(std::max<size_t>(1, L.st_code.size()) *
+    L.off_ent = take((L.st_code.size() + kEntryPad) *
                      (f32 ? sizeof(StEntryT<float>) : sizeof(StEntryT<double>)));
   }
   C.off_ainv = take((size_t)C.ncd * C.ncd * 8);
@@ -1186,11 +1210,11 @@ int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stre
       CMP_HIP(up(L.off_btfac, as32(L.bt_fac), L.bt_fac.size() * 4));
       CMP_HIP(up(L.off_btc7, as32(L.bt_c7), L.bt_c7.size() * 4));
       CMP_HIP(up(L.off_btdiag, as32(L.bt_diag), L.bt_diag.size() * 4));
-      keepe32.emplace_back(L.st_code.size());
+      keepe32.emplace_back(L.st_code.size() + smg::kEntryPad, smg::StEntryT<float>{});
       for (size_t e = 0; e < L.st_code.size(); ++e)
-        keepe32.back()[e] = smg::StEntryT<float>{(float)L.st_val[e], L.st_code[e]};
+        keepe32.back()[e] = device_entry<float>(L, e);
       CMP_HIP(up(L.off_ent, keepe32.back().data(),
-                 L.st_code.size() * sizeof(smg::StEntryT<float>)));
+                 keepe32.back().size() * sizeof(smg::StEntryT<float>)));
       smg::GStencilT<float>& d = L.dev32;
       d.btype = (const int32_t*)(ws + L.off_btype);
       d.bt_sid = (const int32_t*)(ws + L.off_btsid);
@@ -1203,15 +1227,17 @@ int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stre
       d.ny = L.ny;
       d.nz = L.nz;
       d.split = L.split;
+      d.row_lanes = C.row_lanes;
       continue;
     }
     CMP_HIP(up(L.off_btfac, L.bt_fac.data(), L.bt_fac.size() * 8));
 
     CMP_HIP(up(L.off_stoff, L.st_off.data(), L.st_off.size() * 4));
-    keepe64.emplace_back(L.st_code.size());
+    keepe64.emplace_back(L.st_code.size() + smg::kEntryPad, smg::StEntryT<double>{});
     for (size_t e = 0; e < L.st_code.size(); ++e)
-      keepe64.back()[e] = smg::StEntryT<double>{L.st_val[e], L.st_code[e]};
-    CMP_HIP(up(L.off_ent, keepe64.back().data(), L.st_code.size() * sizeof(smg::StEntryT<double>)));
+      keepe64.back()[e] = device_entry<double>(L, e);
+    CMP_HIP(up(L.off_ent, keepe64.back().data(),
+               keepe64.back().size() * sizeof(smg::StEntryT<double>)));
     CMP_HIP(up(L.off_btc7, L.bt_c7.data(), L.bt_c7.size() * 8));
     CMP_HIP(up(L.off_btdiag, L.bt_diag.data(), L.bt_diag.size() * 8));
     L.dev.btype = (const int32_t*)(ws + L.off_btype);
@@ -1220,6 +1246,7 @@ int smg_composite_bind(smg_composite* h, void* dev_ptr, size_t bytes, void* stre
     L.dev.st_off = (const int32_t*)(ws + L.off_stoff);
     L.dev.ent = (const smg::StEntryT<double>*)(ws + L.off_ent);
     L.dev.split = L.split;
+    L.dev.row_lanes = C.row_lanes;
     L.dev.bt_c7 = (const double*)(ws + L.off_btc7);
     L.dev.bt_diag = (const double*)(ws + L.off_btdiag);
     L.dev.nx = L.nx;

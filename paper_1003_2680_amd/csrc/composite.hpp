@@ -33,14 +33,19 @@ struct CompGeom {
 // Operator of a Galerkin base level as a dictionary of sparse stencils: every 2x2x2 block has a
 // block type, a block type names the stencil of each of its 8 cells (in-block index
 // dx + 2dy + 4dz) and carries the factors of its 8x8 diagonal block; a stencil is a list of
-// (coefficient, offset code) records, code = (dz+2)*25 + (dy+2)*5 + (dx+2), offsets periodic in
+// (coefficient, offset) records, offset code = (dz+2)*25 + (dy+2)*5 + (dx+2), offsets periodic in
 // x, y.  T: double (FP64 sweeps) or float (the inner cycle of the FP32-refined form).
 template <typename T>
-struct StEntryT {
+struct alignas(sizeof(T) == 8 ? 16 : 4) StEntryT {
   T a;           // coefficient
-  int32_t code;  // offset code
+  int32_t lin;   // dx + nx (dy + ny dz): the target's index minus the cell's, away from the seams
+  int32_t meta;  // offset code in bits 0-7; bit 8 + k: the target lies in the 2x2x2 block of a
+                 // cell with in-block index k (periodic wrap included)
 };
 using StEntry = StEntryT<double>;
+// records past the end of a level's table, so that the launches may load whole groups of eight
+// (times the lanes per row) without a bounds test
+constexpr int kEntryPad = 64;
 template <typename T>
 struct GStencilT {
   const int32_t* btype;   // [n/8]
@@ -53,9 +58,10 @@ struct GStencilT {
   const T* bt_c7;         // [types]
   const T* bt_diag;       // [types][8]
   int nx, ny, nz;
-  int split;              // lanes per row in the kernels: 1 or 8 (long rows)
+  int split;              // 8: long rows (every block by the long-row launch), else 1
+  int row_lanes;          // lanes per long row: 2 or 8, 0 = by the launch's row count
   // split == 1 levels: the blocks whose type is not plain 7-point, by block colour
-  // (list[list_off[c] .. list_off[c+1])), run by a second launch with eight lanes per row
+  // (list[list_off[c] .. list_off[c+1])), run by a second, long-row launch
   const int32_t* list;
   int list_off[9];
 };

@@ -442,39 +442,52 @@ __device__ __forceinline__ void decode(int code, int& dx, int& dy, int& dz) {
   dx = code % 5 - 2;
 }
 
-// Partial sum over the stencil entries e0 + sub, e0 + sub + S, ... of cell (cx, cy, cz):
-// r -= a_e x[target_e], skipping targets inside block (bx, by, bz) when SKIP.  Entries are read
-// as (coefficient, code) records, eight at a time with independent loads, so the latency of the
-// gathers overlaps instead of forming one chain per entry.
-template <typename T, int S, bool SKIP>
-__device__ __forceinline__ T stencil_partial(const GStencilT<T>& st, const T* __restrict__ x,
-                                             int sid, int sub, int cx, int cy, int cz, int bx,
-                                             int by, int bz, T r) {
-  const int e1 = st.st_off[sid + 1];
-  for (int e = st.st_off[sid] + sub; e < e1; e += 8 * S) {
-    T a[8], xv[8];
-    bool use[8];
+// Partial sum over the stencil entries e0 + sub, e0 + sub + S, ... of cell `cell` = (cx, cy, cz)
+// with in-block index k: r -= a_e x[target_e], skipping targets inside the cell's 2x2x2 block
+// when SKIP.  Eight (coefficient, offset) records are loaded at a time, then their eight
+// gathers, with no branch between them (the record table is padded by kEntryPad records, and a
+// slot past the row's end loads the cell itself with a zero coefficient), so the latencies
+// overlap.  AWAY: the cell is at least two cells from the periodic seams in x and y and adds the
+// record's linear offset to its index (walls never take a target out of the grid in z); else
+// the decoded offsets are wrapped.
+template <typename T, int S, bool SKIP, bool AWAY>
+__device__ __forceinline__ T stencil_run(const GStencilT<T>& st, const T* __restrict__ x, int e,
+                                         int e1, uint32_t kbit, uint32_t cell, int cx, int cy,
+                                         int cz, T r) {
+  for (; e < e1; e += 8 * S) {
+    StEntryT<T> en[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) en[q] = st.ent[e + q * S];
+    T xv[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int eq = e + q * S;
-      use[q] = eq < e1;
-      a[q] = T(0);
-      xv[q] = T(0);
-      if (use[q]) {
-        const StEntryT<T> en = st.ent[eq];
+      uint32_t tgt;
+      if (AWAY) {
+        tgt = cell + en[q].lin;
+      } else {
         int dx, dy, dz;
-        decode(en.code, dx, dy, dz);
-        const int tx = wrapm(cx + dx, st.nx), ty = wrapm(cy + dy, st.ny), tz = cz + dz;
-        if (SKIP && (tx >> 1) == bx && (ty >> 1) == by && (tz >> 1) == bz) use[q] = false;
-        a[q] = en.a;
-        xv[q] = x[tx + st.nx * (ty + st.ny * tz)];
+        decode(en[q].meta & 0xff, dx, dy, dz);
+        tgt = wrapm(cx + dx, st.nx) + st.nx * (wrapm(cy + dy, st.ny) + st.ny * (cz + dz));
       }
+      xv[q] = x[e + q * S < e1 ? tgt : cell];
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (use[q]) r = fma(-a[q], xv[q], r);
+    for (int q = 0; q < 8; ++q) {
+      const bool use = e + q * S < e1 && !(SKIP && (en[q].meta & kbit));
+      r = fma(use ? -en[q].a : T(0), xv[q], r);
+    }
   }
   return r;
+}
+
+template <typename T, int S, bool SKIP>
+__device__ __forceinline__ T stencil_partial(const GStencilT<T>& st, const T* __restrict__ x,
+                                             int sid, int sub, int k, uint32_t cell, int cx,
+                                             int cy, int cz, bool away, T r) {
+  const int e = st.st_off[sid] + sub, e1 = st.st_off[sid + 1];
+  const uint32_t kbit = 1u << (8 + k);
+  return away ? stencil_run<T, S, SKIP, true>(st, x, e, e1, kbit, cell, cx, cy, cz, r)
+              : stencil_run<T, S, SKIP, false>(st, x, e, e1, kbit, cell, cx, cy, cz, r);
 }
 
 // sum over the S consecutive lanes of a row
@@ -529,7 +542,7 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T*
   // wall neighbour loads the cell itself and is dropped)
   T xn0 = T(0), xn1 = T(0), xn2 = T(0);
   bool zin = false;
-  if (S == 1) {
+  if (MODE == 1) {
     const int tx = wrapm(cx + ((k & 1) ? 1 : -1), st.nx);
     const int ty = wrapm(cy + ((k & 2) ? 1 : -1), st.ny);
     const int tz = cz + ((k & 4) ? 1 : -1);
@@ -538,13 +551,15 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T*
     xn1 = x[cx + st.nx * (ty + st.ny * cz)];
     xn2 = x[zin ? cx + st.nx * (cy + st.ny * tz) : cell];
   }
-  const T c7 = S == 1 ? st.bt_c7[typ] : T(0);
+  const T c7 = MODE == 1 ? st.bt_c7[typ] : T(0);
   if (c7 != T(0)) {
     // plain 7-point rows: one coefficient for every off-block face neighbour
     r = fma(-c7, xn0 + xn1 + (zin ? xn2 : T(0)), r);
   } else {
     const int sid = st.bt_sid[typ * 8 + k];
-    r = row_reduce<T, S>(stencil_partial<T, S, true>(st, x, sid, sub, cx, cy, cz, bx, by, bz, r));
+    const bool away = bx >= 1 && bx + 2 <= nbx && by >= 1 && by + 2 <= nby;
+    r = row_reduce<T, S>(
+        stencil_partial<T, S, true>(st, x, sid, sub, k, cell, cx, cy, cz, away, r));
   }
   const T* F = st.bt_fac + (size_t)typ * 128;
   T v = T(0);
@@ -595,7 +610,7 @@ __global__ __launch_bounds__(TPB) void k_gresidual(T* __restrict__ r, const T* _
   if (MODE == 1 && st.bt_c7[typ] == T(0)) return;
   T v = (b && sub == 0) ? b[c] : T(0);
   T sum = T(0), xs = T(0);
-  if (S == 1) {
+  if (MODE == 1) {
     // the six neighbours and the cell, loaded before the block type resolves
     const int xm = wrapm(cx - 1, st.nx), xp = wrapm(cx + 1, st.nx);
     const int ym = wrapm(cy - 1, st.ny), yp = wrapm(cy + 1, st.ny);
@@ -608,12 +623,14 @@ __global__ __launch_bounds__(TPB) void k_gresidual(T* __restrict__ r, const T* _
           x[cx + st.nx * (yp + st.ny * cz)] + (cz > 0 ? zm : T(0)) +
           (cz + 1 < st.nz ? zp : T(0));
   }
-  const T c7 = S == 1 ? st.bt_c7[typ] : T(0);
+  const T c7 = MODE == 1 ? st.bt_c7[typ] : T(0);
   if (c7 != T(0)) {
     v = fma(-st.bt_diag[typ * 8 + k], xs, fma(-c7, sum, v));
   } else {
     const int sid = st.bt_sid[typ * 8 + k];
-    v = row_reduce<T, S>(stencil_partial<T, S, false>(st, x, sid, sub, cx, cy, cz, 0, 0, 0, v));
+    const bool away = cx >= 2 && cx + 3 <= st.nx && cy >= 2 && cy + 3 <= st.ny;
+    v = row_reduce<T, S>(
+        stencil_partial<T, S, false>(st, x, sid, sub, k, c, cx, cy, cz, away, v));
   }
   if (sub == 0) r[c] = v;
 }
@@ -770,27 +787,52 @@ hipError_t launch_comp_prolong(T* xc, T* xf, const T* y, const CompGeom& g, hipS
   return hipGetLastError();
 }
 
+// Lanes per row of the long-row launches (every block of a long-row level, the listed blocks of
+// a level of mostly plain 7-point blocks): two where the launch has enough rows to keep the chip
+// busy with short per-lane loops, else eight, trading loop length for waves in flight (measured
+// on 81- and 125-entry rows: a colour pass of 131 072 rows 20 us with two lanes against 28 us
+// with eight, one of 16 384 rows 6.8 us with eight against 13 us with two).
+constexpr int64_t kManyRowsPass = 1 << 16;
+constexpr int64_t kManyRowsResidual = 1 << 19;
+
+template <typename T, bool NOISE, int MODE>
+void launch_long_pass(T* x, const T* b, const GStencilT<T>& st, int colour, const NoiseArgs& na,
+                      int64_t rows, hipStream_t s) {
+  if (st.row_lanes == 2 || (st.row_lanes == 0 && rows >= kManyRowsPass))
+    k_gblock_pass<T, NOISE, 2, MODE><<<grid_for(rows * 2), TPB, 0, s>>>(x, b, st, colour, na);
+  else
+    k_gblock_pass<T, NOISE, 8, MODE><<<grid_for(rows * 8), TPB, 0, s>>>(x, b, st, colour, na);
+}
+
+template <typename T, int MODE>
+void launch_long_residual(T* r, const T* x, const T* b, const GStencilT<T>& st, int64_t rows,
+                          hipStream_t s) {
+  if (st.row_lanes == 2 || (st.row_lanes == 0 && rows >= kManyRowsResidual))
+    k_gresidual<T, 2, MODE><<<grid_for(rows * 2), TPB, 0, s>>>(r, x, b, st);
+  else
+    k_gresidual<T, 8, MODE><<<grid_for(rows * 8), TPB, 0, s>>>(r, x, b, st);
+}
+
 template <typename T>
 hipError_t launch_gblock_pass(T* x, const T* b, const GStencilT<T>& st, int colour, bool noise,
                               const NoiseArgs& na, hipStream_t s) {
   const int nbz = st.nz / 2;
-  const int64_t groups = (int64_t)(st.nx / 4) * (st.ny / 4) * ((nbz + 1 - (colour >> 2)) / 2) * 8;
-  if (groups <= 0) return hipSuccess;
+  // cells of the colour
+  const int64_t rows = (int64_t)(st.nx / 4) * (st.ny / 4) * ((nbz + 1 - (colour >> 2)) / 2) * 8;
+  if (rows <= 0) return hipSuccess;
   if (st.split == 8) {
-    if (noise)
-      k_gblock_pass<T, true, 8, 0><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
-    else
-      k_gblock_pass<T, false, 8, 0><<<grid_for(groups * 8), TPB, 0, s>>>(x, b, st, colour, na);
+    if (noise) launch_long_pass<T, true, 0>(x, b, st, colour, na, rows, s);
+    else launch_long_pass<T, false, 0>(x, b, st, colour, na, rows, s);
     return hipGetLastError();
   }
-  if (noise) k_gblock_pass<T, true, 1, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
-  else k_gblock_pass<T, false, 1, 1><<<grid_for(groups), TPB, 0, s>>>(x, b, st, colour, na);
+  if (noise) k_gblock_pass<T, true, 1, 1><<<grid_for(rows), TPB, 0, s>>>(x, b, st, colour, na);
+  else k_gblock_pass<T, false, 1, 1><<<grid_for(rows), TPB, 0, s>>>(x, b, st, colour, na);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t listed = (int64_t)(st.list_off[colour + 1] - st.list_off[colour]) * 64;
+  const int64_t listed = (int64_t)(st.list_off[colour + 1] - st.list_off[colour]) * 8;
   if (listed > 0) {
-    if (noise) k_gblock_pass<T, true, 8, 2><<<grid_for(listed), TPB, 0, s>>>(x, b, st, colour, na);
-    else k_gblock_pass<T, false, 8, 2><<<grid_for(listed), TPB, 0, s>>>(x, b, st, colour, na);
+    if (noise) launch_long_pass<T, true, 2>(x, b, st, colour, na, listed, s);
+    else launch_long_pass<T, false, 2>(x, b, st, colour, na, listed, s);
   }
   return hipGetLastError();
 }
@@ -799,14 +841,14 @@ template <typename T>
 hipError_t launch_gresidual(T* r, const T* x, const T* b, const GStencilT<T>& st, hipStream_t s) {
   const int64_t n = (int64_t)st.nx * st.ny * st.nz;
   if (st.split == 8) {
-    k_gresidual<T, 8, 0><<<grid_for(n * 8), TPB, 0, s>>>(r, x, b, st);
+    launch_long_residual<T, 0>(r, x, b, st, n, s);
     return hipGetLastError();
   }
   k_gresidual<T, 1, 1><<<grid_for(n), TPB, 0, s>>>(r, x, b, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t listed = (int64_t)st.list_off[8] * 64;
-  if (listed > 0) k_gresidual<T, 8, 2><<<grid_for(listed), TPB, 0, s>>>(r, x, b, st);
+  const int64_t listed = (int64_t)st.list_off[8] * 8;
+  if (listed > 0) launch_long_residual<T, 2>(r, x, b, st, listed, s);
   return hipGetLastError();
 }
 

@@ -51,3 +51,17 @@ def test_invalid_geometry_rejected(nx, ny, nz, box):
     with pytest.raises(abi.SMGError) as e:
         pc.plan(nx, ny, nz, box)
     assert e.value.code == abi.SMG_EINVAL
+
+
+@pytest.mark.parametrize("lanes", [1, 4, -1, 16])
+def test_invalid_row_lanes_rejected(lanes):
+    with pytest.raises(abi.SMGError) as e:
+        pc.plan(8, 8, 4, (2, 6, 2, 6, 0, 2), row_lanes=lanes)
+    assert e.value.code == abi.SMG_EINVAL and "row_lanes" in str(e.value)
+
+
+@pytest.mark.parametrize("lanes", [0, 2, 8])
+def test_row_lanes_accepted(lanes):
+    hd, info = pc.plan(8, 8, 4, (2, 6, 2, 6, 0, 2), row_lanes=lanes)
+    pc.destroy_plan(hd)
+    assert info.n_levels >= 1

@@ -106,6 +106,42 @@ def test_base_block_passes(setups, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("lanes", [2, 8])
+def test_row_lanes_fixed(setups, name, lanes):
+    """The long-row block passes and residuals with a fixed lane count per row (a large launch
+    takes two lanes, a small one eight): every block pass of every base level, then three
+    stochastic cycles with a right-hand side (the base residuals), against the oracle."""
+    from paper_1003_2680_amd.composite import CompositeSampler
+    st, torch = setups
+    g, fac, _ = st[name]
+    nx, ny, nz, box, cm = CASES[name]
+    print("[gpu-case] composite %s row_lanes=%d" % (name, lanes), flush=True)
+    s = CompositeSampler(nx, ny, nz, box, kT=0.9, coarsest_max=cm, row_lanes=lanes)
+    for l, L in enumerate(fac.base.levels[:-1]):
+        for colour in range(8):
+            rng = np.random.default_rng(2000 + 10 * l + colour)
+            x, b = rng.standard_normal(L.n), rng.standard_normal(L.n)
+            xd = torch.tensor(x, device="cuda")
+            bd = torch.tensor(b, device="cuda")
+            s.debug_base_pass(l, colour, xd, bd, seed=6, cycle=4, slot=1, noise=True)
+            torch.cuda.synchronize()
+            ref = x.copy()
+            fac.base._block_pass(L, ref, b, colour, _KindMap(PhiloxNoise(6)), (4, 1, 0))
+            _close(xd.cpu().numpy(), ref, np.abs(ref).max())
+    rng = np.random.default_rng(8)
+    x, b = rng.standard_normal(g.n), rng.standard_normal(g.n)
+    xc, xf = _dev(torch, g, x)
+    bc, bf = _dev(torch, g, b)
+    ref = x.copy()
+    for cyc in range(3):
+        s.cycle(xc, xf, bc, bf, seed=31, cycle=cyc, noise=True)
+        ref = fac.cycle(ref, b, PhiloxNoise(31), cyc)
+    torch.cuda.synchronize()
+    _close(_host(g, xc, xf), ref, np.abs(ref).max())
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("with_b", [False, True])
 def test_stochastic_cycles(setups, name, with_b):
     st, torch = setups
