@@ -121,6 +121,37 @@ __device__ __forceinline__ void coarse_row(const T* __restrict__ xc, const T* __
   }
 }
 
+// Rows (y, z) of the base grid more than one cell from the box in y (periodically) or in z: no
+// cell of such a row and no face neighbour of one is covered.
+__device__ __forceinline__ bool far_row(const CompGeom& g, int y, int z) {
+  const bool zn = z >= g.z0 - 1 && z <= g.z1;
+  const bool yn = (unsigned)wrapm(y - g.y0 + 1, g.ny) <= (unsigned)(g.y1 - g.y0 + 1);
+  return !(yn && zn);
+}
+
+// coarse_row for cell x of a far row (index `row` = y + ny z, rows rp, rm of y + 1, y - 1, walls
+// below / above when wlo / whi): the same loads, order and arithmetic without the cover tests.
+template <typename T>
+__device__ __forceinline__ void far_coarse_row(const T* __restrict__ xc, const CompGeom& g, int x,
+                                               int row, int rp, int rm, bool wlo, bool whi,
+                                               T& diag, T& off) {
+  const int nx = g.nx;
+  const int c = x + nx * row;
+  const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+  const int plane = nx * g.ny;
+  const T v0 = xc[xp + nx * row], v1 = xc[xm + nx * row];
+  const T v2 = xc[x + nx * rp], v3 = xc[x + nx * rm];
+  const T v4 = xc[whi ? c : c + plane], v5 = xc[wlo ? c : c - plane];
+  diag = T(4) + (whi ? T(2) : T(1)) + (wlo ? T(2) : T(1));
+  off = T(0);
+  off += v0;
+  off += v1;
+  off += v2;
+  off += v3;
+  if (!whi) off += v4;
+  if (!wlo) off += v5;
+}
+
 // Row of fine cell (i,j,k) (box coordinates) in units of 1/h^2, loads first as above: the six
 // neighbours inside the box (an outside neighbour loads the cell itself), then the faces on the
 // box boundary (walls, or coarse-fine faces, only on the interface layer).
@@ -206,6 +237,31 @@ __global__ __launch_bounds__(TPB) void k_comp_coarse_pass(T* __restrict__ xc,
   if (2 * t >= (uint32_t)hx * g.ny * g.nz) return;  // hx ny nz is even (ny is)
   T z[2] = {T(0), T(0)};
   if (NOISE) normal_pair_t<T>(na, na.sid, 0u, t, z[0], z[1]);
+  if ((hx & 1) == 0) {
+    // both sites in one row; a far row (the bulk of the grid) skips every cover test
+    int row, jx, y, zz;
+    divmod_uniform((int)(2 * t), hx, row, jx);
+    divmod_uniform(row, g.ny, zz, y);
+    if (far_row(g, y, zz)) {
+      const int rp = y + 1 == g.ny ? row + 1 - g.ny : row + 1;
+      const int rm = y == 0 ? row - 1 + g.ny : row - 1;
+      const bool wlo = zz == 0, whi = zz == g.nz - 1;
+      const int x0 = 2 * jx + ((y + zz + colour) & 1);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int x = x0 + 2 * q;
+        T diag, off;
+        far_coarse_row<T>(xc, g, x, row, rp, rm, wlo, whi, diag, off);
+        const uint32_t cell = x + g.nx * row;
+        const T ih2 = (T)g.ih2;
+        const T ra = rsqrt_refined<T>(diag * ih2);
+        T v = ((bc ? bc[cell] : T(0)) + off * ih2) * (ra * ra);
+        if (NOISE) v = fma((T)na.sqkT * ra, z[q], v);
+        xc[cell] = v;
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const uint32_t h = 2 * t + q;
@@ -286,15 +342,19 @@ __global__ __launch_bounds__(TPB) void k_comp_res_coarse(T* __restrict__ rc,
                                                          const T* __restrict__ bc, CompGeom g) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)g.nx * g.ny * g.nz) return;
-  const int x = t % g.nx;
-  const int row = t / g.nx;
-  const int y = row % g.ny, z = row / g.ny;
-  if (covered(g, x, y, z)) {
+  int x, row, y, z;
+  divmod_uniform((int)t, g.nx, row, x);
+  divmod_uniform(row, g.ny, z, y);
+  T diag, off;
+  if (far_row(g, y, z)) {
+    far_coarse_row<T>(xc, g, x, row, y + 1 == g.ny ? row + 1 - g.ny : row + 1,
+                      y == 0 ? row - 1 + g.ny : row - 1, z == 0, z == g.nz - 1, diag, off);
+  } else if (covered(g, x, y, z)) {
     rc[t] = T(0);
     return;
+  } else {
+    coarse_row<T>(xc, xf, g, x, y, z, diag, off);
   }
-  T diag, off;
-  coarse_row<T>(xc, xf, g, x, y, z, diag, off);
   rc[t] = (bc ? bc[t] : T(0)) - (diag * xc[t] - off) * (T)g.ih2;
 }
 
@@ -349,9 +409,18 @@ __global__ __launch_bounds__(TPB) void k_comp_restrict(T* __restrict__ b0, T* __
                                                        const T* __restrict__ bc, CompGeom g) {
   const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   if (t >= (uint32_t)g.nx * g.ny * g.nz) return;
-  const int X = t % g.nx;
-  const int row = t / g.nx;
-  const int Y = row % g.ny, Z = row / g.ny;
+  int X, row, Y, Z;
+  divmod_uniform((int)t, g.nx, row, X);
+  divmod_uniform(row, g.ny, Z, Y);
+  if (!rc && far_row(g, Y, Z)) {
+    // no fine cell restricts onto a far row: the coarse residual alone
+    T diag, off;
+    far_coarse_row<T>(xc, g, X, row, Y + 1 == g.ny ? row + 1 - g.ny : row + 1,
+                      Y == 0 ? row - 1 + g.ny : row - 1, Z == 0, Z == g.nz - 1, diag, off);
+    b0[t] = (bc ? bc[t] : T(0)) - (diag * xc[t] - off) * (T)g.ih2;
+    x0[t] = T(0);
+    return;
+  }
   T v;
   if (rc) {
     v = rc[t];
