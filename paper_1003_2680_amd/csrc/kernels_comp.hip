@@ -574,13 +574,13 @@ __device__ __forceinline__ T row_reduce(T r) {
 // MODE 0: every block of the colour; MODE 1: the plain 7-point blocks of the colour only (the
 // others are left to MODE 2); MODE 2: the listed blocks of the colour.
 template <typename T, bool NOISE, int S, int MODE>
-__global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T* __restrict__ b,
-                                                     GStencilT<T> st, int colour, NoiseArgs na) {
+__device__ __forceinline__ void gblock_body(T* __restrict__ x, const T* __restrict__ b,
+                                            const GStencilT<T>& st, int colour,
+                                            const NoiseArgs& na, uint32_t t) {
   const int nbx = st.nx >> 1, nby = st.ny >> 1, nbz = st.nz >> 1;
   const int hbx = nbx >> 1, hby = nby >> 1;
   const int pz = colour >> 2;
   const int nbzc = (nbz + 1 - pz) >> 1;
-  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
   // the total is a multiple of 8*S and so is TPB: a block's group of lanes is active as a whole
   const uint32_t nblocks = MODE == 2 ? (uint32_t)(st.list_off[colour + 1] - st.list_off[colour])
                                      : (uint32_t)hbx * hby * nbzc;
@@ -646,12 +646,34 @@ __global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T*
   if (sub == 0) x[cell] = v;
 }
 
+template <typename T, bool NOISE, int S, int MODE>
+__global__ __launch_bounds__(TPB) void k_gblock_pass(T* __restrict__ x, const T* __restrict__ b,
+                                                     GStencilT<T> st, int colour, NoiseArgs na) {
+  gblock_body<T, NOISE, S, MODE>(x, b, st, colour, na, blockIdx.x * TPB + threadIdx.x);
+}
+
+// MODE 2 and MODE 1 of one colour in one launch (the two touch disjoint blocks of the colour and
+// read only the other colours): the first `listed_wg` work-groups take the listed blocks with S
+// lanes per row, the rest every block of the colour with one lane per row.  The long-row groups
+// come first so that their longer chains of gathers overlap the plain blocks.
+template <typename T, bool NOISE, int S>
+__global__ __launch_bounds__(TPB) void k_gblock_pass_mixed(T* __restrict__ x,
+                                                           const T* __restrict__ b,
+                                                           GStencilT<T> st, int colour,
+                                                           NoiseArgs na, uint32_t listed_wg) {
+  if (blockIdx.x < listed_wg)
+    gblock_body<T, NOISE, S, 2>(x, b, st, colour, na, blockIdx.x * TPB + threadIdx.x);
+  else
+    gblock_body<T, NOISE, 1, 1>(x, b, st, colour, na,
+                                (blockIdx.x - listed_wg) * TPB + threadIdx.x);
+}
+
 // MODE 0: every cell with S lanes per row; MODE 1: the cells of plain 7-point blocks only;
 // MODE 2: the cells of the listed blocks (all colours), eight lanes per row.
 template <typename T, int S, int MODE>
-__global__ __launch_bounds__(TPB) void k_gresidual(T* __restrict__ r, const T* __restrict__ x,
-                                                   const T* __restrict__ b, GStencilT<T> st) {
-  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+__device__ __forceinline__ void gresidual_body(T* __restrict__ r, const T* __restrict__ x,
+                                               const T* __restrict__ b, const GStencilT<T>& st,
+                                               uint32_t t) {
   const int sub = t % S;
   uint32_t c, blk;
   int cx, cy, cz, k;
@@ -702,6 +724,24 @@ __global__ __launch_bounds__(TPB) void k_gresidual(T* __restrict__ r, const T* _
         stencil_partial<T, S, false>(st, x, sid, sub, k, c, cx, cy, cz, away, v));
   }
   if (sub == 0) r[c] = v;
+}
+
+template <typename T, int S, int MODE>
+__global__ __launch_bounds__(TPB) void k_gresidual(T* __restrict__ r, const T* __restrict__ x,
+                                                   const T* __restrict__ b, GStencilT<T> st) {
+  gresidual_body<T, S, MODE>(r, x, b, st, blockIdx.x * TPB + threadIdx.x);
+}
+
+// MODE 2 and MODE 1 in one launch, as k_gblock_pass_mixed
+template <typename T, int S>
+__global__ __launch_bounds__(TPB) void k_gresidual_mixed(T* __restrict__ r,
+                                                         const T* __restrict__ x,
+                                                         const T* __restrict__ b, GStencilT<T> st,
+                                                         uint32_t listed_wg) {
+  if (blockIdx.x < listed_wg)
+    gresidual_body<T, S, 2>(r, x, b, st, blockIdx.x * TPB + threadIdx.x);
+  else
+    gresidual_body<T, 1, 1>(r, x, b, st, (blockIdx.x - listed_wg) * TPB + threadIdx.x);
 }
 
 // Coarsest base level: z = the n normals of the level's stream (call j/2, first or second of the
@@ -864,10 +904,15 @@ hipError_t launch_comp_prolong(T* xc, T* xf, const T* y, const CompGeom& g, hipS
 constexpr int64_t kManyRowsPass = 1 << 16;
 constexpr int64_t kManyRowsResidual = 1 << 19;
 
+template <typename T>
+bool two_lanes(const GStencilT<T>& st, int64_t rows, int64_t many) {
+  return st.row_lanes == 2 || (st.row_lanes == 0 && rows >= many);
+}
+
 template <typename T, bool NOISE, int MODE>
 void launch_long_pass(T* x, const T* b, const GStencilT<T>& st, int colour, const NoiseArgs& na,
                       int64_t rows, hipStream_t s) {
-  if (st.row_lanes == 2 || (st.row_lanes == 0 && rows >= kManyRowsPass))
+  if (two_lanes(st, rows, kManyRowsPass))
     k_gblock_pass<T, NOISE, 2, MODE><<<grid_for(rows * 2), TPB, 0, s>>>(x, b, st, colour, na);
   else
     k_gblock_pass<T, NOISE, 8, MODE><<<grid_for(rows * 8), TPB, 0, s>>>(x, b, st, colour, na);
@@ -876,7 +921,7 @@ void launch_long_pass(T* x, const T* b, const GStencilT<T>& st, int colour, cons
 template <typename T, int MODE>
 void launch_long_residual(T* r, const T* x, const T* b, const GStencilT<T>& st, int64_t rows,
                           hipStream_t s) {
-  if (st.row_lanes == 2 || (st.row_lanes == 0 && rows >= kManyRowsResidual))
+  if (two_lanes(st, rows, kManyRowsResidual))
     k_gresidual<T, 2, MODE><<<grid_for(rows * 2), TPB, 0, s>>>(r, x, b, st);
   else
     k_gresidual<T, 8, MODE><<<grid_for(rows * 8), TPB, 0, s>>>(r, x, b, st);
@@ -894,14 +939,26 @@ hipError_t launch_gblock_pass(T* x, const T* b, const GStencilT<T>& st, int colo
     else launch_long_pass<T, false, 0>(x, b, st, colour, na, rows, s);
     return hipGetLastError();
   }
-  if (noise) k_gblock_pass<T, true, 1, 1><<<grid_for(rows), TPB, 0, s>>>(x, b, st, colour, na);
-  else k_gblock_pass<T, false, 1, 1><<<grid_for(rows), TPB, 0, s>>>(x, b, st, colour, na);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   const int64_t listed = (int64_t)(st.list_off[colour + 1] - st.list_off[colour]) * 8;
-  if (listed > 0) {
-    if (noise) launch_long_pass<T, true, 2>(x, b, st, colour, na, listed, s);
-    else launch_long_pass<T, false, 2>(x, b, st, colour, na, listed, s);
+  if (listed == 0) {
+    if (noise) k_gblock_pass<T, true, 1, 1><<<grid_for(rows), TPB, 0, s>>>(x, b, st, colour, na);
+    else k_gblock_pass<T, false, 1, 1><<<grid_for(rows), TPB, 0, s>>>(x, b, st, colour, na);
+    return hipGetLastError();
+  }
+  // the listed (long-row) blocks and the plain blocks of the colour in one launch
+  const bool two = two_lanes(st, listed, kManyRowsPass);
+  const uint32_t lw = grid_for(listed * (two ? 2 : 8));
+  const uint32_t grid = lw + grid_for(rows);
+  if (two) {
+    if (noise)
+      k_gblock_pass_mixed<T, true, 2><<<grid, TPB, 0, s>>>(x, b, st, colour, na, lw);
+    else
+      k_gblock_pass_mixed<T, false, 2><<<grid, TPB, 0, s>>>(x, b, st, colour, na, lw);
+  } else {
+    if (noise)
+      k_gblock_pass_mixed<T, true, 8><<<grid, TPB, 0, s>>>(x, b, st, colour, na, lw);
+    else
+      k_gblock_pass_mixed<T, false, 8><<<grid, TPB, 0, s>>>(x, b, st, colour, na, lw);
   }
   return hipGetLastError();
 }
@@ -913,11 +970,18 @@ hipError_t launch_gresidual(T* r, const T* x, const T* b, const GStencilT<T>& st
     launch_long_residual<T, 0>(r, x, b, st, n, s);
     return hipGetLastError();
   }
-  k_gresidual<T, 1, 1><<<grid_for(n), TPB, 0, s>>>(r, x, b, st);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   const int64_t listed = (int64_t)st.list_off[8] * 8;
-  if (listed > 0) launch_long_residual<T, 2>(r, x, b, st, listed, s);
+  if (listed == 0) {
+    k_gresidual<T, 1, 1><<<grid_for(n), TPB, 0, s>>>(r, x, b, st);
+    return hipGetLastError();
+  }
+  if (two_lanes(st, listed, kManyRowsResidual)) {
+    const uint32_t lw = grid_for(listed * 2);
+    k_gresidual_mixed<T, 2><<<lw + grid_for(n), TPB, 0, s>>>(r, x, b, st, lw);
+  } else {
+    const uint32_t lw = grid_for(listed * 8);
+    k_gresidual_mixed<T, 8><<<lw + grid_for(n), TPB, 0, s>>>(r, x, b, st, lw);
+  }
   return hipGetLastError();
 }
 
