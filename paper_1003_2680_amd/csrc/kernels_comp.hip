@@ -549,6 +549,48 @@ __device__ __forceinline__ T stencil_run(const GStencilT<T>& st, const T* __rest
   return r;
 }
 
+// stencil_run for a wave whose cells all take row `sid` and lie away from the seams (no skip):
+// the row's records are wave-uniform and come through scalar loads, each lane picking the one of
+// its sub-lane, so a lane issues only its gathers; same entries, order and arithmetic.
+// a value equal on every lane of the wave, marked as such (kept in scalar registers)
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <typename T, int S>
+__device__ __forceinline__ T stencil_uniform(const GStencilT<T>& st, const T* __restrict__ x,
+                                             int sid, int sub, uint32_t cell, T r) {
+  const int e1 = wave_uniform(st.st_off[sid + 1]);
+  for (int e = wave_uniform(st.st_off[sid]); e < e1; e += 8 * S) {
+    T a[8], xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      T aq = wave_uniform(st.ent[e + q * S].a);
+      int lq = wave_uniform(st.ent[e + q * S].lin);
+#pragma unroll
+      for (int j = 1; j < S; ++j) {
+        const T aj = wave_uniform(st.ent[e + q * S + j].a);
+        const int lj = wave_uniform(st.ent[e + q * S + j].lin);
+        aq = sub == j ? aj : aq;
+        lq = sub == j ? lj : lq;
+      }
+      const bool in = e + q * S + sub < e1;
+      a[q] = in ? -aq : T(0);
+      xv[q] = x[in ? cell + lq : cell];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r = fma(a[q], xv[q], r);
+  }
+  return r;
+}
+
 template <typename T, int S, bool SKIP>
 __device__ __forceinline__ T stencil_partial(const GStencilT<T>& st, const T* __restrict__ x,
                                              int sid, int sub, int k, uint32_t cell, int cx,
@@ -720,8 +762,12 @@ __device__ __forceinline__ void gresidual_body(T* __restrict__ r, const T* __res
   } else {
     const int sid = st.bt_sid[typ * 8 + k];
     const bool away = cx >= 2 && cx + 3 <= st.nx && cy >= 2 && cy + 3 <= st.ny;
-    v = row_reduce<T, S>(
-        stencil_partial<T, S, false>(st, x, sid, sub, k, c, cx, cy, cz, away, v));
+    const int sid0 = __builtin_amdgcn_readfirstlane(sid);
+    if (MODE == 0 && S == 2 && __all(sid == sid0 && away))
+      v = row_reduce<T, S>(stencil_uniform<T, S>(st, x, sid0, sub, c, v));
+    else
+      v = row_reduce<T, S>(
+          stencil_partial<T, S, false>(st, x, sid, sub, k, c, cx, cy, cz, away, v));
   }
   if (sub == 0) r[c] = v;
 }

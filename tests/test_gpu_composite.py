@@ -193,3 +193,34 @@ def test_solve(setups, name):
         ref2 = fac.cycle(ref2, f)
     torch.cuda.synchronize()
     _close(_host(g, xc, xf), ref2, np.abs(ref2).max())
+
+
+def test_wide_levels_two_lanes_agree_with_eight():
+    """A base grid 256 cells wide, so that its Galerkin levels hold whole waves of cells away
+    from the periodic seams with one shared row (the residual then reads the row's records as
+    wave-uniform values): three stochastic cycles with a right-hand side with two lanes per
+    long row against eight lanes per long row (the form the oracle parity above pins), equal up
+    to summation order."""
+    import torch
+    from paper_1003_2680_amd.composite import CompositeSampler
+    base, box = (256, 256, 8), (100, 140, 96, 136, 0, 4)
+    print("[gpu-case] composite wide levels %s box %s" % (base, box), flush=True)
+    res = []
+    for lanes in (2, 8):
+        s = CompositeSampler(*base, box, kT=0.9, coarsest_max=512, row_lanes=lanes)
+        assert s.info.n_levels >= 3 and s.info.dims[1][0] == 128
+        rng = np.random.default_rng(12)
+        xc = torch.tensor(rng.standard_normal(s.base_shape), device="cuda")
+        xf = torch.tensor(rng.standard_normal(s.fine_shape), device="cuda")
+        bc = torch.tensor(rng.standard_normal(s.base_shape), device="cuda")
+        bf = torch.tensor(rng.standard_normal(s.fine_shape), device="cuda")
+        for cyc in range(3):
+            s.cycle(xc, xf, bc, bf, seed=17, cycle=cyc, noise=True)
+        torch.cuda.synchronize()
+        cov = torch.zeros(s.base_shape, dtype=torch.bool, device="cuda")
+        cov[box[4]:box[5], box[2]:box[3], box[0]:box[1]] = True
+        res.append((xc.masked_fill(cov, 0).cpu().numpy(), xf.cpu().numpy()))
+        s.close()
+    for a, b in zip(*res):
+        assert np.isfinite(a).all()
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
