@@ -27,7 +27,7 @@ struct ChainKey {
   uint32_t c0, c1;   // first cycle low / high
 };
 
-// Polynomial coefficients of the FP64 Box-Muller (see log_unit and sincospi_turns).  They
+// Polynomial coefficients of the FP64 Box-Muller (see neg2_log_unit and sincospi_turns).  They
 // travel in the kernel arguments so that a wave reads them with scalar loads and the FMAs take
 // them as scalar operands, instead of materialising every 64-bit literal in vector registers.
 struct BoxMullerCoef {
@@ -38,19 +38,29 @@ struct BoxMullerCoef {
   double csq[8];  // (-1)^k pi^(2k)/(2k)!, k = 8 .. 1
 };
 
-// sum_{i < n} c[n-1-i] z^i, lowest power first with the powers formed on the way.  Each term
-// is one FMA whose coefficient is the scalar multiplicand (a nested Horner step would need
-// every coefficient copied into vector registers as the addend).  The series here converge
-// fast (z <= 1/16), so the order of summation costs nothing in accuracy.
+// a z + c and a + c with c wave-uniform (a kernel argument held in scalar registers), written
+// in the three-operand encodings, which read the scalar pair directly.  Left to itself the
+// compiler picks the two-operand accumulate form, whose addend must sit in vector registers,
+// and copies every coefficient there first (two moves per coefficient and lane).
+__device__ __forceinline__ double fma_uniform_addend(double a, double z, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(z), "s"(c));
+  return r;
+}
+__device__ __forceinline__ double add_uniform(double a, double c) {
+  double r;
+  asm("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(c));
+  return r;
+}
+
+// sum_{i < n} c[n-1-i] z^i by Horner's rule, the coefficients entering as scalar addends:
+// n vector instructions for n coefficients.  The series here converge fast (z <= 1/16), so the
+// nested order is as accurate as any.
 template <int n>
-__device__ __forceinline__ double poly_scalar_coef(const double (&c)[n], double z) {
-  double acc = c[n - 1];
-  double zp = z;
+__device__ __forceinline__ double poly_horner(const double (&c)[n], double z) {
+  double acc = add_uniform(c[0] * z, c[1]);
 #pragma unroll
-  for (int i = 1; i < n; ++i) {
-    acc = fma(c[n - 1 - i], zp, acc);
-    if (i + 1 < n) zp *= z;
-  }
+  for (int i = 2; i < n; ++i) acc = fma_uniform_addend(acc, z, c[i]);
   return acc;
 }
 
@@ -155,12 +165,14 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
   return fma((double)a, 0x1p-32, lo);
 }
 
-// ln(u) for u in (0, 1], FP64, within a few ulp.  u = m 2^e with m in [sqrt(1/2), sqrt(2));
-// ln m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, summed as the odd Taylor series
-// 2 s (1 + s^2/3 + s^4/5 + ... + s^18/19) (the first omitted term is below 2^-55 of the sum);
-// the quotient comes from the hardware reciprocal refined by two Newton steps and a residual
-// correction; e ln 2 is added with ln 2 split so that e * ln2_hi is exact.
-__device__ __forceinline__ double log_unit(double u, const BoxMullerCoef& c) {
+// -2 ln(u) for u in (0, 1], FP64, within a few ulp (the radius of Box-Muller before its square
+// root).  u = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s), s = (m - 1)/(m + 1),
+// |s| <= 0.1716, summed as the odd Taylor series 2 s (1 + s^2/3 + s^4/5 + ... + s^18/19) (the
+// first omitted term is below 2^-55 of the sum); the quotient comes from the hardware
+// reciprocal refined by two Newton steps and a residual correction; e ln 2 is added with ln 2
+// split so that e * ln2_hi is exact.  The factor -2 is folded into 2 s and the two parts of
+// ln 2 (exact scalings), so the result is -2 times the rounded logarithm, bit for bit.
+__device__ __forceinline__ double neg2_log_unit(double u, const BoxMullerCoef& c) {
   int e;
   double m = frexp(u, &e);  // m in [1/2, 1)
   if (m < 0.70710678118654752440) {
@@ -175,11 +187,11 @@ __device__ __forceinline__ double log_unit(double u, const BoxMullerCoef& c) {
   double s = f * r;
   s = fma(fma(-d, s, f), r, s);
   const double z = s * s;
-  const double p = poly_scalar_coef(c.lg, z);
-  const double s2 = 2.0 * s;
+  const double p = poly_horner(c.lg, z);
+  const double s2 = -4.0 * s;
   const double lm = fma(s2 * z, p, s2);
-  constexpr double LN2_HI = 0x1.62e42fef00000p-1;  // ln 2 with the low 20 bits cleared
-  constexpr double LN2_LO = 0x1.473de6af278edp-34; // ln 2 - LN2_HI
+  constexpr double LN2_HI = -0x1.62e42fef00000p+0;  // -2 ln 2 with the low 20 bits cleared
+  constexpr double LN2_LO = -0x1.473de6af278edp-33; // -2 ln 2 - LN2_HI
   return fma((double)e, LN2_HI, fma((double)e, LN2_LO, lm));
 }
 
@@ -209,8 +221,8 @@ __device__ __forceinline__ void sincospi_quarter(double t, const BoxMullerCoef& 
   const double n = rint(2.0 * t);
   const double r = fma(-0.5, n, t);
   const double z = r * r;
-  const double S = r * poly_scalar_coef(c.snq, z);
-  const double C = fma(poly_scalar_coef(c.csq, z), z, 1.0);
+  const double S = r * poly_horner(c.snq, z);
+  const double C = fma(poly_horner(c.csq, z), z, 1.0);
   const int q = (int)n & 3;
   const double a = (q & 1) ? C : S;  // sin(pi (r + n/2))
   const double b = (q & 1) ? S : C;  // cos(pi (r + n/2))
@@ -259,7 +271,7 @@ __device__ __forceinline__ void normal_start(const NoiseArgs& na, uint32_t sid, 
 __device__ __forceinline__ void normal_finish(const NoiseArgs& na, const PendingNormals& p,
                                               double& z0, double& z1) {
   const BoxMullerCoef& c = na.bm;
-  const double rad = sqrt_bm(-2.0 * log_unit(p.u1, c));
+  const double rad = sqrt_bm(neg2_log_unit(p.u1, c));
   const double z = p.r * p.r;
   const double S = p.r * fma(z, fma(z, fma(z, c.sn[3], c.sn[2]), c.sn[1]), c.sn[0]);
   const double C = fma(z, fma(z, fma(z, c.cs[2], c.cs[1]), c.cs[0]), 1.0);
@@ -283,7 +295,7 @@ __device__ __forceinline__ void normal_pair_notable(const NoiseArgs& na, uint32_
   uint32_t w0 = call, w1, w2, w3, k0, k1;
   noise_key(na, sid, comp, k0, k1, w1, w2, w3);
   philox4x32_10(w0, w1, w2, w3, k0, k1);
-  const double rad = sqrt_bm(-2.0 * log_unit(uniform53(w0, w1), na.bm));
+  const double rad = sqrt_bm(neg2_log_unit(uniform53(w0, w1), na.bm));
   double s, c;
   sincospi_quarter(2.0 * uniform53(w2, w3), na.bm, s, c);
   z0 = rad * c;
