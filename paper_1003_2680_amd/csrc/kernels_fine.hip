@@ -585,10 +585,17 @@ __global__ __launch_bounds__(TPB) void k_refine_residual_vec(float* __restrict__
                                                               int lg_ny, double inv_h2,
                                                               size_t half) {
   constexpr uint32_t S = 2;
-  const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+  // Work-group order: the two colours of a tile run one after the other and, by the XCD-aware
+  // numbering, on one XCD, so the rows that one colour reads as neighbours and the other as
+  // its own sites come from HBM once and from that XCD's L2 the second time
+  const uint32_t nb = gridDim.x, ncw = gridDim.y;
+  uint32_t lin = blockIdx.x + nb * (blockIdx.y + ncw * blockIdx.z);
+  const uint32_t per = (2 * nb * ncw) / kXcds;
+  if (lin < per * kXcds) lin = (lin % kXcds) * per + lin / kXcds;
+  const int colour = (int)(lin & 1u);
+  const uint32_t comp = (lin >> 1) / nb;
+  const uint32_t t = ((lin >> 1) - comp * nb) * TPB + threadIdx.x;
   if (t >= nthreads) return;
-  const uint32_t comp = blockIdx.y;
-  const int colour = blockIdx.z;
   const uint32_t nht = (uint32_t)nh / S;
   uint32_t row, jt, z, y;
   if (lg_nht >= 0) {
