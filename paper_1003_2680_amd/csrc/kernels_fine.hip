@@ -82,6 +82,12 @@ __device__ __forceinline__ void rb_pass_vec_body(T* __restrict__ xc, const T* __
                                                  uint32_t comp) {
   using V = typename Vec16<T>::type;
   constexpr uint32_t W = sizeof(T), S = 16 / W;
+  // FP64 with noise: a new wave issues its addressing and loads at raised priority, ahead of the
+  // resident waves' noise arithmetic, so its memory latency starts as early as possible (few
+  // waves are resident per SIMD and each waits on its loads for much of its life); it drops to
+  // the normal priority for its own noise.  The FP32 pass, bound by memory, gains nothing.
+  constexpr bool PRIO = NOISE && sizeof(T) == 8;
+  if (PRIO) __builtin_amdgcn_s_setprio(3);
   const uint32_t t = blk * TPB + threadIdx.x;
   if (t >= nthreads) return;
   const uint32_t nht = (uint32_t)nh / S;
@@ -143,6 +149,7 @@ __device__ __forceinline__ void rb_pass_vec_body(T* __restrict__ xc, const T* __
   for (uint32_t k = 0; k < S; ++k) zn[k] = T(0);
   if (NOISE) {
     __builtin_amdgcn_sched_barrier(0);
+    if (PRIO) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (uint32_t p = 0; p < S / 2; ++p)
       level0_normals<T>(na, comp, (S / 2) * t + p, zn[2 * p], zn[2 * p + 1]);
