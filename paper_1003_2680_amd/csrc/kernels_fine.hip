@@ -83,9 +83,9 @@ __device__ __forceinline__ void rb_pass_vec_body(T* __restrict__ xc, const T* __
   using V = typename Vec16<T>::type;
   constexpr uint32_t W = sizeof(T), S = 16 / W;
   // FP64 with noise: a new wave issues its addressing and loads at raised priority, ahead of the
-  // resident waves' noise arithmetic, so its memory latency starts as early as possible (few
-  // waves are resident per SIMD and each waits on its loads for much of its life); it drops to
-  // the normal priority for its own noise.  The FP32 pass, bound by memory, gains nothing.
+  // resident waves' noise arithmetic, so its memory latency starts as early as possible (each
+  // wave waits on its loads for much of its life); it drops to the normal priority for its own
+  // noise.  The FP32 pass, bound by memory, gains nothing.
   constexpr bool PRIO = NOISE && sizeof(T) == 8;
   if (PRIO) __builtin_amdgcn_s_setprio(3);
   const uint32_t t = blk * TPB + threadIdx.x;
