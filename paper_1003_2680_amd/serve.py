@@ -16,6 +16,8 @@
   its queue meanwhile.
 * Admission runs on the server's own thread: submitting a request only queues it, so the
   thread that receives requests never waits for a plan, an upload, an eviction or the device.
+  The admission thread sizes a new shape's pool (host planning) outside the server's lock, so
+  a submission does not wait for that either.
   A solve's right-hand side may come as a generator (`make_f`) that the pool calls on its own
   stream.
 
@@ -254,22 +256,35 @@ class Server:
             self.admit_cv.notify()
 
     def _admit_loop(self):
-        with self.lock:
-            while not self._stop:
+        while True:
+            with self.lock:
+                if self._stop:
+                    return
+                unplanned = {r.dims for r in self.waiting if r.dims not in self._bytes}
+            # host planning of new shapes outside the lock, so a submission never waits for it
+            for dims in unplanned:
+                self.pool_bytes(dims)
+            with self.lock:
+                if self._stop:
+                    return
                 if self.waiting:
                     self._dispatch()
-                # woken by a submission or a completion (a pool may have gone idle)
+                # woken by a submission; polls while requests wait (a pool may go idle, a
+                # shape may still need planning)
                 self.admit_cv.wait(0.002 if self.waiting else None)
 
     def _dispatch(self):
         """Route waiting requests to pools, creating pools inside the budget (lock held, on
-        the admission thread)."""
+        the admission thread; shapes not yet planned wait for the next pass)."""
         keep = collections.deque()
         while self.waiting:
             req = self.waiting.popleft()
             pool = self.pools.get(req.dims)
             if pool is None:
-                need = self.pool_bytes(req.dims)
+                need = self._bytes.get(req.dims)
+                if need is None:            # planned outside the lock on the next pass
+                    keep.append(req)
+                    continue
                 if need > self.budget:
                     req.error = "request does not fit the HBM budget"
                     self._complete(req)

@@ -87,3 +87,30 @@ def test_admission_eviction_and_completion(monkeypatch):
     assert reqs[30].error is not None
     assert srv.evictions >= 1
     assert max(sum(sizes[d] for d in srv.pools) for _ in [0]) <= 520
+
+
+def test_paced_submissions_never_wait_for_planning(monkeypatch):
+    """Requests submitted one by one while new shapes are being planned (0.1 s each, on the
+    admission thread): no submission waits for the planning."""
+    sizes = {(16, 16, 8): 100, (32, 32, 8): 100, (16, 16, 16): 100, (8, 8, 8): 100}
+    def slow_plan(dims, slots, prec):
+        time.sleep(0.1)
+        return sizes[dims]
+    monkeypatch.setattr(serve, "pool_bytes", slow_plan)
+    monkeypatch.setattr(serve, "Pool", FakePool)
+    srv = serve.Server(budget_bytes=10 ** 6, slots=4, stride=2, precision="fp32_refined",
+                       device=torch.device("cuda", 0))
+    shapes = list(sizes)
+    reqs = [serve.Request(i, shapes[i % 4], "sample", seed=i) for i in range(24)]
+    worst = 0.0
+    for r in reqs:
+        t = time.perf_counter()
+        srv.submit(r)
+        worst = max(worst, time.perf_counter() - t)
+        time.sleep(0.01)
+    assert srv.wait(len(reqs), timeout=20.0)
+    srv.shutdown()
+    assert worst < 0.05, worst
+    assert len({r.rid for r in srv.done}) == len(reqs)
+    assert all(r.result == ("done", r.dims) for r in reqs)
+
