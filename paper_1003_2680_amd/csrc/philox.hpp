@@ -165,12 +165,20 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
   return fma((double)a, 0x1p-32, lo);
 }
 
+// 2 uniform53(a, b), formed with the doubled (exact) scalings: the same rounding, one operation
+// fewer
+__device__ __forceinline__ double uniform53_x2(uint32_t a, uint32_t b) {
+  const double lo = fma((double)(b >> 11), 0x1p-52, 0x1p-53);
+  return fma((double)a, 0x1p-31, lo);
+}
+
 // -2 ln(u) for u in (0, 1], FP64, within a few ulp (the radius of Box-Muller before its square
 // root).  u = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s), s = (m - 1)/(m + 1),
 // |s| <= 0.1716, summed as the odd Taylor series 2 s (1 + s^2/3 + s^4/5 + ... + s^18/19) (the
 // first omitted term is below 2^-55 of the sum); the quotient comes from the hardware
-// reciprocal refined by two Newton steps and a residual correction; e ln 2 is added with ln 2
-// split so that e * ln2_hi is exact.  The factor -2 is folded into 2 s and the two parts of
+// reciprocal refined by one Newton step (relative error below 2^-44) and a residual correction
+// of the quotient itself, which squares that error; e ln 2 is added with ln 2 split so that
+// e * ln2_hi is exact.  The factor -2 is folded into 2 s and the two parts of
 // ln 2 (exact scalings), so the result is -2 times the rounded logarithm, bit for bit.
 __device__ __forceinline__ double neg2_log_unit(double u, const BoxMullerCoef& c) {
   int e;
@@ -182,7 +190,6 @@ __device__ __forceinline__ double neg2_log_unit(double u, const BoxMullerCoef& c
   const double f = m - 1.0;  // exact
   const double d = m + 1.0;
   double r = __builtin_amdgcn_rcp(d);
-  r = fma(fma(-d, r, 1.0), r, r);
   r = fma(fma(-d, r, 1.0), r, r);
   double s = f * r;
   s = fma(fma(-d, s, f), r, s);
@@ -232,9 +239,10 @@ __device__ __forceinline__ void sincospi_quarter(double t, const BoxMullerCoef& 
 
 // sqrt(a) for a in [0, 2^10] (Box-Muller's -2 ln u1 <= 75): the hardware reciprocal square
 // root refined by a Goldschmidt step and two residual corrections; no scaling is needed in this
-// range, and a = 0 gives 0.
+// range.  a = +-0 (u1 = 1): the reciprocal root of |a| is +inf, clamped to 2^500 so that every
+// step stays finite and gives 0; a positive a is at least 2^-53, far from the clamp.
 __device__ __forceinline__ double sqrt_bm(double a) {
-  const double y = __builtin_amdgcn_rsq(a);
+  const double y = __builtin_fmin(__builtin_amdgcn_rsq(__builtin_fabs(a)), 0x1p+500);
   double g = a * y, h = 0.5 * y;
   const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
@@ -243,7 +251,7 @@ __device__ __forceinline__ double sqrt_bm(double a) {
   g = fma(d, h, g);
   d = fma(-g, g, a);
   g = fma(d, h, g);
-  return a > 0.0 ? g : 0.0;
+  return g;
 }
 
 // The FP64 normal pair in two stages, so that a kernel can issue its own loads in between:
@@ -297,7 +305,7 @@ __device__ __forceinline__ void normal_pair_notable(const NoiseArgs& na, uint32_
   philox4x32_10(w0, w1, w2, w3, k0, k1);
   const double rad = sqrt_bm(neg2_log_unit(uniform53(w0, w1), na.bm));
   double s, c;
-  sincospi_quarter(2.0 * uniform53(w2, w3), na.bm, s, c);
+  sincospi_quarter(uniform53_x2(w2, w3), na.bm, s, c);
   z0 = rad * c;
   z1 = rad * s;
 }
