@@ -234,7 +234,7 @@ class Server:
         self.done = []
         self.done_cv = threading.Condition()
         self.evictions = 0
-        self._bytes = {}                         # dims -> pool bytes (host planning, cached)
+        self._bytes = {}                         # dims -> pool bytes, or the planning error
         self._stop = False
         self._admitter = threading.Thread(target=self._admit_loop, daemon=True)
         self._admitter.start()
@@ -261,9 +261,13 @@ class Server:
                 if self._stop:
                     return
                 unplanned = {r.dims for r in self.waiting if r.dims not in self._bytes}
-            # host planning of new shapes outside the lock, so a submission never waits for it
+            # host planning of new shapes outside the lock, so a submission never waits for it;
+            # a shape that cannot be planned fails its requests, not the admission thread
             for dims in unplanned:
-                self.pool_bytes(dims)
+                try:
+                    self.pool_bytes(dims)
+                except Exception as e:
+                    self._bytes[dims] = e
             with self.lock:
                 if self._stop:
                     return
@@ -284,6 +288,10 @@ class Server:
                 need = self._bytes.get(req.dims)
                 if need is None:            # planned outside the lock on the next pass
                     keep.append(req)
+                    continue
+                if isinstance(need, Exception):
+                    req.error = "shape cannot be planned: %r" % (need,)
+                    self._complete(req)
                     continue
                 if need > self.budget:
                     req.error = "request does not fit the HBM budget"

@@ -114,3 +114,27 @@ def test_paced_submissions_never_wait_for_planning(monkeypatch):
     assert len({r.rid for r in srv.done}) == len(reqs)
     assert all(r.result == ("done", r.dims) for r in reqs)
 
+
+def test_unplannable_shape_fails_its_requests_only(monkeypatch):
+    """A shape whose planning raises completes its requests with an error; the admission
+    thread keeps serving the other shapes."""
+    def plan(dims, slots, prec):
+        if dims == (10, 10, 3):
+            raise ValueError("unsupported grid")
+        return 100
+    monkeypatch.setattr(serve, "pool_bytes", plan)
+    monkeypatch.setattr(serve, "Pool", FakePool)
+    srv = serve.Server(budget_bytes=10 ** 6, slots=4, stride=2, precision="fp32_refined",
+                       device=torch.device("cuda", 0))
+    reqs = [serve.Request(i, (10, 10, 3) if i % 3 == 0 else (16, 16, 8), "sample", seed=i)
+            for i in range(9)]
+    for r in reqs:
+        srv.submit(r)
+    assert srv.wait(len(reqs), timeout=20.0)
+    srv.shutdown()
+    for r in reqs:
+        if r.dims == (10, 10, 3):
+            assert r.error is not None and "unsupported grid" in r.error
+        else:
+            assert r.error is None and r.result == ("done", r.dims)
+
